@@ -1,0 +1,159 @@
+"""Upwind DG discretisation of the S_N equations on a curved mesh (oracle).
+
+Per direction d and element e the local system of eq. laggedSourceIteration is
+
+  A_e = sigma_t M_e - sum_i Omega_i K_{e,i} + sum_{faces f of e} P_out(f)
+  b_e = M_e (q_e + sigma_s/(4 pi) phi_e) + sum_{faces f} P_in(f) psi_up(f)
+
+(eqs. localGMatrix, localMtMatrix, localMsMatrix, localFDiagonalMatrix,
+localFOffDiagonalMatrix, qVectorDef).  P_out / P_in are the outflow / inflow
+face blocks of ``faces``; psi_up is the upwind neighbour's trace, or the
+constant incident flux on the domain boundary (vacuum: 0).  The diagonal face
+block runs over *all* faces of the element, boundary faces included (reading:
+the printed Gamma_{e,e} must include the domain boundary for the outflow
+there).  The source is given per element (isotropic, per steradian); its load
+vector is M_e q_e (exact for element-constant sources).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import quadrature
+from .faces import FaceSet
+from .geometry import ElementGeometry
+
+VACUUM, ISO_CONST = 0, 1
+
+
+class Discretization:
+    """Direction-independent data of a problem plus per-direction helpers."""
+
+    def __init__(self, prob, omega=None, w=None, source_fn=None, inflow_fn=None):
+        """``source_fn(x (E,Q,dim), Omega (3,)) -> q_d`` replaces the element-
+        constant source (its load is integrated with 4 extra Gauss points per
+        axis); ``inflow_fn(x (...,dim), Omega) -> psi_inc`` replaces the
+        constant incident flux.  Both are oracle-only test hooks."""
+        self.prob = prob
+        self.dim, self.nx, self.r, self.p = prob.dim, tuple(prob.nx), prob.r, prob.p
+        self.E = int(np.prod(self.nx))
+        self.n = (self.p + 1) ** self.dim
+        if omega is None:
+            omega, w = quadrature.level_symmetric(prob.sn_order, prob.dim)
+        self.omega, self.w = np.asarray(omega), np.asarray(w)
+        self.D = len(self.w)
+        self.geo = ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p)
+        self.geo.check_positive()
+        self.M = self.geo.mass()                     # (E, n, n)
+        self.K = self.geo.grad_moments()             # (E, dim, n, n)
+        self.faces = FaceSet(prob.lattice, self.dim, self.nx, self.r, self.p)
+        self.sigma_t = np.asarray(prob.sigma_t, dtype=np.float64)
+        self.sigma_s = np.asarray(prob.sigma_s, dtype=np.float64)
+        self.q = np.asarray(prob.q, dtype=np.float64)
+        self.bc_kind = prob.bc_kind
+        self.psi_inc = prob.psi_inc if prob.bc_kind == ISO_CONST else 0.0
+        # element -> slot -> (face, side, neighbour), trace nodes per slot
+        e = np.arange(self.E)
+        eidx, rem = [], e.copy()
+        for a in range(self.dim):
+            eidx.append(rem % self.nx[a])
+            rem = rem // self.nx[a]
+        self.eidx = eidx
+        ns = 2 * self.dim
+        self.slot_face = np.zeros((self.E, ns), dtype=np.int64)
+        self.slot_side = np.zeros(ns, dtype=np.int64)
+        self.slot_nbr = np.zeros((self.E, ns), dtype=np.int64)
+        self.slot_nodes = np.zeros((ns, self.faces.nf), dtype=np.int64)
+        for s in range(ns):
+            fid, side = self.faces.face_of_slot(eidx, s)
+            self.slot_face[:, s] = fid
+            self.slot_side[s] = side
+            self.slot_nbr[:, s] = np.where(side == 0, self.faces.plus[fid], self.faces.minus[fid])
+            self.slot_nodes[s] = self.faces.trace_nodes(s)
+        self._cache_d = None
+        self._cache = None
+        self.inflow_fn = inflow_fn
+        self.src_load = None
+        if source_fn is not None:
+            fine = ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p,
+                                   extra_points=4)
+            self.src_load = np.stack([fine.load(source_fn(fine.x, self.omega[d]))
+                                      for d in range(self.D)])
+
+    # ------------------------------------------------------------------
+    def opposite_slot(self, s: int) -> int:
+        return s ^ 1
+
+    def face_blocks(self, d: int):
+        """Face integrals for direction d (cached for the last direction)."""
+        if self._cache_d != d:
+            fn = None
+            if self.inflow_fn is not None:
+                om = self.omega[d]
+                fn = lambda x: self.inflow_fn(x, om)
+            self._cache = self.faces.integrals(self.omega[d], fn)
+            self._cache_d = d
+        return self._cache
+
+    def slot_blocks(self, d: int, s: int, elems: np.ndarray):
+        """(P_out, P_in) of slot s for the given elements, direction d."""
+        Pp, Pm, *_ = self.face_blocks(d)
+        fid = self.slot_face[elems, s]
+        if self.slot_side[s] == 0:          # element is the face's minus side
+            return Pp[fid], Pm[fid]
+        return Pm[fid], Pp[fid]
+
+    def local_matrix(self, d: int, elems: np.ndarray) -> np.ndarray:
+        """A_e for the given elements and direction d, (k, n, n)."""
+        om = self.omega[d][: self.dim]
+        A = self.sigma_t[elems, None, None] * self.M[elems]
+        A = A - np.einsum("i,kimn->kmn", om, self.K[elems])
+        for s in range(2 * self.dim):
+            Pout, _ = self.slot_blocks(d, s, elems)
+            tn = self.slot_nodes[s]
+            A[:, tn[:, None], tn[None, :]] += Pout
+        return A
+
+    def volume_source(self, phi: np.ndarray, elems: np.ndarray, d: int = 0) -> np.ndarray:
+        """M_e (q_e + sigma_s/(4 pi) phi_e) for the given elements, (k, n)."""
+        if self.src_load is not None:
+            scat = self.sigma_s[elems, None] / (4.0 * np.pi) * phi[elems]
+            return self.src_load[d][elems] + np.einsum("kmn,kn->km", self.M[elems], scat)
+        src = self.q[elems, None] + self.sigma_s[elems, None] / (4.0 * np.pi) * phi[elems]
+        return np.einsum("kmn,kn->km", self.M[elems], src)
+
+    def boundary_load(self, d: int, s: int, elems: np.ndarray):
+        """Inflow load of slot s from a function-valued incident flux."""
+        blocks = self.face_blocks(d)
+        Lp, Lm = blocks[5], blocks[6]
+        fid = self.slot_face[elems, s]
+        # inflow of the minus side is where g < 0 (L_minus), of the plus side
+        # where g > 0 (L_plus)
+        return Lm[fid] if self.slot_side[s] == 0 else Lp[fid]
+
+    def local_rhs(self, d, elems, phi, psi_kept, psi_lag, lagged_mask):
+        """b_e for direction d.
+
+        psi_kept / psi_lag: (E, n) angular flux of direction d used for kept /
+        lagged upwind couplings; lagged_mask (k, 2*dim) bool marks slots whose
+        inflow edge was removed from the graph (read psi_lag)."""
+        b = self.volume_source(phi, elems, d)
+        for s in range(2 * self.dim):
+            _, Pin = self.slot_blocks(d, s, elems)
+            tn = self.slot_nodes[s]
+            tn_up = self.slot_nodes[self.opposite_slot(s)]
+            nbr = self.slot_nbr[elems, s]
+            interior = nbr >= 0
+            up = np.zeros((len(elems), self.faces.nf))
+            if np.any(interior):
+                src = np.where(lagged_mask[:, s][:, None], psi_lag[np.maximum(nbr, 0)][:, tn_up],
+                               psi_kept[np.maximum(nbr, 0)][:, tn_up])
+                up = np.where(interior[:, None], src, 0.0)
+            if self.inflow_fn is not None:
+                up = np.where(interior[:, None], up, 0.0)
+                b[:, tn] += np.einsum("kab,kb->ka", Pin, up)
+                bl = self.boundary_load(d, s, elems)
+                b[:, tn] += np.where(interior[:, None], 0.0, bl)
+                continue
+            up = np.where(interior[:, None], up, self.psi_inc)
+            b[:, tn] += np.einsum("kab,kb->ka", Pin, up)
+        return b

@@ -1,0 +1,299 @@
+"""Faces of the structured curved mesh and the upwind face integrals (oracle).
+
+Face numbering.  For each reference axis a, faces lie on lattice planes
+P = 0..nx[a]; a face is identified by (a, P, indices of the other axes).  The
+element with index P-1 along a is the face's *minus* element, the one with
+index P its *plus* element (-1 on the domain boundary).  The face is
+parametrised by the remaining reference axes in ascending order (s, t), and
+N(s) is the area-scaled normal pointing from the minus to the plus element:
+  2D  axis 0: N = (t_y, -t_x), t = dx/ds;  axis 1: N = (-t_y, t_x)
+  3D  axis 0, 2: N = dx/ds x dx/dt;        axis 1: N = dx/dt x dx/ds
+i.e. the cofactor of the element Jacobian applied to the face's reference
+normal, so that (Omega . n) ds = (Omega . N) ds_ref.
+
+Upwind face matrices.  With g = Omega . N, for a face and direction
+  P_plus [a, b] = int max(+g, 0) phi_a phi_b ds_ref
+  P_minus[a, b] = int max(-g, 0) phi_a phi_b ds_ref
+where phi_a are the face traces of the GLL nodal basis.  For the minus element
+P_plus is the outflow block of eq. diagonalFaceMatrixBlocks and P_minus the
+inflow coupling from the plus element; for the plus element the roles swap.
+Sign reading (the printed eq. offDiagonalFaceMatrixBlocks and qVectorDef carry
+the opposite sign of the integration by parts): the inflow coupling enters the
+*right-hand side* with a plus sign, b += P_in psi_upwind, equivalently
+F_{e,e'} = -P_in on the left-hand side.
+
+Non-smooth integrands (the paper's "re-entrant faces" where Omega . n changes
+sign; it uses Romberg integration with an unstated tolerance).  Reading:
+* 2D: g is a polynomial of degree r-1 in s; its roots in (0,1) split the face
+  into pieces on which the integrand is a polynomial, integrated exactly with
+  ceil((r+2p)/2) Gauss points per piece.
+* 3D: fixed composite rule, K x K sub-squares (K = 4) with (p+r)^2 Gauss points
+  each (exact on faces without a sign change).
+* Interior faces: a side whose inflow measure int max(-/+g, 0) ds_ref is at
+  most tau = 1e-12 times int |g| ds_ref is dropped entirely (its P is set to
+  zero), so the operator and the dependency graph agree.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import basis
+
+TAU = 1e-12
+KINK_SUBDIV_3D = 4
+
+
+def face_rule_2d(r: int, p: int) -> int:
+    return int(math.ceil((r + 2 * p) / 2.0))
+
+
+class FaceSet:
+    def __init__(self, lattice, dim, nx, r, p):
+        self.dim, self.nx, self.r, self.p = dim, tuple(nx), r, p
+        L = [r * nx[a] + 1 for a in range(dim)]
+        axis, minus, plus, ctrl, idx_all = [], [], [], [], []
+        self.axis_offset = []
+        off = 0
+        for a in range(dim):
+            self.axis_offset.append(off)
+            ext = [nx[b] + (1 if b == a else 0) for b in range(dim)]
+            nf_a = int(np.prod(ext))
+            fid = np.arange(nf_a)
+            idx = []
+            rem = fid.copy()
+            for b in range(dim):
+                idx.append(rem % ext[b])
+                rem = rem // ext[b]
+            P = idx[a]
+            # element linear index helper
+            def elem(ii):
+                e = np.zeros_like(ii[0])
+                s = 1
+                for b in range(dim):
+                    e = e + ii[b] * s
+                    s *= nx[b]
+                return e
+            im = list(idx)
+            im[a] = P - 1
+            ip = list(idx)
+            mi = np.where(P >= 1, elem(im), -1)
+            pl = np.where(P < nx[a], elem(ip), -1)
+            # face control points, remaining axes ascending, first fastest
+            others = [b for b in range(dim) if b != a]
+            nloc = (r + 1) ** (dim - 1)
+            loc = np.arange(nloc)
+            lidx = []
+            rem = loc.copy()
+            for _ in others:
+                lidx.append(rem % (r + 1))
+                rem = rem // (r + 1)
+            flat = np.zeros((nf_a, nloc), dtype=np.int64)
+            stride = 1
+            for b in range(dim):
+                if b == a:
+                    coord = (r * P)[:, None] + 0 * loc[None, :]
+                else:
+                    k = others.index(b)
+                    coord = (r * idx[b])[:, None] + lidx[k][None, :]
+                flat += coord * stride
+                stride *= L[b]
+            axis.append(np.full(nf_a, a))
+            minus.append(mi)
+            plus.append(pl)
+            ctrl.append(lattice[flat])
+            off += nf_a
+        self.axis = np.concatenate(axis)
+        self.minus = np.concatenate(minus)
+        self.plus = np.concatenate(plus)
+        self.ctrl = np.concatenate(ctrl)          # (F, (r+1)^(dim-1), dim)
+        self.n_faces = len(self.axis)
+        self.interior = (self.minus >= 0) & (self.plus >= 0)
+        self.nf = (p + 1) ** (dim - 1)
+        self._geo_nodes = basis.equispaced_points(r)
+        self._dg_nodes = basis.gll_points(p)
+        if dim == 3:
+            self._setup_3d_rule()
+
+    # ------------------------------------------------------------------
+    def face_of_slot(self, e_idx: np.ndarray, slot: int):
+        """Face id and side (0 = element is minus, 1 = plus) of element slot.
+
+        Slot 2a is the element's xi_a = 0 face (element is the plus side),
+        slot 2a+1 its xi_a = 1 face (element is the minus side)."""
+        a, hi = slot // 2, slot % 2
+        ext = [self.nx[b] + (1 if b == a else 0) for b in range(self.dim)]
+        fid = np.zeros(len(e_idx[0]), dtype=np.int64)
+        s = 1
+        for b in range(self.dim):
+            v = e_idx[b] + (hi if b == a else 0)
+            fid = fid + v * s
+            s *= ext[b]
+        side = 0 if hi else 1
+        return self.axis_offset[a] + fid, side
+
+    def trace_nodes(self, slot: int) -> np.ndarray:
+        """Element DG node numbers on a slot, in the face's (s, t) order."""
+        p, dim = self.p, self.dim
+        a, hi = slot // 2, slot % 2
+        others = [b for b in range(dim) if b != a]
+        out = []
+        for loc in range(self.nf):
+            rem = loc
+            idx = [0] * dim
+            for b in others:
+                idx[b] = rem % (p + 1)
+                rem //= (p + 1)
+            idx[a] = p if hi else 0
+            m = 0
+            s = 1
+            for b in range(dim):
+                m += idx[b] * s
+                s *= p + 1
+            out.append(m)
+        return np.array(out)
+
+    # ------------------------------------------------------------------
+    def _normals(self, pts: np.ndarray, per_face: bool) -> np.ndarray:
+        """Scaled normal N at face parameter points.
+
+        pts: (Q, dim-1) shared points, or (F, Q) per-face points in 2D."""
+        dim = self.dim
+        if dim == 2:
+            s = pts if per_face else np.broadcast_to(pts[:, 0], (self.n_faces, pts.shape[0]))
+            _, D = basis.lagrange(self._geo_nodes, s.reshape(-1))
+            D = D.reshape(s.shape + (self.r + 1,))
+            t = np.einsum("fqb,fba->fqa", D, self.ctrl)
+            sgn = np.where(self.axis == 0, 1.0, -1.0)[:, None]
+            return np.stack([sgn * t[..., 1], -sgn * t[..., 0]], axis=-1)
+        V1s, D1s = basis.lagrange(self._geo_nodes, pts[:, 0])
+        V1t, D1t = basis.lagrange(self._geo_nodes, pts[:, 1])
+        # control point loc = bs + (r+1)*bt
+        Ds = np.einsum("qi,qj->qji", D1s, V1t).reshape(len(pts), -1)
+        Dt = np.einsum("qi,qj->qji", V1s, D1t).reshape(len(pts), -1)
+        t1 = np.einsum("qm,fma->fqa", Ds, self.ctrl)
+        t2 = np.einsum("qm,fma->fqa", Dt, self.ctrl)
+        n12 = np.cross(t1, t2)
+        return np.where((self.axis == 1)[:, None, None], -n12, n12)
+
+    def _setup_3d_rule(self):
+        K = KINK_SUBDIV_3D
+        x1, w1 = basis.gauss_legendre(self.p + self.r)
+        xs = np.concatenate([(k + x1) / K for k in range(K)])
+        ws = np.concatenate([w1 / K for _ in range(K)])
+        S, T = np.meshgrid(xs, xs, indexing="ij")      # S varies slowest
+        self.rule3_pts = np.stack([T.reshape(-1), S.reshape(-1)], axis=1)  # s fastest
+        self.rule3_w = np.kron(ws, ws)
+        V1s, _ = basis.lagrange(self._dg_nodes, self.rule3_pts[:, 0])
+        V1t, _ = basis.lagrange(self._dg_nodes, self.rule3_pts[:, 1])
+        self.rule3_phi = np.einsum("qi,qj->qji", V1s, V1t).reshape(len(self.rule3_pts), -1)
+        self.rule3_N = self._normals(self.rule3_pts, per_face=False)  # (F, Q, 3)
+
+    # ------------------------------------------------------------------
+    def _pieces_2d(self, om2: np.ndarray):
+        """Breakpoints of [0,1] at the sign changes of g(s) = Omega . N(s)."""
+        r = self.r
+        F = self.n_faces
+        if r == 1:
+            return np.tile(np.array([0.0, 1.0]), (F, 1))
+        # monomial coefficients of g from its values at r distinct points
+        sfit = (np.arange(r) + 0.5) / r
+        N = self._normals(sfit[:, None], per_face=False)                    # (F, r, 2)
+        gv = N @ om2                                                       # (F, r)
+        Vm = np.vander(sfit, r, increasing=True)                            # (r, r)
+        coef = np.linalg.solve(Vm, gv.T).T                                  # (F, r)
+        roots = np.full((F, r - 1), 2.0)
+        if r == 2:
+            a0, a1 = coef[:, 0], coef[:, 1]
+            with np.errstate(divide="ignore", invalid="ignore"):
+                rt = np.where(a1 != 0.0, -a0 / a1, 2.0)
+            roots[:, 0] = rt
+        elif r == 3:
+            c, b, a = coef[:, 0], coef[:, 1], coef[:, 2]
+            disc = b * b - 4.0 * a * c
+            ok = disc > 0.0
+            sq = np.sqrt(np.where(ok, disc, 0.0))
+            qq = -0.5 * (b + np.where(b >= 0.0, sq, -sq))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                r1 = np.where(ok & (a != 0.0), qq / a, 2.0)
+                r2 = np.where(ok & (qq != 0.0), c / qq, 2.0)
+                lin = np.where(b != 0.0, -c / b, 2.0)
+            r1 = np.where(a == 0.0, lin, r1)
+            r2 = np.where(a == 0.0, 2.0, r2)
+            roots[:, 0], roots[:, 1] = r1, r2
+        else:
+            for f in range(F):
+                rr = np.roots(coef[f, ::-1])
+                rr = rr[np.abs(rr.imag) == 0.0].real
+                roots[f, :len(rr)] = rr
+        roots = np.where((roots > 0.0) & (roots < 1.0), roots, 1.0)
+        roots.sort(axis=1)
+        return np.concatenate([np.zeros((F, 1)), roots, np.ones((F, 1))], axis=1)
+
+    def face_points_physical(self, s: np.ndarray, per_face: bool) -> np.ndarray:
+        """Physical coordinates of face parameter points, (F, Q, dim)."""
+        if self.dim == 2:
+            ss = s if per_face else np.broadcast_to(s[:, 0], (self.n_faces, s.shape[0]))
+            V, _ = basis.lagrange(self._geo_nodes, ss.reshape(-1))
+            V = V.reshape(ss.shape + (self.r + 1,))
+            return np.einsum("fqb,fba->fqa", V, self.ctrl)
+        V1s, _ = basis.lagrange(self._geo_nodes, s[:, 0])
+        V1t, _ = basis.lagrange(self._geo_nodes, s[:, 1])
+        V = np.einsum("qi,qj->qji", V1s, V1t).reshape(len(s), -1)
+        return np.einsum("qm,fma->fqa", V, self.ctrl)
+
+    def integrals(self, omega: np.ndarray, inflow_fn=None):
+        """(P_plus, P_minus, m_plus, m_minus, m_abs[, L_plus, L_minus]).
+
+        P_* (F, nf, nf); m_plus = int max(g,0), m_minus = int max(-g,0),
+        m_abs = int |g| (all over the reference face).  Interior sides below
+        the tau threshold are zeroed (see module docstring).  With
+        ``inflow_fn(x (..., dim)) -> values`` also the boundary loads
+        L_plus[a] = int max(g,0) phi_a f ds_ref and L_minus (max(-g,0))."""
+        dim = self.dim
+        om = np.asarray(omega, dtype=np.float64)[:dim]
+        fvals = None
+        if dim == 2:
+            bp = self._pieces_2d(om)
+            xg, wg = basis.gauss_legendre(face_rule_2d(self.r, self.p))
+            s0, s1 = bp[:, :-1], bp[:, 1:]                              # (F, k)
+            h = s1 - s0
+            s = s0[:, :, None] + h[:, :, None] * xg[None, None, :]      # (F, k, g)
+            w = h[:, :, None] * wg[None, None, :]
+            s = s.reshape(self.n_faces, -1)
+            w = w.reshape(self.n_faces, -1)
+            g = self._normals(s, per_face=True) @ om                     # (F, Q)
+            V, _ = basis.lagrange(self._dg_nodes, s.reshape(-1))
+            phi = V.reshape(s.shape + (self.nf,))
+            wp = w * np.maximum(g, 0.0)
+            wm = w * np.maximum(-g, 0.0)
+            Pp = np.einsum("fq,fqa,fqb->fab", wp, phi, phi)
+            Pm = np.einsum("fq,fqa,fqb->fab", wm, phi, phi)
+            if inflow_fn is not None:
+                fvals = inflow_fn(self.face_points_physical(s, per_face=True))
+                Lp = np.einsum("fq,fq,fqa->fa", wp, fvals, phi)
+                Lm = np.einsum("fq,fq,fqa->fa", wm, fvals, phi)
+        else:
+            g = self.rule3_N @ om                                          # (F, Q)
+            wp = self.rule3_w[None, :] * np.maximum(g, 0.0)
+            wm = self.rule3_w[None, :] * np.maximum(-g, 0.0)
+            phi2 = np.einsum("qa,qb->qab", self.rule3_phi, self.rule3_phi).reshape(len(self.rule3_w), -1)
+            Pp = (wp @ phi2).reshape(self.n_faces, self.nf, self.nf)
+            Pm = (wm @ phi2).reshape(self.n_faces, self.nf, self.nf)
+            if inflow_fn is not None:
+                fvals = inflow_fn(self.face_points_physical(self.rule3_pts, per_face=False))
+                Lp = np.einsum("fq,fq,qa->fa", wp, fvals, self.rule3_phi)
+                Lm = np.einsum("fq,fq,qa->fa", wm, fvals, self.rule3_phi)
+        mp = wp.sum(axis=1)
+        mm = wm.sum(axis=1)
+        mabs = mp + mm
+        drop_p = self.interior & (mp <= TAU * mabs)
+        drop_m = self.interior & (mm <= TAU * mabs)
+        Pp[drop_p] = 0.0
+        Pm[drop_m] = 0.0
+        mp = np.where(drop_p, 0.0, mp)
+        mm = np.where(drop_m, 0.0, mm)
+        if fvals is not None:
+            return Pp, Pm, mp, mm, mabs, Lp, Lm
+        return Pp, Pm, mp, mm, mabs

@@ -1,0 +1,82 @@
+"""Level-symmetric S_N angular quadrature (oracle).
+
+The paper (section 2, below eq. linearSnTransport) requires positive weights
+summing to 4*pi and uses level-symmetric S_2 (cosines a = sqrt(3)/3) and S_4
+sets.  It prints no table, so the construction here is the textbook one:
+
+* cosines mu_i^2 = mu_1^2 + (i-1) * 2*(1 - 3*mu_1^2)/(N-2), i = 1..N/2
+  (S_2: mu_1 = 1/sqrt(3));
+* octant points (mu_i, mu_j, mu_k) with i + j + k = N/2 + 2;
+* one weight per permutation class, fixed by the even moment conditions
+  sum_octant w * mu_x^(2m) = 1/(2m+1), m = 0..N/2-1 (least squares; the system
+  is consistent for the tabulated mu_1);
+* octant weights scaled by 4*pi/8; in 2D only the directions with a positive
+  z cosine are kept and their weights doubled, so the sum stays 4*pi.
+
+Direction order: octant o = [x<0] + 2*[y<0] (+ 4*[z<0]) ascending, then i, then
+j ascending inside the octant.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# mu_1 of the standard level-symmetric sets (textbook table)
+MU1 = {4: 0.3500212, 6: 0.2666355, 8: 0.2182179, 10: 0.1893213,
+       12: 0.1672126, 16: 0.1389568}
+
+
+def cosines(N: int) -> np.ndarray:
+    if N == 2:
+        return np.array([1.0 / math.sqrt(3.0)])
+    if N not in MU1:
+        raise ValueError(f"no level-symmetric set for S{N}")
+    mu1 = MU1[N]
+    i = np.arange(N // 2)
+    return np.sqrt(mu1 ** 2 + i * 2.0 * (1.0 - 3.0 * mu1 ** 2) / (N - 2))
+
+
+def octant_points(N: int):
+    """List of (i, j, k) index triples (0-based) in an octant, i then j."""
+    h = N // 2
+    pts = []
+    for i in range(h):
+        for j in range(h - i):
+            k = h - 1 - i - j
+            pts.append((i, j, k))
+    return pts
+
+
+def octant_weights(N: int) -> np.ndarray:
+    """Octant-normalised point weights (sum 1) from the moment conditions."""
+    mu = cosines(N)
+    pts = octant_points(N)
+    classes = sorted({tuple(sorted(p)) for p in pts})
+    cls_of = [classes.index(tuple(sorted(p))) for p in pts]
+    nm = N // 2
+    A = np.zeros((nm, len(classes)))
+    for m in range(nm):
+        for p, c in zip(pts, cls_of):
+            A[m, c] += mu[p[0]] ** (2 * m)
+    b = 1.0 / (2.0 * np.arange(nm) + 1.0)
+    wc, *_ = np.linalg.lstsq(A, b, rcond=None)
+    return np.array([wc[c] for c in cls_of])
+
+
+def level_symmetric(N: int, dim: int):
+    """Return (omega (D,3), w (D,)) for the level-symmetric S_N set."""
+    mu = cosines(N)
+    pts = octant_points(N)
+    wo = octant_weights(N)
+    n_oct = 8 if dim == 3 else 4
+    scale = 4.0 * math.pi / 8.0 * (2.0 if dim == 2 else 1.0)
+    om, ww = [], []
+    for o in range(n_oct):
+        sx = -1.0 if o & 1 else 1.0
+        sy = -1.0 if o & 2 else 1.0
+        sz = -1.0 if o & 4 else 1.0
+        for (i, j, k), wp in zip(pts, wo):
+            om.append((sx * mu[i], sy * mu[j], sz * mu[k]))
+            ww.append(wp * scale)
+    return np.array(om), np.array(ww)

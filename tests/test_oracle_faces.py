@@ -1,0 +1,109 @@
+"""Pins of the upwind face integrals (eqs. localFDiagonalMatrix,
+localFOffDiagonalMatrix) including faces where Omega . n changes sign."""
+import numpy as np
+import pytest
+from scipy import integrate, optimize
+
+import workloads as W
+from oracle.faces import FaceSet
+from tests.oracle_helpers import gll, lagrange_polys
+
+
+def independent_g_2d(fs, f, om):
+    """g(s) = Omega . N(s) from an independent polynomial interpolation."""
+    r = fs.r
+    X = fs.ctrl[f]
+    L = lagrange_polys(np.linspace(0, 1, r + 1))
+    tx = sum((L[b].deriv() * X[b, 0] for b in range(r + 1)), start=0 * L[0])
+    ty = sum((L[b].deriv() * X[b, 1] for b in range(r + 1)), start=0 * L[0])
+    if fs.axis[f] == 0:
+        return lambda s: om[0] * ty(s) - om[1] * tx(s)
+    return lambda s: -om[0] * ty(s) + om[1] * tx(s)
+
+
+def test_2d_kink_faces_against_adaptive_quadrature():
+    prob = W.small(dim=2, n=8, r=3, p=2, N=8, amp=0.3 / 8, freq=2)
+    fs = FaceSet(prob.lattice, 2, prob.nx, 3, 2)
+    rng = np.random.default_rng(1)
+    phis = lagrange_polys(gll(2))
+    checked_kinks = 0
+    for trial in range(6):
+        th = rng.uniform(0, 2 * np.pi)
+        om = np.array([np.cos(th), np.sin(th), 0.0])
+        Pp, Pm, mp, mm, mabs = fs.integrals(om)
+        for f in rng.choice(fs.n_faces, 25, replace=False):
+            g = independent_g_2d(fs, f, om)
+            ss = np.linspace(0, 1, 2001)
+            gv = g(ss)
+            roots = [optimize.brentq(g, ss[k], ss[k + 1]) for k in range(2000) if gv[k] * gv[k + 1] < 0]
+            checked_kinks += bool(roots)
+            for a in range(3):
+                for b in range(3):
+                    ip, _ = integrate.quad(lambda s: max(g(s), 0) * phis[a](s) * phis[b](s), 0, 1,
+                                           points=roots or None, epsabs=1e-15, epsrel=1e-13)
+                    im, _ = integrate.quad(lambda s: max(-g(s), 0) * phis[a](s) * phis[b](s), 0, 1,
+                                           points=roots or None, epsabs=1e-15, epsrel=1e-13)
+                    scale = abs(Pp[f]).max() + abs(Pm[f]).max()
+                    if fs.interior[f] and Pp[f].max() == 0:
+                        ip = 0.0     # side dropped below the threshold
+                    if fs.interior[f] and Pm[f].max() == 0:
+                        im = 0.0
+                    assert abs(Pp[f, a, b] - ip) <= 1e-12 * scale + 1e-15
+                    assert abs(Pm[f, a, b] - im) <= 1e-12 * scale + 1e-15
+    assert checked_kinks > 0
+
+
+@pytest.mark.parametrize("dim,r,p,n,amp,freq", [(2, 3, 3, 8, 0.3 / 8, 2), (3, 2, 2, 3, 0.05, 1),
+                                                 (3, 1, 2, 3, 0.02, 1)])
+def test_face_identities(dim, r, p, n, amp, freq):
+    """P+ - P- is the polynomial integral of g phi phi; closed element
+    surfaces have zero net flux; P+/P- are positive semidefinite."""
+    prob = W.small(dim=dim, n=n, r=r, p=p, N=2, amp=amp, freq=freq)
+    fs = FaceSet(prob.lattice, dim, prob.nx, r, p)
+    rng = np.random.default_rng(0)
+    om = rng.normal(size=3)
+    om /= np.linalg.norm(om)
+    Pp, Pm, mp, mm, mabs = fs.integrals(om)
+    # exact (single high-order rule) integral of g phi_a phi_b through
+    # the linear dependence on Omega, component by component
+    ref = 0.0
+    for i in range(dim):
+        e = np.zeros(3)
+        e[i] = 1.0
+        Ppi, Pmi, *_ = fs.integrals(e)
+        ref = ref + om[i] * (Ppi - Pmi)
+    scale = np.abs(ref).max()
+    keep = ~fs.interior | ((Pp.reshape(len(Pp), -1).max(1) > 0) & (Pm.reshape(len(Pm), -1).max(1) > 0))
+    assert np.abs((Pp - Pm - ref)[keep]).max() < 1e-11 * scale
+    for P in (Pp, Pm):
+        ev = np.linalg.eigvalsh(0.5 * (P + P.transpose(0, 2, 1)))
+        assert ev.min() > -1e-15 * scale
+    # zero net flux through each element surface
+    from oracle.discretization import Discretization
+    disc = Discretization(prob)
+    net = np.zeros(disc.E)
+    for s in range(2 * dim):
+        fid = disc.slot_face[:, s]
+        sign = 1.0 if disc.slot_side[s] == 0 else -1.0
+        net += sign * (mp[fid] - mm[fid])
+    assert np.abs(net).max() < 1e-13
+
+
+def test_3d_composite_rule_converges():
+    """On kink faces the fixed composite rule approaches the refined one."""
+    import oracle.faces as F
+    prob = W.small(dim=3, n=3, r=2, p=1, N=2, amp=0.08, freq=1)
+    fs4 = FaceSet(prob.lattice, 3, prob.nx, 2, 1)
+    om = np.array([0.05, 0.6, 0.8])
+    om /= np.linalg.norm(om)
+    Pp4, Pm4, *_ = fs4.integrals(om)
+    old = F.KINK_SUBDIV_3D
+    try:
+        F.KINK_SUBDIV_3D = 32
+        fs32 = FaceSet(prob.lattice, 3, prob.nx, 2, 1)
+    finally:
+        F.KINK_SUBDIV_3D = old
+    Pp32, Pm32, *_ = fs32.integrals(om)
+    scale = np.abs(Pp32).max()
+    err = np.abs(Pp4 - Pp32).max() / scale
+    assert err < 5e-3

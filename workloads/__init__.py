@@ -1,0 +1,211 @@
+"""Seeded synthetic workloads for the S_N sweep (inputs only).
+
+This module produces the *inputs* of a problem: the control-point lattice of a
+curved structured quad/hex mesh on the unit square/cube, per-element cross
+sections and sources, and the angular-quadrature order.  It holds none of the
+method's arithmetic (no basis functions, quadrature rules, operators or graph
+work), so that both the CPU oracle and the GPU library can consume it without
+sharing any code with each other.
+
+Mesh recipe.  The domain is [0,1]^dim, split into nx[0] x nx[1] (x nx[2])
+elements of geometric order r.  Control points sit on a global lattice of
+(r*nx[a]+1) points per axis, equispaced in the reference coordinate
+X_a = I_a / (r*nx[a]); each point is displaced by the warp
+    W(X) = X + amp * prod_j sin(2*pi*freq*X_j) * (1, ..., 1),
+which vanishes on the boundary of the unit box, so the domain stays [0,1]^dim.
+Lattice points are ordered x fastest (then y, then z); element e = i + nx*(j +
+ny*k) uses lattice points (r*i + a, r*j + b, r*k + c), a/b/c = 0..r.  Shared
+faces therefore use bit-identical control points (mesh continuity, section 2,
+"Discrete representation of the HO mesh").
+
+Synthetic problems stand in for the paper's meshes (annulus, triple point,
+Rayleigh-Taylor), which are not available: the configurations below follow the
+sizes, orders, quadratures and material layouts of the workloads the
+performance targets are quoted on.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Optional
+
+import numpy as np
+
+VACUUM = 0
+ISO_CONST = 1
+
+
+@dataclass
+class Problem:
+    """Inputs of one steady mono-energetic S_N problem on a curved mesh."""
+    name: str
+    dim: int
+    nx: tuple
+    r: int                 # geometric order of the mesh map (Q_r)
+    p: int                 # DG order (Q_p)
+    sn_order: int          # level-symmetric S_N order (even)
+    lattice: np.ndarray    # (n_lattice, dim) float64 control points
+    sigma_t: np.ndarray    # (E,) float64
+    sigma_s: np.ndarray    # (E,) float64
+    q: np.ndarray          # (E,) float64 isotropic source per steradian
+    bc_kind: int = VACUUM
+    psi_inc: float = 0.0   # constant isotropic inflow for ISO_CONST
+    tol: float = 1e-10
+    weighting: int = 1     # 0 unity, 1 face, 2 sigma-inverse face
+    exact_scc_max: int = 10
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_elements(self) -> int:
+        return int(np.prod(self.nx))
+
+    @property
+    def n_dof(self) -> int:
+        return (self.p + 1) ** self.dim
+
+    @property
+    def n_dirs(self) -> int:
+        n = self.sn_order
+        return n * (n + 2) // 2 if self.dim == 2 else n * (n + 2)
+
+
+def lattice_shape(dim: int, nx, r: int) -> tuple:
+    return tuple(r * int(nx[a]) + 1 for a in range(dim))
+
+
+def make_lattice(dim: int, nx, r: int, amp: float, freq: int) -> np.ndarray:
+    """Warped control-point lattice, x fastest.  See the module docstring."""
+    shape = lattice_shape(dim, nx, r)
+    axes = [np.arange(shape[a], dtype=np.float64) / (r * nx[a]) for a in range(dim)]
+    # meshgrid with 'ij' then transpose so that x is the fastest index
+    grids = np.meshgrid(*axes[::-1], indexing="ij")[::-1]
+    X = np.stack([g.reshape(-1) for g in grids], axis=1)
+    bump = np.ones(X.shape[0])
+    for a in range(dim):
+        bump = bump * np.sin(2.0 * math.pi * freq * X[:, a])
+    return X + amp * bump[:, None]
+
+
+def element_ijk(dim: int, nx) -> np.ndarray:
+    """(E, dim) integer element indices, e = i + nx*(j + ny*k)."""
+    E = int(np.prod(nx))
+    e = np.arange(E)
+    out = np.zeros((E, dim), dtype=np.int64)
+    rem = e.copy()
+    for a in range(dim):
+        out[:, a] = rem % nx[a]
+        rem //= nx[a]
+    return out
+
+
+def make_problem(name: str, dim: int, nx, r: int, p: int, sn_order: int,
+                 amp: float, freq: int, sigma_t, c, q, *, bc_kind=VACUUM,
+                 psi_inc=0.0, tol=1e-10, weighting=1, exact_scc_max=10,
+                 meta: Optional[dict] = None) -> Problem:
+    nx = tuple(int(v) for v in nx)
+    E = int(np.prod(nx))
+    st = np.broadcast_to(np.asarray(sigma_t, dtype=np.float64), (E,)).copy()
+    cc = np.broadcast_to(np.asarray(c, dtype=np.float64), (E,)).copy()
+    qq = np.broadcast_to(np.asarray(q, dtype=np.float64), (E,)).copy()
+    return Problem(name=name, dim=dim, nx=nx, r=r, p=p, sn_order=sn_order,
+                   lattice=make_lattice(dim, nx, r, amp, freq),
+                   sigma_t=st, sigma_s=cc * st, q=qq, bc_kind=bc_kind,
+                   psi_inc=float(psi_inc), tol=tol, weighting=weighting,
+                   exact_scc_max=exact_scc_max,
+                   meta=dict(meta or {}, amp=amp, freq=freq))
+
+
+# --------------------------------------------------------------------------
+# Named configurations
+# --------------------------------------------------------------------------
+
+def c1() -> Problem:
+    """2D 8x8 Q2 mesh, warp 0.05, p=1, S4, sigma_t=1, c=0.5, q=1, vacuum."""
+    return make_problem("c1_2d_8x8_q2_p1_s4", 2, (8, 8), 2, 1, 4, 0.05, 1,
+                        1.0, 0.5, 1.0, tol=1e-10)
+
+
+def c2() -> Problem:
+    """2D 128x128 Q3 mesh warped by 0.3 element widths with a 4-element
+    wavelength (cycles in the sweep graph), p=3, S8, sigma_t=1, c=0.8, q=1."""
+    return make_problem("c2_2d_128x128_q3_p3_s8", 2, (128, 128), 3, 3, 8,
+                        0.3 / 128, 32, 1.0, 0.8, 1.0, tol=1e-8)
+
+
+def c3() -> Problem:
+    """3D 32^3 Q2 mesh, p=2, S8, checkerboard sigma_t in {1,10} (8^3 blocks),
+    c=0.9, q=1 in the central 8^3 block, vacuum."""
+    nx = (32, 32, 32)
+    ijk = element_ijk(3, nx)
+    odd = ((ijk[:, 0] // 8 + ijk[:, 1] // 8 + ijk[:, 2] // 8) % 2) == 1
+    st = np.where(odd, 10.0, 1.0)
+    inside = np.all((ijk >= 12) & (ijk <= 19), axis=1)
+    q = np.where(inside, 1.0, 0.0)
+    return make_problem("c3_3d_32cube_q2_p2_s8", 3, nx, 2, 2, 8, 0.05, 1,
+                        st, 0.9, q, tol=1e-8)
+
+
+def c4(seed: int = 0, count: int = 64) -> List[Problem]:
+    """Batch of independent 2D problems drawn from a seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        m = int(rng.integers(16, 97))
+        p = int(rng.integers(1, 4))
+        N = 2 * int(rng.integers(2, 7))
+        st = float(10.0 ** rng.uniform(-1.0, 1.0))
+        c = float(rng.uniform(0.0, 0.95))
+        out.append(make_problem(f"c4_{b}_2d_{m}x{m}_q2_p{p}_s{N}", 2, (m, m), 2,
+                                p, N, 0.05, 1, st, c, 1.0, tol=1e-8))
+    return out
+
+
+def c5(seed: int = 100, nx: int = 48, sn_order: int = 12) -> Problem:
+    """3D 48^3 Q2 mesh, p=2, S12, c=0.99, random two-material layout with
+    sigma_t in {1,100}, q=1 everywhere, vacuum."""
+    dims = (nx, nx, nx)
+    E = nx ** 3
+    rng = np.random.default_rng(seed)
+    st = np.where(rng.random(E) < 0.5, 100.0, 1.0)
+    return make_problem(f"c5_3d_{nx}cube_q2_p2_s{sn_order}_seed{seed}", 3, dims,
+                        2, 2, sn_order, 0.05, 1, st, 0.99, 1.0, tol=1e-8)
+
+
+def small(dim=2, n=4, r=2, p=1, N=4, amp=0.05, freq=1, sigma_t=1.0, c=0.5,
+          q=1.0, **kw) -> Problem:
+    nx = (n,) * dim if np.isscalar(n) else tuple(n)
+    return make_problem(f"small_{dim}d_{'x'.join(map(str, nx))}_q{r}_p{p}_s{N}",
+                        dim, nx, r, p, N, amp, freq, sigma_t, c, q, **kw)
+
+
+def random_problem(seed: int, dim: int = 2) -> Problem:
+    """A small random problem for parity sweeps (ragged sizes, mixed media)."""
+    rng = np.random.default_rng(seed)
+    # the warp's maximum slope amp*2*pi*freq is drawn directly; the Jacobian
+    # determinant of the warp stays >= 1 - dim*slope > 0
+    if dim == 2:
+        nx = (int(rng.integers(3, 13)), int(rng.integers(3, 13)))
+        r = int(rng.integers(1, 4))
+        p = int(rng.integers(1, 4))
+        N = int(2 * rng.integers(1, 5))
+        freq = int(rng.integers(1, max(2, min(nx) // 2 + 1)))
+        slope = float(rng.uniform(0.0, 0.45))
+    else:
+        nx = tuple(int(v) for v in rng.integers(2, 6, size=3))
+        r = int(rng.integers(1, 3))
+        p = int(rng.integers(1, 3))
+        N = int(2 * rng.integers(1, 4))
+        freq = int(rng.integers(1, 3))
+        slope = float(rng.uniform(0.0, 0.25))
+    amp = slope / (2.0 * math.pi * freq)
+    E = int(np.prod(nx))
+    st = 10.0 ** rng.uniform(-1, 1, size=E)
+    c = rng.uniform(0.0, 0.9, size=E)
+    q = rng.uniform(0.0, 2.0, size=E)
+    bc = int(rng.integers(0, 2))
+    return make_problem(f"rand{seed}_{dim}d", dim, nx, r, p, N, amp, freq, st, c,
+                        q, bc_kind=bc, psi_inc=float(rng.uniform(0, 1)) * bc,
+                        weighting=int(rng.integers(0, 3)))
+
+
+CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c5": c5}
