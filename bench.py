@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the graph-based S_N transport sweep on one MI355X.
+
+Metric: DOF-direction updates per second of one full lagged sweep (every
+level of the combined schedule, the scattering source and the scalar-flux
+reduction), E*n*D / t_sweep, with all inputs resident in HBM.  Default
+workload: 2D 128x128 Q3 curved mesh (warp 0.3 element widths, 4-element
+wavelength, so the sweep graphs have cycles), DG p=3, S8 (40 directions),
+sigma_t = 1, c = 0.8, q = 1, vacuum; seeded synthetic inputs.
+
+Also reported: the roofline of the level-sweep kernel (algorithmic FP64 flops
+per launch over its average launch time, HIP events around every launch in a
+second timed pass), plain source-iteration time to a 1e-8 residual, and the
+CPU oracle timed on a sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+DESCRIPTIONS = {
+    "c1": "2D 8x8 Q2 curved (warp 0.05), p=1, S4 (12 dirs), sigma_t=1, c=0.5, q=1, vacuum",
+    "c2": "2D 128x128 Q3 curved (warp 0.3 h, 4-element wavelength, cyclic sweep graphs), p=3, "
+          "S8 (40 dirs), sigma_t=1, c=0.8, q=1, vacuum",
+    "c3": "3D 32^3 Q2 curved (warp 0.05), p=2, S8 (80 dirs), checkerboard sigma_t {1,10}, c=0.9, "
+          "q=1 in the central 8^3 block, vacuum",
+    "c5": "3D 48^3 Q2 curved (warp 0.05), p=2, S12 (168 dirs), random sigma_t {1,100}, c=0.99, "
+          "q=1, vacuum",
+}
+
+
+def flops_per_pair(dim: int, p: int) -> float:
+    """Algorithmic FP64 flops of one (element, direction) solve: assembly of
+    sigma_t M - sum_i Omega_i K_i (2(d+1)n^2), face blocks from the normal
+    moments (2d faces x 2d nf^2) with d outflow additions (nf^2) and d inflow
+    products (2 nf^2), Gaussian elimination (2/3 n^3) and the two triangular
+    sweeps (2 n^2)."""
+    n = (p + 1) ** dim
+    nf = (p + 1) ** (dim - 1)
+    return (2.0 / 3.0) * n ** 3 + 2 * n ** 2 + 2 * (dim + 1) * n ** 2 + 4 * dim * dim * nf ** 2 \
+        + 3 * dim * nf ** 2
+
+
+def cpu_baseline(wp, n_dirs_sample: int = 4, repeats: int = 1):
+    """Time the oracle's sweep on a sample of the directions of the workload."""
+    import numpy as np
+    from oracle.discretization import Discretization
+    from oracle.quadrature import level_symmetric
+    from oracle.sweep import build_graphs, sweep
+    om, w = level_symmetric(wp.sn_order, wp.dim)
+    sel = np.linspace(0, len(w) - 1, n_dirs_sample).round().astype(int)
+    disc = Discretization(wp, omega=om[sel], w=w[sel])
+    gs = build_graphs(disc)
+    phi = np.zeros((disc.E, disc.n))
+    psi = np.zeros((disc.D, disc.E, disc.n))
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        psi, phi = sweep(disc, gs, phi, psi)
+    dt = time.perf_counter() - t0
+    threads = 1
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
+    except Exception:
+        pass
+    value = disc.E * disc.n * disc.D * repeats / dt
+    return {"value": value, "unit": "DOF-dir/s", "cores": threads, "kind": "oracle",
+            "sample": f"{repeats} sweep(s) of {len(sel)} of {len(w)} directions (ids {sel.tolist()}) "
+                      f"on the full mesh, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(DESCRIPTIONS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(directions would be sharded across GPUs with one scalar-flux all-reduce "
+              "per iteration; not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1810_11080_amd import Context, Problem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wp = W.CONFIGS[args.workload]()
+    prec = 0 if args.precision == "fp64" else 1
+    ctx = Context(device=0)
+    t0 = time.perf_counter()
+    P = Problem.from_workload(ctx, wp, precision=prec)
+    setup_s = time.perf_counter() - t0
+    info = P.info()
+    E, n, D = P.E, P.n, P.D
+    phi = torch.zeros(E * n, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(phi)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        P.sweep(phi, out)
+        phi, out = out, phi
+    torch.cuda.synchronize()
+    # timed pass: whole sweeps
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        P.sweep(phi, out)
+        phi, out = out, phi
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    dof_dir = E * n * D
+    value = dof_dir / (ms_per_step * 1e-3)
+
+    # second timed pass: HIP events around every level-sweep launch
+    P.profile_enable(True)
+    for _ in range(args.steps):
+        P.sweep(phi, out)
+        phi, out = out, phi
+    launches, kernel_ms = P.profile_read()
+    P.profile_enable(False)
+    launches_per_sweep = launches / args.steps
+    avg_launch_ms = kernel_ms / launches
+    flops_sweep = flops_per_pair(wp.dim, wp.p) * E * D
+    flops_per_launch = flops_sweep / launches_per_sweep
+    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5),
+                "traffic": None, "kernel": f"sweep_level_fp64<{wp.dim},{wp.p}>",
+                "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+                "launches_per_sweep": launches_per_sweep,
+                "kernel_share_of_step": round(kernel_ms / args.steps / ms_per_step, 4)}
+
+    solve = None
+    if not args.no_solve:
+        P.reset()
+        phi.zero_()
+        rep = P.solve(phi, tol=1e-8, max_iters=2000, check_every=1, raise_on_not_converged=False)
+        solve = {"method": "plain source iteration", "tol": 1e-8, "iterations": rep["iterations"],
+                 "seconds": round(rep["seconds"], 4), "residual": rep["residual"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wp, n_dirs_sample=4 if args.workload in ("c1", "c2") else 2)
+
+    line = {
+        "metric": "DOF-direction updates/s per sweep",
+        "value": value,
+        "unit": "DOF-dir/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": DESCRIPTIONS[args.workload], "elements": E, "dofs_per_element": n,
+                   "directions": D, "levels": info["n_levels_total"],
+                   "lagged_edges": info["n_removed_total"], "kink_face_dirs": info["n_kink_faces_total"],
+                   "setup_s": round(setup_s, 2), "precision": args.precision},
+        "roofline": roofline,
+        "solve_to_1e-8": solve,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * snsweep -- graph-based upwind DG transport sweeps for the steady,
+ * mono-energetic S_N equations on curved high-order quad/hex meshes, on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Haut, Maginot, Tomov, Southworth, Brunner, Bailey, "An Efficient
+ * Sweep-based Solver for the S_N Equations on High-Order Meshes".
+ *   - problem and quadrature: section 2, eqs. linearSnTransport, snScalarFlux;
+ *   - DG operators: eqs. matrixFormLinearTransport .. localFOffDiagonalMatrix;
+ *   - source iteration and lagged sweep: section 3, eqs. sourceIteration,
+ *     fSplitting, laggedSourceIteration;
+ *   - dependency graph, edge weights, SCC + feedback arc set: section 3,
+ *     eq. graphWeight and the text after it.
+ *
+ * Conventions used by every call:
+ *   - All functions return 0 (SNSW_OK) or a negative SNSW_E_* status; the
+ *     message of the last failure on the calling thread is returned by
+ *     snsw_last_error().  No C++ exception crosses this boundary.
+ *   - Host arrays passed to *_create are copied before the call returns; the
+ *     caller keeps ownership and may free them afterwards.
+ *   - Pointers named d_* are device pointers on the context's device, owned
+ *     by the caller (the library never frees them), contiguous, of the stated
+ *     element type.  Work on them is enqueued on the context's stream and is
+ *     complete once that stream is synchronised, unless stated otherwise.
+ *   - Library device memory is allocated by *_create and freed by *_destroy.
+ *   - Handles are not thread-safe: one thread at a time per handle.
+ *
+ * Array layouts (C order, last index fastest):
+ *   lattice  [L_z][L_y][L_x][dim]   control points of the Q_r mesh map,
+ *                                   L_a = r*nx[a] + 1 (x fastest);
+ *   element  e = i + nx*(j + ny*k);
+ *   DOFs     [E][n],   n = (p+1)^dim nodal values at the Gauss-Lobatto
+ *            points of the element, local node m = a + (p+1)*(b + (p+1)*c);
+ *   psi      [D][E][n] angular flux of direction d;
+ *   phi      [E][n]    scalar flux, phi = sum_d w_d psi_d.
+ */
+#ifndef SNSWEEP_H
+#define SNSWEEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define SNSW_OK                0
+#define SNSW_E_INVALID_ARG    -1  /* null pointer, out-of-range value       */
+#define SNSW_E_SHAPE          -2  /* sizes inconsistent with each other      */
+#define SNSW_E_NONFINITE      -3  /* NaN/Inf in an input array               */
+#define SNSW_E_BAD_JACOBIAN   -4  /* det J <= 0 at a quadrature point        */
+#define SNSW_E_NOT_CONVERGED  -5  /* max_iters reached (last iterate kept)   */
+#define SNSW_E_DIVERGED       -6  /* residual became NaN or grew past 1e300  */
+#define SNSW_E_HIP            -7  /* HIP runtime error                       */
+#define SNSW_E_OOM            -8  /* host or device allocation failed        */
+#define SNSW_E_UNSUPPORTED    -9  /* option not supported (e.g. host-only)   */
+#define SNSW_E_STATE         -10  /* call out of order / bad checkpoint      */
+
+/* ------------------------------------------------------------ enumerations */
+#define SNSW_BC_VACUUM     0      /* psi_inc = 0                             */
+#define SNSW_BC_ISO_CONST  1      /* psi_inc = constant on all inflow faces  */
+
+#define SNSW_WEIGHT_UNITY       0 /* z = 1                                   */
+#define SNSW_WEIGHT_FACE        1 /* z = max |F_{e,e'}|                      */
+#define SNSW_WEIGHT_SIGINVFACE  2 /* z = max |M_{t,e}^{-1} F_{e,e'}|          */
+
+#define SNSW_PREC_FP64   0        /* assembly, LU and solve in FP64          */
+#define SNSW_PREC_MIXED  1        /* FP32 LU + one FP64 residual correction  */
+
+typedef struct snsw_ctx snsw_ctx;
+typedef struct snsw_problem snsw_problem;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* snsw_last_error(void);
+
+/* Library version string. */
+const char* snsw_version(void);
+
+/* ---------------------------------------------------------------- context
+ * Binds a device and a HIP stream.  device = -1 makes a host-only context:
+ * problems built on it run the whole host setup (quadrature, geometry,
+ * faces, graph, levels) and support every introspection call, but no device
+ * work (sweep/solve return SNSW_E_UNSUPPORTED).  hip_stream may be NULL (the
+ * default stream) or a hipStream_t on `device` (e.g. the value of
+ * torch.cuda.current_stream().cuda_stream).                                  */
+int  snsw_ctx_create(int device, void* hip_stream, snsw_ctx** out);
+void snsw_ctx_destroy(snsw_ctx* ctx);
+
+/* ---------------------------------------------------------------- problem */
+typedef struct {
+    int32_t dim;             /* 2 or 3                                        */
+    int32_t nx[3];           /* elements per axis (nx[2] ignored in 2D)       */
+    int32_t geom_order;      /* r >= 1: Q_r mesh map (equispaced control pts) */
+    int32_t dg_order;        /* p >= 1: Q_p DG basis at Gauss-Lobatto points  */
+    const double* lattice;   /* control points, layout above                  */
+    int32_t sn_order;        /* level-symmetric S_N order (2,4,..,12), or 0  
+                                to use n_dirs/omega/w below                   */
+    int32_t n_dirs;          /* user quadrature size (sn_order == 0)          */
+    const double* omega;     /* [n_dirs][3] unit directions (sn_order == 0)   */
+    const double* w;         /* [n_dirs] weights, sum 4*pi (sn_order == 0)    */
+    const double* sigma_t;   /* [E] total cross section, > 0                  */
+    const double* sigma_s;   /* [E] scattering cross section, >= 0            */
+    const double* q;         /* [E] (q_per_dof = 0) or [E][n] (= 1): isotropic
+                                source per steradian, nodal values            */
+    int32_t q_per_dof;
+    int32_t bc_kind;         /* SNSW_BC_*                                     */
+    double  psi_inc;         /* incident flux for SNSW_BC_ISO_CONST           */
+    int32_t weighting;       /* SNSW_WEIGHT_*                                 */
+    int32_t exact_scc_max;   /* components up to this size get an exact
+                                minimum feedback arc set (<= 20; paper: 10)   */
+    int32_t precision;       /* SNSW_PREC_*                                   */
+    int32_t n_threads;       /* host threads for setup (0 = hardware count)   */
+} snsw_problem_desc;
+
+/* Builds the discretisation and the sweep schedule (section 3): quadrature,
+ * geometry and element matrices, upwind face integrals, per-direction
+ * dependency graph, cycle cutting and levels; then uploads to the device.
+ * Errors: SNSW_E_INVALID_ARG/SHAPE/NONFINITE for bad inputs,
+ * SNSW_E_BAD_JACOBIAN for an inverted element, SNSW_E_OOM, SNSW_E_HIP.     */
+int  snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc,
+                         snsw_problem** out);
+void snsw_problem_destroy(snsw_problem* prob);
+
+typedef struct {
+    int64_t n_elements, n_dofs_per_element, n_dirs;
+    int64_t n_levels_total;      /* levels of the combined schedule          */
+    int64_t n_pairs;             /* (element, direction) pairs = E*D         */
+    int64_t n_edges_total;       /* dependency edges over all directions     */
+    int64_t n_removed_total;     /* lagged edges over all directions         */
+    int64_t n_kink_faces_total;  /* (face, direction) with a sign change     */
+    double  setup_seconds;       /* host setup wall time                     */
+} snsw_problem_info;
+int snsw_problem_get_info(const snsw_problem* prob, snsw_problem_info* info);
+
+/* Quadrature actually used: omega [D][3], w [D] (host, caller-allocated). */
+int snsw_get_quadrature(const snsw_problem* prob, double* omega, double* w);
+
+/* Direction-independent element matrices of elements [e0, e0+count) (host,
+ * caller-allocated): M [count][n][n] = int u_m u_n, K [count][dim][n][n] =
+ * int (d u_m/d x_i) u_n (row m, column n).                                   */
+int snsw_get_element_matrices(const snsw_problem* prob, int64_t e0,
+                              int64_t count, double* M, double* K);
+
+/* ------------------------------------------------------ graph introspection
+ * Per direction d (host arrays, caller-allocated).                          */
+typedef struct {
+    int64_t n_edges;             /* dependency edges                         */
+    int64_t n_scc_simple;        /* strongly connected components of size 2  */
+    int64_t n_scc_large;         /* components of size >= 3                  */
+    int64_t n_elements_in_large; /* elements in components of size >= 3      */
+    int64_t max_scc;             /* largest component                        */
+    int64_t n_removed;           /* lagged (removed) edges                   */
+    int64_t n_levels;            /* ASAP levels of the cut graph             */
+    int64_t removed_weight;      /* total quantised weight of removed edges  */
+} snsw_graph_stats;
+int snsw_graph_stats_get(const snsw_problem* prob, int d, snsw_graph_stats* st);
+
+/* Edges up -> down (down receives inflow from up) with quantised weights,
+ * sorted by (down, up).  *count receives the number of edges; at most cap
+ * are written.                                                               */
+int snsw_get_edges(const snsw_problem* prob, int d, int32_t* up,
+                   int32_t* down, int64_t* weight, int64_t cap,
+                   int64_t* count);
+/* Lagged edges, sorted by (down, up).                                        */
+int snsw_get_removed_edges(const snsw_problem* prob, int d, int32_t* down,
+                           int32_t* up, int64_t cap, int64_t* count);
+/* ASAP level of every element in the cut graph of direction d, [E].         */
+int snsw_get_levels(const snsw_problem* prob, int d, int32_t* level);
+
+/* ------------------------------------------------------------------- sweep
+ * One lagged transport sweep over all directions (eq. laggedSourceIteration):
+ * reads d_phi_in [E][n], writes d_phi_out [E][n] and, if d_psi_out is not
+ * NULL, the new angular flux [D][E][n].  Lagged couplings read the angular
+ * flux of the previous sweep kept inside the problem (zero after create or
+ * snsw_reset); the new flux replaces it.  Asynchronous on the ctx stream.   */
+int snsw_sweep(snsw_problem* prob, const double* d_phi_in, double* d_phi_out,
+               double* d_psi_out);
+
+/* Clears the stored angular flux used by lagged couplings.                  */
+int snsw_reset(snsw_problem* prob);
+
+/* ------------------------------------------------------------------- solve
+ * Source iteration (eq. sourceIteration) from the guess in d_phi until
+ * max|phi_{l+1}-phi_l| / max|phi_{l+1}| <= tol (checked every check_every
+ * iterations; only then does the host wait for the device).  d_phi [E][n]
+ * receives the last iterate; d_psi (nullable) its angular flux.  The
+ * residual history is written to report->history if non-NULL (capacity
+ * history_cap).  Returns SNSW_E_NOT_CONVERGED after max_iters (result
+ * kept), SNSW_E_DIVERGED on NaN/overflow.  Synchronous.                     */
+typedef struct {
+    double  tol;
+    int32_t max_iters;
+    int32_t check_every;         /* >= 1                                     */
+} snsw_solve_opts;
+typedef struct {
+    int32_t iterations;
+    double  residual;
+    double  seconds;
+    double* history;             /* caller buffer or NULL                    */
+    int32_t history_cap;
+} snsw_solve_report;
+int snsw_solve(snsw_problem* prob, const snsw_solve_opts* opts, double* d_phi,
+               double* d_psi, snsw_solve_report* report);
+
+/* Relative L-infinity residual of two device scalar-flux vectors:
+ * max|a-b| / max|a| in FP64 (synchronous).                                  */
+int snsw_residual(snsw_problem* prob, const double* d_a, const double* d_b,
+                  double* out);
+
+/* --------------------------------------------------------------- profiling
+ * While enabled, every level-sweep kernel launch is bracketed by two HIP
+ * events on the ctx stream.  snsw_profile_read waits for the stream and
+ * returns the number of level launches and their summed kernel time (ms)
+ * since the last read, then clears the counters.                            */
+int snsw_profile_enable(snsw_problem* prob, int enable);
+int snsw_profile_read(snsw_problem* prob, int64_t* launches, double* kernel_ms);
+
+/* ---------------------------------------------------------- checkpointing
+ * Source-iteration state = the stored angular flux of the previous sweep.
+ * snsw_state_size gives the bytes; save copies it to host memory, load
+ * restores it (same problem shape; SNSW_E_STATE otherwise).  Synchronous.   */
+int snsw_state_size(const snsw_problem* prob, size_t* bytes);
+int snsw_state_save(const snsw_problem* prob, void* host_buf, size_t cap);
+int snsw_state_load(snsw_problem* prob, const void* host_buf, size_t size);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNSWEEP_H */

@@ -1,0 +1,345 @@
+"""ctypes binding of libsnsweep.so (argument marshalling only).
+
+Every ``snsw_*`` function of ``include/snsweep.h`` is available under the
+same name through :func:`lib`; :class:`Context` and :class:`Problem` wrap the
+handles.  Device arrays are PyTorch tensors (float64, contiguous, on the
+context's device); only their data pointers cross the boundary.  There is no
+fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+c_double_p = C.POINTER(C.c_double)
+c_int32_p = C.POINTER(C.c_int32)
+c_int64_p = C.POINTER(C.c_int64)
+
+
+class SnswProblemDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32 * 3), ("geom_order", C.c_int32),
+                ("dg_order", C.c_int32), ("lattice", c_double_p), ("sn_order", C.c_int32),
+                ("n_dirs", C.c_int32), ("omega", c_double_p), ("w", c_double_p),
+                ("sigma_t", c_double_p), ("sigma_s", c_double_p), ("q", c_double_p),
+                ("q_per_dof", C.c_int32), ("bc_kind", C.c_int32), ("psi_inc", C.c_double),
+                ("weighting", C.c_int32), ("exact_scc_max", C.c_int32),
+                ("precision", C.c_int32), ("n_threads", C.c_int32)]
+
+
+class SnswProblemInfo(C.Structure):
+    _fields_ = [("n_elements", C.c_int64), ("n_dofs_per_element", C.c_int64),
+                ("n_dirs", C.c_int64), ("n_levels_total", C.c_int64), ("n_pairs", C.c_int64),
+                ("n_edges_total", C.c_int64), ("n_removed_total", C.c_int64),
+                ("n_kink_faces_total", C.c_int64), ("setup_seconds", C.c_double)]
+
+
+class SnswGraphStats(C.Structure):
+    _fields_ = [("n_edges", C.c_int64), ("n_scc_simple", C.c_int64), ("n_scc_large", C.c_int64),
+                ("n_elements_in_large", C.c_int64), ("max_scc", C.c_int64),
+                ("n_removed", C.c_int64), ("n_levels", C.c_int64), ("removed_weight", C.c_int64)]
+
+
+class SnswSolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("check_every", C.c_int32)]
+
+
+class SnswSolveReport(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("residual", C.c_double), ("seconds", C.c_double),
+                ("history", c_double_p), ("history_cap", C.c_int32)]
+
+
+# name -> (restype, argtypes); mirrors include/snsweep.h
+SIGNATURES = {
+    "snsw_last_error": (C.c_char_p, []),
+    "snsw_version": (C.c_char_p, []),
+    "snsw_ctx_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "snsw_ctx_destroy": (None, [C.c_void_p]),
+    "snsw_problem_create": (C.c_int, [C.c_void_p, C.POINTER(SnswProblemDesc), C.POINTER(C.c_void_p)]),
+    "snsw_problem_destroy": (None, [C.c_void_p]),
+    "snsw_problem_get_info": (C.c_int, [C.c_void_p, C.POINTER(SnswProblemInfo)]),
+    "snsw_get_quadrature": (C.c_int, [C.c_void_p, c_double_p, c_double_p]),
+    "snsw_get_element_matrices": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, c_double_p, c_double_p]),
+    "snsw_graph_stats_get": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(SnswGraphStats)]),
+    "snsw_get_edges": (C.c_int, [C.c_void_p, C.c_int, c_int32_p, c_int32_p, c_int64_p, C.c_int64,
+                                 c_int64_p]),
+    "snsw_get_removed_edges": (C.c_int, [C.c_void_p, C.c_int, c_int32_p, c_int32_p, C.c_int64,
+                                         c_int64_p]),
+    "snsw_get_levels": (C.c_int, [C.c_void_p, C.c_int, c_int32_p]),
+    "snsw_sweep": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "snsw_reset": (C.c_int, [C.c_void_p]),
+    "snsw_solve": (C.c_int, [C.c_void_p, C.POINTER(SnswSolveOpts), C.c_void_p, C.c_void_p,
+                             C.POINTER(SnswSolveReport)]),
+    "snsw_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, c_double_p]),
+    "snsw_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "snsw_profile_read": (C.c_int, [C.c_void_p, c_int64_p, c_double_p]),
+    "snsw_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "snsw_state_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "snsw_state_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+}
+
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "SHAPE", -3: "NONFINITE", -4: "BAD_JACOBIAN",
+          -5: "NOT_CONVERGED", -6: "DIVERGED", -7: "HIP", -8: "OOM", -9: "UNSUPPORTED",
+          -10: "STATE"}
+
+
+class SnswError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"snsweep error {code} ({STATUS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+def library_path() -> str:
+    return os.environ.get("SNSWEEP_LIB", os.path.join(_HERE, "libsnsweep.so"))
+
+
+def lib():
+    """Load libsnsweep.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_1810_11080_amd.build`")
+        L = C.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise SnswError(rc, lib().snsw_last_error().decode())
+
+
+def _dptr(a: np.ndarray, dtype):
+    return a.ctypes.data_as(C.POINTER(dtype))
+
+
+def _tensor_ptr(t, numel: int, device: int, name: str):
+    """Data pointer of a float64 contiguous device tensor of numel entries."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+        raise TypeError(f"{name} must be a contiguous float64 device tensor")
+    if t.device.index != device:
+        raise ValueError(f"{name} is on device {t.device.index}, context uses {device}")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {numel}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        """device = -1: host-only (setup and introspection only)."""
+        self.device = device
+        if stream is None and device >= 0:
+            import torch
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        sp = C.c_void_p(stream.cuda_stream) if stream is not None else C.c_void_p()
+        _check(lib().snsw_ctx_create(device, sp, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().snsw_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """A discretised S_N problem with its sweep schedule."""
+
+    def __init__(self, ctx: Context, *, dim, nx, geom_order, dg_order, lattice, sn_order,
+                 sigma_t, sigma_s, q, bc_kind=0, psi_inc=0.0, weighting=1, exact_scc_max=10,
+                 precision=0, n_threads=0, omega=None, w=None):
+        self.ctx = ctx
+        if dim not in (2, 3):
+            raise SnswError(-1, "dim must be 2 or 3")
+        E = int(np.prod(nx[:dim]))
+        n = (dg_order + 1) ** dim
+        self._keep = []
+
+        def arr(x, size=None):
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+            if size is not None and a.size != size:
+                raise ValueError(f"array has {a.size} entries, expected {size}")
+            self._keep.append(a)
+            return _dptr(a, C.c_double)
+
+        desc = SnswProblemDesc()
+        desc.dim = dim
+        for a in range(3):
+            desc.nx[a] = int(nx[a]) if a < len(nx) else 1
+        desc.geom_order = geom_order
+        desc.dg_order = dg_order
+        L = int(np.prod([geom_order * int(nx[a]) + 1 for a in range(dim)]))
+        desc.lattice = arr(lattice, L * dim)
+        desc.sn_order = sn_order if omega is None else 0
+        if omega is not None:
+            desc.n_dirs = len(w)
+            desc.omega = arr(omega, 3 * len(w))
+            desc.w = arr(w, len(w))
+        desc.sigma_t = arr(sigma_t, E)
+        desc.sigma_s = arr(sigma_s, E)
+        qa = np.asarray(q, dtype=np.float64)
+        desc.q_per_dof = 1 if qa.size == E * n and qa.size != E else 0
+        desc.q = arr(qa, E * n if desc.q_per_dof else E)
+        desc.bc_kind = bc_kind
+        desc.psi_inc = psi_inc
+        desc.weighting = weighting
+        desc.exact_scc_max = exact_scc_max
+        desc.precision = precision
+        desc.n_threads = n_threads
+        h = C.c_void_p()
+        _check(lib().snsw_problem_create(ctx.handle, C.byref(desc), C.byref(h)))
+        self.handle = h
+        self._keep = []
+        info = self.info()
+        self.E, self.n, self.D = info["n_elements"], info["n_dofs_per_element"], info["n_dirs"]
+        self.dim = dim
+
+    @classmethod
+    def from_workload(cls, ctx: Context, prob, precision=0, n_threads=0, weighting=None,
+                      exact_scc_max=None):
+        """Build from a ``workloads.Problem`` (seeded synthetic inputs)."""
+        return cls(ctx, dim=prob.dim, nx=tuple(prob.nx), geom_order=prob.r, dg_order=prob.p,
+                   lattice=prob.lattice, sn_order=prob.sn_order, sigma_t=prob.sigma_t,
+                   sigma_s=prob.sigma_s, q=prob.q, bc_kind=prob.bc_kind, psi_inc=prob.psi_inc,
+                   weighting=prob.weighting if weighting is None else weighting,
+                   exact_scc_max=prob.exact_scc_max if exact_scc_max is None else exact_scc_max,
+                   precision=precision, n_threads=n_threads)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().snsw_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ introspection
+    def info(self) -> dict:
+        i = SnswProblemInfo()
+        _check(lib().snsw_problem_get_info(self.handle, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in SnswProblemInfo._fields_}
+
+    def quadrature(self):
+        om = np.zeros((self.D, 3))
+        w = np.zeros(self.D)
+        _check(lib().snsw_get_quadrature(self.handle, _dptr(om, C.c_double), _dptr(w, C.c_double)))
+        return om, w
+
+    def element_matrices(self, e0=0, count=None):
+        count = self.E - e0 if count is None else count
+        M = np.zeros((count, self.n, self.n))
+        K = np.zeros((count, self.dim, self.n, self.n))
+        _check(lib().snsw_get_element_matrices(self.handle, e0, count, _dptr(M, C.c_double),
+                                               _dptr(K, C.c_double)))
+        return M, K
+
+    def graph_stats(self, d: int) -> dict:
+        s = SnswGraphStats()
+        _check(lib().snsw_graph_stats_get(self.handle, d, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in SnswGraphStats._fields_}
+
+    def edges(self, d: int):
+        cnt = C.c_int64()
+        _check(lib().snsw_get_edges(self.handle, d, None, None, None, 0, C.byref(cnt)))
+        m = cnt.value
+        up = np.zeros(m, dtype=np.int32)
+        down = np.zeros(m, dtype=np.int32)
+        w = np.zeros(m, dtype=np.int64)
+        _check(lib().snsw_get_edges(self.handle, d, _dptr(up, C.c_int32), _dptr(down, C.c_int32),
+                                    _dptr(w, C.c_int64), m, C.byref(cnt)))
+        return up, down, w
+
+    def removed_edges(self, d: int):
+        cnt = C.c_int64()
+        _check(lib().snsw_get_removed_edges(self.handle, d, None, None, 0, C.byref(cnt)))
+        m = cnt.value
+        down = np.zeros(m, dtype=np.int32)
+        up = np.zeros(m, dtype=np.int32)
+        _check(lib().snsw_get_removed_edges(self.handle, d, _dptr(down, C.c_int32),
+                                            _dptr(up, C.c_int32), m, C.byref(cnt)))
+        return down, up
+
+    def levels(self, d: int):
+        lev = np.zeros(self.E, dtype=np.int32)
+        _check(lib().snsw_get_levels(self.handle, d, _dptr(lev, C.c_int32)))
+        return lev
+
+    # ------------------------------------------------------------------ device
+    def sweep(self, phi_in, phi_out, psi_out=None):
+        dev = self.ctx.device
+        a = _tensor_ptr(phi_in, self.E * self.n, dev, "phi_in")
+        b = _tensor_ptr(phi_out, self.E * self.n, dev, "phi_out")
+        c = _tensor_ptr(psi_out, self.D * self.E * self.n, dev, "psi_out") if psi_out is not None \
+            else C.c_void_p()
+        _check(lib().snsw_sweep(self.handle, a, b, c))
+
+    def reset(self):
+        _check(lib().snsw_reset(self.handle))
+
+    def residual(self, a, b) -> float:
+        out = C.c_double()
+        dev = self.ctx.device
+        _check(lib().snsw_residual(self.handle, _tensor_ptr(a, self.E * self.n, dev, "a"),
+                                   _tensor_ptr(b, self.E * self.n, dev, "b"), C.byref(out)))
+        return out.value
+
+    def solve(self, phi, tol=1e-8, max_iters=1000, check_every=1, psi=None, history_cap=0,
+              raise_on_not_converged=True):
+        dev = self.ctx.device
+        opts = SnswSolveOpts(tol=tol, max_iters=max_iters, check_every=check_every)
+        hist = np.zeros(max(history_cap, 1))
+        rep = SnswSolveReport()
+        rep.history = _dptr(hist, C.c_double) if history_cap else None
+        rep.history_cap = history_cap
+        pp = _tensor_ptr(psi, self.D * self.E * self.n, dev, "psi") if psi is not None else C.c_void_p()
+        rc = lib().snsw_solve(self.handle, C.byref(opts), _tensor_ptr(phi, self.E * self.n, dev, "phi"),
+                              pp, C.byref(rep))
+        if rc != 0 and (raise_on_not_converged or rc != -5):
+            _check(rc)
+        n_hist = min(history_cap, rep.iterations)
+        return {"iterations": rep.iterations, "residual": rep.residual, "seconds": rep.seconds,
+                "history": hist[:n_hist].copy() if history_cap else None, "status": rc}
+
+    def profile_enable(self, enable: bool = True):
+        _check(lib().snsw_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        """(level launches, summed kernel milliseconds) since the last read."""
+        n = C.c_int64()
+        ms = C.c_double()
+        _check(lib().snsw_profile_read(self.handle, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    def state_save(self) -> bytes:
+        size = C.c_size_t()
+        _check(lib().snsw_state_size(self.handle, C.byref(size)))
+        buf = C.create_string_buffer(size.value)
+        _check(lib().snsw_state_save(self.handle, buf, size.value))
+        return buf.raw
+
+    def state_load(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        _check(lib().snsw_state_load(self.handle, buf, len(data)))

@@ -1,0 +1,382 @@
+// Faces of the structured curved mesh and the upwind face integrals.
+//
+// Numbering: for each reference axis a, faces lie on lattice planes
+// P = 0..nx[a]; the element with index P-1 along a is the face's minus
+// element, the one with index P its plus element (-1 on the boundary).  A face
+// is parametrised by the remaining axes in ascending order (s, t); N is the
+// area-scaled normal from minus to plus (2D axis 0: (t_y, -t_x), axis 1:
+// (-t_y, t_x); 3D axes 0, 2: x_s x x_t, axis 1: x_t x x_s), so that
+// (Omega . n) ds = (Omega . N) ds_ref and g = Omega . N.
+//
+// Face matrices of the upwind DG operator (eqs. localFDiagonalMatrix and
+// localFOffDiagonalMatrix): P_plus[a][b] = int max(g,0) phi_a phi_b and
+// P_minus[a][b] = int max(-g,0) phi_a phi_b over the reference face.  For a
+// face without a sign change of g these are +-sum_k Omega_k B_k with the
+// direction-independent moments B_k[a][b] = int N_k phi_a phi_b (exact Gauss
+// rule).  Faces where g changes sign ("re-entrant faces", non-smooth
+// integrand) are integrated
+//   2D: exactly, splitting [0,1] at the real roots of the polynomial g(s)
+//       (degree r-1 <= 2) and using ceil((r+2p)/2) Gauss points per piece;
+//   3D: with a fixed composite rule of 4x4 sub-squares, (p+r)^2 Gauss points
+//       each (the rule also decides whether a sign change is present).
+// Interior faces: a side whose measure int max(+-g,0) is at most 1e-12 of
+// int |g| is dropped (matrix set to zero), so the operator and the graph
+// agree.
+#include <algorithm>
+#include <cmath>
+
+#include "host.hpp"
+
+namespace snsw {
+
+namespace {
+constexpr int kSub3 = 4;
+}  // namespace
+
+void build_faces(HostProblem& hp) {
+    const int dim = hp.dim, r = hp.r, p = hp.p;
+    const int nf = hp.nf;
+    int L[3] = {1, 1, 1};
+    for (int a = 0; a < dim; ++a) L[a] = r * hp.nx[a] + 1;
+    const int nloc = dim == 2 ? r + 1 : (r + 1) * (r + 1);
+    hp.f_axis.clear(); hp.f_minus.clear(); hp.f_plus.clear(); hp.f_ctrl.clear();
+    std::vector<int64_t> axis_off(dim);
+    int64_t off = 0;
+    for (int a = 0; a < dim; ++a) {
+        axis_off[a] = off;
+        int ext[3] = {1, 1, 1};
+        for (int b = 0; b < dim; ++b) ext[b] = hp.nx[b] + (b == a ? 1 : 0);
+        int64_t nfa = 1;
+        for (int b = 0; b < dim; ++b) nfa *= ext[b];
+        int others[2] = {0, 0}, no = 0;
+        for (int b = 0; b < dim; ++b) if (b != a) others[no++] = b;
+        for (int64_t fi = 0; fi < nfa; ++fi) {
+            int idx[3] = {0, 0, 0};
+            int64_t rem = fi;
+            for (int b = 0; b < dim; ++b) { idx[b] = (int)(rem % ext[b]); rem /= ext[b]; }
+            const int P = idx[a];
+            auto elem = [&](int pa) -> int32_t {
+                int64_t e = 0, s = 1;
+                for (int b = 0; b < dim; ++b) { e += (b == a ? pa : idx[b]) * s; s *= hp.nx[b]; }
+                return (int32_t)e;
+            };
+            hp.f_axis.push_back(a);
+            hp.f_minus.push_back(P >= 1 ? elem(P - 1) : -1);
+            hp.f_plus.push_back(P < hp.nx[a] ? elem(P) : -1);
+            for (int l = 0; l < nloc; ++l) {
+                int li[2] = {l % (r + 1), l / (r + 1)};
+                int64_t lid = 0, stride = 1;
+                for (int b = 0; b < dim; ++b) {
+                    int coord;
+                    if (b == a) coord = r * P;
+                    else {
+                        int k = (b == others[0]) ? 0 : 1;
+                        coord = r * idx[b] + li[k];
+                    }
+                    lid += (int64_t)coord * stride;
+                    stride *= L[b];
+                }
+                for (int c = 0; c < dim; ++c) hp.f_ctrl.push_back(hp.lattice[lid * dim + c]);
+            }
+        }
+        off += nfa;
+    }
+    hp.F = off;
+    // element slots: slot 2a is the xi_a = 0 face (element = plus side),
+    // slot 2a+1 the xi_a = 1 face (element = minus side)
+    hp.nslot = 2 * dim;
+    hp.slot_face.assign((size_t)hp.E * hp.nslot, -1);
+    hp.slot_nbr.assign((size_t)hp.E * hp.nslot, -1);
+    for (int64_t e = 0; e < hp.E; ++e) {
+        int ei[3] = {0, 0, 0};
+        int64_t re = e;
+        for (int b = 0; b < dim; ++b) { ei[b] = (int)(re % hp.nx[b]); re /= hp.nx[b]; }
+        for (int s = 0; s < hp.nslot; ++s) {
+            const int a = s / 2, hi = s % 2;
+            int ext[3] = {1, 1, 1};
+            for (int b = 0; b < dim; ++b) ext[b] = hp.nx[b] + (b == a ? 1 : 0);
+            int64_t fid = 0, st = 1;
+            for (int b = 0; b < dim; ++b) { fid += (ei[b] + (b == a ? hi : 0)) * st; st *= ext[b]; }
+            fid += axis_off[a];
+            hp.slot_face[e * hp.nslot + s] = (int32_t)fid;
+            hp.slot_nbr[e * hp.nslot + s] = hi ? hp.f_plus[fid] : hp.f_minus[fid];
+        }
+    }
+    hp.slot_nodes.assign((size_t)hp.nslot * nf, 0);
+    for (int s = 0; s < hp.nslot; ++s) {
+        const int a = s / 2, hi = s % 2;
+        for (int l = 0; l < nf; ++l) {
+            int idx[3] = {0, 0, 0}, rem = l;
+            for (int b = 0; b < dim; ++b) {
+                if (b == a) continue;
+                idx[b] = rem % (p + 1);
+                rem /= p + 1;
+            }
+            idx[a] = hi ? p : 0;
+            int m = 0, st = 1;
+            for (int b = 0; b < dim; ++b) { m += idx[b] * st; st *= p + 1; }
+            hp.slot_nodes[s * nf + l] = m;
+        }
+    }
+
+    // normal moments B_k and int N_k with an exact Gauss rule
+    std::vector<double> geo_nodes(r + 1);
+    for (int a = 0; a <= r; ++a) geo_nodes[a] = (double)a / r;
+    const std::vector<double> dg = gll01(p);
+    const int nq1 = dim == 2 ? (r + 2 * p + 1) / 2 : p + r;
+    std::vector<double> x1, w1;
+    gauss_legendre01(nq1, x1, w1);
+    std::vector<double> gV(nq1 * (r + 1)), gD(nq1 * (r + 1)), uV(nq1 * (p + 1));
+    for (int k = 0; k < nq1; ++k) {
+        lagrange_eval(geo_nodes, x1[k], &gV[k * (r + 1)], &gD[k * (r + 1)]);
+        lagrange_eval(dg, x1[k], &uV[k * (p + 1)], nullptr);
+    }
+    hp.B.assign((size_t)hp.F * dim * nf * nf, 0.0);
+    hp.Nint.assign((size_t)hp.F * dim, 0.0);
+    FaceNormalData& nd = hp.fnd;
+    nd = FaceNormalData();
+    if (dim == 2) nd.mono.assign((size_t)hp.F * 2 * r, 0.0);
+    // 3D composite rule tables
+    if (dim == 3) {
+        std::vector<double> xs, ws;
+        gauss_legendre01(p + r, xs, ws);
+        nd.nc1 = kSub3 * (p + r);
+        std::vector<double> c1(nd.nc1), cw1(nd.nc1);
+        for (int k = 0; k < kSub3; ++k)
+            for (int j = 0; j < p + r; ++j) {
+                c1[k * (p + r) + j] = (k + xs[j]) / kSub3;
+                cw1[k * (p + r) + j] = ws[j] / kSub3;
+            }
+        nd.gV1.assign(nd.nc1 * (r + 1), 0.0);
+        nd.gD1.assign(nd.nc1 * (r + 1), 0.0);
+        std::vector<double> u1(nd.nc1 * (p + 1));
+        for (int k = 0; k < nd.nc1; ++k) {
+            lagrange_eval(geo_nodes, c1[k], &nd.gV1[k * (r + 1)], &nd.gD1[k * (r + 1)]);
+            lagrange_eval(dg, c1[k], &u1[k * (p + 1)], nullptr);
+        }
+        for (int j = 0; j < nd.nc1; ++j)
+            for (int i = 0; i < nd.nc1; ++i) {
+                nd.ci.push_back(i);
+                nd.cj.push_back(j);
+                nd.cs.push_back(c1[i]);
+                nd.ct.push_back(c1[j]);
+                nd.cw.push_back(cw1[i] * cw1[j]);
+                for (int bt = 0; bt <= p; ++bt)
+                    for (int bs = 0; bs <= p; ++bs)
+                        nd.cphi.push_back(u1[i * (p + 1) + bs] * u1[j * (p + 1) + bt]);
+            }
+        nd.Rf.assign(hp.F, 0.0);
+    }
+    auto dmono = lagrange_derivative_monomials(geo_nodes);
+
+    parallel_for(hp.F, hp.nthreads, [&](int64_t f0, int64_t f1) {
+        std::vector<double> phi(nf);
+        for (int64_t f = f0; f < f1; ++f) {
+            const double* X = &hp.f_ctrl[(size_t)f * nloc * dim];
+            const int a = hp.f_axis[f];
+            double* Bf = &hp.B[(size_t)f * dim * nf * nf];
+            double* Nf = &hp.Nint[(size_t)f * dim];
+            if (dim == 2) {
+                const double sg = a == 0 ? 1.0 : -1.0;
+                for (int q = 0; q < nq1; ++q) {
+                    double tx = 0, ty = 0;
+                    for (int b = 0; b <= r; ++b) {
+                        tx += X[b * 2 + 0] * gD[q * (r + 1) + b];
+                        ty += X[b * 2 + 1] * gD[q * (r + 1) + b];
+                    }
+                    const double N[2] = {sg * ty, -sg * tx};
+                    for (int k = 0; k < 2; ++k) {
+                        Nf[k] += w1[q] * N[k];
+                        for (int i = 0; i < nf; ++i)
+                            for (int j = 0; j < nf; ++j)
+                                Bf[(k * nf + i) * nf + j] += w1[q] * N[k] * uV[q * (p + 1) + i] * uV[q * (p + 1) + j];
+                    }
+                }
+                double* mo = &nd.mono[(size_t)f * 2 * r];
+                for (int b = 0; b <= r; ++b)
+                    for (int k = 0; k < r; ++k) {
+                        double dk = k < (int)dmono[b].size() ? dmono[b][k] : 0.0;
+                        mo[0 * r + k] += sg * X[b * 2 + 1] * dk;    // N_x = sg * t_y
+                        mo[1 * r + k] += -sg * X[b * 2 + 0] * dk;   // N_y = -sg * t_x
+                    }
+            } else {
+                auto normal_at = [&](const double* Vs, const double* Ds, const double* Vt,
+                                     const double* Dt, double* N) {
+                    double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0};
+                    for (int bt = 0; bt <= r; ++bt)
+                        for (int bs = 0; bs <= r; ++bs) {
+                            const double* x = &X[(bt * (r + 1) + bs) * 3];
+                            for (int c = 0; c < 3; ++c) {
+                                t1[c] += x[c] * Ds[bs] * Vt[bt];
+                                t2[c] += x[c] * Vs[bs] * Dt[bt];
+                            }
+                        }
+                    double c0 = t1[1] * t2[2] - t1[2] * t2[1];
+                    double c1 = t1[2] * t2[0] - t1[0] * t2[2];
+                    double c2 = t1[0] * t2[1] - t1[1] * t2[0];
+                    const double sgn = a == 1 ? -1.0 : 1.0;
+                    N[0] = sgn * c0; N[1] = sgn * c1; N[2] = sgn * c2;
+                };
+                for (int qt = 0; qt < nq1; ++qt)
+                    for (int qs = 0; qs < nq1; ++qs) {
+                        double N[3];
+                        normal_at(&gV[qs * (r + 1)], &gD[qs * (r + 1)], &gV[qt * (r + 1)], &gD[qt * (r + 1)], N);
+                        const double wq = w1[qs] * w1[qt];
+                        for (int bt = 0; bt <= p; ++bt)
+                            for (int bs = 0; bs <= p; ++bs)
+                                phi[bt * (p + 1) + bs] = uV[qs * (p + 1) + bs] * uV[qt * (p + 1) + bt];
+                        for (int k = 0; k < 3; ++k) {
+                            Nf[k] += wq * N[k];
+                            for (int i = 0; i < nf; ++i)
+                                for (int j = 0; j < nf; ++j) Bf[(k * nf + i) * nf + j] += wq * N[k] * phi[i] * phi[j];
+                        }
+                    }
+                // bound of |N - Nbar| over the composite rule points
+                double R = 0.0;
+                const size_t Qc = nd.cw.size();
+                for (size_t q = 0; q < Qc; ++q) {
+                    double N[3];
+                    const int i = nd.ci[q], j = nd.cj[q];
+                    normal_at(&nd.gV1[i * (r + 1)], &nd.gD1[i * (r + 1)], &nd.gV1[j * (r + 1)],
+                              &nd.gD1[j * (r + 1)], N);
+                    double dx = N[0] - Nf[0], dy = N[1] - Nf[1], dz = N[2] - Nf[2];
+                    R = std::max(R, std::sqrt(dx * dx + dy * dy + dz * dz));
+                }
+                nd.Rf[f] = R;
+            }
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Integrals of one face for direction om.  Returns the class; measures
+// mp = int max(g,0), mm = int max(-g,0); for FC_KINK also Pp, Pm (nf x nf).
+uint8_t face_integrals(const HostProblem& hp, int64_t f, const double* om, double& mp,
+                       double& mm, double* Pp, double* Pm);
+
+uint8_t face_integrals(const HostProblem& hp, int64_t f, const double* om, double& mp,
+                       double& mm, double* Pp, double* Pm) {
+    const int dim = hp.dim, r = hp.r, p = hp.p, nf = hp.nf;
+    const FaceNormalData& nd = hp.fnd;
+    const double* Nf = &hp.Nint[(size_t)f * dim];
+    double gbar = 0.0;
+    for (int k = 0; k < dim; ++k) gbar += om[k] * Nf[k];
+    if (dim == 2) {
+        const double* mo = &nd.mono[(size_t)f * 2 * r];
+        double c[4] = {0, 0, 0, 0};
+        for (int k = 0; k < r; ++k) c[k] = om[0] * mo[k] + om[1] * mo[r + k];
+        double roots[2];
+        int nr = 0;
+        auto push = [&](double s) { if (s > 0.0 && s < 1.0) roots[nr++] = s; };
+        if (r == 2) {
+            if (c[1] != 0.0) push(-c[0] / c[1]);
+        } else if (r == 3) {
+            const double A = c[2], Bq = c[1], C = c[0];
+            if (A == 0.0) {
+                if (Bq != 0.0) push(-C / Bq);
+            } else {
+                const double disc = Bq * Bq - 4.0 * A * C;
+                if (disc > 0.0) {
+                    const double sq = std::sqrt(disc);
+                    const double qq = -0.5 * (Bq + (Bq >= 0.0 ? sq : -sq));
+                    push(qq / A);
+                    if (qq != 0.0) push(C / qq);
+                }
+            }
+        } else if (r > 3) {
+            throw Error(SNSW_E_UNSUPPORTED, "2D geometry order r > 3 is not supported");
+        }
+        if (nr == 0) {
+            // no sign change inside the face: sign of g at the midpoint
+            double gm = 0.0, sp = 1.0;
+            for (int k = 0; k < r; ++k) { gm += c[k] * sp; sp *= 0.5; }
+            if (gm >= 0.0) { mp = gbar; mm = 0.0; return FC_POS; }
+            mp = 0.0; mm = -gbar; return FC_NEG;
+        }
+        if (nr == 2 && roots[1] < roots[0]) std::swap(roots[0], roots[1]);
+        double bp[4] = {0.0, 0, 0, 0};
+        int nb = 1;
+        for (int i = 0; i < nr; ++i) bp[nb++] = roots[i];
+        bp[nb++] = 1.0;
+        const int ng = (r + 2 * p + 1) / 2;
+        std::vector<double> xg, wg;
+        gauss_legendre01(ng, xg, wg);
+        const std::vector<double> dg = gll01(p);
+        std::fill(Pp, Pp + nf * nf, 0.0);
+        std::fill(Pm, Pm + nf * nf, 0.0);
+        mp = mm = 0.0;
+        double phi[8];
+        for (int piece = 0; piece + 1 < nb; ++piece) {
+            const double s0 = bp[piece], h = bp[piece + 1] - bp[piece];
+            for (int q = 0; q < ng; ++q) {
+                const double s = s0 + h * xg[q], ww = h * wg[q];
+                double g = 0.0, sp = 1.0;
+                for (int k = 0; k < r; ++k) { g += c[k] * sp; sp *= s; }
+                lagrange_eval(dg, s, phi, nullptr);
+                const double wp = ww * std::max(g, 0.0), wm = ww * std::max(-g, 0.0);
+                mp += wp;
+                mm += wm;
+                for (int i = 0; i < nf; ++i)
+                    for (int j = 0; j < nf; ++j) {
+                        Pp[i * nf + j] += wp * phi[i] * phi[j];
+                        Pm[i * nf + j] += wm * phi[i] * phi[j];
+                    }
+            }
+        }
+        return FC_KINK;
+    }
+    // 3D: cheap bound first
+    const double R = nd.Rf[f];
+    if (std::fabs(gbar) > R * (1.0 + 1e-9) + 1e-300) {
+        if (gbar > 0.0) { mp = gbar; mm = 0.0; return FC_POS; }
+        mp = 0.0; mm = -gbar; return FC_NEG;
+    }
+    const double* X = &hp.f_ctrl[(size_t)f * (r + 1) * (r + 1) * 3];
+    const int a = hp.f_axis[f];
+    const size_t Qc = nd.cw.size();
+    std::vector<double> g(Qc);
+    double gmin = 1e300, gmax = -1e300;
+    for (size_t q = 0; q < Qc; ++q) {
+        const int i = nd.ci[q], j = nd.cj[q];
+        const double* Vs = &nd.gV1[i * (r + 1)];
+        const double* Ds = &nd.gD1[i * (r + 1)];
+        const double* Vt = &nd.gV1[j * (r + 1)];
+        const double* Dt = &nd.gD1[j * (r + 1)];
+        double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0};
+        for (int bt = 0; bt <= r; ++bt)
+            for (int bs = 0; bs <= r; ++bs) {
+                const double* x = &X[(bt * (r + 1) + bs) * 3];
+                for (int cc = 0; cc < 3; ++cc) {
+                    t1[cc] += x[cc] * Ds[bs] * Vt[bt];
+                    t2[cc] += x[cc] * Vs[bs] * Dt[bt];
+                }
+            }
+        double N0 = t1[1] * t2[2] - t1[2] * t2[1];
+        double N1 = t1[2] * t2[0] - t1[0] * t2[2];
+        double N2 = t1[0] * t2[1] - t1[1] * t2[0];
+        if (a == 1) { N0 = -N0; N1 = -N1; N2 = -N2; }
+        g[q] = om[0] * N0 + om[1] * N1 + om[2] * N2;
+        gmin = std::min(gmin, g[q]);
+        gmax = std::max(gmax, g[q]);
+    }
+    if (gmin >= 0.0) { mp = gbar; mm = 0.0; return FC_POS; }
+    if (gmax <= 0.0) { mp = 0.0; mm = -gbar; return FC_NEG; }
+    std::fill(Pp, Pp + nf * nf, 0.0);
+    std::fill(Pm, Pm + nf * nf, 0.0);
+    mp = mm = 0.0;
+    for (size_t q = 0; q < Qc; ++q) {
+        const double wp = nd.cw[q] * std::max(g[q], 0.0), wm = nd.cw[q] * std::max(-g[q], 0.0);
+        mp += wp;
+        mm += wm;
+        const double* ph = &nd.cphi[q * nf];
+        for (int i = 0; i < nf; ++i)
+            for (int j = 0; j < nf; ++j) {
+                Pp[i * nf + j] += wp * ph[i] * ph[j];
+                Pm[i * nf + j] += wm * ph[i] * ph[j];
+            }
+    }
+    (void)p;
+    return FC_KINK;
+}
+
+}  // namespace snsw

@@ -1,0 +1,144 @@
+// Element geometry and direction-independent element matrices.
+//
+// Mesh map T_e(xi) = sum_m x_{e,m} v_m(xi), Q_r Lagrange at equispaced
+// control points (eq. elementTransformation); Jacobian J = sum_m x_{e,m}
+// grad v_m^T (eq. Jacobian).  With the Q_p Gauss-Lobatto nodal basis u_m:
+//   M[m][n]    = int u_m u_n |J|                        (eq. localMtMatrix / sigma)
+//   K_i[m][n]  = int (J^{-T} grad u_m)_i u_n |J|        (eq. localGMatrix:
+//                                                         G = -sum_i Omega_i K_i)
+// on a tensor Gauss-Legendre rule with p+r (2D) or p+ceil(3r/2) (3D) points
+// per axis, exact for these polynomial integrands.
+#include <atomic>
+#include <cmath>
+
+#include "host.hpp"
+
+namespace snsw {
+
+namespace {
+
+// Tensor-product tables: val[q][m] and grad[q][m][b], axis 0 fastest.
+void tensor_tables(int dim, const std::vector<double>& nodes, const std::vector<double>& x1,
+                   std::vector<double>& val, std::vector<double>& grad) {
+    const int nn = (int)nodes.size(), nq1 = (int)x1.size();
+    std::vector<double> V1(nq1 * nn), D1(nq1 * nn);
+    for (int k = 0; k < nq1; ++k) lagrange_eval(nodes, x1[k], &V1[k * nn], &D1[k * nn]);
+    int Q = 1, Nf = 1;
+    for (int a = 0; a < dim; ++a) { Q *= nq1; Nf *= nn; }
+    val.assign((size_t)Q * Nf, 0.0);
+    grad.assign((size_t)Q * Nf * dim, 0.0);
+    for (int q = 0; q < Q; ++q) {
+        int qi[3] = {0, 0, 0}, rq = q;
+        for (int a = 0; a < dim; ++a) { qi[a] = rq % nq1; rq /= nq1; }
+        for (int m = 0; m < Nf; ++m) {
+            int mi[3] = {0, 0, 0}, rm = m;
+            for (int a = 0; a < dim; ++a) { mi[a] = rm % nn; rm /= nn; }
+            double v = 1.0;
+            for (int a = 0; a < dim; ++a) v *= V1[qi[a] * nn + mi[a]];
+            val[(size_t)q * Nf + m] = v;
+            for (int b = 0; b < dim; ++b) {
+                double g = 1.0;
+                for (int a = 0; a < dim; ++a) g *= (a == b ? D1 : V1)[qi[a] * nn + mi[a]];
+                grad[((size_t)q * Nf + m) * dim + b] = g;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+void build_geometry(HostProblem& hp) {
+    const int dim = hp.dim, r = hp.r, p = hp.p, n = hp.n;
+    const int nq1 = dim == 2 ? p + r : p + (3 * r + 1) / 2;
+    std::vector<double> x1, w1;
+    gauss_legendre01(nq1, x1, w1);
+    std::vector<double> geo_nodes(r + 1);
+    for (int a = 0; a <= r; ++a) geo_nodes[a] = (double)a / r;
+    std::vector<double> dg_nodes = gll01(p);
+    std::vector<double> Vg, Gg, U, GU;
+    tensor_tables(dim, geo_nodes, x1, Vg, Gg);
+    tensor_tables(dim, dg_nodes, x1, U, GU);
+    int Q = 1, Nv = 1;
+    for (int a = 0; a < dim; ++a) { Q *= nq1; Nv *= r + 1; }
+    std::vector<double> wq(Q);
+    for (int q = 0; q < Q; ++q) {
+        double ww = 1.0;
+        int rq = q;
+        for (int a = 0; a < dim; ++a) { ww *= w1[rq % nq1]; rq /= nq1; }
+        wq[q] = ww;
+    }
+    int L[3] = {1, 1, 1};
+    for (int a = 0; a < dim; ++a) L[a] = r * hp.nx[a] + 1;
+    hp.M.assign((size_t)hp.E * n * n, 0.0);
+    hp.K.assign((size_t)hp.E * dim * n * n, 0.0);
+    std::atomic<bool> bad(false);
+
+    parallel_for(hp.E, hp.nthreads, [&](int64_t e0, int64_t e1) {
+        std::vector<double> xe(Nv * dim), a(n), gx(n * dim);
+        double local_min = 1e300;
+        for (int64_t e = e0; e < e1; ++e) {
+            int ei[3] = {0, 0, 0};
+            int64_t re = e;
+            for (int ax = 0; ax < dim; ++ax) { ei[ax] = (int)(re % hp.nx[ax]); re /= hp.nx[ax]; }
+            for (int m = 0; m < Nv; ++m) {
+                int mi[3] = {0, 0, 0}, rm = m;
+                for (int ax = 0; ax < dim; ++ax) { mi[ax] = rm % (r + 1); rm /= r + 1; }
+                int64_t lid = 0, stride = 1;
+                for (int ax = 0; ax < dim; ++ax) { lid += (int64_t)(r * ei[ax] + mi[ax]) * stride; stride *= L[ax]; }
+                for (int c = 0; c < dim; ++c) xe[m * dim + c] = hp.lattice[lid * dim + c];
+            }
+            double* Me = &hp.M[(size_t)e * n * n];
+            double* Ke = &hp.K[(size_t)e * dim * n * n];
+            for (int q = 0; q < Q; ++q) {
+                double J[3][3] = {{0}};
+                for (int m = 0; m < Nv; ++m)
+                    for (int c = 0; c < dim; ++c)
+                        for (int b = 0; b < dim; ++b) J[c][b] += xe[m * dim + c] * Gg[((size_t)q * Nv + m) * dim + b];
+                double det, Ji[3][3];   // Ji = J^{-1}
+                if (dim == 2) {
+                    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+                    Ji[0][0] = J[1][1] / det; Ji[0][1] = -J[0][1] / det;
+                    Ji[1][0] = -J[1][0] / det; Ji[1][1] = J[0][0] / det;
+                } else {
+                    double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+                    double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+                    double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+                    det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+                    Ji[0][0] = c00 / det;
+                    Ji[1][0] = c01 / det;
+                    Ji[2][0] = c02 / det;
+                    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+                    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+                    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+                    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+                    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+                    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+                }
+                if (det < local_min) local_min = det;
+                const double wd = wq[q] * det;
+                const double* Uq = &U[(size_t)q * n];
+                for (int m = 0; m < n; ++m) {
+                    a[m] = wd * Uq[m];
+                    for (int i = 0; i < dim; ++i) {
+                        double s = 0.0;
+                        for (int b = 0; b < dim; ++b) s += Ji[b][i] * GU[((size_t)q * n + m) * dim + b];
+                        gx[i * n + m] = wd * s;
+                    }
+                }
+                for (int m = 0; m < n; ++m)
+                    for (int nn2 = 0; nn2 < n; ++nn2) Me[m * n + nn2] += a[m] * Uq[nn2];
+                for (int i = 0; i < dim; ++i)
+                    for (int m = 0; m < n; ++m) {
+                        const double gm = gx[i * n + m];
+                        double* row = &Ke[((size_t)i * n + m) * n];
+                        for (int nn2 = 0; nn2 < n; ++nn2) row[nn2] += gm * Uq[nn2];
+                    }
+            }
+        }
+        // per-chunk minimum is enough to detect an inverted element
+        if (!(local_min > 0.0)) bad.store(true);
+    });
+    if (bad.load()) throw Error(SNSW_E_BAD_JACOBIAN, "non-positive Jacobian determinant in the mesh");
+}
+
+}  // namespace snsw

@@ -1,0 +1,480 @@
+// Per-direction dependency graph, cycle cutting and levels (section 3), and
+// the combined (element, direction) schedule of the device sweep.
+//
+// Graph: vertices are elements; edge up -> down when the downwind element
+// receives inflow through a shared face (its coupling block F_{down,up} is
+// nonzero).  Weights (section 3, eq. graphWeight; ||.|| the max-entry norm):
+// Unity 1, Face ||F||, SigInvFace ||M_{t,down}^{-1} F||, made integer as
+// w = clamp(rint(z / z_max * 2^20), 1, 2^20) (ties to even; Unity: 1) so that
+// everything after this point is exact integer work.
+//
+// Cycle cutting: Tarjan SCCs; in each component an order minimising the
+// total weight of couplings whose upwind element is ordered after the
+// downwind one (those are lagged).  Components of at most exact_max vertices:
+// exact subset dynamic programme (vertices by ascending element id; the last
+// vertex v of a subset T costs sum_{u in T\v} w(v->u); smallest v wins ties).
+// Larger ones: weighted Eades-Lin-Smyth (peel the smallest-id sink / source
+// repeatedly, else the vertex of largest w_out - w_in, smallest id on ties).
+// Levels: ASAP levels of the graph without the lagged edges.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "host.hpp"
+
+namespace snsw {
+
+namespace {
+
+constexpr double kTau = 1e-12;
+constexpr double kQuant = 1048576.0;   // 2^20
+
+struct Edge {
+    int32_t down, up;
+    double z;
+};
+
+// inverse of a small dense matrix (Gauss-Jordan, partial pivoting)
+void invert(int n, const double* A, double* Ainv) {
+    std::vector<double> a(A, A + n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ainv[i * n + j] = (i == j) ? 1.0 : 0.0;
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::fabs(a[i * n + k]) > std::fabs(a[piv * n + k])) piv = i;
+        if (piv != k)
+            for (int j = 0; j < n; ++j) {
+                std::swap(a[k * n + j], a[piv * n + j]);
+                std::swap(Ainv[k * n + j], Ainv[piv * n + j]);
+            }
+        const double d = 1.0 / a[k * n + k];
+        for (int j = 0; j < n; ++j) { a[k * n + j] *= d; Ainv[k * n + j] *= d; }
+        for (int i = 0; i < n; ++i) {
+            if (i == k) continue;
+            const double l = a[i * n + k];
+            if (l == 0.0) continue;
+            for (int j = 0; j < n; ++j) { a[i * n + j] -= l * a[k * n + j]; Ainv[i * n + j] -= l * Ainv[k * n + j]; }
+        }
+    }
+}
+
+// Tarjan's algorithm, iterative.  adj in CSR form.
+std::vector<int32_t> tarjan(int64_t V, const std::vector<int64_t>& off, const std::vector<int32_t>& adj) {
+    std::vector<int32_t> index(V, -1), low(V, 0), comp(V, -1);
+    std::vector<char> on(V, 0);
+    std::vector<int32_t> stack;
+    std::vector<std::pair<int32_t, int64_t>> work;
+    int32_t counter = 0, ncomp = 0;
+    for (int64_t v0 = 0; v0 < V; ++v0) {
+        if (index[v0] != -1) continue;
+        index[v0] = low[v0] = counter++;
+        stack.push_back((int32_t)v0);
+        on[v0] = 1;
+        work.emplace_back((int32_t)v0, off[v0]);
+        while (!work.empty()) {
+            auto& top = work.back();
+            const int32_t v = top.first;
+            if (top.second < off[v + 1]) {
+                const int32_t u = adj[top.second++];
+                if (index[u] == -1) {
+                    index[u] = low[u] = counter++;
+                    stack.push_back(u);
+                    on[u] = 1;
+                    work.emplace_back(u, off[u]);
+                } else if (on[u]) {
+                    low[v] = std::min(low[v], index[u]);
+                }
+            } else {
+                work.pop_back();
+                if (!work.empty()) {
+                    const int32_t parent = work.back().first;
+                    low[parent] = std::min(low[parent], low[v]);
+                }
+                if (low[v] == index[v]) {
+                    while (true) {
+                        const int32_t u = stack.back();
+                        stack.pop_back();
+                        on[u] = 0;
+                        comp[u] = ncomp;
+                        if (u == v) break;
+                    }
+                    ++ncomp;
+                }
+            }
+        }
+    }
+    return comp;
+}
+
+// exact minimum-lagged-weight order of a small component (local indices)
+std::vector<int> exact_order(int s, const std::vector<int64_t>& W) {
+    const uint32_t full = (1u << s) - 1u;
+    std::vector<int64_t> f(full + 1, 0);
+    std::vector<int8_t> best(full + 1, -1);
+    for (uint32_t T = 1; T <= full; ++T) {
+        int64_t bc = 0;
+        int bv = -1;
+        for (int v = 0; v < s; ++v) {
+            if (!((T >> v) & 1u)) continue;
+            const uint32_t rest = T & ~(1u << v);
+            int64_t c = f[rest];
+            for (int u = 0; u < s; ++u)
+                if ((rest >> u) & 1u) c += W[v * s + u];
+            if (bv < 0 || c < bc) { bc = c; bv = v; }
+        }
+        f[T] = bc;
+        best[T] = (int8_t)bv;
+    }
+    std::vector<int> rev;
+    uint32_t T = full;
+    while (T) {
+        const int v = best[T];
+        rev.push_back(v);
+        T &= ~(1u << v);
+    }
+    std::reverse(rev.begin(), rev.end());
+    return rev;
+}
+
+// weighted Eades-Lin-Smyth order of a component (local indices)
+std::vector<int> eades_order(int s, const std::vector<std::vector<std::pair<int, int64_t>>>& out,
+                             const std::vector<std::vector<std::pair<int, int64_t>>>& in) {
+    std::vector<char> alive(s, 1);
+    std::vector<int64_t> outdeg(s), indeg(s), wout(s, 0), win(s, 0);
+    for (int v = 0; v < s; ++v) {
+        outdeg[v] = (int64_t)out[v].size();
+        indeg[v] = (int64_t)in[v].size();
+        for (auto& e : out[v]) wout[v] += e.second;
+        for (auto& e : in[v]) win[v] += e.second;
+    }
+    std::vector<int> head, tail_rev;
+    int left = s;
+    auto remove = [&](int v) {
+        alive[v] = 0;
+        --left;
+        for (auto& e : out[v])
+            if (alive[e.first]) { --indeg[e.first]; win[e.first] -= e.second; }
+        for (auto& e : in[v])
+            if (alive[e.first]) { --outdeg[e.first]; wout[e.first] -= e.second; }
+    };
+    while (left) {
+        while (true) {
+            int v = -1;
+            for (int u = 0; u < s; ++u)
+                if (alive[u] && outdeg[u] == 0) { v = u; break; }
+            if (v < 0) break;
+            remove(v);
+            tail_rev.push_back(v);   // prepended to the tail sequence
+        }
+        while (true) {
+            int v = -1;
+            for (int u = 0; u < s; ++u)
+                if (alive[u] && indeg[u] == 0) { v = u; break; }
+            if (v < 0) break;
+            remove(v);
+            head.push_back(v);
+        }
+        if (left) {
+            int bv = -1;
+            int64_t bd = 0;
+            for (int u = 0; u < s; ++u) {
+                if (!alive[u]) continue;
+                const int64_t dl = wout[u] - win[u];
+                if (bv < 0 || dl > bd) { bd = dl; bv = u; }
+            }
+            remove(bv);
+            head.push_back(bv);
+        }
+    }
+    std::vector<int> order = head;
+    for (auto it = tail_rev.rbegin(); it != tail_rev.rend(); ++it) order.push_back(*it);
+    return order;
+}
+
+void build_direction(const HostProblem& hp, int d, const std::vector<double>& Minv, DirGraph& g) {
+    const int nf = hp.nf, dim = hp.dim;
+    const double* om = &hp.omega[(size_t)d * 3];
+    g.face_class.assign(hp.F, FC_POS);
+    g.face_drop.assign(hp.F, 0);
+    g.kink_face.clear();
+    g.kink_tab.clear();
+    std::vector<Edge> edges;
+    std::vector<double> Pp(nf * nf), Pm(nf * nf), Pin(nf * nf);
+    for (int64_t f = 0; f < hp.F; ++f) {
+        double mp = 0, mm = 0;
+        const uint8_t cls = face_integrals(hp, f, om, mp, mm, Pp.data(), Pm.data());
+        g.face_class[f] = cls;
+        const bool interior = hp.f_minus[f] >= 0 && hp.f_plus[f] >= 0;
+        uint8_t drop = 0;
+        if (interior) {
+            const double mabs = mp + mm;
+            if (mm <= kTau * mabs) { drop |= 1; mm = 0.0; }
+            if (mp <= kTau * mabs) { drop |= 2; mp = 0.0; }
+        }
+        g.face_drop[f] = drop;
+        if (cls == FC_KINK) {
+            if (drop & 1) std::fill(Pm.begin(), Pm.end(), 0.0);
+            if (drop & 2) std::fill(Pp.begin(), Pp.end(), 0.0);
+            g.kink_face.push_back((int32_t)f);
+            g.kink_tab.insert(g.kink_tab.end(), Pp.begin(), Pp.end());
+            g.kink_tab.insert(g.kink_tab.end(), Pm.begin(), Pm.end());
+        }
+        if (!interior) continue;
+        // two possible edges: plus -> minus (inflow P_minus), minus -> plus (P_plus)
+        for (int side = 0; side < 2; ++side) {
+            const double meas = side == 0 ? mm : mp;
+            if (!(meas > 0.0)) continue;
+            const int32_t down = side == 0 ? hp.f_minus[f] : hp.f_plus[f];
+            const int32_t up = side == 0 ? hp.f_plus[f] : hp.f_minus[f];
+            double z = 1.0;
+            if (hp.weighting != SNSW_WEIGHT_UNITY) {
+                if (cls == FC_KINK) {
+                    std::memcpy(Pin.data(), side == 0 ? Pm.data() : Pp.data(), sizeof(double) * nf * nf);
+                } else {
+                    // non-kink: P_in = -(sum_k om_k B_k) for the minus side (g <= 0),
+                    // +(sum_k om_k B_k) for the plus side (g >= 0)
+                    const double sg = side == 0 ? -1.0 : 1.0;
+                    const double* Bf = &hp.B[(size_t)f * dim * nf * nf];
+                    for (int i = 0; i < nf * nf; ++i) {
+                        double v = 0.0;
+                        for (int k = 0; k < dim; ++k) v += om[k] * Bf[k * nf * nf + i];
+                        Pin[i] = sg * v;
+                    }
+                }
+                z = 0.0;
+                if (hp.weighting == SNSW_WEIGHT_FACE) {
+                    for (int i = 0; i < nf * nf; ++i) z = std::max(z, std::fabs(Pin[i]));
+                } else {
+                    const int a = hp.f_axis[f];
+                    const int slot = 2 * a + (side == 0 ? 1 : 0);
+                    const int* tn = &hp.slot_nodes[slot * nf];
+                    const int n = hp.n;
+                    const double* Mi = &Minv[(size_t)down * n * n];
+                    const double st = hp.sigma_t[down];
+                    for (int m = 0; m < n; ++m)
+                        for (int b = 0; b < nf; ++b) {
+                            double v = 0.0;
+                            for (int aa = 0; aa < nf; ++aa) v += Mi[m * n + tn[aa]] * Pin[aa * nf + b];
+                            z = std::max(z, std::fabs(v / st));
+                        }
+                }
+            }
+            edges.push_back({down, up, z});
+        }
+    }
+    // quantised weights
+    double zmax = 0.0;
+    for (auto& e : edges) zmax = std::max(zmax, e.z);
+    std::sort(edges.begin(), edges.end(), [](const Edge& a, const Edge& b) {
+        return a.down != b.down ? a.down < b.down : a.up < b.up;
+    });
+    const size_t m = edges.size();
+    g.up.resize(m);
+    g.down.resize(m);
+    g.weight.resize(m);
+    for (size_t i = 0; i < m; ++i) {
+        g.up[i] = edges[i].up;
+        g.down[i] = edges[i].down;
+        int64_t w = 1;
+        if (hp.weighting != SNSW_WEIGHT_UNITY) {
+            double t = std::nearbyint(edges[i].z / zmax * kQuant);
+            t = std::min(std::max(t, 1.0), kQuant);
+            w = (int64_t)t;
+        }
+        g.weight[i] = w;
+    }
+    // CSR of out-edges (up -> down)
+    const int64_t E = hp.E;
+    std::vector<int64_t> off(E + 1, 0);
+    for (size_t i = 0; i < m; ++i) ++off[g.up[i] + 1];
+    for (int64_t v = 0; v < E; ++v) off[v + 1] += off[v];
+    std::vector<int32_t> adj(m);
+    std::vector<int64_t> adjw(m);
+    {
+        std::vector<int64_t> pos(off.begin(), off.end() - 1);
+        for (size_t i = 0; i < m; ++i) {
+            adj[pos[g.up[i]]] = g.down[i];
+            adjw[pos[g.up[i]]++] = g.weight[i];
+        }
+    }
+    std::vector<int32_t> comp = tarjan(E, off, adj);
+    int32_t ncomp = 0;
+    for (int64_t v = 0; v < E; ++v) ncomp = std::max(ncomp, comp[v] + 1);
+    std::vector<int32_t> csize(ncomp, 0);
+    for (int64_t v = 0; v < E; ++v) ++csize[comp[v]];
+    std::vector<int64_t> coff(ncomp + 1, 0);
+    for (int c = 0; c < ncomp; ++c) coff[c + 1] = coff[c] + csize[c];
+    std::vector<int32_t> members(E);
+    {
+        std::vector<int64_t> pos(coff.begin(), coff.end() - 1);
+        for (int64_t v = 0; v < E; ++v) members[pos[comp[v]]++] = (int32_t)v;   // ascending ids
+    }
+    std::vector<std::pair<int32_t, int32_t>> removed;   // (down, up)
+    snsw_graph_stats st{};
+    st.n_edges = (int64_t)m;
+    std::vector<int> loc(E, -1);
+    for (int c = 0; c < ncomp; ++c) {
+        const int s = csize[c];
+        if (s < 2) continue;
+        st.max_scc = std::max<int64_t>(st.max_scc, s);
+        if (s == 2) ++st.n_scc_simple;
+        else { ++st.n_scc_large; st.n_elements_in_large += s; }
+        const int32_t* vs = &members[coff[c]];
+        for (int i = 0; i < s; ++i) loc[vs[i]] = i;
+        std::vector<int> order;
+        if (s <= hp.exact_max) {
+            std::vector<int64_t> W((size_t)s * s, 0);
+            for (int i = 0; i < s; ++i)
+                for (int64_t k = off[vs[i]]; k < off[vs[i] + 1]; ++k)
+                    if (comp[adj[k]] == c) W[(size_t)i * s + loc[adj[k]]] = adjw[k];
+            order = exact_order(s, W);
+        } else {
+            std::vector<std::vector<std::pair<int, int64_t>>> out(s), in(s);
+            for (int i = 0; i < s; ++i)
+                for (int64_t k = off[vs[i]]; k < off[vs[i] + 1]; ++k)
+                    if (comp[adj[k]] == c) {
+                        out[i].emplace_back(loc[adj[k]], adjw[k]);
+                        in[loc[adj[k]]].emplace_back(i, adjw[k]);
+                    }
+            order = eades_order(s, out, in);
+        }
+        std::vector<int> pos(s);
+        for (int k = 0; k < s; ++k) pos[order[k]] = k;
+        for (int i = 0; i < s; ++i)
+            for (int64_t k = off[vs[i]]; k < off[vs[i] + 1]; ++k) {
+                const int32_t u = adj[k];
+                if (comp[u] == c && pos[i] > pos[loc[u]]) {
+                    removed.emplace_back(u, vs[i]);
+                    st.removed_weight += adjw[k];
+                }
+            }
+        for (int i = 0; i < s; ++i) loc[vs[i]] = -1;
+    }
+    std::sort(removed.begin(), removed.end());
+    g.rem_down.resize(removed.size());
+    g.rem_up.resize(removed.size());
+    for (size_t i = 0; i < removed.size(); ++i) {
+        g.rem_down[i] = removed[i].first;
+        g.rem_up[i] = removed[i].second;
+    }
+    st.n_removed = (int64_t)removed.size();
+    // ASAP levels of the cut graph (Kahn)
+    std::vector<int32_t> indeg(E, 0);
+    auto is_removed = [&](int32_t up, int32_t down) {
+        return std::binary_search(removed.begin(), removed.end(), std::make_pair(down, up));
+    };
+    std::vector<char> kept(m, 1);
+    for (int64_t v = 0; v < E; ++v)
+        for (int64_t k = off[v]; k < off[v + 1]; ++k)
+            if (is_removed((int32_t)v, adj[k])) kept[k] = 0;
+            else ++indeg[adj[k]];
+    g.level.assign(E, 0);
+    std::vector<int32_t> frontier, next;
+    for (int64_t v = 0; v < E; ++v)
+        if (indeg[v] == 0) frontier.push_back((int32_t)v);
+    int64_t seen = 0;
+    while (!frontier.empty()) {
+        next.clear();
+        for (int32_t u : frontier) {
+            ++seen;
+            for (int64_t k = off[u]; k < off[u + 1]; ++k) {
+                if (!kept[k]) continue;
+                const int32_t v = adj[k];
+                g.level[v] = std::max(g.level[v], g.level[u] + 1);
+                if (--indeg[v] == 0) next.push_back(v);
+            }
+        }
+        frontier.swap(next);
+    }
+    if (seen != E) throw Error(SNSW_E_STATE, "cut graph is not acyclic (internal error)");
+    int32_t lmax = 0;
+    for (int64_t v = 0; v < E; ++v) lmax = std::max(lmax, g.level[v]);
+    st.n_levels = E ? lmax + 1 : 0;
+    g.stats = st;
+}
+
+}  // namespace
+
+void build_graphs(HostProblem& hp) {
+    std::vector<double> Minv;
+    if (hp.weighting == SNSW_WEIGHT_SIGINVFACE) {
+        const int n = hp.n;
+        Minv.assign((size_t)hp.E * n * n, 0.0);
+        parallel_for(hp.E, hp.nthreads, [&](int64_t e0, int64_t e1) {
+            for (int64_t e = e0; e < e1; ++e) invert(n, &hp.M[(size_t)e * n * n], &Minv[(size_t)e * n * n]);
+        });
+    }
+    hp.graphs.assign(hp.D, DirGraph());
+    parallel_for(hp.D, hp.nthreads, [&](int64_t d0, int64_t d1) {
+        for (int64_t d = d0; d < d1; ++d) build_direction(hp, (int)d, Minv, hp.graphs[d]);
+    });
+}
+
+void build_schedule(HostProblem& hp) {
+    const int64_t E = hp.E;
+    const int D = hp.D, ns = hp.nslot;
+    int32_t L = 0;
+    for (int d = 0; d < D; ++d) L = std::max<int32_t>(L, (int32_t)hp.graphs[d].stats.n_levels);
+    // global kink rows: per-direction tables concatenated
+    std::vector<int64_t> kink_base(D + 1, 0);
+    for (int d = 0; d < D; ++d) kink_base[d + 1] = kink_base[d] + (int64_t)hp.graphs[d].kink_face.size();
+    hp.n_kinks = kink_base[D];
+    const int nf2 = 2 * hp.nf * hp.nf;
+    hp.kink_tab.assign((size_t)hp.n_kinks * nf2, 0.0);
+    for (int d = 0; d < D; ++d)
+        std::copy(hp.graphs[d].kink_tab.begin(), hp.graphs[d].kink_tab.end(),
+                  hp.kink_tab.begin() + kink_base[d] * nf2);
+    // lag flags per (direction, element): bit s set when slot s is lagged
+    std::vector<std::vector<uint8_t>> lag(D);
+    parallel_for(D, hp.nthreads, [&](int64_t d0, int64_t d1) {
+        for (int64_t d = d0; d < d1; ++d) {
+            lag[d].assign(E, 0);
+            const DirGraph& g = hp.graphs[d];
+            for (size_t i = 0; i < g.rem_down.size(); ++i) {
+                const int32_t dn = g.rem_down[i], up = g.rem_up[i];
+                for (int s = 0; s < ns; ++s)
+                    if (hp.slot_nbr[(size_t)dn * ns + s] == up) lag[d][dn] |= (uint8_t)(1u << s);
+            }
+        }
+    });
+    std::vector<int64_t> count(L + 1, 0);
+    for (int d = 0; d < D; ++d)
+        for (int64_t e = 0; e < E; ++e) ++count[hp.graphs[d].level[e] + 1];
+    hp.level_off.assign(L + 1, 0);
+    for (int k = 0; k < L; ++k) hp.level_off[k + 1] = hp.level_off[k] + count[k + 1];
+    const int64_t P = hp.level_off[L];
+    hp.pairs.assign((size_t)P * 4, 0);
+    hp.kink_idx.clear();
+    std::vector<int64_t> pos(hp.level_off.begin(), hp.level_off.end() - 1);
+    for (int64_t e = 0; e < E; ++e) {
+        for (int d = 0; d < D; ++d) {
+            const DirGraph& g = hp.graphs[d];
+            const int64_t slot_pos = pos[g.level[e]]++;
+            uint32_t packed = (uint32_t)d;
+            const int32_t kb = (int32_t)hp.kink_idx.size();
+            for (int s = 0; s < ns; ++s) {
+                const int32_t f = hp.slot_face[(size_t)e * ns + s];
+                const uint8_t fc = g.face_class[f];
+                uint32_t cls;
+                if (fc == FC_KINK) {
+                    cls = SC_KINK;
+                    auto it = std::lower_bound(g.kink_face.begin(), g.kink_face.end(), f);
+                    hp.kink_idx.push_back((int32_t)(kink_base[d] + (it - g.kink_face.begin())));
+                } else {
+                    const bool minus_side = (s & 1) != 0;
+                    cls = ((fc == FC_POS) == minus_side) ? SC_OUT : SC_IN;
+                }
+                packed |= pack_slot(cls, (lag[d][e] >> s) & 1u, s);
+            }
+            int32_t* pr = &hp.pairs[(size_t)slot_pos * 4];
+            pr[0] = (int32_t)e;
+            pr[1] = (int32_t)packed;
+            pr[2] = kb;
+            pr[3] = 0;
+        }
+    }
+}
+
+}  // namespace snsw

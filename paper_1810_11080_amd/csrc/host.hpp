@@ -1,0 +1,118 @@
+// Internal host-side structures of the snsweep library (not part of the ABI).
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "snsweep.h"
+
+namespace snsw {
+
+// Error carried from deep inside setup to the C boundary.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+// Runs fn(i) for i in [0, n) on up to nthreads host threads (static chunks).
+void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int64_t)>& fn);
+
+// ----------------------------------------------------------------- basis.cpp
+// n-point Gauss-Legendre rule on [0, 1], ascending points.
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);
+// p+1 Gauss-Lobatto-Legendre points on [0, 1], ascending.
+std::vector<double> gll01(int p);
+// Values and derivatives of the Lagrange polynomials of `nodes` at x.
+void lagrange_eval(const std::vector<double>& nodes, double x, double* val, double* der);
+// Monomial coefficients (ascending powers) of the derivative of each Lagrange
+// polynomial of `nodes`: out[m][k], k = 0..nn-2.
+std::vector<std::vector<double>> lagrange_derivative_monomials(const std::vector<double>& nodes);
+
+// ------------------------------------------------------------ quadrature.cpp
+// Level-symmetric S_N set: omega [D][3], w [D] (2D: z > 0 half, doubled).
+void level_symmetric(int N, int dim, std::vector<double>& omega, std::vector<double>& w);
+
+// ------------------------------------------------------------------ mesh data
+// Face classes relative to the face normal N (minus -> plus element).
+enum FaceClass : uint8_t { FC_POS = 0, FC_NEG = 1, FC_KINK = 2 };
+// Slot classes from the element's point of view (packed in the schedule).
+enum SlotClass : uint32_t { SC_OUT = 0, SC_IN = 1, SC_KINK = 2 };
+
+struct DirGraph {
+    std::vector<int32_t> up, down;       // edges sorted by (down, up)
+    std::vector<int64_t> weight;
+    std::vector<int32_t> rem_down, rem_up;  // lagged edges sorted by (down, up)
+    std::vector<int32_t> level;          // [E]
+    snsw_graph_stats stats{};
+    std::vector<uint8_t> face_class;     // [F]
+    std::vector<uint8_t> face_drop;      // [F] bit0: minus side dropped, bit1: plus side
+    std::vector<int32_t> kink_face;      // faces with FC_KINK
+    std::vector<double> kink_tab;        // [nk][2][nf][nf]: P_plus, P_minus
+};
+
+// Per-face normal data used to classify (face, direction) pairs.
+struct FaceNormalData {
+    std::vector<double> mono;        // 2D: monomials of N_x(s), N_y(s) [F][2][r]
+    std::vector<double> cs, ct, cw;  // 3D composite rule points and weights
+    std::vector<double> cphi;        // 3D trace values at the points [Qc][nf]
+    std::vector<double> gV1, gD1;    // geometry 1D tables at the abscissae
+    std::vector<int> ci, cj;         // abscissa index of each point
+    int nc1 = 0;
+    std::vector<double> Rf;          // 3D: max |N_q - int N| over the points
+};
+
+struct HostProblem {
+    int dim = 2, nx[3] = {1, 1, 1}, r = 1, p = 1;
+    int n = 0, nf = 0, nslot = 0;
+    int64_t E = 0, F = 0;
+    int D = 0;
+    int weighting = 1, exact_max = 10, precision = 0, bc = 0, nthreads = 1;
+    double psi_inc = 0.0;
+    std::vector<double> lattice;              // [L][dim]
+    std::vector<double> omega, w;             // [D][3], [D]
+    std::vector<double> sigma_t, sigma_s, q;  // [E], [E], [E][n]
+    // element matrices, row-major (m, n)
+    std::vector<double> M, K;                 // [E][n][n], [E][dim][n][n]
+    // faces
+    std::vector<int32_t> f_axis, f_minus, f_plus;
+    std::vector<double> f_ctrl;               // [F][(r+1)^(dim-1)][dim]
+    std::vector<double> B;                    // [F][dim][nf][nf] int N_k phi_a phi_b
+    std::vector<double> Nint;                 // [F][dim] int N_k
+    FaceNormalData fnd;
+    std::vector<int32_t> slot_face, slot_nbr; // [E][nslot]
+    std::vector<int32_t> slot_nodes;          // [nslot][nf]
+    std::vector<DirGraph> graphs;             // [D]
+    // combined schedule
+    std::vector<int64_t> level_off;           // [L+1]
+    std::vector<int32_t> pairs;               // [P][4]: e, packed, kink_base, 0
+    std::vector<int32_t> kink_idx;            // per pair kink slots -> kink rows
+    std::vector<double> kink_tab;             // [K][2][nf][nf]
+    int64_t n_kinks = 0;
+    double setup_seconds = 0.0;
+};
+
+// geometry.cpp: element matrices; throws Error(SNSW_E_BAD_JACOBIAN)
+void build_geometry(HostProblem& hp);
+// faces.cpp: face enumeration, normal moments, per-direction classification
+void build_faces(HostProblem& hp);
+// Class of face f for direction om with measures mp = int max(g,0),
+// mm = int max(-g,0); for FC_KINK also the matrices Pp, Pm (nf x nf).
+uint8_t face_integrals(const HostProblem& hp, int64_t f, const double* om, double& mp,
+                       double& mm, double* Pp, double* Pm);
+// graph.cpp: per-direction graph, FAS and levels; combined schedule
+void build_graphs(HostProblem& hp);
+void build_schedule(HostProblem& hp);
+
+// Packed pair word: bits 0..9 direction, then per slot s 3 bits at 10+3s:
+// class (2 bits, SlotClass) and lag flag (bit 2).
+constexpr int kDirBits = 10;
+inline uint32_t pack_slot(uint32_t cls, bool lag, int s) {
+    return (cls | (lag ? 4u : 0u)) << (kDirBits + 3 * s);
+}
+
+}  // namespace snsw

@@ -1,0 +1,269 @@
+// C-ABI: errors, contexts, problem setup and host-side introspection.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <memory>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "internal.hpp"
+
+namespace snsw {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int64_t)>& fn) {
+    if (n <= 0) return;
+    int nt = nthreads > 0 ? nthreads : (int)std::max(1u, std::thread::hardware_concurrency());
+    nt = (int)std::min<int64_t>(nt, n);
+    if (nt <= 1) { fn(0, n); return; }
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> errs(nt);
+    // interleaved small chunks balance uneven work (e.g. kink faces)
+    const int64_t chunk = std::max<int64_t>(1, n / (nt * 16));
+    std::atomic<int64_t> next(0);
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            try {
+                while (true) {
+                    const int64_t b = next.fetch_add(chunk);
+                    if (b >= n) break;
+                    fn(b, std::min(n, b + chunk));
+                }
+            } catch (...) {
+                errs[t] = std::current_exception();
+            }
+        });
+    for (auto& x : th) x.join();
+    for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+}
+
+}  // namespace snsw
+
+using namespace snsw;
+
+extern "C" {
+
+const char* snsw_last_error(void) { return g_last_error.c_str(); }
+
+const char* snsw_version(void) { return "snsweep 0.1 (gfx950)"; }
+
+int snsw_ctx_create(int device, void* hip_stream, snsw_ctx** out) {
+    return snsw_guard([&] {
+        if (!out) throw Error(SNSW_E_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (device < -1) throw Error(SNSW_E_INVALID_ARG, "device must be >= -1");
+        auto* c = new snsw_ctx();
+        c->device = device;
+        c->stream = hip_stream;
+        if (device >= 0) {
+            try {
+                device_check_ctx(c);
+            } catch (...) {
+                delete c;
+                throw;
+            }
+        }
+        *out = c;
+    });
+}
+
+void snsw_ctx_destroy(snsw_ctx* ctx) { delete ctx; }
+
+static void check_finite(const double* a, size_t n, const char* name) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) throw Error(SNSW_E_NONFINITE, std::string("non-finite value in ") + name);
+}
+
+int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_problem** out) {
+    return snsw_guard([&] {
+        if (!ctx || !desc || !out) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        const auto t0 = std::chrono::steady_clock::now();
+        auto prob = std::make_unique<snsw_problem>();
+        prob->ctx = ctx;
+        HostProblem& hp = prob->hp;
+        hp.dim = desc->dim;
+        if (hp.dim != 2 && hp.dim != 3) throw Error(SNSW_E_INVALID_ARG, "dim must be 2 or 3");
+        hp.r = desc->geom_order;
+        hp.p = desc->dg_order;
+        if (hp.r < 1 || hp.r > 3) throw Error(SNSW_E_UNSUPPORTED, "geom_order must be 1..3");
+        if (hp.p < 1 || hp.p > 3) throw Error(SNSW_E_UNSUPPORTED, "dg_order must be 1..3");
+        hp.E = 1;
+        for (int a = 0; a < hp.dim; ++a) {
+            hp.nx[a] = desc->nx[a];
+            if (hp.nx[a] < 1) throw Error(SNSW_E_SHAPE, "nx must be >= 1");
+            hp.E *= hp.nx[a];
+        }
+        if (hp.E > (int64_t)1 << 30) throw Error(SNSW_E_SHAPE, "too many elements");
+        hp.n = 1;
+        hp.nf = 1;
+        for (int a = 0; a < hp.dim; ++a) hp.n *= hp.p + 1;
+        for (int a = 0; a + 1 < hp.dim; ++a) hp.nf *= hp.p + 1;
+        hp.nthreads = desc->n_threads > 0 ? desc->n_threads
+                                          : (int)std::max(1u, std::thread::hardware_concurrency());
+        hp.weighting = desc->weighting;
+        if (hp.weighting < 0 || hp.weighting > 2) throw Error(SNSW_E_INVALID_ARG, "weighting must be 0..2");
+        hp.exact_max = desc->exact_scc_max;
+        if (hp.exact_max < 1 || hp.exact_max > 20) throw Error(SNSW_E_INVALID_ARG, "exact_scc_max must be 1..20");
+        hp.precision = desc->precision;
+        if (hp.precision != SNSW_PREC_FP64 && hp.precision != SNSW_PREC_MIXED)
+            throw Error(SNSW_E_INVALID_ARG, "precision must be FP64 or MIXED");
+        hp.bc = desc->bc_kind;
+        if (hp.bc != SNSW_BC_VACUUM && hp.bc != SNSW_BC_ISO_CONST) throw Error(SNSW_E_INVALID_ARG, "bc_kind");
+        hp.psi_inc = hp.bc == SNSW_BC_ISO_CONST ? desc->psi_inc : 0.0;
+        if (!std::isfinite(hp.psi_inc)) throw Error(SNSW_E_NONFINITE, "psi_inc");
+        // lattice
+        if (!desc->lattice) throw Error(SNSW_E_INVALID_ARG, "lattice is NULL");
+        int64_t Lp = 1;
+        for (int a = 0; a < hp.dim; ++a) Lp *= (int64_t)hp.r * hp.nx[a] + 1;
+        hp.lattice.assign(desc->lattice, desc->lattice + Lp * hp.dim);
+        check_finite(hp.lattice.data(), hp.lattice.size(), "lattice");
+        // quadrature
+        if (desc->sn_order > 0) {
+            if (desc->sn_order % 2) throw Error(SNSW_E_INVALID_ARG, "sn_order must be even");
+            level_symmetric(desc->sn_order, hp.dim, hp.omega, hp.w);
+        } else {
+            if (desc->n_dirs < 1 || !desc->omega || !desc->w) throw Error(SNSW_E_INVALID_ARG, "quadrature");
+            hp.omega.assign(desc->omega, desc->omega + 3 * desc->n_dirs);
+            hp.w.assign(desc->w, desc->w + desc->n_dirs);
+            check_finite(hp.omega.data(), hp.omega.size(), "omega");
+            check_finite(hp.w.data(), hp.w.size(), "w");
+        }
+        hp.D = (int)hp.w.size();
+        if (hp.D >= (1 << kDirBits)) throw Error(SNSW_E_SHAPE, "too many directions (max 1023)");
+        // materials and source
+        if (!desc->sigma_t || !desc->sigma_s || !desc->q) throw Error(SNSW_E_INVALID_ARG, "materials/source NULL");
+        hp.sigma_t.assign(desc->sigma_t, desc->sigma_t + hp.E);
+        hp.sigma_s.assign(desc->sigma_s, desc->sigma_s + hp.E);
+        check_finite(hp.sigma_t.data(), hp.E, "sigma_t");
+        check_finite(hp.sigma_s.data(), hp.E, "sigma_s");
+        for (int64_t e = 0; e < hp.E; ++e) {
+            if (!(hp.sigma_t[e] > 0.0)) throw Error(SNSW_E_INVALID_ARG, "sigma_t must be > 0");
+            if (hp.sigma_s[e] < 0.0) throw Error(SNSW_E_INVALID_ARG, "sigma_s must be >= 0");
+        }
+        hp.q.assign((size_t)hp.E * hp.n, 0.0);
+        if (desc->q_per_dof) std::copy(desc->q, desc->q + hp.E * hp.n, hp.q.begin());
+        else
+            for (int64_t e = 0; e < hp.E; ++e)
+                for (int i = 0; i < hp.n; ++i) hp.q[(size_t)e * hp.n + i] = desc->q[e];
+        check_finite(hp.q.data(), hp.q.size(), "q");
+
+        build_geometry(hp);
+        build_faces(hp);
+        build_graphs(hp);
+        build_schedule(hp);
+        hp.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (ctx->device >= 0) {
+            try {
+                device_upload(prob.get());
+            } catch (...) {
+                device_release(prob.get());
+                throw;
+            }
+        }
+        *out = prob.release();
+    });
+}
+
+void snsw_problem_destroy(snsw_problem* prob) {
+    if (!prob) return;
+    device_release(prob);
+    delete prob;
+}
+
+int snsw_problem_get_info(const snsw_problem* prob, snsw_problem_info* info) {
+    return snsw_guard([&] {
+        if (!prob || !info) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
+        const HostProblem& hp = prob->hp;
+        info->n_elements = hp.E;
+        info->n_dofs_per_element = hp.n;
+        info->n_dirs = hp.D;
+        info->n_levels_total = (int64_t)hp.level_off.size() - 1;
+        info->n_pairs = hp.E * hp.D;
+        info->n_edges_total = 0;
+        info->n_removed_total = 0;
+        for (auto& g : hp.graphs) {
+            info->n_edges_total += g.stats.n_edges;
+            info->n_removed_total += g.stats.n_removed;
+        }
+        info->n_kink_faces_total = hp.n_kinks;
+        info->setup_seconds = hp.setup_seconds;
+    });
+}
+
+int snsw_get_quadrature(const snsw_problem* prob, double* omega, double* w) {
+    return snsw_guard([&] {
+        if (!prob || !omega || !w) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
+        std::copy(prob->hp.omega.begin(), prob->hp.omega.end(), omega);
+        std::copy(prob->hp.w.begin(), prob->hp.w.end(), w);
+    });
+}
+
+int snsw_get_element_matrices(const snsw_problem* prob, int64_t e0, int64_t count, double* M, double* K) {
+    return snsw_guard([&] {
+        if (!prob) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
+        const HostProblem& hp = prob->hp;
+        if (e0 < 0 || count < 0 || e0 + count > hp.E) throw Error(SNSW_E_SHAPE, "element range");
+        const size_t nn = (size_t)hp.n * hp.n;
+        if (M) std::copy(hp.M.begin() + e0 * nn, hp.M.begin() + (e0 + count) * nn, M);
+        if (K) std::copy(hp.K.begin() + e0 * nn * hp.dim, hp.K.begin() + (e0 + count) * nn * hp.dim, K);
+    });
+}
+
+static const DirGraph& graph_of(const snsw_problem* prob, int d) {
+    if (!prob) throw Error(SNSW_E_INVALID_ARG, "NULL problem");
+    if (d < 0 || d >= prob->hp.D) throw Error(SNSW_E_INVALID_ARG, "direction out of range");
+    return prob->hp.graphs[d];
+}
+
+int snsw_graph_stats_get(const snsw_problem* prob, int d, snsw_graph_stats* st) {
+    return snsw_guard([&] {
+        const DirGraph& g = graph_of(prob, d);
+        if (!st) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
+        *st = g.stats;
+    });
+}
+
+int snsw_get_edges(const snsw_problem* prob, int d, int32_t* up, int32_t* down, int64_t* weight,
+                   int64_t cap, int64_t* count) {
+    return snsw_guard([&] {
+        const DirGraph& g = graph_of(prob, d);
+        const int64_t m = (int64_t)g.up.size();
+        if (count) *count = m;
+        const int64_t k = std::min(cap, m);
+        for (int64_t i = 0; i < k; ++i) {
+            if (up) up[i] = g.up[i];
+            if (down) down[i] = g.down[i];
+            if (weight) weight[i] = g.weight[i];
+        }
+    });
+}
+
+int snsw_get_removed_edges(const snsw_problem* prob, int d, int32_t* down, int32_t* up, int64_t cap,
+                           int64_t* count) {
+    return snsw_guard([&] {
+        const DirGraph& g = graph_of(prob, d);
+        const int64_t m = (int64_t)g.rem_down.size();
+        if (count) *count = m;
+        const int64_t k = std::min(cap, m);
+        for (int64_t i = 0; i < k; ++i) {
+            if (down) down[i] = g.rem_down[i];
+            if (up) up[i] = g.rem_up[i];
+        }
+    });
+}
+
+int snsw_get_levels(const snsw_problem* prob, int d, int32_t* level) {
+    return snsw_guard([&] {
+        const DirGraph& g = graph_of(prob, d);
+        if (!level) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
+        std::copy(g.level.begin(), g.level.end(), level);
+    });
+}
+
+}  // extern "C"

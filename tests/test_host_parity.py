@@ -1,0 +1,67 @@
+"""The library's host setup (C++) against the oracle, on the CPU: quadrature
+and element matrices to rounding, and the integer graph work -- edges,
+quantised weights, lagged edges and levels -- bit for bit."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.lib_helpers import graph_parity, rel_err
+
+CASES = {
+    "c1": W.c1,
+    "cyclic2d": lambda: W.small(dim=2, n=12, r=3, p=2, N=8, amp=0.3 / 12, freq=3),
+    "c2crop": lambda: W.make_problem("c2crop", 2, (32, 32), 3, 3, 8, 0.3 / 32, 8, 1.0, 0.8, 1.0),
+    "warp3d": lambda: W.small(dim=3, n=4, r=2, p=2, N=4, amp=0.08, freq=1),
+    "ragged3d": lambda: W.make_problem("r3", 3, (5, 3, 2), 2, 1, 2, 0.06, 1, 1.0, 0.5, 1.0),
+}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1810_11080_amd import Context
+    return Context(device=-1)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("weighting", [0, 1, 2])
+def test_graph_bit_exact(ctx, case, weighting):
+    from paper_1810_11080_amd import Problem
+    wp = CASES[case]()
+    P = Problem.from_workload(ctx, wp, weighting=weighting)
+    bad, disc = graph_parity(P, wp, weighting=weighting)
+    assert bad == []
+    om, w = P.quadrature()
+    assert rel_err(om, disc.omega) < 1e-14 and rel_err(w, disc.w) < 1e-13
+    M, K = P.element_matrices()
+    assert rel_err(M, disc.M) < 1e-13 and rel_err(K, disc.K) < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_problems(ctx, seed):
+    from paper_1810_11080_amd import Problem
+    wp = W.random_problem(seed, dim=2 if seed % 2 == 0 else 3)
+    P = Problem.from_workload(ctx, wp)
+    bad, _ = graph_parity(P, wp)
+    assert bad == []
+
+
+def test_exact_limit_one_uses_heuristic(ctx):
+    """exact_scc_max = 1 sends every component through Eades-Lin-Smyth."""
+    from paper_1810_11080_amd import Problem
+    wp = CASES["cyclic2d"]()
+    wp.exact_scc_max = 1
+    P = Problem.from_workload(ctx, wp)
+    bad, _ = graph_parity(P, wp)
+    assert bad == []
+
+
+@pytest.mark.slow
+def test_c2_full_graph(ctx):
+    """Full 128x128 Q3 S8 workload: all 40 directions bit-exact."""
+    from paper_1810_11080_amd import Problem
+    wp = W.c2()
+    P = Problem.from_workload(ctx, wp)
+    info = P.info()
+    assert info["n_removed_total"] > 0
+    bad, _ = graph_parity(P, wp)
+    assert bad == []
