@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--schedule", default="persistent", choices=["persistent", "levels"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     args = ap.parse_args()
@@ -104,7 +105,8 @@ def main():
     prec = 0 if args.precision == "fp64" else 1
     ctx = Context(device=0)
     t0 = time.perf_counter()
-    P = Problem.from_workload(ctx, wp, precision=prec)
+    sched = 0 if args.schedule == "persistent" else 1
+    P = Problem.from_workload(ctx, wp, precision=prec, schedule=sched)
     setup_s = time.perf_counter() - t0
     info = P.info()
     E, n, D = P.E, P.n, P.D
@@ -136,6 +138,7 @@ def main():
         phi, out = out, phi
     launches, kernel_ms = P.profile_read()
     P.profile_enable(False)
+    P.synchronize()
     launches_per_sweep = launches / args.steps
     avg_launch_ms = kernel_ms / launches
     flops_sweep = flops_per_pair(wp.dim, wp.p) * E * D
@@ -143,7 +146,8 @@ def main():
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5),
-                "traffic": None, "kernel": f"sweep_level_fp64<{wp.dim},{wp.p}>",
+                "traffic": None,
+                "kernel": f"sweep_{'persistent' if sched == 0 else 'level'}_fp64<{wp.dim},{wp.p}>",
                 "avg_launch_us": round(avg_launch_ms * 1e3, 3),
                 "launches_per_sweep": launches_per_sweep,
                 "kernel_share_of_step": round(kernel_ms / args.steps / ms_per_step, 4)}
@@ -176,7 +180,8 @@ def main():
         "config": {"workload": DESCRIPTIONS[args.workload], "elements": E, "dofs_per_element": n,
                    "directions": D, "levels": info["n_levels_total"],
                    "lagged_edges": info["n_removed_total"], "kink_face_dirs": info["n_kink_faces_total"],
-                   "setup_s": round(setup_s, 2), "precision": args.precision},
+                   "setup_s": round(setup_s, 2), "precision": args.precision,
+                   "schedule": args.schedule},
         "roofline": roofline,
         "solve_to_1e-8": solve,
         "cpu_baseline": cpu,

@@ -68,6 +68,12 @@ extern "C" {
 #define SNSW_PREC_FP64   0        /* assembly, LU and solve in FP64          */
 #define SNSW_PREC_MIXED  1        /* FP32 LU + one FP64 residual correction  */
 
+/* Device schedule of one sweep.  PERSISTENT: one launch; wavefronts claim
+ * (element, direction) pairs in level order and wait only for the completion
+ * flags of their kept upwind neighbours.  LEVELS: one launch per level.     */
+#define SNSW_SCHED_PERSISTENT  0
+#define SNSW_SCHED_LEVELS      1
+
 typedef struct snsw_ctx snsw_ctx;
 typedef struct snsw_problem snsw_problem;
 
@@ -111,6 +117,7 @@ typedef struct {
                                 minimum feedback arc set (<= 20; paper: 10)   */
     int32_t precision;       /* SNSW_PREC_*                                   */
     int32_t n_threads;       /* host threads for setup (0 = hardware count)   */
+    int32_t schedule;        /* SNSW_SCHED_*                                  */
 } snsw_problem_desc;
 
 /* Builds the discretisation and the sweep schedule (section 3): quadrature,
@@ -179,6 +186,11 @@ int snsw_sweep(snsw_problem* prob, const double* d_phi_in, double* d_phi_out,
 
 /* Clears the stored angular flux used by lagged couplings.                  */
 int snsw_reset(snsw_problem* prob);
+
+/* Waits for the ctx stream and reports device-side failures of earlier
+ * sweeps: SNSW_E_STATE if a dependency wait of the persistent schedule timed
+ * out (the affected sweep's output is invalid).                              */
+int snsw_synchronize(snsw_problem* prob);
 
 /* ------------------------------------------------------------------- solve
  * Source iteration (eq. sourceIteration) from the guess in d_phi until

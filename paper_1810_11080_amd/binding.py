@@ -29,7 +29,7 @@ class SnswProblemDesc(C.Structure):
                 ("sigma_t", c_double_p), ("sigma_s", c_double_p), ("q", c_double_p),
                 ("q_per_dof", C.c_int32), ("bc_kind", C.c_int32), ("psi_inc", C.c_double),
                 ("weighting", C.c_int32), ("exact_scc_max", C.c_int32),
-                ("precision", C.c_int32), ("n_threads", C.c_int32)]
+                ("precision", C.c_int32), ("n_threads", C.c_int32), ("schedule", C.c_int32)]
 
 
 class SnswProblemInfo(C.Structure):
@@ -73,6 +73,7 @@ SIGNATURES = {
     "snsw_get_levels": (C.c_int, [C.c_void_p, C.c_int, c_int32_p]),
     "snsw_sweep": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "snsw_reset": (C.c_int, [C.c_void_p]),
+    "snsw_synchronize": (C.c_int, [C.c_void_p]),
     "snsw_solve": (C.c_int, [C.c_void_p, C.POINTER(SnswSolveOpts), C.c_void_p, C.c_void_p,
                              C.POINTER(SnswSolveReport)]),
     "snsw_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, c_double_p]),
@@ -167,7 +168,7 @@ class Problem:
 
     def __init__(self, ctx: Context, *, dim, nx, geom_order, dg_order, lattice, sn_order,
                  sigma_t, sigma_s, q, bc_kind=0, psi_inc=0.0, weighting=1, exact_scc_max=10,
-                 precision=0, n_threads=0, omega=None, w=None):
+                 precision=0, n_threads=0, omega=None, w=None, schedule=0):
         self.ctx = ctx
         if dim not in (2, 3):
             raise SnswError(-1, "dim must be 2 or 3")
@@ -206,6 +207,7 @@ class Problem:
         desc.exact_scc_max = exact_scc_max
         desc.precision = precision
         desc.n_threads = n_threads
+        desc.schedule = schedule
         h = C.c_void_p()
         _check(lib().snsw_problem_create(ctx.handle, C.byref(desc), C.byref(h)))
         self.handle = h
@@ -216,14 +218,14 @@ class Problem:
 
     @classmethod
     def from_workload(cls, ctx: Context, prob, precision=0, n_threads=0, weighting=None,
-                      exact_scc_max=None):
+                      exact_scc_max=None, schedule=0):
         """Build from a ``workloads.Problem`` (seeded synthetic inputs)."""
         return cls(ctx, dim=prob.dim, nx=tuple(prob.nx), geom_order=prob.r, dg_order=prob.p,
                    lattice=prob.lattice, sn_order=prob.sn_order, sigma_t=prob.sigma_t,
                    sigma_s=prob.sigma_s, q=prob.q, bc_kind=prob.bc_kind, psi_inc=prob.psi_inc,
                    weighting=prob.weighting if weighting is None else weighting,
                    exact_scc_max=prob.exact_scc_max if exact_scc_max is None else exact_scc_max,
-                   precision=precision, n_threads=n_threads)
+                   precision=precision, n_threads=n_threads, schedule=schedule)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -298,6 +300,10 @@ class Problem:
 
     def reset(self):
         _check(lib().snsw_reset(self.handle))
+
+    def synchronize(self):
+        """Wait for the stream; raises if a device-side dependency wait failed."""
+        _check(lib().snsw_synchronize(self.handle))
 
     def residual(self, a, b) -> float:
         out = C.c_double()

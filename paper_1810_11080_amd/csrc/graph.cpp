@@ -442,10 +442,15 @@ void build_schedule(HostProblem& hp) {
     std::vector<int64_t> count(L + 1, 0);
     for (int d = 0; d < D; ++d)
         for (int64_t e = 0; e < E; ++e) ++count[hp.graphs[d].level[e] + 1];
+    // Levels are padded to a multiple of G = 64/n pairs (the pairs one
+    // wavefront claims at once), so that a wavefront never holds a pair
+    // together with one of its upwind pairs.  Padding entries have e = -1.
+    const int64_t G = std::max(1, 64 / hp.n);
     hp.level_off.assign(L + 1, 0);
-    for (int k = 0; k < L; ++k) hp.level_off[k + 1] = hp.level_off[k] + count[k + 1];
+    for (int k = 0; k < L; ++k) hp.level_off[k + 1] = hp.level_off[k] + (count[k + 1] + G - 1) / G * G;
     const int64_t P = hp.level_off[L];
     hp.pairs.assign((size_t)P * 4, 0);
+    for (int64_t t = 0; t < P; ++t) hp.pairs[(size_t)t * 4] = -1;
     hp.kink_idx.clear();
     std::vector<int64_t> pos(hp.level_off.begin(), hp.level_off.end() - 1);
     for (int64_t e = 0; e < E; ++e) {
@@ -457,22 +462,54 @@ void build_schedule(HostProblem& hp) {
             for (int s = 0; s < ns; ++s) {
                 const int32_t f = hp.slot_face[(size_t)e * ns + s];
                 const uint8_t fc = g.face_class[f];
+                const bool minus_side = (s & 1) != 0;
+                // drop bits: 1 = P_minus side, 2 = P_plus side
+                const bool in_dropped = (g.face_drop[f] & (minus_side ? 1 : 2)) != 0;
+                const bool out_dropped = (g.face_drop[f] & (minus_side ? 2 : 1)) != 0;
+                bool lagged = (lag[d][e] >> s) & 1u;
                 uint32_t cls;
                 if (fc == FC_KINK) {
                     cls = SC_KINK;
                     auto it = std::lower_bound(g.kink_face.begin(), g.kink_face.end(), f);
                     hp.kink_idx.push_back((int32_t)(kink_base[d] + (it - g.kink_face.begin())));
+                    if (in_dropped) lagged = true;
                 } else {
-                    const bool minus_side = (s & 1) != 0;
                     cls = ((fc == FC_POS) == minus_side) ? SC_OUT : SC_IN;
+                    if ((cls == SC_IN && in_dropped) || (cls == SC_OUT && out_dropped)) cls = SC_NONE;
                 }
-                packed |= pack_slot(cls, (lag[d][e] >> s) & 1u, s);
+                packed |= pack_slot(cls, lagged, s);
             }
             int32_t* pr = &hp.pairs[(size_t)slot_pos * 4];
             pr[0] = (int32_t)e;
             pr[1] = (int32_t)packed;
             pr[2] = kb;
             pr[3] = 0;
+        }
+    }
+    // Every pair that a pair waits for (kept inflow) must lie in an earlier
+    // batch of G pairs: the persistent kernel claims batches in schedule
+    // order, so each awaited pair is owned by another, running wavefront.
+    std::vector<int64_t> where((size_t)D * E, -1);
+    for (int64_t t = 0; t < P; ++t) {
+        const int32_t* pr = &hp.pairs[(size_t)t * 4];
+        if (pr[0] < 0) continue;
+        where[(size_t)((uint32_t)pr[1] & ((1u << kDirBits) - 1)) * E + pr[0]] = t;
+    }
+    for (size_t i = 0; i < where.size(); ++i)
+        if (where[i] < 0) throw Error(SNSW_E_STATE, "schedule: a pair is missing");
+    for (int64_t t = 0; t < P; ++t) {
+        const int32_t* pr = &hp.pairs[(size_t)t * 4];
+        if (pr[0] < 0) continue;
+        const int64_t batch0 = t - t % G;
+        const uint32_t packed = (uint32_t)pr[1];
+        const int d = (int)(packed & ((1u << kDirBits) - 1));
+        for (int s = 0; s < ns; ++s) {
+            const uint32_t bits = packed >> (kDirBits + 3 * s);
+            const uint32_t cls = bits & 3u;
+            const bool lagged = (bits >> 2) & 1u;
+            const int32_t nb = hp.slot_nbr[(size_t)pr[0] * ns + s];
+            if ((cls == SC_IN || cls == SC_KINK) && !lagged && nb >= 0 && where[(size_t)d * E + nb] >= batch0)
+                throw Error(SNSW_E_STATE, "schedule: a kept upwind pair does not precede its dependant");
         }
     }
 }

@@ -41,7 +41,8 @@ void level_symmetric(int N, int dim, std::vector<double>& omega, std::vector<dou
 // Face classes relative to the face normal N (minus -> plus element).
 enum FaceClass : uint8_t { FC_POS = 0, FC_NEG = 1, FC_KINK = 2 };
 // Slot classes from the element's point of view (packed in the schedule).
-enum SlotClass : uint32_t { SC_OUT = 0, SC_IN = 1, SC_KINK = 2 };
+// SC_NONE: the face carries no flux for this direction (both sides dropped).
+enum SlotClass : uint32_t { SC_OUT = 0, SC_IN = 1, SC_KINK = 2, SC_NONE = 3 };
 
 struct DirGraph {
     std::vector<int32_t> up, down;       // edges sorted by (down, up)
@@ -71,7 +72,7 @@ struct HostProblem {
     int n = 0, nf = 0, nslot = 0;
     int64_t E = 0, F = 0;
     int D = 0;
-    int weighting = 1, exact_max = 10, precision = 0, bc = 0, nthreads = 1;
+    int weighting = 1, exact_max = 10, precision = 0, bc = 0, nthreads = 1, schedule = 0;
     double psi_inc = 0.0;
     std::vector<double> lattice;              // [L][dim]
     std::vector<double> omega, w;             // [D][3], [D]
@@ -109,7 +110,9 @@ void build_graphs(HostProblem& hp);
 void build_schedule(HostProblem& hp);
 
 // Packed pair word: bits 0..9 direction, then per slot s 3 bits at 10+3s:
-// class (2 bits, SlotClass) and lag flag (bit 2).
+// class (2 bits, SlotClass) and lag flag (bit 2).  The lag flag is also set
+// when the slot's inflow side was dropped (its matrix is zero): such a slot
+// never waits for the upwind element.
 constexpr int kDirBits = 10;
 inline uint32_t pack_slot(uint32_t cls, bool lag, int s) {
     return (cls | (lag ? 4u : 0u)) << (kDirBits + 3 * s);

@@ -16,6 +16,9 @@
 // column-major so that the n lanes of a group load consecutive addresses.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace snsw {
@@ -25,7 +28,7 @@ namespace {
 constexpr int kWaves = 4;              // wavefronts per block
 constexpr int kDirMask = 1023;         // packed word: direction bits
 constexpr int kSlotShift = 10;         // then 3 bits per slot
-constexpr unsigned kOut = 0, kIn = 1, kKink = 2;
+constexpr unsigned kOut = 0, kIn = 1, kKink = 2, kNone = 3;
 
 template <int DIM, int P>
 struct Shape {
@@ -61,86 +64,113 @@ struct Shape {
     }
 };
 
+// Assembles row `row` of A and b for pair (e, d).  With DEFER, inflow through
+// kept couplings (read from this sweep's flux) is left out of b and the slots
+// that need it are returned in *kept; lagged and boundary inflow are added.
+template <int DIM, int P, bool DEFER, bool KEEP_PIN = false>
+__device__ __forceinline__ void assemble_row(const SweepArgs& args, int4 pr, int row, double (&a)[Shape<DIM, P>::N],
+                                             double& rhs, unsigned& kept, int (&krow)[2 * DIM],
+                                             double (*pk)[Shape<DIM, P>::NF] = nullptr) {
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, NF = S::NF, NS = S::NS;
+    const int e = pr.x;
+    const unsigned packed = (unsigned)pr.y;
+    const int kb = pr.z;
+    const int d = (int)(packed & kDirMask);
+    const double* Ge = args.geo + (size_t)e * (DIM + 1) * N * N;
+    const double st = args.sigma_t[e];
+    const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1], o2 = args.omega[3 * d + 2];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double v = st * Ge[j * N + row];
+        v -= o0 * Ge[1 * N * N + j * N + row];
+        v -= o1 * Ge[2 * N * N + j * N + row];
+        if (DIM == 3) v -= o2 * Ge[3 * N * N + j * N + row];
+        a[j] = v;
+    }
+    rhs = args.src[(size_t)e * N + row];
+    kept = 0;
+    int kc = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+        const bool lagged = (packed >> (kSlotShift + 3 * s + 2)) & 1u;
+        krow[s] = 0;
+        if (cls == kKink) krow[s] = args.kink_idx[kb + kc++];
+        if (cls == kNone) continue;
+        const int nb = args.slot_nbr[(size_t)e * NS + s];
+        const bool defer = DEFER && cls != kOut && nb >= 0 && !lagged;
+        if (defer) kept |= 1u << s;
+        const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+        if (!on) continue;
+        const int la = S::local(row, s);
+        double pout[NF], pin[NF];
+        if (cls == kKink) {
+            // element is the face's minus side on odd slots: out = P_plus
+            const double* T = args.kink_tab + (size_t)krow[s] * 2 * NF * NF;
+            const double* To = T + ((s & 1) ? 0 : NF * NF);
+            const double* Ti = T + ((s & 1) ? NF * NF : 0);
+#pragma unroll
+            for (int b = 0; b < NF; ++b) {
+                pout[b] = To[la * NF + b];
+                pin[b] = Ti[la * NF + b];
+            }
+        } else {
+            const int f = args.slot_face[(size_t)e * NS + s];
+            const double* Bf = args.B + (size_t)f * DIM * NF * NF + la * NF;
+            const double sgn = (s & 1) ? 1.0 : -1.0;   // outward normal = sgn * N
+#pragma unroll
+            for (int b = 0; b < NF; ++b) {
+                double v = o0 * Bf[b] + o1 * Bf[NF * NF + b];
+                if (DIM == 3) v += o2 * Bf[2 * NF * NF + b];
+                v *= sgn;                               // int (Omega . n_out) phi phi
+                pout[b] = cls == kOut ? v : 0.0;
+                pin[b] = cls == kOut ? 0.0 : -v;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NF; ++b) a[S::tn(s, b)] += pout[b];
+        if constexpr (KEEP_PIN) {
+            if (defer) {
+#pragma unroll
+                for (int b = 0; b < NF; ++b) pk[s][b] = pin[b];
+            }
+        }
+        if (cls != kOut && !defer) {
+            if (nb >= 0) {
+                const double* up = (lagged ? args.psi_prev : args.psi_cur) + ((size_t)d * args.E + nb) * N;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) rhs += pin[b] * up[S::tn(s ^ 1, b)];
+            } else {
+#pragma unroll
+                for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
+            }
+        }
+    }
+}
+
 template <int DIM, int P>
 __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(SweepArgs args, int64_t begin, int64_t count) {
     using S = Shape<DIM, P>;
-    constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
+    constexpr int N = S::N, G = S::G;
     __shared__ double lds[kWaves][G][N + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / N, row = lane - grp * N;
     const bool in_group = grp < G;
     const int64_t pidx = begin + ((int64_t)blockIdx.x * kWaves + wave) * G + grp;
-    const bool active = in_group && pidx < begin + count;
+    int4 pr = make_int4(-1, 0, 0, 0);
+    if (in_group && pidx < begin + count) pr = args.pairs[pidx];
+    const bool active = pr.x >= 0;    // padding entries have e = -1
 
     double a[N];
     double rhs = 0.0;
     int e = 0, d = 0;
     if (active) {
-        const int4 pr = args.pairs[pidx];
         e = pr.x;
-        const unsigned packed = (unsigned)pr.y;
-        const int kb = pr.z;
-        d = (int)(packed & kDirMask);
-        const double* Ge = args.geo + (size_t)e * (DIM + 1) * N * N;
-        const double st = args.sigma_t[e];
-        const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1], o2 = args.omega[3 * d + 2];
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            double v = st * Ge[j * N + row];
-            v -= o0 * Ge[1 * N * N + j * N + row];
-            v -= o1 * Ge[2 * N * N + j * N + row];
-            if (DIM == 3) v -= o2 * Ge[3 * N * N + j * N + row];
-            a[j] = v;
-        }
-        rhs = args.src[(size_t)e * N + row];
-        int kc = 0;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
-            const bool lagged = (packed >> (kSlotShift + 3 * s + 2)) & 1u;
-            int krow = 0;
-            if (cls == kKink) krow = args.kink_idx[kb + kc++];
-            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
-            if (!on) continue;
-            const int la = S::local(row, s);
-            double pout[NF], pin[NF];
-            if (cls == kKink) {
-                // element is the face's minus side on odd slots: out = P_plus
-                const double* T = args.kink_tab + (size_t)krow * 2 * NF * NF;
-                const double* To = T + ((s & 1) ? 0 : NF * NF);
-                const double* Ti = T + ((s & 1) ? NF * NF : 0);
-#pragma unroll
-                for (int b = 0; b < NF; ++b) {
-                    pout[b] = To[la * NF + b];
-                    pin[b] = Ti[la * NF + b];
-                }
-            } else {
-                const int f = args.slot_face[(size_t)e * NS + s];
-                const double* Bf = args.B + (size_t)f * DIM * NF * NF + la * NF;
-                const double sgn = (s & 1) ? 1.0 : -1.0;   // outward normal = sgn * N
-#pragma unroll
-                for (int b = 0; b < NF; ++b) {
-                    double v = o0 * Bf[b] + o1 * Bf[NF * NF + b];
-                    if (DIM == 3) v += o2 * Bf[2 * NF * NF + b];
-                    v *= sgn;                               // int (Omega . n_out) phi phi
-                    pout[b] = cls == kOut ? v : 0.0;
-                    pin[b] = cls == kOut ? 0.0 : -v;
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < NF; ++b) a[S::tn(s, b)] += pout[b];
-            if (cls != kOut) {
-                const int nb = args.slot_nbr[(size_t)e * NS + s];
-                if (nb >= 0) {
-                    const double* up = (lagged ? args.psi_prev : args.psi_cur) + ((size_t)d * args.E + nb) * N;
-#pragma unroll
-                    for (int b = 0; b < NF; ++b) rhs += pin[b] * up[S::tn(s ^ 1, b)];
-                } else {
-#pragma unroll
-                    for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
-                }
-            }
-        }
+        d = (int)((unsigned)pr.y & kDirMask);
+        unsigned kept;
+        int krow[2 * DIM];
+        assemble_row<DIM, P, false>(args, pr, row, a, rhs, kept, krow);
     } else {
 #pragma unroll
         for (int j = 0; j < N; ++j) a[j] = (j == row) ? 1.0 : 0.0;
@@ -178,6 +208,456 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(SweepArgs args, 
     if (active) args.psi_cur[((size_t)d * args.E + e) * N + row] = x;
 }
 
+// Orders LDS traffic of one wavefront (no hardware barrier needed: a
+// wavefront's LDS instructions execute in order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bit pattern marking "not yet written in this sweep": a quiet NaN whose
+// payload is the sweep epoch (>= 1), so it never equals a computed flux and
+// needs no reset between sweeps.
+__device__ __forceinline__ unsigned long long sentinel_bits(int epoch) {
+    return 0x7FF8000000000000ull | (unsigned long long)(unsigned)epoch;
+}
+
+// Persistent sweep: each wavefront repeatedly claims G consecutive pairs of
+// the level-ordered schedule.  Everything that does not depend on this
+// sweep's upwind fluxes is done first -- assembly, Gauss-Jordan inversion of
+// A, x0 = A^{-1} b0 with the lagged and boundary inflow in b0, and (2D) the
+// folded inflow operators W_s = A^{-1} P_in,s.  Then the wavefront polls the
+// upwind face values it needs until none holds this sweep's sentinel, and
+// finishes with x += sum_s A^{-1} P_in,s psi_up,s.  Fluxes are stored and
+// polled with device-scope accesses (coherent across the XCD L2 caches).
+// Pairs are claimed in increasing schedule order, levels are padded to whole
+// batches and every kept upwind pair sits on an earlier level, so each
+// awaited pair belongs to another running wavefront: the waits end.  A wait
+// that exceeds spin_limit polls sets *error and gives up (the result is then
+// wrong but the kernel still terminates).
+template <int DIM, int P>
+__global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs pa) {
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
+    constexpr bool FOLD = DIM == 2;   // 3D keeps the register budget for A and A^{-1}
+    __shared__ double lds[kWaves][G][N + 1];   // odd stride: groups hit different banks
+    __shared__ double ups[kWaves][G][NS][NF];
+    const SweepArgs& args = pa.s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / N, row = lane - grp * N;
+    const bool in_group = grp < G;
+    const int g0 = in_group ? grp : 0;
+    double* L = &lds[wave][g0][0];
+    const unsigned long long sent = sentinel_bits(pa.epoch);
+
+    while (true) {
+        unsigned t0 = 0;
+        if (lane == 0) t0 = atomicAdd(pa.ticket, (unsigned)G);
+        t0 = __shfl(t0, 0);
+        if ((int64_t)t0 >= pa.total) break;
+        const int64_t pidx = (int64_t)t0 + grp;
+        int4 pr = make_int4(-1, 0, 0, 0);
+        if (in_group && pidx < pa.total) pr = args.pairs[pidx];
+        const bool active = pr.x >= 0;    // padding entries have e = -1
+
+        double a[N], v[N];
+        double rhs = 0.0;
+        unsigned kept = 0;
+        int krow[2 * DIM];
+        if (active) {
+            assemble_row<DIM, P, true>(args, pr, row, a, rhs, kept, krow);
+        } else {
+#pragma unroll
+            for (int j = 0; j < N; ++j) a[j] = (j == row) ? 1.0 : 0.0;
+        }
+        const int e = active ? pr.x : 0;
+        const unsigned packed = (unsigned)pr.y;
+        const int d = (int)(packed & kDirMask);
+        const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1], o2 = args.omega[3 * d + 2];
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = (j == row) ? 1.0 : 0.0;
+
+        // Gauss-Jordan: row `row` of A^{-1} into v.  At step k the pivot row
+        // holds v (support 0..k) in slots <= k and a in slots > k.
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (in_group && row == k) {
+                const double r = 1.0 / a[k];
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    if (j > k) { a[j] *= r; L[j] = a[j]; }
+                    else { v[j] *= r; L[j] = v[j]; }
+                }
+            }
+            wave_sync();
+            if (in_group && row != k) {
+                const double f = a[k];
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    if (j > k) a[j] -= f * L[j];
+                    else v[j] -= f * L[j];
+                }
+            }
+            wave_sync();
+        }
+        // x0 = A^{-1} b0
+        if (in_group) L[row] = rhs;
+        wave_sync();
+        double x = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) x += v[j] * L[j];
+        wave_sync();
+
+        // inflow matrix entry P_in,s[a][b] of a kept slot
+        auto pin_entry = [&](int s, int aa, int b) -> double {
+            const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+            if (cls == kKink)
+                return args.kink_tab[(size_t)krow[s] * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + aa * NF + b];
+            const int f = args.slot_face[(size_t)e * NS + s];
+            const double* Bf = args.B + (size_t)f * DIM * NF * NF + aa * NF + b;
+            double pv = o0 * Bf[0] + o1 * Bf[NF * NF];
+            if (DIM == 3) pv += o2 * Bf[2 * NF * NF];
+            return (s & 1) ? -pv : pv;    // P_in = -(outward) normal moments
+        };
+        double W[FOLD ? NS : 1][FOLD ? NF : 1];
+        if constexpr (FOLD) {
+            // W_s[b] = sum_a A^{-1}[row][tn_s(a)] P_in,s[a][b]
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+#pragma unroll
+                for (int b = 0; b < NF; ++b) W[s][b] = 0.0;
+                if (!(active && ((kept >> s) & 1u))) continue;
+#pragma unroll
+                for (int aa = 0; aa < NF; ++aa) {
+                    const double va = v[S::tn(s, aa)];
+#pragma unroll
+                    for (int b = 0; b < NF; ++b) W[s][b] += va * pin_entry(s, aa, b);
+                }
+            }
+        }
+
+        // Wait: the lane on face-local node la of a kept slot polls the
+        // upwind element's value at the matching node.
+        const double* addr[NS];
+        bool need[NS];
+        double own[NS];
+        bool ok = true;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+            need[s] = active && on && ((kept >> s) & 1u);
+            addr[s] = args.psi_cur;
+            own[s] = 0.0;
+            if (need[s]) {
+                const int nb = args.slot_nbr[(size_t)e * NS + s];
+                // the neighbour's node facing this lane's node
+                addr[s] = args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, S::local(row, s));
+                ok = false;
+            }
+        }
+        int polls = 0;
+        while (true) {
+            if (!ok) {
+                bool all = true;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (!need[s]) continue;
+                    const double val =
+                        __hip_atomic_load(const_cast<double*>(addr[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((unsigned long long)__double_as_longlong(val) == sent) all = false;
+                    else { own[s] = val; need[s] = false; }
+                }
+                ok = all;
+            }
+            if (__all(ok)) break;
+            if (++polls > pa.spin_limit) {
+                if (!ok) atomicExch(pa.error, 1);
+                break;
+            }
+            if ((polls & 255) == 0) {
+                // another wait already failed: stop waiting so the grid drains
+                int err = 0;
+                if (lane == 0) err = __hip_atomic_load(pa.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__shfl(err, 0)) break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        // share the upwind values inside the group
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+            if (in_group && on && ((kept >> s) & 1u)) ups[wave][g0][s][S::local(row, s)] = own[s];
+        }
+        wave_sync();
+        if constexpr (FOLD) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (!((kept >> s) & 1u)) continue;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) x += W[s][b] * ups[wave][g0][s][b];
+            }
+            wave_sync();
+        } else {
+            // c_s = P_in psi_up on the slot's lanes, then x += A^{-1}[:, tn_s] c_s
+            double c[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                c[s] = 0.0;
+                const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+                if (!(active && on && ((kept >> s) & 1u))) continue;
+                const int la = S::local(row, s);
+#pragma unroll
+                for (int b = 0; b < NF; ++b) c[s] += pin_entry(s, la, b) * ups[wave][g0][s][b];
+            }
+            wave_sync();
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+                if (in_group && on && ((kept >> s) & 1u)) ups[wave][g0][s][S::local(row, s)] = c[s];
+            }
+            wave_sync();
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (!((kept >> s) & 1u)) continue;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) x += v[S::tn(s, b)] * ups[wave][g0][s][b];
+            }
+            wave_sync();
+        }
+        // publish with device-scope (write-through) stores
+        if (active)
+            __hip_atomic_store(args.psi_cur + ((size_t)d * args.E + e) * N + row, x, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Broadcast of lane K of each group of N lanes to the whole group, register
+// to register: DPP row broadcast for 16-lane groups, quad permutation for
+// 4-lane groups.
+template <int N, int K>
+__device__ __forceinline__ double group_bcast(double x) {
+    static_assert(N == 16 || N == 4, "DPP broadcast needs 4- or 16-lane groups");
+    constexpr int ctrl = N == 16 ? 0x150 + K : (K | (K << 2) | (K << 4) | (K << 6));
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Persistent sweep for 4- and 16-lane groups (2D, p = 1 and p = 3): the same
+// schedule and protocol as sweep_persistent_fp64, with every intra-group
+// exchange done by DPP broadcasts.  Register economy decides occupancy here:
+// the matrix columns are assembled in chunks, the inflow rows of the
+// deferred slots are parked in LDS (each face lane writes its own row), and
+// after the wait the face lanes form c = P_in psi_up, which is broadcast into
+// x += A^{-1}[:, tn_s] c.
+template <int DIM, int P>
+__global__ void __launch_bounds__(64 * kWaves) sweep_persistent_dpp(PersistArgs pa) {
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
+    constexpr int CH = 4;   // matrix columns assembled per chunk
+    static_assert(G * N == 64, "groups must tile the wavefront");
+    __shared__ double pin_lds[kWaves][G][NS][NF][NF + 1];
+    const SweepArgs& args = pa.s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / N, row = lane - grp * N;
+    const unsigned long long sent = sentinel_bits(pa.epoch);
+
+    while (true) {
+        unsigned t0 = 0;
+        if (lane == 0) t0 = atomicAdd(pa.ticket, (unsigned)G);
+        t0 = __shfl(t0, 0);
+        if ((int64_t)t0 >= pa.total) break;
+        const int64_t pidx = (int64_t)t0 + grp;
+        int4 pr = make_int4(-1, 0, 0, 0);
+        if (pidx < pa.total) pr = args.pairs[pidx];
+        const bool active = pr.x >= 0;    // padding entries have e = -1
+        const int e = active ? pr.x : 0;
+        const unsigned packed = (unsigned)pr.y;
+        const int d = (int)(packed & kDirMask);
+
+        // ---- assembly of row `row`, branch-free: padding lanes assemble
+        // element 0 and are masked (divergent branches here would keep two
+        // copies of the row alive).  Volume part in chunks of CH columns.
+        double m[N];
+        {
+            const double* Ge = args.geo + (size_t)e * (DIM + 1) * N * N + row;
+            const double st = args.sigma_t[e];
+            const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1];
+#pragma unroll
+            for (int j0 = 0; j0 < N; j0 += CH) {
+#pragma unroll
+                for (int j = j0; j < j0 + CH; ++j)
+                    m[j] = st * Ge[j * N] - o0 * Ge[N * N + j * N] - o1 * Ge[2 * N * N + j * N];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // ---- faces
+        double rhs = args.src[(size_t)e * N + row];
+        unsigned kept = 0;
+        int kc = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const unsigned cls = active ? (packed >> (kSlotShift + 3 * s)) & 3u : kNone;
+            const bool lagged = (packed >> (kSlotShift + 3 * s + 2)) & 1u;
+            if (cls == kNone) continue;
+            int krow = 0;
+            if (cls == kKink) krow = args.kink_idx[pr.z + kc++];
+            const int nb = args.slot_nbr[(size_t)e * NS + s];
+            const bool defer = cls != kOut && nb >= 0 && !lagged;
+            if (defer) kept |= 1u << s;
+            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+            if (!on) continue;
+            const int la = S::local(row, s);
+            double pout[NF], pin[NF];
+            if (cls == kKink) {
+                const double* T = args.kink_tab + (size_t)krow * 2 * NF * NF;
+                const double* To = T + ((s & 1) ? 0 : NF * NF);
+                const double* Ti = T + ((s & 1) ? NF * NF : 0);
+#pragma unroll
+                for (int b = 0; b < NF; ++b) {
+                    pout[b] = To[la * NF + b];
+                    pin[b] = Ti[la * NF + b];
+                }
+            } else {
+                const int f = args.slot_face[(size_t)e * NS + s];
+                const double* Bf = args.B + (size_t)f * DIM * NF * NF + la * NF;
+                const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1];
+                const double sgn = (s & 1) ? 1.0 : -1.0;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) {
+                    const double vv = sgn * (o0 * Bf[b] + o1 * Bf[NF * NF + b]);
+                    pout[b] = cls == kOut ? vv : 0.0;
+                    pin[b] = cls == kOut ? 0.0 : -vv;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < NF; ++b) m[S::tn(s, b)] += pout[b];
+            if (cls == kOut) continue;
+            if (defer) {
+#pragma unroll
+                for (int b = 0; b < NF; ++b) pin_lds[wave][grp][s][la][b] = pin[b];
+            } else if (nb >= 0) {
+                const double* up = args.psi_prev + ((size_t)d * args.E + nb) * N;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) rhs += pin[b] * up[S::tn(s ^ 1, b)];
+            } else {
+#pragma unroll
+                for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
+            }
+        }
+        // ---- in-place Gauss-Jordan: m ends as row `row` of A^{-1}
+        static_for<0, N>([&](auto kc2) {
+            constexpr int k = decltype(kc2)::value;
+            const bool piv = row == k;
+            const double r = 1.0 / m[k];
+            const double f = piv ? 0.0 : m[k];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                if (j == k) m[j] = piv ? r : 0.0;
+                else m[j] = piv ? m[j] * r : m[j];
+            }
+            static_for<0, N>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                m[j] -= f * group_bcast<N, k>(m[j]);
+            });
+        });
+        // x0 = A^{-1} b0
+        double x = 0.0;
+        static_for<0, N>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            x += m[j] * group_bcast<N, j>(rhs);
+        });
+
+        // ---- wait and finish: the lane on face-local node la of a kept slot
+        // polls the upwind element's value at the matching node; each group
+        // finishes its pair as soon as all of its values are there, so the
+        // pairs of one wavefront do not wait for each other.
+        const double* addr[NS];
+        bool need[NS];
+        double own[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+            need[s] = active && on && ((kept >> s) & 1u);
+            addr[s] = args.psi_cur;
+            own[s] = 0.0;
+            if (need[s]) {
+                const int nb = args.slot_nbr[(size_t)e * NS + s];
+                addr[s] = args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, S::local(row, s));
+            }
+        }
+        constexpr unsigned long long gmask = N == 64 ? ~0ull : ((1ull << N) - 1ull);
+        bool done = !active;
+        int polls = 0;
+        while (true) {
+            bool have = true;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (!need[s]) continue;
+                const double val =
+                    __hip_atomic_load(const_cast<double*>(addr[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((unsigned long long)__double_as_longlong(val) == sent) have = false;
+                else { own[s] = val; need[s] = false; }
+            }
+            const unsigned long long ready = __ballot(have);
+            const bool gready = ((ready >> (grp * N)) & gmask) == gmask;
+            if (gready && !done) {
+                // c_s[la] = sum_b P_in,s[la][b] psi_up,s[b] on the face lanes
+                // (psi_up,s[b] sits on lane tn_s(b)); then
+                // x += sum_a A^{-1}[row][tn_s(a)] c_s[a].  The whole group
+                // takes this branch together, so the DPP sources are active.
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                static_for<0, NS>([&](auto sc) {
+                    constexpr int s = decltype(sc)::value;
+                    if ((kept >> s) & 1u) {
+                        const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+                        const int la = on ? S::local(row, s) : 0;
+                        double c = 0.0;
+                        static_for<0, NF>([&](auto bc) {
+                            constexpr int b = decltype(bc)::value;
+                            c += pin_lds[wave][grp][s][la][b] * group_bcast<N, S::tn(s, b)>(own[s]);
+                        });
+                        static_for<0, NF>([&](auto ac) {
+                            constexpr int aa = decltype(ac)::value;
+                            x += m[S::tn(s, aa)] * group_bcast<N, S::tn(s, aa)>(c);
+                        });
+                    }
+                });
+                __hip_atomic_store(args.psi_cur + ((size_t)d * args.E + e) * N + row, x, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                done = true;
+            }
+            if (__all(done)) break;
+            if (++polls > pa.spin_limit) {
+                atomicExch(pa.error, 1);
+                break;
+            }
+            if ((polls & 255) == 0) {
+                // another wait already failed: stop waiting so the grid drains
+                int err = 0;
+                if (lane == 0) err = __hip_atomic_load(pa.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__shfl(err, 0)) break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+}
+
+__global__ void fill_sentinel_kernel(unsigned long long* p, int64_t count, unsigned long long bits) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = bits;
+}
+
 template <int DIM, int P>
 void launch_tpl(const SweepArgs& a, int64_t begin, int64_t count, hipStream_t stream) {
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
@@ -187,10 +667,38 @@ void launch_tpl(const SweepArgs& a, int64_t begin, int64_t count, hipStream_t st
                        begin, count);
 }
 
+// groups of 4 or 16 lanes exchange values by DPP, the others through LDS
+template <int DIM, int P>
+constexpr bool use_dpp() {
+    return Shape<DIM, P>::N == 16 || Shape<DIM, P>::N == 4;
+}
+
+template <int DIM, int P>
+void launch_persist_tpl(const PersistArgs& a, int blocks, hipStream_t stream) {
+    if constexpr (use_dpp<DIM, P>())
+        hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, a);
+    else
+        hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, a);
+}
+
+template <int DIM, int P>
+int occupancy_tpl() {
+    int nb = 0;
+    hipError_t rc;
+    if constexpr (use_dpp<DIM, P>())
+        rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P>, 64 * kWaves, 0);
+    else
+        rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P>, 64 * kWaves, 0);
+    if (rc != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
 __global__ void source_kernel(int dim, int n, int64_t E, const double* __restrict__ geo,
                               const double* __restrict__ q, const double* __restrict__ sigma_s,
-                              const double* __restrict__ phi, double* __restrict__ src) {
+                              const double* __restrict__ phi, double* __restrict__ src,
+                              unsigned int* ticket) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0 && ticket) *ticket = 0u;
     if (t >= E * n) return;
     const int64_t e = t / n;
     const int i = (int)(t - e * n);
@@ -255,11 +763,38 @@ void launch_sweep_level(int dim, int p, bool mixed, const SweepArgs& a, int64_t 
 }
 
 void launch_source(int dim, int n, int64_t E, const double* geo, const double* q, const double* sigma_s,
-                   const double* phi, double* src, hipStream_t stream) {
+                   const double* phi, double* src, unsigned int* ticket, hipStream_t stream) {
     const int64_t tot = E * n;
     const int64_t blocks = (tot + 255) / 256;
     hipLaunchKernelGGL(source_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, dim, n, E, geo, q, sigma_s,
-                       phi, src);
+                       phi, src, ticket);
+}
+
+void launch_fill_sentinel(double* psi, int64_t count, int epoch, hipStream_t stream) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    const unsigned long long bits = 0x7FF8000000000000ull | (unsigned long long)(unsigned)epoch;
+    hipLaunchKernelGGL(fill_sentinel_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                       reinterpret_cast<unsigned long long*>(psi), count, bits);
+}
+
+void launch_sweep_persistent(int dim, int p, bool mixed, const PersistArgs& a, int blocks, hipStream_t stream) {
+    (void)mixed;
+    if (dim == 2) {
+        if (p == 1) launch_persist_tpl<2, 1>(a, blocks, stream);
+        else if (p == 2) launch_persist_tpl<2, 2>(a, blocks, stream);
+        else launch_persist_tpl<2, 3>(a, blocks, stream);
+    } else {
+        if (p == 1) launch_persist_tpl<3, 1>(a, blocks, stream);
+        else if (p == 2) launch_persist_tpl<3, 2>(a, blocks, stream);
+        else launch_persist_tpl<3, 3>(a, blocks, stream);
+    }
+}
+
+int persistent_blocks_per_cu(int dim, int p, bool mixed) {
+    (void)mixed;
+    if (dim == 2) return p == 1 ? occupancy_tpl<2, 1>() : p == 2 ? occupancy_tpl<2, 2>() : occupancy_tpl<2, 3>();
+    return p == 1 ? occupancy_tpl<3, 1>() : p == 2 ? occupancy_tpl<3, 2>() : occupancy_tpl<3, 3>();
 }
 
 void launch_scalar_flux(int D, int64_t En, const double* w, const double* psi, double* phi, hipStream_t stream) {

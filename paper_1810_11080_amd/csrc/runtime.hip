@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -39,6 +41,10 @@ struct DeviceProblem {
     double* psi[2] = {nullptr, nullptr};
     double* phi_tmp = nullptr;    // [E][n]
     unsigned long long* red = nullptr;   // residual scratch [2]
+    unsigned int* ticket = nullptr;
+    int32_t* error = nullptr;     // device-side wait failure flag
+    int32_t epoch = 0;
+    int blocks = 0;               // persistent grid size
     int cur = 0;                  // psi[cur] holds the previous sweep
     std::vector<int64_t> level_off;
     size_t bytes = 0;
@@ -87,7 +93,9 @@ void do_sweep(snsw_problem* prob, const double* phi_in, double* phi_out, double*
     DeviceProblem* dp = need_device(prob);
     const HostProblem& hp = prob->hp;
     const hipStream_t s = dp->stream;
-    launch_source(hp.dim, hp.n, hp.E, dp->geo, dp->q, dp->sigma_s, phi_in, dp->src, s);
+    const bool persistent = hp.schedule == SNSW_SCHED_PERSISTENT;
+    launch_source(hp.dim, hp.n, hp.E, dp->geo, dp->q, dp->sigma_s, phi_in, dp->src,
+                  persistent ? dp->ticket : nullptr, s);
     HIP_OK(hipGetLastError());
     SweepArgs a;
     a.pairs = dp->pairs;
@@ -105,7 +113,28 @@ void do_sweep(snsw_problem* prob, const double* phi_in, double* phi_out, double*
     a.psi_inc = hp.psi_inc;
     a.E = hp.E;
     const bool mixed = hp.precision == SNSW_PREC_MIXED;
-    for (size_t k = 0; k + 1 < dp->level_off.size(); ++k) {
+    if (persistent) {
+        if (dp->epoch == INT32_MAX) dp->epoch = 0;   // sentinel payloads only need to differ from 0
+        PersistArgs pa;
+        pa.s = a;
+        pa.ticket = dp->ticket;
+        pa.error = dp->error;
+        pa.total = dp->level_off.back();
+        pa.epoch = ++dp->epoch;
+        pa.spin_limit = 1 << 20;
+        launch_fill_sentinel(a.psi_cur, (int64_t)hp.D * hp.E * hp.n, pa.epoch, s);
+        if (dp->profiling) {
+            while (dp->n_events + 2 > dp->events.size()) {
+                hipEvent_t ev;
+                HIP_OK(hipEventCreate(&ev));
+                dp->events.push_back(ev);
+            }
+            HIP_OK(hipEventRecord(dp->events[dp->n_events++], s));
+        }
+        launch_sweep_persistent(hp.dim, hp.p, mixed, pa, dp->blocks, s);
+        if (dp->profiling) HIP_OK(hipEventRecord(dp->events[dp->n_events++], s));
+    }
+    for (size_t k = 0; !persistent && k + 1 < dp->level_off.size(); ++k) {
         const int64_t b = dp->level_off[k], c = dp->level_off[k + 1] - b;
         if (dp->profiling) {
             while (dp->n_events + 2 > dp->events.size()) {
@@ -128,6 +157,17 @@ void do_sweep(snsw_problem* prob, const double* phi_in, double* phi_out, double*
     dp->cur = 1 - dp->cur;
 }
 
+void check_device_error(DeviceProblem* dp) {
+    int32_t err = 0;
+    HIP_OK(hipMemcpyAsync(&err, dp->error, sizeof(err), hipMemcpyDeviceToHost, dp->stream));
+    HIP_OK(hipStreamSynchronize(dp->stream));
+    if (err) {
+        HIP_OK(hipMemsetAsync(dp->error, 0, sizeof(int32_t), dp->stream));
+        HIP_OK(hipStreamSynchronize(dp->stream));
+        throw Error(SNSW_E_STATE, "a dependency wait of the persistent sweep timed out; results are invalid");
+    }
+}
+
 double do_residual(DeviceProblem* dp, int64_t len, const double* a, const double* b) {
     HIP_OK(hipMemsetAsync(dp->red, 0, 2 * sizeof(unsigned long long), dp->stream));
     launch_residual(len, a, b, dp->red, dp->stream);
@@ -135,6 +175,7 @@ double do_residual(DeviceProblem* dp, int64_t len, const double* a, const double
     unsigned long long h[2] = {0, 0};
     HIP_OK(hipMemcpyAsync(h, dp->red, sizeof(h), hipMemcpyDeviceToHost, dp->stream));
     HIP_OK(hipStreamSynchronize(dp->stream));
+    check_device_error(dp);
     double num, den;
     std::memcpy(&num, &h[0], 8);
     std::memcpy(&den, &h[1], 8);
@@ -199,7 +240,20 @@ void device_upload(snsw_problem* prob) {
         HIP_OK(hipMemsetAsync(dp->psi[b], 0, sizeof(double) * hp.D * hp.E * n, s));
     }
     dp->red = dalloc<unsigned long long>(dp, 2);
+    dp->ticket = dalloc<unsigned int>(dp, 1);
+    HIP_OK(hipMemsetAsync(dp->ticket, 0, sizeof(unsigned int), s));
+    dp->error = dalloc<int32_t>(dp, 1);
+    HIP_OK(hipMemsetAsync(dp->error, 0, sizeof(int32_t), s));
     dp->level_off = hp.level_off;
+    {
+        int cus = 0;
+        HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dp->device));
+        const int per_cu = persistent_blocks_per_cu(hp.dim, hp.p, hp.precision == SNSW_PREC_MIXED);
+        const int64_t total = hp.level_off.back();
+        const int64_t per_block = 4 * (64 / hp.n);
+        const int64_t need = (total + per_block - 1) / per_block;
+        dp->blocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * cus));
+    }
     HIP_OK(hipStreamSynchronize(s));
 }
 
@@ -213,7 +267,7 @@ void device_release(snsw_problem* prob) noexcept {
     for (hipEvent_t ev : dp->events) (void)hipEventDestroy(ev);
     void* ptrs[] = {dp->geo, dp->B, dp->kink_tab, dp->kink_idx, dp->pairs, dp->slot_face, dp->slot_nbr,
                     dp->sigma_t, dp->sigma_s, dp->q, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
-                    dp->phi_tmp, dp->red};
+                    dp->phi_tmp, dp->red, dp->ticket, dp->error};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -244,6 +298,14 @@ int snsw_reset(snsw_problem* prob) {
         for (int b = 0; b < 2; ++b)
             HIP_OK(hipMemsetAsync(dp->psi[b], 0, sizeof(double) * hp.D * hp.E * hp.n, dp->stream));
         dp->cur = 0;
+    });
+}
+
+int snsw_synchronize(snsw_problem* prob) {
+    return snsw_guard([&] {
+        DeviceProblem* dp = need_device(prob);
+        DeviceGuard g(dp->device);
+        check_device_error(dp);
     });
 }
 
@@ -327,6 +389,7 @@ int snsw_profile_read(snsw_problem* prob, int64_t* launches, double* kernel_ms) 
         if (launches) *launches = (int64_t)(dp->n_events / 2);
         if (kernel_ms) *kernel_ms = total;
         dp->n_events = 0;
+        check_device_error(dp);
     });
 }
 

@@ -84,12 +84,14 @@ SMALL = {
 }
 
 
+@pytest.mark.parametrize("schedule", [0, 1], ids=["persistent", "levels"])
 @pytest.mark.parametrize("case", sorted(SMALL))
-def test_sweeps_match_oracle(torch, ctx, case):
+def test_sweeps_match_oracle(torch, ctx, case, schedule):
     from paper_1810_11080_amd import Problem
     wp = SMALL[case]()
-    P = Problem.from_workload(ctx, wp)
+    P = Problem.from_workload(ctx, wp, schedule=schedule)
     g_phi, g_psi = gpu_sweeps(torch, P, 3)
+    P.synchronize()
     o_phi, o_psi, _, _ = oracle_sweeps(wp, 3)
     for k in range(3):
         assert rel_err(g_phi[k], o_phi[k]) < TOL, (case, k)
@@ -102,6 +104,7 @@ def test_random_problems(torch, ctx, seed):
     wp = W.random_problem(seed, dim=2 if seed < 5 else 3)
     P = Problem.from_workload(ctx, wp)
     g_phi, g_psi = gpu_sweeps(torch, P, 2)
+    P.synchronize()
     o_phi, o_psi, _, _ = oracle_sweeps(wp, 2)
     assert rel_err(g_phi[-1], o_phi[-1]) < TOL
     assert rel_err(g_psi[-1], o_psi[-1]) < TOL
@@ -121,21 +124,30 @@ def test_c1_converged(torch, ctx):
     assert rep["history"][-1] <= 1e-12
 
 
-def test_c2_full_one_sweep(torch, ctx):
+@pytest.fixture(scope="module")
+def c2_oracle():
+    wp = W.c2()
+    rng = np.random.default_rng(7)
+    E, n, D = wp.n_elements, wp.n_dof, wp.n_dirs
+    phi0 = rng.uniform(0.0, 2.0, (E, n))
+    psi0 = rng.uniform(0.0, 0.2, (D, E, n))
+    o_phi, o_psi, _, _ = oracle_sweeps(wp, 1, phi0, psi0)
+    return wp, phi0, psi0, o_phi[0], o_psi[0]
+
+
+@pytest.mark.parametrize("schedule", [0, 1], ids=["persistent", "levels"])
+def test_c2_full_one_sweep(torch, ctx, c2_oracle, schedule):
     """128x128 Q3 p=3 S8 (cyclic graphs), one sweep from seeded scalar flux
     and seeded lagged angular flux, against the oracle."""
     from paper_1810_11080_amd import Problem
-    wp = W.c2()
-    P = Problem.from_workload(ctx, wp)
+    wp, phi0, psi0, o_phi, o_psi = c2_oracle
+    P = Problem.from_workload(ctx, wp, schedule=schedule)
     assert P.info()["n_removed_total"] > 0
-    rng = np.random.default_rng(7)
-    phi0 = rng.uniform(0.0, 2.0, (P.E, P.n))
-    psi0 = rng.uniform(0.0, 0.2, (P.D, P.E, P.n))
     P.state_load(state_bytes(wp, psi0))
     g_phi, g_psi = gpu_sweeps(torch, P, 1, phi0)
-    o_phi, o_psi, _, _ = oracle_sweeps(wp, 1, phi0, psi0)
-    assert rel_err(g_phi[0], o_phi[0]) < TOL
-    assert rel_err(g_psi[0], o_psi[0]) < TOL
+    P.synchronize()
+    assert rel_err(g_phi[0], o_phi) < TOL
+    assert rel_err(g_psi[0], o_psi) < TOL
 
 
 def test_constant_solution_full_size(torch, ctx):
