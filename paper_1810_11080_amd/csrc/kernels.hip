@@ -251,11 +251,19 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
     double* L = &lds[wave][g0][0];
     const unsigned long long sent = sentinel_bits(pa.epoch);
 
+    // The next batch is claimed while the current one is processed, which
+    // hides the atomic's latency.  Deadlock-free: the smallest unfinished
+    // ticket is always being processed (a held-but-unstarted ticket implies
+    // a smaller unfinished one in progress), and its upwind pairs are in
+    // smaller, finished tickets.
+    unsigned t_next = 0;
+    if (lane == 0) t_next = atomicAdd(pa.ticket, (unsigned)G);
+    t_next = __shfl(t_next, 0);
     while (true) {
-        unsigned t0 = 0;
-        if (lane == 0) t0 = atomicAdd(pa.ticket, (unsigned)G);
-        t0 = __shfl(t0, 0);
+        const unsigned t0 = t_next;
         if ((int64_t)t0 >= pa.total) break;
+        unsigned t_pre = 0;
+        if (lane == 0) t_pre = atomicAdd(pa.ticket, (unsigned)G);
         const int64_t pidx = (int64_t)t0 + grp;
         int4 pr = make_int4(-1, 0, 0, 0);
         if (in_group && pidx < pa.total) pr = args.pairs[pidx];
@@ -430,6 +438,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
         if (active)
             __hip_atomic_store(args.psi_cur + ((size_t)d * args.E + e) * N + row, x, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+        t_next = __shfl(t_pre, 0);
     }
 }
 
@@ -456,15 +465,14 @@ __device__ __forceinline__ void static_for(F&& f) {
 // Persistent sweep for 4- and 16-lane groups (2D, p = 1 and p = 3): the same
 // schedule and protocol as sweep_persistent_fp64, with every intra-group
 // exchange done by DPP broadcasts.  Register economy decides occupancy here:
-// the matrix columns are assembled in chunks, the inflow rows of the
+// the assembly is branch-free, the inflow rows of the
 // deferred slots are parked in LDS (each face lane writes its own row), and
 // after the wait the face lanes form c = P_in psi_up, which is broadcast into
 // x += A^{-1}[:, tn_s] c.
 template <int DIM, int P>
-__global__ void __launch_bounds__(64 * kWaves) sweep_persistent_dpp(PersistArgs pa) {
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3, 8))) sweep_persistent_dpp(PersistArgs pa) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
-    constexpr int CH = 4;   // matrix columns assembled per chunk
     static_assert(G * N == 64, "groups must tile the wavefront");
     __shared__ double pin_lds[kWaves][G][NS][NF][NF + 1];
     const SweepArgs& args = pa.s;
@@ -472,11 +480,19 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_dpp(PersistArgs 
     const int grp = lane / N, row = lane - grp * N;
     const unsigned long long sent = sentinel_bits(pa.epoch);
 
+    // The next batch is claimed while the current one is processed, which
+    // hides the atomic's latency.  Deadlock-free: the smallest unfinished
+    // ticket is always being processed (a held-but-unstarted ticket implies
+    // a smaller unfinished one in progress), and its upwind pairs are in
+    // smaller, finished tickets.
+    unsigned t_next = 0;
+    if (lane == 0) t_next = atomicAdd(pa.ticket, (unsigned)G);
+    t_next = __shfl(t_next, 0);
     while (true) {
-        unsigned t0 = 0;
-        if (lane == 0) t0 = atomicAdd(pa.ticket, (unsigned)G);
-        t0 = __shfl(t0, 0);
+        const unsigned t0 = t_next;
         if ((int64_t)t0 >= pa.total) break;
+        unsigned t_pre = 0;
+        if (lane == 0) t_pre = atomicAdd(pa.ticket, (unsigned)G);
         const int64_t pidx = (int64_t)t0 + grp;
         int4 pr = make_int4(-1, 0, 0, 0);
         if (pidx < pa.total) pr = args.pairs[pidx];
@@ -487,32 +503,37 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_dpp(PersistArgs 
 
         // ---- assembly of row `row`, branch-free: padding lanes assemble
         // element 0 and are masked (divergent branches here would keep two
-        // copies of the row alive).  Volume part in chunks of CH columns.
+        // copies of the row alive).
         double m[N];
         {
             const double* Ge = args.geo + (size_t)e * (DIM + 1) * N * N + row;
             const double st = args.sigma_t[e];
             const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1];
 #pragma unroll
-            for (int j0 = 0; j0 < N; j0 += CH) {
+            for (int j = 0; j < N; ++j) m[j] = st * Ge[j * N] - o0 * Ge[N * N + j * N] - o1 * Ge[2 * N * N + j * N];
+        }
+        // ---- faces.  All index loads first (one round trip together with
+        // the volume loads), then all face data (a second one).
+        int nbs[NS], fcs[NS], krows[NS];
+        {
+            int kc = 0;
 #pragma unroll
-                for (int j = j0; j < j0 + CH; ++j)
-                    m[j] = st * Ge[j * N] - o0 * Ge[N * N + j * N] - o1 * Ge[2 * N * N + j * N];
-                __builtin_amdgcn_sched_barrier(0);
+            for (int s = 0; s < NS; ++s) {
+                nbs[s] = args.slot_nbr[(size_t)e * NS + s];
+                fcs[s] = args.slot_face[(size_t)e * NS + s];
+                const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+                krows[s] = (active && cls == kKink) ? args.kink_idx[pr.z + kc] : 0;
+                kc += (cls == kKink) ? 1 : 0;
             }
         }
-        // ---- faces
         double rhs = args.src[(size_t)e * N + row];
         unsigned kept = 0;
-        int kc = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const unsigned cls = active ? (packed >> (kSlotShift + 3 * s)) & 3u : kNone;
             const bool lagged = (packed >> (kSlotShift + 3 * s + 2)) & 1u;
             if (cls == kNone) continue;
-            int krow = 0;
-            if (cls == kKink) krow = args.kink_idx[pr.z + kc++];
-            const int nb = args.slot_nbr[(size_t)e * NS + s];
+            const int nb = nbs[s];
             const bool defer = cls != kOut && nb >= 0 && !lagged;
             if (defer) kept |= 1u << s;
             const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
@@ -520,7 +541,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_dpp(PersistArgs 
             const int la = S::local(row, s);
             double pout[NF], pin[NF];
             if (cls == kKink) {
-                const double* T = args.kink_tab + (size_t)krow * 2 * NF * NF;
+                const double* T = args.kink_tab + (size_t)krows[s] * 2 * NF * NF;
                 const double* To = T + ((s & 1) ? 0 : NF * NF);
                 const double* Ti = T + ((s & 1) ? NF * NF : 0);
 #pragma unroll
@@ -529,8 +550,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_dpp(PersistArgs 
                     pin[b] = Ti[la * NF + b];
                 }
             } else {
-                const int f = args.slot_face[(size_t)e * NS + s];
-                const double* Bf = args.B + (size_t)f * DIM * NF * NF + la * NF;
+                const double* Bf = args.B + (size_t)fcs[s] * DIM * NF * NF + la * NF;
                 const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1];
                 const double sgn = (s & 1) ? 1.0 : -1.0;
 #pragma unroll
@@ -555,6 +575,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_dpp(PersistArgs 
                 for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
             }
         }
+
         // ---- in-place Gauss-Jordan: m ends as row `row` of A^{-1}
         static_for<0, N>([&](auto kc2) {
             constexpr int k = decltype(kc2)::value;
@@ -592,22 +613,28 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_dpp(PersistArgs 
             addr[s] = args.psi_cur;
             own[s] = 0.0;
             if (need[s]) {
-                const int nb = args.slot_nbr[(size_t)e * NS + s];
-                addr[s] = args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, S::local(row, s));
+                addr[s] = args.psi_cur + ((size_t)d * args.E + nbs[s]) * N + S::tn(s ^ 1, S::local(row, s));
             }
         }
         constexpr unsigned long long gmask = N == 64 ? ~0ull : ((1ull << N) - 1ull);
         bool done = !active;
         int polls = 0;
         while (true) {
+            // Only the lane on the first node of a face polls; the other
+            // face lanes load once it has seen data.  This keeps the polling
+            // traffic (device-scope loads bypass the L2) low.
             bool have = true;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                if (!need[s]) continue;
-                const double val =
-                    __hip_atomic_load(const_cast<double*>(addr[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if ((unsigned long long)__double_as_longlong(val) == sent) have = false;
-                else { own[s] = val; need[s] = false; }
+                const bool leader = row == S::tn(s, 0);
+                const unsigned long long lead_done = __ballot(!need[s]);
+                const bool go = need[s] && (leader || ((lead_done >> (grp * N + S::tn(s, 0))) & 1ull));
+                if (go) {
+                    const double val =
+                        __hip_atomic_load(const_cast<double*>(addr[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((unsigned long long)__double_as_longlong(val) != sent) { own[s] = val; need[s] = false; }
+                }
+                if (need[s]) have = false;
             }
             const unsigned long long ready = __ballot(have);
             const bool gready = ((ready >> (grp * N)) & gmask) == gmask;
@@ -650,6 +677,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_dpp(PersistArgs 
             }
             __builtin_amdgcn_s_sleep(1);
         }
+        t_next = __shfl(t_pre, 0);
     }
 }
 
