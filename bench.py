@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--schedule", default="persistent", choices=["persistent", "levels"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "persistent", "levels"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     args = ap.parse_args()
@@ -105,7 +105,9 @@ def main():
     prec = 0 if args.precision == "fp64" else 1
     ctx = Context(device=0)
     t0 = time.perf_counter()
-    sched = 0 if args.schedule == "persistent" else 1
+    sched = {"auto": 0, "persistent": 1, "levels": 2}[args.schedule]
+    if sched == 0:
+        sched = 1 if (wp.dim == 2 and wp.p != 2) else 2
     P = Problem.from_workload(ctx, wp, precision=prec, schedule=sched)
     setup_s = time.perf_counter() - t0
     info = P.info()
@@ -147,7 +149,8 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5),
                 "traffic": None,
-                "kernel": f"sweep_{'persistent' if sched == 0 else 'level'}_fp64<{wp.dim},{wp.p}>",
+                "kernel": (f"sweep_persistent_{'dpp' if wp.dim == 2 and wp.p != 2 else 'fp64'}<{wp.dim},{wp.p}>"
+                           if sched == 1 else f"sweep_level_fp64<{wp.dim},{wp.p}>"),
                 "avg_launch_us": round(avg_launch_ms * 1e3, 3),
                 "launches_per_sweep": launches_per_sweep,
                 "kernel_share_of_step": round(kernel_ms / args.steps / ms_per_step, 4)}
@@ -181,7 +184,7 @@ def main():
                    "directions": D, "levels": info["n_levels_total"],
                    "lagged_edges": info["n_removed_total"], "kink_face_dirs": info["n_kink_faces_total"],
                    "setup_s": round(setup_s, 2), "precision": args.precision,
-                   "schedule": args.schedule},
+                   "schedule": "persistent" if sched == 1 else "levels"},
         "roofline": roofline,
         "solve_to_1e-8": solve,
         "cpu_baseline": cpu,

@@ -69,10 +69,13 @@ extern "C" {
 #define SNSW_PREC_MIXED  1        /* FP32 LU + one FP64 residual correction  */
 
 /* Device schedule of one sweep.  PERSISTENT: one launch; wavefronts claim
- * (element, direction) pairs in level order and wait only for the completion
- * flags of their kept upwind neighbours.  LEVELS: one launch per level.     */
-#define SNSW_SCHED_PERSISTENT  0
-#define SNSW_SCHED_LEVELS      1
+ * (element, direction) pairs in level order and wait only for the upwind
+ * values they read (latency-bound sweeps: 2D).  LEVELS: one launch per level
+ * (throughput-bound sweeps: 3D).  AUTO picks PERSISTENT for 2D p = 1 or 3
+ * and LEVELS otherwise.                                                      */
+#define SNSW_SCHED_AUTO        0
+#define SNSW_SCHED_PERSISTENT  1
+#define SNSW_SCHED_LEVELS      2
 
 typedef struct snsw_ctx snsw_ctx;
 typedef struct snsw_problem snsw_problem;

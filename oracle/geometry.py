@@ -91,15 +91,15 @@ class ElementGeometry:
 
     def mass(self) -> np.ndarray:
         wdet = self.wq[None, :] * self.detJ                              # (E, Q)
-        return np.einsum("eq,qm,qn->emn", wdet, self.U, self.U)
+        return np.einsum("eq,qm,qn->emn", wdet, self.U, self.U, optimize=True)
 
     def grad_moments(self) -> np.ndarray:
         """K[e, i, m, n] = int (d u_m / d x_i) u_n dx."""
         Jinv = np.linalg.inv(self.J)                                      # (E,Q,b,a)
         # physical gradient of u_m: (grad_x u_m)_i = sum_b Jinv[b, i] d_b u_m
-        gx = np.einsum("eqbi,qmb->eqmi", Jinv, self.GU)
+        gx = np.einsum("eqbi,qmb->eqmi", Jinv, self.GU, optimize=True)
         wdet = self.wq[None, :] * self.detJ
-        return np.einsum("eq,eqmi,qn->eimn", wdet, gx, self.U)
+        return np.einsum("eq,eqmi,qn->eimn", wdet, gx, self.U, optimize=True)
 
     def load(self, f_values: np.ndarray) -> np.ndarray:
         """int f u_m dx for f given at the physical quadrature points (E, Q)."""

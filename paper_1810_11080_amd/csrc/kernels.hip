@@ -80,13 +80,20 @@ __device__ __forceinline__ void assemble_row(const SweepArgs& args, int4 pr, int
     const double* Ge = args.geo + (size_t)e * (DIM + 1) * N * N;
     const double st = args.sigma_t[e];
     const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1], o2 = args.omega[3 * d + 2];
+    // large rows are assembled in chunks of 9 columns so that the loads in
+    // flight do not dictate the register budget
+    constexpr int CH = N > 16 ? 9 : N;
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-        double v = st * Ge[j * N + row];
-        v -= o0 * Ge[1 * N * N + j * N + row];
-        v -= o1 * Ge[2 * N * N + j * N + row];
-        if (DIM == 3) v -= o2 * Ge[3 * N * N + j * N + row];
-        a[j] = v;
+    for (int j0 = 0; j0 < N; j0 += CH) {
+#pragma unroll
+        for (int j = j0; j < j0 + CH && j < N; ++j) {
+            double v = st * Ge[j * N + row];
+            v -= o0 * Ge[1 * N * N + j * N + row];
+            v -= o1 * Ge[2 * N * N + j * N + row];
+            if (DIM == 3) v -= o2 * Ge[3 * N * N + j * N + row];
+            a[j] = v;
+        }
+        if (N > 16) __builtin_amdgcn_sched_barrier(0);
     }
     rhs = args.src[(size_t)e * N + row];
     kept = 0;
@@ -223,26 +230,26 @@ __device__ __forceinline__ unsigned long long sentinel_bits(int epoch) {
     return 0x7FF8000000000000ull | (unsigned long long)(unsigned)epoch;
 }
 
-// Persistent sweep: each wavefront repeatedly claims G consecutive pairs of
-// the level-ordered schedule.  Everything that does not depend on this
-// sweep's upwind fluxes is done first -- assembly, Gauss-Jordan inversion of
-// A, x0 = A^{-1} b0 with the lagged and boundary inflow in b0, and (2D) the
-// folded inflow operators W_s = A^{-1} P_in,s.  Then the wavefront polls the
-// upwind face values it needs until none holds this sweep's sentinel, and
-// finishes with x += sum_s A^{-1} P_in,s psi_up,s.  Fluxes are stored and
-// polled with device-scope accesses (coherent across the XCD L2 caches).
-// Pairs are claimed in increasing schedule order, levels are padded to whole
-// batches and every kept upwind pair sits on an earlier level, so each
-// awaited pair belongs to another running wavefront: the waits end.  A wait
-// that exceeds spin_limit polls sets *error and gives up (the result is then
-// wrong but the kernel still terminates).
+// Persistent sweep with LDS broadcasts (groups of 8, 9, 27 or 64 lanes):
+// each wavefront repeatedly claims G consecutive pairs of the level-ordered
+// schedule, assembles A and b0 (lagged and boundary inflow included) and
+// factors A = LU (no pivoting; multipliers kept below the diagonal) before
+// it waits.  Then the lane on the first node of each kept face polls the
+// upwind flux until it no longer holds this sweep's sentinel, the face lanes
+// add their inflow rows P_in psi_up straight into b, and the two triangular
+// solves finish the pair.  Fluxes are stored and polled with device-scope
+// accesses (coherent across the XCD L2 caches).  Pairs are claimed in
+// increasing schedule order, levels are padded to whole batches and every
+// kept upwind pair sits on an earlier level, so each awaited pair belongs to
+// another running wavefront (or to a ticket held by a wavefront that is
+// finishing a smaller one): the waits end.  A wait that exceeds spin_limit
+// polls sets *error and gives up (the result is then wrong but the kernel
+// still terminates).
 template <int DIM, int P>
 __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs pa) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
-    constexpr bool FOLD = DIM == 2;   // 3D keeps the register budget for A and A^{-1}
     __shared__ double lds[kWaves][G][N + 1];   // odd stride: groups hit different banks
-    __shared__ double ups[kWaves][G][NS][NF];
     const SweepArgs& args = pa.s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / N, row = lane - grp * N;
@@ -252,10 +259,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
     const unsigned long long sent = sentinel_bits(pa.epoch);
 
     // The next batch is claimed while the current one is processed, which
-    // hides the atomic's latency.  Deadlock-free: the smallest unfinished
-    // ticket is always being processed (a held-but-unstarted ticket implies
-    // a smaller unfinished one in progress), and its upwind pairs are in
-    // smaller, finished tickets.
+    // hides the atomic's latency.
     unsigned t_next = 0;
     if (lane == 0) t_next = atomicAdd(pa.ticket, (unsigned)G);
     t_next = __shfl(t_next, 0);
@@ -269,100 +273,44 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
         if (in_group && pidx < pa.total) pr = args.pairs[pidx];
         const bool active = pr.x >= 0;    // padding entries have e = -1
 
-        double a[N], v[N];
+        // Branch-free: padding lanes assemble element 0 with every face an
+        // outflow face (packed = 0) and never publish (a divergent branch
+        // here would keep two copies of the row alive).
+        double a[N];
         double rhs = 0.0;
         unsigned kept = 0;
         int krow[2 * DIM];
-        if (active) {
-            assemble_row<DIM, P, true>(args, pr, row, a, rhs, kept, krow);
-        } else {
-#pragma unroll
-            for (int j = 0; j < N; ++j) a[j] = (j == row) ? 1.0 : 0.0;
-        }
-        const int e = active ? pr.x : 0;
+        const int4 prs = active ? pr : make_int4(0, 0, 0, 0);
+        assemble_row<DIM, P, true>(args, prs, row, a, rhs, kept, krow);
+        const int e = prs.x;
         const unsigned packed = (unsigned)pr.y;
         const int d = (int)(packed & kDirMask);
-        const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1], o2 = args.omega[3 * d + 2];
-#pragma unroll
-        for (int j = 0; j < N; ++j) v[j] = (j == row) ? 1.0 : 0.0;
 
-        // Gauss-Jordan: row `row` of A^{-1} into v.  At step k the pivot row
-        // holds v (support 0..k) in slots <= k and a in slots > k.
+        // LU factorisation; row `row` keeps its multipliers in a[0..row-1]
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
+        for (int k = 0; k < N - 1; ++k) {
             if (in_group && row == k) {
-                const double r = 1.0 / a[k];
 #pragma unroll
-                for (int j = 0; j < N; ++j) {
-                    if (j > k) { a[j] *= r; L[j] = a[j]; }
-                    else { v[j] *= r; L[j] = v[j]; }
-                }
+                for (int j = k; j < N; ++j) L[j] = a[j];
             }
             wave_sync();
-            if (in_group && row != k) {
-                const double f = a[k];
+            if (in_group && row > k) {
+                const double l = a[k] / L[k];
+                a[k] = l;
 #pragma unroll
-                for (int j = 0; j < N; ++j) {
-                    if (j > k) a[j] -= f * L[j];
-                    else v[j] -= f * L[j];
-                }
+                for (int j = k + 1; j < N; ++j) a[j] -= l * L[j];
             }
             wave_sync();
         }
-        // x0 = A^{-1} b0
-        if (in_group) L[row] = rhs;
-        wave_sync();
-        double x = 0.0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) x += v[j] * L[j];
-        wave_sync();
 
-        // inflow matrix entry P_in,s[a][b] of a kept slot
-        auto pin_entry = [&](int s, int aa, int b) -> double {
-            const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
-            if (cls == kKink)
-                return args.kink_tab[(size_t)krow[s] * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + aa * NF + b];
-            const int f = args.slot_face[(size_t)e * NS + s];
-            const double* Bf = args.B + (size_t)f * DIM * NF * NF + aa * NF + b;
-            double pv = o0 * Bf[0] + o1 * Bf[NF * NF];
-            if (DIM == 3) pv += o2 * Bf[2 * NF * NF];
-            return (s & 1) ? -pv : pv;    // P_in = -(outward) normal moments
-        };
-        double W[FOLD ? NS : 1][FOLD ? NF : 1];
-        if constexpr (FOLD) {
-            // W_s[b] = sum_a A^{-1}[row][tn_s(a)] P_in,s[a][b]
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-#pragma unroll
-                for (int b = 0; b < NF; ++b) W[s][b] = 0.0;
-                if (!(active && ((kept >> s) & 1u))) continue;
-#pragma unroll
-                for (int aa = 0; aa < NF; ++aa) {
-                    const double va = v[S::tn(s, aa)];
-#pragma unroll
-                    for (int b = 0; b < NF; ++b) W[s][b] += va * pin_entry(s, aa, b);
-                }
-            }
-        }
-
-        // Wait: the lane on face-local node la of a kept slot polls the
-        // upwind element's value at the matching node.
-        const double* addr[NS];
+        // wait: the lane on the first node of each kept face polls the
+        // upwind value there; then every face lane reads its face's values
         bool need[NS];
-        double own[NS];
         bool ok = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
-            need[s] = active && on && ((kept >> s) & 1u);
-            addr[s] = args.psi_cur;
-            own[s] = 0.0;
-            if (need[s]) {
-                const int nb = args.slot_nbr[(size_t)e * NS + s];
-                // the neighbour's node facing this lane's node
-                addr[s] = args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, S::local(row, s));
-                ok = false;
-            }
+            need[s] = active && row == S::tn(s, 0) && ((kept >> s) & 1u);
+            if (need[s]) ok = false;
         }
         int polls = 0;
         while (true) {
@@ -371,10 +319,11 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (!need[s]) continue;
-                    const double val =
-                        __hip_atomic_load(const_cast<double*>(addr[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int nb = args.slot_nbr[(size_t)e * NS + s];
+                    double* ad = args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, 0);
+                    const double val = __hip_atomic_load(ad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if ((unsigned long long)__double_as_longlong(val) == sent) all = false;
-                    else { own[s] = val; need[s] = false; }
+                    else need[s] = false;
                 }
                 ok = all;
             }
@@ -392,46 +341,61 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
             __builtin_amdgcn_s_sleep(1);
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        // share the upwind values inside the group
+        // kept inflow straight into this lane's entry of b; values written
+        // by other lanes of the upwind wavefront may lag the first node, so
+        // each is re-read until it is not the sentinel (bounded likewise)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
-            if (in_group && on && ((kept >> s) & 1u)) ups[wave][g0][s][S::local(row, s)] = own[s];
+            if (!(active && on && ((kept >> s) & 1u))) continue;
+            const int la = S::local(row, s);
+            const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+            const int nb = args.slot_nbr[(size_t)e * NS + s];
+            double* up = args.psi_cur + ((size_t)d * args.E + nb) * N;
+            const double* prow;
+            double scale = 1.0;
+            double o[3] = {args.omega[3 * d + 0], args.omega[3 * d + 1], args.omega[3 * d + 2]};
+            if (cls == kKink) {
+                prow = args.kink_tab + (size_t)krow[s] * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + la * NF;
+            } else {
+                prow = args.B + (size_t)args.slot_face[(size_t)e * NS + s] * DIM * NF * NF + la * NF;
+                scale = (s & 1) ? -1.0 : 1.0;   // P_in = -(outward) normal moments
+            }
+#pragma unroll
+            for (int b = 0; b < NF; ++b) {
+                double val = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int spin = 0; (unsigned long long)__double_as_longlong(val) == sent && spin < pa.spin_limit; ++spin) {
+                    __builtin_amdgcn_s_sleep(1);
+                    val = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                double pv;
+                if (cls == kKink) {
+                    pv = prow[b];
+                } else {
+                    pv = o[0] * prow[b] + o[1] * prow[NF * NF + b];
+                    if (DIM == 3) pv += o[2] * prow[2 * NF * NF + b];
+                    pv *= scale;
+                }
+                rhs += pv * val;
+            }
         }
-        wave_sync();
-        if constexpr (FOLD) {
+        // forward substitution (unit lower), then back substitution
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                if (!((kept >> s) & 1u)) continue;
+        for (int k = 0; k < N - 1; ++k) {
+            if (in_group && row == k) L[0] = rhs;
+            wave_sync();
+            if (in_group && row > k) rhs -= a[k] * L[0];
+            wave_sync();
+        }
+        double x = 0.0;
 #pragma unroll
-                for (int b = 0; b < NF; ++b) x += W[s][b] * ups[wave][g0][s][b];
+        for (int k = N - 1; k >= 0; --k) {
+            if (in_group && row == k) {
+                x = rhs / a[k];
+                L[0] = x;
             }
             wave_sync();
-        } else {
-            // c_s = P_in psi_up on the slot's lanes, then x += A^{-1}[:, tn_s] c_s
-            double c[NS];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                c[s] = 0.0;
-                const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
-                if (!(active && on && ((kept >> s) & 1u))) continue;
-                const int la = S::local(row, s);
-#pragma unroll
-                for (int b = 0; b < NF; ++b) c[s] += pin_entry(s, la, b) * ups[wave][g0][s][b];
-            }
-            wave_sync();
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
-                if (in_group && on && ((kept >> s) & 1u)) ups[wave][g0][s][S::local(row, s)] = c[s];
-            }
-            wave_sync();
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                if (!((kept >> s) & 1u)) continue;
-#pragma unroll
-                for (int b = 0; b < NF; ++b) x += v[S::tn(s, b)] * ups[wave][g0][s][b];
-            }
+            if (in_group && row < k) rhs -= a[k] * L[0];
             wave_sync();
         }
         // publish with device-scope (write-through) stores
