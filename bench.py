@@ -106,8 +106,8 @@ def main():
     ctx = Context(device=0)
     t0 = time.perf_counter()
     sched = {"auto": 0, "persistent": 1, "levels": 2}[args.schedule]
-    if sched == 0:
-        sched = 1 if (wp.dim == 2 and wp.p != 2) else 2
+    if sched == 0:   # same rule as the library's automatic choice
+        sched = 1 if (wp.dim == 2 and wp.p != 2 and prec == 0) else 2
     P = Problem.from_workload(ctx, wp, precision=prec, schedule=sched)
     setup_s = time.perf_counter() - t0
     info = P.info()

@@ -156,7 +156,12 @@ __device__ __forceinline__ void assemble_row(const SweepArgs& args, int4 pr, int
     }
 }
 
-template <int DIM, int P>
+// One launch per level.  FP64: Gaussian elimination of [A | b] and back
+// substitution, pivot rows broadcast through LDS.  MIXED: the assembled FP64
+// row is rounded to FP32, factored A32 = L U in FP32, x0 = (LU)^{-1} b in
+// FP32; then one correction with the FP64 operator, r = b - A x0 (FP64),
+// x = x0 + (LU)^{-1} r.
+template <int DIM, int P, bool MIXED>
 __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(SweepArgs args, int64_t begin, int64_t count) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, G = S::G;
@@ -183,34 +188,88 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(SweepArgs args, 
         for (int j = 0; j < N; ++j) a[j] = (j == row) ? 1.0 : 0.0;
     }
 
-    // Gaussian elimination, pivot row broadcast through LDS
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        if (in_group && row == k) {
-#pragma unroll
-            for (int j = k; j < N; ++j) lds[wave][grp][j] = a[j];
-            lds[wave][grp][N] = rhs;
-        }
-        __syncthreads();
-        if (in_group && row > k) {
-            const double l = a[k] / lds[wave][grp][k];
-#pragma unroll
-            for (int j = k + 1; j < N; ++j) a[j] -= l * lds[wave][grp][j];
-            rhs -= l * lds[wave][grp][N];
-        }
-        __syncthreads();
-    }
-    // back substitution
     double x = 0.0;
+    if constexpr (!MIXED) {
+        // Gaussian elimination, pivot row broadcast through LDS
 #pragma unroll
-    for (int k = N - 1; k >= 0; --k) {
-        if (in_group && row == k) {
-            x = rhs / a[k];
-            lds[wave][grp][0] = x;
+        for (int k = 0; k < N; ++k) {
+            if (in_group && row == k) {
+#pragma unroll
+                for (int j = k; j < N; ++j) lds[wave][grp][j] = a[j];
+                lds[wave][grp][N] = rhs;
+            }
+            __syncthreads();
+            if (in_group && row > k) {
+                const double l = a[k] / lds[wave][grp][k];
+#pragma unroll
+                for (int j = k + 1; j < N; ++j) a[j] -= l * lds[wave][grp][j];
+                rhs -= l * lds[wave][grp][N];
+            }
+            __syncthreads();
         }
+        // back substitution
+#pragma unroll
+        for (int k = N - 1; k >= 0; --k) {
+            if (in_group && row == k) {
+                x = rhs / a[k];
+                lds[wave][grp][0] = x;
+            }
+            __syncthreads();
+            if (in_group && row < k) rhs -= a[k] * lds[wave][grp][0];
+            __syncthreads();
+        }
+    } else {
+        float* F = reinterpret_cast<float*>(&lds[wave][grp][0]);
+        float f[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) f[j] = (float)a[j];
+        // LU in FP32, multipliers below the diagonal
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) {
+            if (in_group && row == k) {
+#pragma unroll
+                for (int j = k; j < N; ++j) F[j] = f[j];
+            }
+            __syncthreads();
+            if (in_group && row > k) {
+                const float l = f[k] / F[k];
+                f[k] = l;
+#pragma unroll
+                for (int j = k + 1; j < N; ++j) f[j] -= l * F[j];
+            }
+            __syncthreads();
+        }
+        // solves (LU) y = c in FP32 for this lane's entry c of the column
+        auto lu_solve = [&](float c) -> float {
+#pragma unroll
+            for (int k = 0; k < N - 1; ++k) {
+                if (in_group && row == k) F[0] = c;
+                __syncthreads();
+                if (in_group && row > k) c -= f[k] * F[0];
+                __syncthreads();
+            }
+            float y = 0.0f;
+#pragma unroll
+            for (int k = N - 1; k >= 0; --k) {
+                if (in_group && row == k) {
+                    y = c / f[k];
+                    F[0] = y;
+                }
+                __syncthreads();
+                if (in_group && row < k) c -= f[k] * F[0];
+                __syncthreads();
+            }
+            return y;
+        };
+        const double x0 = (double)lu_solve((float)rhs);
+        // r = b - A x0 with the FP64 row and x0 shared through LDS
+        if (in_group) lds[wave][grp][row] = x0;
         __syncthreads();
-        if (in_group && row < k) rhs -= a[k] * lds[wave][grp][0];
+        double r = rhs;
+#pragma unroll
+        for (int j = 0; j < N; ++j) r -= a[j] * lds[wave][grp][j];
         __syncthreads();
+        x = x0 + (double)lu_solve((float)r);
     }
     if (active) args.psi_cur[((size_t)d * args.E + e) * N + row] = x;
 }
@@ -651,12 +710,16 @@ __global__ void fill_sentinel_kernel(unsigned long long* p, int64_t count, unsig
 }
 
 template <int DIM, int P>
-void launch_tpl(const SweepArgs& a, int64_t begin, int64_t count, hipStream_t stream) {
+void launch_tpl(const SweepArgs& a, int64_t begin, int64_t count, bool mixed, hipStream_t stream) {
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
-    hipLaunchKernelGGL((sweep_level_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, a,
-                       begin, count);
+    if (mixed)
+        hipLaunchKernelGGL((sweep_level_fp64<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
+                           a, begin, count);
+    else
+        hipLaunchKernelGGL((sweep_level_fp64<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
+                           a, begin, count);
 }
 
 // groups of 4 or 16 lanes exchange values by DPP, the others through LDS
@@ -742,15 +805,14 @@ __global__ void residual_kernel(int64_t len, const double* __restrict__ a, const
 
 void launch_sweep_level(int dim, int p, bool mixed, const SweepArgs& a, int64_t begin, int64_t count,
                         hipStream_t stream) {
-    (void)mixed;
     if (dim == 2) {
-        if (p == 1) launch_tpl<2, 1>(a, begin, count, stream);
-        else if (p == 2) launch_tpl<2, 2>(a, begin, count, stream);
-        else launch_tpl<2, 3>(a, begin, count, stream);
+        if (p == 1) launch_tpl<2, 1>(a, begin, count, mixed, stream);
+        else if (p == 2) launch_tpl<2, 2>(a, begin, count, mixed, stream);
+        else launch_tpl<2, 3>(a, begin, count, mixed, stream);
     } else {
-        if (p == 1) launch_tpl<3, 1>(a, begin, count, stream);
-        else if (p == 2) launch_tpl<3, 2>(a, begin, count, stream);
-        else launch_tpl<3, 3>(a, begin, count, stream);
+        if (p == 1) launch_tpl<3, 1>(a, begin, count, mixed, stream);
+        else if (p == 2) launch_tpl<3, 2>(a, begin, count, mixed, stream);
+        else launch_tpl<3, 3>(a, begin, count, mixed, stream);
     }
 }
 

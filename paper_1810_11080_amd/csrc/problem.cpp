@@ -118,7 +118,10 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
             hp.schedule != SNSW_SCHED_LEVELS)
             throw Error(SNSW_E_INVALID_ARG, "schedule must be AUTO, PERSISTENT or LEVELS");
         if (hp.schedule == SNSW_SCHED_AUTO)
-            hp.schedule = (hp.dim == 2 && hp.p != 2) ? SNSW_SCHED_PERSISTENT : SNSW_SCHED_LEVELS;
+            hp.schedule = (hp.dim == 2 && hp.p != 2 && desc->precision == SNSW_PREC_FP64) ? SNSW_SCHED_PERSISTENT
+                                                                                      : SNSW_SCHED_LEVELS;
+        if (desc->precision == SNSW_PREC_MIXED && hp.schedule == SNSW_SCHED_PERSISTENT)
+            throw Error(SNSW_E_UNSUPPORTED, "mixed precision runs on the LEVELS schedule");
         hp.bc = desc->bc_kind;
         if (hp.bc != SNSW_BC_VACUUM && hp.bc != SNSW_BC_ISO_CONST) throw Error(SNSW_E_INVALID_ARG, "bc_kind");
         hp.psi_inc = hp.bc == SNSW_BC_ISO_CONST ? desc->psi_inc : 0.0;

@@ -224,3 +224,30 @@ def test_c3_full_sampled_directions(torch, ctx):
     gs = build_graphs(disc)
     o_psi, _ = oracle_sweep(disc, gs, phi0, psi0[sel])
     assert rel_err(g_psi[0][sel], o_psi) < TOL
+
+
+MIXED_TOL = 1e-5
+
+
+@pytest.mark.parametrize("case", ["c1", "cyclic2d_p3", "warp3d_p2", "strip"])
+def test_mixed_precision_sweeps(torch, ctx, case):
+    """FP32 factorisation + one FP64 correction against the FP64 oracle."""
+    from paper_1810_11080_amd import Problem
+    wp = SMALL[case]()
+    P = Problem.from_workload(ctx, wp, precision=1)
+    g_phi, g_psi = gpu_sweeps(torch, P, 3)
+    o_phi, o_psi, _, _ = oracle_sweeps(wp, 3)
+    for k in range(3):
+        assert rel_err(g_phi[k], o_phi[k]) < MIXED_TOL
+    assert rel_err(g_psi[-1], o_psi[-1]) < MIXED_TOL
+
+
+def test_mixed_precision_c2_full(torch, ctx, c2_oracle):
+    from paper_1810_11080_amd import Problem
+    wp, phi0, psi0, o_phi, o_psi = c2_oracle
+    P = Problem.from_workload(ctx, wp, precision=1)
+    P.state_load(state_bytes(wp, psi0))
+    g_phi, g_psi = gpu_sweeps(torch, P, 1, phi0)
+    P.synchronize()
+    assert rel_err(g_phi[0], o_phi) < MIXED_TOL
+    assert rel_err(g_psi[0], o_psi) < MIXED_TOL
