@@ -239,6 +239,62 @@ int snsw_state_size(const snsw_problem* prob, size_t* bytes);
 int snsw_state_save(const snsw_problem* prob, void* host_buf, size_t cap);
 int snsw_state_load(snsw_problem* prob, const void* host_buf, size_t size);
 
+/* ------------------------------------------------------------------ batch
+ * Many independent problems swept together (same context, device-backed,
+ * each at most once per batch).  Problems with equal (dim, p, precision)
+ * form a class: its schedule concatenates, level by level, the level
+ * segments of its problems, so one persistent launch (or one launch per
+ * level) sweeps all of them.  Each sweep of the batch is one captured
+ * hipGraph replay (one graph per distinct set of flux pointers, at most 4
+ * kept) or, with use_graph = 0, an eager launch sequence.
+ *
+ * opts (nullable: all fields 0):
+ *   schedule   SNSW_SCHED_AUTO: the autotuner times, per FP64 class, the
+ *              level schedule and the persistent one at full and half grid
+ *              (tune_reps sweeps each, default 3) and keeps the fastest;
+ *              SNSW_SCHED_PERSISTENT / SNSW_SCHED_LEVELS force one for every
+ *              FP64 class.  Mixed-precision classes always use LEVELS.
+ *   use_graph  0: eager launches; otherwise hipGraph replay.
+ * Autotuning sweeps the member problems, so create leaves their stored
+ * angular flux zero (as snsw_reset).  A batch refers to its problems'
+ * device data: destroy the batch before any of its problems.  A problem may
+ * also be swept on its own or through other batches between batch sweeps;
+ * its lagged angular flux stays consistent.                                 */
+typedef struct snsw_batch snsw_batch;
+typedef struct {
+    int32_t schedule;
+    int32_t use_graph;
+    int32_t tune_reps;
+} snsw_batch_opts;
+
+int  snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count,
+                       const snsw_batch_opts* opts, snsw_batch** out);
+void snsw_batch_destroy(snsw_batch* batch);
+
+/* One lagged sweep of every problem: d_phi_in[k] / d_phi_out[k] are device
+ * scalar-flux vectors [E_k][n_k] of problem k (host arrays of count device
+ * pointers; in and out must not alias).  Asynchronous on the ctx stream.    */
+int snsw_batch_sweep(snsw_batch* batch, const double* const* d_phi_in,
+                     double* const* d_phi_out);
+
+/* Waits for the ctx stream; SNSW_E_STATE if a persistent dependency wait of
+ * an earlier batch sweep timed out.                                         */
+int snsw_batch_synchronize(snsw_batch* batch);
+
+typedef struct {
+    int32_t dim, dg_order, precision;
+    int32_t persistent;          /* chosen schedule: 1 persistent, 0 levels   */
+    int32_t blocks;              /* persistent grid (0 for levels)            */
+    int32_t n_problems;
+    int64_t n_levels;            /* levels of the merged schedule            */
+    int64_t n_entries;           /* schedule entries incl. padding           */
+    double  tuned_ms[3];         /* autotuner: levels, persistent full grid,
+                                    persistent half grid (ms per sweep; 0 if
+                                    not timed)                               */
+} snsw_batch_class_info;
+int snsw_batch_n_classes(const snsw_batch* batch, int32_t* n);
+int snsw_batch_class_get(const snsw_batch* batch, int32_t c, snsw_batch_class_info* info);
+
 #ifdef __cplusplus
 }
 #endif

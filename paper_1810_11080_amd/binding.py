@@ -54,6 +54,16 @@ class SnswSolveReport(C.Structure):
                 ("history", c_double_p), ("history_cap", C.c_int32)]
 
 
+class SnswBatchOpts(C.Structure):
+    _fields_ = [("schedule", C.c_int32), ("use_graph", C.c_int32), ("tune_reps", C.c_int32)]
+
+
+class SnswBatchClassInfo(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("dg_order", C.c_int32), ("precision", C.c_int32),
+                ("persistent", C.c_int32), ("blocks", C.c_int32), ("n_problems", C.c_int32),
+                ("n_levels", C.c_int64), ("n_entries", C.c_int64), ("tuned_ms", C.c_double * 3)]
+
+
 # name -> (restype, argtypes); mirrors include/snsweep.h
 SIGNATURES = {
     "snsw_last_error": (C.c_char_p, []),
@@ -82,6 +92,13 @@ SIGNATURES = {
     "snsw_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "snsw_state_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "snsw_state_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "snsw_batch_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(SnswBatchOpts),
+                                    C.POINTER(C.c_void_p)]),
+    "snsw_batch_destroy": (None, [C.c_void_p]),
+    "snsw_batch_sweep": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    "snsw_batch_synchronize": (C.c_int, [C.c_void_p]),
+    "snsw_batch_n_classes": (C.c_int, [C.c_void_p, c_int32_p]),
+    "snsw_batch_class_get": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(SnswBatchClassInfo)]),
 }
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "SHAPE", -3: "NONFINITE", -4: "BAD_JACOBIAN",
@@ -349,3 +366,57 @@ class Problem:
     def state_load(self, data: bytes):
         buf = C.create_string_buffer(data, len(data))
         _check(lib().snsw_state_load(self.handle, buf, len(data)))
+
+
+class Batch:
+    """Independent problems swept together (merged per-class schedules,
+    autotuned schedule choice, hipGraph replay).  Keep the problems alive
+    while the batch exists."""
+
+    def __init__(self, ctx: Context, problems, schedule: int = 0, use_graph: bool = True,
+                 tune_reps: int = 0):
+        self.ctx = ctx
+        self.problems = list(problems)
+        handles = (C.c_void_p * len(self.problems))(*[p.handle.value for p in self.problems])
+        opts = SnswBatchOpts(schedule=schedule, use_graph=1 if use_graph else 0, tune_reps=tune_reps)
+        h = C.c_void_p()
+        _check(lib().snsw_batch_create(ctx.handle, handles, len(self.problems), C.byref(opts), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().snsw_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, phi_in, phi_out):
+        """One sweep of every problem: phi_in[k] -> phi_out[k] (device tensors)."""
+        n = len(self.problems)
+        if len(phi_in) != n or len(phi_out) != n:
+            raise ValueError(f"expected {n} input and output tensors")
+        dev = self.ctx.device
+        a = (C.c_void_p * n)(*[_tensor_ptr(t, p.E * p.n, dev, f"phi_in[{k}]").value
+                               for k, (t, p) in enumerate(zip(phi_in, self.problems))])
+        b = (C.c_void_p * n)(*[_tensor_ptr(t, p.E * p.n, dev, f"phi_out[{k}]").value
+                               for k, (t, p) in enumerate(zip(phi_out, self.problems))])
+        _check(lib().snsw_batch_sweep(self.handle, a, b))
+
+    def synchronize(self):
+        _check(lib().snsw_batch_synchronize(self.handle))
+
+    def classes(self):
+        n = C.c_int32()
+        _check(lib().snsw_batch_n_classes(self.handle, C.byref(n)))
+        out = []
+        for c in range(n.value):
+            info = SnswBatchClassInfo()
+            _check(lib().snsw_batch_class_get(self.handle, c, C.byref(info)))
+            d = {k: getattr(info, k) for k, _ in info._fields_ if k != "tuned_ms"}
+            d["tuned_ms"] = list(info.tuned_ms)
+            out.append(d)
+        return out

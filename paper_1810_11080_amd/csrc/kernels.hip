@@ -16,6 +16,7 @@
 // column-major so that the n lanes of a group load consecutive addresses.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -63,6 +64,41 @@ struct Shape {
         return l;
     }
 };
+
+// Table entry and problem index read through the constant address space, so
+// that a wavefront-uniform index gives scalar loads (neither is written while
+// a sweep kernel runs).
+__device__ __forceinline__ int batch_problem(const int4* pairs, int64_t t) {
+    typedef const __attribute__((address_space(4))) int* cint_ptr;
+    return ((cint_ptr)(const int*)(pairs + t))[3];
+}
+
+__device__ __forceinline__ SweepArgs load_args(const SweepArgs* table, int k) {
+    typedef const __attribute__((address_space(4))) SweepArgs* cargs_ptr;
+    const cargs_ptr c = (cargs_ptr)(table + k);
+    SweepArgs a;
+    a.geo = c->geo;
+    a.B = c->B;
+    a.kink_tab = c->kink_tab;
+    a.kink_idx = c->kink_idx;
+    a.slot_face = c->slot_face;
+    a.slot_nbr = c->slot_nbr;
+    a.sigma_t = c->sigma_t;
+    a.sigma_s = c->sigma_s;
+    a.q = c->q;
+    a.omega = c->omega;
+    a.w = c->w;
+    a.src = c->src;
+    a.psi_cur = c->psi_cur;
+    a.psi_prev = c->psi_prev;
+    a.psi_inc = c->psi_inc;
+    a.E = c->E;
+    a.n = c->n;
+    a.D = c->D;
+    a.dim = c->dim;
+    a.persistent = c->persistent;
+    return a;
+}
 
 // Assembles row `row` of A and b for pair (e, d).  With DEFER, inflow through
 // kept couplings (read from this sweep's flux) is left out of b and the slots
@@ -156,22 +192,35 @@ __device__ __forceinline__ void assemble_row(const SweepArgs& args, int4 pr, int
     }
 }
 
+// Orders LDS traffic of one wavefront (no hardware barrier needed: a
+// wavefront's LDS instructions execute in order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One launch per level.  FP64: Gaussian elimination of [A | b] and back
 // substitution, pivot rows broadcast through LDS.  MIXED: the assembled FP64
 // row is rounded to FP32, factored A32 = L U in FP32, x0 = (LU)^{-1} b in
 // FP32; then one correction with the FP64 operator, r = b - A x0 (FP64),
 // x = x0 + (LU)^{-1} r.
 template <int DIM, int P, bool MIXED>
-__global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(SweepArgs args, int64_t begin, int64_t count) {
+__global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(const SweepArgs* table, const int4* pairs,
+                                                                 int64_t begin, int64_t count) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, G = S::G;
     __shared__ double lds[kWaves][G][N + 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = lane / N, row = lane - grp * N;
     const bool in_group = grp < G;
-    const int64_t pidx = begin + ((int64_t)blockIdx.x * kWaves + wave) * G + grp;
+    // this wavefront's batch of G entries (one problem; count is a multiple of G)
+    const int64_t wbase = begin + ((int64_t)blockIdx.x * kWaves + wave) * G;
+    if (wbase >= begin + count) return;   // LDS is per wavefront: no block barrier follows
+    const SweepArgs args = load_args(table, batch_problem(pairs, wbase));
     int4 pr = make_int4(-1, 0, 0, 0);
-    if (in_group && pidx < begin + count) pr = args.pairs[pidx];
+    if (in_group) pr = pairs[wbase + grp];
     const bool active = pr.x >= 0;    // padding entries have e = -1
 
     double a[N];
@@ -198,14 +247,14 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(SweepArgs args, 
                 for (int j = k; j < N; ++j) lds[wave][grp][j] = a[j];
                 lds[wave][grp][N] = rhs;
             }
-            __syncthreads();
+            wave_sync();
             if (in_group && row > k) {
                 const double l = a[k] / lds[wave][grp][k];
 #pragma unroll
                 for (int j = k + 1; j < N; ++j) a[j] -= l * lds[wave][grp][j];
                 rhs -= l * lds[wave][grp][N];
             }
-            __syncthreads();
+            wave_sync();
         }
         // back substitution
 #pragma unroll
@@ -214,9 +263,9 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(SweepArgs args, 
                 x = rhs / a[k];
                 lds[wave][grp][0] = x;
             }
-            __syncthreads();
+            wave_sync();
             if (in_group && row < k) rhs -= a[k] * lds[wave][grp][0];
-            __syncthreads();
+            wave_sync();
         }
     } else {
         float* F = reinterpret_cast<float*>(&lds[wave][grp][0]);
@@ -230,23 +279,23 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(SweepArgs args, 
 #pragma unroll
                 for (int j = k; j < N; ++j) F[j] = f[j];
             }
-            __syncthreads();
+            wave_sync();
             if (in_group && row > k) {
                 const float l = f[k] / F[k];
                 f[k] = l;
 #pragma unroll
                 for (int j = k + 1; j < N; ++j) f[j] -= l * F[j];
             }
-            __syncthreads();
+            wave_sync();
         }
         // solves (LU) y = c in FP32 for this lane's entry c of the column
         auto lu_solve = [&](float c) -> float {
 #pragma unroll
             for (int k = 0; k < N - 1; ++k) {
                 if (in_group && row == k) F[0] = c;
-                __syncthreads();
+                wave_sync();
                 if (in_group && row > k) c -= f[k] * F[0];
-                __syncthreads();
+                wave_sync();
             }
             float y = 0.0f;
 #pragma unroll
@@ -255,39 +304,30 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(SweepArgs args, 
                     y = c / f[k];
                     F[0] = y;
                 }
-                __syncthreads();
+                wave_sync();
                 if (in_group && row < k) c -= f[k] * F[0];
-                __syncthreads();
+                wave_sync();
             }
             return y;
         };
         const double x0 = (double)lu_solve((float)rhs);
         // r = b - A x0 with the FP64 row and x0 shared through LDS
         if (in_group) lds[wave][grp][row] = x0;
-        __syncthreads();
+        wave_sync();
         double r = rhs;
 #pragma unroll
         for (int j = 0; j < N; ++j) r -= a[j] * lds[wave][grp][j];
-        __syncthreads();
+        wave_sync();
         x = x0 + (double)lu_solve((float)r);
     }
     if (active) args.psi_cur[((size_t)d * args.E + e) * N + row] = x;
 }
 
-// Orders LDS traffic of one wavefront (no hardware barrier needed: a
-// wavefront's LDS instructions execute in order).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
-// Bit pattern marking "not yet written in this sweep": a quiet NaN whose
-// payload is the sweep epoch (>= 1), so it never equals a computed flux and
-// needs no reset between sweeps.
-__device__ __forceinline__ unsigned long long sentinel_bits(int epoch) {
-    return 0x7FF8000000000000ull | (unsigned long long)(unsigned)epoch;
-}
+// Bit pattern marking "not yet written in this sweep": a signalling NaN.
+// Arithmetic never produces a signalling NaN (IEEE quiets them), so no
+// computed flux can carry this pattern; only the fill kernel writes it.
+constexpr unsigned long long kSentinel = 0x7FF4000000005EEDull;
 
 // Persistent sweep with LDS broadcasts (groups of 8, 9, 27 or 64 lanes):
 // each wavefront repeatedly claims G consecutive pairs of the level-ordered
@@ -309,13 +349,12 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
     using S = Shape<DIM, P>;
     constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
     __shared__ double lds[kWaves][G][N + 1];   // odd stride: groups hit different banks
-    const SweepArgs& args = pa.s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / N, row = lane - grp * N;
     const bool in_group = grp < G;
     const int g0 = in_group ? grp : 0;
     double* L = &lds[wave][g0][0];
-    const unsigned long long sent = sentinel_bits(pa.epoch);
+    const unsigned long long sent = kSentinel;
 
     // The next batch is claimed while the current one is processed, which
     // hides the atomic's latency.
@@ -323,13 +362,14 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
     if (lane == 0) t_next = atomicAdd(pa.ticket, (unsigned)G);
     t_next = __shfl(t_next, 0);
     while (true) {
-        const unsigned t0 = t_next;
+        const unsigned t0 = __builtin_amdgcn_readfirstlane(t_next);
         if ((int64_t)t0 >= pa.total) break;
         unsigned t_pre = 0;
         if (lane == 0) t_pre = atomicAdd(pa.ticket, (unsigned)G);
+        const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0));
         const int64_t pidx = (int64_t)t0 + grp;
         int4 pr = make_int4(-1, 0, 0, 0);
-        if (in_group && pidx < pa.total) pr = args.pairs[pidx];
+        if (in_group && pidx < pa.total) pr = pa.pairs[pidx];
         const bool active = pr.x >= 0;    // padding entries have e = -1
 
         // Branch-free: padding lanes assemble element 0 with every face an
@@ -498,10 +538,9 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
     constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
     static_assert(G * N == 64, "groups must tile the wavefront");
     __shared__ double pin_lds[kWaves][G][NS][NF][NF + 1];
-    const SweepArgs& args = pa.s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / N, row = lane - grp * N;
-    const unsigned long long sent = sentinel_bits(pa.epoch);
+    const unsigned long long sent = kSentinel;
 
     // The next batch is claimed while the current one is processed, which
     // hides the atomic's latency.  Deadlock-free: the smallest unfinished
@@ -512,13 +551,14 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
     if (lane == 0) t_next = atomicAdd(pa.ticket, (unsigned)G);
     t_next = __shfl(t_next, 0);
     while (true) {
-        const unsigned t0 = t_next;
+        const unsigned t0 = __builtin_amdgcn_readfirstlane(t_next);
         if ((int64_t)t0 >= pa.total) break;
         unsigned t_pre = 0;
         if (lane == 0) t_pre = atomicAdd(pa.ticket, (unsigned)G);
+        const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0));
         const int64_t pidx = (int64_t)t0 + grp;
         int4 pr = make_int4(-1, 0, 0, 0);
-        if (pidx < pa.total) pr = args.pairs[pidx];
+        if (pidx < pa.total) pr = pa.pairs[pidx];
         const bool active = pr.x >= 0;    // padding entries have e = -1
         const int e = active ? pr.x : 0;
         const unsigned packed = (unsigned)pr.y;
@@ -704,22 +744,27 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
     }
 }
 
-__global__ void fill_sentinel_kernel(unsigned long long* p, int64_t count, unsigned long long bits) {
+__global__ void fill_sentinel_kernel(const SweepArgs* table) {
+    const SweepArgs& a = table[blockIdx.y];
+    if (!a.persistent) return;
+    const int64_t count = (int64_t)a.D * a.E * a.n;
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(a.psi_cur);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
-        p[t] = bits;
+        p[t] = kSentinel;
 }
 
 template <int DIM, int P>
-void launch_tpl(const SweepArgs& a, int64_t begin, int64_t count, bool mixed, hipStream_t stream) {
+void launch_tpl(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, bool mixed,
+                hipStream_t stream) {
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
     if (mixed)
         hipLaunchKernelGGL((sweep_level_fp64<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
-                           a, begin, count);
+                           table, pairs, begin, count);
     else
         hipLaunchKernelGGL((sweep_level_fp64<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
-                           a, begin, count);
+                           table, pairs, begin, count);
 }
 
 // groups of 4 or 16 lanes exchange values by DPP, the others through LDS
@@ -748,28 +793,44 @@ int occupancy_tpl() {
     return nb > 0 ? nb : 1;
 }
 
-__global__ void source_kernel(int dim, int n, int64_t E, const double* __restrict__ geo,
-                              const double* __restrict__ q, const double* __restrict__ sigma_s,
-                              const double* __restrict__ phi, double* __restrict__ src,
-                              unsigned int* ticket) {
+// blockIdx.y = problem.  Block (0, k) starts problem k's sweep: it swaps the
+// two angular-flux buffers; block (0, 0) also zeroes the tickets.  No other
+// block reads the buffer pointers.
+__global__ void source_kernel(SweepArgs* table, const double* const* phi_list, const double* phi_one,
+                              unsigned int* tickets, int n_tickets) {
+    SweepArgs& a = table[blockIdx.y];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double* t = a.psi_cur;
+        a.psi_cur = a.psi_prev;
+        a.psi_prev = t;
+        if (blockIdx.y == 0)
+            for (int k = 0; k < n_tickets; ++k) tickets[k] = 0u;
+    }
+    const int n = a.n;
+    const int64_t E = a.E;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0 && ticket) *ticket = 0u;
     if (t >= E * n) return;
+    const double* __restrict__ phi = phi_list ? phi_list[blockIdx.y] : phi_one;
     const int64_t e = t / n;
     const int i = (int)(t - e * n);
-    const double c = sigma_s[e] * (0.25 / M_PI);
-    const double* M = geo + (size_t)e * (dim + 1) * n * n;
+    const double c = a.sigma_s[e] * (0.25 / M_PI);
+    const double* M = a.geo + (size_t)e * (a.dim + 1) * n * n;
+    const double* qe = a.q + e * n;
+    const double* pe = phi + e * n;
     double s = 0.0;
-    for (int j = 0; j < n; ++j) s += M[(size_t)j * n + i] * (q[e * n + j] + c * phi[e * n + j]);
-    src[t] = s;
+    for (int j = 0; j < n; ++j) s += M[(size_t)j * n + i] * (qe[j] + c * pe[j]);
+    a.src[t] = s;
 }
 
-__global__ void scalar_flux_kernel(int D, int64_t En, const double* __restrict__ w,
-                                   const double* __restrict__ psi, double* __restrict__ phi) {
+__global__ void scalar_flux_kernel(const SweepArgs* table, double* const* phi_list, double* phi_one) {
+    const SweepArgs& a = table[blockIdx.y];
+    const int64_t En = a.E * a.n;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= En) return;
+    double* __restrict__ phi = phi_list ? phi_list[blockIdx.y] : phi_one;
+    const double* __restrict__ psi = a.psi_cur;
     double s = 0.0;
-    for (int d = 0; d < D; ++d) s += w[d] * psi[(size_t)d * En + t];
+    for (int d = 0; d < a.D; ++d) s += a.w[d] * psi[(size_t)d * En + t];
     phi[t] = s;
 }
 
@@ -803,37 +864,33 @@ __global__ void residual_kernel(int64_t len, const double* __restrict__ a, const
 
 }  // namespace
 
-void launch_sweep_level(int dim, int p, bool mixed, const SweepArgs& a, int64_t begin, int64_t count,
-                        hipStream_t stream) {
+void launch_sweep_level(int dim, int p, bool mixed, const SweepArgs* table, const int4* pairs, int64_t begin,
+                        int64_t count, hipStream_t stream) {
     if (dim == 2) {
-        if (p == 1) launch_tpl<2, 1>(a, begin, count, mixed, stream);
-        else if (p == 2) launch_tpl<2, 2>(a, begin, count, mixed, stream);
-        else launch_tpl<2, 3>(a, begin, count, mixed, stream);
+        if (p == 1) launch_tpl<2, 1>(table, pairs, begin, count, mixed, stream);
+        else if (p == 2) launch_tpl<2, 2>(table, pairs, begin, count, mixed, stream);
+        else launch_tpl<2, 3>(table, pairs, begin, count, mixed, stream);
     } else {
-        if (p == 1) launch_tpl<3, 1>(a, begin, count, mixed, stream);
-        else if (p == 2) launch_tpl<3, 2>(a, begin, count, mixed, stream);
-        else launch_tpl<3, 3>(a, begin, count, mixed, stream);
+        if (p == 1) launch_tpl<3, 1>(table, pairs, begin, count, mixed, stream);
+        else if (p == 2) launch_tpl<3, 2>(table, pairs, begin, count, mixed, stream);
+        else launch_tpl<3, 3>(table, pairs, begin, count, mixed, stream);
     }
 }
 
-void launch_source(int dim, int n, int64_t E, const double* geo, const double* q, const double* sigma_s,
-                   const double* phi, double* src, unsigned int* ticket, hipStream_t stream) {
-    const int64_t tot = E * n;
-    const int64_t blocks = (tot + 255) / 256;
-    hipLaunchKernelGGL(source_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, dim, n, E, geo, q, sigma_s,
-                       phi, src, ticket);
+void launch_source(SweepArgs* table, int count, int64_t max_En, const double* const* phi_list,
+                   const double* phi_one, unsigned int* tickets, int n_tickets, hipStream_t stream) {
+    const int64_t blocks = std::max<int64_t>(1, (max_En + 255) / 256);
+    hipLaunchKernelGGL(source_kernel, dim3((unsigned)blocks, (unsigned)count), dim3(256), 0, stream, table,
+                       phi_list, phi_one, tickets, n_tickets);
 }
 
-void launch_fill_sentinel(double* psi, int64_t count, int epoch, hipStream_t stream) {
-    int64_t blocks = (count + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    const unsigned long long bits = 0x7FF8000000000000ull | (unsigned long long)(unsigned)epoch;
-    hipLaunchKernelGGL(fill_sentinel_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
-                       reinterpret_cast<unsigned long long*>(psi), count, bits);
+void launch_fill_sentinel(const SweepArgs* table, int count, int64_t max_DEn, hipStream_t stream) {
+    int64_t blocks = (max_DEn + 255) / 256;
+    blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, std::max<int64_t>(1, 8192 / count)));
+    hipLaunchKernelGGL(fill_sentinel_kernel, dim3((unsigned)blocks, (unsigned)count), dim3(256), 0, stream, table);
 }
 
-void launch_sweep_persistent(int dim, int p, bool mixed, const PersistArgs& a, int blocks, hipStream_t stream) {
-    (void)mixed;
+void launch_sweep_persistent(int dim, int p, const PersistArgs& a, int blocks, hipStream_t stream) {
     if (dim == 2) {
         if (p == 1) launch_persist_tpl<2, 1>(a, blocks, stream);
         else if (p == 2) launch_persist_tpl<2, 2>(a, blocks, stream);
@@ -845,15 +902,16 @@ void launch_sweep_persistent(int dim, int p, bool mixed, const PersistArgs& a, i
     }
 }
 
-int persistent_blocks_per_cu(int dim, int p, bool mixed) {
-    (void)mixed;
+int persistent_blocks_per_cu(int dim, int p) {
     if (dim == 2) return p == 1 ? occupancy_tpl<2, 1>() : p == 2 ? occupancy_tpl<2, 2>() : occupancy_tpl<2, 3>();
     return p == 1 ? occupancy_tpl<3, 1>() : p == 2 ? occupancy_tpl<3, 2>() : occupancy_tpl<3, 3>();
 }
 
-void launch_scalar_flux(int D, int64_t En, const double* w, const double* psi, double* phi, hipStream_t stream) {
-    const int64_t blocks = (En + 255) / 256;
-    hipLaunchKernelGGL(scalar_flux_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, D, En, w, psi, phi);
+void launch_scalar_flux(const SweepArgs* table, int count, int64_t max_En, double* const* phi_list,
+                        double* phi_one, hipStream_t stream) {
+    const int64_t blocks = std::max<int64_t>(1, (max_En + 255) / 256);
+    hipLaunchKernelGGL(scalar_flux_kernel, dim3((unsigned)blocks, (unsigned)count), dim3(256), 0, stream, table,
+                       phi_list, phi_one);
 }
 
 void launch_residual(int64_t len, const double* a, const double* b, unsigned long long* out, hipStream_t stream) {

@@ -9,50 +9,9 @@
 #include <cstring>
 #include <string>
 
-#include "internal.hpp"
-#include "kernels.hpp"
+#include "device.hpp"
 
 namespace snsw {
-
-#define HIP_OK(expr)                                                                          \
-    do {                                                                                      \
-        hipError_t _e = (expr);                                                               \
-        if (_e != hipSuccess)                                                                 \
-            throw Error(_e == hipErrorOutOfMemory ? SNSW_E_OOM : SNSW_E_HIP,                  \
-                        std::string(#expr) + ": " + hipGetErrorString(_e));                  \
-    } while (0)
-
-struct DeviceProblem {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    double* geo = nullptr;        // [E][dim+1][n][n] column-major matrices
-    double* B = nullptr;          // [F][dim][nf][nf]
-    double* kink_tab = nullptr;   // [K][2][nf][nf]
-    int32_t* kink_idx = nullptr;
-    int4* pairs = nullptr;
-    int32_t* slot_face = nullptr;
-    int32_t* slot_nbr = nullptr;
-    double* sigma_t = nullptr;
-    double* sigma_s = nullptr;
-    double* q = nullptr;
-    double* omega = nullptr;
-    double* w = nullptr;
-    double* src = nullptr;        // [E][n]
-    double* psi[2] = {nullptr, nullptr};
-    double* phi_tmp = nullptr;    // [E][n]
-    unsigned long long* red = nullptr;   // residual scratch [2]
-    unsigned int* ticket = nullptr;
-    int32_t* error = nullptr;     // device-side wait failure flag
-    int32_t epoch = 0;
-    int blocks = 0;               // persistent grid size
-    int cur = 0;                  // psi[cur] holds the previous sweep
-    std::vector<int64_t> level_off;
-    size_t bytes = 0;
-    // profiling: event pairs around level launches
-    bool profiling = false;
-    std::vector<hipEvent_t> events;
-    size_t n_events = 0;
-};
 
 namespace {
 
@@ -72,100 +31,33 @@ T* dupload(DeviceProblem* dp, const std::vector<T>& v, hipStream_t s) {
     return p;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (dev >= 0 && dev != prev) HIP_OK(hipSetDevice(dev));
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-DeviceProblem* need_device(snsw_problem* prob) {
-    if (!prob) throw Error(SNSW_E_INVALID_ARG, "NULL problem");
-    if (!prob->dev) throw Error(SNSW_E_UNSUPPORTED, "host-only context: no device work");
-    return prob->dev;
+__global__ void set_entry_kernel(SweepArgs* table, int k, double* cur, double* prev) {
+    table[k].psi_cur = cur;
+    table[k].psi_prev = prev;
 }
 
 void do_sweep(snsw_problem* prob, const double* phi_in, double* phi_out, double* psi_out) {
     DeviceProblem* dp = need_device(prob);
     const HostProblem& hp = prob->hp;
     const hipStream_t s = dp->stream;
-    const bool persistent = hp.schedule == SNSW_SCHED_PERSISTENT;
-    launch_source(hp.dim, hp.n, hp.E, dp->geo, dp->q, dp->sigma_s, phi_in, dp->src,
-                  persistent ? dp->ticket : nullptr, s);
-    HIP_OK(hipGetLastError());
-    SweepArgs a;
-    a.pairs = dp->pairs;
-    a.geo = dp->geo;
-    a.B = dp->B;
-    a.kink_tab = dp->kink_tab;
-    a.kink_idx = dp->kink_idx;
-    a.slot_face = dp->slot_face;
-    a.slot_nbr = dp->slot_nbr;
-    a.sigma_t = dp->sigma_t;
-    a.omega = dp->omega;
-    a.src = dp->src;
-    a.psi_prev = dp->psi[dp->cur];
-    a.psi_cur = dp->psi[1 - dp->cur];
-    a.psi_inc = hp.psi_inc;
-    a.E = hp.E;
-    const bool mixed = hp.precision == SNSW_PREC_MIXED;
-    if (persistent) {
-        if (dp->epoch == INT32_MAX) dp->epoch = 0;   // sentinel payloads only need to differ from 0
-        PersistArgs pa;
-        pa.s = a;
-        pa.ticket = dp->ticket;
-        pa.error = dp->error;
-        pa.total = dp->level_off.back();
-        pa.epoch = ++dp->epoch;
-        pa.spin_limit = 1 << 20;
-        launch_fill_sentinel(a.psi_cur, (int64_t)hp.D * hp.E * hp.n, pa.epoch, s);
-        if (dp->profiling) {
-            while (dp->n_events + 2 > dp->events.size()) {
-                hipEvent_t ev;
-                HIP_OK(hipEventCreate(&ev));
-                dp->events.push_back(ev);
-            }
-            HIP_OK(hipEventRecord(dp->events[dp->n_events++], s));
-        }
-        launch_sweep_persistent(hp.dim, hp.p, mixed, pa, dp->blocks, s);
-        if (dp->profiling) HIP_OK(hipEventRecord(dp->events[dp->n_events++], s));
-    }
-    for (size_t k = 0; !persistent && k + 1 < dp->level_off.size(); ++k) {
-        const int64_t b = dp->level_off[k], c = dp->level_off[k + 1] - b;
-        if (dp->profiling) {
-            while (dp->n_events + 2 > dp->events.size()) {
-                hipEvent_t ev;
-                HIP_OK(hipEventCreate(&ev));
-                dp->events.push_back(ev);
-            }
-            HIP_OK(hipEventRecord(dp->events[dp->n_events++], s));
-            launch_sweep_level(hp.dim, hp.p, mixed, a, b, c, s);
-            HIP_OK(hipEventRecord(dp->events[dp->n_events++], s));
-        } else {
-            launch_sweep_level(hp.dim, hp.p, mixed, a, b, c, s);
-        }
-    }
-    HIP_OK(hipGetLastError());
-    launch_scalar_flux(hp.D, hp.E * hp.n, dp->w, a.psi_cur, phi_out, s);
-    HIP_OK(hipGetLastError());
-    if (psi_out)
-        HIP_OK(hipMemcpyAsync(psi_out, a.psi_cur, sizeof(double) * hp.D * hp.E * hp.n, hipMemcpyDeviceToDevice, s));
+    sync_entry(dp->table, 0, prob, &dp->table_cur, s);
+    SweepLaunch L;
+    L.table = dp->table;
+    L.count = 1;
+    L.max_En = hp.E * hp.n;
+    L.max_DEn = hp.D * hp.E * hp.n;
+    L.any_persistent = dp->cls.persistent;
+    L.tickets = dp->ticket;
+    L.n_tickets = 1;
+    L.error = dp->error;
+    L.phi_in_one = phi_in;
+    L.phi_out_one = phi_out;
+    enqueue_sweep(L, std::vector<SweepClass>{dp->cls}, s, &dp->prof);
     dp->cur = 1 - dp->cur;
-}
-
-void check_device_error(DeviceProblem* dp) {
-    int32_t err = 0;
-    HIP_OK(hipMemcpyAsync(&err, dp->error, sizeof(err), hipMemcpyDeviceToHost, dp->stream));
-    HIP_OK(hipStreamSynchronize(dp->stream));
-    if (err) {
-        HIP_OK(hipMemsetAsync(dp->error, 0, sizeof(int32_t), dp->stream));
-        HIP_OK(hipStreamSynchronize(dp->stream));
-        throw Error(SNSW_E_STATE, "a dependency wait of the persistent sweep timed out; results are invalid");
-    }
+    dp->table_cur = dp->cur;
+    if (psi_out)
+        HIP_OK(hipMemcpyAsync(psi_out, dp->psi[dp->cur], sizeof(double) * hp.D * hp.E * hp.n,
+                              hipMemcpyDeviceToDevice, s));
 }
 
 double do_residual(DeviceProblem* dp, int64_t len, const double* a, const double* b) {
@@ -175,7 +67,7 @@ double do_residual(DeviceProblem* dp, int64_t len, const double* a, const double
     unsigned long long h[2] = {0, 0};
     HIP_OK(hipMemcpyAsync(h, dp->red, sizeof(h), hipMemcpyDeviceToHost, dp->stream));
     HIP_OK(hipStreamSynchronize(dp->stream));
-    check_device_error(dp);
+    check_error_flag(dp->error, dp->stream);
     double num, den;
     std::memcpy(&num, &h[0], 8);
     std::memcpy(&den, &h[1], 8);
@@ -184,6 +76,136 @@ double do_residual(DeviceProblem* dp, int64_t len, const double* a, const double
 }
 
 }  // namespace
+
+DeviceProblem* need_device(snsw_problem* prob) {
+    if (!prob) throw Error(SNSW_E_INVALID_ARG, "NULL problem");
+    if (!prob->dev) throw Error(SNSW_E_UNSUPPORTED, "host-only context: no device work");
+    return prob->dev;
+}
+
+void LaunchProfiler::begin(hipStream_t s) {
+    if (!on) return;
+    while (used + 2 > events.size()) {
+        hipEvent_t ev;
+        HIP_OK(hipEventCreate(&ev));
+        events.push_back(ev);
+    }
+    HIP_OK(hipEventRecord(events[used++], s));
+}
+
+void LaunchProfiler::end(hipStream_t s) {
+    if (!on) return;
+    HIP_OK(hipEventRecord(events[used++], s));
+}
+
+void LaunchProfiler::read(int64_t* launches, double* ms) {
+    double total = 0.0;
+    for (size_t i = 0; i + 1 < used; i += 2) {
+        float t = 0.0f;
+        HIP_OK(hipEventElapsedTime(&t, events[i], events[i + 1]));
+        total += t;
+    }
+    if (launches) *launches = (int64_t)(used / 2);
+    if (ms) *ms = total;
+    used = 0;
+}
+
+void LaunchProfiler::release() noexcept {
+    for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
+    events.clear();
+    used = 0;
+}
+
+SweepArgs make_args(const snsw_problem* prob, int cur) {
+    const DeviceProblem* dp = prob->dev;
+    const HostProblem& hp = prob->hp;
+    SweepArgs a{};
+    a.geo = dp->geo;
+    a.B = dp->B;
+    a.kink_tab = dp->kink_tab;
+    a.kink_idx = dp->kink_idx;
+    a.slot_face = dp->slot_face;
+    a.slot_nbr = dp->slot_nbr;
+    a.sigma_t = dp->sigma_t;
+    a.sigma_s = dp->sigma_s;
+    a.q = dp->q;
+    a.omega = dp->omega;
+    a.w = dp->w;
+    a.src = dp->src;
+    a.psi_cur = dp->psi[cur];
+    a.psi_prev = dp->psi[1 - cur];
+    a.psi_inc = hp.psi_inc;
+    a.E = hp.E;
+    a.n = hp.n;
+    a.D = hp.D;
+    a.dim = hp.dim;
+    a.persistent = 0;
+    return a;
+}
+
+void sync_entry(SweepArgs* table, int k, const snsw_problem* prob, int* entry_cur, hipStream_t s) {
+    const DeviceProblem* dp = prob->dev;
+    if (*entry_cur == dp->cur) return;
+    hipLaunchKernelGGL(set_entry_kernel, dim3(1), dim3(1), 0, s, table, k, dp->psi[dp->cur], dp->psi[1 - dp->cur]);
+    HIP_OK(hipGetLastError());
+    *entry_cur = dp->cur;
+}
+
+void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes, hipStream_t s,
+                   LaunchProfiler* prof) {
+    launch_source(L.table, L.count, L.max_En, L.phi_in_list, L.phi_in_one, L.tickets, L.n_tickets, s);
+    HIP_OK(hipGetLastError());
+    if (L.any_persistent) {
+        launch_fill_sentinel(L.table, L.count, L.max_DEn, s);
+        HIP_OK(hipGetLastError());
+    }
+    for (const SweepClass& c : classes) {
+        if (c.persistent) {
+            PersistArgs pa;
+            pa.table = L.table;
+            pa.pairs = c.pairs;
+            pa.ticket = L.tickets + c.ticket;
+            pa.error = L.error;
+            pa.total = c.level_off.back();
+            pa.spin_limit = 1 << 20;
+            if (prof) prof->begin(s);
+            launch_sweep_persistent(c.dim, c.p, pa, c.blocks, s);
+            if (prof) prof->end(s);
+        } else {
+            for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
+                const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
+                if (prof) prof->begin(s);
+                launch_sweep_level(c.dim, c.p, c.mixed, L.table, c.pairs, b, n, s);
+                if (prof) prof->end(s);
+            }
+        }
+        HIP_OK(hipGetLastError());
+    }
+    launch_scalar_flux(L.table, L.count, L.max_En, L.phi_out_list, L.phi_out_one, s);
+    HIP_OK(hipGetLastError());
+}
+
+void check_error_flag(int32_t* flag, hipStream_t s) {
+    int32_t err = 0;
+    HIP_OK(hipMemcpyAsync(&err, flag, sizeof(err), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (err) {
+        HIP_OK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+        HIP_OK(hipStreamSynchronize(s));
+        throw Error(SNSW_E_STATE, "a dependency wait of the persistent sweep timed out; results are invalid");
+    }
+}
+
+int persistent_grid(int dim, int p, int64_t total, int device, double fraction) {
+    int cus = 0;
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    const int per_cu = persistent_blocks_per_cu(dim, p);
+    const int n = dim == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
+    const int64_t per_block = 4 * (64 / n);
+    const int64_t need = (total + per_block - 1) / per_block;
+    const int64_t cap = std::max<int64_t>(1, (int64_t)(fraction * per_cu * cus));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
+}
 
 void device_check_ctx(snsw_ctx* ctx) {
     int n = 0;
@@ -244,15 +266,23 @@ void device_upload(snsw_problem* prob) {
     HIP_OK(hipMemsetAsync(dp->ticket, 0, sizeof(unsigned int), s));
     dp->error = dalloc<int32_t>(dp, 1);
     HIP_OK(hipMemsetAsync(dp->error, 0, sizeof(int32_t), s));
-    dp->level_off = hp.level_off;
+    SweepClass& c = dp->cls;
+    c.dim = hp.dim;
+    c.p = hp.p;
+    c.mixed = hp.precision == SNSW_PREC_MIXED;
+    c.persistent = hp.schedule == SNSW_SCHED_PERSISTENT;
+    c.ticket = 0;
+    c.pairs = dp->pairs;
+    c.level_off = hp.level_off;
+    c.members = {0};
+    c.blocks = persistent_grid(hp.dim, hp.p, hp.level_off.back(), dp->device);
     {
-        int cus = 0;
-        HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dp->device));
-        const int per_cu = persistent_blocks_per_cu(hp.dim, hp.p, hp.precision == SNSW_PREC_MIXED);
-        const int64_t total = hp.level_off.back();
-        const int64_t per_block = 4 * (64 / hp.n);
-        const int64_t need = (total + per_block - 1) / per_block;
-        dp->blocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * cus));
+        dp->cur = 0;
+        dp->table_cur = 0;
+        SweepArgs a = make_args(prob, 0);
+        a.persistent = c.persistent ? 1 : 0;
+        dp->table = dalloc<SweepArgs>(dp, 1);
+        HIP_OK(hipMemcpyAsync(dp->table, &a, sizeof(a), hipMemcpyHostToDevice, s));
     }
     HIP_OK(hipStreamSynchronize(s));
 }
@@ -264,10 +294,10 @@ void device_release(snsw_problem* prob) noexcept {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(dp->device);
     (void)hipStreamSynchronize(dp->stream);
-    for (hipEvent_t ev : dp->events) (void)hipEventDestroy(ev);
+    dp->prof.release();
     void* ptrs[] = {dp->geo, dp->B, dp->kink_tab, dp->kink_idx, dp->pairs, dp->slot_face, dp->slot_nbr,
                     dp->sigma_t, dp->sigma_s, dp->q, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
-                    dp->phi_tmp, dp->red, dp->ticket, dp->error};
+                    dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -305,7 +335,7 @@ int snsw_synchronize(snsw_problem* prob) {
     return snsw_guard([&] {
         DeviceProblem* dp = need_device(prob);
         DeviceGuard g(dp->device);
-        check_device_error(dp);
+        check_error_flag(dp->error, dp->stream);
     });
 }
 
@@ -371,7 +401,7 @@ int snsw_solve(snsw_problem* prob, const snsw_solve_opts* opts, double* d_phi, d
 int snsw_profile_enable(snsw_problem* prob, int enable) {
     return snsw_guard([&] {
         DeviceProblem* dp = need_device(prob);
-        dp->profiling = enable != 0;
+        dp->prof.on = enable != 0;
     });
 }
 
@@ -380,16 +410,8 @@ int snsw_profile_read(snsw_problem* prob, int64_t* launches, double* kernel_ms) 
         DeviceProblem* dp = need_device(prob);
         DeviceGuard g(dp->device);
         HIP_OK(hipStreamSynchronize(dp->stream));
-        double total = 0.0;
-        for (size_t i = 0; i + 1 < dp->n_events; i += 2) {
-            float ms = 0.0f;
-            HIP_OK(hipEventElapsedTime(&ms, dp->events[i], dp->events[i + 1]));
-            total += ms;
-        }
-        if (launches) *launches = (int64_t)(dp->n_events / 2);
-        if (kernel_ms) *kernel_ms = total;
-        dp->n_events = 0;
-        check_device_error(dp);
+        dp->prof.read(launches, kernel_ms);
+        check_error_flag(dp->error, dp->stream);
     });
 }
 
