@@ -13,7 +13,7 @@ per launch over its average launch time, HIP events around every launch in a
 second timed pass), plain source-iteration time to a 1e-8 residual, and the
 CPU oracle timed on a sample of the same workload.
 
-  python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c5]
+  python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5]
 """
 from __future__ import annotations
 
@@ -35,6 +35,9 @@ DESCRIPTIONS = {
           "q=1 in the central 8^3 block, vacuum",
     "c5": "3D 48^3 Q2 curved (warp 0.05), p=2, S12 (168 dirs), random sigma_t {1,100}, c=0.99, "
           "q=1, vacuum",
+    "c4": "batch of 64 independent 2D problems (seed 0): m^2 Q2 meshes m in [16,96], p in {1,2,3}, "
+          "S4-S12, sigma_t log-uniform [0.1,10], c uniform [0,0.95], q=1, vacuum; one hipGraph "
+          "replay per batch sweep, schedule per (dim, p) class chosen by the autotuner",
 }
 
 
@@ -78,16 +81,95 @@ def cpu_baseline(wp, n_dirs_sample: int = 4, repeats: int = 1):
                       f"on the full mesh, {dt:.2f} s"}
 
 
+def bench_batch(args):
+    """Batched sweep of the 64-problem workload: value = summed E*n*D over
+    the batch / time of one batch sweep (graph replay)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1810_11080_amd import Batch, Context, Problem
+
+    wps = W.c4()
+    ctx = Context(device=0)
+    t0 = time.perf_counter()
+    problems = [Problem.from_workload(ctx, wp) for wp in wps]
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    B = Batch(ctx, problems, schedule={"auto": 0, "persistent": 1, "levels": 2}[args.schedule], use_graph=True)
+    tune_s = time.perf_counter() - t0
+    ins = [torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda") for P in problems]
+    outs = [torch.empty_like(t) for t in ins]
+    for _ in range(args.warmup):
+        B.sweep(ins, outs)
+        ins, outs = outs, ins
+    B.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        B.sweep(ins, outs)
+        ins, outs = outs, ins
+    ev1.record(stream)
+    B.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    dof_dir = sum(P.E * P.n * P.D for P in problems)
+    flops = sum(flops_per_pair(wp.dim, wp.p) * P.E * P.D for wp, P in zip(wps, problems))
+    achieved = flops / (ms * 1e-3) / 1e12
+    classes = B.classes()
+    line = {
+        "metric": "DOF-direction updates/s per sweep",
+        "value": dof_dir / (ms * 1e-3),
+        "unit": "DOF-dir/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": DESCRIPTIONS["c4"], "problems": len(problems), "dof_dir_per_sweep": dof_dir,
+                   "setup_s": round(setup_s, 2), "tune_s": round(tune_s, 2),
+                   "classes": [{"p": c["dg_order"], "problems": c["n_problems"], "levels": c["n_levels"],
+                                "schedule": "persistent" if c["persistent"] else "levels",
+                                "blocks": c["blocks"], "tuned_ms": [round(x, 3) for x in c["tuned_ms"]]}
+                               for c in classes]},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                     "kernel": "whole batch sweep (graph replay: source, fill, class sweeps, scalar flux)"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line))
+
+
+def calibrate_copy(nbytes: int = 1 << 30, reps: int = 3):
+    """A plain streaming kernel of known traffic (read nbytes, write nbytes):
+    the reference for scaling HBM counter readings to bytes."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "elementwise copy kernel", "read_bytes": nbytes, "write_bytes": nbytes,
+                      "launches": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(DESCRIPTIONS))
+    ap.add_argument("--workload", default="c2", choices=sorted(DESCRIPTIONS),
+                    help="c2 (default): the single-problem benchmark; c4: the 64-problem batch")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "persistent", "levels"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a copy kernel of known size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -101,6 +183,12 @@ def main():
     from paper_1810_11080_amd import Context, Problem
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.workload == "c4":
+        bench_batch(args)
+        return
     wp = W.CONFIGS[args.workload]()
     prec = 0 if args.precision == "fp64" else 1
     ctx = Context(device=0)
