@@ -27,6 +27,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+# HBM bytes per launch of the timed kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes, scaled by a copy kernel of known size (fetch x2.000,
+# write x1.000); profiles/sweep_persistent_dpp_c2_128x128_q3_p3_s8.md.
+# Only valid for the kernel build it was measured on: drop an entry when the
+# kernel changes.
+MEASURED_TRAFFIC = {("sweep_persistent_dpp<2,3>", "c2", "fp64"): 2.395e9}
 DESCRIPTIONS = {
     "c1": "2D 8x8 Q2 curved (warp 0.05), p=1, S4 (12 dirs), sigma_t=1, c=0.5, q=1, vacuum",
     "c2": "2D 128x128 Q3 curved (warp 0.3 h, 4-element wavelength, cyclic sweep graphs), p=3, "
@@ -234,11 +240,12 @@ def main():
     flops_sweep = flops_per_pair(wp.dim, wp.p) * E * D
     flops_per_launch = flops_sweep / launches_per_sweep
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    kname = (f"sweep_persistent_{'dpp' if wp.dim == 2 and wp.p != 2 else 'fp64'}<{wp.dim},{wp.p}>"
+             if sched == 1 else f"sweep_level_fp64<{wp.dim},{wp.p}>")
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5),
-                "traffic": None,
-                "kernel": (f"sweep_persistent_{'dpp' if wp.dim == 2 and wp.p != 2 else 'fp64'}<{wp.dim},{wp.p}>"
-                           if sched == 1 else f"sweep_level_fp64<{wp.dim},{wp.p}>"),
+                "traffic": MEASURED_TRAFFIC.get((kname, args.workload, args.precision)),
+                "kernel": kname,
                 "avg_launch_us": round(avg_launch_ms * 1e3, 3),
                 "launches_per_sweep": launches_per_sweep,
                 "kernel_share_of_step": round(kernel_ms / args.steps / ms_per_step, 4)}

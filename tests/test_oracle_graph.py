@@ -125,3 +125,30 @@ def test_unwarped_levels(dim, n):
             ia = disc.eidx[a]
             lev += np.where(om[a] > 0, ia, n - 1 - ia)
         assert np.array_equal(g.level, lev)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_edge_weights_closed_form_unwarped(p):
+    """On an unwarped square mesh every x-face block of direction d is
+    |Omega_x| times the same face mass matrix and every y-face block
+    |Omega_y| times it, so Face weights are rint(|Omega_a| / max_b |Omega_b|
+    * 2^20) for an edge across an axis-a face.  SigInvFace multiplies by the
+    same M^{-1} up to the element's 1/sigma_t and the x/y symmetry of the
+    square, so its weight is rint((|Omega_a| / sigma_down) / max(...) *
+    2^20).  Unity weights are 1."""
+    n = 4
+    sig = np.linspace(0.5, 3.0, n * n)
+    wp = W.make_problem("flat", 2, (n, n), 1, p, 4, 0.0, 1, sig, 0.5, 1.0)
+    disc = Discretization(wp)
+    for d in range(disc.D):
+        om = np.abs(disc.omega[d, :2])
+        for weighting in (0, 1, 2):
+            g = direction_graph(disc, d, weighting)
+            # axis of the shared face: elements differ along x (axis 0) or y
+            axis = np.where(np.abs(g.up - g.down) == 1, 0, 1)
+            if weighting == 0:
+                assert np.all(g.w == 1)
+                continue
+            raw = om[axis] / (sig[g.down] if weighting == 2 else 1.0)
+            expect = np.clip(np.rint(raw / raw.max() * 2 ** 20), 1, 2 ** 20).astype(np.int64)
+            assert np.array_equal(g.w, expect), (d, weighting)
