@@ -202,11 +202,25 @@ int snsw_synchronize(snsw_problem* prob);
  * receives the last iterate; d_psi (nullable) its angular flux.  The
  * residual history is written to report->history if non-NULL (capacity
  * history_cap).  Returns SNSW_E_NOT_CONVERGED after max_iters (result
- * kept), SNSW_E_DIVERGED on NaN/overflow.  Synchronous.                     */
+ * kept), SNSW_E_DIVERGED on NaN/overflow.  Synchronous.
+ *
+ * With opts->precond, after the plain sweeps phi~ = S(phi_l) numbered
+ * k, 2k, 3k, ... (k = precond_every) the element means of the residual,
+ * rbar_e = mean over element e of (phi~ - phi_l), scaled by s = max|rbar|,
+ * together with log(sigma_t)/5 and c = sigma_s/sigma_t, form the network
+ * input on the element grid; the network output y gives
+ * phi_{l+1} = phi~ + s*y_e on every node of element e.  Convergence is
+ * judged by the plain-sweep residual only, so the fixed point is unchanged.  Safeguard: a correction is judged precond_every
+ * sweeps later; if the residual then is not below the residual at which it
+ * was applied, it counts as rejected and the next correction is skipped;
+ * after 3 rejections the network is not used again in this solve.          */
+typedef struct snsw_net snsw_net;
 typedef struct {
     double  tol;
     int32_t max_iters;
-    int32_t check_every;         /* >= 1                                     */
+    int32_t check_every;         /* >= 1 (ignored with precond: every step) */
+    snsw_net* precond;           /* learned correction (see above) or NULL  */
+    int32_t precond_every;       /* correct after every k-th sweep (0 = 1)  */
 } snsw_solve_opts;
 typedef struct {
     int32_t iterations;
@@ -214,6 +228,8 @@ typedef struct {
     double  seconds;
     double* history;             /* caller buffer or NULL                    */
     int32_t history_cap;
+    int32_t n_corrected;         /* steps the learned correction was applied */
+    int32_t n_rejected;          /* steps it was skipped by the safeguard    */
 } snsw_solve_report;
 int snsw_solve(snsw_problem* prob, const snsw_solve_opts* opts, double* d_phi,
                double* d_psi, snsw_solve_report* report);
@@ -238,6 +254,56 @@ int snsw_profile_read(snsw_problem* prob, int64_t* launches, double* kernel_ms);
 int snsw_state_size(const snsw_problem* prob, size_t* bytes);
 int snsw_state_save(const snsw_problem* prob, void* host_buf, size_t cap);
 int snsw_state_load(snsw_problem* prob, const void* host_buf, size_t size);
+
+/* ------------------------------------------------------ learned correction
+ * A 3D U-Net over the element grid (nz, ny, nx) (nz = 1 for 2D problems):
+ * 3x3x3 convolutions with zero padding and bias, leaky ReLU (slope 0.1),
+ * widths (c0, c1, c2) at full, half and quarter resolution (stride-2
+ * convolutions down, nearest-neighbour upsampling plus skip connections
+ * up), 3 input channels (scaled residual mean, log(sigma_t)/5, c), one
+ * output channel.  Parameters: FP32 masters, in layer order weights
+ * [cout][cin][3][3][3] then bias [cout]; the convolutions use a BF16 copy of
+ * the weights and accumulate in FP32.  The paper has no learned component
+ * (it leaves the strongly scattering regime open); this is the project's.   */
+typedef struct {
+    int32_t  widths[3];          /* (c0, c1, c2), each in [1, 64]             */
+    uint64_t seed;               /* initial weights: He-uniform from seed     */
+} snsw_net_desc;
+typedef struct {
+    float lr, beta1, beta2, eps; /* Adam (bias-corrected)                      */
+} snsw_adam;
+
+int  snsw_net_create(snsw_ctx* ctx, const snsw_net_desc* desc, snsw_net** out);
+void snsw_net_destroy(snsw_net* net);
+int  snsw_net_n_params(const snsw_net* net, int64_t* n);
+/* host float[n_params]; set also clears the Adam moments (synchronous)     */
+int  snsw_net_get_params(const snsw_net* net, float* host);
+int  snsw_net_set_params(snsw_net* net, const float* host);
+/* gradient of the last backward pass, host float[n_params] (synchronous)   */
+int  snsw_net_get_grads(const snsw_net* net, float* host);
+
+/* d_x float [batch][3][nz][ny][nx] -> d_y float [batch][1][nz][ny][nx].
+ * Keeps the activations for snsw_net_backward; d_x must stay unchanged
+ * until then.                                                               */
+int snsw_net_forward(snsw_net* net, const float* d_x, float* d_y, int32_t batch,
+                     int32_t nz, int32_t ny, int32_t nx);
+/* loss = mean((y - t)^2) over count values (FP64 accumulation) and
+ * d_dy = 2 (y - t) / count (synchronous for the loss value).                */
+int snsw_net_loss(snsw_net* net, const float* d_y, const float* d_t, int64_t count,
+                  float* d_dy, double* loss);
+/* Gradient of sum(d_dy * y) for the last forward pass: replaces the
+ * parameter gradient; d_dx (nullable) receives the input gradient.          */
+int snsw_net_backward(snsw_net* net, const float* d_dy, float* d_dx);
+/* One Adam step on the masters with the current gradient; refreshes the
+ * BF16 weights.                                                              */
+int snsw_net_step(snsw_net* net, const snsw_adam* opt);
+
+/* Training pair of one plain iteration phi_prev -> phi_swept of a problem
+ * converged to phi_star: d_x float [3][E] network input (as in the solve),
+ * d_t float [E] target mean(phi_star - phi_swept)_e / s (d_phi_star and d_t
+ * nullable: input only).  Synchronous.                                      */
+int snsw_learn_pair(snsw_problem* prob, const double* d_phi_prev, const double* d_phi_swept,
+                    const double* d_phi_star, float* d_x, float* d_t);
 
 /* ------------------------------------------------------------------ batch
  * Many independent problems swept together (same context, device-backed,

@@ -16,9 +16,13 @@ the project's definition, stated plainly:
   element is represented exactly by equal nodal values);
 * the plain-sweep residual rho_l = max|phi~ - phi_l| / max|phi~| alone
   decides convergence, so the fixed point is that of plain source iteration;
-* safeguard: when the residual after a corrected step is not smaller than
-  the one before it, the next step is plain; after 3 such rejections the
-  network is switched off for the rest of the solve.
+* the correction is tried after sweeps k, 2k, 3k, ... (k = ``every``), so
+  that the plain sweeps in between damp the fast error modes it excites;
+* safeguard: a correction is judged k sweeps later -- if the plain-sweep
+  residual at the next correction point is not below the residual at which
+  the correction was applied, the correction counts as rejected and the next
+  one is skipped; after 3 rejections the network is switched off for the
+  rest of the solve.
 
 Training pairs from a plain source iteration converged to phi*: input
 x^l = [a(phi_{l+1} - phi_l) / s_l, features], target
@@ -83,30 +87,33 @@ def training_pair(disc, phi_prev, phi_swept, phi_star):
     return x[0], t
 
 
-def preconditioned_si(disc, graphs, theta, widths, tol, max_iters):
+def preconditioned_si(disc, graphs, theta, widths, tol, max_iters, every=1):
     """Source iteration with the learned correction and the safeguard.
     Returns phi, the residual history and the number of corrected steps."""
     phi = np.zeros((disc.E, disc.n))
     psi = np.zeros((disc.D, disc.E, disc.n))
     hist = []
-    enabled, rejections, corrected_last, n_corr = theta is not None, 0, False, 0
-    for _ in range(max_iters):
+    enabled, rejections, n_corr = theta is not None, 0, 0
+    pending, res_at_corr = False, np.inf
+    for it in range(1, max_iters + 1):
         psi, phi_t = sweep(disc, graphs, phi, psi)
         res = float(np.abs(phi_t - phi).max() / np.abs(phi_t).max())
         hist.append(res)
         if res <= tol:
             return phi_t, hist, n_corr
-        apply = enabled
-        if corrected_last and len(hist) >= 2 and res >= hist[-2]:
-            rejections += 1
-            apply = False
-            if rejections >= MAX_REJECTIONS:
-                enabled = False
+        apply = False
+        if enabled and it % every == 0:
+            apply = True
+            if pending and res >= res_at_corr:
+                rejections += 1
+                apply = False
+                if rejections >= MAX_REJECTIONS:
+                    enabled = False
+            pending = apply
         if apply:
             phi = correction(disc, theta, widths, phi, phi_t)
             n_corr += 1
-            corrected_last = True
+            res_at_corr = res
         else:
             phi = phi_t
-            corrected_last = False
     return phi, hist, n_corr

@@ -173,8 +173,9 @@ def forward(theta, widths, x):
     return y, cache
 
 
-def backward(theta, widths, cache, dy):
-    """Gradient of sum(dy * forward(x)) with respect to theta (same order)."""
+def backward(theta, widths, cache, dy, return_dx=False):
+    """Gradient of sum(dy * forward(x)) with respect to theta (same order);
+    with return_dx also the gradient with respect to the input x."""
     P = unpack(theta, widths)
     grads = {}
 
@@ -200,13 +201,14 @@ def backward(theta, widths, cache, dy):
     g = back("e1b", g + g_s1)
     g = back("e1a", g)
     g = back("e0b", g + g_s0)
-    back("e0a", g)
+    dx = back("e0a", g)
     parts = []
     for name, *_ in layer_specs(widths):
         dw, db = grads[name]
         parts.append(dw.reshape(-1))
         parts.append(db)
-    return np.concatenate(parts)
+    theta_grad = np.concatenate(parts)
+    return (theta_grad, dx) if return_dx else theta_grad
 
 
 def mse(y, t):

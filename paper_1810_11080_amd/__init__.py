@@ -5,6 +5,6 @@ C++, sweep kernels in HIP for gfx950); this package is a thin ctypes binding
 with the same function names (``snsw_*``) plus small convenience classes.
 PyTorch provides device memory and streams only.
 """
-from .binding import (Batch, Context, Problem, SnswError, lib, library_path)  # noqa: F401
+from .binding import (Batch, Context, Net, Problem, SnswError, lib, library_path)  # noqa: F401
 
-__all__ = ["Batch", "Context", "Problem", "SnswError", "lib", "library_path"]
+__all__ = ["Batch", "Context", "Net", "Problem", "SnswError", "lib", "library_path"]

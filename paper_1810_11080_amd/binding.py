@@ -46,12 +46,22 @@ class SnswGraphStats(C.Structure):
 
 
 class SnswSolveOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("check_every", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("check_every", C.c_int32),
+                ("precond", C.c_void_p), ("precond_every", C.c_int32)]
 
 
 class SnswSolveReport(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("residual", C.c_double), ("seconds", C.c_double),
-                ("history", c_double_p), ("history_cap", C.c_int32)]
+                ("history", c_double_p), ("history_cap", C.c_int32), ("n_corrected", C.c_int32),
+                ("n_rejected", C.c_int32)]
+
+
+class SnswNetDesc(C.Structure):
+    _fields_ = [("widths", C.c_int32 * 3), ("seed", C.c_uint64)]
+
+
+class SnswAdam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 class SnswBatchOpts(C.Structure):
@@ -92,6 +102,18 @@ SIGNATURES = {
     "snsw_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "snsw_state_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "snsw_state_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "snsw_net_create": (C.c_int, [C.c_void_p, C.POINTER(SnswNetDesc), C.POINTER(C.c_void_p)]),
+    "snsw_net_destroy": (None, [C.c_void_p]),
+    "snsw_net_n_params": (C.c_int, [C.c_void_p, c_int64_p]),
+    "snsw_net_get_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    "snsw_net_set_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    "snsw_net_get_grads": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    "snsw_net_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                   C.c_int32]),
+    "snsw_net_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, c_double_p]),
+    "snsw_net_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "snsw_net_step": (C.c_int, [C.c_void_p, C.POINTER(SnswAdam)]),
+    "snsw_learn_pair": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "snsw_batch_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(SnswBatchOpts),
                                     C.POINTER(C.c_void_p)]),
     "snsw_batch_destroy": (None, [C.c_void_p]),
@@ -148,6 +170,20 @@ def _tensor_ptr(t, numel: int, device: int, name: str):
         raise TypeError(f"{name} must be a torch tensor")
     if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
         raise TypeError(f"{name} must be a contiguous float64 device tensor")
+    if t.device.index != device:
+        raise ValueError(f"{name} is on device {t.device.index}, context uses {device}")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {numel}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f32_ptr(t, numel: int, device: int, name: str):
+    """Data pointer of a float32 contiguous device tensor of numel entries."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+        raise TypeError(f"{name} must be a contiguous float32 device tensor")
     if t.device.index != device:
         raise ValueError(f"{name} is on device {t.device.index}, context uses {device}")
     if t.numel() != numel:
@@ -232,6 +268,7 @@ class Problem:
         info = self.info()
         self.E, self.n, self.D = info["n_elements"], info["n_dofs_per_element"], info["n_dirs"]
         self.dim = dim
+        self.nx = tuple(int(v) for v in nx[:dim])
 
     @classmethod
     def from_workload(cls, ctx: Context, prob, precision=0, n_threads=0, weighting=None,
@@ -330,9 +367,11 @@ class Problem:
         return out.value
 
     def solve(self, phi, tol=1e-8, max_iters=1000, check_every=1, psi=None, history_cap=0,
-              raise_on_not_converged=True):
+              raise_on_not_converged=True, precond=None, precond_every=1):
         dev = self.ctx.device
-        opts = SnswSolveOpts(tol=tol, max_iters=max_iters, check_every=check_every)
+        opts = SnswSolveOpts(tol=tol, max_iters=max_iters, check_every=check_every,
+                             precond=precond.handle if precond is not None else None,
+                             precond_every=precond_every)
         hist = np.zeros(max(history_cap, 1))
         rep = SnswSolveReport()
         rep.history = _dptr(hist, C.c_double) if history_cap else None
@@ -344,7 +383,18 @@ class Problem:
             _check(rc)
         n_hist = min(history_cap, rep.iterations)
         return {"iterations": rep.iterations, "residual": rep.residual, "seconds": rep.seconds,
-                "history": hist[:n_hist].copy() if history_cap else None, "status": rc}
+                "history": hist[:n_hist].copy() if history_cap else None, "status": rc,
+                "n_corrected": rep.n_corrected, "n_rejected": rep.n_rejected}
+
+    def learn_pair(self, phi_prev, phi_swept, phi_star, x, t):
+        """Network input x (float32 [3][E]) and target t (float32 [E], or None)."""
+        dev = self.ctx.device
+        En = self.E * self.n
+        star = _tensor_ptr(phi_star, En, dev, "phi_star") if phi_star is not None else C.c_void_p()
+        tp = _f32_ptr(t, self.E, dev, "t") if t is not None else C.c_void_p()
+        _check(lib().snsw_learn_pair(self.handle, _tensor_ptr(phi_prev, En, dev, "phi_prev"),
+                                     _tensor_ptr(phi_swept, En, dev, "phi_swept"), star,
+                                     _f32_ptr(x, 3 * self.E, dev, "x"), tp))
 
     def profile_enable(self, enable: bool = True):
         _check(lib().snsw_profile_enable(self.handle, 1 if enable else 0))
@@ -420,3 +470,72 @@ class Batch:
             d["tuned_ms"] = list(info.tuned_ms)
             out.append(d)
         return out
+
+
+class Net:
+    """The learned source-iteration correction (3D U-Net on the element grid)."""
+
+    def __init__(self, ctx: Context, widths=(16, 32, 32), seed: int = 0):
+        self.ctx = ctx
+        self.widths = tuple(int(w) for w in widths)
+        desc = SnswNetDesc(widths=(C.c_int32 * 3)(*self.widths), seed=seed)
+        h = C.c_void_p()
+        _check(lib().snsw_net_create(ctx.handle, C.byref(desc), C.byref(h)))
+        self.handle = h
+        n = C.c_int64()
+        _check(lib().snsw_net_n_params(h, C.byref(n)))
+        self.n_params = n.value
+        self._shape = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().snsw_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().snsw_net_get_params(self.handle, _dptr(out, C.c_float)))
+        return out
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        if a.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _check(lib().snsw_net_set_params(self.handle, _dptr(a, C.c_float)))
+
+    def get_grads(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().snsw_net_get_grads(self.handle, _dptr(out, C.c_float)))
+        return out
+
+    def forward(self, x, y, batch, nz, ny, nx):
+        n = batch * nz * ny * nx
+        dev = self.ctx.device
+        _check(lib().snsw_net_forward(self.handle, _f32_ptr(x, 3 * n, dev, "x"), _f32_ptr(y, n, dev, "y"),
+                                      batch, nz, ny, nx))
+        self._shape = (batch, nz, ny, nx)
+
+    def loss(self, y, t, dy) -> float:
+        n = y.numel()
+        dev = self.ctx.device
+        out = C.c_double()
+        _check(lib().snsw_net_loss(self.handle, _f32_ptr(y, n, dev, "y"), _f32_ptr(t, n, dev, "t"), n,
+                                   _f32_ptr(dy, n, dev, "dy"), C.byref(out)))
+        return out.value
+
+    def backward(self, dy, dx=None):
+        b, z, y, x = self._shape
+        n = b * z * y * x
+        dev = self.ctx.device
+        dxp = _f32_ptr(dx, 3 * n, dev, "dx") if dx is not None else C.c_void_p()
+        _check(lib().snsw_net_backward(self.handle, _f32_ptr(dy, n, dev, "dy"), dxp))
+
+    def step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        opt = SnswAdam(lr=lr, beta1=beta1, beta2=beta2, eps=eps)
+        _check(lib().snsw_net_step(self.handle, C.byref(opt)))

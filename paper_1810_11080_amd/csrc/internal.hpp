@@ -11,6 +11,7 @@ struct snsw_ctx {
 namespace snsw {
 struct DeviceProblem;
 }
+struct snsw_net;
 
 struct snsw_problem {
     snsw_ctx* ctx = nullptr;

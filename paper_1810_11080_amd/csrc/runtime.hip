@@ -10,6 +10,7 @@
 #include <string>
 
 #include "device.hpp"
+#include "net.hpp"
 
 namespace snsw {
 
@@ -365,9 +366,17 @@ int snsw_solve(snsw_problem* prob, const snsw_solve_opts* opts, double* d_phi, d
         double res = INFINITY;
         int it = 0, nh = 0;
         bool done = false;
+        // learned correction and its safeguard
+        snsw_net* net = opts->precond;
+        bool enabled = net != nullptr, pending = false;
+        double res_at_corr = INFINITY;
+        int rejections = 0, n_corr = 0, n_rej = 0;
+        const int check_every = net ? 1 : opts->check_every;
+        if (opts->precond_every < 0) throw Error(SNSW_E_INVALID_ARG, "precond_every must be >= 0");
+        const int every = opts->precond_every > 1 ? opts->precond_every : 1;
         for (it = 1; it <= opts->max_iters; ++it) {
             do_sweep(prob, cur, nxt, nullptr);
-            if (it % opts->check_every == 0 || it == opts->max_iters) {
+            if (it % check_every == 0 || it == opts->max_iters) {
                 res = do_residual(dp, len, nxt, cur);
                 if (report && report->history && nh < report->history_cap) report->history[nh++] = res;
                 if (std::isnan(res) || res > 1e300) {
@@ -375,6 +384,22 @@ int snsw_solve(snsw_problem* prob, const snsw_solve_opts* opts, double* d_phi, d
                     done = true;
                 } else if (res <= opts->tol) {
                     done = true;
+                }
+            }
+            if (!done && net && enabled && it % every == 0) {
+                // the previous correction is judged now, `every` sweeps later
+                bool apply = true;
+                if (pending && res >= res_at_corr) {
+                    ++rejections;
+                    ++n_rej;
+                    apply = false;
+                    if (rejections >= 3) enabled = false;
+                }
+                pending = apply;
+                if (apply) {
+                    net_apply_correction(net, prob, cur, nxt);
+                    ++n_corr;
+                    res_at_corr = res;
                 }
             }
             std::swap(cur, nxt);
@@ -390,6 +415,8 @@ int snsw_solve(snsw_problem* prob, const snsw_solve_opts* opts, double* d_phi, d
             report->iterations = it;
             report->residual = res;
             report->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            report->n_corrected = n_corr;
+            report->n_rejected = n_rej;
         }
         if (status == SNSW_OK && !(res <= opts->tol)) status = SNSW_E_NOT_CONVERGED;
         if (status == SNSW_E_DIVERGED) throw Error(SNSW_E_DIVERGED, "source iteration diverged");

@@ -1,0 +1,167 @@
+"""Learned correction on the GPU (HIP kernels through the C-ABI) against the
+CPU FP64 oracle.
+
+The kernels use BF16 weights and FP32 activations and accumulation; the
+oracle is evaluated in FP64 with the same BF16-rounded weights (round to
+nearest even, done here on the host) and FP32 biases, so the comparison
+measures only FP32 accumulation: each output sums c*27 <= 864 products, so
+its relative rounding error is below about 864 * 2^-24 = 5e-5 per layer,
+and 12 layers stay within the 1e-3 bar used here (normwise L-infinity).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import learned as LR
+from oracle import net as N
+from oracle.discretization import Discretization
+from oracle.sweep import build_graphs
+from tests.lib_helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+NET_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a GPU"
+    return T
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_1810_11080_amd import Context
+    return Context(device=0)
+
+
+def bf16_round(a32):
+    """float32 -> nearest-even bfloat16 value, as float32."""
+    u = np.asarray(a32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def device_weights(theta32, widths):
+    """Parameters as the kernels see them: BF16 weights, FP32 biases."""
+    out = theta32.astype(np.float64).copy()
+    k = 0
+    for _, i, o, _, _ in N.layer_specs(widths):
+        nw = o * i * 27
+        out[k:k + nw] = bf16_round(theta32[k:k + nw]).astype(np.float64)
+        k += nw + o
+    return out
+
+
+CASES = [((4, 6, 8), (2, 5, 6, 7)), ((16, 32, 32), (2, 7, 6, 9)), ((4, 6, 8), (3, 1, 9, 8)),
+         ((3, 5, 4), (1, 2, 3, 2))]
+
+
+@pytest.mark.parametrize("widths,shape", CASES, ids=["small-3d", "default-3d", "2d-grid", "tiny-ragged"])
+def test_forward_backward_match_oracle(torch, ctx, widths, shape):
+    from paper_1810_11080_amd import Net
+    B, Z, Y, X = shape
+    print(f"net {widths} on {shape}", flush=True)
+    net = Net(ctx, widths=widths, seed=1)
+    rng = np.random.default_rng(7)
+    theta = (N.init_params(widths, seed=3) + 0.02 * rng.standard_normal(N.n_params(widths))).astype(np.float32)
+    assert net.n_params == theta.size
+    net.set_params(theta)
+    assert np.array_equal(net.get_params(), theta)
+    x = rng.standard_normal((B, 3, Z, Y, X)).astype(np.float32)
+    dy = rng.standard_normal((B, 1, Z, Y, X)).astype(np.float32)
+    xd = torch.tensor(x.reshape(-1), device="cuda")
+    yd = torch.empty(B * Z * Y * X, dtype=torch.float32, device="cuda")
+    net.forward(xd, yd, B, Z, Y, X)
+    dyd = torch.tensor(dy.reshape(-1), device="cuda")
+    dxd = torch.empty_like(xd)
+    net.backward(dyd, dxd)
+    torch.cuda.synchronize()
+    th64 = device_weights(theta, widths)
+    y_ref, cache = N.forward(th64, widths, x.astype(np.float64))
+    g_ref, dx_ref = N.backward(th64, widths, cache, dy.astype(np.float64), return_dx=True)
+    assert rel_err(yd.cpu().numpy().reshape(y_ref.shape), y_ref) <= NET_TOL
+    assert rel_err(dxd.cpu().numpy().reshape(x.shape), dx_ref) <= NET_TOL
+    g = net.get_grads()
+    # layer by layer, so that small early-layer gradients are checked too
+    k = 0
+    for name, i, o, _, _ in N.layer_specs(widths):
+        nw = o * i * 27
+        assert rel_err(g[k:k + nw], g_ref[k:k + nw]) <= NET_TOL, name
+        assert rel_err(g[k + nw:k + nw + o], g_ref[k + nw:k + nw + o]) <= NET_TOL, name + " bias"
+        k += nw + o
+
+
+def test_loss_and_adam_match_oracle(torch, ctx):
+    from paper_1810_11080_amd import Net
+    widths = (3, 4, 5)
+    net = Net(ctx, widths=widths, seed=2)
+    rng = np.random.default_rng(11)
+    theta = N.init_params(widths, seed=5).astype(np.float32)
+    net.set_params(theta)
+    B, Z, Y, X = 2, 4, 5, 3
+    x = rng.standard_normal((B, 3, Z, Y, X)).astype(np.float32)
+    t = rng.standard_normal((B, 1, Z, Y, X)).astype(np.float32)
+    xd = torch.tensor(x.reshape(-1), device="cuda")
+    td = torch.tensor(t.reshape(-1), device="cuda")
+    yd = torch.empty_like(td)
+    dyd = torch.empty_like(td)
+    net.forward(xd, yd, B, Z, Y, X)
+    loss = net.loss(yd, td, dyd)
+    y = yd.cpu().numpy().astype(np.float64)
+    ref_loss, ref_dy = N.mse(y, t.reshape(-1).astype(np.float64))
+    assert abs(loss - ref_loss) <= 1e-6 * ref_loss
+    assert rel_err(dyd.cpu().numpy(), ref_dy) <= 1e-6
+    net.backward(dyd)
+    g = net.get_grads().astype(np.float64)
+    th = theta.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for step in (1, 2, 3):
+        net.step(lr=1e-2)
+        th, m, v = N.adam_step(th, g, m, v, step, lr=1e-2)
+    got = net.get_params().astype(np.float64)
+    assert np.abs(got - th).max() <= 1e-6 * max(1.0, np.abs(th).max())
+
+
+def test_learn_pair_and_correction_match_oracle(torch, ctx):
+    """Network input/target from three GPU sweeps against the oracle's
+    definitions on the same fluxes."""
+    from paper_1810_11080_amd import Problem
+    wp = W.c5_reduced(seed=3, nx=4, p=1, sn_order=2)
+    P = Problem.from_workload(ctx, wp)
+    En = P.E * P.n
+    phis = [torch.zeros(En, dtype=torch.float64, device="cuda")]
+    for _ in range(3):
+        out = torch.empty_like(phis[0])
+        P.sweep(phis[-1], out)
+        phis.append(out)
+    x = torch.empty(3 * P.E, dtype=torch.float32, device="cuda")
+    t = torch.empty(P.E, dtype=torch.float32, device="cuda")
+    P.learn_pair(phis[1], phis[2], phis[3], x, t)
+    torch.cuda.synchronize()
+    disc = Discretization(wp)
+    h = [p.cpu().numpy().reshape(P.E, P.n) for p in phis]
+    xr, tr = LR.training_pair(disc, h[1], h[2], h[3])
+    assert rel_err(x.cpu().numpy(), xr.reshape(-1)) <= 1e-6
+    assert rel_err(t.cpu().numpy(), tr.reshape(-1)) <= 1e-6
+
+
+def test_preconditioned_solve_matches_oracle(torch, ctx):
+    """Source iteration with a (random) network on the GPU and in the oracle
+    converge to the same fixed point; the safeguard keeps it convergent."""
+    from paper_1810_11080_amd import Net, Problem
+    wp = W.c5_reduced(seed=4, nx=4, p=1, sn_order=2)
+    widths = (3, 4, 5)
+    theta = N.init_params(widths, seed=6).astype(np.float32)
+    net = Net(ctx, widths=widths)
+    net.set_params(theta)
+    P = Problem.from_workload(ctx, wp)
+    phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+    rep = P.solve(phi, tol=1e-11, max_iters=20000, precond=net)
+    disc = Discretization(wp)
+    gs = build_graphs(disc)
+    phi_ref, hist, ncorr = LR.preconditioned_si(disc, gs, device_weights(theta, widths), widths, 1e-11, 20000)
+    assert rep["residual"] <= 1e-11 and hist[-1] <= 1e-11
+    assert rep["n_corrected"] > 0 and ncorr > 0
+    assert rel_err(phi.cpu().numpy().reshape(P.E, P.n), phi_ref) <= 1e-8

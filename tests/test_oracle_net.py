@@ -64,6 +64,22 @@ def test_backward_matches_finite_differences():
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)), (k, fd, g[k])
 
 
+def test_input_gradient_matches_finite_differences():
+    widths = (2, 3, 3)
+    rng = np.random.default_rng(8)
+    theta = N.init_params(widths, seed=2)
+    x = rng.standard_normal((1, 3, 4, 3, 5))
+    dy = rng.standard_normal((1, 1, 4, 3, 5))
+    _, cache = N.forward(theta, widths, x)
+    _, dx = N.backward(theta, widths, cache, dy, return_dx=True)
+    h = 1e-7
+    for idx in [(0, 0, 0, 0, 0), (0, 1, 2, 1, 3), (0, 2, 3, 2, 4), (0, 0, 1, 1, 1)]:
+        e = np.zeros_like(x)
+        e[idx] = h
+        fd = (np.sum(dy * N.forward(theta, widths, x + e)[0]) - np.sum(dy * N.forward(theta, widths, x - e)[0])) / (2 * h)
+        assert abs(fd - dx[idx]) <= 1e-6 * max(1.0, abs(fd)), (idx, fd, dx[idx])
+
+
 def test_adam_first_step_closed_form():
     theta = np.array([1.0, -2.0, 0.5])
     g = np.array([0.3, -4.0, 1e-3])

@@ -171,6 +171,18 @@ def c5(seed: int = 100, nx: int = 48, sn_order: int = 12) -> Problem:
                         2, 2, sn_order, 0.05, 1, st, 0.99, 1.0, tol=1e-8)
 
 
+def c5_reduced(seed: int = 100, nx: int = 12, p: int = 1, sn_order: int = 4) -> Problem:
+    """The 48^3 two-material c = 0.99 family at a size where plain source
+    iteration converges in seconds: nx^3 Q2 mesh (warp 0.05), sigma_t = 100
+    where default_rng(seed).random(E) < 0.5 else 1, c = 0.99, q = 1, vacuum."""
+    dims = (nx, nx, nx)
+    E = nx ** 3
+    rng = np.random.default_rng(seed)
+    st = np.where(rng.random(E) < 0.5, 100.0, 1.0)
+    return make_problem(f"c5r_3d_{nx}cube_q2_p{p}_s{sn_order}_seed{seed}", 3, dims,
+                        2, p, sn_order, 0.05, 1, st, 0.99, 1.0, tol=1e-8)
+
+
 def small(dim=2, n=4, r=2, p=1, N=4, amp=0.05, freq=1, sigma_t=1.0, c=0.5,
           q=1.0, **kw) -> Problem:
     nx = (n,) * dim if np.isscalar(n) else tuple(n)
