@@ -8,10 +8,12 @@ workload: 2D 128x128 Q3 curved mesh (warp 0.3 element widths, 4-element
 wavelength, so the sweep graphs have cycles), DG p=3, S8 (40 directions),
 sigma_t = 1, c = 0.8, q = 1, vacuum; seeded synthetic inputs.
 
-Also reported: the roofline of the level-sweep kernel (algorithmic FP64 flops
-per launch over its average launch time, HIP events around every launch in a
-second timed pass), plain source-iteration time to a 1e-8 residual, and the
-CPU oracle timed on a sample of the same workload.
+Also reported: the roofline of the sweep kernel (algorithmic FP64 flops per
+launch over its average launch time, HIP events around every launch in a
+second timed pass), plain source-iteration time to a 1e-8 residual, the
+time to a 1e-8 residual with and without the learned correction on the
+two-material c = 0.99 family (training included, reported separately), and
+the CPU oracle timed on a sample of the same workload.
 
   python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5]
 """
@@ -150,6 +152,63 @@ def bench_batch(args):
     print(json.dumps(line))
 
 
+def learned_vs_plain(nx=16, p=2, sn_order=8, train_seeds=(0, 1, 2, 3), eval_seeds=(100, 101), steps=3000,
+                     every=40):
+    """Time to a 1e-8 residual with and without the learned correction on
+    the two-material c = 0.99 family (the 48^3 S12 configuration's
+    materials at nx^3): train on plain-SI pairs of train_seeds, evaluate on
+    held-out eval_seeds.  Returns a JSON-ready dict."""
+    import torch
+    import workloads as W
+    from paper_1810_11080_amd import Context, Net, Problem
+    from paper_1810_11080_amd import learn as L
+
+    ctx = Context(device=0)
+    t0 = time.perf_counter()
+    Xs, Ts = [], []
+    for seed in train_seeds:
+        P = Problem.from_workload(ctx, W.c5_reduced(seed=seed, nx=nx, p=p, sn_order=sn_order))
+        kept, star, _ = L.plain_trajectory(P, tol=1e-12, max_iters=50000, sample=lambda l: l % 3 == 0)
+        X, T = L.make_pairs(P, kept, star)
+        Xs.append(X)
+        Ts.append(T)
+        del kept, P
+    X = torch.cat(Xs)
+    T = torch.cat(Ts)
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    net = Net(ctx, widths=(16, 32, 32), seed=0)
+    t0 = time.perf_counter()
+    losses = L.train(net, (nx, nx, nx), X, T, steps=steps, batch=8, lr=2e-3, lr_final=1e-4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    runs = []
+    for seed in eval_seeds:
+        P = Problem.from_workload(ctx, W.c5_reduced(seed=seed, nx=nx, p=p, sn_order=sn_order))
+        row = {"seed": seed}
+        for name, pre in (("plain", None), ("learned", net)):
+            P.reset()
+            phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+            rep = P.solve(phi, tol=1e-8, max_iters=50000, precond=pre, precond_every=every)
+            row[name] = {"seconds": round(rep["seconds"], 4), "sweeps": rep["iterations"]}
+            if pre is not None:
+                row[name].update(corrections=rep["n_corrected"], rejected=rep["n_rejected"])
+        runs.append(row)
+    plain = sum(r["plain"]["seconds"] for r in runs)
+    learned = sum(r["learned"]["seconds"] for r in runs)
+    saved = (plain - learned) / len(runs)
+    return {"workload": f"3D {nx}^3 Q2 (warp 0.05), p={p}, S{sn_order}, sigma_t in {{1,100}} (random, 50/50), "
+                        f"c=0.99, q=1, vacuum; trained on seeds {list(train_seeds)}, evaluated on "
+                        f"{list(eval_seeds)}",
+            "tol": 1e-8, "precond_every": every, "params": net.n_params,
+            "time_plain_s": round(plain / len(runs), 4), "time_learned_s": round(learned / len(runs), 4),
+            "speedup": round(plain / learned, 3), "runs": runs,
+            "training": {"pairs": int(X.shape[0]), "data_s": round(data_s, 2), "train_s": round(train_s, 2),
+                         "steps": steps, "loss_first": float(losses[:10].mean()),
+                         "loss_last": float(losses[-100:].mean()),
+                         "break_even_solves": round((data_s + train_s) / saved, 1) if saved > 0 else None}}
+
+
 def calibrate_copy(nbytes: int = 1 << 30, reps: int = 3):
     """A plain streaming kernel of known traffic (read nbytes, write nbytes):
     the reference for scaling HBM counter readings to bytes."""
@@ -174,6 +233,7 @@ def main():
     ap.add_argument("--schedule", default="auto", choices=["auto", "persistent", "levels"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a copy kernel of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -258,12 +318,16 @@ def main():
         solve = {"method": "plain source iteration", "tol": 1e-8, "iterations": rep["iterations"],
                  "seconds": round(rep["seconds"], 4), "residual": rep["residual"]}
 
+    learned = None
+    if not args.no_learned and args.workload == "c2":
+        learned = learned_vs_plain()
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wp, n_dirs_sample=4 if args.workload in ("c1", "c2") else 2)
+        cpu = cpu_baseline(wp, n_dirs_sample=40 if args.workload in ("c1", "c2") else 4)
 
     line = {
-        "metric": "DOF-direction updates/s per sweep",
+        "metric": "DOF-direction updates/s per sweep; time to 1e-8 residual, learned vs plain SI",
         "value": value,
         "unit": "DOF-dir/s",
         "n_gpus": 1,
@@ -282,6 +346,7 @@ def main():
                    "schedule": "persistent" if sched == 1 else "levels"},
         "roofline": roofline,
         "solve_to_1e-8": solve,
+        "learned_vs_plain": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -210,10 +210,12 @@ int snsw_synchronize(snsw_problem* prob);
  * together with log(sigma_t)/5 and c = sigma_s/sigma_t, form the network
  * input on the element grid; the network output y gives
  * phi_{l+1} = phi~ + s*y_e on every node of element e.  Convergence is
- * judged by the plain-sweep residual only, so the fixed point is unchanged.  Safeguard: a correction is judged precond_every
- * sweeps later; if the residual then is not below the residual at which it
- * was applied, it counts as rejected and the next correction is skipped;
- * after 3 rejections the network is not used again in this solve.          */
+ * judged by the plain-sweep residual only, so the fixed point is unchanged.
+ * Safeguard: over the k sweeps after a correction the mean residual
+ * reduction per sweep must beat the one of the latest window without a
+ * correction (sweeps 1..k are plain); otherwise the correction counts as
+ * rejected and the next window is plain.  After 3 rejections the network is
+ * not used again in this solve.                                             */
 typedef struct snsw_net snsw_net;
 typedef struct {
     double  tol;

@@ -18,11 +18,13 @@ the project's definition, stated plainly:
   decides convergence, so the fixed point is that of plain source iteration;
 * the correction is tried after sweeps k, 2k, 3k, ... (k = ``every``), so
   that the plain sweeps in between damp the fast error modes it excites;
-* safeguard: a correction is judged k sweeps later -- if the plain-sweep
-  residual at the next correction point is not below the residual at which
-  the correction was applied, the correction counts as rejected and the next
-  one is skipped; after 3 rejections the network is switched off for the
-  rest of the solve.
+* safeguard: the correction is judged over the window of k sweeps that
+  follows it, against the plain iteration it replaces -- the mean residual
+  reduction per sweep over that window, (rho_t / rho_{t-k})^(1/k), must be
+  below the one measured over the latest window without a correction (the
+  first window, sweeps 1..k, is plain); otherwise it counts as rejected and
+  the next window is plain.  After 3 rejections the network is switched off
+  for the rest of the solve.
 
 Training pairs from a plain source iteration converged to phi*: input
 x^l = [a(phi_{l+1} - phi_l) / s_l, features], target
@@ -94,26 +96,34 @@ def preconditioned_si(disc, graphs, theta, widths, tol, max_iters, every=1):
     psi = np.zeros((disc.D, disc.E, disc.n))
     hist = []
     enabled, rejections, n_corr = theta is not None, 0, 0
-    pending, res_at_corr = False, np.inf
+    pending = False                 # the window now ending followed a correction
+    start_it, start_res = 1, None   # start of the current window
+    plain_rate = np.inf             # per-sweep reduction of the latest plain window
     for it in range(1, max_iters + 1):
         psi, phi_t = sweep(disc, graphs, phi, psi)
         res = float(np.abs(phi_t - phi).max() / np.abs(phi_t).max())
         hist.append(res)
         if res <= tol:
             return phi_t, hist, n_corr
+        if start_res is None:
+            start_res = res
         apply = False
         if enabled and it % every == 0:
+            rate = (res / start_res) ** (1.0 / max(1, it - start_it))
             apply = True
-            if pending and res >= res_at_corr:
-                rejections += 1
-                apply = False
-                if rejections >= MAX_REJECTIONS:
-                    enabled = False
+            if pending:
+                if rate >= plain_rate:
+                    rejections += 1
+                    apply = False
+                    if rejections >= MAX_REJECTIONS:
+                        enabled = False
+            else:
+                plain_rate = rate
             pending = apply
+            start_it, start_res = it, res
         if apply:
             phi = correction(disc, theta, widths, phi, phi_t)
             n_corr += 1
-            res_at_corr = res
         else:
             phi = phi_t
     return phi, hist, n_corr

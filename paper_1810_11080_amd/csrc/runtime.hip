@@ -368,8 +368,9 @@ int snsw_solve(snsw_problem* prob, const snsw_solve_opts* opts, double* d_phi, d
         bool done = false;
         // learned correction and its safeguard
         snsw_net* net = opts->precond;
-        bool enabled = net != nullptr, pending = false;
-        double res_at_corr = INFINITY;
+        bool enabled = net != nullptr, pending = false, have_start = false;
+        int start_it = 1;
+        double start_res = 0.0, plain_rate = INFINITY;
         int rejections = 0, n_corr = 0, n_rej = 0;
         const int check_every = net ? 1 : opts->check_every;
         if (opts->precond_every < 0) throw Error(SNSW_E_INVALID_ARG, "precond_every must be >= 0");
@@ -386,20 +387,32 @@ int snsw_solve(snsw_problem* prob, const snsw_solve_opts* opts, double* d_phi, d
                     done = true;
                 }
             }
+            if (!done && net && !have_start) {
+                start_res = res;
+                have_start = true;
+            }
             if (!done && net && enabled && it % every == 0) {
-                // the previous correction is judged now, `every` sweeps later
+                // per-sweep residual reduction over the window now ending;
+                // a window that followed a correction must beat the latest
+                // plain window
+                const double rate = std::pow(res / start_res, 1.0 / std::max(1, it - start_it));
                 bool apply = true;
-                if (pending && res >= res_at_corr) {
-                    ++rejections;
-                    ++n_rej;
-                    apply = false;
-                    if (rejections >= 3) enabled = false;
+                if (pending) {
+                    if (rate >= plain_rate) {
+                        ++rejections;
+                        ++n_rej;
+                        apply = false;
+                        if (rejections >= 3) enabled = false;
+                    }
+                } else {
+                    plain_rate = rate;
                 }
                 pending = apply;
+                start_it = it;
+                start_res = res;
                 if (apply) {
                     net_apply_correction(net, prob, cur, nxt);
                     ++n_corr;
-                    res_at_corr = res;
                 }
             }
             std::swap(cur, nxt);

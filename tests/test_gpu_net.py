@@ -147,7 +147,8 @@ def test_learn_pair_and_correction_match_oracle(torch, ctx):
     assert rel_err(t.cpu().numpy(), tr.reshape(-1)) <= 1e-6
 
 
-def test_preconditioned_solve_matches_oracle(torch, ctx):
+@pytest.mark.parametrize("every", [1, 3])
+def test_preconditioned_solve_matches_oracle(torch, ctx, every):
     """Source iteration with a (random) network on the GPU and in the oracle
     converge to the same fixed point; the safeguard keeps it convergent."""
     from paper_1810_11080_amd import Net, Problem
@@ -158,10 +159,48 @@ def test_preconditioned_solve_matches_oracle(torch, ctx):
     net.set_params(theta)
     P = Problem.from_workload(ctx, wp)
     phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
-    rep = P.solve(phi, tol=1e-11, max_iters=20000, precond=net)
+    rep = P.solve(phi, tol=1e-11, max_iters=20000, precond=net, precond_every=every)
     disc = Discretization(wp)
     gs = build_graphs(disc)
-    phi_ref, hist, ncorr = LR.preconditioned_si(disc, gs, device_weights(theta, widths), widths, 1e-11, 20000)
+    phi_ref, hist, ncorr = LR.preconditioned_si(disc, gs, device_weights(theta, widths), widths, 1e-11, 20000,
+                                                every=every)
     assert rep["residual"] <= 1e-11 and hist[-1] <= 1e-11
     assert rep["n_corrected"] > 0 and ncorr > 0
     assert rel_err(phi.cpu().numpy().reshape(P.E, P.n), phi_ref) <= 1e-8
+
+
+def test_trained_network_gains(torch, ctx):
+    """Train on plain-SI pairs of three seeds of the two-material c = 0.99
+    family (12^3 Q2, p = 1, S4), then solve a held-out seed to 1e-8 with and
+    without the network: fewer sweeps and less wall time with it."""
+    import time
+    from paper_1810_11080_amd import Net, Problem
+    from paper_1810_11080_amd import learn as L
+    Xs, Ts = [], []
+    for seed in range(3):
+        P = Problem.from_workload(ctx, W.c5_reduced(seed=seed, nx=12, p=1, sn_order=4))
+        kept, star, its = L.plain_trajectory(P, tol=1e-12, max_iters=20000, sample=lambda l: l % 3 == 0)
+        X, T = L.make_pairs(P, kept, star)
+        Xs.append(X)
+        Ts.append(T)
+        print(f"training seed {seed}: {its} plain sweeps, {len(kept)} pairs", flush=True)
+    X = torch.cat(Xs)
+    T = torch.cat(Ts)
+    net = Net(ctx, widths=(16, 32, 32), seed=0)
+    losses = L.train(net, (12, 12, 12), X, T, steps=2500, batch=8, lr=2e-3, lr_final=1e-4)
+    assert losses[-100:].mean() < 0.2 * losses[:10].mean()
+    P = Problem.from_workload(ctx, W.c5_reduced(seed=100, nx=12, p=1, sn_order=4))
+    out = {}
+    for name, pre in (("plain", None), ("learned", net)):
+        best = None
+        for _ in range(2):
+            P.reset()
+            phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+            t0 = time.perf_counter()
+            rep = P.solve(phi, tol=1e-8, max_iters=20000, precond=pre, precond_every=40)
+            dt = time.perf_counter() - t0
+            best = (rep["iterations"], dt) if best is None or dt < best[1] else best
+        out[name] = best
+    print(out, flush=True)
+    assert out["learned"][0] < 0.8 * out["plain"][0]
+    assert out["learned"][1] < out["plain"][1]
