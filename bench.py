@@ -68,7 +68,7 @@ def cpu_baseline(wp, n_dirs_sample: int = 4, repeats: int = 1):
     from oracle.quadrature import level_symmetric
     from oracle.sweep import build_graphs, sweep
     om, w = level_symmetric(wp.sn_order, wp.dim)
-    sel = np.linspace(0, len(w) - 1, n_dirs_sample).round().astype(int)
+    sel = np.linspace(0, len(w) - 1, min(n_dirs_sample, len(w))).round().astype(int)
     disc = Discretization(wp, omega=om[sel], w=w[sel])
     gs = build_graphs(disc)
     phi = np.zeros((disc.E, disc.n))
