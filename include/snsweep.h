@@ -72,10 +72,22 @@ extern "C" {
  * (element, direction) pairs in level order and wait only for the upwind
  * values they read (latency-bound sweeps: 2D).  LEVELS: one launch per level
  * (throughput-bound sweeps: 3D).  AUTO picks PERSISTENT for 2D p = 1 or 3
- * in FP64 and LEVELS otherwise; SNSW_PREC_MIXED requires LEVELS.            */
+ * in FP64 and LEVELS otherwise; SNSW_PREC_MIXED requires LEVELS.  With a
+ * cached inverse the persistent kernel for n = 9, 27 or 64 still
+ * assembles and factors per sweep.                                          */
 #define SNSW_SCHED_AUTO        0
 #define SNSW_SCHED_PERSISTENT  1
 #define SNSW_SCHED_LEVELS      2
+
+/* The element operator of a pair, A = sigma_t M - sum_i Omega_i K_i + its
+ * outflow face blocks, is the same in every source iteration.  With a cached
+ * inverse it is factored once (Gauss-Jordan on the device, at create) and a
+ * sweep only assembles b and forms A^{-1} b: D*E*n^2 doubles of device
+ * memory (e.g. 15 GB for 32^3 elements, p = 2, S8).  AUTO caches in FP64
+ * mode when that takes at most half of the free device memory.             */
+#define SNSW_CACHE_AUTO    0
+#define SNSW_CACHE_ON      1
+#define SNSW_CACHE_OFF     2
 
 typedef struct snsw_ctx snsw_ctx;
 typedef struct snsw_problem snsw_problem;
@@ -121,6 +133,8 @@ typedef struct {
     int32_t precision;       /* SNSW_PREC_*                                   */
     int32_t n_threads;       /* host threads for setup (0 = hardware count)   */
     int32_t schedule;        /* SNSW_SCHED_*                                  */
+    int32_t cache_inverse;   /* SNSW_CACHE_*: keep A^{-1} of every (element,
+                                direction) pair in device memory            */
 } snsw_problem_desc;
 
 /* Builds the discretisation and the sweep schedule (section 3): quadrature,
@@ -140,6 +154,8 @@ typedef struct {
     int64_t n_removed_total;     /* lagged edges over all directions         */
     int64_t n_kink_faces_total;  /* (face, direction) with a sign change     */
     double  setup_seconds;       /* host setup wall time                     */
+    int32_t cached_inverse;      /* 1 if A^{-1} per pair is kept on device   */
+    int32_t schedule;            /* resolved SNSW_SCHED_PERSISTENT / LEVELS  */
 } snsw_problem_info;
 int snsw_problem_get_info(const snsw_problem* prob, snsw_problem_info* info);
 

@@ -29,14 +29,16 @@ class SnswProblemDesc(C.Structure):
                 ("sigma_t", c_double_p), ("sigma_s", c_double_p), ("q", c_double_p),
                 ("q_per_dof", C.c_int32), ("bc_kind", C.c_int32), ("psi_inc", C.c_double),
                 ("weighting", C.c_int32), ("exact_scc_max", C.c_int32),
-                ("precision", C.c_int32), ("n_threads", C.c_int32), ("schedule", C.c_int32)]
+                ("precision", C.c_int32), ("n_threads", C.c_int32), ("schedule", C.c_int32),
+                ("cache_inverse", C.c_int32)]
 
 
 class SnswProblemInfo(C.Structure):
     _fields_ = [("n_elements", C.c_int64), ("n_dofs_per_element", C.c_int64),
                 ("n_dirs", C.c_int64), ("n_levels_total", C.c_int64), ("n_pairs", C.c_int64),
                 ("n_edges_total", C.c_int64), ("n_removed_total", C.c_int64),
-                ("n_kink_faces_total", C.c_int64), ("setup_seconds", C.c_double)]
+                ("n_kink_faces_total", C.c_int64), ("setup_seconds", C.c_double),
+                ("cached_inverse", C.c_int32), ("schedule", C.c_int32)]
 
 
 class SnswGraphStats(C.Structure):
@@ -221,7 +223,7 @@ class Problem:
 
     def __init__(self, ctx: Context, *, dim, nx, geom_order, dg_order, lattice, sn_order,
                  sigma_t, sigma_s, q, bc_kind=0, psi_inc=0.0, weighting=1, exact_scc_max=10,
-                 precision=0, n_threads=0, omega=None, w=None, schedule=0):
+                 precision=0, n_threads=0, omega=None, w=None, schedule=0, cache_inverse=0):
         self.ctx = ctx
         if dim not in (2, 3):
             raise SnswError(-1, "dim must be 2 or 3")
@@ -261,6 +263,7 @@ class Problem:
         desc.precision = precision
         desc.n_threads = n_threads
         desc.schedule = schedule
+        desc.cache_inverse = cache_inverse
         h = C.c_void_p()
         _check(lib().snsw_problem_create(ctx.handle, C.byref(desc), C.byref(h)))
         self.handle = h
@@ -272,14 +275,15 @@ class Problem:
 
     @classmethod
     def from_workload(cls, ctx: Context, prob, precision=0, n_threads=0, weighting=None,
-                      exact_scc_max=None, schedule=0):
+                      exact_scc_max=None, schedule=0, cache_inverse=0):
         """Build from a ``workloads.Problem`` (seeded synthetic inputs)."""
         return cls(ctx, dim=prob.dim, nx=tuple(prob.nx), geom_order=prob.r, dg_order=prob.p,
                    lattice=prob.lattice, sn_order=prob.sn_order, sigma_t=prob.sigma_t,
                    sigma_s=prob.sigma_s, q=prob.q, bc_kind=prob.bc_kind, psi_inc=prob.psi_inc,
                    weighting=prob.weighting if weighting is None else weighting,
                    exact_scc_max=prob.exact_scc_max if exact_scc_max is None else exact_scc_max,
-                   precision=precision, n_threads=n_threads, schedule=schedule)
+                   precision=precision, n_threads=n_threads, schedule=schedule,
+                   cache_inverse=cache_inverse)
 
     def close(self):
         if getattr(self, "handle", None):

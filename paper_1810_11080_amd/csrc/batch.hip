@@ -24,6 +24,7 @@ struct BatchGraph {
 
 struct BatchClass {
     SweepClass cls;
+    bool has_inv = false;              // every member keeps cached inverses
     int4* d_pairs = nullptr;
     int full_blocks = 0;
     double tuned_ms[3] = {0.0, 0.0, 0.0};
@@ -206,6 +207,7 @@ double time_class(snsw_batch* b, size_t ci, bool persistent, int blocks, int rep
     SweepClass c = b->classes[ci].cls;
     c.persistent = persistent;
     c.blocks = blocks;
+    c.inv = b->classes[ci].has_inv && (!persistent || persistent_uses_inverse(c.dim, c.p));
     SweepLaunch L = base_launch(b);
     L.any_persistent = true;
     L.phi_in_one = phi_in;
@@ -285,15 +287,15 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
         PersistArgs pa;
         pa.table = L.table;
         pa.pairs = c.pairs;
-        pa.ticket = L.tickets + c.ticket;
+        pa.ticket = L.tickets + (size_t)c.ticket * kTicketWords;
         pa.error = L.error;
         pa.total = c.level_off.back();
         pa.spin_limit = 1 << 20;
-        launch_sweep_persistent(c.dim, c.p, pa, c.blocks, s);
+        launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
     } else {
         for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
             const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
-            launch_sweep_level(c.dim, c.p, c.mixed, L.table, c.pairs, b, n, s);
+            launch_sweep_level(c.dim, c.p, c.mixed, c.inv, L.table, c.pairs, b, n, s);
         }
     }
     HIP_OK(hipGetLastError());
@@ -332,12 +334,13 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
         b->ctx = ctx;
         b->probs.assign(probs, probs + count);
         b->use_graph = o.use_graph != 0;
-        // classes by (dim, p, precision), in order of first appearance
-        std::map<std::tuple<int, int, int>, int> key;
+        // classes by (dim, p, precision, cached inverse), in order of first appearance
+        std::map<std::tuple<int, int, int, int>, int> key;
         b->entry_class.resize(count);
         for (int32_t k = 0; k < count; ++k) {
             const HostProblem& hp = probs[k]->hp;
-            const auto kk = std::make_tuple(hp.dim, hp.p, hp.precision);
+            const int has_inv = probs[k]->dev->ainv != nullptr ? 1 : 0;
+            const auto kk = std::make_tuple(hp.dim, hp.p, hp.precision, has_inv);
             auto it = key.find(kk);
             if (it == key.end()) {
                 it = key.emplace(kk, (int)b->classes.size()).first;
@@ -345,6 +348,7 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
                 bc.cls.dim = hp.dim;
                 bc.cls.p = hp.p;
                 bc.cls.mixed = hp.precision == SNSW_PREC_MIXED;
+                bc.has_inv = has_inv != 0;
                 bc.cls.ticket = (int)b->classes.size();
                 b->classes.push_back(bc);
             }
@@ -360,13 +364,15 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
             HIP_OK(hipMemcpyAsync(bc.d_pairs, pairs.data(), pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
             HIP_OK(hipStreamSynchronize(s));
             bc.cls.pairs = bc.d_pairs;
-            bc.full_blocks = persistent_grid(bc.cls.dim, bc.cls.p, bc.cls.level_off.back(), ctx->device);
-            bc.cls.blocks = bc.full_blocks;
             bc.cls.persistent = !bc.cls.mixed && o.schedule == SNSW_SCHED_PERSISTENT;
+            const bool pinv = bc.has_inv && persistent_uses_inverse(bc.cls.dim, bc.cls.p);
+            bc.full_blocks = persistent_grid(bc.cls.dim, bc.cls.p, pinv, bc.cls.level_off.back(), ctx->device);
+            bc.cls.blocks = bc.full_blocks;
+            bc.cls.inv = bc.has_inv && (!bc.cls.persistent || pinv);
         }
         HIP_OK(hipMalloc(&b->table, count * sizeof(SweepArgs)));
-        HIP_OK(hipMalloc(&b->tickets, b->classes.size() * sizeof(unsigned int)));
-        HIP_OK(hipMemsetAsync(b->tickets, 0, b->classes.size() * sizeof(unsigned int), s));
+        HIP_OK(hipMalloc(&b->tickets, b->classes.size() * kTicketWords * sizeof(unsigned int)));
+        HIP_OK(hipMemsetAsync(b->tickets, 0, b->classes.size() * kTicketWords * sizeof(unsigned int), s));
         HIP_OK(hipMalloc(&b->error, sizeof(int32_t)));
         HIP_OK(hipMemsetAsync(b->error, 0, sizeof(int32_t), s));
         HIP_OK(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
@@ -392,6 +398,7 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
                     const int best = (int)(std::min_element(bc.tuned_ms, bc.tuned_ms + 3) - bc.tuned_ms);
                     bc.cls.persistent = best != 0;
                     bc.cls.blocks = best == 2 ? half : bc.full_blocks;
+                    bc.cls.inv = bc.has_inv && (!bc.cls.persistent || persistent_uses_inverse(bc.cls.dim, bc.cls.p));
                 }
             } catch (...) {
                 (void)hipFree(phi_in);

@@ -39,6 +39,7 @@ struct SweepClass {
     int dim = 2, p = 1;
     bool mixed = false;
     bool persistent = false;
+    bool inv = false;                  // cached inverses (every member has them)
     int blocks = 0;                    // persistent grid
     int ticket = 0;                    // index into the ticket array
     const int4* pairs = nullptr;       // device schedule
@@ -78,6 +79,7 @@ struct DeviceProblem {
     unsigned long long* red = nullptr;   // residual scratch [2]
     unsigned int* ticket = nullptr;
     int32_t* error = nullptr;     // device-side wait failure flag
+    double* ainv = nullptr;       // [D][E][n][n] cached A^{-1} (column-major) or null
     SweepArgs* table = nullptr;   // this problem as a table of one
     int table_cur = 0;            // buffer index in table->psi_cur
     int cur = 0;                  // psi[cur] holds the latest sweep
@@ -116,6 +118,6 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
 void check_error_flag(int32_t* flag, hipStream_t s);
 
 DeviceProblem* need_device(snsw_problem* prob);
-int persistent_grid(int dim, int p, int64_t total, int device, double fraction = 1.0);
+int persistent_grid(int dim, int p, bool inv, int64_t total, int device, double fraction = 1.0);
 
 }  // namespace snsw

@@ -72,7 +72,8 @@ struct HostProblem {
     int n = 0, nf = 0, nslot = 0;
     int64_t E = 0, F = 0;
     int D = 0;
-    int weighting = 1, exact_max = 10, precision = 0, bc = 0, nthreads = 1, schedule = 0;
+    int weighting = 1, exact_max = 10, precision = 0, bc = 0, nthreads = 1, schedule = 0, cache_inverse = 0;
+    int inverse_cached = 0;   // set by the device upload
     double psi_inc = 0.0;
     std::vector<double> lattice;              // [L][dim]
     std::vector<double> omega, w;             // [D][3], [D]

@@ -30,6 +30,9 @@ constexpr int kWaves = 4;              // wavefronts per block
 constexpr int kDirMask = 1023;         // packed word: direction bits
 constexpr int kSlotShift = 10;         // then 3 bits per slot
 constexpr unsigned kOut = 0, kIn = 1, kKink = 2, kNone = 3;
+#ifndef SNSW_POLL_SLEEP
+#define SNSW_POLL_SLEEP 1   // s_sleep units (64 clocks) between dependency polls
+#endif
 
 template <int DIM, int P>
 struct Shape {
@@ -97,6 +100,7 @@ __device__ __forceinline__ SweepArgs load_args(const SweepArgs* table, int k) {
     a.D = c->D;
     a.dim = c->dim;
     a.persistent = c->persistent;
+    a.ainv = c->ainv;
     return a;
 }
 
@@ -324,6 +328,32 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(const SweepArgs*
 }
 
 
+// Striped tickets.  One global counter handing out one batch per atomic cost
+// about 12 ns per batch (the atomics on one address serialise) and bounded
+// the persistent sweeps.  Instead block b belongs to stream s = b mod
+// kStreams and takes batches s, s + kStreams, s + 2 kStreams, ... in
+// increasing order from the stream's own counter.  Deadlock-free: the
+// smallest unfinished batch depends only on smaller (earlier-level) batches,
+// which are finished; and it is either held by a wavefront of its stream
+// (which processes its batches in increasing order) or not yet handed out,
+// in which case every batch its stream has handed out is smaller, finished,
+// and the stream's wavefronts go on to take it.
+#ifndef SNSW_STREAMS
+#define SNSW_STREAMS 16
+#endif
+constexpr unsigned kStreams = SNSW_STREAMS;
+
+static_assert(kStreams >= 1 && kStreams <= kMaxStreams, "stream count");
+
+// Next batch index of this block's stream (one lane per wavefront).  A grid
+// smaller than kStreams uses one stream per block, so that every stream has
+// resident wavefronts.
+__device__ __forceinline__ unsigned take_batch(unsigned* counters) {
+    const unsigned S = gridDim.x < kStreams ? gridDim.x : kStreams;
+    const unsigned s = blockIdx.x % S;
+    return atomicAdd(counters + s * kTicketStride, 1u) * S + s;
+}
+
 // Bit pattern marking "not yet written in this sweep": a signalling NaN.
 // Arithmetic never produces a signalling NaN (IEEE quiets them), so no
 // computed flux can carry this pattern; only the fill kernel writes it.
@@ -359,13 +389,13 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
     // The next batch is claimed while the current one is processed, which
     // hides the atomic's latency.
     unsigned t_next = 0;
-    if (lane == 0) t_next = atomicAdd(pa.ticket, (unsigned)G);
+    if (lane == 0) t_next = take_batch(pa.ticket) * (unsigned)G;
     t_next = __shfl(t_next, 0);
     while (true) {
         const unsigned t0 = __builtin_amdgcn_readfirstlane(t_next);
         if ((int64_t)t0 >= pa.total) break;
         unsigned t_pre = 0;
-        if (lane == 0) t_pre = atomicAdd(pa.ticket, (unsigned)G);
+        if (lane == 0) t_pre = take_batch(pa.ticket) * (unsigned)G;
         const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0));
         const int64_t pidx = (int64_t)t0 + grp;
         int4 pr = make_int4(-1, 0, 0, 0);
@@ -532,7 +562,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 // deferred slots are parked in LDS (each face lane writes its own row), and
 // after the wait the face lanes form c = P_in psi_up, which is broadcast into
 // x += A^{-1}[:, tn_s] c.
-template <int DIM, int P>
+template <int DIM, int P, bool INV>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3, 8))) sweep_persistent_dpp(PersistArgs pa) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
@@ -548,13 +578,13 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
     // a smaller unfinished one in progress), and its upwind pairs are in
     // smaller, finished tickets.
     unsigned t_next = 0;
-    if (lane == 0) t_next = atomicAdd(pa.ticket, (unsigned)G);
+    if (lane == 0) t_next = take_batch(pa.ticket) * (unsigned)G;
     t_next = __shfl(t_next, 0);
     while (true) {
         const unsigned t0 = __builtin_amdgcn_readfirstlane(t_next);
         if ((int64_t)t0 >= pa.total) break;
         unsigned t_pre = 0;
-        if (lane == 0) t_pre = atomicAdd(pa.ticket, (unsigned)G);
+        if (lane == 0) t_pre = take_batch(pa.ticket) * (unsigned)G;
         const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0));
         const int64_t pidx = (int64_t)t0 + grp;
         int4 pr = make_int4(-1, 0, 0, 0);
@@ -568,7 +598,12 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         // element 0 and are masked (divergent branches here would keep two
         // copies of the row alive).
         double m[N];
-        {
+        if constexpr (INV) {
+            // row `row` of the cached A^{-1} (stored column-major)
+            const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
+#pragma unroll
+            for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+        } else {
             const double* Ge = args.geo + (size_t)e * (DIM + 1) * N * N + row;
             const double st = args.sigma_t[e];
             const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1];
@@ -623,8 +658,10 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
                     pin[b] = cls == kOut ? 0.0 : -vv;
                 }
             }
+            if constexpr (!INV) {
 #pragma unroll
-            for (int b = 0; b < NF; ++b) m[S::tn(s, b)] += pout[b];
+                for (int b = 0; b < NF; ++b) m[S::tn(s, b)] += pout[b];
+            }
             if (cls == kOut) continue;
             if (defer) {
 #pragma unroll
@@ -640,7 +677,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         }
 
         // ---- in-place Gauss-Jordan: m ends as row `row` of A^{-1}
-        static_for<0, N>([&](auto kc2) {
+        if constexpr (!INV) static_for<0, N>([&](auto kc2) {
             constexpr int k = decltype(kc2)::value;
             const bool piv = row == k;
             const double r = 1.0 / m[k];
@@ -738,10 +775,159 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
                 if (lane == 0) err = __hip_atomic_load(pa.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (__shfl(err, 0)) break;
             }
-            __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_s_sleep(SNSW_POLL_SLEEP);
         }
         t_next = __shfl(t_pre, 0);
     }
+}
+
+
+// ---- cached element inverses ------------------------------------------
+//
+// The element operator A = sigma_t M - sum_i Omega_i K_i + outflow blocks of
+// a pair does not change between source iterations, so it can be inverted
+// once and kept in HBM; a sweep then only assembles b and forms A^{-1} b.
+
+// Setup: for schedule entries [0, count) of one problem, assemble A and
+// invert it in place by Gauss-Jordan without pivoting (A + A^T is positive
+// definite), pivot rows broadcast through LDS; A^{-1} is stored
+// column-major at ainv[(d E + e) n^2 + j n + i].
+template <int DIM, int P>
+__global__ void __launch_bounds__(64 * kWaves) factor_kernel(const SweepArgs* table, const int4* pairs, int64_t count,
+                                                            double* ainv) {
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, G = S::G;
+    __shared__ double lds[kWaves][G][N + 1];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = lane / N, row = lane - grp * N;
+    const bool in_group = grp < G;
+    const int64_t wbase = ((int64_t)blockIdx.x * kWaves + wave) * G;
+    if (wbase >= count) return;   // LDS is per wavefront: no block barrier follows
+    const SweepArgs args = load_args(table, batch_problem(pairs, wbase));
+    int4 pr = make_int4(-1, 0, 0, 0);
+    if (in_group) pr = pairs[wbase + grp];
+    const bool active = pr.x >= 0;
+    const int4 prs = active ? pr : make_int4(0, 0, 0, 0);
+    double m[N];
+    double rhs;
+    unsigned kept;
+    int krow[2 * DIM];
+    assemble_row<DIM, P, true>(args, prs, row, m, rhs, kept, krow);
+    double* L = &lds[wave][in_group ? grp : 0][0];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        if (in_group && row == k) {
+            const double r = 1.0 / m[k];
+#pragma unroll
+            for (int j = 0; j < N; ++j) L[j] = (j == k) ? r : m[j] * r;
+        }
+        wave_sync();
+        if (in_group) {
+            if (row == k) {
+#pragma unroll
+                for (int j = 0; j < N; ++j) m[j] = L[j];
+            } else {
+                const double f = m[k];
+                m[k] = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) m[j] -= f * L[j];
+            }
+        }
+        wave_sync();
+    }
+    if (active) {
+        const int d = (int)((unsigned)pr.y & kDirMask);
+        double* dst = ainv + ((size_t)d * args.E + pr.x) * N * N + row;
+#pragma unroll
+        for (int j = 0; j < N; ++j) dst[j * N] = m[j];
+    }
+}
+
+// b of row `row` of pair pr: source plus every inflow term (kept couplings
+// read this sweep's flux, lagged ones the previous sweep's, boundary faces
+// psi_inc).
+template <int DIM, int P>
+__device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int row) {
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, NF = S::NF, NS = S::NS;
+    const int e = pr.x;
+    const unsigned packed = (unsigned)pr.y;
+    const int d = (int)(packed & kDirMask);
+    double rhs = args.src[(size_t)e * N + row];
+    const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1], o2 = args.omega[3 * d + 2];
+    int kc = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+        const bool lagged = (packed >> (kSlotShift + 3 * s + 2)) & 1u;
+        int kr = 0;
+        if (cls == kKink) kr = args.kink_idx[pr.z + kc++];
+        if (cls == kOut || cls == kNone) continue;
+        const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+        if (!on) continue;
+        const int la = S::local(row, s);
+        double pin[NF];
+        if (cls == kKink) {
+            const double* Ti = args.kink_tab + (size_t)kr * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + la * NF;
+#pragma unroll
+            for (int b = 0; b < NF; ++b) pin[b] = Ti[b];
+        } else {
+            const double* Bf = args.B + (size_t)args.slot_face[(size_t)e * NS + s] * DIM * NF * NF + la * NF;
+            const double sgn = (s & 1) ? -1.0 : 1.0;   // P_in = -(outward normal) moments
+#pragma unroll
+            for (int b = 0; b < NF; ++b) {
+                double v = o0 * Bf[b] + o1 * Bf[NF * NF + b];
+                if (DIM == 3) v += o2 * Bf[2 * NF * NF + b];
+                pin[b] = sgn * v;
+            }
+        }
+        const int nb = args.slot_nbr[(size_t)e * NS + s];
+        if (nb >= 0) {
+            const double* up = (lagged ? args.psi_prev : args.psi_cur) + ((size_t)d * args.E + nb) * N;
+#pragma unroll
+            for (int b = 0; b < NF; ++b) rhs += pin[b] * up[S::tn(s ^ 1, b)];
+        } else {
+#pragma unroll
+            for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
+        }
+    }
+    return rhs;
+}
+
+// One launch per level with cached inverses: b assembled per row, shared
+// through the wavefront's LDS, x = A^{-1} b.
+template <int DIM, int P>
+__global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* table, const int4* pairs,
+                                                              int64_t begin, int64_t count) {
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, G = S::G;
+    __shared__ double lds[kWaves][G][N + 1];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = lane / N, row = lane - grp * N;
+    const bool in_group = grp < G;
+    const int64_t wbase = begin + ((int64_t)blockIdx.x * kWaves + wave) * G;
+    if (wbase >= begin + count) return;   // LDS is per wavefront: no block barrier follows
+    const SweepArgs args = load_args(table, batch_problem(pairs, wbase));
+    int4 pr = make_int4(-1, 0, 0, 0);
+    if (in_group) pr = pairs[wbase + grp];
+    const bool active = pr.x >= 0;
+    const int4 prs = active ? pr : make_int4(0, 0, 0, 0);
+    const int e = prs.x;
+    const int d = (int)((unsigned)prs.y & kDirMask);
+    const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
+    double m[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+    const double b = inflow_rhs<DIM, P>(args, prs, row);
+    double* L = &lds[wave][in_group ? grp : 0][0];
+    if (in_group) L[row] = b;
+    wave_sync();
+    double x = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) x += m[j] * L[j];
+    if (active) args.psi_cur[((size_t)d * args.E + e) * N + row] = x;
 }
 
 __global__ void fill_sentinel_kernel(const SweepArgs* table) {
@@ -754,12 +940,15 @@ __global__ void fill_sentinel_kernel(const SweepArgs* table) {
 }
 
 template <int DIM, int P>
-void launch_tpl(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, bool mixed,
+void launch_tpl(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, bool mixed, bool inv,
                 hipStream_t stream) {
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
-    if (mixed)
+    if (inv)
+        hipLaunchKernelGGL((sweep_level_inv<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, table,
+                           pairs, begin, count);
+    else if (mixed)
         hipLaunchKernelGGL((sweep_level_fp64<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
                            table, pairs, begin, count);
     else
@@ -774,19 +963,35 @@ constexpr bool use_dpp() {
 }
 
 template <int DIM, int P>
-void launch_persist_tpl(const PersistArgs& a, int blocks, hipStream_t stream) {
-    if constexpr (use_dpp<DIM, P>())
-        hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, a);
-    else
+void launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, hipStream_t stream) {
+    if constexpr (use_dpp<DIM, P>()) {
+        if (inv)
+            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                               stream, a);
+        else
+            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                               stream, a);
+    } else {
         hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, a);
+    }
 }
 
 template <int DIM, int P>
-int occupancy_tpl() {
+void launch_factor_tpl(const SweepArgs* table, const int4* pairs, int64_t count, double* ainv, hipStream_t stream) {
+    constexpr int per_block = kWaves * Shape<DIM, P>::G;
+    const int64_t blocks = (count + per_block - 1) / per_block;
+    if (blocks == 0) return;
+    hipLaunchKernelGGL((factor_kernel<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, table, pairs,
+                       count, ainv);
+}
+
+template <int DIM, int P>
+int occupancy_tpl(bool inv) {
     int nb = 0;
     hipError_t rc;
     if constexpr (use_dpp<DIM, P>())
-        rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P>, 64 * kWaves, 0);
+        rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, true>, 64 * kWaves, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, false>, 64 * kWaves, 0);
     else
         rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P>, 64 * kWaves, 0);
     if (rc != hipSuccess) return 1;
@@ -803,9 +1008,9 @@ __global__ void source_kernel(SweepArgs* table, const double* const* phi_list, c
         double* t = a.psi_cur;
         a.psi_cur = a.psi_prev;
         a.psi_prev = t;
-        if (blockIdx.y == 0)
-            for (int k = 0; k < n_tickets; ++k) tickets[k] = 0u;
     }
+    if (blockIdx.x == 0 && blockIdx.y == 0)
+        for (int k = threadIdx.x; k < n_tickets * (int)kMaxStreams; k += blockDim.x) tickets[k * kTicketStride] = 0u;
     const int n = a.n;
     const int64_t E = a.E;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -864,16 +1069,29 @@ __global__ void residual_kernel(int64_t len, const double* __restrict__ a, const
 
 }  // namespace
 
-void launch_sweep_level(int dim, int p, bool mixed, const SweepArgs* table, const int4* pairs, int64_t begin,
-                        int64_t count, hipStream_t stream) {
+void launch_sweep_level(int dim, int p, bool mixed, bool inv, const SweepArgs* table, const int4* pairs,
+                        int64_t begin, int64_t count, hipStream_t stream) {
     if (dim == 2) {
-        if (p == 1) launch_tpl<2, 1>(table, pairs, begin, count, mixed, stream);
-        else if (p == 2) launch_tpl<2, 2>(table, pairs, begin, count, mixed, stream);
-        else launch_tpl<2, 3>(table, pairs, begin, count, mixed, stream);
+        if (p == 1) launch_tpl<2, 1>(table, pairs, begin, count, mixed, inv, stream);
+        else if (p == 2) launch_tpl<2, 2>(table, pairs, begin, count, mixed, inv, stream);
+        else launch_tpl<2, 3>(table, pairs, begin, count, mixed, inv, stream);
     } else {
-        if (p == 1) launch_tpl<3, 1>(table, pairs, begin, count, mixed, stream);
-        else if (p == 2) launch_tpl<3, 2>(table, pairs, begin, count, mixed, stream);
-        else launch_tpl<3, 3>(table, pairs, begin, count, mixed, stream);
+        if (p == 1) launch_tpl<3, 1>(table, pairs, begin, count, mixed, inv, stream);
+        else if (p == 2) launch_tpl<3, 2>(table, pairs, begin, count, mixed, inv, stream);
+        else launch_tpl<3, 3>(table, pairs, begin, count, mixed, inv, stream);
+    }
+}
+
+void launch_factor(int dim, int p, const SweepArgs* table, const int4* pairs, int64_t count, double* ainv,
+                   hipStream_t stream) {
+    if (dim == 2) {
+        if (p == 1) launch_factor_tpl<2, 1>(table, pairs, count, ainv, stream);
+        else if (p == 2) launch_factor_tpl<2, 2>(table, pairs, count, ainv, stream);
+        else launch_factor_tpl<2, 3>(table, pairs, count, ainv, stream);
+    } else {
+        if (p == 1) launch_factor_tpl<3, 1>(table, pairs, count, ainv, stream);
+        else if (p == 2) launch_factor_tpl<3, 2>(table, pairs, count, ainv, stream);
+        else launch_factor_tpl<3, 3>(table, pairs, count, ainv, stream);
     }
 }
 
@@ -890,21 +1108,27 @@ void launch_fill_sentinel(const SweepArgs* table, int count, int64_t max_DEn, hi
     hipLaunchKernelGGL(fill_sentinel_kernel, dim3((unsigned)blocks, (unsigned)count), dim3(256), 0, stream, table);
 }
 
-void launch_sweep_persistent(int dim, int p, const PersistArgs& a, int blocks, hipStream_t stream) {
+void launch_sweep_persistent(int dim, int p, bool inv, const PersistArgs& a, int blocks, hipStream_t stream) {
     if (dim == 2) {
-        if (p == 1) launch_persist_tpl<2, 1>(a, blocks, stream);
-        else if (p == 2) launch_persist_tpl<2, 2>(a, blocks, stream);
-        else launch_persist_tpl<2, 3>(a, blocks, stream);
+        if (p == 1) launch_persist_tpl<2, 1>(a, blocks, inv, stream);
+        else if (p == 2) launch_persist_tpl<2, 2>(a, blocks, inv, stream);
+        else launch_persist_tpl<2, 3>(a, blocks, inv, stream);
     } else {
-        if (p == 1) launch_persist_tpl<3, 1>(a, blocks, stream);
-        else if (p == 2) launch_persist_tpl<3, 2>(a, blocks, stream);
-        else launch_persist_tpl<3, 3>(a, blocks, stream);
+        if (p == 1) launch_persist_tpl<3, 1>(a, blocks, inv, stream);
+        else if (p == 2) launch_persist_tpl<3, 2>(a, blocks, inv, stream);
+        else launch_persist_tpl<3, 3>(a, blocks, inv, stream);
     }
 }
 
-int persistent_blocks_per_cu(int dim, int p) {
-    if (dim == 2) return p == 1 ? occupancy_tpl<2, 1>() : p == 2 ? occupancy_tpl<2, 2>() : occupancy_tpl<2, 3>();
-    return p == 1 ? occupancy_tpl<3, 1>() : p == 2 ? occupancy_tpl<3, 2>() : occupancy_tpl<3, 3>();
+int persistent_blocks_per_cu(int dim, int p, bool inv) {
+    if (dim == 2)
+        return p == 1 ? occupancy_tpl<2, 1>(inv) : p == 2 ? occupancy_tpl<2, 2>(inv) : occupancy_tpl<2, 3>(inv);
+    return p == 1 ? occupancy_tpl<3, 1>(inv) : p == 2 ? occupancy_tpl<3, 2>(inv) : occupancy_tpl<3, 3>(inv);
+}
+
+bool persistent_uses_inverse(int dim, int p) {
+    const int n = dim == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
+    return n == 4 || n == 16;
 }
 
 void launch_scalar_flux(const SweepArgs* table, int count, int64_t max_En, double* const* phi_list,

@@ -30,7 +30,14 @@ struct SweepArgs {
     int64_t E;
     int32_t n, D, dim;
     int32_t persistent;       // swept by a persistent kernel (needs the sentinel fill)
+    const double* ainv;       // [D][E][n][n] cached A^{-1} per pair, column-major (null: not cached)
 };
+
+// Persistent sweeps take batches from kStreams counters per schedule, each
+// kTicketStride words apart (separate cache lines).
+constexpr unsigned kTicketStride = 64;
+constexpr unsigned kMaxStreams = 64;
+constexpr unsigned kTicketWords = kMaxStreams * kTicketStride;   // per schedule
 
 // Schedule entry (int4): {element (-1 = padding), packed word, kink base,
 // problem index}.
@@ -41,23 +48,30 @@ struct SweepArgs {
 struct PersistArgs {
     const SweepArgs* table;
     const int4* pairs;
-    unsigned int* ticket;     // zeroed by the source kernel before each sweep
+    unsigned int* ticket;     // kMaxStreams counters, kTicketStride apart; zeroed by the source kernel
     int32_t* error;           // set to 1 when a dependency wait times out
     int64_t total;            // entries in the schedule
     int32_t spin_limit;       // polls per dependency wait before giving up
 };
 
-// Launches the persistent sweep kernel (all levels in one launch).
-void launch_sweep_persistent(int dim, int p, const PersistArgs& a, int blocks, hipStream_t stream);
+// Launches the persistent sweep kernel (all levels in one launch); inv: read
+// the cached inverses (only for n = 4 and 16, see persistent_uses_inverse).
+void launch_sweep_persistent(int dim, int p, bool inv, const PersistArgs& a, int blocks, hipStream_t stream);
 // Blocks per CU that the persistent kernel can keep resident.
-int persistent_blocks_per_cu(int dim, int p);
+int persistent_blocks_per_cu(int dim, int p, bool inv);
+// Whether the persistent kernel of this shape has a cached-inverse variant.
+bool persistent_uses_inverse(int dim, int p);
 // Launches the level-sweep kernel over schedule entries [begin, begin+count)
-// (begin and count multiples of G).
-void launch_sweep_level(int dim, int p, bool mixed, const SweepArgs* table, const int4* pairs, int64_t begin,
-                        int64_t count, hipStream_t stream);
+// (begin and count multiples of G); inv: x = A^{-1} b with cached inverses.
+void launch_sweep_level(int dim, int p, bool mixed, bool inv, const SweepArgs* table, const int4* pairs,
+                        int64_t begin, int64_t count, hipStream_t stream);
+// Computes and stores A^{-1} of schedule entries [0, count) of one problem.
+void launch_factor(int dim, int p, const SweepArgs* table, const int4* pairs, int64_t count, double* ainv,
+                   hipStream_t stream);
 
 // Start of a sweep, for problems [0, count) of the table: swaps psi_cur and
-// psi_prev of each entry, zeroes tickets[0, n_tickets), and computes
+// psi_prev of each entry, zeroes the ticket counters of n_tickets schedules
+// (kTicketWords words each), and computes
 // src[e][i] = sum_j M_e[i][j] (q[e][j] + sigma_s[e]/(4 pi) phi_in[e][j]).
 // phi_in of problem k is phi_list[k], or phi_one when phi_list is null.
 void launch_source(SweepArgs* table, int count, int64_t max_En, const double* const* phi_list,

@@ -120,6 +120,12 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
         if (hp.schedule == SNSW_SCHED_AUTO)
             hp.schedule = (hp.dim == 2 && hp.p != 2 && desc->precision == SNSW_PREC_FP64) ? SNSW_SCHED_PERSISTENT
                                                                                       : SNSW_SCHED_LEVELS;
+        hp.cache_inverse = desc->cache_inverse;
+        if (hp.cache_inverse != SNSW_CACHE_AUTO && hp.cache_inverse != SNSW_CACHE_ON &&
+            hp.cache_inverse != SNSW_CACHE_OFF)
+            throw Error(SNSW_E_INVALID_ARG, "cache_inverse must be AUTO, ON or OFF");
+        if (hp.cache_inverse == SNSW_CACHE_ON && desc->precision == SNSW_PREC_MIXED)
+            throw Error(SNSW_E_UNSUPPORTED, "cached inverses are FP64 only");
         if (desc->precision == SNSW_PREC_MIXED && hp.schedule == SNSW_SCHED_PERSISTENT)
             throw Error(SNSW_E_UNSUPPORTED, "mixed precision runs on the LEVELS schedule");
         hp.bc = desc->bc_kind;
@@ -202,6 +208,8 @@ int snsw_problem_get_info(const snsw_problem* prob, snsw_problem_info* info) {
         }
         info->n_kink_faces_total = hp.n_kinks;
         info->setup_seconds = hp.setup_seconds;
+        info->cached_inverse = hp.inverse_cached;
+        info->schedule = hp.schedule;
     });
 }
 

@@ -141,6 +141,7 @@ SweepArgs make_args(const snsw_problem* prob, int cur) {
     a.D = hp.D;
     a.dim = hp.dim;
     a.persistent = 0;
+    a.ainv = dp->ainv;
     return a;
 }
 
@@ -165,18 +166,18 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             PersistArgs pa;
             pa.table = L.table;
             pa.pairs = c.pairs;
-            pa.ticket = L.tickets + c.ticket;
+            pa.ticket = L.tickets + (size_t)c.ticket * kTicketWords;
             pa.error = L.error;
             pa.total = c.level_off.back();
             pa.spin_limit = 1 << 20;
             if (prof) prof->begin(s);
-            launch_sweep_persistent(c.dim, c.p, pa, c.blocks, s);
+            launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
             if (prof) prof->end(s);
         } else {
             for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
                 const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
                 if (prof) prof->begin(s);
-                launch_sweep_level(c.dim, c.p, c.mixed, L.table, c.pairs, b, n, s);
+                launch_sweep_level(c.dim, c.p, c.mixed, c.inv, L.table, c.pairs, b, n, s);
                 if (prof) prof->end(s);
             }
         }
@@ -197,10 +198,10 @@ void check_error_flag(int32_t* flag, hipStream_t s) {
     }
 }
 
-int persistent_grid(int dim, int p, int64_t total, int device, double fraction) {
+int persistent_grid(int dim, int p, bool inv, int64_t total, int device, double fraction) {
     int cus = 0;
     HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-    const int per_cu = persistent_blocks_per_cu(dim, p);
+    const int per_cu = persistent_blocks_per_cu(dim, p, inv);
     const int n = dim == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
     const int64_t per_block = 4 * (64 / n);
     const int64_t need = (total + per_block - 1) / per_block;
@@ -263,20 +264,33 @@ void device_upload(snsw_problem* prob) {
         HIP_OK(hipMemsetAsync(dp->psi[b], 0, sizeof(double) * hp.D * hp.E * n, s));
     }
     dp->red = dalloc<unsigned long long>(dp, 2);
-    dp->ticket = dalloc<unsigned int>(dp, 1);
-    HIP_OK(hipMemsetAsync(dp->ticket, 0, sizeof(unsigned int), s));
+    dp->ticket = dalloc<unsigned int>(dp, kTicketWords);
+    HIP_OK(hipMemsetAsync(dp->ticket, 0, sizeof(unsigned int) * kTicketWords, s));
     dp->error = dalloc<int32_t>(dp, 1);
     HIP_OK(hipMemsetAsync(dp->error, 0, sizeof(int32_t), s));
+    // cached inverses: D*E*n^2 doubles
+    {
+        const size_t need = sizeof(double) * (size_t)hp.D * hp.E * n * n;
+        bool cache = false;
+        if (hp.precision == SNSW_PREC_FP64 && hp.cache_inverse != SNSW_CACHE_OFF) {
+            size_t free_b = 0, total_b = 0;
+            HIP_OK(hipMemGetInfo(&free_b, &total_b));
+            cache = hp.cache_inverse == SNSW_CACHE_ON || need <= free_b / 2;
+        }
+        if (cache) dp->ainv = dalloc<double>(dp, (size_t)hp.D * hp.E * n * n);
+        hp.inverse_cached = cache ? 1 : 0;
+    }
     SweepClass& c = dp->cls;
     c.dim = hp.dim;
     c.p = hp.p;
     c.mixed = hp.precision == SNSW_PREC_MIXED;
     c.persistent = hp.schedule == SNSW_SCHED_PERSISTENT;
+    c.inv = dp->ainv != nullptr && (!c.persistent || persistent_uses_inverse(hp.dim, hp.p));
     c.ticket = 0;
     c.pairs = dp->pairs;
     c.level_off = hp.level_off;
     c.members = {0};
-    c.blocks = persistent_grid(hp.dim, hp.p, hp.level_off.back(), dp->device);
+    c.blocks = persistent_grid(hp.dim, hp.p, c.inv, hp.level_off.back(), dp->device);
     {
         dp->cur = 0;
         dp->table_cur = 0;
@@ -284,6 +298,10 @@ void device_upload(snsw_problem* prob) {
         a.persistent = c.persistent ? 1 : 0;
         dp->table = dalloc<SweepArgs>(dp, 1);
         HIP_OK(hipMemcpyAsync(dp->table, &a, sizeof(a), hipMemcpyHostToDevice, s));
+    }
+    if (dp->ainv) {
+        launch_factor(hp.dim, hp.p, dp->table, dp->pairs, hp.level_off.back(), dp->ainv, s);
+        HIP_OK(hipGetLastError());
     }
     HIP_OK(hipStreamSynchronize(s));
 }
@@ -298,7 +316,7 @@ void device_release(snsw_problem* prob) noexcept {
     dp->prof.release();
     void* ptrs[] = {dp->geo, dp->B, dp->kink_tab, dp->kink_idx, dp->pairs, dp->slot_face, dp->slot_nbr,
                     dp->sigma_t, dp->sigma_s, dp->q, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
-                    dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table};
+                    dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table, dp->ainv};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);

@@ -84,12 +84,16 @@ SMALL = {
 }
 
 
+@pytest.mark.parametrize("cache", [1, 2], ids=["inverse", "assembled"])
 @pytest.mark.parametrize("schedule", [1, 2], ids=["persistent", "levels"])
 @pytest.mark.parametrize("case", sorted(SMALL))
-def test_sweeps_match_oracle(torch, ctx, case, schedule):
+def test_sweeps_match_oracle(torch, ctx, case, schedule, cache):
+    """Three sweeps per schedule, with the element inverses cached at setup
+    or assembled and factored in every sweep."""
     from paper_1810_11080_amd import Problem
     wp = SMALL[case]()
-    P = Problem.from_workload(ctx, wp, schedule=schedule)
+    P = Problem.from_workload(ctx, wp, schedule=schedule, cache_inverse=cache)
+    assert P.info()["cached_inverse"] == (1 if cache == 1 else 0)
     g_phi, g_psi = gpu_sweeps(torch, P, 3)
     P.synchronize()
     o_phi, o_psi, _, _ = oracle_sweeps(wp, 3)
@@ -135,13 +139,14 @@ def c2_oracle():
     return wp, phi0, psi0, o_phi[0], o_psi[0]
 
 
+@pytest.mark.parametrize("cache", [1, 2], ids=["inverse", "assembled"])
 @pytest.mark.parametrize("schedule", [1, 2], ids=["persistent", "levels"])
-def test_c2_full_one_sweep(torch, ctx, c2_oracle, schedule):
+def test_c2_full_one_sweep(torch, ctx, c2_oracle, schedule, cache):
     """128x128 Q3 p=3 S8 (cyclic graphs), one sweep from seeded scalar flux
     and seeded lagged angular flux, against the oracle."""
     from paper_1810_11080_amd import Problem
     wp, phi0, psi0, o_phi, o_psi = c2_oracle
-    P = Problem.from_workload(ctx, wp, schedule=schedule)
+    P = Problem.from_workload(ctx, wp, schedule=schedule, cache_inverse=cache)
     assert P.info()["n_removed_total"] > 0
     P.state_load(state_bytes(wp, psi0))
     g_phi, g_psi = gpu_sweeps(torch, P, 1, phi0)
@@ -212,6 +217,7 @@ def test_c3_full_sampled_directions(torch, ctx):
     from paper_1810_11080_amd import Problem
     wp = W.c3()
     P = Problem.from_workload(ctx, wp)
+    assert P.info()["cached_inverse"] == 1
     rng = np.random.default_rng(11)
     phi0 = rng.uniform(0.0, 2.0, (P.E, P.n))
     psi0 = rng.uniform(0.0, 0.2, (P.D, P.E, P.n))
