@@ -72,9 +72,7 @@ extern "C" {
  * (element, direction) pairs in level order and wait only for the upwind
  * values they read (latency-bound sweeps: 2D).  LEVELS: one launch per level
  * (throughput-bound sweeps: 3D).  AUTO picks PERSISTENT for 2D p = 1 or 3
- * in FP64 and LEVELS otherwise; SNSW_PREC_MIXED requires LEVELS.  With a
- * cached inverse the persistent kernel for n = 9, 27 or 64 still
- * assembles and factors per sweep.                                          */
+ * in FP64 and LEVELS otherwise; SNSW_PREC_MIXED requires LEVELS.          */
 #define SNSW_SCHED_AUTO        0
 #define SNSW_SCHED_PERSISTENT  1
 #define SNSW_SCHED_LEVELS      2

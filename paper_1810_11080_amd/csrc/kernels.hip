@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         // kept inflow straight into this lane's entry of b; values written
         // by other lanes of the upwind wavefront may lag the first node, so
-        // each is re-read until it is not the sentinel (bounded likewise)
+        // any that still holds the sentinel is re-read (bounded likewise)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
@@ -490,13 +490,21 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
                 prow = args.B + (size_t)args.slot_face[(size_t)e * NS + s] * DIM * NF * NF + la * NF;
                 scale = (s & 1) ? -1.0 : 1.0;   // P_in = -(outward) normal moments
             }
+            double vals[NF];
+#pragma unroll
+            for (int b = 0; b < NF; ++b)
+                vals[b] = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
             for (int b = 0; b < NF; ++b) {
-                double val = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                for (int spin = 0; (unsigned long long)__double_as_longlong(val) == sent && spin < pa.spin_limit; ++spin) {
+                for (int spin = 0;
+                     (unsigned long long)__double_as_longlong(vals[b]) == sent && spin < pa.spin_limit; ++spin) {
                     __builtin_amdgcn_s_sleep(1);
-                    val = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    vals[b] = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
+            }
+#pragma unroll
+            for (int b = 0; b < NF; ++b) {
+                const double val = vals[b];
                 double pv;
                 if (cls == kKink) {
                     pv = prow[b];
@@ -847,8 +855,8 @@ __global__ void __launch_bounds__(64 * kWaves) factor_kernel(const SweepArgs* ta
 // b of row `row` of pair pr: source plus every inflow term (kept couplings
 // read this sweep's flux, lagged ones the previous sweep's, boundary faces
 // psi_inc).
-template <int DIM, int P>
-__device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int row) {
+template <int DIM, int P, bool DEFER = false>
+__device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int row, unsigned* kept_out = nullptr) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, NF = S::NF, NS = S::NS;
     const int e = pr.x;
@@ -857,6 +865,7 @@ __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int
     double rhs = args.src[(size_t)e * N + row];
     const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1], o2 = args.omega[3 * d + 2];
     int kc = 0;
+    unsigned kept = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
@@ -864,6 +873,10 @@ __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int
         int kr = 0;
         if (cls == kKink) kr = args.kink_idx[pr.z + kc++];
         if (cls == kOut || cls == kNone) continue;
+        if (DEFER && !lagged && args.slot_nbr[(size_t)e * NS + s] >= 0) {
+            kept |= 1u << s;   // read from this sweep's flux after the wait
+            continue;
+        }
         const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
         if (!on) continue;
         const int la = S::local(row, s);
@@ -892,6 +905,7 @@ __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int
             for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
         }
     }
+    if (kept_out) *kept_out = kept;
     return rhs;
 }
 
@@ -928,6 +942,143 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
 #pragma unroll
     for (int j = 0; j < N; ++j) x += m[j] * L[j];
     if (active) args.psi_cur[((size_t)d * args.E + e) * N + row] = x;
+}
+
+
+// Persistent sweep with cached inverses for the LDS shapes (n = 8, 9, 27,
+// 64): the ticket and wait protocol of sweep_persistent_fp64; per pair the
+// row of A^{-1} is loaded and b assembled without the kept inflow before the
+// wait; after it the face lanes add the kept inflow and x = A^{-1} b is one
+// LDS exchange of b.
+template <int DIM, int P>
+__global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs pa) {
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
+    __shared__ double lds[kWaves][G][N + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / N, row = lane - grp * N;
+    const bool in_group = grp < G;
+    double* L = &lds[wave][in_group ? grp : 0][0];
+    const unsigned long long sent = kSentinel;
+
+    unsigned t_next = 0;
+    if (lane == 0) t_next = take_batch(pa.ticket) * (unsigned)G;
+    t_next = __shfl(t_next, 0);
+    while (true) {
+        const unsigned t0 = __builtin_amdgcn_readfirstlane(t_next);
+        if ((int64_t)t0 >= pa.total) break;
+        unsigned t_pre = 0;
+        if (lane == 0) t_pre = take_batch(pa.ticket) * (unsigned)G;
+        const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0));
+        const int64_t pidx = (int64_t)t0 + grp;
+        int4 pr = make_int4(-1, 0, 0, 0);
+        if (in_group && pidx < pa.total) pr = pa.pairs[pidx];
+        const bool active = pr.x >= 0;    // padding entries have e = -1
+        const int4 prs = active ? pr : make_int4(0, 0, 0, 0);
+        const int e = prs.x;
+        const unsigned packed = (unsigned)prs.y;
+        const int d = (int)(packed & kDirMask);
+        const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
+        double m[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+        unsigned kept = 0;
+        double rhs = inflow_rhs<DIM, P, true>(args, prs, row, &kept);
+        if (!active) kept = 0;
+
+        // wait: the lane on the first node of each kept face polls the
+        // upwind value there (bounded, as in sweep_persistent_fp64)
+        bool need[NS];
+        bool ok = true;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            need[s] = row == S::tn(s, 0) && ((kept >> s) & 1u);
+            if (need[s]) ok = false;
+        }
+        int polls = 0;
+        while (true) {
+            if (!ok) {
+                bool all = true;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (!need[s]) continue;
+                    const int nb = args.slot_nbr[(size_t)e * NS + s];
+                    double* ad = args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, 0);
+                    const double val = __hip_atomic_load(ad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((unsigned long long)__double_as_longlong(val) == sent) all = false;
+                    else need[s] = false;
+                }
+                ok = all;
+            }
+            if (__all(ok)) break;
+            if (++polls > pa.spin_limit) {
+                if (!ok) atomicExch(pa.error, 1);
+                break;
+            }
+            if ((polls & 255) == 0) {
+                int err = 0;
+                if (lane == 0) err = __hip_atomic_load(pa.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__shfl(err, 0)) break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        // kept inflow into this lane's entry of b
+        {
+            const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1], o2 = args.omega[3 * d + 2];
+            int kc = 0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+                int kr = 0;
+                if (cls == kKink) kr = args.kink_idx[prs.z + kc++];
+                const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+                if (!(on && ((kept >> s) & 1u))) continue;
+                const int la = S::local(row, s);
+                const int nb = args.slot_nbr[(size_t)e * NS + s];
+                double* up = args.psi_cur + ((size_t)d * args.E + nb) * N;
+                // all values of the face in flight together, then re-read
+                // any that still hold the sentinel
+                double val[NF];
+#pragma unroll
+                for (int b = 0; b < NF; ++b)
+                    val[b] = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int b = 0; b < NF; ++b) {
+                    for (int spin = 0;
+                         (unsigned long long)__double_as_longlong(val[b]) == sent && spin < pa.spin_limit; ++spin) {
+                        __builtin_amdgcn_s_sleep(1);
+                        val[b] = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < NF; ++b) {
+                    double pv;
+                    if (cls == kKink) {
+                        pv = args.kink_tab[(size_t)kr * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + la * NF + b];
+                    } else {
+                        const double* Bf =
+                            args.B + (size_t)args.slot_face[(size_t)e * NS + s] * DIM * NF * NF + la * NF;
+                        pv = o0 * Bf[b] + o1 * Bf[NF * NF + b];
+                        if (DIM == 3) pv += o2 * Bf[2 * NF * NF + b];
+                        pv *= (s & 1) ? -1.0 : 1.0;
+                    }
+                    rhs += pv * val[b];
+                }
+            }
+        }
+        // x = A^{-1} b
+        if (in_group) L[row] = rhs;
+        wave_sync();
+        double x = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) x += m[j] * L[j];
+        wave_sync();
+        if (active)
+            __hip_atomic_store(args.psi_cur + ((size_t)d * args.E + e) * N + row, x, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        t_next = __shfl(t_pre, 0);
+    }
 }
 
 __global__ void fill_sentinel_kernel(const SweepArgs* table) {
@@ -972,7 +1123,12 @@ void launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, hipStream_t 
             hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
                                stream, a);
     } else {
-        hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, a);
+        if (inv)
+            hipLaunchKernelGGL((sweep_persistent_inv<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
+                               a);
+        else
+            hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                               stream, a);
     }
 }
 
@@ -993,7 +1149,8 @@ int occupancy_tpl(bool inv) {
         rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, true>, 64 * kWaves, 0)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, false>, 64 * kWaves, 0);
     else
-        rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P>, 64 * kWaves, 0);
+        rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_inv<DIM, P>, 64 * kWaves, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P>, 64 * kWaves, 0);
     if (rc != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
@@ -1127,8 +1284,9 @@ int persistent_blocks_per_cu(int dim, int p, bool inv) {
 }
 
 bool persistent_uses_inverse(int dim, int p) {
-    const int n = dim == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
-    return n == 4 || n == 16;
+    (void)dim;
+    (void)p;
+    return true;
 }
 
 void launch_scalar_flux(const SweepArgs* table, int count, int64_t max_En, double* const* phi_list,

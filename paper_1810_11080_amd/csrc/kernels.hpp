@@ -55,7 +55,7 @@ struct PersistArgs {
 };
 
 // Launches the persistent sweep kernel (all levels in one launch); inv: read
-// the cached inverses (only for n = 4 and 16, see persistent_uses_inverse).
+// the cached inverses.
 void launch_sweep_persistent(int dim, int p, bool inv, const PersistArgs& a, int blocks, hipStream_t stream);
 // Blocks per CU that the persistent kernel can keep resident.
 int persistent_blocks_per_cu(int dim, int p, bool inv);
