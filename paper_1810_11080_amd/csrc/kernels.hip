@@ -931,16 +931,33 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     const int e = prs.x;
     const int d = (int)((unsigned)prs.y & kDirMask);
     const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
-    double m[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
-    const double b = inflow_rhs<DIM, P>(args, prs, row);
     double* L = &lds[wave][in_group ? grp : 0][0];
-    if (in_group) L[row] = b;
-    wave_sync();
     double x = 0.0;
+    if constexpr (N > 16) {
+        // large elements: b first, then A^{-1} streamed in column chunks
+        // (fewer registers, more wavefronts in flight)
+        const double b = inflow_rhs<DIM, P>(args, prs, row);
+        if (in_group) L[row] = b;
+        wave_sync();
+        __builtin_amdgcn_sched_barrier(0);
+        constexpr int CH = 9;
 #pragma unroll
-    for (int j = 0; j < N; ++j) x += m[j] * L[j];
+        for (int j0 = 0; j0 < N; j0 += CH) {
+#pragma unroll
+            for (int j = j0; j < j0 + CH && j < N; ++j) x += Ai[j * N] * L[j];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+        // the row of A^{-1} is loaded while b is assembled
+        double m[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+        const double b = inflow_rhs<DIM, P>(args, prs, row);
+        if (in_group) L[row] = b;
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < N; ++j) x += m[j] * L[j];
+    }
     if (active) args.psi_cur[((size_t)d * args.E + e) * N + row] = x;
 }
 
