@@ -154,6 +154,10 @@ typedef struct {
     double  setup_seconds;       /* host setup wall time                     */
     int32_t cached_inverse;      /* 1 if A^{-1} per pair is kept on device   */
     int32_t schedule;            /* resolved SNSW_SCHED_PERSISTENT / LEVELS  */
+    int32_t tile;                /* T > 0: the persistent sweep takes T x T
+                                    tiles of elements of one direction per
+                                    wavefront (2D, p = 1 or 3); 0: single
+                                    pairs                                    */
 } snsw_problem_info;
 int snsw_problem_get_info(const snsw_problem* prob, snsw_problem_info* info);
 

@@ -38,7 +38,7 @@ class SnswProblemInfo(C.Structure):
                 ("n_dirs", C.c_int64), ("n_levels_total", C.c_int64), ("n_pairs", C.c_int64),
                 ("n_edges_total", C.c_int64), ("n_removed_total", C.c_int64),
                 ("n_kink_faces_total", C.c_int64), ("setup_seconds", C.c_double),
-                ("cached_inverse", C.c_int32), ("schedule", C.c_int32)]
+                ("cached_inverse", C.c_int32), ("schedule", C.c_int32), ("tile", C.c_int32)]
 
 
 class SnswGraphStats(C.Structure):

@@ -43,6 +43,7 @@ struct SweepClass {
     int blocks = 0;                    // persistent grid
     int ticket = 0;                    // index into the ticket array
     const int4* pairs = nullptr;       // device schedule
+    const int32_t* intra = nullptr;    // tiled schedule: intra-tile dependency words
     std::vector<int64_t> level_off;    // [L+1] offsets into pairs
     std::vector<int> members;          // table indices of its problems
 };
@@ -66,6 +67,8 @@ struct DeviceProblem {
     double* kink_tab = nullptr;   // [K][2][nf][nf]
     int32_t* kink_idx = nullptr;
     int4* pairs = nullptr;
+    int4* tpairs = nullptr;       // tiled schedule (or null)
+    int32_t* tintra = nullptr;
     int32_t* slot_face = nullptr;
     int32_t* slot_nbr = nullptr;
     double* sigma_t = nullptr;

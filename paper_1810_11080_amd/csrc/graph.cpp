@@ -17,6 +17,7 @@
 // repeatedly, else the vertex of largest w_out - w_in, smallest id on ties).
 // Levels: ASAP levels of the graph without the lagged edges.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -512,6 +513,118 @@ void build_schedule(HostProblem& hp) {
                 throw Error(SNSW_E_STATE, "schedule: a kept upwind pair does not precede its dependant");
         }
     }
+}
+
+
+bool build_tiled_schedule(HostProblem& hp, int T) {
+    hp.tile = 0;
+    hp.tlevel_off.clear();
+    hp.tpairs.clear();
+    hp.tintra.clear();
+    if (hp.dim != 2 || T < 1 || T * T != std::max(1, 64 / hp.n)) return false;
+    const int64_t E = hp.E;
+    const int D = hp.D, ns = hp.nslot;
+    const int nx = hp.nx[0], ny = hp.nx[1];
+    const int tx = (nx + T - 1) / T, ty = (ny + T - 1) / T;
+    const int64_t NT = (int64_t)tx * ty;
+    const int G = T * T;
+    auto tile_of = [&](int64_t e) { return (int64_t)((e % nx) / T) + (int64_t)tx * ((e / nx) / T); };
+    auto group_of = [&](int64_t e) { return (int)((e % nx) % T) + T * (int)((e / nx) % T); };
+    // entry of every (d, e) in the level schedule
+    std::vector<int64_t> where((size_t)D * E, -1);
+    const int64_t P = hp.level_off.back();
+    for (int64_t t = 0; t < P; ++t) {
+        const int32_t* pr = &hp.pairs[(size_t)t * 4];
+        if (pr[0] >= 0) where[(size_t)((uint32_t)pr[1] & ((1u << kDirBits) - 1)) * E + pr[0]] = t;
+    }
+    auto kept_up = [&](const int32_t* pr, int s) -> int32_t {
+        const uint32_t bits = (uint32_t)pr[1] >> (kDirBits + 3 * s);
+        const uint32_t cls = bits & 3u;
+        const bool lagged = (bits >> 2) & 1u;
+        if ((cls != SC_IN && cls != SC_KINK) || lagged) return -1;
+        return hp.slot_nbr[(size_t)pr[0] * ns + s];
+    };
+    // tile levels per direction (ASAP in the contracted kept graph)
+    std::vector<std::vector<int32_t>> tlev(D);
+    std::atomic<bool> cyclic{false};
+    parallel_for(D, hp.nthreads, [&](int64_t d0, int64_t d1) {
+        for (int64_t d = d0; d < d1 && !cyclic; ++d) {
+            std::vector<std::vector<int32_t>> adj(NT);
+            std::vector<int32_t> indeg(NT, 0);
+            for (int64_t e = 0; e < E; ++e) {
+                const int32_t* pr = &hp.pairs[(size_t)where[(size_t)d * E + e] * 4];
+                for (int s = 0; s < ns; ++s) {
+                    const int32_t up = kept_up(pr, s);
+                    if (up < 0) continue;
+                    const int64_t a = tile_of(up), b = tile_of(e);
+                    if (a != b) adj[a].push_back((int32_t)b);
+                }
+            }
+            for (auto& v : adj) {
+                std::sort(v.begin(), v.end());
+                v.erase(std::unique(v.begin(), v.end()), v.end());
+                for (int32_t b : v) ++indeg[b];
+            }
+            std::vector<int32_t>& lev = tlev[d];
+            lev.assign(NT, 0);
+            std::vector<int32_t> queue;
+            for (int64_t t = 0; t < NT; ++t)
+                if (indeg[t] == 0) queue.push_back((int32_t)t);
+            for (size_t h = 0; h < queue.size(); ++h) {
+                const int32_t t = queue[h];
+                for (int32_t b : adj[t]) {
+                    lev[b] = std::max(lev[b], lev[t] + 1);
+                    if (--indeg[b] == 0) queue.push_back(b);
+                }
+            }
+            if ((int64_t)queue.size() != NT) cyclic = true;
+        }
+    });
+    if (cyclic) return false;
+    int32_t Lt = 0;
+    for (int d = 0; d < D; ++d)
+        for (int32_t l : tlev[d]) Lt = std::max(Lt, l + 1);
+    std::vector<int64_t> count(Lt + 1, 0);
+    for (int d = 0; d < D; ++d)
+        for (int32_t l : tlev[d]) ++count[l + 1];
+    hp.tlevel_off.assign(Lt + 1, 0);
+    for (int32_t l = 0; l < Lt; ++l) hp.tlevel_off[l + 1] = hp.tlevel_off[l] + count[l + 1] * G;
+    const int64_t PT = hp.tlevel_off[Lt];
+    hp.tpairs.assign((size_t)PT * 4, 0);
+    hp.tintra.assign((size_t)PT, 0);
+    for (int64_t t = 0; t < PT; ++t) hp.tpairs[(size_t)t * 4] = -1;
+    // batches: level by level, direction by direction, tile by tile
+    std::vector<int64_t> pos(hp.tlevel_off.begin(), hp.tlevel_off.end() - 1);
+    std::vector<int64_t> batch_of((size_t)D * NT, -1);
+    for (int d = 0; d < D; ++d)
+        for (int64_t t = 0; t < NT; ++t) {
+            batch_of[(size_t)d * NT + t] = pos[tlev[d][t]];
+            pos[tlev[d][t]] += G;
+        }
+    for (int d = 0; d < D; ++d)
+        for (int64_t e = 0; e < E; ++e) {
+            const int64_t src = where[(size_t)d * E + e];
+            const int64_t tt = tile_of(e);
+            const int64_t dst = batch_of[(size_t)d * NT + tt] + group_of(e);
+            const int32_t* pr = &hp.pairs[(size_t)src * 4];
+            int32_t* out = &hp.tpairs[(size_t)dst * 4];
+            out[0] = pr[0];
+            out[1] = pr[1];
+            out[2] = pr[2];
+            out[3] = 0;
+            uint32_t intra = 0;
+            for (int s = 0; s < ns; ++s) {
+                const int32_t up = kept_up(pr, s);
+                if (up < 0) continue;
+                if (tile_of(up) == tt)
+                    intra |= (1u << s) | ((uint32_t)group_of(up) << (kIntraGroupShift + 4 * s));
+                else if (batch_of[(size_t)d * NT + tile_of(up)] >= batch_of[(size_t)d * NT + tt])
+                    throw Error(SNSW_E_STATE, "tiled schedule: an upwind tile does not precede its dependant");
+            }
+            hp.tintra[(size_t)dst] = (int32_t)intra;
+        }
+    hp.tile = T;
+    return true;
 }
 
 }  // namespace snsw

@@ -93,6 +93,12 @@ struct HostProblem {
     std::vector<int64_t> level_off;           // [L+1]
     std::vector<int32_t> pairs;               // [P][4]: e, packed, kink_base, 0
     std::vector<int32_t> kink_idx;            // per pair kink slots -> kink rows
+    // tiled schedule (2D, persistent kernels with G = T*T groups): a batch is
+    // one T x T tile of elements for one direction; empty when not built
+    int tile = 0;                             // T, 0 = no tiled schedule
+    std::vector<int64_t> tlevel_off;          // [Lt+1]
+    std::vector<int32_t> tpairs;              // [Pt][4] as pairs
+    std::vector<int32_t> tintra;              // [Pt] intra-tile dependency word
     std::vector<double> kink_tab;             // [K][2][nf][nf]
     int64_t n_kinks = 0;
     double setup_seconds = 0.0;
@@ -109,6 +115,14 @@ uint8_t face_integrals(const HostProblem& hp, int64_t f, const double* om, doubl
 // graph.cpp: per-direction graph, FAS and levels; combined schedule
 void build_graphs(HostProblem& hp);
 void build_schedule(HostProblem& hp);
+// Tiled schedule with T x T tiles (T*T = 64/n); returns false (and leaves it
+// empty) when the contracted tile graph of some direction has a cycle.
+bool build_tiled_schedule(HostProblem& hp, int T);
+
+// Intra-tile dependency word of a tiled schedule entry: bit s set when slot
+// s reads a kept upwind pair of the same tile, whose group index is in bits
+// [8 + 4s, 12 + 4s).
+constexpr int kIntraGroupShift = 8;
 
 // Packed pair word: bits 0..9 direction, then per slot s 3 bits at 10+3s:
 // class (2 bits, SlotClass) and lag flag (bit 2).  The lag flag is also set

@@ -30,6 +30,7 @@ constexpr int kWaves = 4;              // wavefronts per block
 constexpr int kDirMask = 1023;         // packed word: direction bits
 constexpr int kSlotShift = 10;         // then 3 bits per slot
 constexpr unsigned kOut = 0, kIn = 1, kKink = 2, kNone = 3;
+constexpr int kIntraGroupShiftDev = 8;   // intra word: group of slot s at bits 8 + 4 s
 #ifndef SNSW_POLL_SLEEP
 #define SNSW_POLL_SLEEP 1   // s_sleep units (64 clocks) between dependency polls
 #endif
@@ -543,6 +544,15 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
     }
 }
 
+// Value of v on lane src of the wavefront (any lane; the source lane must be
+// active).
+__device__ __forceinline__ double lane_read(double v, int src) {
+    const int addr = src << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 // Broadcast of lane K of each group of N lanes to the whole group, register
 // to register: DPP row broadcast for 16-lane groups, quad permutation for
 // 4-lane groups.
@@ -711,66 +721,97 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         // polls the upwind element's value at the matching node; each group
         // finishes its pair as soon as all of its values are there, so the
         // pairs of one wavefront do not wait for each other.
+        // With a tiled schedule the groups of a wavefront are the pairs of
+        // one tile of elements for one direction: a kept upwind pair in the
+        // same tile (intra bit s) is read from its group's registers once
+        // that group is done, not from memory.
+        const unsigned intra = (active && pa.intra) ? (unsigned)pa.intra[pidx] : 0u;
         const double* addr[NS];
         bool need[NS];
         double own[NS];
+        int src_lane[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
-            need[s] = active && on && ((kept >> s) & 1u);
+            const bool internal = (intra >> s) & 1u;
+            need[s] = active && on && ((kept >> s) & 1u) && !internal;
             addr[s] = args.psi_cur;
             own[s] = 0.0;
+            src_lane[s] = lane;
             if (need[s]) {
                 addr[s] = args.psi_cur + ((size_t)d * args.E + nbs[s]) * N + S::tn(s ^ 1, S::local(row, s));
+            }
+            if (internal && on) {
+                const int g_up = (int)((intra >> (kIntraGroupShiftDev + 4 * s)) & 15u);
+                src_lane[s] = g_up * N + S::tn(s ^ 1, S::local(row, s));
             }
         }
         constexpr unsigned long long gmask = N == 64 ? ~0ull : ((1ull << N) - 1ull);
         bool done = !active;
         int polls = 0;
         while (true) {
-            // Only the lane on the first node of a face polls; the other
-            // face lanes load once it has seen data.  This keeps the polling
-            // traffic (device-scope loads bypass the L2) low.
+            // groups already done (their x is final)
+            // every face lane of a kept face polls its own upwind value
+            // (one round trip per poll; the polling traffic is small)
             bool have = true;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const bool leader = row == S::tn(s, 0);
-                const unsigned long long lead_done = __ballot(!need[s]);
-                const bool go = need[s] && (leader || ((lead_done >> (grp * N + S::tn(s, 0))) & 1ull));
-                if (go) {
+                if (need[s]) {
                     const double val =
                         __hip_atomic_load(const_cast<double*>(addr[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if ((unsigned long long)__double_as_longlong(val) != sent) { own[s] = val; need[s] = false; }
                 }
                 if (need[s]) have = false;
             }
-            const unsigned long long ready = __ballot(have);
-            const bool gready = ((ready >> (grp * N)) & gmask) == gmask;
-            if (gready && !done) {
-                // c_s[la] = sum_b P_in,s[la][b] psi_up,s[b] on the face lanes
-                // (psi_up,s[b] sits on lane tn_s(b)); then
-                // x += sum_a A^{-1}[row][tn_s(a)] c_s[a].  The whole group
-                // takes this branch together, so the DPP sources are active.
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                static_for<0, NS>([&](auto sc) {
-                    constexpr int s = decltype(sc)::value;
-                    if ((kept >> s) & 1u) {
-                        const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
-                        const int la = on ? S::local(row, s) : 0;
-                        double c = 0.0;
-                        static_for<0, NF>([&](auto bc) {
-                            constexpr int b = decltype(bc)::value;
-                            c += pin_lds[wave][grp][s][la][b] * group_bcast<N, S::tn(s, b)>(own[s]);
-                        });
-                        static_for<0, NF>([&](auto ac) {
-                            constexpr int aa = decltype(ac)::value;
-                            x += m[S::tn(s, aa)] * group_bcast<N, S::tn(s, aa)>(c);
-                        });
+            // Finish every ready group.  With a tiled schedule a finished
+            // group can make groups of the same tile ready; they are finished
+            // in further passes without new polls (at most G passes).
+            for (int pass = 0; pass < G; ++pass) {
+                const unsigned long long done_mask = __ballot(done);
+                bool ready_lane = have;
+                // intra-tile upwind values from the upwind group's lanes (all
+                // lanes execute the permutes; only finished sources are used)
+                double perm[NS];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    perm[s] = 0.0;
+                    if (pa.intra) perm[s] = lane_read(x, src_lane[s]);
+                    if ((intra >> s) & 1u) {
+                        const int g_up = (int)((intra >> (kIntraGroupShiftDev + 4 * s)) & 15u);
+                        if (!((done_mask >> (g_up * N)) & 1ull)) ready_lane = false;
                     }
-                });
-                __hip_atomic_store(args.psi_cur + ((size_t)d * args.E + e) * N + row, x, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                done = true;
+                }
+                const unsigned long long ready = __ballot(ready_lane);
+                const bool gready = ((ready >> (grp * N)) & gmask) == gmask;
+                const bool fin = gready && !done;
+                if (fin) {
+                    // c_s[la] = sum_b P_in,s[la][b] psi_up,s[b] on the face
+                    // lanes (psi_up,s[b] sits on lane tn_s(b)); then
+                    // x += sum_a A^{-1}[row][tn_s(a)] c_s[a].  The whole group
+                    // takes this branch together, so the DPP sources are active.
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    static_for<0, NS>([&](auto sc) {
+                        constexpr int s = decltype(sc)::value;
+                        if ((intra >> s) & 1u) own[s] = perm[s];
+                        if ((kept >> s) & 1u) {
+                            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+                            const int la = on ? S::local(row, s) : 0;
+                            double c = 0.0;
+                            static_for<0, NF>([&](auto bc) {
+                                constexpr int b = decltype(bc)::value;
+                                c += pin_lds[wave][grp][s][la][b] * group_bcast<N, S::tn(s, b)>(own[s]);
+                            });
+                            static_for<0, NF>([&](auto ac) {
+                                constexpr int aa = decltype(ac)::value;
+                                x += m[S::tn(s, aa)] * group_bcast<N, S::tn(s, aa)>(c);
+                            });
+                        }
+                    });
+                    __hip_atomic_store(args.psi_cur + ((size_t)d * args.E + e) * N + row, x, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    done = true;
+                }
+                if (!pa.intra || !__any(fin)) break;
             }
             if (__all(done)) break;
             if (++polls > pa.spin_limit) {

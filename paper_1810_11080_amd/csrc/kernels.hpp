@@ -52,6 +52,7 @@ struct PersistArgs {
     int32_t* error;           // set to 1 when a dependency wait times out
     int64_t total;            // entries in the schedule
     int32_t spin_limit;       // polls per dependency wait before giving up
+    const int32_t* intra;     // tiled schedules: intra-tile dependency word per entry (else null)
 };
 
 // Launches the persistent sweep kernel (all levels in one launch); inv: read

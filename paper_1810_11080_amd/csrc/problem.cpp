@@ -172,6 +172,8 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
         build_faces(hp);
         build_graphs(hp);
         build_schedule(hp);
+        // tiles of T x T elements per persistent batch for the DPP shapes
+        if (hp.dim == 2 && (hp.n == 16 || hp.n == 4)) build_tiled_schedule(hp, hp.n == 16 ? 2 : 4);
         hp.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (ctx->device >= 0) {
             try {
@@ -209,6 +211,7 @@ int snsw_problem_get_info(const snsw_problem* prob, snsw_problem_info* info) {
         info->n_kink_faces_total = hp.n_kinks;
         info->setup_seconds = hp.setup_seconds;
         info->cached_inverse = hp.inverse_cached;
+        info->tile = hp.tile;
         info->schedule = hp.schedule;
     });
 }

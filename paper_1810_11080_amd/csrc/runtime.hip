@@ -170,6 +170,7 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             pa.error = L.error;
             pa.total = c.level_off.back();
             pa.spin_limit = 1 << 20;
+            pa.intra = c.intra;
             if (prof) prof->begin(s);
             launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
             if (prof) prof->end(s);
@@ -250,6 +251,12 @@ void device_upload(snsw_problem* prob) {
         HIP_OK(hipMemcpyAsync(pp, hp.pairs.data(), hp.pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         dp->pairs = pp;
     }
+    if (hp.tile > 0) {
+        dp->tpairs = dalloc<int4>(dp, hp.tpairs.size() / 4);
+        HIP_OK(hipMemcpyAsync(dp->tpairs, hp.tpairs.data(), hp.tpairs.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+        dp->tintra = dupload(dp, hp.tintra, s);
+    }
     dp->slot_face = dupload(dp, hp.slot_face, s);
     dp->slot_nbr = dupload(dp, hp.slot_nbr, s);
     dp->sigma_t = dupload(dp, hp.sigma_t, s);
@@ -289,6 +296,11 @@ void device_upload(snsw_problem* prob) {
     c.ticket = 0;
     c.pairs = dp->pairs;
     c.level_off = hp.level_off;
+    if (c.persistent && hp.tile > 0) {
+        c.pairs = dp->tpairs;
+        c.level_off = hp.tlevel_off;
+        c.intra = dp->tintra;
+    }
     c.members = {0};
     c.blocks = persistent_grid(hp.dim, hp.p, c.inv, hp.level_off.back(), dp->device);
     {
@@ -314,7 +326,8 @@ void device_release(snsw_problem* prob) noexcept {
     (void)hipSetDevice(dp->device);
     (void)hipStreamSynchronize(dp->stream);
     dp->prof.release();
-    void* ptrs[] = {dp->geo, dp->B, dp->kink_tab, dp->kink_idx, dp->pairs, dp->slot_face, dp->slot_nbr,
+    void* ptrs[] = {dp->geo, dp->B, dp->kink_tab, dp->kink_idx, dp->pairs, dp->tpairs, dp->tintra,
+                    dp->slot_face, dp->slot_nbr,
                     dp->sigma_t, dp->sigma_s, dp->q, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
                     dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table, dp->ainv};
     for (void* p : ptrs)

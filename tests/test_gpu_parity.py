@@ -148,6 +148,7 @@ def test_c2_full_one_sweep(torch, ctx, c2_oracle, schedule, cache):
     wp, phi0, psi0, o_phi, o_psi = c2_oracle
     P = Problem.from_workload(ctx, wp, schedule=schedule, cache_inverse=cache)
     assert P.info()["n_removed_total"] > 0
+    assert P.info()["tile"] == 2     # persistent sweeps take 2x2 tiles here
     P.state_load(state_bytes(wp, psi0))
     g_phi, g_psi = gpu_sweeps(torch, P, 1, phi0)
     P.synchronize()
