@@ -166,7 +166,7 @@ def bench_batch(args):
         "config": {"workload": DESCRIPTIONS["c4"], "problems": len(problems), "dof_dir_per_sweep": dof_dir,
                    "setup_s": round(setup_s, 2), "tune_s": round(tune_s, 2),
                    "classes": [{"p": c["dg_order"], "problems": c["n_problems"], "levels": c["n_levels"],
-                                "schedule": "persistent" if c["persistent"] else "levels",
+                                "schedule": ("persistent" + (" tiled" if c["tiled"] else "")) if c["persistent"] else "levels",
                                 "blocks": c["blocks"], "tuned_ms": [round(x, 3) for x in c["tuned_ms"]]}
                                for c in classes]},
         "roofline": roof,

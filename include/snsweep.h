@@ -336,8 +336,10 @@ int snsw_learn_pair(snsw_problem* prob, const double* d_phi_prev, const double* 
  *
  * opts (nullable: all fields 0):
  *   schedule   SNSW_SCHED_AUTO: the autotuner times, per FP64 class, the
- *              level schedule and the persistent one at full and half grid
- *              (tune_reps sweeps each, default 3) and keeps the fastest;
+ *              level schedule and the persistent one at full and half grid,
+ *              and with single pairs instead of tiles per wavefront where
+ *              the class has tiles (tune_reps sweeps each, default 3), and
+ *              keeps the fastest;
  *              SNSW_SCHED_PERSISTENT / SNSW_SCHED_LEVELS force one for every
  *              FP64 class.  Mixed-precision classes always use LEVELS.
  *   use_graph  0: eager launches; otherwise hipGraph replay.
@@ -374,9 +376,11 @@ typedef struct {
     int32_t n_problems;
     int64_t n_levels;            /* levels of the merged schedule            */
     int64_t n_entries;           /* schedule entries incl. padding           */
-    double  tuned_ms[3];         /* autotuner: levels, persistent full grid,
-                                    persistent half grid (ms per sweep; 0 if
-                                    not timed)                               */
+    double  tuned_ms[4];         /* autotuner: levels, persistent full grid,
+                                    persistent half grid, persistent full grid
+                                    without tiles (ms per sweep; 0 if not
+                                    timed)                                   */
+    int32_t tiled;               /* chosen schedule takes tiles per wavefront */
 } snsw_batch_class_info;
 int snsw_batch_n_classes(const snsw_batch* batch, int32_t* n);
 int snsw_batch_class_get(const snsw_batch* batch, int32_t c, snsw_batch_class_info* info);

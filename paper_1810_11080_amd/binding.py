@@ -73,7 +73,8 @@ class SnswBatchOpts(C.Structure):
 class SnswBatchClassInfo(C.Structure):
     _fields_ = [("dim", C.c_int32), ("dg_order", C.c_int32), ("precision", C.c_int32),
                 ("persistent", C.c_int32), ("blocks", C.c_int32), ("n_problems", C.c_int32),
-                ("n_levels", C.c_int64), ("n_entries", C.c_int64), ("tuned_ms", C.c_double * 3)]
+                ("n_levels", C.c_int64), ("n_entries", C.c_int64), ("tuned_ms", C.c_double * 4),
+                ("tiled", C.c_int32)]
 
 
 # name -> (restype, argtypes); mirrors include/snsweep.h

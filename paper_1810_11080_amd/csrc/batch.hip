@@ -25,9 +25,14 @@ struct BatchGraph {
 struct BatchClass {
     SweepClass cls;
     bool has_inv = false;              // every member keeps cached inverses
-    int4* d_pairs = nullptr;
+    int4* d_pairs = nullptr;           // level schedule
+    std::vector<int64_t> level_off;
+    bool tiled = false;                // every member has a tiled schedule
+    int4* d_tpairs = nullptr;          // tiled schedule (persistent kernels)
+    int32_t* d_tintra = nullptr;
+    std::vector<int64_t> tlevel_off;
     int full_blocks = 0;
-    double tuned_ms[3] = {0.0, 0.0, 0.0};
+    double tuned_ms[4] = {0.0, 0.0, 0.0, 0.0};
 };
 
 }  // namespace snsw
@@ -67,8 +72,11 @@ void release_batch(snsw_batch* b) noexcept {
     hipStream_t s = static_cast<hipStream_t>(b->ctx->stream);
     (void)hipStreamSynchronize(s);
     for (BatchGraph& g : b->graphs) release_graph(g);
-    for (BatchClass& c : b->classes)
+    for (BatchClass& c : b->classes) {
         if (c.d_pairs) (void)hipFree(c.d_pairs);
+        if (c.d_tpairs) (void)hipFree(c.d_tpairs);
+        if (c.d_tintra) (void)hipFree(c.d_tintra);
+    }
     if (b->table) (void)hipFree(b->table);
     if (b->tickets) (void)hipFree(b->tickets);
     if (b->error) (void)hipFree(b->error);
@@ -134,52 +142,60 @@ void reset_members(snsw_batch* b) {
 
 // Merged schedule of one class: level k lists, problem by problem, every
 // member's level-k segment (each a multiple of G entries); the problem field
-// of each entry is its table index.  Checks that every kept upwind pair lies
-// in an earlier batch of G entries than its dependant.
-void build_class_schedule(const std::vector<snsw_problem*>& probs, SweepClass& c, std::vector<int32_t>& pairs) {
+// of each entry is its table index.  `tiled` merges the members' tiled
+// schedules instead (levels of tiles; intra-tile dependency words kept).
+// Checks that every kept upwind pair lies in an earlier batch of G entries
+// than its dependant, or in the same tile when the intra word says so.
+void build_class_schedule(const std::vector<snsw_problem*>& probs, const std::vector<int>& members, bool tiled,
+                          std::vector<int64_t>& level_off, std::vector<int32_t>& pairs, std::vector<int32_t>& intra) {
+    auto lo_of = [&](const HostProblem& hp) -> const std::vector<int64_t>& { return tiled ? hp.tlevel_off : hp.level_off; };
+    auto pr_of = [&](const HostProblem& hp) -> const std::vector<int32_t>& { return tiled ? hp.tpairs : hp.pairs; };
     int64_t L = 0;
-    for (int k : c.members) L = std::max<int64_t>(L, (int64_t)probs[k]->hp.level_off.size() - 1);
-    const int n = probs[c.members[0]]->hp.n;
+    for (int k : members) L = std::max<int64_t>(L, (int64_t)lo_of(probs[k]->hp).size() - 1);
+    const int n = probs[members[0]]->hp.n;
     const int64_t G = std::max(1, 64 / n);
-    c.level_off.assign(L + 1, 0);
+    level_off.assign(L + 1, 0);
     for (int64_t l = 0; l < L; ++l) {
         int64_t cnt = 0;
-        for (int k : c.members) {
-            const auto& lo = probs[k]->hp.level_off;
+        for (int k : members) {
+            const auto& lo = lo_of(probs[k]->hp);
             if (l + 1 < (int64_t)lo.size()) cnt += lo[l + 1] - lo[l];
         }
-        c.level_off[l + 1] = c.level_off[l] + cnt;
+        level_off[l + 1] = level_off[l] + cnt;
     }
-    const int64_t total = c.level_off[L];
+    const int64_t total = level_off[L];
     pairs.assign((size_t)total * 4, 0);
-    std::vector<std::vector<int64_t>> where(c.members.size());
-    for (size_t m = 0; m < c.members.size(); ++m) {
-        const HostProblem& hp = probs[c.members[m]]->hp;
+    intra.assign(tiled ? (size_t)total : 0, 0);
+    std::vector<std::vector<int64_t>> where(members.size());
+    for (size_t m = 0; m < members.size(); ++m) {
+        const HostProblem& hp = probs[members[m]]->hp;
         where[m].assign((size_t)hp.D * hp.E, -1);
     }
     for (int64_t l = 0; l < L; ++l) {
-        int64_t pos = c.level_off[l];
-        for (size_t m = 0; m < c.members.size(); ++m) {
-            const int k = c.members[m];
+        int64_t pos = level_off[l];
+        for (size_t m = 0; m < members.size(); ++m) {
+            const int k = members[m];
             const HostProblem& hp = probs[k]->hp;
-            const auto& lo = hp.level_off;
+            const auto& lo = lo_of(hp);
+            const auto& hpairs = pr_of(hp);
             if (l + 1 >= (int64_t)lo.size()) continue;
             if ((pos % G) != 0 || ((lo[l + 1] - lo[l]) % G) != 0)
                 throw Error(SNSW_E_STATE, "batch schedule: level segment not a multiple of G");
             for (int64_t t = lo[l]; t < lo[l + 1]; ++t, ++pos) {
-                const int32_t* src = &hp.pairs[(size_t)t * 4];
+                const int32_t* src = &hpairs[(size_t)t * 4];
                 int32_t* dst = &pairs[(size_t)pos * 4];
                 dst[0] = src[0];
                 dst[1] = src[1];
                 dst[2] = src[2];
                 dst[3] = k;
+                if (tiled) intra[(size_t)pos] = hp.tintra[(size_t)t];
                 if (src[0] >= 0)
                     where[m][(size_t)((uint32_t)src[1] & ((1u << kDirBits) - 1)) * hp.E + src[0]] = pos;
             }
         }
     }
-    for (size_t m = 0; m < c.members.size(); ++m) {
-        const HostProblem& hp = probs[c.members[m]]->hp;
+    for (size_t m = 0; m < members.size(); ++m) {
+        const HostProblem& hp = probs[members[m]]->hp;
         const int ns = 2 * hp.dim;
         for (size_t i = 0; i < where[m].size(); ++i)
             if (where[m][i] < 0) throw Error(SNSW_E_STATE, "batch schedule: a pair is missing");
@@ -187,27 +203,47 @@ void build_class_schedule(const std::vector<snsw_problem*>& probs, SweepClass& c
             for (int64_t e = 0; e < hp.E; ++e) {
                 const int64_t t = where[m][(size_t)d * hp.E + e];
                 const uint32_t packed = (uint32_t)pairs[(size_t)t * 4 + 1];
+                const uint32_t iw = tiled ? (uint32_t)intra[(size_t)t] : 0u;
                 for (int s = 0; s < ns; ++s) {
                     const uint32_t bits = packed >> (kDirBits + 3 * s);
                     const uint32_t cls = bits & 3u;
                     const bool lagged = (bits >> 2) & 1u;
                     const int32_t nb = hp.slot_nbr[(size_t)e * ns + s];
-                    if ((cls == SC_IN || cls == SC_KINK) && !lagged && nb >= 0 &&
-                        where[m][(size_t)d * hp.E + nb] >= t - t % G)
+                    if (!((cls == SC_IN || cls == SC_KINK) && !lagged && nb >= 0)) continue;
+                    const int64_t tu = where[m][(size_t)d * hp.E + nb];
+                    if ((iw >> s) & 1u) {
+                        const int64_t g_up = (iw >> (kIntraGroupShift + 4 * s)) & 15u;
+                        if (tu != t - t % G + g_up)
+                            throw Error(SNSW_E_STATE, "batch schedule: an intra-tile dependency is misplaced");
+                    } else if (tu >= t - t % G) {
                         throw Error(SNSW_E_STATE, "batch schedule: a kept upwind pair does not precede its dependant");
+                    }
                 }
             }
     }
 }
 
+// Active schedule of a class for a schedule choice (tiles: use the tiled
+// schedule when the class has one).
+void choose(BatchClass& bc, bool persistent, int blocks, bool tiles = true) {
+    SweepClass& c = bc.cls;
+    c.persistent = persistent;
+    c.blocks = persistent ? blocks : 0;
+    c.inv = bc.has_inv && (!persistent || persistent_uses_inverse(c.dim, c.p));
+    tiles = tiles && persistent && bc.tiled;
+    c.pairs = tiles ? bc.d_tpairs : bc.d_pairs;
+    c.level_off = tiles ? bc.tlevel_off : bc.level_off;
+    c.intra = tiles ? bc.d_tintra : nullptr;
+}
+
 // Times `reps` sweeps of one class with the given schedule (ms per sweep,
 // class kernels only).
-double time_class(snsw_batch* b, size_t ci, bool persistent, int blocks, int reps, double* phi_in, double* phi_out) {
+double time_class(snsw_batch* b, size_t ci, bool persistent, int blocks, bool tiles, int reps, double* phi_in,
+                  double* phi_out) {
     hipStream_t s = static_cast<hipStream_t>(b->ctx->stream);
-    SweepClass c = b->classes[ci].cls;
-    c.persistent = persistent;
-    c.blocks = blocks;
-    c.inv = b->classes[ci].has_inv && (!persistent || persistent_uses_inverse(c.dim, c.p));
+    BatchClass tmp = b->classes[ci];
+    choose(tmp, persistent, blocks, tiles);
+    const SweepClass c = tmp.cls;
     SweepLaunch L = base_launch(b);
     L.any_persistent = true;
     L.phi_in_one = phi_in;
@@ -359,17 +395,26 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
             b->max_DEn = std::max<int64_t>(b->max_DEn, hp.D * hp.E * hp.n);
         }
         for (BatchClass& bc : b->classes) {
-            std::vector<int32_t> pairs;
-            build_class_schedule(b->probs, bc.cls, pairs);
+            std::vector<int32_t> pairs, intra;
+            build_class_schedule(b->probs, bc.cls.members, false, bc.level_off, pairs, intra);
             HIP_OK(hipMalloc(&bc.d_pairs, std::max<size_t>(1, pairs.size()) * sizeof(int32_t)));
             HIP_OK(hipMemcpyAsync(bc.d_pairs, pairs.data(), pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            bc.tiled = !bc.cls.mixed;
+            for (int k : bc.cls.members) bc.tiled = bc.tiled && b->probs[k]->hp.tile > 0;
+            if (bc.tiled) {
+                build_class_schedule(b->probs, bc.cls.members, true, bc.tlevel_off, pairs, intra);
+                HIP_OK(hipMalloc(&bc.d_tpairs, std::max<size_t>(1, pairs.size()) * sizeof(int32_t)));
+                HIP_OK(hipMemcpyAsync(bc.d_tpairs, pairs.data(), pairs.size() * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, s));
+                HIP_OK(hipMalloc(&bc.d_tintra, std::max<size_t>(1, intra.size()) * sizeof(int32_t)));
+                HIP_OK(hipMemcpyAsync(bc.d_tintra, intra.data(), intra.size() * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, s));
+            }
             HIP_OK(hipStreamSynchronize(s));
-            bc.cls.pairs = bc.d_pairs;
-            bc.cls.persistent = !bc.cls.mixed && o.schedule == SNSW_SCHED_PERSISTENT;
             const bool pinv = bc.has_inv && persistent_uses_inverse(bc.cls.dim, bc.cls.p);
-            bc.full_blocks = persistent_grid(bc.cls.dim, bc.cls.p, pinv, bc.cls.level_off.back(), ctx->device);
-            bc.cls.blocks = bc.full_blocks;
-            bc.cls.inv = bc.has_inv && (!bc.cls.persistent || pinv);
+            const int64_t ptotal = bc.tiled ? bc.tlevel_off.back() : bc.level_off.back();
+            bc.full_blocks = persistent_grid(bc.cls.dim, bc.cls.p, pinv, ptotal, ctx->device);
+            choose(bc, !bc.cls.mixed && o.schedule == SNSW_SCHED_PERSISTENT, bc.full_blocks);
         }
         HIP_OK(hipMalloc(&b->table, count * sizeof(SweepArgs)));
         HIP_OK(hipMalloc(&b->tickets, b->classes.size() * kTicketWords * sizeof(unsigned int)));
@@ -393,13 +438,13 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
                     BatchClass& bc = b->classes[ci];
                     if (bc.cls.mixed) continue;
                     const int half = std::max(1, bc.full_blocks / 2);
-                    bc.tuned_ms[0] = time_class(b, ci, false, 0, reps, phi_in, phi_out);
-                    bc.tuned_ms[1] = time_class(b, ci, true, bc.full_blocks, reps, phi_in, phi_out);
-                    bc.tuned_ms[2] = time_class(b, ci, true, half, reps, phi_in, phi_out);
-                    const int best = (int)(std::min_element(bc.tuned_ms, bc.tuned_ms + 3) - bc.tuned_ms);
-                    bc.cls.persistent = best != 0;
-                    bc.cls.blocks = best == 2 ? half : bc.full_blocks;
-                    bc.cls.inv = bc.has_inv && (!bc.cls.persistent || persistent_uses_inverse(bc.cls.dim, bc.cls.p));
+                    bc.tuned_ms[0] = time_class(b, ci, false, 0, true, reps, phi_in, phi_out);
+                    bc.tuned_ms[1] = time_class(b, ci, true, bc.full_blocks, true, reps, phi_in, phi_out);
+                    bc.tuned_ms[2] = time_class(b, ci, true, half, true, reps, phi_in, phi_out);
+                    const int cands = bc.tiled ? 4 : 3;
+                    if (bc.tiled) bc.tuned_ms[3] = time_class(b, ci, true, bc.full_blocks, false, reps, phi_in, phi_out);
+                    const int best = (int)(std::min_element(bc.tuned_ms, bc.tuned_ms + cands) - bc.tuned_ms);
+                    choose(bc, best != 0, best == 2 ? half : bc.full_blocks, best != 3);
                 }
             } catch (...) {
                 (void)hipFree(phi_in);
@@ -505,7 +550,8 @@ int snsw_batch_class_get(const snsw_batch* b, int32_t c, snsw_batch_class_info* 
         info->n_problems = (int32_t)bc.cls.members.size();
         info->n_levels = (int64_t)bc.cls.level_off.size() - 1;
         info->n_entries = bc.cls.level_off.back();
-        for (int i = 0; i < 3; ++i) info->tuned_ms[i] = bc.tuned_ms[i];
+        for (int i = 0; i < 4; ++i) info->tuned_ms[i] = bc.tuned_ms[i];
+        info->tiled = (bc.cls.persistent && bc.cls.intra) ? 1 : 0;
     });
 }
 

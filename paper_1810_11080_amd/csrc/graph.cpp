@@ -524,11 +524,11 @@ bool build_tiled_schedule(HostProblem& hp, int T) {
     if (hp.dim != 2 || T < 1 || T * T != std::max(1, 64 / hp.n)) return false;
     const int64_t E = hp.E;
     const int D = hp.D, ns = hp.nslot;
-    const int nx = hp.nx[0], ny = hp.nx[1];
-    const int tx = (nx + T - 1) / T, ty = (ny + T - 1) / T;
-    const int64_t NT = (int64_t)tx * ty;
+    const int nx = hp.nx[0];
+    const int tx = (nx + T - 1) / T, ty = (hp.nx[1] + T - 1) / T;
+    const int64_t NT = (int64_t)tx * ty;   // tile ids: [0, NT) T x T tiles, NT + e singleton of e
     const int G = T * T;
-    auto tile_of = [&](int64_t e) { return (int64_t)((e % nx) / T) + (int64_t)tx * ((e / nx) / T); };
+    auto base_tile = [&](int64_t e) { return (int64_t)((e % nx) / T) + (int64_t)tx * ((e / nx) / T); };
     auto group_of = [&](int64_t e) { return (int)((e % nx) % T) + T * (int)((e / nx) % T); };
     // entry of every (d, e) in the level schedule
     std::vector<int64_t> where((size_t)D * E, -1);
@@ -544,68 +544,107 @@ bool build_tiled_schedule(HostProblem& hp, int T) {
         if ((cls != SC_IN && cls != SC_KINK) || lagged) return -1;
         return hp.slot_nbr[(size_t)pr[0] * ns + s];
     };
-    // tile levels per direction (ASAP in the contracted kept graph)
-    std::vector<std::vector<int32_t>> tlev(D);
-    std::atomic<bool> cyclic{false};
+    // Per direction: tiles of the kept graph, contracted; tiles in a cycle
+    // of the contracted graph are split into single elements (repeated
+    // until it is acyclic, which single elements always are); then ASAP
+    // levels of the tiles.
+    const int64_t NI = NT + E;
+    std::vector<std::vector<int64_t>> tile_id(D);
+    std::vector<std::vector<int32_t>> tlev(D);   // [NI], -1 for unused ids
     parallel_for(D, hp.nthreads, [&](int64_t d0, int64_t d1) {
-        for (int64_t d = d0; d < d1 && !cyclic; ++d) {
-            std::vector<std::vector<int32_t>> adj(NT);
-            std::vector<int32_t> indeg(NT, 0);
+        for (int64_t d = d0; d < d1; ++d) {
+            std::vector<int64_t>& tid = tile_id[d];
+            tid.resize(E);
+            for (int64_t e = 0; e < E; ++e) tid[e] = base_tile(e);
+            std::vector<std::pair<int32_t, int32_t>> edges;   // element edges up -> down
             for (int64_t e = 0; e < E; ++e) {
                 const int32_t* pr = &hp.pairs[(size_t)where[(size_t)d * E + e] * 4];
                 for (int s = 0; s < ns; ++s) {
                     const int32_t up = kept_up(pr, s);
-                    if (up < 0) continue;
-                    const int64_t a = tile_of(up), b = tile_of(e);
-                    if (a != b) adj[a].push_back((int32_t)b);
+                    if (up >= 0) edges.emplace_back(up, (int32_t)e);
                 }
             }
-            for (auto& v : adj) {
-                std::sort(v.begin(), v.end());
-                v.erase(std::unique(v.begin(), v.end()), v.end());
-                for (int32_t b : v) ++indeg[b];
-            }
-            std::vector<int32_t>& lev = tlev[d];
-            lev.assign(NT, 0);
-            std::vector<int32_t> queue;
-            for (int64_t t = 0; t < NT; ++t)
-                if (indeg[t] == 0) queue.push_back((int32_t)t);
-            for (size_t h = 0; h < queue.size(); ++h) {
-                const int32_t t = queue[h];
-                for (int32_t b : adj[t]) {
-                    lev[b] = std::max(lev[b], lev[t] + 1);
-                    if (--indeg[b] == 0) queue.push_back(b);
+            while (true) {
+                std::vector<std::pair<int32_t, int32_t>> tedges;
+                for (auto& ed : edges) {
+                    const int64_t a = tid[ed.first], b = tid[ed.second];
+                    if (a != b) tedges.emplace_back((int32_t)a, (int32_t)b);
                 }
+                std::sort(tedges.begin(), tedges.end());
+                tedges.erase(std::unique(tedges.begin(), tedges.end()), tedges.end());
+                std::vector<int64_t> off(NI + 1, 0);
+                for (auto& te : tedges) ++off[te.first + 1];
+                for (int64_t i = 0; i < NI; ++i) off[i + 1] += off[i];
+                std::vector<int32_t> adj(tedges.size());
+                {
+                    std::vector<int64_t> fill(off.begin(), off.end() - 1);
+                    for (auto& te : tedges) adj[fill[te.first]++] = te.second;
+                }
+                const std::vector<int32_t> comp = tarjan(NI, off, adj);
+                std::vector<int32_t> csize(NI, 0);
+                for (int64_t i = 0; i < NI; ++i) ++csize[comp[i]];
+                bool split = false;
+                for (int64_t e = 0; e < E; ++e)
+                    if (csize[comp[tid[e]]] > 1) {
+                        tid[e] = NT + e;
+                        split = true;
+                    }
+                if (split) continue;
+                // ASAP levels (Kahn) of the used tile ids
+                std::vector<int32_t> indeg(NI, 0);
+                for (int32_t v : adj) ++indeg[v];
+                std::vector<char> used(NI, 0);
+                for (int64_t e = 0; e < E; ++e) used[tid[e]] = 1;
+                std::vector<int32_t>& lev = tlev[d];
+                lev.assign(NI, -1);
+                std::vector<int32_t> queue;
+                for (int64_t i = 0; i < NI; ++i)
+                    if (used[i] && indeg[i] == 0) {
+                        queue.push_back((int32_t)i);
+                        lev[i] = 0;
+                    }
+                for (size_t h = 0; h < queue.size(); ++h) {
+                    const int32_t t = queue[h];
+                    for (int64_t k = off[t]; k < off[t + 1]; ++k) {
+                        const int32_t b = adj[k];
+                        lev[b] = std::max(lev[b], lev[t] + 1);
+                        if (--indeg[b] == 0) queue.push_back(b);
+                    }
+                }
+                break;
             }
-            if ((int64_t)queue.size() != NT) cyclic = true;
         }
     });
-    if (cyclic) return false;
     int32_t Lt = 0;
     for (int d = 0; d < D; ++d)
         for (int32_t l : tlev[d]) Lt = std::max(Lt, l + 1);
     std::vector<int64_t> count(Lt + 1, 0);
     for (int d = 0; d < D; ++d)
-        for (int32_t l : tlev[d]) ++count[l + 1];
+        for (int32_t l : tlev[d])
+            if (l >= 0) ++count[l + 1];
     hp.tlevel_off.assign(Lt + 1, 0);
     for (int32_t l = 0; l < Lt; ++l) hp.tlevel_off[l + 1] = hp.tlevel_off[l] + count[l + 1] * G;
     const int64_t PT = hp.tlevel_off[Lt];
     hp.tpairs.assign((size_t)PT * 4, 0);
     hp.tintra.assign((size_t)PT, 0);
     for (int64_t t = 0; t < PT; ++t) hp.tpairs[(size_t)t * 4] = -1;
-    // batches: level by level, direction by direction, tile by tile
+    // batches: level by level, direction by direction, tile id by tile id
     std::vector<int64_t> pos(hp.tlevel_off.begin(), hp.tlevel_off.end() - 1);
-    std::vector<int64_t> batch_of((size_t)D * NT, -1);
-    for (int d = 0; d < D; ++d)
-        for (int64_t t = 0; t < NT; ++t) {
-            batch_of[(size_t)d * NT + t] = pos[tlev[d][t]];
-            pos[tlev[d][t]] += G;
+    std::vector<std::vector<int64_t>> batch_of(D);
+    for (int d = 0; d < D; ++d) {
+        batch_of[d].assign(NI, -1);
+        for (int64_t i = 0; i < NI; ++i) {
+            const int32_t l = tlev[d][i];
+            if (l < 0) continue;
+            batch_of[d][i] = pos[l];
+            pos[l] += G;
         }
+    }
     for (int d = 0; d < D; ++d)
         for (int64_t e = 0; e < E; ++e) {
             const int64_t src = where[(size_t)d * E + e];
-            const int64_t tt = tile_of(e);
-            const int64_t dst = batch_of[(size_t)d * NT + tt] + group_of(e);
+            const int64_t tt = tile_id[d][e];
+            const int64_t dst = batch_of[d][tt] + group_of(e);
             const int32_t* pr = &hp.pairs[(size_t)src * 4];
             int32_t* out = &hp.tpairs[(size_t)dst * 4];
             out[0] = pr[0];
@@ -616,9 +655,10 @@ bool build_tiled_schedule(HostProblem& hp, int T) {
             for (int s = 0; s < ns; ++s) {
                 const int32_t up = kept_up(pr, s);
                 if (up < 0) continue;
-                if (tile_of(up) == tt)
+                const int64_t tu = tile_id[d][up];
+                if (tu == tt)
                     intra |= (1u << s) | ((uint32_t)group_of(up) << (kIntraGroupShift + 4 * s));
-                else if (batch_of[(size_t)d * NT + tile_of(up)] >= batch_of[(size_t)d * NT + tt])
+                else if (batch_of[d][tu] >= batch_of[d][tt])
                     throw Error(SNSW_E_STATE, "tiled schedule: an upwind tile does not precede its dependant");
             }
             hp.tintra[(size_t)dst] = (int32_t)intra;
