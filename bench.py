@@ -177,25 +177,32 @@ def bench_batch(args):
 
 
 def learned_vs_plain(nx=16, p=2, sn_order=8, train_seeds=(0, 1, 2, 3), eval_seeds=(100, 101), steps=3000,
-                     every=40):
+                     every=40, stride=3, tol_train=1e-12, verbose=False):
     """Time to a 1e-8 residual with and without the learned correction on
     the two-material c = 0.99 family (the 48^3 S12 configuration's
-    materials at nx^3): train on plain-SI pairs of train_seeds, evaluate on
-    held-out eval_seeds.  Returns a JSON-ready dict."""
+    materials at nx^3): train on plain-SI pairs (every `stride`-th iteration
+    of a solve to tol_train) of train_seeds, evaluate on held-out
+    eval_seeds.  Returns a JSON-ready dict."""
     import torch
     import workloads as W
     from paper_1810_11080_amd import Context, Net, Problem
     from paper_1810_11080_amd import learn as L
+
+    def note(msg):
+        if verbose:
+            print(msg, file=sys.stderr, flush=True)
 
     ctx = Context(device=0)
     t0 = time.perf_counter()
     Xs, Ts = [], []
     for seed in train_seeds:
         P = Problem.from_workload(ctx, W.c5_reduced(seed=seed, nx=nx, p=p, sn_order=sn_order))
-        kept, star, _ = L.plain_trajectory(P, tol=1e-12, max_iters=50000, sample=lambda l: l % 3 == 0)
+        kept, star, its = L.plain_trajectory(P, tol=tol_train, max_iters=50000, sample=lambda l: l % stride == 0,
+                                             progress=note if verbose else None)
         X, T = L.make_pairs(P, kept, star)
         Xs.append(X)
         Ts.append(T)
+        note(f"training seed {seed}: {its} plain sweeps, {len(kept)} pairs, {time.perf_counter() - t0:.1f} s")
         del kept, P
     X = torch.cat(Xs)
     T = torch.cat(Ts)
@@ -203,7 +210,8 @@ def learned_vs_plain(nx=16, p=2, sn_order=8, train_seeds=(0, 1, 2, 3), eval_seed
     data_s = time.perf_counter() - t0
     net = Net(ctx, widths=(16, 32, 32), seed=0)
     t0 = time.perf_counter()
-    losses = L.train(net, (nx, nx, nx), X, T, steps=steps, batch=8, lr=2e-3, lr_final=1e-4)
+    losses = L.train(net, (nx, nx, nx), X, T, steps=steps, batch=8, lr=2e-3, lr_final=1e-4,
+                     log_every=500 if verbose else 0)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     runs = []
@@ -215,6 +223,7 @@ def learned_vs_plain(nx=16, p=2, sn_order=8, train_seeds=(0, 1, 2, 3), eval_seed
             phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
             rep = P.solve(phi, tol=1e-8, max_iters=50000, precond=pre, precond_every=every)
             row[name] = {"seconds": round(rep["seconds"], 4), "sweeps": rep["iterations"]}
+            note(f"eval seed {seed} {name}: {row[name]}")
             if pre is not None:
                 row[name].update(corrections=rep["n_corrected"], rejected=rep["n_rejected"])
         runs.append(row)
@@ -260,6 +269,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain comparison")
+    ap.add_argument("--learned-only", choices=["c5"], default=None,
+                    help="only the learned-vs-plain comparison at the full 48^3 S12 size (minutes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a copy kernel of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -277,6 +288,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.learned_only == "c5":
+        res = learned_vs_plain(nx=48, p=2, sn_order=12, train_seeds=(0, 1), eval_seeds=(100,), steps=2000,
+                               every=40, stride=10, tol_train=1e-10, verbose=True)
+        print(json.dumps({"learned_vs_plain": res}))
         return
     if args.workload == "c4":
         bench_batch(args)

@@ -23,10 +23,10 @@ def element_grid(P: Problem):
     return nx[2], nx[1], nx[0]
 
 
-def plain_trajectory(P: Problem, tol: float = 1e-12, max_iters: int = 20000, sample=None):
+def plain_trajectory(P: Problem, tol: float = 1e-12, max_iters: int = 20000, sample=None, progress=None):
     """Plain source iteration from phi = 0 to `tol`.  Keeps (phi_l, phi_{l+1})
     for the iterations chosen by sample(l) (default: all).  Returns
-    (pairs, phi_star, iterations)."""
+    (pairs, phi_star, iterations); progress(msg) is called every 500 sweeps."""
     import torch
     En = P.E * P.n
     P.reset()
@@ -37,6 +37,8 @@ def plain_trajectory(P: Problem, tol: float = 1e-12, max_iters: int = 20000, sam
     for it in range(max_iters):
         P.sweep(cur, nxt)
         res = P.residual(nxt, cur)
+        if progress is not None and it % 500 == 0:
+            progress(f"  sweep {it}: residual {res:.3e}")
         if sample is None or sample(it):
             kept.append((cur.clone(), nxt.clone()))
         cur, nxt = nxt, cur
