@@ -338,7 +338,10 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(const SweepArgs*
 // which are finished; and it is either held by a wavefront of its stream
 // (which processes its batches in increasing order) or not yet handed out,
 // in which case every batch its stream has handed out is smaller, finished,
-// and the stream's wavefronts go on to take it.
+// and the stream's wavefronts go on to take it.  This needs a resident block
+// in every stream: the grid is sized to what stays resident, and workgroups
+// are dispatched in increasing id order, so blocks 0 .. S-1 start first.
+// (Assigning streams in arrival order instead measured 5 % slower.)
 #ifndef SNSW_STREAMS
 #define SNSW_STREAMS 16
 #endif
