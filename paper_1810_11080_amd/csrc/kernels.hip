@@ -549,6 +549,10 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
 
 // Value of v on lane src of the wavefront (any lane; the source lane must be
 // active).
+// A double in the global address space: loads through such pointers are
+// global (not flat) memory instructions.
+typedef __attribute__((address_space(1))) double gdouble;
+
 __device__ __forceinline__ double lane_read(double v, int src) {
     const int addr = src << 2;
     const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
@@ -559,13 +563,13 @@ __device__ __forceinline__ double lane_read(double v, int src) {
 // Broadcast of lane K of each group of N lanes to the whole group, register
 // to register: DPP row broadcast for 16-lane groups, quad permutation for
 // 4-lane groups.
+// Every lane has a valid source lane under both controls, so the old value
+// is never used; the 16-lane form is one 64-bit DPP move (v_mov_b64_dpp).
 template <int N, int K>
 __device__ __forceinline__ double group_bcast(double x) {
     static_assert(N == 16 || N == 4, "DPP broadcast needs 4- or 16-lane groups");
     constexpr int ctrl = N == 16 ? 0x150 + K : (K | (K << 2) | (K << 4) | (K << 6));
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
+    return __builtin_amdgcn_update_dpp(x, x, ctrl, 0xF, 0xF, true);
 }
 
 template <int B, int E, class F>
@@ -729,7 +733,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         // same tile (intra bit s) is read from its group's registers once
         // that group is done, not from memory.
         const unsigned intra = (active && pa.intra) ? (unsigned)pa.intra[pidx] : 0u;
-        const double* addr[NS];
+        const gdouble* addr[NS];
         bool need[NS];
         double own[NS];
         int src_lane[NS];
@@ -738,11 +742,12 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
             const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
             const bool internal = (intra >> s) & 1u;
             need[s] = active && on && ((kept >> s) & 1u) && !internal;
-            addr[s] = args.psi_cur;
+            addr[s] = (const gdouble*)args.psi_cur;
             own[s] = 0.0;
             src_lane[s] = lane;
             if (need[s]) {
-                addr[s] = args.psi_cur + ((size_t)d * args.E + nbs[s]) * N + S::tn(s ^ 1, S::local(row, s));
+                addr[s] = (const gdouble*)(args.psi_cur + ((size_t)d * args.E + nbs[s]) * N +
+                                            S::tn(s ^ 1, S::local(row, s)));
             }
             if (internal && on) {
                 const int g_up = (int)((intra >> (kIntraGroupShiftDev + 4 * s)) & 15u);
@@ -756,13 +761,17 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
             // groups already done (their x is final)
             // every face lane of a kept face polls its own upwind value
             // (one round trip per poll; the polling traffic is small)
+            // (all slots' loads are issued before the first compare)
+            double val[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                val[s] = need[s] ? __hip_atomic_load(addr[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
             bool have = true;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                if (need[s]) {
-                    const double val =
-                        __hip_atomic_load(const_cast<double*>(addr[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if ((unsigned long long)__double_as_longlong(val) != sent) { own[s] = val; need[s] = false; }
+                if (need[s] && (unsigned long long)__double_as_longlong(val[s]) != sent) {
+                    own[s] = val[s];
+                    need[s] = false;
                 }
                 if (need[s]) have = false;
             }
