@@ -320,7 +320,7 @@ BatchGraph& graph_for(snsw_batch* b, const double* const* in, double* const* out
 
 void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t s) {
     if (c.persistent) {
-        PersistArgs pa;
+        PersistArgs pa{};
         pa.table = L.table;
         pa.pairs = c.pairs;
         pa.ticket = L.tickets + (size_t)c.ticket * kTicketWords;
@@ -328,11 +328,12 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
         pa.total = c.level_off.back();
         pa.spin_limit = 1 << 20;
         pa.intra = c.intra;
+        pa.problem = class_problem(c);
         launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
     } else {
         for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
             const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
-            launch_sweep_level(c.dim, c.p, c.mixed, c.inv, L.table, c.pairs, b, n, s);
+            launch_sweep_level(c.dim, c.p, c.mixed, c.inv, L.table, c.pairs, b, n, class_problem(c), s);
         }
     }
     HIP_OK(hipGetLastError());

@@ -48,6 +48,9 @@ struct SweepClass {
     std::vector<int> members;          // table indices of its problems
 };
 
+// The table index shared by every entry of a one-problem class, else -1.
+inline int class_problem(const SweepClass& c) { return c.members.size() == 1 ? c.members[0] : -1; }
+
 // Optional HIP events around the sweep kernels of eager sweeps.
 struct LaunchProfiler {
     bool on = false;

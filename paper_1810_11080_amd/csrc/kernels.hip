@@ -31,6 +31,13 @@ constexpr int kDirMask = 1023;         // packed word: direction bits
 constexpr int kSlotShift = 10;         // then 3 bits per slot
 constexpr unsigned kOut = 0, kIn = 1, kKink = 2, kNone = 3;
 constexpr int kIntraGroupShiftDev = 8;   // intra word: group of slot s at bits 8 + 4 s
+#ifndef SNSW_WAIT_PRIO
+#define SNSW_WAIT_PRIO 0    // wavefront priority (0-3) while a persistent sweep waits and finishes
+#endif
+constexpr int kWaitPrio = SNSW_WAIT_PRIO;
+#ifndef SNSW_LEVEL_CHUNK_MIN
+#define SNSW_LEVEL_CHUNK_MIN 16   // level sweeps stream A^{-1} in chunks for n above this
+#endif
 #ifndef SNSW_POLL_SLEEP
 #define SNSW_POLL_SLEEP 1   // s_sleep units (64 clocks) between dependency polls
 #endif
@@ -72,9 +79,12 @@ struct Shape {
 // Table entry and problem index read through the constant address space, so
 // that a wavefront-uniform index gives scalar loads (neither is written while
 // a sweep kernel runs).
-__device__ __forceinline__ int batch_problem(const int4* pairs, int64_t t) {
+// Table index of the problem owning schedule entry t: `fixed` when the
+// schedule belongs to one problem (no load on the wavefront's critical path),
+// else read from the entry.
+__device__ __forceinline__ int batch_problem(const int4* pairs, int64_t t, int fixed) {
     typedef const __attribute__((address_space(4))) int* cint_ptr;
-    return ((cint_ptr)(const int*)(pairs + t))[3];
+    return fixed >= 0 ? fixed : ((cint_ptr)(const int*)(pairs + t))[3];
 }
 
 __device__ __forceinline__ SweepArgs load_args(const SweepArgs* table, int k) {
@@ -212,7 +222,7 @@ __device__ __forceinline__ void wave_sync() {
 // x = x0 + (LU)^{-1} r.
 template <int DIM, int P, bool MIXED>
 __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(const SweepArgs* table, const int4* pairs,
-                                                                 int64_t begin, int64_t count) {
+                                                                 int64_t begin, int64_t count, int problem) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, G = S::G;
     __shared__ double lds[kWaves][G][N + 1];
@@ -223,7 +233,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(const SweepArgs*
     // this wavefront's batch of G entries (one problem; count is a multiple of G)
     const int64_t wbase = begin + ((int64_t)blockIdx.x * kWaves + wave) * G;
     if (wbase >= begin + count) return;   // LDS is per wavefront: no block barrier follows
-    const SweepArgs args = load_args(table, batch_problem(pairs, wbase));
+    const SweepArgs args = load_args(table, batch_problem(pairs, wbase, problem));
     int4 pr = make_int4(-1, 0, 0, 0);
     if (in_group) pr = pairs[wbase + grp];
     const bool active = pr.x >= 0;    // padding entries have e = -1
@@ -400,7 +410,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
         if ((int64_t)t0 >= pa.total) break;
         unsigned t_pre = 0;
         if (lane == 0) t_pre = take_batch(pa.ticket) * (unsigned)G;
-        const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0));
+        const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0, pa.problem));
         const int64_t pidx = (int64_t)t0 + grp;
         int4 pr = make_int4(-1, 0, 0, 0);
         if (in_group && pidx < pa.total) pr = pa.pairs[pidx];
@@ -610,7 +620,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         if ((int64_t)t0 >= pa.total) break;
         unsigned t_pre = 0;
         if (lane == 0) t_pre = take_batch(pa.ticket) * (unsigned)G;
-        const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0));
+        const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0, pa.problem));
         const int64_t pidx = (int64_t)t0 + grp;
         int4 pr = make_int4(-1, 0, 0, 0);
         if (pidx < pa.total) pr = pa.pairs[pidx];
@@ -757,6 +767,9 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         constexpr unsigned long long gmask = N == 64 ? ~0ull : ((1ull << N) - 1ull);
         bool done = !active;
         int polls = 0;
+        // the wait and the finish are the critical path: issue priority
+        // over wavefronts that are still loading and assembling
+        if constexpr (kWaitPrio > 0) __builtin_amdgcn_s_setprio(kWaitPrio);
         while (true) {
             // groups already done (their x is final)
             // every face lane of a kept face polls its own upwind value
@@ -823,7 +836,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
                                        __HIP_MEMORY_SCOPE_AGENT);
                     done = true;
                 }
-                if (!pa.intra || !__any(fin)) break;
+                if (!pa.intra || !__any(fin) || __all(done)) break;
             }
             if (__all(done)) break;
             if (++polls > pa.spin_limit) {
@@ -838,6 +851,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
             }
             __builtin_amdgcn_s_sleep(SNSW_POLL_SLEEP);
         }
+        if constexpr (kWaitPrio > 0) __builtin_amdgcn_s_setprio(0);
         t_next = __shfl(t_pre, 0);
     }
 }
@@ -865,7 +879,7 @@ __global__ void __launch_bounds__(64 * kWaves) factor_kernel(const SweepArgs* ta
     const bool in_group = grp < G;
     const int64_t wbase = ((int64_t)blockIdx.x * kWaves + wave) * G;
     if (wbase >= count) return;   // LDS is per wavefront: no block barrier follows
-    const SweepArgs args = load_args(table, batch_problem(pairs, wbase));
+    const SweepArgs args = load_args(table, batch_problem(pairs, wbase, -1));
     int4 pr = make_int4(-1, 0, 0, 0);
     if (in_group) pr = pairs[wbase + grp];
     const bool active = pr.x >= 0;
@@ -966,7 +980,7 @@ __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int
 // through the wavefront's LDS, x = A^{-1} b.
 template <int DIM, int P>
 __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* table, const int4* pairs,
-                                                              int64_t begin, int64_t count) {
+                                                              int64_t begin, int64_t count, int problem) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, G = S::G;
     __shared__ double lds[kWaves][G][N + 1];
@@ -976,7 +990,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     const bool in_group = grp < G;
     const int64_t wbase = begin + ((int64_t)blockIdx.x * kWaves + wave) * G;
     if (wbase >= begin + count) return;   // LDS is per wavefront: no block barrier follows
-    const SweepArgs args = load_args(table, batch_problem(pairs, wbase));
+    const SweepArgs args = load_args(table, batch_problem(pairs, wbase, problem));
     int4 pr = make_int4(-1, 0, 0, 0);
     if (in_group) pr = pairs[wbase + grp];
     const bool active = pr.x >= 0;
@@ -986,7 +1000,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
     double* L = &lds[wave][in_group ? grp : 0][0];
     double x = 0.0;
-    if constexpr (N > 16) {
+    if constexpr (N > SNSW_LEVEL_CHUNK_MIN) {
         // large elements: b first, then A^{-1} streamed in column chunks
         // (fewer registers, more wavefronts in flight)
         const double b = inflow_rhs<DIM, P>(args, prs, row);
@@ -1039,7 +1053,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs 
         if ((int64_t)t0 >= pa.total) break;
         unsigned t_pre = 0;
         if (lane == 0) t_pre = take_batch(pa.ticket) * (unsigned)G;
-        const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0));
+        const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0, pa.problem));
         const int64_t pidx = (int64_t)t0 + grp;
         int4 pr = make_int4(-1, 0, 0, 0);
         if (in_group && pidx < pa.total) pr = pa.pairs[pidx];
@@ -1161,20 +1175,20 @@ __global__ void fill_sentinel_kernel(const SweepArgs* table) {
 }
 
 template <int DIM, int P>
-void launch_tpl(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, bool mixed, bool inv,
-                hipStream_t stream) {
+void launch_tpl(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem, bool mixed,
+                bool inv, hipStream_t stream) {
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
     if (inv)
         hipLaunchKernelGGL((sweep_level_inv<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, table,
-                           pairs, begin, count);
+                           pairs, begin, count, problem);
     else if (mixed)
         hipLaunchKernelGGL((sweep_level_fp64<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
-                           table, pairs, begin, count);
+                           table, pairs, begin, count, problem);
     else
         hipLaunchKernelGGL((sweep_level_fp64<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
-                           table, pairs, begin, count);
+                           table, pairs, begin, count, problem);
 }
 
 // groups of 4 or 16 lanes exchange values by DPP, the others through LDS
@@ -1297,15 +1311,15 @@ __global__ void residual_kernel(int64_t len, const double* __restrict__ a, const
 }  // namespace
 
 void launch_sweep_level(int dim, int p, bool mixed, bool inv, const SweepArgs* table, const int4* pairs,
-                        int64_t begin, int64_t count, hipStream_t stream) {
+                        int64_t begin, int64_t count, int problem, hipStream_t stream) {
     if (dim == 2) {
-        if (p == 1) launch_tpl<2, 1>(table, pairs, begin, count, mixed, inv, stream);
-        else if (p == 2) launch_tpl<2, 2>(table, pairs, begin, count, mixed, inv, stream);
-        else launch_tpl<2, 3>(table, pairs, begin, count, mixed, inv, stream);
+        if (p == 1) launch_tpl<2, 1>(table, pairs, begin, count, problem, mixed, inv, stream);
+        else if (p == 2) launch_tpl<2, 2>(table, pairs, begin, count, problem, mixed, inv, stream);
+        else launch_tpl<2, 3>(table, pairs, begin, count, problem, mixed, inv, stream);
     } else {
-        if (p == 1) launch_tpl<3, 1>(table, pairs, begin, count, mixed, inv, stream);
-        else if (p == 2) launch_tpl<3, 2>(table, pairs, begin, count, mixed, inv, stream);
-        else launch_tpl<3, 3>(table, pairs, begin, count, mixed, inv, stream);
+        if (p == 1) launch_tpl<3, 1>(table, pairs, begin, count, problem, mixed, inv, stream);
+        else if (p == 2) launch_tpl<3, 2>(table, pairs, begin, count, problem, mixed, inv, stream);
+        else launch_tpl<3, 3>(table, pairs, begin, count, problem, mixed, inv, stream);
     }
 }
 

@@ -53,6 +53,7 @@ struct PersistArgs {
     int64_t total;            // entries in the schedule
     int32_t spin_limit;       // polls per dependency wait before giving up
     const int32_t* intra;     // tiled schedules: intra-tile dependency word per entry (else null)
+    int32_t problem;          // table index of every entry, or -1 when entries name their problem
 };
 
 // Launches the persistent sweep kernel (all levels in one launch); inv: read
@@ -63,9 +64,10 @@ int persistent_blocks_per_cu(int dim, int p, bool inv);
 // Whether the persistent kernel of this shape has a cached-inverse variant.
 bool persistent_uses_inverse(int dim, int p);
 // Launches the level-sweep kernel over schedule entries [begin, begin+count)
-// (begin and count multiples of G); inv: x = A^{-1} b with cached inverses.
+// (begin and count multiples of G); inv: x = A^{-1} b with cached inverses;
+// problem: table index of every entry, or -1 when entries name their problem.
 void launch_sweep_level(int dim, int p, bool mixed, bool inv, const SweepArgs* table, const int4* pairs,
-                        int64_t begin, int64_t count, hipStream_t stream);
+                        int64_t begin, int64_t count, int problem, hipStream_t stream);
 // Computes and stores A^{-1} of schedule entries [0, count) of one problem.
 void launch_factor(int dim, int p, const SweepArgs* table, const int4* pairs, int64_t count, double* ainv,
                    hipStream_t stream);

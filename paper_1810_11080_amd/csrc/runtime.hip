@@ -163,7 +163,7 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
     }
     for (const SweepClass& c : classes) {
         if (c.persistent) {
-            PersistArgs pa;
+            PersistArgs pa{};
             pa.table = L.table;
             pa.pairs = c.pairs;
             pa.ticket = L.tickets + (size_t)c.ticket * kTicketWords;
@@ -171,6 +171,7 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             pa.total = c.level_off.back();
             pa.spin_limit = 1 << 20;
             pa.intra = c.intra;
+            pa.problem = class_problem(c);
             if (prof) prof->begin(s);
             launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
             if (prof) prof->end(s);
@@ -178,7 +179,7 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
                 const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
                 if (prof) prof->begin(s);
-                launch_sweep_level(c.dim, c.p, c.mixed, c.inv, L.table, c.pairs, b, n, s);
+                launch_sweep_level(c.dim, c.p, c.mixed, c.inv, L.table, c.pairs, b, n, class_problem(c), s);
                 if (prof) prof->end(s);
             }
         }
