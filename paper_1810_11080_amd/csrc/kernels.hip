@@ -31,10 +31,6 @@ constexpr int kDirMask = 1023;         // packed word: direction bits
 constexpr int kSlotShift = 10;         // then 3 bits per slot
 constexpr unsigned kOut = 0, kIn = 1, kKink = 2, kNone = 3;
 constexpr int kIntraGroupShiftDev = 8;   // intra word: group of slot s at bits 8 + 4 s
-#ifndef SNSW_WAIT_PRIO
-#define SNSW_WAIT_PRIO 0    // wavefront priority (0-3) while a persistent sweep waits and finishes
-#endif
-constexpr int kWaitPrio = SNSW_WAIT_PRIO;
 #ifndef SNSW_LEVEL_CHUNK_MIN
 #define SNSW_LEVEL_CHUNK_MIN 16   // level sweeps stream A^{-1} in chunks for n above this
 #endif
@@ -767,9 +763,6 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         constexpr unsigned long long gmask = N == 64 ? ~0ull : ((1ull << N) - 1ull);
         bool done = !active;
         int polls = 0;
-        // the wait and the finish are the critical path: issue priority
-        // over wavefronts that are still loading and assembling
-        if constexpr (kWaitPrio > 0) __builtin_amdgcn_s_setprio(kWaitPrio);
         while (true) {
             // groups already done (their x is final)
             // every face lane of a kept face polls its own upwind value
@@ -851,7 +844,6 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
             }
             __builtin_amdgcn_s_sleep(SNSW_POLL_SLEEP);
         }
-        if constexpr (kWaitPrio > 0) __builtin_amdgcn_s_setprio(0);
         t_next = __shfl(t_pre, 0);
     }
 }
