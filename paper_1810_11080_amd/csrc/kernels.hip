@@ -34,6 +34,15 @@ constexpr int kIntraGroupShiftDev = 8;   // intra word: group of slot s at bits 
 #ifndef SNSW_LEVEL_CHUNK_MIN
 #define SNSW_LEVEL_CHUNK_MIN 16   // level sweeps stream A^{-1} in chunks for n above this
 #endif
+#ifndef SNSW_RHS_SPLIT
+#define SNSW_RHS_SPLIT 0   // n > 16: slots per load group when assembling inflow (0: no split)
+#endif
+#ifndef SNSW_LEVEL_CHUNK
+#define SNSW_LEVEL_CHUNK 0        // level sweeps, n > 16: A^{-1} columns per chunk (0: automatic)
+#endif
+#ifndef SNSW_LEVEL_LDS_GROUP
+#define SNSW_LEVEL_LDS_GROUP 4    // level sweeps, n > 16: entries of b read from LDS per group
+#endif
 #ifndef SNSW_POLL_SLEEP
 #define SNSW_POLL_SLEEP 1   // s_sleep units (64 clocks) between dependency polls
 #endif
@@ -963,8 +972,69 @@ __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int
 #pragma unroll
             for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
         }
+        if constexpr (SNSW_RHS_SPLIT > 0 && N > 16)
+            if ((s + 1) % SNSW_RHS_SPLIT == 0) __builtin_amdgcn_sched_barrier(0);
     }
     if (kept_out) *kept_out = kept;
+    return rhs;
+}
+
+// Inflow of one pair assembled cooperatively (3D, n >= dim * nf): lane
+// (a, la) = (row / nf, row mod nf) contracts component a of the face moments
+// with the upwind trace, t = sum_b B_a[la][b] psi_up[b], so each lane loads
+// nf contiguous moments instead of a face lane loading dim * nf of them; the
+// dim partial sums of face-local row la meet in LDS (cf, [NS][dim * nf] per
+// pair) and are added to the rows on the face.  Same sums as inflow_rhs up to
+// their order.
+template <int DIM, int P>
+__device__ __forceinline__ double inflow_rhs_coop(const SweepArgs& args, int4 pr, int row, bool in_group,
+                                                  double (*cf)[DIM * Shape<DIM, P>::NF]) {
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, NF = S::NF, NS = S::NS;
+    static_assert(DIM * NF <= N, "one lane per moment row and component");
+    const int e = pr.x;
+    const unsigned packed = (unsigned)pr.y;
+    const int d = (int)(packed & kDirMask);
+    const int a = row / NF, la = row - a * NF;
+    const bool worker = in_group && a < DIM;
+    const double oa = args.omega[3 * d + (a < DIM ? a : 0)];
+    int kc = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+        const bool lagged = (packed >> (kSlotShift + 3 * s + 2)) & 1u;
+        int kr = 0;
+        if (cls == kKink) kr = args.kink_idx[pr.z + kc++];
+        if (cls == kOut || cls == kNone || !worker) continue;
+        const int nb = args.slot_nbr[(size_t)e * NS + s];
+        const double* up = (lagged ? args.psi_prev : args.psi_cur) + ((size_t)d * args.E + (nb >= 0 ? nb : 0)) * N;
+        double t = 0.0;
+        if (cls == kKink) {
+            // the tabulated inflow block is the whole moment: component 0 only
+            if (a == 0) {
+                const double* Ti = args.kink_tab + (size_t)kr * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + la * NF;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) t += Ti[b] * (nb >= 0 ? up[S::tn(s ^ 1, b)] : args.psi_inc);
+            }
+        } else {
+            const double* Bf = args.B + ((size_t)args.slot_face[(size_t)e * NS + s] * DIM + a) * NF * NF + la * NF;
+#pragma unroll
+            for (int b = 0; b < NF; ++b) t += Bf[b] * (nb >= 0 ? up[S::tn(s ^ 1, b)] : args.psi_inc);
+            t *= (s & 1) ? -oa : oa;   // P_in = -(outward normal) moments
+        }
+        cf[s][row] = t;
+    }
+    wave_sync();
+    double rhs = in_group ? args.src[(size_t)e * N + row] : 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+        if (cls == kOut || cls == kNone) continue;
+        if (S::coord(row, s / 2) != ((s & 1) ? P : 0)) continue;
+        const int l = S::local(row, s);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) rhs += cf[s][c * NF + l];
+    }
     return rhs;
 }
 
@@ -975,7 +1045,9 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
                                                               int64_t begin, int64_t count, int problem) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, G = S::G;
+    constexpr bool kCoop = DIM == 3 && DIM * S::NF <= N;
     __shared__ double lds[kWaves][G][N + 1];
+    __shared__ double cfl[kWaves][kCoop ? G : 1][kCoop ? S::NS : 1][DIM * S::NF];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = lane / N, row = lane - grp * N;
@@ -990,28 +1062,45 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     const int e = prs.x;
     const int d = (int)((unsigned)prs.y & kDirMask);
     const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
+    auto rhs_of = [&]() {
+        if constexpr (kCoop) return inflow_rhs_coop<DIM, P>(args, prs, row, in_group, cfl[wave][in_group ? grp : 0]);
+        else return inflow_rhs<DIM, P>(args, prs, row);
+    };
     double* L = &lds[wave][in_group ? grp : 0][0];
     double x = 0.0;
     if constexpr (N > SNSW_LEVEL_CHUNK_MIN) {
-        // large elements: b first, then A^{-1} streamed in column chunks
-        // (fewer registers, more wavefronts in flight)
-        const double b = inflow_rhs<DIM, P>(args, prs, row);
+        // large elements: b first; then the row of A^{-1} is loaded a chunk
+        // of columns at a time (all of it for n <= 32) while b is read back
+        // from LDS a few entries at a time.  The scheduling barriers keep
+        // the LDS values from all being live together (fewer registers, more
+        // wavefronts in flight); the empty asm keeps the products out of the
+        // store branch, where they would lose the barriers.
+        const double b = rhs_of();
         if (in_group) L[row] = b;
         wave_sync();
         __builtin_amdgcn_sched_barrier(0);
-        constexpr int CH = 9;
+        constexpr int CH = SNSW_LEVEL_CHUNK > 0 ? SNSW_LEVEL_CHUNK : (N <= 32 ? N : 16);
+        constexpr int LG = SNSW_LEVEL_LDS_GROUP;
 #pragma unroll
         for (int j0 = 0; j0 < N; j0 += CH) {
+            double a[CH];
 #pragma unroll
-            for (int j = j0; j < j0 + CH && j < N; ++j) x += Ai[j * N] * L[j];
+            for (int j = 0; j < CH; ++j) a[j] = j0 + j < N ? Ai[(j0 + j) * N] : 0.0;
+#pragma unroll
+            for (int g0 = 0; g0 < CH; g0 += LG) {
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int j = g0; j < g0 + LG && j < CH && j0 + j < N; ++j) x += a[j] * L[j0 + j];
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
+        __asm__ volatile("" : "+v"(x));
     } else {
         // the row of A^{-1} is loaded while b is assembled
         double m[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
-        const double b = inflow_rhs<DIM, P>(args, prs, row);
+        const double b = rhs_of();
         if (in_group) L[row] = b;
         wave_sync();
 #pragma unroll
