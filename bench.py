@@ -241,6 +241,58 @@ def learned_vs_plain(nx=16, p=2, sn_order=8, train_seeds=(0, 1, 2, 3), eval_seed
                          "break_even_solves": round((data_s + train_s) / saved, 1) if saved > 0 else None}}
 
 
+def lagged_face_fraction(P, P_face) -> float:
+    """Share of the face-weighted coupling that a problem's cut lags: the sum
+    over its removed edges of the face weights (taken from P_face, the same
+    mesh built with face weighting) over the sum of all face weights."""
+    import numpy as np
+    lag = tot = 0
+    for d in range(P.D):
+        up, down, w = P_face.edges(d)
+        wd = {(int(u), int(v)): int(x) for u, v, x in zip(up, down, w)}
+        tot += int(np.sum(w))
+        rd, ru = P.removed_edges(d)
+        lag += sum(wd[(int(u), int(v))] for u, v in zip(ru, rd))
+    return lag / max(tot, 1)
+
+
+def weighting_study(tol: float = 1e-8, max_iters: int = 20000):
+    """Unity vs face vs sigma-inverse-face edge weights on meshes whose sweep
+    graphs have cycles (eq. graphWeight and the cycle-cutting of section 3):
+    removed edges, largest SCC, levels, share of the face coupling that is
+    lagged, and plain source iteration to `tol` on the GPU."""
+    import dataclasses
+    import torch
+    import workloads as W
+    from paper_1810_11080_amd import Context, Problem
+    ctx = Context(0)
+    host = Context(-1)
+    cases = [W.standin_2d(16, 21), W.standin_2d(32, 42), W.standin_3d(), W.cyclic_2d(32, 4, 0.9, 2, 8),
+             W.cyclic_2d(64, 8, 0.9, 2, 8), W.c2()]
+    names = {0: "unity", 1: "face", 2: "siginvface"}
+    rows = []
+    for wp in cases:
+        P_face = Problem.from_workload(host, dataclasses.replace(wp, weighting=1))
+        for wgt in (0, 1, 2):
+            P = Problem.from_workload(ctx, dataclasses.replace(wp, weighting=wgt))
+            st = [P.graph_stats(d) for d in range(P.D)]
+            frac = lagged_face_fraction(P, P_face)
+            phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+            rep = P.solve(phi, tol=tol, max_iters=max_iters)
+            row = {"case": wp.name, "weighting": names[wgt], "E": P.E, "D": P.D,
+                   "removed": int(sum(x["n_removed"] for x in st)),
+                   "max_scc": int(max(x["max_scc"] for x in st)),
+                   "levels_max": int(max(x["n_levels"] for x in st)),
+                   "lagged_face_coupling": round(frac, 6),
+                   "iterations": int(rep["iterations"]), "solve_s": round(rep["seconds"], 4)}
+            rows.append(row)
+            print("| {case} | {weighting} | {removed} | {max_scc} | {levels_max} | {lagged_face_coupling:.4%} | "
+                  "{iterations} | {solve_s} |".format(**row), file=sys.stderr, flush=True)
+            P.close()
+        P_face.close()
+    return rows
+
+
 def calibrate_copy(nbytes: int = 1 << 30, reps: int = 3):
     """A plain streaming kernel of known traffic (read nbytes, write nbytes):
     the reference for scaling HBM counter readings to bytes."""
@@ -272,6 +324,8 @@ def main():
                     help="only the learned-vs-plain comparison at the full 48^3 S12 size (minutes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a copy kernel of known size (HBM counter calibration)")
+    ap.add_argument("--weighting-study", action="store_true",
+                    help="only the unity / face / sigma-inverse-face weighting comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -287,6 +341,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.weighting_study:
+        print(json.dumps({"weighting_study": weighting_study()}))
         return
     if args.learned_only == "c5":
         res = learned_vs_plain(nx=48, p=2, sn_order=12, train_seeds=(0, 1), eval_seeds=(100,), steps=2000,

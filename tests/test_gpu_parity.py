@@ -81,6 +81,10 @@ SMALL = {
     "single2d": lambda: W.small(dim=2, n=1, r=2, p=3, N=4, amp=0.0),
     "single3d": lambda: W.small(dim=3, n=1, r=1, p=2, N=2, amp=0.0),
     "strip": lambda: W.make_problem("strip", 2, (40, 1), 2, 2, 6, 0.02, 1, 1.0, 0.5, 1.0),
+    # strongly warped stand-ins of the weighting study (cycles of up to 10
+    # elements, inflow 1, sources varying per element)
+    "standin2d": lambda: W.standin_2d(16, 21),
+    "standin3d": lambda: W.standin_3d(p=1),
 }
 
 

@@ -13,6 +13,11 @@ CASES = {
     "c2crop": lambda: W.make_problem("c2crop", 2, (32, 32), 3, 3, 8, 0.3 / 32, 8, 1.0, 0.8, 1.0),
     "warp3d": lambda: W.small(dim=3, n=4, r=2, p=2, N=4, amp=0.08, freq=1),
     "ragged3d": lambda: W.make_problem("r3", 3, (5, 3, 2), 2, 1, 2, 0.06, 1, 1.0, 0.5, 1.0),
+    # strongly warped meshes of the weighting study: cycles of up to 10
+    # elements at S2 (exact cut), up to 16 at S8 (Eades-Lin-Smyth)
+    "standin2d": lambda: W.standin_2d(16, 21),
+    "standin3d": lambda: W.standin_3d(p=1),
+    "strongcyc": lambda: W.cyclic_2d(16, 2, 0.9, 1, 8),
 }
 
 

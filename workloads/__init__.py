@@ -183,6 +183,68 @@ def c5_reduced(seed: int = 100, nx: int = 12, p: int = 1, sn_order: int = 4) -> 
                         2, p, sn_order, 0.05, 1, st, 0.99, 1.0, tol=1e-8)
 
 
+def element_centres(dim: int, nx, r: int, lattice: np.ndarray) -> np.ndarray:
+    """(E, dim) mean of each element's control points (used to place
+    analytic sources on elements)."""
+    shape = lattice_shape(dim, nx, r)
+    grid = lattice.reshape(tuple(reversed(shape)) + (dim,))
+    ijk = element_ijk(dim, nx)
+    out = np.zeros((len(ijk), dim))
+    for e, idx in enumerate(ijk):
+        sl = tuple(slice(r * idx[a], r * idx[a] + r + 1) for a in reversed(range(dim)))
+        out[e] = grid[sl].reshape(-1, dim).mean(axis=0)
+    return out
+
+
+def strong_warp_amp(dim: int, slope: float, freq: int) -> float:
+    """Warp amplitude whose largest slope amp*2*pi*freq is `slope`.  The
+    Jacobian determinant of the warp is 1 + sum_a dW/dX_a >= 1 - slope in 2D
+    and >= 1 - 1.155 slope in 3D (the largest of sum_a of the partial
+    derivatives of prod_j sin), so slope < 1 (2D) / < 0.866 (3D) keeps the
+    map invertible."""
+    return slope / (2.0 * math.pi * freq)
+
+
+def cyclic_2d(n: int = 32, freq: int = 8, slope: float = 0.9, p: int = 2, sn_order: int = 8,
+              c: float = 0.9) -> Problem:
+    """Strongly warped 2D n x n Q3 mesh: faces tilt past the directions of
+    the quadrature, so the sweep graphs have cycles (at n = 32, S8: up to 4
+    elements per cycle with freq 8, up to 16 with freq 4); p, S_N,
+    sigma_t = 1, scattering ratio c, q = 1, vacuum."""
+    return make_problem(f"cyc_2d_{n}x{n}_q3_f{freq}_s{slope}_p{p}_s{sn_order}", 2, (n, n), 3, p, sn_order,
+                        strong_warp_amp(2, slope, freq), freq, 1.0, c, 1.0, tol=1e-8)
+
+
+def standin_2d(nx: int = 16, ny: int = 21, slope: float = 0.9, p: int = 2) -> Problem:
+    """Stand-in shaped like the paper's 2D weighting tests (336 or 1344 Q3
+    elements, S2, sigma_s = 1, sigma_t = 2, q = 1 + sin^2(2x + y), isotropic
+    inflow 1) on a strongly warped unit square (warp frequency nx/4) instead
+    of the paper's meshes, which are not available; q is evaluated at
+    element centres."""
+    freq = max(1, nx // 4)
+    lat = make_lattice(2, (nx, ny), 3, strong_warp_amp(2, slope, freq), freq)
+    xc = element_centres(2, (nx, ny), 3, lat)
+    q = 1.0 + np.sin(2.0 * xc[:, 0] + xc[:, 1]) ** 2
+    wp = make_problem(f"standin_2d_{nx}x{ny}_q3_p{p}_s2", 2, (nx, ny), 3, p, 2,
+                      strong_warp_amp(2, slope, freq), freq, 2.0, 0.5, q, bc_kind=ISO_CONST,
+                      psi_inc=1.0, tol=1e-8)
+    return wp
+
+
+def standin_3d(slope: float = 0.8, p: int = 2) -> Problem:
+    """Stand-in shaped like the paper's 3D weighting test (8 x 8 x 4 Q3
+    elements, S2, sigma_s = 1, sigma_t = 2, q = 1 + sin^2(4x + 2yz + 2y),
+    isotropic inflow 1) on a strongly warped unit cube (warp frequency 2)."""
+    nx = (8, 8, 4)
+    freq = 2
+    lat = make_lattice(3, nx, 3, strong_warp_amp(3, slope, freq), freq)
+    xc = element_centres(3, nx, 3, lat)
+    q = 1.0 + np.sin(4.0 * xc[:, 0] + 2.0 * xc[:, 1] * xc[:, 2] + 2.0 * xc[:, 1]) ** 2
+    return make_problem(f"standin_3d_8x8x4_q3_p{p}_s2", 3, nx, 3, p, 2,
+                        strong_warp_amp(3, slope, freq), freq, 2.0, 0.5, q, bc_kind=ISO_CONST,
+                        psi_inc=1.0, tol=1e-8)
+
+
 def small(dim=2, n=4, r=2, p=1, N=4, amp=0.05, freq=1, sigma_t=1.0, c=0.5,
           q=1.0, **kw) -> Problem:
     nx = (n,) * dim if np.isscalar(n) else tuple(n)
