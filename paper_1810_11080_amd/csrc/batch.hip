@@ -329,6 +329,7 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
         pa.spin_limit = 1 << 20;
         pa.intra = c.intra;
         pa.problem = class_problem(c);
+        pa.slots = c.slots;
         launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
     } else {
         for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {

@@ -44,6 +44,7 @@ struct SweepClass {
     int ticket = 0;                    // index into the ticket array
     const int4* pairs = nullptr;       // device schedule
     const int32_t* intra = nullptr;    // tiled schedule: intra-tile dependency words
+    const int4* slots = nullptr;       // per entry slot records (2D; else null: element tables)
     std::vector<int64_t> level_off;    // [L+1] offsets into pairs
     std::vector<int> members;          // table indices of its problems
 };
@@ -72,6 +73,7 @@ struct DeviceProblem {
     int4* pairs = nullptr;
     int4* tpairs = nullptr;       // tiled schedule (or null)
     int32_t* tintra = nullptr;
+    int4* tslots = nullptr;       // tiled schedule: per entry neighbours, faces, kink rows of its slots
     int32_t* slot_face = nullptr;
     int32_t* slot_nbr = nullptr;
     double* sigma_t = nullptr;

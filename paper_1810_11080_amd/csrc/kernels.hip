@@ -564,6 +564,11 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
 
 // Value of v on lane src of the wavefront (any lane; the source lane must be
 // active).
+// Component s (0..3) of an int4.
+__device__ __forceinline__ int int4_get(const int4& v, int s) {
+    return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
+}
+
 // A double in the global address space: loads through such pointers are
 // global (not flat) memory instructions.
 typedef __attribute__((address_space(1))) double gdouble;
@@ -629,6 +634,12 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         const int64_t pidx = (int64_t)t0 + grp;
         int4 pr = make_int4(-1, 0, 0, 0);
         if (pidx < pa.total) pr = pa.pairs[pidx];
+        // the entry's slot records, loaded together with the entry
+        int4 rec[3] = {make_int4(0, 0, 0, 0), make_int4(0, 0, 0, 0), make_int4(0, 0, 0, 0)};
+        if (pa.slots && pidx < pa.total) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) rec[k] = pa.slots[3 * pidx + k];
+        }
         const bool active = pr.x >= 0;    // padding entries have e = -1
         const int e = active ? pr.x : 0;
         const unsigned packed = (unsigned)pr.y;
@@ -653,7 +664,15 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         // ---- faces.  All index loads first (one round trip together with
         // the volume loads), then all face data (a second one).
         int nbs[NS], fcs[NS], krows[NS];
-        {
+        static_assert(NS == 4, "slot records hold four slots");
+        if (pa.slots) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                nbs[s] = int4_get(rec[0], s);
+                fcs[s] = int4_get(rec[1], s);
+                krows[s] = active ? int4_get(rec[2], s) : 0;
+            }
+        } else {
             int kc = 0;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {

@@ -54,6 +54,7 @@ struct PersistArgs {
     int32_t spin_limit;       // polls per dependency wait before giving up
     const int32_t* intra;     // tiled schedules: intra-tile dependency word per entry (else null)
     int32_t problem;          // table index of every entry, or -1 when entries name their problem
+    const int4* slots;        // 2D: per entry {neighbour[4]}, {face[4]}, {kink row[4]} of its slots, or null
 };
 
 // Launches the persistent sweep kernel (all levels in one launch); inv: read

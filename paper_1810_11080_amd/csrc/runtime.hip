@@ -172,6 +172,7 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             pa.spin_limit = 1 << 20;
             pa.intra = c.intra;
             pa.problem = class_problem(c);
+            pa.slots = c.slots;
             if (prof) prof->begin(s);
             launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
             if (prof) prof->end(s);
@@ -257,6 +258,27 @@ void device_upload(snsw_problem* prob) {
         HIP_OK(hipMemcpyAsync(dp->tpairs, hp.tpairs.data(), hp.tpairs.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, s));
         dp->tintra = dupload(dp, hp.tintra, s);
+        if (hp.dim == 2) {
+            // slot records of every tiled entry, read together with the entry
+            // (one round trip less before the element's inflow can be formed)
+            const int NS = 4;
+            const size_t Pt = hp.tpairs.size() / 4;
+            std::vector<int32_t> rec(Pt * 3 * NS, 0);
+            for (size_t t = 0; t < Pt; ++t) {
+                const int32_t e = hp.tpairs[4 * t], packed = hp.tpairs[4 * t + 1], kb = hp.tpairs[4 * t + 2];
+                if (e < 0) continue;
+                int kc = 0;
+                for (int sl = 0; sl < NS; ++sl) {
+                    rec[(3 * t + 0) * NS + sl] = hp.slot_nbr[(size_t)e * NS + sl];
+                    rec[(3 * t + 1) * NS + sl] = hp.slot_face[(size_t)e * NS + sl];
+                    const uint32_t cls = ((uint32_t)packed >> (kDirBits + 3 * sl)) & 3u;
+                    if (cls == SC_KINK) rec[(3 * t + 2) * NS + sl] = hp.kink_idx[(size_t)kb + kc++];
+                }
+            }
+            dp->tslots = dalloc<int4>(dp, Pt * 3);
+            HIP_OK(hipMemcpyAsync(dp->tslots, rec.data(), rec.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            HIP_OK(hipStreamSynchronize(s));
+        }
     }
     dp->slot_face = dupload(dp, hp.slot_face, s);
     dp->slot_nbr = dupload(dp, hp.slot_nbr, s);
@@ -301,6 +323,7 @@ void device_upload(snsw_problem* prob) {
         c.pairs = dp->tpairs;
         c.level_off = hp.tlevel_off;
         c.intra = dp->tintra;
+        c.slots = dp->tslots;
     }
     c.members = {0};
     c.blocks = persistent_grid(hp.dim, hp.p, c.inv, hp.level_off.back(), dp->device);
@@ -327,7 +350,7 @@ void device_release(snsw_problem* prob) noexcept {
     (void)hipSetDevice(dp->device);
     (void)hipStreamSynchronize(dp->stream);
     dp->prof.release();
-    void* ptrs[] = {dp->geo, dp->B, dp->kink_tab, dp->kink_idx, dp->pairs, dp->tpairs, dp->tintra,
+    void* ptrs[] = {dp->geo, dp->B, dp->kink_tab, dp->kink_idx, dp->pairs, dp->tpairs, dp->tintra, dp->tslots,
                     dp->slot_face, dp->slot_nbr,
                     dp->sigma_t, dp->sigma_s, dp->q, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
                     dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table, dp->ainv};
