@@ -788,11 +788,6 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
                 src_lane[s] = g_up * N + S::tn(s ^ 1, S::local(row, s));
             }
         }
-        // slots that are intra-tile for some lane of the wavefront (the
-        // others need no permutes in the finish passes)
-        bool intra_any[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) intra_any[s] = __any((intra >> s) & 1u);
         constexpr unsigned long long gmask = N == 64 ? ~0ull : ((1ull << N) - 1ull);
         bool done = !active;
         int polls = 0;
@@ -826,7 +821,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     perm[s] = 0.0;
-                    if (intra_any[s]) perm[s] = lane_read(x, src_lane[s]);
+                    if (pa.intra) perm[s] = lane_read(x, src_lane[s]);
                     if ((intra >> s) & 1u) {
                         const int g_up = (int)((intra >> (kIntraGroupShiftDev + 4 * s)) & 15u);
                         if (!((done_mask >> (g_up * N)) & 1ull)) ready_lane = false;
