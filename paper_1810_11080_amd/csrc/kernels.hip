@@ -34,9 +34,6 @@ constexpr int kIntraGroupShiftDev = 8;   // intra word: group of slot s at bits 
 #ifndef SNSW_LEVEL_CHUNK_MIN
 #define SNSW_LEVEL_CHUNK_MIN 16   // level sweeps stream A^{-1} in chunks for n above this
 #endif
-#ifndef SNSW_RHS_SPLIT
-#define SNSW_RHS_SPLIT 0   // n > 16: slots per load group when assembling inflow (0: no split)
-#endif
 #ifndef SNSW_LEVEL_CHUNK
 #define SNSW_LEVEL_CHUNK 0        // level sweeps, n > 16: A^{-1} columns per chunk (0: automatic)
 #endif
@@ -991,8 +988,6 @@ __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int
 #pragma unroll
             for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
         }
-        if constexpr (SNSW_RHS_SPLIT > 0 && N > 16)
-            if ((s + 1) % SNSW_RHS_SPLIT == 0) __builtin_amdgcn_sched_barrier(0);
     }
     if (kept_out) *kept_out = kept;
     return rhs;
