@@ -177,6 +177,27 @@ def test_constant_solution_full_size(torch, ctx):
     assert float((psi - C0).abs().max()) < 1e-10
 
 
+def test_constant_solution_c5_size(torch, ctx):
+    """The same exact constant solution on the 3D 48^3 Q2 p=2 S12 mesh of the
+    large configuration (168 directions, 18.6M pairs, two-material sigma_t
+    in {1, 100} of seed 100), in the launch configuration bench.py times
+    there (level schedule, cached inverses)."""
+    from paper_1810_11080_amd import Problem
+    C0 = 0.75
+    base = W.c5()
+    st = base.sigma_t
+    wp = W.make_problem("const3d", 3, base.nx, 2, 2, 12, 0.05, 1, st, 0.0, st * C0,
+                        bc_kind=W.ISO_CONST, psi_inc=C0)
+    P = Problem.from_workload(ctx, wp)
+    assert P.info()["cached_inverse"] == 1 and P.info()["schedule"] == 2
+    phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+    psi = torch.empty(P.D * P.E * P.n, dtype=torch.float64, device="cuda")
+    P.solve(phi, tol=1e-14, max_iters=20, psi=psi, raise_on_not_converged=False)
+    assert float((psi - C0).abs().max()) < 1e-10
+    assert float((phi - 4.0 * np.pi * C0).abs().max()) < 1e-9
+    P.close()
+
+
 def test_determinism_and_checkpoint(torch, ctx):
     from paper_1810_11080_amd import Problem
     wp = SMALL["cyclic2d_p2"]()
