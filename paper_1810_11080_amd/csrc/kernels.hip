@@ -1355,10 +1355,12 @@ __global__ void source_kernel(SweepArgs* table, const double* const* phi_list, c
     const int64_t e = t / n;
     const int i = (int)(t - e * n);
     const double c = a.sigma_s[e] * (0.25 / M_PI);
-    const double* M = a.geo + (size_t)e * (a.dim + 1) * n * n;
-    const double* qe = a.q + e * n;
-    const double* pe = phi + e * n;
+    // global (not flat) loads, eight columns of M in flight
+    const gdouble* M = (const gdouble*)(a.geo + (size_t)e * (a.dim + 1) * n * n);
+    const gdouble* qe = (const gdouble*)(a.q + e * n);
+    const gdouble* pe = (const gdouble*)(phi + e * n);
     double s = 0.0;
+#pragma unroll 8
     for (int j = 0; j < n; ++j) s += M[(size_t)j * n + i] * (qe[j] + c * pe[j]);
     a.src[t] = s;
 }
@@ -1369,9 +1371,12 @@ __global__ void scalar_flux_kernel(const SweepArgs* table, double* const* phi_li
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= En) return;
     double* __restrict__ phi = phi_list ? phi_list[blockIdx.y] : phi_one;
-    const double* __restrict__ psi = a.psi_cur;
+    // global (not flat) loads, eight directions in flight
+    const gdouble* __restrict__ psi = (const gdouble*)a.psi_cur;
+    const gdouble* __restrict__ w = (const gdouble*)a.w;
     double s = 0.0;
-    for (int d = 0; d < a.D; ++d) s += a.w[d] * psi[(size_t)d * En + t];
+#pragma unroll 8
+    for (int d = 0; d < a.D; ++d) s += w[d] * psi[(size_t)d * En + t];
     phi[t] = s;
 }
 
