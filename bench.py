@@ -402,8 +402,12 @@ def main():
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     inv = bool(info["cached_inverse"])
     if sched == 1:
-        dpp = wp.dim == 2 and wp.p != 2
-        kname = f"sweep_persistent_{'dpp' if dpp else 'fp64'}<{wp.dim},{wp.p}{',inv' if inv and dpp else ''}>"
+        if wp.dim == 2 and wp.p != 2:
+            kname = f"sweep_persistent_dpp<{wp.dim},{wp.p}{',inv' if inv else ''}>"
+        elif inv:
+            kname = f"sweep_persistent_lds2d<{wp.p}>" if wp.dim == 2 else f"sweep_persistent_inv<{wp.dim},{wp.p}>"
+        else:
+            kname = f"sweep_persistent_fp64<{wp.dim},{wp.p}>"
     else:
         kname = f"sweep_level_inv<{wp.dim},{wp.p}>" if inv else f"sweep_level_fp64<{wp.dim},{wp.p}>"
     if inv:

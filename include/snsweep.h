@@ -71,8 +71,9 @@ extern "C" {
 /* Device schedule of one sweep.  PERSISTENT: one launch; wavefronts claim
  * (element, direction) pairs in level order and wait only for the upwind
  * values they read (latency-bound sweeps: 2D).  LEVELS: one launch per level
- * (throughput-bound sweeps: 3D).  AUTO picks PERSISTENT for 2D p = 1 or 3
- * in FP64 and LEVELS otherwise; SNSW_PREC_MIXED requires LEVELS.          */
+ * (throughput-bound sweeps: 3D).  AUTO picks PERSISTENT for 2D FP64
+ * problems (for p = 2 unless cache_inverse is SNSW_CACHE_OFF) and LEVELS
+ * otherwise; SNSW_PREC_MIXED requires LEVELS.                              */
 #define SNSW_SCHED_AUTO        0
 #define SNSW_SCHED_PERSISTENT  1
 #define SNSW_SCHED_LEVELS      2

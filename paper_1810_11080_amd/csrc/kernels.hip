@@ -874,6 +874,183 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
 }
 
 
+// Persistent sweep with cached inverses for 2D groups that DPP cannot
+// broadcast within (p = 2, n = 9 lanes): the protocol of
+// sweep_persistent_dpp with LDS exchanges.  Before the wait each face lane
+// parks its inflow row P_in,s[la] of every kept slot in LDS and the lagged
+// and boundary inflow go into b; every face lane of a kept face then polls
+// all nf upwind values of the face (all loads of a poll issued together),
+// and each group finishes as soon as its lanes hold them: b += P_in psi_up
+// on the face lanes, b through LDS, x = A^{-1} b, device-scope store.  The
+// groups of a wavefront do not wait for each other.
+template <int P>
+__global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArgs pa) {
+    constexpr int DIM = 2;
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
+    __shared__ double lds[kWaves][G][N + 1];
+    __shared__ double pin_lds[kWaves][G][NS][NF][NF + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / N, row = lane - grp * N;
+    const bool in_group = grp < G;
+    const int g0 = in_group ? grp : 0;
+    double* L = &lds[wave][g0][0];
+    const unsigned long long sent = kSentinel;
+    constexpr unsigned long long gmask = (1ull << N) - 1ull;
+
+    unsigned t_next = 0;
+    if (lane == 0) t_next = take_batch(pa.ticket) * (unsigned)G;
+    t_next = __shfl(t_next, 0);
+    while (true) {
+        const unsigned t0 = __builtin_amdgcn_readfirstlane(t_next);
+        if ((int64_t)t0 >= pa.total) break;
+        unsigned t_pre = 0;
+        if (lane == 0) t_pre = take_batch(pa.ticket) * (unsigned)G;
+        const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0, pa.problem));
+        const int64_t pidx = (int64_t)t0 + grp;
+        int4 pr = make_int4(-1, 0, 0, 0);
+        if (in_group && pidx < pa.total) pr = pa.pairs[pidx];
+        const bool active = pr.x >= 0;    // padding entries have e = -1
+        const int4 prs = active ? pr : make_int4(0, 0, 0, 0);
+        const int e = prs.x;
+        const unsigned packed = (unsigned)prs.y;
+        const int d = (int)(packed & kDirMask);
+        const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
+        double m[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+
+        // ---- faces: index loads first, then face data
+        int nbs[NS], fcs[NS], krows[NS];
+        {
+            int kc = 0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                nbs[s] = args.slot_nbr[(size_t)e * NS + s];
+                fcs[s] = args.slot_face[(size_t)e * NS + s];
+                const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+                krows[s] = (active && cls == kKink) ? args.kink_idx[prs.z + kc] : 0;
+                kc += (cls == kKink) ? 1 : 0;
+            }
+        }
+        double rhs = args.src[(size_t)e * N + row];
+        const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1];
+        unsigned kept = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const unsigned cls = active ? (packed >> (kSlotShift + 3 * s)) & 3u : kNone;
+            const bool lagged = (packed >> (kSlotShift + 3 * s + 2)) & 1u;
+            if (cls == kNone || cls == kOut) continue;
+            const int nb = nbs[s];
+            const bool defer = nb >= 0 && !lagged;
+            if (defer) kept |= 1u << s;
+            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+            if (!on) continue;
+            const int la = S::local(row, s);
+            double pin[NF];
+            if (cls == kKink) {
+                const double* Ti = args.kink_tab + (size_t)krows[s] * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + la * NF;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) pin[b] = Ti[b];
+            } else {
+                const double* Bf = args.B + (size_t)fcs[s] * DIM * NF * NF + la * NF;
+                const double sgn = (s & 1) ? -1.0 : 1.0;   // P_in = -(outward normal) moments
+#pragma unroll
+                for (int b = 0; b < NF; ++b) pin[b] = sgn * (o0 * Bf[b] + o1 * Bf[NF * NF + b]);
+            }
+            if (defer) {
+#pragma unroll
+                for (int b = 0; b < NF; ++b) pin_lds[wave][grp][s][la][b] = pin[b];
+            } else if (nb >= 0) {
+                const double* up = args.psi_prev + ((size_t)d * args.E + nb) * N;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) rhs += pin[b] * up[S::tn(s ^ 1, b)];
+            } else {
+#pragma unroll
+                for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
+            }
+        }
+
+        // ---- wait and finish
+        const gdouble* up[NS];
+        bool need[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+            need[s] = active && on && ((kept >> s) & 1u);
+            up[s] = (const gdouble*)(args.psi_cur + ((size_t)d * args.E + (need[s] ? nbs[s] : 0)) * N);
+        }
+        double vals[NS][NF];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int b = 0; b < NF; ++b) vals[s][b] = 0.0;
+        bool done = !active;
+        int polls = 0;
+        while (true) {
+            double v[NS][NF];
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int b = 0; b < NF; ++b)
+                    v[s][b] = need[s] ? __hip_atomic_load(up[s] + S::tn(s ^ 1, b), __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                      : 0.0;
+            bool have = true;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (!need[s]) continue;
+                bool all = true;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) all = all && (unsigned long long)__double_as_longlong(v[s][b]) != sent;
+                if (all) {
+#pragma unroll
+                    for (int b = 0; b < NF; ++b) vals[s][b] = v[s][b];
+                    need[s] = false;
+                } else {
+                    have = false;
+                }
+            }
+            const unsigned long long ready = __ballot(have);
+            const bool fin = in_group && !done && ((ready >> (grp * N)) & gmask) == gmask;
+            if (fin) {
+                // the whole group takes this branch together
+                double b = rhs;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+                    if (!(on && ((kept >> s) & 1u))) continue;
+                    const int la = S::local(row, s);
+#pragma unroll
+                    for (int bb = 0; bb < NF; ++bb) b += pin_lds[wave][grp][s][la][bb] * vals[s][bb];
+                }
+                L[row] = b;
+                wave_sync();
+                double x = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) x += m[j] * L[j];
+                __hip_atomic_store(args.psi_cur + ((size_t)d * args.E + e) * N + row, x, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                done = true;
+            }
+            if (__all(done)) break;
+            if (++polls > pa.spin_limit) {
+                atomicExch(pa.error, 1);
+                break;
+            }
+            if ((polls & 255) == 0) {
+                // another wait already failed: stop waiting so the grid drains
+                int err = 0;
+                if (lane == 0) err = __hip_atomic_load(pa.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__shfl(err, 0)) break;
+            }
+            __builtin_amdgcn_s_sleep(SNSW_POLL_SLEEP);
+        }
+        t_next = __shfl(t_pre, 0);
+    }
+}
+
+
 // ---- cached element inverses ------------------------------------------
 //
 // The element operator A = sigma_t M - sum_i Omega_i K_i + outflow blocks of
@@ -1301,6 +1478,12 @@ void launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, hipStream_t 
         else
             hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
                                stream, a);
+    } else if constexpr (DIM == 2) {
+        if (inv)
+            hipLaunchKernelGGL((sweep_persistent_lds2d<P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, a);
+        else
+            hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                               stream, a);
     } else {
         if (inv)
             hipLaunchKernelGGL((sweep_persistent_inv<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
@@ -1327,6 +1510,9 @@ int occupancy_tpl(bool inv) {
     if constexpr (use_dpp<DIM, P>())
         rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, true>, 64 * kWaves, 0)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, false>, 64 * kWaves, 0);
+    else if constexpr (DIM == 2)
+        rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_lds2d<P>, 64 * kWaves, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P>, 64 * kWaves, 0);
     else
         rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_inv<DIM, P>, 64 * kWaves, 0)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P>, 64 * kWaves, 0);

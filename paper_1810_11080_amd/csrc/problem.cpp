@@ -117,10 +117,15 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
         if (hp.schedule != SNSW_SCHED_AUTO && hp.schedule != SNSW_SCHED_PERSISTENT &&
             hp.schedule != SNSW_SCHED_LEVELS)
             throw Error(SNSW_E_INVALID_ARG, "schedule must be AUTO, PERSISTENT or LEVELS");
-        if (hp.schedule == SNSW_SCHED_AUTO)
-            hp.schedule = (hp.dim == 2 && hp.p != 2 && desc->precision == SNSW_PREC_FP64) ? SNSW_SCHED_PERSISTENT
-                                                                                      : SNSW_SCHED_LEVELS;
         hp.cache_inverse = desc->cache_inverse;
+        if (hp.schedule == SNSW_SCHED_AUTO) {
+            // 2D FP64 sweeps are latency-bound: persistent (p = 2 only with
+            // cached inverses; its assembled persistent kernel is slower than
+            // the level schedule)
+            const bool ok = hp.dim == 2 && desc->precision == SNSW_PREC_FP64 &&
+                            (hp.p != 2 || hp.cache_inverse != SNSW_CACHE_OFF);
+            hp.schedule = ok ? SNSW_SCHED_PERSISTENT : SNSW_SCHED_LEVELS;
+        }
         if (hp.cache_inverse != SNSW_CACHE_AUTO && hp.cache_inverse != SNSW_CACHE_ON &&
             hp.cache_inverse != SNSW_CACHE_OFF)
             throw Error(SNSW_E_INVALID_ARG, "cache_inverse must be AUTO, ON or OFF");
