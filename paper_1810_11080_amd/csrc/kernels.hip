@@ -1301,7 +1301,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
 }
 
 
-// Persistent sweep with cached inverses for the LDS shapes (n = 8, 9, 27,
+// Persistent sweep with cached inverses for the 3D LDS shapes (n = 8, 27,
 // 64): the ticket and wait protocol of sweep_persistent_fp64; per pair the
 // row of A^{-1} is loaded and b assembled without the kept inflow before the
 // wait; after it the face lanes add the kept inflow and x = A^{-1} b is one
