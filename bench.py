@@ -268,8 +268,8 @@ def weighting_study(tol: float = 1e-8, max_iters: int = 20000):
     from paper_1810_11080_amd import Context, Problem
     ctx = Context(0)
     host = Context(-1)
-    cases = [W.standin_2d(16, 21), W.standin_2d(32, 42), W.standin_3d(), W.cyclic_2d(32, 4, 0.9, 2, 8),
-             W.cyclic_2d(64, 8, 0.9, 2, 8), W.c2()]
+    cases = [W.standin_2d(16, 21), W.standin_2d(32, 42), W.standin_3d(), W.annulus_quarter(9, 15, 3, 4),
+             W.annulus_quarter(18, 30, 3, 4), W.cyclic_2d(32, 4, 0.9, 2, 8), W.cyclic_2d(64, 8, 0.9, 2, 8), W.c2()]
     names = {0: "unity", 1: "face", 2: "siginvface"}
     rows = []
     for wp in cases:

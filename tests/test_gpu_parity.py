@@ -85,6 +85,8 @@ SMALL = {
     # elements, inflow 1, sources varying per element)
     "standin2d": lambda: W.standin_2d(16, 21),
     "standin3d": lambda: W.standin_3d(p=1),
+    # curved domain boundary (quarter annulus, three material rings)
+    "annulus": lambda: W.annulus_quarter(9, 15, 3, 4),
 }
 
 

@@ -18,6 +18,8 @@ CASES = {
     "standin2d": lambda: W.standin_2d(16, 21),
     "standin3d": lambda: W.standin_3d(p=1),
     "strongcyc": lambda: W.cyclic_2d(16, 2, 0.9, 1, 8),
+    # curved domain boundary: quarter annulus, cycles of up to 9 elements
+    "annulus": lambda: W.annulus_quarter(9, 15, 3, 4),
 }
 
 

@@ -245,6 +245,28 @@ def standin_3d(slope: float = 0.8, p: int = 2) -> Problem:
                         psi_inc=1.0, tol=1e-8)
 
 
+def annulus_quarter(nr: int = 9, nt: int = 15, p: int = 3, sn_order: int = 4, r_in: float = 1.0,
+                    r_out: float = 2.0) -> Problem:
+    """Quarter annulus r in [r_in, r_out], theta in [0, pi/2], nr x nt Q3
+    elements (radial index fastest), control points on circles, so the arcs
+    are curved boundaries and curved interior faces; three nested rings of
+    equal width with sigma_t = 2.0, 2.2, 2.4 and sigma_s = 1 (the material
+    table of the paper's nested-annuli problem, whose dimensions are not
+    given), q = 1, vacuum.  A quarter of the paper's coarse and refined HO
+    element counts (540, 2160) is 9 x 15 and 18 x 30."""
+    r = 3
+    unit = make_lattice(2, (nr, nt), r, 0.0, 1)
+    rad = r_in + (r_out - r_in) * unit[:, 0]
+    th = 0.5 * math.pi * unit[:, 1]
+    lattice = np.stack([rad * np.cos(th), rad * np.sin(th)], axis=1)
+    ring = np.minimum(element_ijk(2, (nr, nt))[:, 0] * 3 // nr, 2)
+    st = np.array([2.0, 2.2, 2.4])[ring]
+    E = nr * nt
+    return Problem(name=f"annulus_quarter_{nr}x{nt}_q3_p{p}_s{sn_order}", dim=2, nx=(nr, nt), r=r, p=p,
+                   sn_order=sn_order, lattice=lattice, sigma_t=st, sigma_s=np.ones(E), q=np.ones(E),
+                   tol=1e-8, meta=dict(r_in=r_in, r_out=r_out))
+
+
 def small(dim=2, n=4, r=2, p=1, N=4, amp=0.05, freq=1, sigma_t=1.0, c=0.5,
           q=1.0, **kw) -> Problem:
     nx = (n,) * dim if np.isscalar(n) else tuple(n)
