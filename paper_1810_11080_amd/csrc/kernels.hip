@@ -40,6 +40,9 @@ constexpr int kIntraGroupShiftDev = 8;   // intra word: group of slot s at bits 
 #ifndef SNSW_LEVEL_LDS_GROUP
 #define SNSW_LEVEL_LDS_GROUP 4    // level sweeps, n > 16: entries of b read from LDS per group
 #endif
+#ifndef SNSW_AINV_NT
+#define SNSW_AINV_NT 1   // stream the cached inverses with non-temporal loads
+#endif
 #ifndef SNSW_POLL_SLEEP
 #define SNSW_POLL_SLEEP 1   // s_sleep units (64 clocks) between dependency polls
 #endif
@@ -561,6 +564,18 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
 
 // Value of v on lane src of the wavefront (any lane; the source lane must be
 // active).
+// A load of a cached inverse.  Each entry of A^{-1} is read once per sweep,
+// so it is loaded as streaming (non-temporal) data that should not push the
+// face moments, sources and upwind traces, which are reused, out of the
+// caches.
+__device__ __forceinline__ double ainv_load(const double* p) {
+#if SNSW_AINV_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
 // Component s (0..3) of an int4.
 __device__ __forceinline__ int int4_get(const int4& v, int s) {
     return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
@@ -650,7 +665,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
             // row `row` of the cached A^{-1} (stored column-major)
             const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
 #pragma unroll
-            for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+            for (int j = 0; j < N; ++j) m[j] = ainv_load(Ai + j * N);
         } else {
             const double* Ge = args.geo + (size_t)e * (DIM + 1) * N * N + row;
             const double st = args.sigma_t[e];
@@ -918,7 +933,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
         const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
         double m[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+        for (int j = 0; j < N; ++j) m[j] = ainv_load(Ai + j * N);
 
         // ---- faces: index loads first, then face data
         int nbs[NS], fcs[NS], krows[NS];
@@ -1276,7 +1291,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
         for (int j0 = 0; j0 < N; j0 += CH) {
             double a[CH];
 #pragma unroll
-            for (int j = 0; j < CH; ++j) a[j] = j0 + j < N ? Ai[(j0 + j) * N] : 0.0;
+            for (int j = 0; j < CH; ++j) a[j] = j0 + j < N ? ainv_load(Ai + (j0 + j) * N) : 0.0;
 #pragma unroll
             for (int g0 = 0; g0 < CH; g0 += LG) {
                 __builtin_amdgcn_sched_barrier(0);
@@ -1290,7 +1305,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
         // the row of A^{-1} is loaded while b is assembled
         double m[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+        for (int j = 0; j < N; ++j) m[j] = ainv_load(Ai + j * N);
         const double b = rhs_of();
         if (in_group) L[row] = b;
         wave_sync();
@@ -1337,7 +1352,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs 
         const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
         double m[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+        for (int j = 0; j < N; ++j) m[j] = ainv_load(Ai + j * N);
         unsigned kept = 0;
         double rhs = inflow_rhs<DIM, P, true>(args, prs, row, &kept);
         if (!active) kept = 0;
