@@ -330,6 +330,7 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
         pa.intra = c.intra;
         pa.problem = class_problem(c);
         pa.slots = c.slots;
+        pa.nt = 0;
         launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
     } else {
         for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {

@@ -40,9 +40,6 @@ constexpr int kIntraGroupShiftDev = 8;   // intra word: group of slot s at bits 
 #ifndef SNSW_LEVEL_LDS_GROUP
 #define SNSW_LEVEL_LDS_GROUP 4    // level sweeps, n > 16: entries of b read from LDS per group
 #endif
-#ifndef SNSW_AINV_NT
-#define SNSW_AINV_NT 1   // stream the cached inverses with non-temporal loads
-#endif
 #ifndef SNSW_POLL_SLEEP
 #define SNSW_POLL_SLEEP 1   // s_sleep units (64 clocks) between dependency polls
 #endif
@@ -564,17 +561,6 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
 
 // Value of v on lane src of the wavefront (any lane; the source lane must be
 // active).
-// A load of a cached inverse.  Each entry of A^{-1} is read once per sweep,
-// so it is loaded as streaming (non-temporal) data that should not push the
-// face moments, sources and upwind traces, which are reused, out of the
-// caches.
-__device__ __forceinline__ double ainv_load(const double* p) {
-#if SNSW_AINV_NT
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
 
 // Component s (0..3) of an int4.
 __device__ __forceinline__ int int4_get(const int4& v, int s) {
@@ -619,7 +605,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 // deferred slots are parked in LDS (each face lane writes its own row), and
 // after the wait the face lanes form c = P_in psi_up, which is broadcast into
 // x += A^{-1}[:, tn_s] c.
-template <int DIM, int P, bool INV>
+template <int DIM, int P, bool INV, bool NT = false>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3, 8))) sweep_persistent_dpp(PersistArgs pa) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
@@ -662,10 +648,18 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         // copies of the row alive).
         double m[N];
         if constexpr (INV) {
-            // row `row` of the cached A^{-1} (stored column-major)
+            // row `row` of the cached A^{-1} (stored column-major; a column
+            // of n = 4 or 16 doubles lies in one 128 B line).  NT: read as
+            // streaming (non-temporal) data, once per sweep, so that it does
+            // not push the reused face data out of the caches
             const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
+            if constexpr (NT) {
 #pragma unroll
-            for (int j = 0; j < N; ++j) m[j] = ainv_load(Ai + j * N);
+                for (int j = 0; j < N; ++j) m[j] = __builtin_nontemporal_load(Ai + j * N);
+            } else {
+#pragma unroll
+                for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+            }
         } else {
             const double* Ge = args.geo + (size_t)e * (DIM + 1) * N * N + row;
             const double st = args.sigma_t[e];
@@ -933,7 +927,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
         const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
         double m[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) m[j] = ainv_load(Ai + j * N);
+        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
 
         // ---- faces: index loads first, then face data
         int nbs[NS], fcs[NS], krows[NS];
@@ -1291,7 +1285,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
         for (int j0 = 0; j0 < N; j0 += CH) {
             double a[CH];
 #pragma unroll
-            for (int j = 0; j < CH; ++j) a[j] = j0 + j < N ? ainv_load(Ai + (j0 + j) * N) : 0.0;
+            for (int j = 0; j < CH; ++j) a[j] = j0 + j < N ? Ai[(j0 + j) * N] : 0.0;
 #pragma unroll
             for (int g0 = 0; g0 < CH; g0 += LG) {
                 __builtin_amdgcn_sched_barrier(0);
@@ -1305,7 +1299,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
         // the row of A^{-1} is loaded while b is assembled
         double m[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) m[j] = ainv_load(Ai + j * N);
+        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
         const double b = rhs_of();
         if (in_group) L[row] = b;
         wave_sync();
@@ -1352,7 +1346,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs 
         const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
         double m[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) m[j] = ainv_load(Ai + j * N);
+        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
         unsigned kept = 0;
         double rhs = inflow_rhs<DIM, P, true>(args, prs, row, &kept);
         if (!active) kept = 0;
@@ -1487,7 +1481,10 @@ constexpr bool use_dpp() {
 template <int DIM, int P>
 void launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, hipStream_t stream) {
     if constexpr (use_dpp<DIM, P>()) {
-        if (inv)
+        if (inv && a.nt)
+            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, true, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                               stream, a);
+        else if (inv)
             hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
                                stream, a);
         else

@@ -55,6 +55,7 @@ struct PersistArgs {
     const int32_t* intra;     // tiled schedules: intra-tile dependency word per entry (else null)
     int32_t problem;          // table index of every entry, or -1 when entries name their problem
     const int4* slots;        // 2D: per entry {neighbour[4]}, {face[4]}, {kink row[4]} of its slots, or null
+    int32_t nt;               // DPP kernels: read the cached inverses with non-temporal loads
 };
 
 // Launches the persistent sweep kernel (all levels in one launch); inv: read

@@ -173,6 +173,9 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             pa.intra = c.intra;
             pa.problem = class_problem(c);
             pa.slots = c.slots;
+            // streaming loads of A^{-1} paid off on tiled single-problem
+            // sweeps (2D 128^2 p = 3 S8: 4 %) and lost on batches
+            pa.nt = c.intra != nullptr ? 1 : 0;
             if (prof) prof->begin(s);
             launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
             if (prof) prof->end(s);
