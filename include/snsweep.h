@@ -214,6 +214,14 @@ int snsw_reset(snsw_problem* prob);
  * out (the affected sweep's output is invalid).                              */
 int snsw_synchronize(snsw_problem* prob);
 
+/* Bound of every dependency wait of this problem's persistent sweeps: polls
+ * before the wait gives up, flags the failure (reported by
+ * snsw_synchronize as SNSW_E_STATE) and lets the grid drain.  polls >= 0;
+ * default 2^20 (far above any wait of a valid schedule).  A small bound
+ * forces the failure path from the host, for tests of it; the sweeps of a
+ * batch keep the default.  SNSW_E_INVALID_ARG for polls < 0.                */
+int snsw_set_wait_limit(snsw_problem* prob, int32_t polls);
+
 /* ------------------------------------------------------------------- solve
  * Source iteration (eq. sourceIteration) from the guess in d_phi until
  * max|phi_{l+1}-phi_l| / max|phi_{l+1}| <= tol (checked every check_every

@@ -97,6 +97,7 @@ SIGNATURES = {
     "snsw_sweep": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "snsw_reset": (C.c_int, [C.c_void_p]),
     "snsw_synchronize": (C.c_int, [C.c_void_p]),
+    "snsw_set_wait_limit": (C.c_int, [C.c_void_p, C.c_int32]),
     "snsw_solve": (C.c_int, [C.c_void_p, C.POINTER(SnswSolveOpts), C.c_void_p, C.c_void_p,
                              C.POINTER(SnswSolveReport)]),
     "snsw_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, c_double_p]),
@@ -363,6 +364,10 @@ class Problem:
     def synchronize(self):
         """Wait for the stream; raises if a device-side dependency wait failed."""
         _check(lib().snsw_synchronize(self.handle))
+
+    def set_wait_limit(self, polls: int):
+        """Polls per dependency wait of persistent sweeps before giving up."""
+        _check(lib().snsw_set_wait_limit(self.handle, int(polls)))
 
     def residual(self, a, b) -> float:
         out = C.c_double()

@@ -326,7 +326,7 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
         pa.ticket = L.tickets + (size_t)c.ticket * kTicketWords;
         pa.error = L.error;
         pa.total = c.level_off.back();
-        pa.spin_limit = 1 << 20;
+        pa.spin_limit = L.spin_limit;
         pa.intra = c.intra;
         pa.problem = class_problem(c);
         pa.slots = c.slots;

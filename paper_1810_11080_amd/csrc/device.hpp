@@ -87,6 +87,7 @@ struct DeviceProblem {
     unsigned long long* red = nullptr;   // residual scratch [2]
     unsigned int* ticket = nullptr;
     int32_t* error = nullptr;     // device-side wait failure flag
+    int32_t spin_limit = 1 << 20; // polls per dependency wait of persistent sweeps
     double* ainv = nullptr;       // [D][E][n][n] cached A^{-1} (column-major) or null
     SweepArgs* table = nullptr;   // this problem as a table of one
     int table_cur = 0;            // buffer index in table->psi_cur
@@ -111,6 +112,7 @@ struct SweepLaunch {
     unsigned int* tickets = nullptr;
     int n_tickets = 0;
     int32_t* error = nullptr;
+    int32_t spin_limit = 1 << 20;      // polls per dependency wait of persistent sweeps
     const double* const* phi_in_list = nullptr;
     const double* phi_in_one = nullptr;
     double* const* phi_out_list = nullptr;

@@ -48,6 +48,7 @@ void do_sweep(snsw_problem* prob, const double* phi_in, double* phi_out, double*
     L.max_En = hp.E * hp.n;
     L.max_DEn = hp.D * hp.E * hp.n;
     L.any_persistent = dp->cls.persistent;
+    L.spin_limit = dp->spin_limit;
     L.tickets = dp->ticket;
     L.n_tickets = 1;
     L.error = dp->error;
@@ -169,7 +170,7 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             pa.ticket = L.tickets + (size_t)c.ticket * kTicketWords;
             pa.error = L.error;
             pa.total = c.level_off.back();
-            pa.spin_limit = 1 << 20;
+            pa.spin_limit = L.spin_limit;
             pa.intra = c.intra;
             pa.problem = class_problem(c);
             pa.slots = c.slots;
@@ -395,6 +396,13 @@ int snsw_synchronize(snsw_problem* prob) {
         DeviceProblem* dp = need_device(prob);
         DeviceGuard g(dp->device);
         check_error_flag(dp->error, dp->stream);
+    });
+}
+
+int snsw_set_wait_limit(snsw_problem* prob, int32_t polls) {
+    return snsw_guard([&] {
+        if (polls < 0) throw Error(SNSW_E_INVALID_ARG, "wait limit must be >= 0");
+        need_device(prob)->spin_limit = polls;
     });
 }
 

@@ -200,6 +200,39 @@ def test_constant_solution_c5_size(torch, ctx):
     P.close()
 
 
+@pytest.mark.parametrize("case", ["cyclic2d_p3", "standin2d"])
+def test_wait_failure_reported_and_recovered(torch, ctx, case):
+    """The failure path of a persistent sweep, forced from the host: with a
+    bound of zero polls every dependency wait whose value is not there at
+    the first poll gives up at once, the grid drains and snsw_synchronize
+    reports SNSW_E_STATE.  With the default bound back and the stored flux
+    reset, sweeps equal those of a fresh problem bit for bit."""
+    from paper_1810_11080_amd import Problem
+    from paper_1810_11080_amd.binding import SnswError
+    wp = SMALL[case]()
+    P = Problem.from_workload(ctx, wp, schedule=1)
+    with pytest.raises(SnswError):
+        P.set_wait_limit(-1)
+    P.set_wait_limit(0)
+    phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(phi)
+    P.sweep(phi, out)
+    with pytest.raises(SnswError) as info:
+        P.synchronize()
+    assert info.value.code == -10
+    P.set_wait_limit(1 << 20)
+    P.reset()
+    g_phi, g_psi = gpu_sweeps(torch, P, 3)
+    P.synchronize()
+    Q = Problem.from_workload(ctx, wp, schedule=1)
+    r_phi, r_psi = gpu_sweeps(torch, Q, 3)
+    Q.synchronize()
+    for k in range(3):
+        assert np.array_equal(g_phi[k], r_phi[k]) and np.array_equal(g_psi[k], r_psi[k])
+    P.close()
+    Q.close()
+
+
 def test_determinism_and_checkpoint(torch, ctx):
     from paper_1810_11080_amd import Problem
     wp = SMALL["cyclic2d_p2"]()
