@@ -773,25 +773,32 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         // same tile (intra bit s) is read from its group's registers once
         // that group is done, not from memory.
         const unsigned intra = (active && pa.intra) ? (unsigned)pa.intra[pidx] : 0u;
-        const gdouble* addr[NS];
-        bool need[NS];
-        double own[NS];
-        int src_lane[NS];
+        // Wait state per axis: in 2D a face lane lies on at most one face of
+        // each axis (slot 2a or 2a + 1), so its polled value, address and
+        // intra-tile source are kept per axis, not per slot.
+        static_assert(DIM == 2, "per-axis wait state");
+        const gdouble* addr[DIM];
+        bool need[DIM];
+        double own[DIM];
+        int src_lane[DIM];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+        for (int a = 0; a < DIM; ++a) {
+            const int ca = S::coord(row, a);
+            const bool on = ca == 0 || ca == P;
+            const int s = 2 * a + (ca == P ? 1 : 0);
             const bool internal = (intra >> s) & 1u;
-            need[s] = active && on && ((kept >> s) & 1u) && !internal;
-            addr[s] = (const gdouble*)args.psi_cur;
-            own[s] = 0.0;
-            src_lane[s] = lane;
-            if (need[s]) {
-                addr[s] = (const gdouble*)(args.psi_cur + ((size_t)d * args.E + nbs[s]) * N +
-                                            S::tn(s ^ 1, S::local(row, s)));
+            need[a] = active && on && ((kept >> s) & 1u) && !internal;
+            addr[a] = (const gdouble*)args.psi_cur;
+            own[a] = 0.0;
+            src_lane[a] = lane;
+            const int la = S::local(row, s);
+            if (need[a]) {
+                const int nb = ca == P ? nbs[2 * a + 1] : nbs[2 * a];
+                addr[a] = (const gdouble*)(args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, la));
             }
             if (internal && on) {
                 const int g_up = (int)((intra >> (kIntraGroupShiftDev + 4 * s)) & 15u);
-                src_lane[s] = g_up * N + S::tn(s ^ 1, S::local(row, s));
+                src_lane[a] = g_up * N + S::tn(s ^ 1, la);
             }
         }
         constexpr unsigned long long gmask = N == 64 ? ~0ull : ((1ull << N) - 1ull);
@@ -802,18 +809,18 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
             // every face lane of a kept face polls its own upwind value
             // (one round trip per poll; the polling traffic is small)
             // (all slots' loads are issued before the first compare)
-            double val[NS];
+            double val[DIM];
 #pragma unroll
-            for (int s = 0; s < NS; ++s)
-                val[s] = need[s] ? __hip_atomic_load(addr[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+            for (int a = 0; a < DIM; ++a)
+                val[a] = need[a] ? __hip_atomic_load(addr[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
             bool have = true;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                if (need[s] && (unsigned long long)__double_as_longlong(val[s]) != sent) {
-                    own[s] = val[s];
-                    need[s] = false;
+            for (int a = 0; a < DIM; ++a) {
+                if (need[a] && (unsigned long long)__double_as_longlong(val[a]) != sent) {
+                    own[a] = val[a];
+                    need[a] = false;
                 }
-                if (need[s]) have = false;
+                if (need[a]) have = false;
             }
             // Finish every ready group.  With a tiled schedule a finished
             // group can make groups of the same tile ready; they are finished
@@ -823,11 +830,11 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
                 bool ready_lane = have;
                 // intra-tile upwind values from the upwind group's lanes (all
                 // lanes execute the permutes; only finished sources are used)
-                double perm[NS];
+                double perm[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) perm[a] = pa.intra ? lane_read(x, src_lane[a]) : 0.0;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    perm[s] = 0.0;
-                    if (pa.intra) perm[s] = lane_read(x, src_lane[s]);
                     if ((intra >> s) & 1u) {
                         const int g_up = (int)((intra >> (kIntraGroupShiftDev + 4 * s)) & 15u);
                         if (!((done_mask >> (g_up * N)) & 1ull)) ready_lane = false;
@@ -844,14 +851,15 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
                     __atomic_signal_fence(__ATOMIC_SEQ_CST);
                     static_for<0, NS>([&](auto sc) {
                         constexpr int s = decltype(sc)::value;
-                        if ((intra >> s) & 1u) own[s] = perm[s];
+                        constexpr int a = s / 2;
+                        const bool on = S::coord(row, a) == ((s & 1) ? P : 0);
+                        if (((intra >> s) & 1u) && on) own[a] = perm[a];
                         if ((kept >> s) & 1u) {
-                            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
                             const int la = on ? S::local(row, s) : 0;
                             double c = 0.0;
                             static_for<0, NF>([&](auto bc) {
                                 constexpr int b = decltype(bc)::value;
-                                c += pin_lds[wave][grp][s][la][b] * group_bcast<N, S::tn(s, b)>(own[s]);
+                                c += pin_lds[wave][grp][s][la][b] * group_bcast<N, S::tn(s, b)>(own[a]);
                             });
                             static_for<0, NF>([&](auto ac) {
                                 constexpr int aa = decltype(ac)::value;
