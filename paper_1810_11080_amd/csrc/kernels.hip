@@ -114,6 +114,7 @@ __device__ __forceinline__ SweepArgs load_args(const SweepArgs* table, int k) {
     a.dim = c->dim;
     a.persistent = c->persistent;
     a.ainv = c->ainv;
+    a.Bsym = c->Bsym;
     return a;
 }
 
@@ -1225,9 +1226,22 @@ __device__ __forceinline__ double inflow_rhs_coop(const SweepArgs& args, int4 pr
                 for (int b = 0; b < NF; ++b) t += Ti[b] * (nb >= 0 ? up[S::tn(s ^ 1, b)] : args.psi_inc);
             }
         } else {
-            const double* Bf = args.B + ((size_t)args.slot_face[(size_t)e * NS + s] * DIM + a) * NF * NF + la * NF;
+            const int fc = args.slot_face[(size_t)e * NS + s];
+            if (args.Bsym) {
+                // row la of the symmetric moment matrix from its packed upper
+                // triangle (44 % fewer bytes than the full matrix)
+                constexpr int NT = NF * (NF + 1) / 2;
+                const double* Bs = args.Bsym + ((size_t)fc * DIM + a) * NT;
 #pragma unroll
-            for (int b = 0; b < NF; ++b) t += Bf[b] * (nb >= 0 ? up[S::tn(s ^ 1, b)] : args.psi_inc);
+                for (int b = 0; b < NF; ++b) {
+                    const int i = la < b ? la : b, j = la < b ? b : la;
+                    t += Bs[i * NF - (i * (i - 1)) / 2 + (j - i)] * (nb >= 0 ? up[S::tn(s ^ 1, b)] : args.psi_inc);
+                }
+            } else {
+                const double* Bf = args.B + ((size_t)fc * DIM + a) * NF * NF + la * NF;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) t += Bf[b] * (nb >= 0 ? up[S::tn(s ^ 1, b)] : args.psi_inc);
+            }
             t *= (s & 1) ? -oa : oa;   // P_in = -(outward normal) moments
         }
         cf[s][row] = t;

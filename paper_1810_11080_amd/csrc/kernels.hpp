@@ -31,6 +31,8 @@ struct SweepArgs {
     int32_t n, D, dim;
     int32_t persistent;       // swept by a persistent kernel (needs the sentinel fill)
     const double* ainv;       // [D][E][n][n] cached A^{-1} per pair, column-major (null: not cached)
+    const double* Bsym;       // 3D: [F][dim][nf (nf + 1) / 2] the face moments (symmetric in the two
+                              // face nodes), upper triangle row by row (null in 2D)
 };
 
 // Persistent sweeps take batches from kStreams counters per schedule, each

@@ -143,6 +143,7 @@ SweepArgs make_args(const snsw_problem* prob, int cur) {
     a.dim = hp.dim;
     a.persistent = 0;
     a.ainv = dp->ainv;
+    a.Bsym = dp->Bsym;
     return a;
 }
 
@@ -250,6 +251,20 @@ void device_upload(snsw_problem* prob) {
         HIP_OK(hipStreamSynchronize(s));
     }
     dp->B = dupload(dp, hp.B, s);
+    if (hp.dim == 3) {
+        // B_a[i][j] = int N_a phi_i phi_j is symmetric in the two face nodes:
+        // the level sweeps read its packed upper triangle
+        const int nf = hp.nf, nt = nf * (nf + 1) / 2;
+        std::vector<double> bs((size_t)hp.F * 3 * nt);
+        for (int64_t fa = 0; fa < hp.F * 3; ++fa) {
+            const double* Bm = &hp.B[(size_t)fa * nf * nf];
+            for (int i = 0; i < nf; ++i)
+                for (int j = i; j < nf; ++j)
+                    bs[(size_t)fa * nt + i * nf - (i * (i - 1)) / 2 + (j - i)] = 0.5 * (Bm[i * nf + j] + Bm[j * nf + i]);
+        }
+        dp->Bsym = dupload(dp, bs, s);
+        HIP_OK(hipStreamSynchronize(s));
+    }
     dp->kink_tab = dupload(dp, hp.kink_tab, s);
     dp->kink_idx = dupload(dp, hp.kink_idx, s);
     {
@@ -354,7 +369,7 @@ void device_release(snsw_problem* prob) noexcept {
     (void)hipSetDevice(dp->device);
     (void)hipStreamSynchronize(dp->stream);
     dp->prof.release();
-    void* ptrs[] = {dp->geo, dp->B, dp->kink_tab, dp->kink_idx, dp->pairs, dp->tpairs, dp->tintra, dp->tslots,
+    void* ptrs[] = {dp->geo, dp->B, dp->Bsym, dp->kink_tab, dp->kink_idx, dp->pairs, dp->tpairs, dp->tintra, dp->tslots,
                     dp->slot_face, dp->slot_nbr,
                     dp->sigma_t, dp->sigma_s, dp->q, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
                     dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table, dp->ainv};
