@@ -602,10 +602,11 @@ __device__ __forceinline__ void static_for(F&& f) {
 // Persistent sweep for 4- and 16-lane groups (2D, p = 1 and p = 3): the same
 // schedule and protocol as sweep_persistent_fp64, with every intra-group
 // exchange done by DPP broadcasts.  Register economy decides occupancy here:
-// the assembly is branch-free, the inflow rows of the
-// deferred slots are parked in LDS (each face lane writes its own row), and
-// after the wait the face lanes form c = P_in psi_up, which is broadcast into
-// x += A^{-1}[:, tn_s] c.
+// the assembly is branch-free, the inflow rows of the deferred slots are
+// parked in LDS (each face lane writes its own row), the wait state is kept
+// per axis, and after the wait the face lanes form c = P_in psi_up, which is
+// broadcast into x += A^{-1}[:, tn_s] c.  NT: the rows of A^{-1} are read
+// with non-temporal loads.
 template <int DIM, int P, bool INV, bool NT = false>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3, 8))) sweep_persistent_dpp(PersistArgs pa) {
     using S = Shape<DIM, P>;
@@ -806,10 +807,9 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         bool done = !active;
         int polls = 0;
         while (true) {
-            // groups already done (their x is final)
-            // every face lane of a kept face polls its own upwind value
-            // (one round trip per poll; the polling traffic is small)
-            // (all slots' loads are issued before the first compare)
+            // every face lane of a kept face polls its own upwind value, one
+            // per axis, both loads issued before the first compare (one
+            // round trip per poll; the polling traffic is small)
             double val[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a)
