@@ -1260,6 +1260,87 @@ __device__ __forceinline__ double inflow_rhs_coop(const SweepArgs& args, int4 pr
     return rhs;
 }
 
+// inflow_rhs_coop with the upwind traces staged: first the lanes of component
+// 0 park the trace of each inflow slot in LDS (uf, [NS][nf] per pair), one
+// load per face lane instead of nf broadcast loads in every lane (p = 2: 24
+// fewer vector memory instructions per wavefront of two pairs, about a tenth
+// of the 3D level sweep); then the contraction reads the trace from LDS.  The
+// same sums in the same order as inflow_rhs_coop.  Not used for nf = 16,
+// where holding the staged slots costs more registers than it saves.
+template <int DIM, int P>
+__device__ __forceinline__ double inflow_rhs_staged(const SweepArgs& args, int4 pr, int row, bool in_group,
+                                                  double (*cf)[DIM * Shape<DIM, P>::NF],
+                                                  double (*uf)[Shape<DIM, P>::NF]) {
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, NF = S::NF, NS = S::NS;
+    static_assert(DIM * NF <= N, "one lane per moment row and component");
+    const int e = pr.x;
+    const unsigned packed = (unsigned)pr.y;
+    const int d = (int)(packed & kDirMask);
+    const int a = row / NF, la = row - a * NF;
+    const bool worker = in_group && a < DIM;
+    const double oa = args.omega[3 * d + (a < DIM ? a : 0)];
+    int fcs[NS], krs[NS];
+    int kc = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+        const bool lagged = (packed >> (kSlotShift + 3 * s + 2)) & 1u;
+        krs[s] = 0;
+        fcs[s] = 0;
+        if (cls == kKink) krs[s] = args.kink_idx[pr.z + kc++];
+        if (cls == kOut || cls == kNone || !worker) continue;
+        if (cls != kKink) fcs[s] = args.slot_face[(size_t)e * NS + s];
+        if (a == 0) {
+            const int nb = args.slot_nbr[(size_t)e * NS + s];
+            const double* up = (lagged ? args.psi_prev : args.psi_cur) + ((size_t)d * args.E + (nb >= 0 ? nb : 0)) * N;
+            uf[s][la] = nb >= 0 ? up[S::tn(s ^ 1, la)] : args.psi_inc;
+        }
+    }
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+        if (cls == kOut || cls == kNone || !worker) continue;
+        double t = 0.0;
+        if (cls == kKink) {
+            if (a == 0) {
+                const double* Ti = args.kink_tab + (size_t)krs[s] * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + la * NF;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) t += Ti[b] * uf[s][b];
+            }
+        } else {
+            if (args.Bsym) {
+                constexpr int NT = NF * (NF + 1) / 2;
+                const double* Bs = args.Bsym + ((size_t)fcs[s] * DIM + a) * NT;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) {
+                    const int i = la < b ? la : b, j = la < b ? b : la;
+                    t += Bs[i * NF - (i * (i - 1)) / 2 + (j - i)] * uf[s][b];
+                }
+            } else {
+                const double* Bf = args.B + ((size_t)fcs[s] * DIM + a) * NF * NF + la * NF;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) t += Bf[b] * uf[s][b];
+            }
+            t *= (s & 1) ? -oa : oa;
+        }
+        cf[s][row] = t;
+    }
+    wave_sync();
+    double rhs = in_group ? args.src[(size_t)e * N + row] : 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+        if (cls == kOut || cls == kNone) continue;
+        if (S::coord(row, s / 2) != ((s & 1) ? P : 0)) continue;
+        const int l = S::local(row, s);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) rhs += cf[s][c * NF + l];
+    }
+    return rhs;
+}
+
 // One launch per level with cached inverses: b assembled per row, shared
 // through the wavefront's LDS, x = A^{-1} b.
 template <int DIM, int P>
@@ -1270,6 +1351,8 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     constexpr bool kCoop = DIM == 3 && DIM * S::NF <= N;
     __shared__ double lds[kWaves][G][N + 1];
     __shared__ double cfl[kWaves][kCoop ? G : 1][kCoop ? S::NS : 1][DIM * S::NF];
+    constexpr bool kStage = kCoop && S::NF <= 9;
+    __shared__ double ufl[kWaves][kStage ? G : 1][kStage ? S::NS : 1][kStage ? S::NF : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = lane / N, row = lane - grp * N;
@@ -1285,7 +1368,9 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     const int d = (int)((unsigned)prs.y & kDirMask);
     const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
     auto rhs_of = [&]() {
-        if constexpr (kCoop) return inflow_rhs_coop<DIM, P>(args, prs, row, in_group, cfl[wave][in_group ? grp : 0]);
+        const int g = in_group ? grp : 0;
+        if constexpr (kStage) return inflow_rhs_staged<DIM, P>(args, prs, row, in_group, cfl[wave][g], ufl[wave][g]);
+        else if constexpr (kCoop) return inflow_rhs_coop<DIM, P>(args, prs, row, in_group, cfl[wave][g]);
         else return inflow_rhs<DIM, P>(args, prs, row);
     };
     double* L = &lds[wave][in_group ? grp : 0][0];
@@ -1296,7 +1381,9 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
         // from LDS a few entries at a time.  The scheduling barriers keep
         // the LDS values from all being live together (fewer registers, more
         // wavefronts in flight); the empty asm keeps the products out of the
-        // store branch, where they would lose the barriers.
+        // store branch, where they would lose the barriers.  In 3D the rows
+        // are read as streaming data (each is read once per sweep), which
+        // leaves the L2 to the face moments and traces that pairs share.
         const double b = rhs_of();
         if (in_group) L[row] = b;
         wave_sync();
@@ -1307,7 +1394,12 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
         for (int j0 = 0; j0 < N; j0 += CH) {
             double a[CH];
 #pragma unroll
-            for (int j = 0; j < CH; ++j) a[j] = j0 + j < N ? Ai[(j0 + j) * N] : 0.0;
+            for (int j = 0; j < CH; ++j) {
+                if constexpr (DIM == 3)
+                    a[j] = j0 + j < N ? __builtin_nontemporal_load(&Ai[(j0 + j) * N]) : 0.0;
+                else
+                    a[j] = j0 + j < N ? Ai[(j0 + j) * N] : 0.0;
+            }
 #pragma unroll
             for (int g0 = 0; g0 < CH; g0 += LG) {
                 __builtin_amdgcn_sched_barrier(0);
