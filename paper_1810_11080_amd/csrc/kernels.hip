@@ -78,6 +78,23 @@ struct Shape {
     }
 };
 
+// Layout of one pair's cached A^{-1} block.  Column-major (entry (i, j) at
+// j n + i), except for 3D p = 2 (n = 27): there columns 2c and 2c + 1 are
+// interleaved row by row (entry (i, j) at 2 (c n + i) + (j & 1)), the odd
+// last column follows plainly, and blocks are padded to an even length, so
+// that a lane reads two entries of its row with one aligned 16-byte load
+// (14 loads per row instead of 27).
+template <int DIM, int P>
+struct InvLayout {
+    static constexpr int N = Shape<DIM, P>::N;
+    static constexpr bool kPaired = DIM == 3 && P == 2;
+    static constexpr int kStride = kPaired ? N * N + (N * N & 1) : N * N;
+    __host__ __device__ static constexpr int at(int i, int j) {
+        return !kPaired ? j * N + i : (j < (N & ~1) ? ((j >> 1) * N + i) * 2 + (j & 1) : (N & ~1) * N + i);
+    }
+};
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
 // Table entry and problem index read through the constant address space, so
 // that a wavefront-uniform index gives scalar loads (neither is written while
 // a sweep kernel runs).
@@ -654,6 +671,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
             // of n = 4 or 16 doubles lies in one 128 B line).  NT: read as
             // streaming (non-temporal) data, once per sweep, so that it does
             // not push the reused face data out of the caches
+            static_assert(!InvLayout<DIM, P>::kPaired, "column-major blocks only");
             const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
             if constexpr (NT) {
 #pragma unroll
@@ -933,6 +951,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
         const int e = prs.x;
         const unsigned packed = (unsigned)prs.y;
         const int d = (int)(packed & kDirMask);
+        static_assert(!InvLayout<DIM, P>::kPaired, "column-major blocks only");
         const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
         double m[N];
 #pragma unroll
@@ -1077,8 +1096,8 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
 
 // Setup: for schedule entries [0, count) of one problem, assemble A and
 // invert it in place by Gauss-Jordan without pivoting (A + A^T is positive
-// definite), pivot rows broadcast through LDS; A^{-1} is stored
-// column-major at ainv[(d E + e) n^2 + j n + i].
+// definite), pivot rows broadcast through LDS; A^{-1} is stored at
+// ainv[(d E + e) stride + InvLayout::at(i, j)].
 template <int DIM, int P>
 __global__ void __launch_bounds__(64 * kWaves) factor_kernel(const SweepArgs* table, const int4* pairs, int64_t count,
                                                             double* ainv) {
@@ -1125,9 +1144,10 @@ __global__ void __launch_bounds__(64 * kWaves) factor_kernel(const SweepArgs* ta
     }
     if (active) {
         const int d = (int)((unsigned)pr.y & kDirMask);
-        double* dst = ainv + ((size_t)d * args.E + pr.x) * N * N + row;
+        using IL = InvLayout<DIM, P>;
+        double* dst = ainv + ((size_t)d * args.E + pr.x) * IL::kStride;
 #pragma unroll
-        for (int j = 0; j < N; ++j) dst[j * N] = m[j];
+        for (int j = 0; j < N; ++j) dst[IL::at(row, j)] = m[j];
     }
 }
 
@@ -1366,7 +1386,8 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     const int4 prs = active ? pr : make_int4(0, 0, 0, 0);
     const int e = prs.x;
     const int d = (int)((unsigned)prs.y & kDirMask);
-    const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
+    using IL = InvLayout<DIM, P>;
+    const double* Ab = args.ainv + ((size_t)d * args.E + e) * IL::kStride;
     auto rhs_of = [&]() {
         const int g = in_group ? grp : 0;
         if constexpr (kStage) return inflow_rhs_staged<DIM, P>(args, prs, row, in_group, cfl[wave][g], ufl[wave][g]);
@@ -1395,10 +1416,21 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
             double a[CH];
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
-                if constexpr (DIM == 3)
-                    a[j] = j0 + j < N ? __builtin_nontemporal_load(&Ai[(j0 + j) * N]) : 0.0;
-                else
-                    a[j] = j0 + j < N ? Ai[(j0 + j) * N] : 0.0;
+                if constexpr (IL::kPaired) {
+                    static_assert(CH == N, "paired columns are read in one chunk");
+                    if (j + 1 < (N & ~1) && !(j & 1)) {
+                        const dbl2 v = __builtin_nontemporal_load(
+                            reinterpret_cast<const dbl2*>(Ab + IL::at(row, j)));
+                        a[j] = v.x;
+                        a[j + 1] = v.y;
+                    } else if (j >= (N & ~1)) {
+                        a[j] = __builtin_nontemporal_load(Ab + IL::at(row, j));
+                    }
+                } else if constexpr (DIM == 3) {
+                    a[j] = j0 + j < N ? __builtin_nontemporal_load(Ab + IL::at(row, j0 + j)) : 0.0;
+                } else {
+                    a[j] = j0 + j < N ? Ab[IL::at(row, j0 + j)] : 0.0;
+                }
             }
 #pragma unroll
             for (int g0 = 0; g0 < CH; g0 += LG) {
@@ -1413,7 +1445,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
         // the row of A^{-1} is loaded while b is assembled
         double m[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+        for (int j = 0; j < N; ++j) m[j] = Ab[IL::at(row, j)];
         const double b = rhs_of();
         if (in_group) L[row] = b;
         wave_sync();
@@ -1457,10 +1489,11 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs 
         const int e = prs.x;
         const unsigned packed = (unsigned)prs.y;
         const int d = (int)(packed & kDirMask);
-        const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
+        using IL = InvLayout<DIM, P>;
+        const double* Ai = args.ainv + ((size_t)d * args.E + e) * IL::kStride;
         double m[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+        for (int j = 0; j < N; ++j) m[j] = Ai[IL::at(row, j)];
         unsigned kept = 0;
         double rhs = inflow_rhs<DIM, P, true>(args, prs, row, &kept);
         if (!active) kept = 0;
@@ -1733,6 +1766,11 @@ void launch_sweep_level(int dim, int p, bool mixed, bool inv, const SweepArgs* t
         else if (p == 2) launch_tpl<3, 2>(table, pairs, begin, count, problem, mixed, inv, stream);
         else launch_tpl<3, 3>(table, pairs, begin, count, problem, mixed, inv, stream);
     }
+}
+
+int64_t ainv_block_stride(int dim, int p) {
+    if (dim == 2) return p == 1 ? InvLayout<2, 1>::kStride : p == 2 ? InvLayout<2, 2>::kStride : InvLayout<2, 3>::kStride;
+    return p == 1 ? InvLayout<3, 1>::kStride : p == 2 ? InvLayout<3, 2>::kStride : InvLayout<3, 3>::kStride;
 }
 
 void launch_factor(int dim, int p, const SweepArgs* table, const int4* pairs, int64_t count, double* ainv,

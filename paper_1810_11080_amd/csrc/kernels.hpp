@@ -30,7 +30,7 @@ struct SweepArgs {
     int64_t E;
     int32_t n, D, dim;
     int32_t persistent;       // swept by a persistent kernel (needs the sentinel fill)
-    const double* ainv;       // [D][E][n][n] cached A^{-1} per pair, column-major (null: not cached)
+    const double* ainv;       // [D][E] blocks of cached A^{-1} (kernels.hip InvLayout; null: not cached)
     const double* Bsym;       // 3D: [F][dim][nf (nf + 1) / 2] the face moments (symmetric in the two
                               // face nodes), upper triangle row by row (null in 2D)
 };
@@ -72,6 +72,9 @@ bool persistent_uses_inverse(int dim, int p);
 // problem: table index of every entry, or -1 when entries name their problem.
 void launch_sweep_level(int dim, int p, bool mixed, bool inv, const SweepArgs* table, const int4* pairs,
                         int64_t begin, int64_t count, int problem, hipStream_t stream);
+// Doubles per pair in the cached A^{-1} array (n^2, or n^2 + 1 where blocks
+// are padded to a 16-byte multiple).
+int64_t ainv_block_stride(int dim, int p);
 // Computes and stores A^{-1} of schedule entries [0, count) of one problem.
 void launch_factor(int dim, int p, const SweepArgs* table, const int4* pairs, int64_t count, double* ainv,
                    hipStream_t stream);

@@ -317,16 +317,16 @@ void device_upload(snsw_problem* prob) {
     HIP_OK(hipMemsetAsync(dp->ticket, 0, sizeof(unsigned int) * kTicketWords, s));
     dp->error = dalloc<int32_t>(dp, 1);
     HIP_OK(hipMemsetAsync(dp->error, 0, sizeof(int32_t), s));
-    // cached inverses: D*E*n^2 doubles
+    // cached inverses: D*E blocks of about n^2 doubles
     {
-        const size_t need = sizeof(double) * (size_t)hp.D * hp.E * n * n;
+        const size_t need = sizeof(double) * (size_t)hp.D * hp.E * ainv_block_stride(hp.dim, hp.p);
         bool cache = false;
         if (hp.precision == SNSW_PREC_FP64 && hp.cache_inverse != SNSW_CACHE_OFF) {
             size_t free_b = 0, total_b = 0;
             HIP_OK(hipMemGetInfo(&free_b, &total_b));
             cache = hp.cache_inverse == SNSW_CACHE_ON || need <= free_b / 2;
         }
-        if (cache) dp->ainv = dalloc<double>(dp, (size_t)hp.D * hp.E * n * n);
+        if (cache) dp->ainv = dalloc<double>(dp, (size_t)hp.D * hp.E * ainv_block_stride(hp.dim, hp.p));
         hp.inverse_cached = cache ? 1 : 0;
     }
     SweepClass& c = dp->cls;
