@@ -34,7 +34,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 # write x1.000); profiles/sweep_persistent_dpp_c2_128x128_q3_p3_s8.md and
 # profiles/sweep_level_inv_c3_32cube_q2_p2_s8.md.  Only valid for the kernel
 # build it was measured on: drop an entry when the kernel changes.
-MEASURED_TRAFFIC = {("sweep_persistent_dpp<2,3,inv,nt>", "c2", "fp64"): 1.903e9}
+MEASURED_TRAFFIC = {("sweep_persistent_dpp<2,3,inv,nt>", "c2", "fp64"): 1.903e9,
+                    ("sweep_level_inv<3,2>", "c3", "fp64"): 1.456e8}
 DESCRIPTIONS = {
     "c1": "2D 8x8 Q2 curved (warp 0.05), p=1, S4 (12 dirs), sigma_t=1, c=0.5, q=1, vacuum",
     "c2": "2D 128x128 Q3 curved (warp 0.3 h, 4-element wavelength, cyclic sweep graphs), p=3, "
