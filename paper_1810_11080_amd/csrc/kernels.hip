@@ -95,6 +95,27 @@ struct InvLayout {
 };
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
+// Every block layout is a permutation of [0, n^2) inside its stride, and the
+// paired columns sit at even offsets next to each other (16-byte loads).
+template <int DIM, int P>
+constexpr bool inv_layout_ok() {
+    using IL = InvLayout<DIM, P>;
+    constexpr int N = IL::N;
+    bool seen[IL::kStride] = {};
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            const int k = IL::at(i, j);
+            if (k < 0 || k >= IL::kStride || seen[k]) return false;
+            seen[k] = true;
+            if (IL::kPaired && j + 1 < (N & ~1) && !(j & 1) && (k % 2 != 0 || IL::at(i, j + 1) != k + 1))
+                return false;
+        }
+    return IL::kStride % 2 == 0 || !IL::kPaired;
+}
+static_assert(inv_layout_ok<2, 1>() && inv_layout_ok<2, 2>() && inv_layout_ok<2, 3>() && inv_layout_ok<3, 1>() &&
+                  inv_layout_ok<3, 2>() && inv_layout_ok<3, 3>(),
+              "A^{-1} block layouts");
+
 // Table entry and problem index read through the constant address space, so
 // that a wavefront-uniform index gives scalar loads (neither is written while
 // a sweep kernel runs).
