@@ -62,3 +62,46 @@ def test_warped_invariants(dim, r, p, n, amp, freq):
             S[:, tn[:, None], tn[None, :]] += sign * (Pp[fid] - Pm[fid])
         Ki = disc.K[:, i]
         assert np.abs(Ki + Ki.transpose(0, 2, 1) - S).max() < 1e-12 * max(1, np.abs(S).max())
+
+
+@pytest.mark.parametrize("dim,r,p,n,amp,freq", [(2, 3, 3, (5, 4), 0.3 / 8, 2), (2, 2, 2, (3, 4), 0.05, 1),
+                                                 (3, 2, 2, (2, 3, 3), 0.05, 1), (3, 1, 1, (3, 2, 2), 0.02, 1)])
+def test_warped_mass_against_independent_jacobian(dim, r, p, n, amp, freq):
+    """M_e = int phi_i phi_j |J| on curved elements, recomputed from the
+    lattice with independent polynomials and a tensor Gauss rule that is
+    exact for the polynomial integrand (the Jacobian determinant of a Q_r map
+    has degree dim*r - 1 per axis)."""
+    prob = W.small(dim=dim, n=n, r=r, p=p, N=2, amp=amp, freq=freq)
+    disc = Discretization(prob)
+    nx = prob.nx
+    sizes = [r * nx[a] + 1 for a in range(dim)]
+    lat = prob.lattice.reshape(tuple(reversed(sizes)) + (dim,))        # [z][y][x] or [y][x]
+    G = lagrange_polys(np.linspace(0, 1, r + 1))
+    Bp = lagrange_polys(gll(p))
+    xq, wq = np.polynomial.legendre.leggauss(p + (dim * r + 1) // 2 + 1)
+    xq, wq = (xq + 1) / 2, wq / 2
+    Gv = np.array([g(xq) for g in G])                  # (r+1, Q)
+    dGv = np.array([g.deriv()(xq) for g in G])
+    Bv = np.array([b(xq) for b in Bp])                 # (p+1, Q)
+    k = p + 1
+    for e in range(disc.E):
+        ia = [(e // int(np.prod(nx[:a]))) % nx[a] for a in range(dim)]
+        if dim == 2:
+            X = lat[ia[1] * r:ia[1] * r + r + 1, ia[0] * r:ia[0] * r + r + 1]          # [b_y][b_x][c]
+            jx = np.einsum("bac,aq,br->rqc", X, dGv, Gv)     # d x / d xi  at [eta_r][xi_q]
+            jy = np.einsum("bac,aq,br->rqc", X, Gv, dGv)     # d x / d eta
+            det = jx[..., 0] * jy[..., 1] - jx[..., 1] * jy[..., 0]
+            phi = np.einsum("iq,jr->jirq", Bv, Bv).reshape(k * k, len(xq), len(xq))  # m = i + k j
+            w = np.outer(wq, wq)
+            Me = np.einsum("mrq,nrq,rq->mn", phi, phi, det * w)
+        else:
+            X = lat[ia[2] * r:ia[2] * r + r + 1, ia[1] * r:ia[1] * r + r + 1, ia[0] * r:ia[0] * r + r + 1]
+            cols = [np.einsum("cbad,aq,br,cs->srqd", X, dGv, Gv, Gv),
+                    np.einsum("cbad,aq,br,cs->srqd", X, Gv, dGv, Gv),
+                    np.einsum("cbad,aq,br,cs->srqd", X, Gv, Gv, dGv)]
+            det = np.linalg.det(np.stack(cols, axis=-1))
+            phi = np.einsum("iq,jr,ls->ljisrq", Bv, Bv, Bv).reshape(k ** 3, len(xq), len(xq), len(xq))
+            w = np.einsum("s,r,q->srq", wq, wq, wq)
+            Me = np.einsum("msrq,nsrq,srq->mn", phi, phi, det * w)
+        assert det.min() > 0
+        assert np.abs(disc.M[e] - Me).max() <= 1e-13 * np.abs(Me).max(), e
