@@ -82,8 +82,9 @@ extern "C" {
  * outflow face blocks, is the same in every source iteration.  With a cached
  * inverse it is factored once (Gauss-Jordan on the device, at create) and a
  * sweep only assembles b and forms A^{-1} b: D*E*n^2 doubles of device
- * memory (e.g. 15 GB for 32^3 elements, p = 2, S8).  AUTO caches in FP64
- * mode when that takes at most half of the free device memory.             */
+ * memory, one more double per pair for 3D p = 2 (e.g. 15 GB for 32^3
+ * elements, p = 2, S8).  AUTO caches in FP64 mode when that takes at most
+ * half of the free device memory.                                          */
 #define SNSW_CACHE_AUTO    0
 #define SNSW_CACHE_ON      1
 #define SNSW_CACHE_OFF     2
