@@ -9,7 +9,12 @@ sets.  It prints no table, so the construction here is the textbook one:
 * octant points (mu_i, mu_j, mu_k) with i + j + k = N/2 + 2;
 * one weight per permutation class, fixed by the even moment conditions
   sum_octant w * mu_x^(2m) = 1/(2m+1), m = 0..N/2-1 (least squares; the system
-  is consistent for the tabulated mu_1);
+  is consistent: the m = 1 condition follows from mu_x^2 + mu_y^2 + mu_z^2 = 1);
+* mu_1 itself is the one free parameter left, and the sets are defined by the
+  next even moment, sum_octant w * mu_x^N = 1/(N+1): mu_1 is the root of that
+  condition in (0, 1/sqrt(3)) at which every class weight is positive (unique
+  for S_4..S_12; bracketed by a scan, refined by bisection).  The textbook
+  table (S_4 0.3500212 ... S_12 0.1672126) is these roots to 7 digits;
 * octant weights scaled by 4*pi/8; in 2D only the directions with a positive
   z cosine are kept and their weights doubled, so the sum stays 4*pi.
 
@@ -18,25 +23,79 @@ j ascending inside the octant.
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
 
-# mu_1 of the standard level-symmetric sets (textbook table)
-MU1 = {4: 0.3500212, 6: 0.2666355, 8: 0.2182179, 10: 0.1893213,
-       12: 0.1672126}
+ORDERS = (2, 4, 6, 8, 10, 12)
 # (S_16 is left out: its moment system is rank deficient, so the moment
 # conditions alone do not fix its weights.)
+
+
+def cosines_of(N: int, mu1: float) -> np.ndarray:
+    """Level cosines mu_1 .. mu_{N/2} for a given mu_1."""
+    i = np.arange(N // 2)
+    return np.sqrt(mu1 ** 2 + i * 2.0 * (1.0 - 3.0 * mu1 ** 2) / (N - 2))
+
+
+def _class_weights(N: int, mu: np.ndarray) -> np.ndarray:
+    """Per-point octant weights (sum 1) from the moments m < N/2."""
+    pts = octant_points(N)
+    classes = sorted({tuple(sorted(p)) for p in pts})
+    cls_of = [classes.index(tuple(sorted(p))) for p in pts]
+    nm = N // 2
+    A = np.zeros((nm, len(classes)))
+    for m in range(nm):
+        for p, c in zip(pts, cls_of):
+            A[m, c] += mu[p[0]] ** (2 * m)
+    b = 1.0 / (2.0 * np.arange(nm) + 1.0)
+    wc, *_ = np.linalg.lstsq(A, b, rcond=None)
+    return np.array([wc[c] for c in cls_of])
+
+
+def next_moment_defect(N: int, mu1: float) -> float:
+    """sum_octant w mu_x^N - 1/(N+1) for the set built from mu1."""
+    mu = cosines_of(N, mu1)
+    w = _class_weights(N, mu)
+    return float(sum(wp * mu[p[0]] ** N for p, wp in zip(octant_points(N), w))) - 1.0 / (N + 1)
+
+
+@functools.lru_cache(maxsize=None)
+def mu1_of(N: int) -> float:
+    """mu_1 of S_N: the root of the next even moment condition in
+    (0, 1/sqrt(3)) with all class weights positive."""
+    if N == 2:
+        return 1.0 / math.sqrt(3.0)
+    if N not in ORDERS:
+        raise ValueError(f"no level-symmetric set for S{N}")
+    grid = np.linspace(0.02, 1.0 / math.sqrt(3.0) - 1e-4, 2001)
+    vals = [next_moment_defect(N, x) for x in grid]
+    for k in range(len(grid) - 1):
+        if vals[k] == 0.0 or vals[k] * vals[k + 1] < 0.0:
+            a, b, fa = grid[k], grid[k + 1], vals[k]
+            for _ in range(200):
+                m = 0.5 * (a + b)
+                if m <= a or m >= b:
+                    break
+                fm = next_moment_defect(N, m)
+                if fm == 0.0:
+                    a = b = m
+                    break
+                if (fa < 0.0) == (fm < 0.0):
+                    a, fa = m, fm
+                else:
+                    b = m
+            root = 0.5 * (a + b)
+            if np.all(_class_weights(N, cosines_of(N, root)) > 0.0):
+                return root
+    raise ValueError(f"no positive level-symmetric set for S{N}")
 
 
 def cosines(N: int) -> np.ndarray:
     if N == 2:
         return np.array([1.0 / math.sqrt(3.0)])
-    if N not in MU1:
-        raise ValueError(f"no level-symmetric set for S{N}")
-    mu1 = MU1[N]
-    i = np.arange(N // 2)
-    return np.sqrt(mu1 ** 2 + i * 2.0 * (1.0 - 3.0 * mu1 ** 2) / (N - 2))
+    return cosines_of(N, mu1_of(N))
 
 
 def octant_points(N: int):
@@ -52,18 +111,7 @@ def octant_points(N: int):
 
 def octant_weights(N: int) -> np.ndarray:
     """Octant-normalised point weights (sum 1) from the moment conditions."""
-    mu = cosines(N)
-    pts = octant_points(N)
-    classes = sorted({tuple(sorted(p)) for p in pts})
-    cls_of = [classes.index(tuple(sorted(p))) for p in pts]
-    nm = N // 2
-    A = np.zeros((nm, len(classes)))
-    for m in range(nm):
-        for p, c in zip(pts, cls_of):
-            A[m, c] += mu[p[0]] ** (2 * m)
-    b = 1.0 / (2.0 * np.arange(nm) + 1.0)
-    wc, *_ = np.linalg.lstsq(A, b, rcond=None)
-    return np.array([wc[c] for c in cls_of])
+    return _class_weights(N, cosines(N))
 
 
 def level_symmetric(N: int, dim: int):

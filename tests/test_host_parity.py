@@ -72,3 +72,19 @@ def test_c2_full_graph(ctx):
     assert info["n_removed_total"] > 0
     bad, _ = graph_parity(P, wp)
     assert bad == []
+
+
+@pytest.mark.parametrize("N", [4, 6, 8, 10, 12])
+def test_library_mu1_fixed_by_next_even_moment(ctx, N):
+    """The library's level-symmetric set satisfies the defining condition of
+    mu_1, sum w Omega_x^N = 4 pi/(N+1), to rounding, and its smallest cosine
+    rounds to the 7-digit textbook value (pinned without the oracle)."""
+    import math
+    from paper_1810_11080_amd import Problem
+    table = {4: 0.3500212, 6: 0.2666355, 8: 0.2182179, 10: 0.1893213, 12: 0.1672126}
+    wp = W.make_problem("q", 3, (2, 2, 2), 1, 1, N, 0.0, 1, 1.0, 0.5, 1.0)
+    P = Problem.from_workload(ctx, wp)
+    om, w = P.quadrature()
+    for i in range(3):
+        assert abs(np.dot(w, om[:, i] ** N) - 4 * math.pi / (N + 1)) < 1e-13
+    assert abs(np.abs(om).min() - table[N]) <= 1.5e-7

@@ -73,3 +73,33 @@ def test_direction_order():
         assert (om[d, 0] < 0) == bool(o & 1)
         assert (om[d, 1] < 0) == bool(o & 2)
         assert (om[d, 2] < 0) == bool(o & 4)
+
+
+# mu_1 of the level-symmetric sets as printed in the transport literature
+# (Lewis and Miller's tables, 7 digits).  Independent of the oracle's root
+# finding: the roots must round to these.
+TEXTBOOK_MU1 = {4: 0.3500212, 6: 0.2666355, 8: 0.2182179, 10: 0.1893213, 12: 0.1672126}
+
+
+@pytest.mark.parametrize("N", [4, 6, 8, 10, 12])
+def test_mu1_fixed_by_next_even_moment(N):
+    """mu_1 is defined by the first even moment the weights are not fitted
+    to: sum w Omega_x^N = 4 pi/(N+1) on the sphere.  It holds to rounding,
+    and the root agrees with the 7-digit textbook table (a typo or a 1 %
+    change of mu_1 fails both)."""
+    om, w = Q.level_symmetric(N, 3)
+    for i in range(3):
+        assert abs(np.dot(w, om[:, i] ** N) - 4 * math.pi / (N + 1)) < 1e-13
+    mu1 = np.abs(om).min()
+    assert abs(mu1 - TEXTBOOK_MU1[N]) <= 1.5e-7
+    # the moment after it is not matched (the set is not a product rule)
+    assert abs(np.dot(w, om[:, 0] ** (N + 2)) - 4 * math.pi / (N + 3)) > 1e-6
+
+
+@pytest.mark.parametrize("N", [4, 8, 12])
+def test_perturbed_mu1_breaks_next_moment(N):
+    """A 1e-6 relative change of mu_1 violates the defining condition by far
+    more than rounding (the condition is a sharp pin on mu_1)."""
+    mu1 = Q.mu1_of(N)
+    assert abs(Q.next_moment_defect(N, mu1)) < 1e-15
+    assert abs(Q.next_moment_defect(N, mu1 * (1 + 1e-6))) > 1e-10
