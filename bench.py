@@ -3,19 +3,28 @@
 
 Metric: DOF-direction updates per second of one full lagged sweep (every
 level of the combined schedule, the scattering source and the scalar-flux
-reduction), E*n*D / t_sweep, with all inputs resident in HBM.  Default
-workload: 2D 128x128 Q3 curved mesh (warp 0.3 element widths, 4-element
-wavelength, so the sweep graphs have cycles), DG p=3, S8 (40 directions),
-sigma_t = 1, c = 0.8, q = 1, vacuum; seeded synthetic inputs.
+reduction), E*n*D / t_sweep, with all inputs resident in HBM; and the time to
+a 1e-8 residual of source iteration with and without the learned correction.
+Default workload: 3D 48^3 Q2 curved mesh (warp 0.05), DG p=2, S12 (168
+directions), sigma_t in {1, 100} at random (seed 100), c = 0.99, q = 1,
+vacuum; seeded synthetic inputs.
 
-Also reported: the roofline of the sweep kernel (algorithmic FP64 flops per
-launch over its average launch time, HIP events around every launch in a
-second timed pass), plain source-iteration time to a 1e-8 residual, the
-time to a 1e-8 residual with and without the learned correction on the
-two-material c = 0.99 family (training included, reported separately), and
-the CPU oracle timed on a sample of the same workload.
+The line also carries:
+  * roofline -- the algorithmic work of the method per (element, direction)
+    pair (element assembly, face blocks, LU and the two triangular solves;
+    geometry read once per element, traces written and read once) over the
+    sweep kernel's average launch time (HIP events around every launch in a
+    second timed pass), against the FP64 vector peak or HBM, whichever
+    bounds that work; the cached-inverse byte stream the kernel actually
+    reads is reported beside it (``inverse_stream``);
+  * learned_vs_plain -- plain source iteration and the learned correction to
+    1e-8 on the benchmarked problem (held out: the network is trained on
+    other seeds of the same family first; training reported separately);
+  * cpu_baseline -- the CPU oracle on a bounded sample of the same workload,
+    with all host threads and with one;
+  * secondary -- the 2D 128x128 Q3 S8 cyclic workload's sweep rate.
 
-  python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5]
+  python bench.py [--steps K] [--warmup W] [--workload c5|c1|c2|c3|c4]
 """
 from __future__ import annotations
 
@@ -29,11 +38,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+METRIC = "DOF-direction updates/s per sweep; time to 1e-8 residual, learned vs plain SI"
 # HBM bytes per launch of the timed kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes, scaled by a copy kernel of known size (fetch x2.000,
-# write x1.000); profiles/sweep_persistent_dpp_c2_128x128_q3_p3_s8.md and
-# profiles/sweep_level_inv_c3_32cube_q2_p2_s8.md.  Only valid for the kernel
-# build it was measured on: drop an entry when the kernel changes.
+# write x1.000), averaged over the launches of a sweep; the profiles/ files
+# named after each kernel and workload hold the counts.  Only valid for the
+# kernel build it was measured on: drop an entry when the kernel changes.
 MEASURED_TRAFFIC = {("sweep_persistent_dpp<2,3,inv,nt>", "c2", "fp64"): 1.903e9,
                     ("sweep_level_inv<3,2>", "c3", "fp64"): 1.456e8}
 DESCRIPTIONS = {
@@ -42,65 +53,203 @@ DESCRIPTIONS = {
           "S8 (40 dirs), sigma_t=1, c=0.8, q=1, vacuum",
     "c3": "3D 32^3 Q2 curved (warp 0.05), p=2, S8 (80 dirs), checkerboard sigma_t {1,10}, c=0.9, "
           "q=1 in the central 8^3 block, vacuum",
-    "c5": "3D 48^3 Q2 curved (warp 0.05), p=2, S12 (168 dirs), random sigma_t {1,100}, c=0.99, "
-          "q=1, vacuum",
+    "c5": "3D 48^3 Q2 curved (warp 0.05), p=2, S12 (168 dirs), random sigma_t {1,100} (seed 100), "
+          "c=0.99, q=1, vacuum",
     "c4": "batch of 64 independent 2D problems (seed 0): m^2 Q2 meshes m in [16,96], p in {1,2,3}, "
           "S4-S12, sigma_t log-uniform [0.1,10], c uniform [0,0.95], q=1, vacuum; one hipGraph "
           "replay per batch sweep, schedule per (dim, p) class chosen by the autotuner",
 }
 
 
-def flops_per_pair(dim: int, p: int) -> float:
-    """Algorithmic FP64 flops of one (element, direction) solve: assembly of
-    sigma_t M - sum_i Omega_i K_i (2(d+1)n^2), face blocks from the normal
-    moments (2d faces x 2d nf^2) with d outflow additions (nf^2) and d inflow
-    products (2 nf^2), Gaussian elimination (2/3 n^3) and the two triangular
-    sweeps (2 n^2)."""
+def work_model(dim: int, p: int):
+    """Algorithmic work of one (element, direction) update of the method:
+    LU of the n x n element system (2/3 n^3) and the two triangular solves
+    (2 n^2); assembly of sigma_t M - sum_i Omega_i K_i from the
+    direction-independent matrices (2 (d+1) n^2) and of the scattering and
+    source load M phi (2 n^2); face blocks from the normal moments
+    (4 d (d+1) nf^2).  Returns (flops per pair, n, nf)."""
     n = (p + 1) ** dim
     nf = (p + 1) ** (dim - 1)
-    return (2.0 / 3.0) * n ** 3 + 2 * n ** 2 + 2 * (dim + 1) * n ** 2 + 4 * dim * dim * nf ** 2 \
-        + 3 * dim * nf ** 2
+    flops = (2.0 / 3.0) * n ** 3 + 2 * n ** 2 + 2 * (dim + 1) * n ** 2 + 2 * n ** 2 + 4 * dim * (dim + 1) * nf ** 2
+    return flops, n, nf
 
 
-HBM_PEAK_GBS = 8000.0
+def algorithmic_bytes(dim: int, p: int, E: int, D: int, F_int: int) -> float:
+    """HBM bytes the method must move per sweep: the direction-independent
+    geometry (M and the d matrices K_i, FP64) once per element, every
+    interior trace written once and read once (nf FP64 values per interior
+    face and direction), and the scalar flux read and written."""
+    n = (p + 1) ** dim
+    nf = (p + 1) ** (dim - 1)
+    return 8.0 * (E * (dim + 1) * n * n + 2.0 * F_int * D * nf + 2.0 * E * n)
 
 
-def bytes_per_pair_inverse(dim: int, p: int) -> float:
-    """Algorithmic HBM bytes of one (element, direction) update when the
-    element inverses are cached: the pair's A^{-1} (n^2 doubles), its new
-    angular flux (n) and the upwind traces it reads (d inflow faces of nf
-    values); the source term (n per element) is counted per element."""
+def interior_faces(nx) -> int:
+    nx = list(nx)
+    tot = 0
+    for a in range(len(nx)):
+        prod = 1
+        for b in range(len(nx)):
+            prod *= (nx[b] - 1) if b == a else nx[b]
+        tot += prod
+    return tot
+
+
+def inverse_stream_bytes_per_pair(dim: int, p: int) -> float:
+    """Bytes the cached-inverse kernels read or write per pair: its A^{-1}
+    (n^2 doubles), its new angular flux (n) and the upwind traces of its d
+    inflow faces (nf each)."""
     n = (p + 1) ** dim
     nf = (p + 1) ** (dim - 1)
     return 8.0 * (n * n + n + dim * nf)
 
 
-def cpu_baseline(wp, n_dirs_sample: int = 4, repeats: int = 1):
-    """Time the oracle's sweep on a sample of the directions of the workload."""
+def host_cpu():
+    """(cores available to this process, CPU model name)."""
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return len(os.sched_getaffinity(0)), model
+
+
+def cpu_baseline(wp, block: int = None, n_dirs_sample: int = None):
+    """The oracle's lagged sweep timed on a bounded sample of the workload
+    (CPU baseline, not tuned): for 3D workloads the corner block of
+    block^3 elements of the same mesh and materials, all directions unless
+    n_dirs_sample is given; the setup (geometry, faces, graphs) is not timed,
+    as on the GPU.  Timed twice: with the host's BLAS threads and with one."""
     import numpy as np
+    import workloads as W
     from oracle.discretization import Discretization
     from oracle.quadrature import level_symmetric
     from oracle.sweep import build_graphs, sweep
-    om, w = level_symmetric(wp.sn_order, wp.dim)
-    sel = np.linspace(0, len(w) - 1, min(n_dirs_sample, len(w))).round().astype(int)
-    disc = Discretization(wp, omega=om[sel], w=w[sel])
+    sample = wp if block is None else W.corner_block(wp, block)
+    om, w = level_symmetric(sample.sn_order, sample.dim)
+    sel = np.arange(len(w)) if n_dirs_sample is None else \
+        np.linspace(0, len(w) - 1, min(n_dirs_sample, len(w))).round().astype(int)
+    disc = Discretization(sample, omega=om[sel], w=w[sel])
     gs = build_graphs(disc)
-    phi = np.zeros((disc.E, disc.n))
-    psi = np.zeros((disc.D, disc.E, disc.n))
-    t0 = time.perf_counter()
-    for _ in range(repeats):
-        psi, phi = sweep(disc, gs, phi, psi)
-    dt = time.perf_counter() - t0
-    threads = 1
+    rng = np.random.default_rng(5)
+    phi0 = rng.uniform(0.0, 2.0, (disc.E, disc.n))
+    psi0 = rng.uniform(0.0, 0.2, (disc.D, disc.E, disc.n))
+    cores, model = host_cpu()
+    blas = None
+    runs = {}
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        blas = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
     except Exception:
-        pass
-    value = disc.E * disc.n * disc.D * repeats / dt
-    return {"value": value, "unit": "DOF-dir/s", "cores": threads, "kind": "oracle",
-            "sample": f"{repeats} sweep(s) of {len(sel)} of {len(w)} directions (ids {sel.tolist()}) "
-                      f"on the full mesh, {dt:.2f} s"}
+        threadpool_limits = None
+    for label in ("all", "serial"):
+        if label == "serial" and threadpool_limits is None:
+            continue
+        t0 = time.perf_counter()
+        if label == "serial":
+            with threadpool_limits(limits=1):
+                sweep(disc, gs, phi0, psi0)
+        else:
+            sweep(disc, gs, phi0, psi0)
+        runs[label] = time.perf_counter() - t0
+    dof_dir = disc.E * disc.n * disc.D
+    where = f"the {block}^{sample.dim} corner block of the mesh" if block is not None else "the full mesh"
+    out = {"value": dof_dir / runs["all"], "unit": "DOF-dir/s", "cores": blas or 1, "kind": "oracle",
+           "sample": f"1 lagged sweep of {len(sel)} of {len(w)} directions on {where} ({disc.E} elements, "
+                     f"{dof_dir} DOF-dir) from seeded fluxes, {runs['all']:.2f} s",
+           "host_cores": cores, "cpu_model": model}
+    if "serial" in runs:
+        out["serial"] = {"value": dof_dir / runs["serial"], "cores": 1, "seconds": round(runs["serial"], 2)}
+    return out
+
+
+def kernel_name(wp, sched: int, inv: bool, tile: int) -> str:
+    if sched == 1:
+        if wp.dim == 2 and wp.p != 2:
+            nt = ",nt" if inv and tile > 0 else ""
+            return f"sweep_persistent_dpp<{wp.dim},{wp.p}{',inv' if inv else ''}{nt}>"
+        if inv:
+            return f"sweep_persistent_lds2d<{wp.p}>" if wp.dim == 2 else f"sweep_persistent_inv<{wp.dim},{wp.p}>"
+        return f"sweep_persistent_fp64<{wp.dim},{wp.p}>"
+    return f"sweep_level_inv<{wp.dim},{wp.p}>" if inv else f"sweep_level_fp64<{wp.dim},{wp.p}>"
+
+
+def time_sweeps(P, steps: int, warmup: int):
+    """Whole-sweep time (ms) between HIP events on the problem's stream, then
+    a second pass with HIP events around every sweep-kernel launch.
+    Returns (ms per sweep, launches per sweep, summed kernel ms per sweep)."""
+    import torch
+    E, n = P.E, P.n
+    phi = torch.zeros(E * n, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(phi)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        P.sweep(phi, out)
+        phi, out = out, phi
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        P.sweep(phi, out)
+        phi, out = out, phi
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    P.profile_enable(True)
+    for _ in range(steps):
+        P.sweep(phi, out)
+        phi, out = out, phi
+    launches, kernel_ms = P.profile_read()
+    P.profile_enable(False)
+    P.synchronize()
+    return ms, launches / steps, kernel_ms / steps
+
+
+def sweep_line(P, wp, name: str, sched: int, prec: int, steps: int, warmup: int):
+    """Sweep rate and roofline of one problem (dict parts of the JSON line)."""
+    info = P.info()
+    E, n, D = P.E, P.n, P.D
+    ms, launches, kernel_ms = time_sweeps(P, steps, warmup)
+    inv = bool(info["cached_inverse"])
+    kname = kernel_name(wp, sched, inv, info["tile"])
+    flops_pair, _, _ = work_model(wp.dim, wp.p)
+    flops = flops_pair * E * D
+    nbytes = algorithmic_bytes(wp.dim, wp.p, E, D, interior_faces(wp.nx))
+    t_alu = flops / (FP64_VECTOR_PEAK_TFLOPS * 1e12)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    avg_launch_s = kernel_ms / launches * 1e-3
+    if t_alu >= t_hbm:
+        achieved = flops / launches / avg_launch_s / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5)}
+    else:
+        achieved = nbytes / launches / avg_launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5)}
+    traffic = MEASURED_TRAFFIC.get((kname, name, "fp64" if prec == 0 else "mixed"))
+    roof.update({"traffic": traffic, "kernel": kname,
+                 "algorithmic_flops_per_sweep": flops, "algorithmic_bytes_per_sweep": nbytes,
+                 "roofline_ms_per_sweep": round(max(t_alu, t_hbm) * 1e3, 4),
+                 "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches_per_sweep": launches,
+                 "kernel_share_of_step": round(kernel_ms / ms, 4)})
+    if inv:
+        sb = inverse_stream_bytes_per_pair(wp.dim, wp.p) * E * D + 8.0 * E * n
+        gbs = sb / launches / avg_launch_s / 1e9
+        roof["inverse_stream"] = {"bytes_per_sweep": sb, "achieved_gbs": round(gbs, 1),
+                                  "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 5),
+                                  "traffic_over_stream": round(traffic * launches / sb, 3) if traffic else None}
+    return {"value": E * n * D / (ms * 1e-3), "ms_per_step": round(ms, 5), "roofline": roof,
+            "config": {"workload": DESCRIPTIONS[name], "elements": E, "dofs_per_element": n, "directions": D,
+                       "levels": info["n_levels_total"], "lagged_edges": info["n_removed_total"],
+                       "kink_face_dirs": info["n_kink_faces_total"], "cached_inverse": inv,
+                       "schedule": "persistent" if sched == 1 else "levels",
+                       "precision": "fp64" if prec == 0 else "mixed"}}
 
 
 def bench_batch(args):
@@ -136,23 +285,26 @@ def bench_batch(args):
     B.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
     dof_dir = sum(P.E * P.n * P.D for P in problems)
-    flops = sum(flops_per_pair(wp.dim, wp.p) * P.E * P.D for wp, P in zip(wps, problems))
-    achieved = flops / (ms * 1e-3) / 1e12
+    # the method's algorithmic work summed over the problems (same model as
+    # the single-problem line); the batch is timed as a whole replay
+    flops = sum(work_model(wp.dim, wp.p)[0] * P.E * P.D for wp, P in zip(wps, problems))
+    nbytes = sum(algorithmic_bytes(wp.dim, wp.p, P.E, P.D, interior_faces(wp.nx)) for wp, P in zip(wps, problems))
     classes = B.classes()
-    inv = all(P.info()["cached_inverse"] for P in problems)
-    if inv:
-        nbytes = sum(bytes_per_pair_inverse(wp.dim, wp.p) * P.E * P.D + 8.0 * P.E * P.n
-                     for wp, P in zip(wps, problems))
-        gbs = nbytes / (ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None, "algorithmic_bytes_per_sweep": nbytes,
-                "kernel": "whole batch sweep (graph replay: source, fill, class sweeps, scalar flux)"}
-    else:
+    t_alu = flops / (FP64_VECTOR_PEAK_TFLOPS * 1e12)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    kname = "whole batch sweep (graph replay: source, fill, class sweeps, scalar flux)"
+    if t_alu >= t_hbm:
+        achieved = flops / (ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
-                "kernel": "whole batch sweep (graph replay: source, fill, class sweeps, scalar flux)"}
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5)}
+    else:
+        achieved = nbytes / (ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5)}
+    roof.update({"traffic": None, "kernel": kname, "algorithmic_flops_per_sweep": flops,
+                 "algorithmic_bytes_per_sweep": nbytes, "roofline_ms_per_sweep": round(max(t_alu, t_hbm) * 1e3, 4)})
     line = {
-        "metric": "DOF-direction updates/s per sweep; time to 1e-8 residual, learned vs plain SI",
+        "metric": METRIC,
         "value": dof_dir / (ms * 1e-3),
         "unit": "DOF-dir/s",
         "n_gpus": 1,
@@ -176,70 +328,75 @@ def bench_batch(args):
     print(json.dumps(line))
 
 
-def learned_vs_plain(nx=16, p=2, sn_order=8, train_seeds=(0, 1, 2, 3), eval_seeds=(100, 101), steps=3000,
-                     every=40, stride=3, tol_train=1e-12, verbose=False):
-    """Time to a 1e-8 residual with and without the learned correction on
-    the two-material c = 0.99 family (the 48^3 S12 configuration's
-    materials at nx^3): train on plain-SI pairs (every `stride`-th iteration
-    of a solve to tol_train) of train_seeds, evaluate on held-out
-    eval_seeds.  Returns a JSON-ready dict."""
+def note(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def train_correction(ctx, family, train_seeds, steps: int, stride: int, tol_train: float):
+    """Trains the learned correction (widths 16/32/32) on plain-SI pairs of
+    the training seeds of a problem family: every `stride`-th iteration of a
+    solve from zero to tol_train gives a pair.  Each training problem is
+    freed before the next one is built.  Returns (net, training report)."""
     import torch
-    import workloads as W
-    from paper_1810_11080_amd import Context, Net, Problem
+    from paper_1810_11080_amd import Net, Problem
     from paper_1810_11080_amd import learn as L
-
-    def note(msg):
-        if verbose:
-            print(msg, file=sys.stderr, flush=True)
-
-    ctx = Context(device=0)
     t0 = time.perf_counter()
-    Xs, Ts = [], []
+    Xs, Ts, grid = [], [], None
     for seed in train_seeds:
-        P = Problem.from_workload(ctx, W.c5_reduced(seed=seed, nx=nx, p=p, sn_order=sn_order))
-        kept, star, its = L.plain_trajectory(P, tol=tol_train, max_iters=50000, sample=lambda l: l % stride == 0,
-                                             progress=note if verbose else None)
+        P = Problem.from_workload(ctx, family(seed))
+        grid = L.element_grid(P)
+        kept, star, its = L.plain_trajectory(P, tol=tol_train, max_iters=50000, sample=lambda l: l % stride == 0)
         X, T = L.make_pairs(P, kept, star)
         Xs.append(X)
         Ts.append(T)
         note(f"training seed {seed}: {its} plain sweeps, {len(kept)} pairs, {time.perf_counter() - t0:.1f} s")
-        del kept, P
+        del kept, star
+        P.close()
+        del P
     X = torch.cat(Xs)
     T = torch.cat(Ts)
+    del Xs, Ts
     torch.cuda.synchronize()
     data_s = time.perf_counter() - t0
     net = Net(ctx, widths=(16, 32, 32), seed=0)
     t0 = time.perf_counter()
-    losses = L.train(net, (nx, nx, nx), X, T, steps=steps, batch=8, lr=2e-3, lr_final=1e-4,
-                     log_every=500 if verbose else 0)
+    losses = L.train(net, grid, X, T, steps=steps, batch=8, lr=2e-3, lr_final=1e-4)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    runs = []
-    for seed in eval_seeds:
-        P = Problem.from_workload(ctx, W.c5_reduced(seed=seed, nx=nx, p=p, sn_order=sn_order))
-        row = {"seed": seed}
-        for name, pre in (("plain", None), ("learned", net)):
-            P.reset()
-            phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
-            rep = P.solve(phi, tol=1e-8, max_iters=50000, precond=pre, precond_every=every)
-            row[name] = {"seconds": round(rep["seconds"], 4), "sweeps": rep["iterations"]}
-            note(f"eval seed {seed} {name}: {row[name]}")
-            if pre is not None:
-                row[name].update(corrections=rep["n_corrected"], rejected=rep["n_rejected"])
-        runs.append(row)
-    plain = sum(r["plain"]["seconds"] for r in runs)
-    learned = sum(r["learned"]["seconds"] for r in runs)
-    saved = (plain - learned) / len(runs)
-    return {"workload": f"3D {nx}^3 Q2 (warp 0.05), p={p}, S{sn_order}, sigma_t in {{1,100}} (random, 50/50), "
-                        f"c=0.99, q=1, vacuum; trained on seeds {list(train_seeds)}, evaluated on "
-                        f"{list(eval_seeds)}",
-            "tol": 1e-8, "precond_every": every, "params": net.n_params,
-            "time_plain_s": round(plain / len(runs), 4), "time_learned_s": round(learned / len(runs), 4),
-            "speedup": round(plain / learned, 3), "runs": runs,
-            "training": {"pairs": int(X.shape[0]), "data_s": round(data_s, 2), "train_s": round(train_s, 2),
-                         "steps": steps, "loss_first": float(losses[:10].mean()),
-                         "loss_last": float(losses[-100:].mean()),
-                         "break_even_solves": round((data_s + train_s) / saved, 1) if saved > 0 else None}}
+    note(f"trained {steps} steps in {train_s:.1f} s, loss {losses[:10].mean():.4g} -> {losses[-100:].mean():.4g}")
+    rep = {"seeds": list(train_seeds), "pairs": int(X.shape[0]), "tol": tol_train, "stride": stride,
+           "data_s": round(data_s, 2), "train_s": round(train_s, 2), "steps": steps, "batch": 8,
+           "loss_first": float(losses[:10].mean()), "loss_last": float(losses[-100:].mean())}
+    return net, rep
+
+
+def compare_solves(P, net, every: int, tol: float = 1e-8, max_iters: int = 50000):
+    """Source iteration from zero to tol, plain and with the learned
+    correction, on the same problem.  Returns the two reports."""
+    import torch
+    out = {}
+    for name, pre in (("plain", None), ("learned", net)):
+        P.reset()
+        phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+        rep = P.solve(phi, tol=tol, max_iters=max_iters, precond=pre, precond_every=every,
+                      raise_on_not_converged=False)
+        out[name] = {"seconds": round(rep["seconds"], 4), "sweeps": rep["iterations"],
+                     "residual": rep["residual"]}
+        if pre is not None:
+            out[name].update(corrections=rep["n_corrected"], rejected=rep["n_rejected"])
+        note(f"{name}: {out[name]}")
+    return out
+
+
+def learned_block(runs, training, every, eval_desc, params):
+    plain = sum(r["plain"]["seconds"] for r in runs) / len(runs)
+    learned = sum(r["learned"]["seconds"] for r in runs) / len(runs)
+    saved = plain - learned
+    training = dict(training, break_even_solves=round((training["data_s"] + training["train_s"]) / saved, 1)
+                    if saved > 0 else None)
+    return {"workload": eval_desc, "tol": 1e-8, "precond_every": every, "params": params,
+            "time_plain_s": round(plain, 4), "time_learned_s": round(learned, 4),
+            "speedup": round(plain / learned, 3), "runs": runs, "training": training}
 
 
 def lagged_face_fraction(P, P_face) -> float:
@@ -312,17 +469,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(DESCRIPTIONS),
-                    help="c2 (default): the single-problem benchmark; c4: the 64-problem batch")
+    ap.add_argument("--workload", default="c5", choices=sorted(DESCRIPTIONS),
+                    help="c5 (default): the 48^3 S12 benchmark; c4: the 64-problem batch")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "persistent", "levels"])
     ap.add_argument("--cache-inverse", default="auto", choices=["auto", "on", "off"],
                     help="keep each pair's A^{-1} on the device (factored once at setup)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain comparison")
-    ap.add_argument("--learned-only", choices=["c5"], default=None,
-                    help="only the learned-vs-plain comparison at the full 48^3 S12 size (minutes)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training and the learned-vs-plain comparison (plain solve only)")
+    ap.add_argument("--no-solve", action="store_true", help="no solves at all")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 2D cyclic secondary line")
+    ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a copy kernel of known size (HBM counter calibration)")
     ap.add_argument("--weighting-study", action="store_true",
@@ -334,7 +492,6 @@ def main():
               "per iteration; not implemented)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import workloads as W
     from paper_1810_11080_amd import Context, Problem
@@ -346,17 +503,19 @@ def main():
     if args.weighting_study:
         print(json.dumps({"weighting_study": weighting_study()}))
         return
-    if args.learned_only == "c5":
-        res = learned_vs_plain(nx=48, p=2, sn_order=12, train_seeds=(0, 1), eval_seeds=(100,), steps=2000,
-                               every=40, stride=10, tol_train=1e-10, verbose=True)
-        print(json.dumps({"learned_vs_plain": res}))
-        return
     if args.workload == "c4":
         bench_batch(args)
         return
-    wp = W.CONFIGS[args.workload]()
-    prec = 0 if args.precision == "fp64" else 1
     ctx = Context(device=0)
+    name = args.workload
+    prec = 0 if args.precision == "fp64" else 1
+    net = training = None
+    every = 40
+    if name == "c5" and not (args.no_learned or args.no_solve):
+        # training first, so that only one 48^3 problem holds device memory
+        # at a time (each caches 108 GB of element inverses)
+        net, training = train_correction(ctx, lambda seed: W.c5(seed=seed), (0, 1), args.train_steps, 10, 1e-10)
+    wp = W.CONFIGS[name]()
     t0 = time.perf_counter()
     sched = {"auto": 0, "persistent": 1, "levels": 2}[args.schedule]
     if sched == 0:   # same rule as the library's automatic choice
@@ -364,112 +523,66 @@ def main():
     cache = {"auto": 0, "on": 1, "off": 2}[args.cache_inverse]
     P = Problem.from_workload(ctx, wp, precision=prec, schedule=sched, cache_inverse=cache)
     setup_s = time.perf_counter() - t0
-    info = P.info()
-    E, n, D = P.E, P.n, P.D
-    phi = torch.zeros(E * n, dtype=torch.float64, device="cuda")
-    out = torch.empty_like(phi)
-    stream = torch.cuda.current_stream()
+    note(f"{name}: setup {setup_s:.1f} s")
+    main_line = sweep_line(P, wp, name, sched, prec, args.steps, args.warmup)
+    main_line["config"]["setup_s"] = round(setup_s, 2)
+    note(f"{name}: {main_line['ms_per_step']} ms per sweep")
 
-    for _ in range(args.warmup):
-        P.sweep(phi, out)
-        phi, out = out, phi
-    torch.cuda.synchronize()
-    # timed pass: whole sweeps
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        P.sweep(phi, out)
-        phi, out = out, phi
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    dof_dir = E * n * D
-    value = dof_dir / (ms_per_step * 1e-3)
-
-    # second timed pass: HIP events around every level-sweep launch
-    P.profile_enable(True)
-    for _ in range(args.steps):
-        P.sweep(phi, out)
-        phi, out = out, phi
-    launches, kernel_ms = P.profile_read()
-    P.profile_enable(False)
-    P.synchronize()
-    launches_per_sweep = launches / args.steps
-    avg_launch_ms = kernel_ms / launches
-    flops_sweep = flops_per_pair(wp.dim, wp.p) * E * D
-    flops_per_launch = flops_sweep / launches_per_sweep
-    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
-    inv = bool(info["cached_inverse"])
-    if sched == 1:
-        if wp.dim == 2 and wp.p != 2:
-            nt = ",nt" if inv and info["tile"] > 0 else ""
-            kname = f"sweep_persistent_dpp<{wp.dim},{wp.p}{',inv' if inv else ''}{nt}>"
-        elif inv:
-            kname = f"sweep_persistent_lds2d<{wp.p}>" if wp.dim == 2 else f"sweep_persistent_inv<{wp.dim},{wp.p}>"
-        else:
-            kname = f"sweep_persistent_fp64<{wp.dim},{wp.p}>"
-    else:
-        kname = f"sweep_level_inv<{wp.dim},{wp.p}>" if inv else f"sweep_level_fp64<{wp.dim},{wp.p}>"
-    if inv:
-        # cached inverses: the sweep streams A^{-1}; HBM bound
-        bytes_sweep = bytes_per_pair_inverse(wp.dim, wp.p) * E * D + 8.0 * E * n
-        gbs = bytes_sweep / launches_per_sweep / (avg_launch_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 5),
-                    "traffic": MEASURED_TRAFFIC.get((kname, args.workload, args.precision)),
-                    "kernel": kname, "algorithmic_bytes_per_sweep": bytes_sweep,
-                    "avg_launch_us": round(avg_launch_ms * 1e3, 3), "launches_per_sweep": launches_per_sweep,
-                    "kernel_share_of_step": round(kernel_ms / args.steps / ms_per_step, 4),
-                    "fp64_alu_view_tflops": round(achieved, 4)}
-    else:
-        roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5),
-                    "traffic": MEASURED_TRAFFIC.get((kname, args.workload, args.precision)),
-                    "kernel": kname,
-                    "avg_launch_us": round(avg_launch_ms * 1e3, 3),
-                    "launches_per_sweep": launches_per_sweep,
-                    "kernel_share_of_step": round(kernel_ms / args.steps / ms_per_step, 4)}
-
-    solve = None
+    solve = learned = None
     if not args.no_solve:
-        P.reset()
-        phi.zero_()
-        rep = P.solve(phi, tol=1e-8, max_iters=2000, check_every=1, raise_on_not_converged=False)
-        solve = {"method": "plain source iteration", "tol": 1e-8, "iterations": rep["iterations"],
-                 "seconds": round(rep["seconds"], 4), "residual": rep["residual"]}
+        runs = compare_solves(P, net, every) if net is not None else None
+        if runs is not None:
+            learned = learned_block([dict(seed=100, **runs)], training, every,
+                                    DESCRIPTIONS[name] + "; network trained on seeds 0 and 1 of the same family",
+                                    net.n_params)
+            plain = runs["plain"]
+        else:
+            P.reset()
+            phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+            rep = P.solve(phi, tol=1e-8, max_iters=50000, raise_on_not_converged=False)
+            plain = {"seconds": round(rep["seconds"], 4), "sweeps": rep["iterations"], "residual": rep["residual"]}
+        solve = dict(method="plain source iteration", tol=1e-8, **plain)
+    P.close()
+    del P
+    torch.cuda.synchronize()
 
-    learned = None
-    if not args.no_learned and args.workload == "c2":
-        learned = learned_vs_plain()
+    secondary = None
+    if name == "c5" and not args.no_secondary:
+        wp2 = W.c2()
+        P2 = Problem.from_workload(ctx, wp2, schedule=1)
+        sec = sweep_line(P2, wp2, "c2", 1, 0, args.steps, args.warmup)
+        secondary = {"workload": sec["config"]["workload"], "value": sec["value"], "unit": "DOF-dir/s",
+                     "ms_per_step": sec["ms_per_step"], "roofline": sec["roofline"]}
+        P2.close()
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wp, n_dirs_sample=40 if args.workload in ("c1", "c2") else 4)
+        if name == "c5":
+            cpu = cpu_baseline(wp, block=12, n_dirs_sample=84)
+        elif wp.dim == 3:
+            cpu = cpu_baseline(wp, block=16, n_dirs_sample=40)
+        else:
+            cpu = cpu_baseline(wp)
 
     line = {
-        "metric": "DOF-direction updates/s per sweep; time to 1e-8 residual, learned vs plain SI",
-        "value": value,
+        "metric": METRIC,
+        "value": main_line["value"],
         "unit": "DOF-dir/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": main_line["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": DESCRIPTIONS[args.workload], "elements": E, "dofs_per_element": n,
-                   "directions": D, "levels": info["n_levels_total"],
-                   "lagged_edges": info["n_removed_total"], "kink_face_dirs": info["n_kink_faces_total"],
-                   "setup_s": round(setup_s, 2), "precision": args.precision,
-                   "cached_inverse": inv,
-                   "schedule": "persistent" if sched == 1 else "levels"},
-        "roofline": roofline,
+        "config": main_line["config"],
+        "roofline": main_line["roofline"],
         "solve_to_1e-8": solve,
         "learned_vs_plain": learned,
         "cpu_baseline": cpu,
+        "secondary": secondary,
     }
     print(json.dumps(line))
 

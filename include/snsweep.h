@@ -241,8 +241,9 @@ int snsw_set_wait_limit(snsw_problem* prob, int32_t polls);
  * judged by the plain-sweep residual only, so the fixed point is unchanged.
  * Safeguard: over the k sweeps after a correction the mean residual
  * reduction per sweep must beat the one of the latest window without a
- * correction (sweeps 1..k are plain); otherwise the correction counts as
- * rejected and the next window is plain.  After 3 rejections the network is
+ * correction (sweeps 1..k are plain; a window must span at least one sweep,
+ * so with k = 1 the first correction follows sweep 2); otherwise the
+ * correction counts as rejected and the next window is plain.  After 3 rejections the network is
  * not used again in this solve.                                             */
 typedef struct snsw_net snsw_net;
 typedef struct {

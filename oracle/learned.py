@@ -22,9 +22,10 @@ the project's definition, stated plainly:
   follows it, against the plain iteration it replaces -- the mean residual
   reduction per sweep over that window, (rho_t / rho_{t-k})^(1/k), must be
   below the one measured over the latest window without a correction (the
-  first window, sweeps 1..k, is plain); otherwise it counts as rejected and
-  the next window is plain.  After 3 rejections the network is switched off
-  for the rest of the solve.
+  first window, sweeps 1..k, is plain; a window must span at least one sweep
+  to give a rate, so with k = 1 the first correction follows sweep 2);
+  otherwise it counts as rejected and the next window is plain.  After 3
+  rejections the network is switched off for the rest of the solve.
 
 Training pairs from a plain source iteration converged to phi*: input
 x^l = [a(phi_{l+1} - phi_l) / s_l, features], target
@@ -108,7 +109,7 @@ def preconditioned_si(disc, graphs, theta, widths, tol, max_iters, every=1):
         if start_res is None:
             start_res = res
         apply = False
-        if enabled and it % every == 0:
+        if enabled and it % every == 0 and it > start_it:
             rate = (res / start_res) ** (1.0 / max(1, it - start_it))
             apply = True
             if pending:

@@ -423,9 +423,11 @@ class Problem:
         _check(lib().snsw_state_save(self.handle, buf, size.value))
         return buf.raw
 
-    def state_load(self, data: bytes):
-        buf = C.create_string_buffer(data, len(data))
-        _check(lib().snsw_state_load(self.handle, buf, len(data)))
+    def state_load(self, data):
+        """Restore from bytes or any contiguous buffer (e.g. a numpy array),
+        read in place."""
+        buf = np.frombuffer(data, dtype=np.uint8)
+        _check(lib().snsw_state_load(self.handle, buf.ctypes.data_as(C.c_void_p), buf.nbytes))
 
 
 class Batch:

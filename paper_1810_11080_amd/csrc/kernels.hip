@@ -556,6 +556,8 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
                     __builtin_amdgcn_s_sleep(1);
                     vals[b] = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
+                // a value still unwritten after the bound is a failed wait
+                if ((unsigned long long)__double_as_longlong(vals[b]) == sent) atomicExch(pa.error, 1);
             }
 #pragma unroll
             for (int b = 0; b < NF; ++b) {
@@ -1583,6 +1585,8 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs 
                         __builtin_amdgcn_s_sleep(1);
                         val[b] = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
+                    // a value still unwritten after the bound is a failed wait
+                    if ((unsigned long long)__double_as_longlong(val[b]) == sent) atomicExch(pa.error, 1);
                 }
 #pragma unroll
                 for (int b = 0; b < NF; ++b) {

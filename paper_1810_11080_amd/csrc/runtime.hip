@@ -472,10 +472,11 @@ int snsw_solve(snsw_problem* prob, const snsw_solve_opts* opts, double* d_phi, d
                 start_res = res;
                 have_start = true;
             }
-            if (!done && net && enabled && it % every == 0) {
-                // per-sweep residual reduction over the window now ending;
-                // a window that followed a correction must beat the latest
-                // plain window
+            if (!done && net && enabled && it % every == 0 && it > start_it) {
+                // per-sweep residual reduction over the window now ending
+                // (at least one sweep long: with every = 1 the first
+                // correction follows sweep 2); a window that followed a
+                // correction must beat the latest plain window
                 const double rate = std::pow(res / start_res, 1.0 / std::max(1, it - start_it));
                 bool apply = true;
                 if (pending) {

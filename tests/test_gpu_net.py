@@ -204,3 +204,60 @@ def test_trained_network_gains(torch, ctx):
     print(out, flush=True)
     assert out["learned"][0] < 0.8 * out["plain"][0]
     assert out["learned"][1] < out["plain"][1]
+
+
+def test_safeguard_rejects_slower_correction(torch, ctx):
+    """The library's safeguard at period 1 (the solve's default): an
+    under-relaxing network is rejected three times and switched off, as in
+    the oracle, and the solve keeps the plain iteration count within 3."""
+    from paper_1810_11080_amd import Net, Problem
+    from tests.lib_helpers import damping_params
+    widths = (2, 2, 2)
+    wp = W.make_problem("damp", 2, (6, 6), 2, 1, 4, 0.05, 1, 1.0, 0.9, 1.0)
+    theta = damping_params(widths, -0.5).astype(np.float32)
+    net = Net(ctx, widths=widths)
+    net.set_params(theta)
+    P = Problem.from_workload(ctx, wp)
+    phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+    plain = P.solve(phi, tol=1e-10, max_iters=2000)
+    P.reset()
+    phi_c = torch.zeros_like(phi)
+    rep = P.solve(phi_c, tol=1e-10, max_iters=2000, precond=net, precond_every=1)
+    disc = Discretization(wp)
+    gs = build_graphs(disc)
+    _, hist, ncorr = LR.preconditioned_si(disc, gs, device_weights(theta, widths), widths, 1e-10, 2000, every=1)
+    print(f"plain {plain['iterations']}, corrected {rep['iterations']} ({rep['n_corrected']} applied, "
+          f"{rep['n_rejected']} rejected), oracle {len(hist)}", flush=True)
+    assert rep["n_rejected"] == LR.MAX_REJECTIONS and rep["n_corrected"] == ncorr == LR.MAX_REJECTIONS
+    assert rep["iterations"] == len(hist)
+    assert rep["iterations"] <= plain["iterations"] + 3
+    assert rel_err(phi_c.cpu().numpy(), phi.cpu().numpy()) <= 1e-9
+
+
+def test_default_network_correction_matches_oracle(torch, ctx):
+    """The default 16/32/32 network applied inside the solve on a 12^3
+    element grid (two plain sweeps, then the correction): the correction
+    phi_corrected - phi~ matches the oracle's (FP64 with the same BF16
+    weights) to the network bar, and phi~ itself to FP64 rounding."""
+    from paper_1810_11080_amd import Net, Problem
+    from oracle.sweep import sweep
+    widths = (16, 32, 32)
+    wp = W.c5_reduced(seed=7, nx=12, p=1, sn_order=2)
+    theta = (N.init_params(widths, seed=9)).astype(np.float32)
+    net = Net(ctx, widths=widths)
+    net.set_params(theta)
+    P = Problem.from_workload(ctx, wp)
+    phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+    rep = P.solve(phi, tol=0.0, max_iters=2, precond=net, precond_every=2, raise_on_not_converged=False)
+    assert rep["n_corrected"] == 1
+    disc = Discretization(wp)
+    gs = build_graphs(disc)
+    o_phi = np.zeros((disc.E, disc.n))
+    o_psi = np.zeros((disc.D, disc.E, disc.n))
+    for _ in range(2):
+        o_prev = o_phi
+        o_psi, o_phi = sweep(disc, gs, o_phi, o_psi)
+    ref = LR.correction(disc, device_weights(theta, widths), widths, o_prev, o_phi)
+    got = phi.cpu().numpy().reshape(P.E, P.n)
+    assert np.abs(ref - o_phi).max() > 1e-3 * np.abs(o_phi).max()    # a correction of some size
+    assert rel_err(got - o_phi, ref - o_phi) <= NET_TOL

@@ -200,17 +200,22 @@ def test_constant_solution_c5_size(torch, ctx):
     P.close()
 
 
-@pytest.mark.parametrize("case", ["cyclic2d_p3", "standin2d"])
-def test_wait_failure_reported_and_recovered(torch, ctx, case):
+@pytest.mark.parametrize("case,cache", [("cyclic2d_p3", 0), ("standin2d", 0), ("cyclic2d_p2", 2), ("warp3d_p2", 1)],
+                         ids=["dpp", "lds2d", "assembled2d_p2", "inverse3d_p2"])
+def test_wait_failure_reported_and_recovered(torch, ctx, case, cache):
     """The failure path of a persistent sweep, forced from the host: with a
     bound of zero polls every dependency wait whose value is not there at
-    the first poll gives up at once, the grid drains and snsw_synchronize
-    reports SNSW_E_STATE.  With the default bound back and the stored flux
-    reset, sweeps equal those of a fresh problem bit for bit."""
+    the first poll (or at its re-read) gives up at once, the grid drains and
+    snsw_synchronize reports SNSW_E_STATE.  With the default bound back and
+    the stored flux reset, sweeps equal those of a fresh problem bit for
+    bit.  Cases: the DPP kernel (2D p = 3), the LDS kernel with cached
+    inverses (2D p = 2 stand-in), the assembled kernel (2D p = 2, no cache)
+    and the 3D kernel with cached inverses (p = 2)."""
     from paper_1810_11080_amd import Problem
     from paper_1810_11080_amd.binding import SnswError
     wp = SMALL[case]()
-    P = Problem.from_workload(ctx, wp, schedule=1)
+    print(f"wait failure: {case}, cache {cache}", flush=True)
+    P = Problem.from_workload(ctx, wp, schedule=1, cache_inverse=cache)
     with pytest.raises(SnswError):
         P.set_wait_limit(-1)
     P.set_wait_limit(0)
@@ -224,7 +229,7 @@ def test_wait_failure_reported_and_recovered(torch, ctx, case):
     P.reset()
     g_phi, g_psi = gpu_sweeps(torch, P, 3)
     P.synchronize()
-    Q = Problem.from_workload(ctx, wp, schedule=1)
+    Q = Problem.from_workload(ctx, wp, schedule=1, cache_inverse=cache)
     r_phi, r_psi = gpu_sweeps(torch, Q, 3)
     Q.synchronize()
     for k in range(3):
@@ -318,3 +323,47 @@ def test_mixed_precision_c2_full(torch, ctx, c2_oracle):
     P.synchronize()
     assert rel_err(g_phi[0], o_phi) < MIXED_TOL
     assert rel_err(g_psi[0], o_psi) < MIXED_TOL
+
+
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_full_size_sampled_directions_stored(torch, ctx, name):
+    """Full-size 3D workloads in the configuration bench.py times (level
+    schedule, cached inverses): 32^3 Q2 p=2 S8 (checkerboard sigma_t in
+    {1, 10}, c = 0.9) and 48^3 Q2 p=2 S12 (sigma_t in {1, 100} at random,
+    c = 0.99).  One sweep from seeded scalar and lagged angular fluxes
+    (scattering source on); the angular flux of one direction per octant on
+    sampled elements against the oracle's values, stored by
+    tests/golden/make_large_sweep_samples.py (the oracle takes minutes
+    here)."""
+    import os
+    from paper_1810_11080_amd import Problem
+    data = np.load(os.path.join(os.path.dirname(__file__), "golden", f"{name}_sweep_samples.npz"))
+    wp = {"c3": W.c3, "c5": W.c5}[name]()
+    dirs, elems = data["dirs"], data["elems"]
+    print(f"{name}: building problem", flush=True)
+    P = Problem.from_workload(ctx, wp)
+    assert P.info()["cached_inverse"] == 1 and P.info()["schedule"] == 2
+    phi0, psi0 = W.sweep_inputs(wp, int(data["seed"]), dirs)
+    # lagged state: the sampled directions seeded, the others zero (directions
+    # are independent within a sweep)
+    state = np.zeros(8 + P.D * P.E * P.n)
+    state[:8].view(np.int64)[:] = [0x534e535745455031, wp.dim, P.E, P.n, P.D, 0, 0, 0]
+    body = state[8:].reshape(P.D, P.E, P.n)
+    for d in dirs:
+        body[d] = psi0[int(d)]
+    P.state_load(state)
+    del state, body
+    print(f"{name}: sweeping", flush=True)
+    phi = torch.tensor(phi0.reshape(-1), dtype=torch.float64, device="cuda")
+    out = torch.empty_like(phi)
+    psi = torch.empty(P.D * P.E * P.n, dtype=torch.float64, device="cuda")
+    P.sweep(phi, out, psi)
+    P.synchronize()
+    dd = torch.tensor(dirs, device="cuda")
+    ee = torch.tensor(elems, device="cuda")
+    got = psi.view(P.D, P.E, P.n).index_select(0, dd).index_select(1, ee).cpu().numpy()
+    ref = data["psi"]
+    assert got.shape == ref.shape
+    for k, d in enumerate(dirs):
+        assert rel_err(got[k], ref[k]) < TOL, (name, int(d))
+    P.close()

@@ -88,3 +88,27 @@ def test_library_mu1_fixed_by_next_even_moment(ctx, N):
     for i in range(3):
         assert abs(np.dot(w, om[:, i] ** N) - 4 * math.pi / (N + 1)) < 1e-13
     assert abs(np.abs(om).min() - table[N]) <= 1.5e-7
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_full_size_graphs_sampled_directions(ctx, name):
+    """Full-size 3D workloads (32^3 S8, 48^3 S12): for one direction per
+    octant, the library's edges, quantised weights, lagged edges and levels
+    hash to the oracle's (stored by tests/golden/make_large_sweep_samples.py,
+    since the oracle needs minutes here)."""
+    import hashlib
+    import os
+    from paper_1810_11080_amd import Problem
+    data = np.load(os.path.join(os.path.dirname(__file__), "golden", f"{name}_sweep_samples.npz"))
+    wp = {"c3": W.c3, "c5": W.c5}[name]()
+    P = Problem.from_workload(ctx, wp)
+    for k, d in enumerate(data["dirs"]):
+        up, down, w = P.edges(int(d))
+        rd, ru = P.removed_edges(int(d))
+        lev = P.levels(int(d))
+        h = hashlib.sha256()
+        for a in (up, down, w, rd, ru, lev):
+            h.update(np.ascontiguousarray(a, dtype="<i8").tobytes())
+        assert (len(up), len(rd), int(lev.max()) + 1) == tuple(data["graph_counts"][k]), int(d)
+        assert h.hexdigest() == str(data["graph_sha256"][k]), int(d)

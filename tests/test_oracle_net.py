@@ -131,3 +131,32 @@ def test_random_network_keeps_fixed_point():
     phi_p = source_iteration(disc, gs, tol=1e-12, max_iters=2000)[0]
     assert hist_l[-1] <= 1e-12
     assert np.abs(phi_l - phi_p).max() / np.abs(phi_p).max() < 1e-9
+
+
+def test_damping_network_is_linear():
+    from tests.lib_helpers import damping_params
+    widths = (2, 3, 2)
+    th = damping_params(widths, -0.5)
+    x = np.random.default_rng(0).uniform(-1, 1, (1, 3, 3, 5, 6))
+    y, _ = N.forward(th, widths, x)
+    assert np.abs(y[0, 0] + 0.5 * x[0, 0]).max() < 1e-15
+
+
+@pytest.mark.parametrize("every", [1, 2, 3])
+def test_safeguard_rejects_slower_correction(every):
+    """A correction that lowers the residual but converges more slowly than
+    plain sweeps (under-relaxation by one half) is rejected three times and
+    then switched off, for every period including 1 (whose reference plain
+    window spans sweeps 1..2): the solve takes at most 3 sweeps more than
+    plain source iteration and reaches its fixed point."""
+    from tests.lib_helpers import damping_params
+    widths = (2, 2, 2)
+    wp = W.make_problem("damp", 2, (6, 6), 2, 1, 4, 0.05, 1, 1.0, 0.9, 1.0)
+    disc = Discretization(wp)
+    gs = build_graphs(disc)
+    phi, _, plain_its, _ = source_iteration(disc, gs, tol=1e-10, max_iters=2000)
+    phi_c, hist, ncorr = LR.preconditioned_si(disc, gs, damping_params(widths, -0.5), widths, 1e-10, 2000,
+                                              every=every)
+    assert ncorr == LR.MAX_REJECTIONS
+    assert len(hist) <= plain_its + 3
+    assert np.abs(phi_c - phi).max() <= 1e-9 * np.abs(phi).max()

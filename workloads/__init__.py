@@ -305,3 +305,44 @@ def random_problem(seed: int, dim: int = 2) -> Problem:
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c5": c5}
+
+
+def sweep_inputs(prob: Problem, seed: int, directions) -> tuple:
+    """Seeded inputs of one lagged sweep: scalar flux phi0 (E, n) uniform in
+    [0, 2], and for each listed direction d its lagged angular flux (E, n)
+    uniform in [0, 0.2] from its own stream default_rng([seed, d]), so that
+    the rows of any subset of directions are the same whichever subset is
+    drawn.  Returns (phi0, {d: psi0_d})."""
+    E, n = prob.n_elements, prob.n_dof
+    phi0 = np.random.default_rng([seed, 1 << 20]).uniform(0.0, 2.0, (E, n))
+    psi0 = {int(d): np.random.default_rng([seed, int(d)]).uniform(0.0, 0.2, (E, n)) for d in directions}
+    return phi0, psi0
+
+
+def sample_elements(prob: Problem, seed: int, count: int) -> np.ndarray:
+    """Sorted distinct element ids drawn from default_rng(seed), plus the
+    first and last element (the corners a sweep starts or ends at)."""
+    E = prob.n_elements
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(E, size=min(count, E), replace=False)
+    return np.unique(np.concatenate([pick, [0, E - 1]])).astype(np.int64)
+
+
+def corner_block(prob: Problem, m: int) -> Problem:
+    """The m x m (x m) corner block of elements 0 <= i, j (, k) < m of a
+    structured problem, as a problem of its own: the same control points,
+    materials and source on those elements (a bounded sample of a large
+    workload; its outer faces become vacuum boundaries)."""
+    dim, r = prob.dim, prob.r
+    nx = tuple(int(v) for v in prob.nx)
+    m = min(m, min(nx))
+    shape = lattice_shape(dim, nx, r)
+    grid = prob.lattice.reshape(tuple(reversed(shape)) + (dim,))
+    sl = tuple(slice(0, r * m + 1) for _ in range(dim))
+    lat = np.ascontiguousarray(grid[sl]).reshape(-1, dim)
+    ijk = element_ijk(dim, nx)
+    keep = np.all(ijk < m, axis=1)
+    sub = tuple([m] * dim)
+    return replace(prob, name=f"{prob.name}_corner{m}", nx=sub, lattice=lat,
+                   sigma_t=prob.sigma_t[keep].copy(), sigma_s=prob.sigma_s[keep].copy(),
+                   q=prob.q[keep].copy(), meta=dict(prob.meta, corner_of=prob.name, corner=m))
