@@ -451,6 +451,56 @@ def weighting_study(tol: float = 1e-8, max_iters: int = 20000):
     return rows
 
 
+def mms_error(ctx, wp, tol: float = 1e-13, extra: int = 4):
+    """Solve the manufactured problem of eq. psiAnnularMMS on the mesh and
+    materials of wp with the library (nodal source and tabulated incident
+    flux evaluated at the library's DG node positions); returns the scalar
+    flux L2 error against the closed form (Gauss rule with `extra` points per
+    axis beyond the element-matrix rule), the unknowns per direction and the
+    solve report."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1810_11080_amd import Problem
+    P = Problem.from_workload(ctx, wp)
+    om, w = P.quadrature()
+    st = np.repeat(wp.sigma_t, P.n).reshape(P.E, P.n)
+    ss = np.repeat(wp.sigma_s, P.n).reshape(P.E, P.n)
+    q, psi_exact, _ = W.mms_annular(P.node_coordinates(), om, w, st, ss)
+    P.set_source(q, bc_kind=W.TABULATED, psi_inc_tab=psi_exact)
+    phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+    rep = P.solve(phi, tol=tol, max_iters=2000)
+    x, wd, basis = P.volume_rule(extra=extra)
+    _, _, phi_exact = W.mms_annular(x, om, w, 0.0, 0.0)
+    ph = phi.cpu().numpy().reshape(P.E, P.n) @ basis.T
+    err = float(np.sqrt(np.sum(wd * (ph - phi_exact) ** 2)))
+    out = (err, P.E * P.n, rep)
+    P.close()
+    return out
+
+
+def ho_vs_lo(levels=(1, 2, 4)):
+    """High-order vs straightened low-order accuracy on the quarter annulus
+    (curved boundaries, the three material rings of the nested-annuli
+    problem), manufactured solution of eq. psiAnnularMMS, S4: Q3 meshes with
+    cubic DG (9k x 15k elements) against their straightening into linear
+    elements with linear DG (N_ref = 3: 27k x 45k elements), the format of
+    the paper's L2-error table."""
+    import workloads as W
+    from paper_1810_11080_amd import Context
+    ctx = Context(0)
+    rows = []
+    for k in levels:
+        ho = W.annulus_quarter(9 * k, 15 * k, 3, 4)
+        for name, wp in (("HO (Q3 mesh, p=3)", ho), ("straightened (Q1 mesh, p=1)", W.straightened(ho, p=1))):
+            err, unknowns, rep = mms_error(ctx, wp)
+            row = {"mesh": name, "refinement": k, "elements": int(wp.n_elements), "unknowns": int(unknowns),
+                   "l2_error": err, "sweeps": rep["iterations"], "solve_s": round(rep["seconds"], 4)}
+            rows.append(row)
+            note("| {mesh} | {refinement} | {elements} | {unknowns} | {l2_error:.4e} | {sweeps} |".format(**row))
+    return rows
+
+
 def calibrate_copy(nbytes: int = 1 << 30, reps: int = 3):
     """A plain streaming kernel of known traffic (read nbytes, write nbytes):
     the reference for scaling HBM counter readings to bytes."""
@@ -485,6 +535,8 @@ def main():
                     help="run only a copy kernel of known size (HBM counter calibration)")
     ap.add_argument("--weighting-study", action="store_true",
                     help="only the unity / face / sigma-inverse-face weighting comparison")
+    ap.add_argument("--ho-vs-lo", action="store_true",
+                    help="only the high-order vs straightened low-order manufactured-solution comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -502,6 +554,9 @@ def main():
         return
     if args.weighting_study:
         print(json.dumps({"weighting_study": weighting_study()}))
+        return
+    if args.ho_vs_lo:
+        print(json.dumps({"ho_vs_lo": ho_vs_lo()}))
         return
     if args.workload == "c4":
         bench_batch(args)

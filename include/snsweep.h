@@ -60,6 +60,13 @@ extern "C" {
 /* ------------------------------------------------------------ enumerations */
 #define SNSW_BC_VACUUM     0      /* psi_inc = 0                             */
 #define SNSW_BC_ISO_CONST  1      /* psi_inc = constant on all inflow faces  */
+#define SNSW_BC_TABULATED  2      /* psi_inc per direction and boundary node
+                                     (psi_inc_tab)                           */
+
+/* Layout of the volume source q (snsw_problem_desc.q_per_dof).              */
+#define SNSW_Q_PER_ELEMENT    0   /* [E]: isotropic, constant per element    */
+#define SNSW_Q_PER_DOF        1   /* [E][n]: isotropic, nodal values         */
+#define SNSW_Q_PER_DIRECTION  2   /* [D][E][n]: nodal values per direction   */
 
 #define SNSW_WEIGHT_UNITY       0 /* z = 1                                   */
 #define SNSW_WEIGHT_FACE        1 /* z = max |F_{e,e'}|                      */
@@ -122,8 +129,9 @@ typedef struct {
     const double* w;         /* [n_dirs] weights, sum 4*pi (sn_order == 0)    */
     const double* sigma_t;   /* [E] total cross section, > 0                  */
     const double* sigma_s;   /* [E] scattering cross section, >= 0            */
-    const double* q;         /* [E] (q_per_dof = 0) or [E][n] (= 1): isotropic
-                                source per steradian, nodal values            */
+    const double* q;         /* volume source per steradian, layout by
+                                q_per_dof (SNSW_Q_*): [E], [E][n] nodal, or
+                                [D][E][n] nodal per direction                 */
     int32_t q_per_dof;
     int32_t bc_kind;         /* SNSW_BC_*                                     */
     double  psi_inc;         /* incident flux for SNSW_BC_ISO_CONST           */
@@ -135,6 +143,10 @@ typedef struct {
     int32_t schedule;        /* SNSW_SCHED_*                                  */
     int32_t cache_inverse;   /* SNSW_CACHE_*: keep A^{-1} of every (element,
                                 direction) pair in device memory            */
+    const double* psi_inc_tab; /* SNSW_BC_TABULATED: [D][E][n] incident flux
+                                of direction d at the DG nodes of element e;
+                                only nodes on boundary faces through which d
+                                flows in are read (others are ignored)      */
 } snsw_problem_desc;
 
 /* Builds the discretisation and the sweep schedule (section 3): quadrature,
@@ -165,6 +177,43 @@ int snsw_problem_get_info(const snsw_problem* prob, snsw_problem_info* info);
 
 /* Quadrature actually used: omega [D][3], w [D] (host, caller-allocated). */
 int snsw_get_quadrature(const snsw_problem* prob, double* omega, double* w);
+
+/* Load vector of eq. qVectorDef for sources and incident fluxes given as
+ * nodal values (the DG interpolant is integrated exactly): the source term
+ * is M_e q (per direction with SNSW_Q_PER_DIRECTION); the boundary term of
+ * a slot through which direction d flows in is P_in psi_inc, with P_in the
+ * same inflow face block the sweep applies to an upwind neighbour (normal
+ * moments of the face, or the split integrals of a face where Omega . n
+ * changes sign).  Direction-dependent parts are assembled once into a fixed
+ * right-hand side per (element, direction) pair: D*E*n doubles of device
+ * memory while a SNSW_Q_PER_DIRECTION source or SNSW_BC_TABULATED inflow is
+ * set.
+ *
+ * Replaces the volume source and the boundary condition of an existing
+ * problem (arguments as the fields of the same names in snsw_problem_desc;
+ * host arrays, copied).  The graph, schedule and cached inverses do not
+ * depend on them and are kept, as is the stored angular flux.  Synchronous.
+ * Batches created earlier keep the old source: set sources before creating a
+ * batch that includes the problem.  Errors: SNSW_E_INVALID_ARG,
+ * SNSW_E_NONFINITE, SNSW_E_OOM, SNSW_E_HIP.                                  */
+int snsw_problem_set_source(snsw_problem* prob, int32_t q_per_dof, const double* q, int32_t bc_kind,
+                            double psi_inc, const double* psi_inc_tab);
+
+/* Physical coordinates of the DG nodes of elements [e0, e0+count): the mesh
+ * map of eq. elementTransformation at the Gauss-Lobatto nodes, host
+ * [count][n][dim] (caller-allocated).  For evaluating sources and incident
+ * fluxes at the nodes.                                                      */
+int snsw_get_node_coordinates(const snsw_problem* prob, int64_t e0, int64_t count, double* xyz);
+
+/* Tensor Gauss-Legendre rule on elements [e0, e0+count) with `extra` points
+ * per axis beyond the rule of the element matrices (extra in [0, 8]):
+ * *n_points receives Q, the points per element; if x is not NULL, x
+ * [count][Q][dim] receives the physical points, wdet [count][Q] the weights
+ * times |det J|, and basis (nullable) [Q][n] the DG basis at the reference
+ * points (the same for every element).  For error norms of nodal fields:
+ * int f over element e = sum_q wdet[e][q] f(x[e][q]).  Host arrays.          */
+int snsw_get_volume_rule(const snsw_problem* prob, int32_t extra, int64_t e0, int64_t count,
+                         int32_t* n_points, double* x, double* wdet, double* basis);
 
 /* Direction-independent element matrices of elements [e0, e0+count) (host,
  * caller-allocated): M [count][n][n] = int u_m u_n, K [count][dim][n][n] =

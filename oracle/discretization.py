@@ -22,7 +22,7 @@ from . import quadrature
 from .faces import FaceSet
 from .geometry import ElementGeometry
 
-VACUUM, ISO_CONST = 0, 1
+VACUUM, ISO_CONST, TABULATED = 0, 1, 2
 
 
 class Discretization:
@@ -51,6 +51,15 @@ class Discretization:
         self.q = np.asarray(prob.q, dtype=np.float64)
         self.bc_kind = prob.bc_kind
         self.psi_inc = prob.psi_inc if prob.bc_kind == ISO_CONST else 0.0
+        # nodal data per direction (reading: the source and the incident
+        # flux are given by their values at the DG nodes, and their loads are
+        # those of the DG interpolants): q_dir (D, E, n) replaces q; the
+        # tabulated inflow (D, E, n) is read at the nodes of inflow boundary
+        # faces
+        q_dir = getattr(prob, "q_dir", None)
+        self.q_dir = None if q_dir is None else np.asarray(q_dir, dtype=np.float64).reshape(-1, self.E, self.n)
+        tab = getattr(prob, "psi_inc_tab", None) if prob.bc_kind == TABULATED else None
+        self.psi_tab = None if tab is None else np.asarray(tab, dtype=np.float64).reshape(-1, self.E, self.n)
         # element -> slot -> (face, side, neighbour), trace nodes per slot
         e = np.arange(self.E)
         eidx, rem = [], e.copy()
@@ -80,6 +89,12 @@ class Discretization:
                                       for d in range(self.D)])
 
     # ------------------------------------------------------------------
+    def dir_index(self, d: int) -> int:
+        """Row of the per-direction nodal data for direction d (the data
+        covers the full quadrature; a Discretization built on a subset of
+        directions maps its d back through dir_rows)."""
+        return int(self.dir_rows[d]) if getattr(self, "dir_rows", None) is not None else d
+
     def opposite_slot(self, s: int) -> int:
         return s ^ 1
 
@@ -118,6 +133,9 @@ class Discretization:
         if self.src_load is not None:
             scat = self.sigma_s[elems, None] / (4.0 * np.pi) * phi[elems]
             return self.src_load[d][elems] + np.einsum("kmn,kn->km", self.M[elems], scat)
+        if self.q_dir is not None:
+            src = self.q_dir[self.dir_index(d)][elems] + self.sigma_s[elems, None] / (4.0 * np.pi) * phi[elems]
+            return np.einsum("kmn,kn->km", self.M[elems], src)
         src = self.q[elems, None] + self.sigma_s[elems, None] / (4.0 * np.pi) * phi[elems]
         return np.einsum("kmn,kn->km", self.M[elems], src)
 
@@ -148,6 +166,12 @@ class Discretization:
                 src = np.where(lagged_mask[:, s][:, None], psi_lag[np.maximum(nbr, 0)][:, tn_up],
                                psi_kept[np.maximum(nbr, 0)][:, tn_up])
                 up = np.where(interior[:, None], src, 0.0)
+            if self.psi_tab is not None:
+                # tabulated incident flux at this element's own face nodes
+                tab = self.psi_tab[self.dir_index(d)][elems][:, tn]
+                up = np.where(interior[:, None], up, tab)
+                b[:, tn] += np.einsum("kab,kb->ka", Pin, up)
+                continue
             if self.inflow_fn is not None:
                 up = np.where(interior[:, None], up, 0.0)
                 b[:, tn] += np.einsum("kab,kb->ka", Pin, up)

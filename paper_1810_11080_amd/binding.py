@@ -30,7 +30,7 @@ class SnswProblemDesc(C.Structure):
                 ("q_per_dof", C.c_int32), ("bc_kind", C.c_int32), ("psi_inc", C.c_double),
                 ("weighting", C.c_int32), ("exact_scc_max", C.c_int32),
                 ("precision", C.c_int32), ("n_threads", C.c_int32), ("schedule", C.c_int32),
-                ("cache_inverse", C.c_int32)]
+                ("cache_inverse", C.c_int32), ("psi_inc_tab", c_double_p)]
 
 
 class SnswProblemInfo(C.Structure):
@@ -88,6 +88,10 @@ SIGNATURES = {
     "snsw_problem_get_info": (C.c_int, [C.c_void_p, C.POINTER(SnswProblemInfo)]),
     "snsw_get_quadrature": (C.c_int, [C.c_void_p, c_double_p, c_double_p]),
     "snsw_get_element_matrices": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, c_double_p, c_double_p]),
+    "snsw_problem_set_source": (C.c_int, [C.c_void_p, C.c_int32, c_double_p, C.c_int32, C.c_double, c_double_p]),
+    "snsw_get_node_coordinates": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, c_double_p]),
+    "snsw_get_volume_rule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, c_int32_p, c_double_p,
+                                       c_double_p, c_double_p]),
     "snsw_graph_stats_get": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(SnswGraphStats)]),
     "snsw_get_edges": (C.c_int, [C.c_void_p, C.c_int, c_int32_p, c_int32_p, c_int64_p, C.c_int64,
                                  c_int64_p]),
@@ -130,6 +134,17 @@ SIGNATURES = {
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "SHAPE", -3: "NONFINITE", -4: "BAD_JACOBIAN",
           -5: "NOT_CONVERGED", -6: "DIVERGED", -7: "HIP", -8: "OOM", -9: "UNSUPPORTED",
           -10: "STATE"}
+
+
+def _q_kind(qa, E: int, n: int) -> int:
+    """Layout code of a source array: 0 [E], 1 [E][n], 2 [D][E][n]."""
+    if qa.size == E:
+        return 0
+    if qa.size == E * n:
+        return 1
+    if qa.size % (E * n) == 0:
+        return 2
+    raise ValueError(f"source has {qa.size} entries: expected E, E*n or D*E*n")
 
 
 class SnswError(RuntimeError):
@@ -225,7 +240,10 @@ class Problem:
 
     def __init__(self, ctx: Context, *, dim, nx, geom_order, dg_order, lattice, sn_order,
                  sigma_t, sigma_s, q, bc_kind=0, psi_inc=0.0, weighting=1, exact_scc_max=10,
-                 precision=0, n_threads=0, omega=None, w=None, schedule=0, cache_inverse=0):
+                 precision=0, n_threads=0, omega=None, w=None, schedule=0, cache_inverse=0,
+                 psi_inc_tab=None):
+        """q: [E] or [E][n] isotropic, or [D][E][n] per direction (nodal
+        values); psi_inc_tab: [D][E][n] incident flux for bc_kind 2."""
         self.ctx = ctx
         if dim not in (2, 3):
             raise SnswError(-1, "dim must be 2 or 3")
@@ -256,10 +274,12 @@ class Problem:
         desc.sigma_t = arr(sigma_t, E)
         desc.sigma_s = arr(sigma_s, E)
         qa = np.asarray(q, dtype=np.float64)
-        desc.q_per_dof = 1 if qa.size == E * n and qa.size != E else 0
-        desc.q = arr(qa, E * n if desc.q_per_dof else E)
+        desc.q_per_dof = _q_kind(qa, E, n)
+        desc.q = arr(qa)
         desc.bc_kind = bc_kind
         desc.psi_inc = psi_inc
+        if psi_inc_tab is not None:
+            desc.psi_inc_tab = arr(psi_inc_tab)
         desc.weighting = weighting
         desc.exact_scc_max = exact_scc_max
         desc.precision = precision
@@ -279,13 +299,45 @@ class Problem:
     def from_workload(cls, ctx: Context, prob, precision=0, n_threads=0, weighting=None,
                       exact_scc_max=None, schedule=0, cache_inverse=0):
         """Build from a ``workloads.Problem`` (seeded synthetic inputs)."""
+        q_dir = getattr(prob, "q_dir", None)
         return cls(ctx, dim=prob.dim, nx=tuple(prob.nx), geom_order=prob.r, dg_order=prob.p,
                    lattice=prob.lattice, sn_order=prob.sn_order, sigma_t=prob.sigma_t,
-                   sigma_s=prob.sigma_s, q=prob.q, bc_kind=prob.bc_kind, psi_inc=prob.psi_inc,
+                   sigma_s=prob.sigma_s, q=prob.q if q_dir is None else q_dir, bc_kind=prob.bc_kind,
+                   psi_inc=prob.psi_inc, psi_inc_tab=getattr(prob, "psi_inc_tab", None),
                    weighting=prob.weighting if weighting is None else weighting,
                    exact_scc_max=prob.exact_scc_max if exact_scc_max is None else exact_scc_max,
                    precision=precision, n_threads=n_threads, schedule=schedule,
                    cache_inverse=cache_inverse)
+
+    def set_source(self, q, bc_kind=0, psi_inc=0.0, psi_inc_tab=None):
+        """Replace the volume source and boundary condition (snsw_problem_set_source)."""
+        qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+        kind = _q_kind(qa, self.E, self.n)
+        tab = None if psi_inc_tab is None else np.ascontiguousarray(np.asarray(psi_inc_tab, dtype=np.float64))
+        if tab is not None and tab.size != self.D * self.E * self.n:
+            raise ValueError("psi_inc_tab must have D*E*n entries")
+        if kind == 2 and qa.size != self.D * self.E * self.n:
+            raise ValueError("a per-direction source must have D*E*n entries")
+        _check(lib().snsw_problem_set_source(self.handle, kind, _dptr(qa, C.c_double), bc_kind, psi_inc,
+                                             _dptr(tab, C.c_double) if tab is not None else None))
+
+    def node_coordinates(self):
+        """(E, n, dim) physical coordinates of the DG nodes."""
+        out = np.zeros((self.E, self.n, self.dim))
+        _check(lib().snsw_get_node_coordinates(self.handle, 0, self.E, _dptr(out, C.c_double)))
+        return out
+
+    def volume_rule(self, extra=0):
+        """(x (E, Q, dim), wdet (E, Q), basis (Q, n)) of the tensor Gauss rule
+        with `extra` points per axis beyond the element-matrix rule."""
+        Q = C.c_int32()
+        _check(lib().snsw_get_volume_rule(self.handle, extra, 0, self.E, C.byref(Q), None, None, None))
+        x = np.zeros((self.E, Q.value, self.dim))
+        wd = np.zeros((self.E, Q.value))
+        basis = np.zeros((Q.value, self.n))
+        _check(lib().snsw_get_volume_rule(self.handle, extra, 0, self.E, C.byref(Q), _dptr(x, C.c_double),
+                                          _dptr(wd, C.c_double), _dptr(basis, C.c_double)))
+        return x, wd, basis
 
     def close(self):
         if getattr(self, "handle", None):

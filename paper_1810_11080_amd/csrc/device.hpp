@@ -80,6 +80,7 @@ struct DeviceProblem {
     double* sigma_t = nullptr;
     double* sigma_s = nullptr;
     double* q = nullptr;
+    double* rhs_dir = nullptr;    // [D][E][n] fixed right-hand side per pair, or null
     double* omega = nullptr;
     double* w = nullptr;
     double* src = nullptr;        // [E][n]

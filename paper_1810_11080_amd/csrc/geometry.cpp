@@ -45,7 +45,90 @@ void tensor_tables(int dim, const std::vector<double>& nodes, const std::vector<
     }
 }
 
+// Control points of element e of the structured lattice, [(r+1)^dim][dim],
+// local order a + (r+1) (b + (r+1) c).
+void element_ctrl(const HostProblem& hp, int64_t e, double* xe) {
+    const int dim = hp.dim, r = hp.r;
+    int L[3] = {1, 1, 1};
+    for (int a = 0; a < dim; ++a) L[a] = r * hp.nx[a] + 1;
+    int ei[3] = {0, 0, 0};
+    int64_t re = e;
+    for (int ax = 0; ax < dim; ++ax) { ei[ax] = (int)(re % hp.nx[ax]); re /= hp.nx[ax]; }
+    int Nv = 1;
+    for (int a = 0; a < dim; ++a) Nv *= r + 1;
+    for (int m = 0; m < Nv; ++m) {
+        int mi[3] = {0, 0, 0}, rm = m;
+        for (int ax = 0; ax < dim; ++ax) { mi[ax] = rm % (r + 1); rm /= r + 1; }
+        int64_t lid = 0, stride = 1;
+        for (int ax = 0; ax < dim; ++ax) { lid += (int64_t)(r * ei[ax] + mi[ax]) * stride; stride *= L[ax]; }
+        for (int c = 0; c < dim; ++c) xe[m * dim + c] = hp.lattice[lid * dim + c];
+    }
+}
+
+std::vector<double> equispaced(int r) {
+    std::vector<double> g(r + 1);
+    for (int a = 0; a <= r; ++a) g[a] = (double)a / r;
+    return g;
+}
+
 }  // namespace
+
+void node_coordinates(const HostProblem& hp, int64_t e0, int64_t count, double* xyz) {
+    const int dim = hp.dim, n = hp.n;
+    std::vector<double> Vg, Gg;
+    tensor_tables(dim, equispaced(hp.r), gll01(hp.p), Vg, Gg);
+    const int Nv = (int)(Vg.size() / n);
+    std::vector<double> xe((size_t)Nv * dim);
+    for (int64_t e = e0; e < e0 + count; ++e) {
+        element_ctrl(hp, e, xe.data());
+        for (int q = 0; q < n; ++q)
+            for (int c = 0; c < dim; ++c) {
+                double v = 0.0;
+                for (int m = 0; m < Nv; ++m) v += xe[m * dim + c] * Vg[(size_t)q * Nv + m];
+                xyz[((e - e0) * n + q) * dim + c] = v;
+            }
+    }
+}
+
+int volume_rule(const HostProblem& hp, int extra, int64_t e0, int64_t count, double* x, double* wdet,
+                double* basis) {
+    const int dim = hp.dim, r = hp.r, p = hp.p, n = hp.n;
+    const int nq1 = (dim == 2 ? p + r : p + (3 * r + 1) / 2) + extra;
+    int Q = 1;
+    for (int a = 0; a < dim; ++a) Q *= nq1;
+    if (!x) return Q;
+    std::vector<double> x1, w1;
+    gauss_legendre01(nq1, x1, w1);
+    std::vector<double> Vg, Gg, U, GU;
+    tensor_tables(dim, equispaced(r), x1, Vg, Gg);
+    tensor_tables(dim, gll01(p), x1, U, GU);
+    const int Nv = (int)(Vg.size() / Q);
+    if (basis) std::copy(U.begin(), U.end(), basis);
+    std::vector<double> xe((size_t)Nv * dim);
+    for (int64_t e = e0; e < e0 + count; ++e) {
+        element_ctrl(hp, e, xe.data());
+        for (int q = 0; q < Q; ++q) {
+            double J[3][3] = {{0}}, X[3] = {0, 0, 0};
+            for (int m = 0; m < Nv; ++m)
+                for (int c = 0; c < dim; ++c) {
+                    X[c] += xe[m * dim + c] * Vg[(size_t)q * Nv + m];
+                    for (int b = 0; b < dim; ++b) J[c][b] += xe[m * dim + c] * Gg[((size_t)q * Nv + m) * dim + b];
+                }
+            double det;
+            if (dim == 2) det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            else
+                det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                      J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+            double wq = 1.0;
+            int rq = q;
+            for (int a = 0; a < dim; ++a) { wq *= w1[rq % nq1]; rq /= nq1; }
+            for (int c = 0; c < dim; ++c) x[((e - e0) * Q + q) * dim + c] = X[c];
+            wdet[(e - e0) * Q + q] = wq * std::fabs(det);
+        }
+    }
+    return Q;
+}
 
 void build_geometry(HostProblem& hp) {
     const int dim = hp.dim, r = hp.r, p = hp.p, n = hp.n;
@@ -67,8 +150,6 @@ void build_geometry(HostProblem& hp) {
         for (int a = 0; a < dim; ++a) { ww *= w1[rq % nq1]; rq /= nq1; }
         wq[q] = ww;
     }
-    int L[3] = {1, 1, 1};
-    for (int a = 0; a < dim; ++a) L[a] = r * hp.nx[a] + 1;
     hp.M.assign((size_t)hp.E * n * n, 0.0);
     hp.K.assign((size_t)hp.E * dim * n * n, 0.0);
     std::atomic<bool> bad(false);
@@ -77,16 +158,7 @@ void build_geometry(HostProblem& hp) {
         std::vector<double> xe(Nv * dim), a(n), gx(n * dim);
         double local_min = 1e300;
         for (int64_t e = e0; e < e1; ++e) {
-            int ei[3] = {0, 0, 0};
-            int64_t re = e;
-            for (int ax = 0; ax < dim; ++ax) { ei[ax] = (int)(re % hp.nx[ax]); re /= hp.nx[ax]; }
-            for (int m = 0; m < Nv; ++m) {
-                int mi[3] = {0, 0, 0}, rm = m;
-                for (int ax = 0; ax < dim; ++ax) { mi[ax] = rm % (r + 1); rm /= r + 1; }
-                int64_t lid = 0, stride = 1;
-                for (int ax = 0; ax < dim; ++ax) { lid += (int64_t)(r * ei[ax] + mi[ax]) * stride; stride *= L[ax]; }
-                for (int c = 0; c < dim; ++c) xe[m * dim + c] = hp.lattice[lid * dim + c];
-            }
+            element_ctrl(hp, e, xe.data());
             double* Me = &hp.M[(size_t)e * n * n];
             double* Ke = &hp.K[(size_t)e * dim * n * n];
             for (int q = 0; q < Q; ++q) {

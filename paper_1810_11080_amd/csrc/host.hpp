@@ -77,7 +77,10 @@ struct HostProblem {
     double psi_inc = 0.0;
     std::vector<double> lattice;              // [L][dim]
     std::vector<double> omega, w;             // [D][3], [D]
-    std::vector<double> sigma_t, sigma_s, q;  // [E], [E], [E][n]
+    std::vector<double> sigma_t, sigma_s, q;  // [E], [E], [E][n] (isotropic source)
+    std::vector<double> q_dir;                // [D][E][n] direction-dependent source, or empty
+    std::vector<double> psi_tab;              // [D][E][n] tabulated incident flux, or empty
+    std::vector<double> rhs_fixed;            // [D][E][n] M q_dir + tabulated inflow, or empty
     // element matrices, row-major (m, n)
     std::vector<double> M, K;                 // [E][n][n], [E][dim][n][n]
     // faces
@@ -112,6 +115,17 @@ void build_faces(HostProblem& hp);
 // mm = int max(-g,0); for FC_KINK also the matrices Pp, Pm (nf x nf).
 uint8_t face_integrals(const HostProblem& hp, int64_t f, const double* om, double& mp,
                        double& mm, double* Pp, double* Pm);
+// sources.cpp: fixed right-hand side per pair from q_dir and psi_tab
+// (needs the element matrices, faces and graphs)
+void build_fixed_rhs(HostProblem& hp);
+// Physical coordinates of the DG nodes of elements [e0, e0+count): [count][n][dim].
+void node_coordinates(const HostProblem& hp, int64_t e0, int64_t count, double* xyz);
+// Volume rule with `extra` Gauss points per axis beyond the element-matrix
+// rule: points per element (returned), and if x is not null the physical
+// points [count][Q][dim], weights times |det J| [count][Q] and, if basis is
+// not null, the DG basis at the reference points [Q][n].
+int volume_rule(const HostProblem& hp, int extra, int64_t e0, int64_t count, double* x, double* wdet,
+                double* basis);
 // graph.cpp: per-direction graph, FAS and levels; combined schedule
 void build_graphs(HostProblem& hp);
 void build_schedule(HostProblem& hp);

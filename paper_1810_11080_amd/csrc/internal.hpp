@@ -24,6 +24,7 @@ namespace snsw {
 void device_check_ctx(snsw_ctx* ctx);           // validates the device id
 void device_upload(snsw_problem* prob);         // allocates and copies
 void device_release(snsw_problem* prob) noexcept;
+void device_update_source(snsw_problem* prob);  // re-uploads q and the fixed right-hand side
 }  // namespace snsw
 
 // Wraps a C-ABI body: maps snsw::Error / std::bad_alloc / others to codes.

@@ -153,7 +153,18 @@ __device__ __forceinline__ SweepArgs load_args(const SweepArgs* table, int k) {
     a.persistent = c->persistent;
     a.ainv = c->ainv;
     a.Bsym = c->Bsym;
+    a.rhs_dir = c->rhs_dir;
     return a;
+}
+
+// Volume source of row `row` of pair (e, d): the direction-independent
+// src = M (q + sigma_s phi / (4 pi)), plus the optional per-pair fixed term
+// (direction-dependent source and tabulated boundary inflow, assembled at
+// setup; null when the problem has neither).
+__device__ __forceinline__ double source_row(const SweepArgs& args, int e, int d, int row, int N) {
+    double v = args.src[(size_t)e * N + row];
+    if (args.rhs_dir) v += args.rhs_dir[((size_t)d * args.E + e) * N + row];
+    return v;
 }
 
 // Assembles row `row` of A and b for pair (e, d).  With DEFER, inflow through
@@ -187,7 +198,7 @@ __device__ __forceinline__ void assemble_row(const SweepArgs& args, int4 pr, int
         }
         if (N > 16) __builtin_amdgcn_sched_barrier(0);
     }
-    rhs = args.src[(size_t)e * N + row];
+    rhs = source_row(args, e, d, row, N);
     kept = 0;
     int kc = 0;
 #pragma unroll
@@ -732,7 +743,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
                 kc += (cls == kKink) ? 1 : 0;
             }
         }
-        double rhs = args.src[(size_t)e * N + row];
+        double rhs = source_row(args, e, d, row, N);
         unsigned kept = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -993,7 +1004,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
                 kc += (cls == kKink) ? 1 : 0;
             }
         }
-        double rhs = args.src[(size_t)e * N + row];
+        double rhs = source_row(args, e, d, row, N);
         const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1];
         unsigned kept = 0;
 #pragma unroll
@@ -1184,7 +1195,7 @@ __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int
     const int e = pr.x;
     const unsigned packed = (unsigned)pr.y;
     const int d = (int)(packed & kDirMask);
-    double rhs = args.src[(size_t)e * N + row];
+    double rhs = source_row(args, e, d, row, N);
     const double o0 = args.omega[3 * d + 0], o1 = args.omega[3 * d + 1], o2 = args.omega[3 * d + 2];
     int kc = 0;
     unsigned kept = 0;
@@ -1290,7 +1301,7 @@ __device__ __forceinline__ double inflow_rhs_coop(const SweepArgs& args, int4 pr
         cf[s][row] = t;
     }
     wave_sync();
-    double rhs = in_group ? args.src[(size_t)e * N + row] : 0.0;
+    double rhs = in_group ? source_row(args, e, d, row, N) : 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
@@ -1371,7 +1382,7 @@ __device__ __forceinline__ double inflow_rhs_staged(const SweepArgs& args, int4 
         cf[s][row] = t;
     }
     wave_sync();
-    double rhs = in_group ? args.src[(size_t)e * N + row] : 0.0;
+    double rhs = in_group ? source_row(args, e, d, row, N) : 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;

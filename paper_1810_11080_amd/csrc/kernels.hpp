@@ -33,6 +33,8 @@ struct SweepArgs {
     const double* ainv;       // [D][E] blocks of cached A^{-1} (kernels.hip InvLayout; null: not cached)
     const double* Bsym;       // 3D: [F][dim][nf (nf + 1) / 2] the face moments (symmetric in the two
                               // face nodes), upper triangle row by row (null in 2D)
+    const double* rhs_dir;    // [D][E][n] fixed right-hand side per pair: M q_d (direction-dependent
+                              // source) + tabulated boundary inflow; null when the problem has neither
 };
 
 // Persistent sweeps take batches from kStreams counters per schedule, each

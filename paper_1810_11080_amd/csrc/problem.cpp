@@ -79,6 +79,39 @@ static void check_finite(const double* a, size_t n, const char* name) {
         if (!std::isfinite(a[i])) throw Error(SNSW_E_NONFINITE, std::string("non-finite value in ") + name);
 }
 
+// Validates and stores the volume source and the boundary condition (the
+// fixed right-hand side is rebuilt separately, once the discretisation
+// exists).
+static void set_host_source(HostProblem& hp, int q_kind, const double* q, int bc, double psi_inc,
+                            const double* psi_tab) {
+    if (!q) throw Error(SNSW_E_INVALID_ARG, "source q is NULL");
+    if (bc != SNSW_BC_VACUUM && bc != SNSW_BC_ISO_CONST && bc != SNSW_BC_TABULATED)
+        throw Error(SNSW_E_INVALID_ARG, "bc_kind");
+    if (q_kind != SNSW_Q_PER_ELEMENT && q_kind != SNSW_Q_PER_DOF && q_kind != SNSW_Q_PER_DIRECTION)
+        throw Error(SNSW_E_INVALID_ARG, "q_per_dof must be 0, 1 or 2");
+    if (bc == SNSW_BC_TABULATED && !psi_tab) throw Error(SNSW_E_INVALID_ARG, "psi_inc_tab is NULL");
+    const size_t en = (size_t)hp.E * hp.n, den = (size_t)hp.D * en;
+    std::vector<double> qn(en, 0.0), qd, pt;
+    if (q_kind == SNSW_Q_PER_DOF) std::copy(q, q + en, qn.begin());
+    else if (q_kind == SNSW_Q_PER_ELEMENT)
+        for (int64_t e = 0; e < hp.E; ++e)
+            for (int i = 0; i < hp.n; ++i) qn[(size_t)e * hp.n + i] = q[e];
+    else qd.assign(q, q + den);
+    check_finite(qn.data(), qn.size(), "q");
+    check_finite(qd.data(), qd.size(), "q");
+    if (bc == SNSW_BC_TABULATED) {
+        pt.assign(psi_tab, psi_tab + den);
+        check_finite(pt.data(), pt.size(), "psi_inc_tab");
+    }
+    const double pin = bc == SNSW_BC_ISO_CONST ? psi_inc : 0.0;
+    if (!std::isfinite(pin)) throw Error(SNSW_E_NONFINITE, "psi_inc");
+    hp.bc = bc;
+    hp.psi_inc = pin;
+    hp.q.swap(qn);
+    hp.q_dir.swap(qd);
+    hp.psi_tab.swap(pt);
+}
+
 int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_problem** out) {
     return snsw_guard([&] {
         if (!ctx || !desc || !out) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
@@ -133,10 +166,7 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
             throw Error(SNSW_E_UNSUPPORTED, "cached inverses are FP64 only");
         if (desc->precision == SNSW_PREC_MIXED && hp.schedule == SNSW_SCHED_PERSISTENT)
             throw Error(SNSW_E_UNSUPPORTED, "mixed precision runs on the LEVELS schedule");
-        hp.bc = desc->bc_kind;
-        if (hp.bc != SNSW_BC_VACUUM && hp.bc != SNSW_BC_ISO_CONST) throw Error(SNSW_E_INVALID_ARG, "bc_kind");
-        hp.psi_inc = hp.bc == SNSW_BC_ISO_CONST ? desc->psi_inc : 0.0;
-        if (!std::isfinite(hp.psi_inc)) throw Error(SNSW_E_NONFINITE, "psi_inc");
+
         // lattice
         if (!desc->lattice) throw Error(SNSW_E_INVALID_ARG, "lattice is NULL");
         int64_t Lp = 1;
@@ -157,7 +187,7 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
         hp.D = (int)hp.w.size();
         if (hp.D >= (1 << kDirBits)) throw Error(SNSW_E_SHAPE, "too many directions (max 1023)");
         // materials and source
-        if (!desc->sigma_t || !desc->sigma_s || !desc->q) throw Error(SNSW_E_INVALID_ARG, "materials/source NULL");
+        if (!desc->sigma_t || !desc->sigma_s) throw Error(SNSW_E_INVALID_ARG, "materials NULL");
         hp.sigma_t.assign(desc->sigma_t, desc->sigma_t + hp.E);
         hp.sigma_s.assign(desc->sigma_s, desc->sigma_s + hp.E);
         check_finite(hp.sigma_t.data(), hp.E, "sigma_t");
@@ -166,17 +196,13 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
             if (!(hp.sigma_t[e] > 0.0)) throw Error(SNSW_E_INVALID_ARG, "sigma_t must be > 0");
             if (hp.sigma_s[e] < 0.0) throw Error(SNSW_E_INVALID_ARG, "sigma_s must be >= 0");
         }
-        hp.q.assign((size_t)hp.E * hp.n, 0.0);
-        if (desc->q_per_dof) std::copy(desc->q, desc->q + hp.E * hp.n, hp.q.begin());
-        else
-            for (int64_t e = 0; e < hp.E; ++e)
-                for (int i = 0; i < hp.n; ++i) hp.q[(size_t)e * hp.n + i] = desc->q[e];
-        check_finite(hp.q.data(), hp.q.size(), "q");
+        set_host_source(hp, desc->q_per_dof, desc->q, desc->bc_kind, desc->psi_inc, desc->psi_inc_tab);
 
         build_geometry(hp);
         build_faces(hp);
         build_graphs(hp);
         build_schedule(hp);
+        build_fixed_rhs(hp);
         // tiles of T x T elements per persistent batch for the DPP shapes
         if (hp.dim == 2 && (hp.n == 16 || hp.n == 4)) build_tiled_schedule(hp, hp.n == 16 ? 2 : 4);
         hp.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -226,6 +252,36 @@ int snsw_get_quadrature(const snsw_problem* prob, double* omega, double* w) {
         if (!prob || !omega || !w) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
         std::copy(prob->hp.omega.begin(), prob->hp.omega.end(), omega);
         std::copy(prob->hp.w.begin(), prob->hp.w.end(), w);
+    });
+}
+
+int snsw_problem_set_source(snsw_problem* prob, int32_t q_per_dof, const double* q, int32_t bc_kind, double psi_inc,
+                            const double* psi_inc_tab) {
+    return snsw_guard([&] {
+        if (!prob) throw Error(SNSW_E_INVALID_ARG, "NULL problem");
+        HostProblem& hp = prob->hp;
+        set_host_source(hp, q_per_dof, q, bc_kind, psi_inc, psi_inc_tab);
+        build_fixed_rhs(hp);
+        if (prob->dev) device_update_source(prob);
+    });
+}
+
+int snsw_get_node_coordinates(const snsw_problem* prob, int64_t e0, int64_t count, double* xyz) {
+    return snsw_guard([&] {
+        if (!prob || !xyz) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
+        if (e0 < 0 || count < 0 || e0 + count > prob->hp.E) throw Error(SNSW_E_SHAPE, "element range");
+        node_coordinates(prob->hp, e0, count, xyz);
+    });
+}
+
+int snsw_get_volume_rule(const snsw_problem* prob, int32_t extra, int64_t e0, int64_t count, int32_t* n_points,
+                         double* x, double* wdet, double* basis) {
+    return snsw_guard([&] {
+        if (!prob || !n_points) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
+        if (extra < 0 || extra > 8) throw Error(SNSW_E_INVALID_ARG, "extra must be 0..8");
+        if (e0 < 0 || count < 0 || e0 + count > prob->hp.E) throw Error(SNSW_E_SHAPE, "element range");
+        if (x && !wdet) throw Error(SNSW_E_INVALID_ARG, "wdet is NULL");
+        *n_points = volume_rule(prob->hp, extra, e0, count, x, wdet, basis);
     });
 }
 

@@ -1,6 +1,8 @@
 // Device side of a problem: uploads, one sweep, source iteration, state.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include <algorithm>
 #include <chrono>
 #include <climits>
@@ -144,6 +146,7 @@ SweepArgs make_args(const snsw_problem* prob, int cur) {
     a.persistent = 0;
     a.ainv = dp->ainv;
     a.Bsym = dp->Bsym;
+    a.rhs_dir = hp.rhs_fixed.empty() ? nullptr : dp->rhs_dir;
     return a;
 }
 
@@ -304,6 +307,7 @@ void device_upload(snsw_problem* prob) {
     dp->sigma_t = dupload(dp, hp.sigma_t, s);
     dp->sigma_s = dupload(dp, hp.sigma_s, s);
     dp->q = dupload(dp, hp.q, s);
+    if (!hp.rhs_fixed.empty()) dp->rhs_dir = dupload(dp, hp.rhs_fixed, s);
     dp->omega = dupload(dp, hp.omega, s);
     dp->w = dupload(dp, hp.w, s);
     dp->src = dalloc<double>(dp, (size_t)hp.E * n);
@@ -361,6 +365,26 @@ void device_upload(snsw_problem* prob) {
     HIP_OK(hipStreamSynchronize(s));
 }
 
+void device_update_source(snsw_problem* prob) {
+    DeviceProblem* dp = prob->dev;
+    const HostProblem& hp = prob->hp;
+    DeviceGuard g(dp->device);
+    hipStream_t s = dp->stream;
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipMemcpy(dp->q, hp.q.data(), sizeof(double) * hp.q.size(), hipMemcpyHostToDevice));
+    if (!hp.rhs_fixed.empty()) {
+        if (!dp->rhs_dir) dp->rhs_dir = dalloc<double>(dp, hp.rhs_fixed.size());
+        HIP_OK(hipMemcpy(dp->rhs_dir, hp.rhs_fixed.data(), sizeof(double) * hp.rhs_fixed.size(),
+                         hipMemcpyHostToDevice));
+    }
+    // patch the problem's table entry (its flux buffers stay as they are)
+    const double* rd = hp.rhs_fixed.empty() ? nullptr : dp->rhs_dir;
+    HIP_OK(hipMemcpy(reinterpret_cast<char*>(dp->table) + offsetof(SweepArgs, rhs_dir), &rd, sizeof(rd),
+                     hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(reinterpret_cast<char*>(dp->table) + offsetof(SweepArgs, psi_inc), &hp.psi_inc,
+                     sizeof(double), hipMemcpyHostToDevice));
+}
+
 void device_release(snsw_problem* prob) noexcept {
     DeviceProblem* dp = prob->dev;
     if (!dp) return;
@@ -371,7 +395,7 @@ void device_release(snsw_problem* prob) noexcept {
     dp->prof.release();
     void* ptrs[] = {dp->geo, dp->B, dp->Bsym, dp->kink_tab, dp->kink_idx, dp->pairs, dp->tpairs, dp->tintra, dp->tslots,
                     dp->slot_face, dp->slot_nbr,
-                    dp->sigma_t, dp->sigma_s, dp->q, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
+                    dp->sigma_t, dp->sigma_s, dp->q, dp->rhs_dir, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
                     dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table, dp->ainv};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);

@@ -105,3 +105,56 @@ def test_mms_convergence(p):
     errs = [mms_error(n, p) for n in ns]
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(len(ns) - 1)]
     assert rates[-1] > p + 0.4, (errs, rates)
+
+
+def mms_error_nodal(n, p):
+    """The same manufactured problem with the source and the incident flux
+    given by their values at the DG nodes (per direction), as the library
+    takes them."""
+    import dataclasses
+    from oracle.geometry import ElementGeometry
+    from oracle.quadrature import level_symmetric
+    st, ss = 1.0, 0.5
+    prob = W.small(dim=2, n=n, r=2, p=p, N=4, amp=0.05, freq=1, sigma_t=st, c=ss / st, q=0.0)
+    om, w = level_symmetric(4, 2)
+    g = ElementGeometry(prob.lattice, 2, prob.nx, 2, p)
+    q, psi_exact, _ = W.mms_annular(g.dg_node_positions(), om, w, st, ss)
+    prob = dataclasses.replace(prob, q_dir=q, psi_inc_tab=psi_exact, bc_kind=W.TABULATED)
+    disc = Discretization(prob)
+    gs = build_graphs(disc)
+    phi, psi, it, rho = source_iteration(disc, gs, tol=1e-13, max_iters=300)
+    fine = ElementGeometry(prob.lattice, 2, prob.nx, 2, p, extra_points=4)
+    _, _, phi_exact = W.mms_annular(fine.x, om, w, st, ss)
+    phih = np.einsum("en,qn->eq", phi, fine.U)
+    return np.sqrt(np.einsum("q,eq,eq->", fine.wq, fine.detJ, (phih - phi_exact) ** 2))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_mms_convergence_nodal_data(p):
+    """Nodal (interpolated) source and tabulated inflow keep order p+1."""
+    ns = [4, 8, 16]
+    errs = [mms_error_nodal(n, p) for n in ns]
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(len(ns) - 1)]
+    assert rates[-1] > p + 0.4, (errs, rates)
+
+
+@pytest.mark.parametrize("dim,n,r,p,N,amp,freq", [(2, 5, 3, 2, 8, 0.3 / 5, 2), (3, 3, 2, 2, 4, 0.07, 1)])
+def test_constant_solution_tabulated(dim, n, r, p, N, amp, freq):
+    """psi = C per direction (C_d differs between directions), sigma_s = 0:
+    source sigma_t C_d at every node and tabulated inflow C_d reproduce
+    psi_d = C_d exactly on a curved mesh (the boundary term of eq. qVectorDef
+    taken from tabulated nodal values)."""
+    import dataclasses
+    prob = W.small(dim=dim, n=n, r=r, p=p, N=N, amp=amp, freq=freq, sigma_t=1.0, c=0.0, q=0.0)
+    E, nd = prob.n_elements, prob.n_dof
+    D = prob.n_dirs
+    st = np.linspace(0.5, 2.0, E)
+    Cd = 1.0 + 0.1 * np.arange(D)
+    q = Cd[:, None, None] * st[None, :, None] * np.ones((D, E, nd))
+    tab = Cd[:, None, None] * np.ones((D, E, nd))
+    prob = dataclasses.replace(prob, sigma_t=st, sigma_s=np.zeros(E), q_dir=q, psi_inc_tab=tab,
+                               bc_kind=W.TABULATED)
+    disc = Discretization(prob)
+    gs = build_graphs(disc)
+    _, psi, _, _ = source_iteration(disc, gs, tol=1e-15, max_iters=200)
+    assert np.abs(psi - Cd[:, None, None]).max() < 1e-10

@@ -33,6 +33,7 @@ import numpy as np
 
 VACUUM = 0
 ISO_CONST = 1
+TABULATED = 2
 
 
 @dataclass
@@ -54,6 +55,9 @@ class Problem:
     weighting: int = 1     # 0 unity, 1 face, 2 sigma-inverse face
     exact_scc_max: int = 10
     meta: dict = field(default_factory=dict)
+    # optional direction-dependent data, nodal values at the DG nodes:
+    q_dir: Optional[np.ndarray] = None        # (D, E, n) source per direction (replaces q)
+    psi_inc_tab: Optional[np.ndarray] = None  # (D, E, n) incident flux (bc_kind TABULATED)
 
     @property
     def n_elements(self) -> int:
@@ -346,3 +350,58 @@ def corner_block(prob: Problem, m: int) -> Problem:
     return replace(prob, name=f"{prob.name}_corner{m}", nx=sub, lattice=lat,
                    sigma_t=prob.sigma_t[keep].copy(), sigma_s=prob.sigma_s[keep].copy(),
                    q=prob.q[keep].copy(), meta=dict(prob.meta, corner_of=prob.name, corner=m))
+
+
+def random_direction_data(prob: Problem, n_dirs: int, seed: int) -> tuple:
+    """Seeded nodal data per direction: a source q_dir uniform in [0, 2] and
+    an incident flux uniform in [0.5, 1.5], both (D, E, n)."""
+    rng = np.random.default_rng(seed)
+    shape = (n_dirs, prob.n_elements, prob.n_dof)
+    return rng.uniform(0.0, 2.0, shape), rng.uniform(0.5, 1.5, shape)
+
+
+def mms_annular(xyz: np.ndarray, omega: np.ndarray, w: np.ndarray, sigma_t, sigma_s) -> tuple:
+    """The manufactured solution of the paper's annulus test (eq.
+    psiAnnularMMS), psi_d(x, y) = f(x, y) (mu_d^2 + eta_d) with
+    f = (1 + x^2 + y^2)/2 + cos(3x + 3y/2), evaluated at given points xyz
+    (..., dim) for every direction: returns (q, psi, phi) with
+      q_d   = Omega_d . grad psi_d + sigma_t psi_d - sigma_s/(4 pi) phi,
+      psi_d the solution, phi = sum_d w_d psi_d (with the quadrature given,
+    so that the discrete problem has psi as its exact solution up to the
+    discretisation error); sigma_t, sigma_s broadcast against xyz[..., 0].
+    Shapes (D,) + xyz.shape[:-1]."""
+    x, y = xyz[..., 0], xyz[..., 1]
+    f = 0.5 * (1.0 + x * x + y * y) + np.cos(3.0 * x + 1.5 * y)
+    sn = np.sin(3.0 * x + 1.5 * y)
+    fx, fy = x - 3.0 * sn, y - 1.5 * sn
+    a = omega[:, 0] ** 2 + omega[:, 1]                       # (D,)
+    aw = float(np.dot(w, a))
+    st = np.broadcast_to(np.asarray(sigma_t, dtype=np.float64), x.shape)
+    ss = np.broadcast_to(np.asarray(sigma_s, dtype=np.float64), x.shape)
+    psi = a[:, None] * f.reshape(1, -1)
+    grad = omega[:, 0:1] * fx.reshape(1, -1) + omega[:, 1:2] * fy.reshape(1, -1)
+    q = a[:, None] * grad + st.reshape(1, -1) * psi - ss.reshape(1, -1) / (4.0 * np.pi) * aw * f.reshape(1, -1)
+    shp = (len(a),) + x.shape
+    return q.reshape(shp), psi.reshape(shp), (aw * f)
+
+
+def straightened(prob: Problem, p: int = 1) -> Problem:
+    """The low-order mesh of a Q_r problem refined r times per axis: every
+    element is split into r^dim sub-elements whose vertices are its control
+    points (equispaced in the reference element, so they lie on the curved
+    element: the straightening of the paper's high-order vs low-order
+    comparison with N_ref = r), as a Q_1 problem on the same lattice with DG
+    order p; each sub-element keeps its parent's materials and source."""
+    r, dim = prob.r, prob.dim
+    nx = tuple(int(v) for v in prob.nx)
+    sub = tuple(r * v for v in nx)
+    ijk = element_ijk(dim, sub)
+    parent = np.zeros(len(ijk), dtype=np.int64)
+    stride = 1
+    for a in range(dim):
+        parent += (ijk[:, a] // r) * stride
+        stride *= nx[a]
+    return replace(prob, name=f"{prob.name}_straightened", nx=sub, r=1, p=p, lattice=prob.lattice.copy(),
+                   sigma_t=prob.sigma_t[parent].copy(), sigma_s=prob.sigma_s[parent].copy(),
+                   q=prob.q[parent].copy(), q_dir=None, psi_inc_tab=None,
+                   meta=dict(prob.meta, straightened_from=prob.name, n_ref=r))
