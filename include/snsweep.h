@@ -385,6 +385,20 @@ int snsw_net_step(snsw_net* net, const snsw_adam* opt);
 int snsw_learn_pair(snsw_problem* prob, const double* d_phi_prev, const double* d_phi_swept,
                     const double* d_phi_star, float* d_x, float* d_t);
 
+/* snsw_learn_pair for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid hipMalloc): same arguments and results, but its element-mean
+ * scratch lives in a static device array of the library instead of a
+ * per-call allocation, and it is only enqueued on the problem's stream (not
+ * synchronous; results are valid after the stream is synchronised).
+ * Limit: E <= 2^20 elements (SNSW_E_SHAPE beyond).  The array is allocated
+ * once per GPU when the library is loaded (16 MiB) and held until the
+ * process ends; the call itself allocates nothing.  Every call on a GPU
+ * shares that GPU's array, so calls on one GPU that overlap in time (on
+ * different streams) race; calls on one stream are ordered.                 */
+int snsw_learn_pair_noalloc(snsw_problem* prob, const double* d_phi_prev, const double* d_phi_swept,
+                            const double* d_phi_star, float* d_x, float* d_t);
+
 /* ------------------------------------------------------------------ batch
  * Many independent problems swept together (same context, device-backed,
  * each at most once per batch).  Problems with equal (dim, p, precision)

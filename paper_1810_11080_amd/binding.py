@@ -122,6 +122,8 @@ SIGNATURES = {
     "snsw_net_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "snsw_net_step": (C.c_int, [C.c_void_p, C.POINTER(SnswAdam)]),
     "snsw_learn_pair": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "snsw_learn_pair_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p]),
     "snsw_batch_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(SnswBatchOpts),
                                     C.POINTER(C.c_void_p)]),
     "snsw_batch_destroy": (None, [C.c_void_p]),
@@ -457,6 +459,17 @@ class Problem:
         _check(lib().snsw_learn_pair(self.handle, _tensor_ptr(phi_prev, En, dev, "phi_prev"),
                                      _tensor_ptr(phi_swept, En, dev, "phi_swept"), star,
                                      _f32_ptr(x, 3 * self.E, dev, "x"), tp))
+
+    def learn_pair_noalloc(self, phi_prev, phi_swept, phi_star, x, t):
+        """As learn_pair, through the entry point that allocates nothing
+        (static device scratch; enqueued only, not synchronous)."""
+        dev = self.ctx.device
+        En = self.E * self.n
+        star = _tensor_ptr(phi_star, En, dev, "phi_star") if phi_star is not None else C.c_void_p()
+        tp = _f32_ptr(t, self.E, dev, "t") if t is not None else C.c_void_p()
+        _check(lib().snsw_learn_pair_noalloc(self.handle, _tensor_ptr(phi_prev, En, dev, "phi_prev"),
+                                             _tensor_ptr(phi_swept, En, dev, "phi_swept"), star,
+                                             _f32_ptr(x, 3 * self.E, dev, "x"), tp))
 
     def profile_enable(self, enable: bool = True):
         _check(lib().snsw_profile_enable(self.handle, 1 if enable else 0))

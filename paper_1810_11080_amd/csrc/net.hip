@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "device.hpp"
@@ -689,6 +690,39 @@ void net_apply_correction(snsw_net* net, snsw_problem* prob, const double* phi_p
     HIP_OK(hipGetLastError());
 }
 
+// Scratch of snsw_learn_pair_noalloc: the two element-mean vectors and the
+// max-bits counter live in a file-scope device array (one copy per GPU, held
+// until the process ends) instead of per-call allocations.  Layout in
+// doubles: [0] max counter (u64 bits), [1..31] unused (keeps the vectors on
+// a 256-byte boundary), [32, 32 + E) residual means, [32 + E, 32 + 2E)
+// target means.
+constexpr int64_t kNoAllocMaxE = int64_t(1) << 20;
+constexpr int64_t kNoAllocHead = 32;
+static __device__ __align__(256) double scratch[kNoAllocHead + 2 * kNoAllocMaxE];
+
+namespace {
+
+__global__ void clear_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+// Device address of `scratch` on each device, taken once per device with
+// that device current (the array's host-side name is not a device address).
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};
+
+double* scratch_on(int device) {
+    if (device < 0 || device >= 64) throw Error(SNSW_E_INVALID_ARG, "device id out of range for the static scratch");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw Error(SNSW_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[device] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 }  // namespace snsw
 
 extern "C" {
@@ -879,6 +913,41 @@ int snsw_learn_pair(snsw_problem* prob, const double* d_phi_prev, const double* 
         }
         HIP_OK(hipFree(avg));
         HIP_OK(hipFree(mx));
+    });
+}
+
+int snsw_learn_pair_noalloc(snsw_problem* prob, const double* d_phi_prev, const double* d_phi_swept,
+                            const double* d_phi_star, float* d_x, float* d_t) {
+    return snsw_guard([&] {
+        if (!d_phi_prev || !d_phi_swept || !d_x) throw Error(SNSW_E_INVALID_ARG, "NULL argument");
+        DeviceProblem* dp = need_device(prob);
+        const HostProblem& hp = prob->hp;
+        if (hp.E > kNoAllocMaxE)
+            throw Error(SNSW_E_SHAPE, "snsw_learn_pair_noalloc: " + std::to_string(hp.E) +
+                                          " elements exceed the static scratch's maximum of " +
+                                          std::to_string(kNoAllocMaxE));
+        DeviceGuard g(dp->device);
+        hipStream_t s = dp->stream;
+        double* base = scratch_on(dp->device);
+        unsigned long long* mx = reinterpret_cast<unsigned long long*>(base);
+        double* avg = base + kNoAllocHead;
+        // the counter keeps the previous call's value: clear it with a kernel
+        // (no memset node, so a captured call replays correctly)
+        hipLaunchKernelGGL(clear_u64_kernel, dim3(1), dim3(1), 0, s, mx);
+        HIP_OK(hipGetLastError());
+        hipLaunchKernelGGL(elem_avg_kernel, dim3(grid1(hp.E)), dim3(256), 0, s, dp->geo, hp.dim, hp.n, hp.E,
+                           d_phi_swept, d_phi_prev, avg, mx);
+        HIP_OK(hipGetLastError());
+        hipLaunchKernelGGL(net_input_kernel, dim3(grid1(hp.E)), dim3(256), 0, s, avg, mx, dp->sigma_t, dp->sigma_s,
+                           hp.E, d_x);
+        HIP_OK(hipGetLastError());
+        if (d_t && d_phi_star) {
+            hipLaunchKernelGGL(elem_avg_kernel, dim3(grid1(hp.E)), dim3(256), 0, s, dp->geo, hp.dim, hp.n, hp.E,
+                               d_phi_star, d_phi_swept, avg + hp.E, nullptr);
+            HIP_OK(hipGetLastError());
+            hipLaunchKernelGGL(net_target_kernel, dim3(grid1(hp.E)), dim3(256), 0, s, avg + hp.E, mx, hp.E, d_t);
+            HIP_OK(hipGetLastError());
+        }
     });
 }
 
