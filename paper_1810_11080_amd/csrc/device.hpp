@@ -68,7 +68,7 @@ struct DeviceProblem {
     hipStream_t stream = nullptr;
     double* geo = nullptr;        // [E][dim+1][n][n] column-major matrices
     double* B = nullptr;          // [F][dim][nf][nf]
-    double* Bsym = nullptr;       // 3D: [F][dim][nf (nf + 1) / 2] packed upper triangles of B
+    double* Bsym = nullptr;       // 3D: [F][bsym_face_stride(nf)] packed upper triangles of B
     double* kink_tab = nullptr;   // [K][2][nf][nf]
     int32_t* kink_idx = nullptr;
     int4* pairs = nullptr;

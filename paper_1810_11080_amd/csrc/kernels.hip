@@ -1285,7 +1285,7 @@ __device__ __forceinline__ double inflow_rhs_coop(const SweepArgs& args, int4 pr
                 // row la of the symmetric moment matrix from its packed upper
                 // triangle (44 % fewer bytes than the full matrix)
                 constexpr int NT = NF * (NF + 1) / 2;
-                const double* Bs = args.Bsym + ((size_t)fc * DIM + a) * NT;
+                const double* Bs = args.Bsym + (size_t)fc * bsym_face_stride(NF) + a * NT;
 #pragma unroll
                 for (int b = 0; b < NF; ++b) {
                     const int i = la < b ? la : b, j = la < b ? b : la;
@@ -1366,7 +1366,7 @@ __device__ __forceinline__ double inflow_rhs_staged(const SweepArgs& args, int4 
         } else {
             if (args.Bsym) {
                 constexpr int NT = NF * (NF + 1) / 2;
-                const double* Bs = args.Bsym + ((size_t)fcs[s] * DIM + a) * NT;
+                const double* Bs = args.Bsym + (size_t)fcs[s] * bsym_face_stride(NF) + a * NT;
 #pragma unroll
                 for (int b = 0; b < NF; ++b) {
                     const int i = la < b ? la : b, j = la < b ? b : la;
@@ -1629,6 +1629,213 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs 
     }
 }
 
+// Persistent form of the 3D staged level sweep (n >= dim nf with nf <= 9:
+// p = 2): the per-pair structure of sweep_level_inv (upwind traces staged in
+// LDS, face moments contracted cooperatively, the row of A^{-1} in 16-byte
+// column pairs) with the level barriers replaced by per-value waits.  A
+// wavefront claims kChunk consecutive batches of G pairs at a time from its
+// stream's ticket and processes them in order; the lanes that stage a kept
+// upwind trace poll that value until it no longer holds this sweep's
+// sentinel (each flux value is its own ready flag: it is stored once, with a
+// device-scope store, after the pair is solved).  Deadlock freedom is the
+// argument of sweep_persistent_fp64 with chunks in place of batches: the
+// smallest unfinished batch depends only on smaller ones, and its chunk is
+// either held by a wavefront that has finished the chunk's smaller batches
+// or not yet handed out, in which case its stream's earlier chunks are all
+// finished and the stream's wavefronts go on to claim it.
+constexpr unsigned kChunk = 4;
+#ifndef SNSW_STAGED_MIN_WAVES
+#define SNSW_STAGED_MIN_WAVES 5   // wavefronts per SIMD the register allocation must allow
+#endif
+
+template <int DIM, int P>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(SNSW_STAGED_MIN_WAVES, 8)))
+sweep_persistent_staged(PersistArgs pa) {
+    using S = Shape<DIM, P>;
+    constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
+    static_assert(DIM == 3 && DIM * NF <= N && NF <= 9, "staged 3D shapes");
+    using IL = InvLayout<DIM, P>;
+    static_assert(IL::kPaired, "paired A^{-1} columns");
+    __shared__ double lds[kWaves][G][N + 1];
+    __shared__ double cfl[kWaves][G][NS][DIM * NF];
+    __shared__ double ufl[kWaves][G][NS][NF];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned long long sent = kSentinel;
+    const int64_t nbatch = pa.total / G;
+
+    unsigned chunk = 0;
+    if (lane == 0) chunk = take_batch(pa.ticket);
+    chunk = __builtin_amdgcn_readfirstlane(__shfl(chunk, 0));
+    while ((int64_t)chunk * kChunk < nbatch) {
+        unsigned next = 0;
+        if (lane == 0) next = take_batch(pa.ticket);
+        for (unsigned j = 0; j < kChunk; ++j) {
+            const int64_t bt = (int64_t)chunk * kChunk + j;
+            if (bt >= nbatch) break;
+            const int64_t t0 = bt * G;
+            // lane-derived indices are recomputed in every batch instead of
+            // being kept live across the loop (registers for wavefronts)
+            int lane_b = lane;
+            __asm__ volatile("" : "+v"(lane_b));
+            const int grp = lane_b / N, row = lane_b - grp * N;
+            const bool in_group = grp < G;
+            const int g = in_group ? grp : 0;
+            double* L = &lds[wave][g][0];
+            const SweepArgs args = load_args(pa.table, batch_problem(pa.pairs, t0, pa.problem));
+            int4 pr = make_int4(-1, 0, 0, 0);
+            if (in_group) pr = pa.pairs[t0 + grp];
+            const bool active = pr.x >= 0;   // padding entries have e = -1
+            const int4 prs = active ? pr : make_int4(0, 0, 0, 0);
+            const int e = prs.x;
+            const unsigned packed = (unsigned)prs.y;
+            const int d = (int)(packed & kDirMask);
+            const int a = row / NF, la = row - a * NF;
+            const bool worker = in_group && a < DIM && active;
+            const double oa = args.omega[3 * d + (a < DIM ? a : 0)];
+
+            // 1. traces: lane (0, la) of each inflow slot loads the upwind
+            // value on face node la (kept couplings from this sweep's flux,
+            // polled until written; lagged ones from the previous sweep;
+            // boundary faces the incident flux)
+            int fcs[NS], krs[NS];
+            double tv[NS];
+            bool wait[NS];
+            int kc = 0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+                const bool lagged = (packed >> (kSlotShift + 3 * s + 2)) & 1u;
+                krs[s] = 0;
+                fcs[s] = 0;
+                tv[s] = 0.0;
+                wait[s] = false;
+                if (cls == kKink) krs[s] = args.kink_idx[prs.z + kc++];
+                if (cls == kOut || cls == kNone || !worker) continue;
+                if (cls != kKink) fcs[s] = args.slot_face[(size_t)e * NS + s];
+                if (a == 0) {
+                    const int nb = args.slot_nbr[(size_t)e * NS + s];
+                    if (nb < 0) {
+                        tv[s] = args.psi_inc;
+                    } else if (lagged) {
+                        tv[s] = args.psi_prev[((size_t)d * args.E + nb) * N + S::tn(s ^ 1, la)];
+                    } else {
+                        tv[s] = __hip_atomic_load(args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, la),
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        wait[s] = true;
+                    }
+                }
+            }
+            int polls = 0;
+            while (true) {
+                bool pending = false;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (!wait[s]) continue;
+                    if ((unsigned long long)__double_as_longlong(tv[s]) == sent) pending = true;
+                    else wait[s] = false;
+                }
+                if (!__any(pending)) break;
+                if (++polls > pa.spin_limit) {
+                    if (pending) atomicExch(pa.error, 1);   // a failed wait: reported, the kernel drains
+                    break;
+                }
+                if ((polls & 255) == 0) {
+                    int err = 0;
+                    if (lane == 0) err = __hip_atomic_load(pa.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (__shfl(err, 0)) break;
+                }
+                __builtin_amdgcn_s_sleep(SNSW_POLL_SLEEP);
+                const int nbr_base = e * NS;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (!wait[s]) continue;
+                    const int nb = args.slot_nbr[(size_t)nbr_base + s];
+                    tv[s] = __hip_atomic_load(args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, la),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (worker && a == 0) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) ufl[wave][g][s][la] = tv[s];
+            }
+            wave_sync();
+
+            // 2. inflow contraction: lane (a, la), component a of row la of
+            // each inflow face's moments, partial sums through LDS
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+                if (cls == kOut || cls == kNone || !worker) continue;
+                double t = 0.0;
+                if (cls == kKink) {
+                    if (a == 0) {
+                        const double* Ti =
+                            args.kink_tab + (size_t)krs[s] * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + la * NF;
+#pragma unroll
+                        for (int b = 0; b < NF; ++b) t += Ti[b] * ufl[wave][g][s][b];
+                    }
+                } else {
+                    constexpr int NT = NF * (NF + 1) / 2;
+                    const double* Bs = args.Bsym + (size_t)fcs[s] * bsym_face_stride(NF) + a * NT;
+#pragma unroll
+                    for (int b = 0; b < NF; ++b) {
+                        const int i = la < b ? la : b, jj = la < b ? b : la;
+                        t += Bs[i * NF - (i * (i - 1)) / 2 + (jj - i)] * ufl[wave][g][s][b];
+                    }
+                    t *= (s & 1) ? -oa : oa;   // P_in = -(outward normal) moments
+                }
+                cfl[wave][g][s][row] = t;
+            }
+            wave_sync();
+            double rhs = (in_group && active) ? source_row(args, e, d, row, N) : 0.0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+                if (cls == kOut || cls == kNone || !active) continue;
+                if (S::coord(row, s / 2) != ((s & 1) ? P : 0)) continue;
+                const int l = S::local(row, s);
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) rhs += cfl[wave][g][s][c * NF + l];
+            }
+
+            // 3. x = A^{-1} b: b through LDS, the row of A^{-1} streamed in
+            // 16-byte column pairs while b is read back a few entries at a time
+            if (in_group) L[row] = rhs;
+            wave_sync();
+            __builtin_amdgcn_sched_barrier(0);
+            const double* Ab = args.ainv + ((size_t)d * args.E + e) * IL::kStride;
+            double m[N];
+#pragma unroll
+            for (int jj = 0; jj < N; ++jj) {
+                if (jj + 1 < (N & ~1) && !(jj & 1)) {
+                    const dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(Ab + IL::at(row, jj)));
+                    m[jj] = v.x;
+                    m[jj + 1] = v.y;
+                } else if (jj >= (N & ~1)) {
+                    m[jj] = __builtin_nontemporal_load(Ab + IL::at(row, jj));
+                }
+            }
+            constexpr int LG = SNSW_LEVEL_LDS_GROUP;
+            double x = 0.0;
+#pragma unroll
+            for (int g0 = 0; g0 < N; g0 += LG) {
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int jj = g0; jj < g0 + LG && jj < N; ++jj) x += m[jj] * L[jj];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            __asm__ volatile("" : "+v"(x));
+            wave_sync();   // L, cfl and ufl are reused by the next batch
+            if (in_group && active)
+                __hip_atomic_store(args.psi_cur + ((size_t)d * args.E + e) * N + row, x, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        chunk = __builtin_amdgcn_readfirstlane(__shfl(next, 0));
+    }
+}
+
 __global__ void fill_sentinel_kernel(const SweepArgs* table) {
     const SweepArgs& a = table[blockIdx.y];
     if (!a.persistent) return;
@@ -1661,6 +1868,12 @@ constexpr bool use_dpp() {
     return Shape<DIM, P>::N == 16 || Shape<DIM, P>::N == 4;
 }
 
+// 3D shapes with the staged persistent kernel (cached inverses)
+template <int DIM, int P>
+constexpr bool use_staged() {
+    return DIM == 3 && P == 2;
+}
+
 template <int DIM, int P>
 void launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, hipStream_t stream) {
     if constexpr (use_dpp<DIM, P>()) {
@@ -1676,6 +1889,13 @@ void launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, hipStream_t 
     } else if constexpr (DIM == 2) {
         if (inv)
             hipLaunchKernelGGL((sweep_persistent_lds2d<P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, a);
+        else
+            hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                               stream, a);
+    } else if constexpr (use_staged<DIM, P>()) {
+        if (inv)
+            hipLaunchKernelGGL((sweep_persistent_staged<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                               stream, a);
         else
             hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
                                stream, a);
@@ -1707,6 +1927,9 @@ int occupancy_tpl(bool inv) {
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, false>, 64 * kWaves, 0);
     else if constexpr (DIM == 2)
         rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_lds2d<P>, 64 * kWaves, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P>, 64 * kWaves, 0);
+    else if constexpr (use_staged<DIM, P>())
+        rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_staged<DIM, P>, 64 * kWaves, 0)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P>, 64 * kWaves, 0);
     else
         rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_inv<DIM, P>, 64 * kWaves, 0)

@@ -31,11 +31,17 @@ struct SweepArgs {
     int32_t n, D, dim;
     int32_t persistent;       // swept by a persistent kernel (needs the sentinel fill)
     const double* ainv;       // [D][E] blocks of cached A^{-1} (kernels.hip InvLayout; null: not cached)
-    const double* Bsym;       // 3D: [F][dim][nf (nf + 1) / 2] the face moments (symmetric in the two
-                              // face nodes), upper triangle row by row (null in 2D)
+    const double* Bsym;       // 3D: [F][bsym_face_stride(nf)]: per face the dim moment matrices
+                              // (symmetric in the two face nodes), each as its upper triangle row by
+                              // row, nf (nf + 1) / 2 entries (null in 2D)
     const double* rhs_dir;    // [D][E][n] fixed right-hand side per pair: M q_d (direction-dependent
                               // source) + tabulated boundary inflow; null when the problem has neither
 };
+
+// Doubles per face in the packed face-moment array Bsym: dim packed upper
+// triangles of nf (nf + 1) / 2 entries, padded to an even count so that every
+// face starts on a 16-byte boundary.
+__host__ __device__ constexpr int bsym_face_stride(int nf) { return (3 * nf * (nf + 1) / 2 + 1) & ~1; }
 
 // Persistent sweeps take batches from kStreams counters per schedule, each
 // kTicketStride words apart (separate cache lines).

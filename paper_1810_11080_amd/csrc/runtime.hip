@@ -257,14 +257,16 @@ void device_upload(snsw_problem* prob) {
     if (hp.dim == 3) {
         // B_a[i][j] = int N_a phi_i phi_j is symmetric in the two face nodes:
         // the level sweeps read its packed upper triangle
-        const int nf = hp.nf, nt = nf * (nf + 1) / 2;
-        std::vector<double> bs((size_t)hp.F * 3 * nt);
-        for (int64_t fa = 0; fa < hp.F * 3; ++fa) {
-            const double* Bm = &hp.B[(size_t)fa * nf * nf];
-            for (int i = 0; i < nf; ++i)
-                for (int j = i; j < nf; ++j)
-                    bs[(size_t)fa * nt + i * nf - (i * (i - 1)) / 2 + (j - i)] = 0.5 * (Bm[i * nf + j] + Bm[j * nf + i]);
-        }
+        const int nf = hp.nf, nt = nf * (nf + 1) / 2, fs = bsym_face_stride(nf);
+        std::vector<double> bs((size_t)hp.F * fs, 0.0);
+        for (int64_t f = 0; f < hp.F; ++f)
+            for (int a = 0; a < 3; ++a) {
+                const double* Bm = &hp.B[((size_t)f * 3 + a) * nf * nf];
+                double* dst = &bs[(size_t)f * fs + a * nt];
+                for (int i = 0; i < nf; ++i)
+                    for (int j = i; j < nf; ++j)
+                        dst[i * nf - (i * (i - 1)) / 2 + (j - i)] = 0.5 * (Bm[i * nf + j] + Bm[j * nf + i]);
+            }
         dp->Bsym = dupload(dp, bs, s);
         HIP_OK(hipStreamSynchronize(s));
     }
