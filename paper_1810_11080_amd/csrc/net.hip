@@ -2,7 +2,10 @@
 // grid (BF16 convolution weights, FP32 activations and accumulation, FP32
 // master weights with Adam), its training kernels, and the kernels that turn
 // a sweep's scalar-flux residual into network input and apply the network's
-// correction (FP64).
+// correction (FP64).  The convolutions (forward, data gradient, weight
+// gradient) run on the matrix cores as implicit GEMMs in BF16 MFMA tiles
+// with FP32 accumulation; FP32 activations and gradients enter them as pairs
+// of BF16 terms.
 //
 // Network (widths c0, c1, c2; 3x3x3 convolutions, zero padding 1, bias,
 // leaky ReLU slope 0.1 except on the output layer):
@@ -29,8 +32,6 @@ namespace {
 
 constexpr float kSlope = 0.1f;
 
-__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
 // float -> bfloat16, round to nearest even; NaN stays a quiet NaN
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     const uint32_t u = __float_as_uint(f);
@@ -41,186 +42,6 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 
 __host__ __device__ inline int out_size(int n, int s) { return (n - 1) / s + 1; }
 
-// y[b][o][v] = act(bias[o] + sum_{i,k} w[o][i][k] x[b][i][s v + k - 1]);
-// block: blockDim.x output voxels x CO_T output channels, weights of the channel
-// tile staged in LDS as FP32.
-template <int CO_T>
-__global__ void __launch_bounds__(256) conv_fwd_kernel(const float* __restrict__ x, const uint16_t* __restrict__ w,
-                                                      const float* __restrict__ bias, float* __restrict__ y, int Ci,
-                                                      int Co, int Z, int Y, int X, int Zo, int Yo, int Xo, int s,
-                                                      int act) {
-    extern __shared__ float wl[];   // [CO_T][Ci*27]
-    const int o0 = blockIdx.y * CO_T;
-    const int b = blockIdx.z;
-    const int K = Ci * 27;
-    for (int t = threadIdx.x; t < CO_T * K; t += blockDim.x) {
-        const int oo = t / K, r = t - oo * K;
-        wl[t] = (o0 + oo < Co) ? bf16_to_f32(w[(size_t)(o0 + oo) * K + r]) : 0.0f;
-    }
-    __syncthreads();
-    const int nvo = Zo * Yo * Xo;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nvo) return;
-    const int xo = v % Xo, yo = (v / Xo) % Yo, zo = v / (Xo * Yo);
-    float acc[CO_T];
-#pragma unroll
-    for (int t = 0; t < CO_T; ++t) acc[t] = (o0 + t < Co) ? bias[o0 + t] : 0.0f;
-    const size_t plane = (size_t)Z * Y * X;
-    for (int i = 0; i < Ci; ++i) {
-        const float* xi = x + ((size_t)b * Ci + i) * plane;
-        for (int kz = 0; kz < 3; ++kz) {
-            const int z = s * zo + kz - 1;
-            if (z < 0 || z >= Z) continue;
-            for (int ky = 0; ky < 3; ++ky) {
-                const int yy = s * yo + ky - 1;
-                if (yy < 0 || yy >= Y) continue;
-#pragma unroll
-                for (int kx = 0; kx < 3; ++kx) {
-                    const int xx = s * xo + kx - 1;
-                    if (xx < 0 || xx >= X) continue;
-                    const float xv = xi[((size_t)z * Y + yy) * X + xx];
-                    const int k = i * 27 + kz * 9 + ky * 3 + kx;
-#pragma unroll
-                    for (int t = 0; t < CO_T; ++t) acc[t] += wl[t * K + k] * xv;
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < CO_T; ++t) {
-        if (o0 + t >= Co) break;
-        float r = acc[t];
-        if (act && r <= 0.0f) r *= kSlope;
-        y[((size_t)b * Co + o0 + t) * nvo + v] = r;
-    }
-}
-
-// g_in[b][i][u] (+)= sum_{o,k} w[o][i][k] g_out[b][o][(u + 1 - k)/s]
-// over the k for which (u + 1 - k) is a non-negative multiple of s in range.
-template <int CI_T>
-__global__ void __launch_bounds__(256) conv_bwd_data_kernel(const float* __restrict__ gout,
-                                                           const uint16_t* __restrict__ w, float* __restrict__ gin,
-                                                           int Ci, int Co, int Z, int Y, int X, int Zo, int Yo,
-                                                           int Xo, int s, int accumulate) {
-    extern __shared__ float wl[];   // [CI_T][Co*27]
-    const int i0 = blockIdx.y * CI_T;
-    const int b = blockIdx.z;
-    const int K = Co * 27;
-    for (int t = threadIdx.x; t < CI_T * K; t += blockDim.x) {
-        const int ii = t / K, r = t - ii * K;
-        const int o = r / 27, k = r - o * 27;
-        wl[t] = (i0 + ii < Ci) ? bf16_to_f32(w[((size_t)o * Ci + i0 + ii) * 27 + k]) : 0.0f;
-    }
-    __syncthreads();
-    const int nv = Z * Y * X;
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= nv) return;
-    const int xx = u % X, yy = (u / X) % Y, zz = u / (X * Y);
-    float acc[CI_T];
-#pragma unroll
-    for (int t = 0; t < CI_T; ++t) acc[t] = 0.0f;
-    const size_t plane = (size_t)Zo * Yo * Xo;
-    for (int o = 0; o < Co; ++o) {
-        const float* go = gout + ((size_t)b * Co + o) * plane;
-        for (int kz = 0; kz < 3; ++kz) {
-            const int nz = zz + 1 - kz;
-            if (nz < 0 || nz % s) continue;
-            const int zo = nz / s;
-            if (zo >= Zo) continue;
-            for (int ky = 0; ky < 3; ++ky) {
-                const int ny = yy + 1 - ky;
-                if (ny < 0 || ny % s) continue;
-                const int yo = ny / s;
-                if (yo >= Yo) continue;
-                for (int kx = 0; kx < 3; ++kx) {
-                    const int nx = xx + 1 - kx;
-                    if (nx < 0 || nx % s) continue;
-                    const int xo = nx / s;
-                    if (xo >= Xo) continue;
-                    const float g = go[((size_t)zo * Yo + yo) * Xo + xo];
-                    const int k = o * 27 + kz * 9 + ky * 3 + kx;
-#pragma unroll
-                    for (int t = 0; t < CI_T; ++t) acc[t] += wl[t * K + k] * g;
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < CI_T; ++t) {
-        if (i0 + t >= Ci) break;
-        float* dst = gin + ((size_t)b * Ci + i0 + t) * nv + u;
-        *dst = accumulate ? *dst + acc[t] : acc[t];
-    }
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-// dw[o][i][k] = sum_{b,v} g_out[b][o][v] x[b][i][s v + k - 1]; one block per
-// (o, i); the 27 partial sums of each thread are reduced across the block.
-__global__ void __launch_bounds__(256) conv_bwd_weight_kernel(const float* __restrict__ x,
-                                                             const float* __restrict__ gout, float* __restrict__ dw,
-                                                             int B, int Ci, int Co, int Z, int Y, int X, int Zo,
-                                                             int Yo, int Xo, int s) {
-    __shared__ float red[4][27];
-    const int o = blockIdx.x / Ci, i = blockIdx.x - (blockIdx.x / Ci) * Ci;
-    const int nvo = Zo * Yo * Xo;
-    const size_t plane = (size_t)Z * Y * X;
-    float acc[27];
-#pragma unroll
-    for (int k = 0; k < 27; ++k) acc[k] = 0.0f;
-    for (int64_t t = threadIdx.x; t < (int64_t)B * nvo; t += blockDim.x) {
-        const int b = (int)(t / nvo), v = (int)(t - (int64_t)b * nvo);
-        const float g = gout[((size_t)b * Co + o) * nvo + v];
-        const int xo = v % Xo, yo = (v / Xo) % Yo, zo = v / (Xo * Yo);
-        const float* xi = x + ((size_t)b * Ci + i) * plane;
-#pragma unroll
-        for (int kz = 0; kz < 3; ++kz) {
-            const int z = s * zo + kz - 1;
-#pragma unroll
-            for (int ky = 0; ky < 3; ++ky) {
-                const int yy = s * yo + ky - 1;
-#pragma unroll
-                for (int kx = 0; kx < 3; ++kx) {
-                    const int xx = s * xo + kx - 1;
-                    const bool in = z >= 0 && z < Z && yy >= 0 && yy < Y && xx >= 0 && xx < X;
-                    const float xv = in ? xi[((size_t)z * Y + yy) * X + xx] : 0.0f;
-                    acc[kz * 9 + ky * 3 + kx] += g * xv;
-                }
-            }
-        }
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < 27; ++k) {
-        const float r = wave_sum(acc[k]);
-        if (lane == 0) red[wave][k] = r;
-    }
-    __syncthreads();
-    if (threadIdx.x < 27) {
-        const float r = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-        dw[((size_t)o * Ci + i) * 27 + threadIdx.x] = r;
-    }
-}
-
-// db[o] = sum_{b,v} g_out[b][o][v]; one block per o
-__global__ void __launch_bounds__(256) bias_grad_kernel(const float* __restrict__ gout, float* __restrict__ db, int B,
-                                                       int Co, int nvo) {
-    __shared__ float red[4];
-    const int o = blockIdx.x;
-    float acc = 0.0f;
-    for (int64_t t = threadIdx.x; t < (int64_t)B * nvo; t += blockDim.x) {
-        const int b = (int)(t / nvo), v = (int)(t - (int64_t)b * nvo);
-        acc += gout[((size_t)b * Co + o) * nvo + v];
-    }
-    const float r = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
-    __syncthreads();
-    if (threadIdx.x == 0) db[o] = red[0] + red[1] + red[2] + red[3];
-}
 
 // g *= act'(y) for the leaky ReLU (y has the sign of its input)
 __global__ void act_backward_kernel(const float* __restrict__ y, float* __restrict__ g, int64_t n) {
@@ -259,13 +80,18 @@ __global__ void upsample_back_kernel(const float* __restrict__ gh, float* __rest
     glow[t] = acc;
 }
 
-// loss = mean((y - t)^2) (FP64 accumulation, one block), dy = 2 (y - t) / n
-__global__ void __launch_bounds__(1024) mse_kernel(const float* __restrict__ y, const float* __restrict__ tgt,
-                                                  int64_t n, float* __restrict__ dy, double* __restrict__ loss) {
-    __shared__ double red[16];
+// Mean squared error in two deterministic passes: each block writes the sum
+// of (y - t)^2 over its grid-strided share (FP64) and dy = 2 (y - t) / n;
+// then one block adds the partial sums in block order: loss = sum / n.
+constexpr int kMseBlocks = 256;
+
+__global__ void __launch_bounds__(256) mse_partial_kernel(const float* __restrict__ y, const float* __restrict__ tgt,
+                                                         int64_t n, float* __restrict__ dy,
+                                                         double* __restrict__ partial) {
+    __shared__ double red[4];
     double acc = 0.0;
     const float scale = 2.0f / (float)n;
-    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
         const float d = y[t] - tgt[t];
         acc += (double)d * (double)d;
         dy[t] = scale * d;
@@ -273,11 +99,14 @@ __global__ void __launch_bounds__(1024) mse_kernel(const float* __restrict__ y, 
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
-        *loss = s / (double)n;
-    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void mse_final_kernel(const double* __restrict__ partial, int count, int64_t n, double* __restrict__ loss) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < count; ++k) s += partial[k];
+    *loss = s / (double)n;
 }
 
 // Adam (bias-corrected) on the FP32 masters; refreshes the BF16 copy
@@ -362,6 +191,309 @@ __global__ void apply_correction_kernel(double* __restrict__ phi, const float* _
     phi[t] += s * (double)y[t / n];
 }
 
+// ---- convolutions on the matrix cores (BF16 MFMA, FP32 accumulation) ----
+//
+// A 3x3x3 convolution is an implicit GEMM: out[o][v] = sum_kk W[o][kk] X[kk][v]
+// with kk = tap * C8 + c (tap = 9 kz + 3 ky + kx, c the input channel, C8 the
+// channel count rounded up to 8 so that the eight K values a lane holds are
+// eight channels of one tap).  v_mfma_f32_16x16x32_bf16 takes a 16 x 32 tile
+// of W (lane l: row l mod 16, K values 8 (l / 16) .. + 7) and a 32 x 16 tile
+// of X (lane l: column = voxel l mod 16, the same K values) and accumulates a
+// 16 x 16 FP32 tile (lane l: rows 4 (l / 16) .. + 3, column l mod 16).  The
+// weights are exact BF16 (the network's weights); an FP32 activation x is
+// split into two BF16 terms, x = hi + lo up to 2^-16 relative, and both are
+// multiplied, so the products keep the FP32 activations' precision.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (hardware conversions)
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+// Packed BF16 weights of one layer for the implicit GEMM: rows (output
+// channels of the GEMM, padded to 16) of KP = 32 * ceil(27 * C8 / 32) values,
+// kk = tap * C8 + c, zeros in the padding.  transposed = 0: the forward
+// convolution, row o, c = input channel, W[o][c][tap].  transposed = 1: the
+// data gradient, row i (input channel), c = output channel o, the tap
+// mirrored: W[o][i][26 - tap].
+__global__ void pack_weights_kernel(const float* __restrict__ theta, uint16_t* __restrict__ dst, int Cout, int Cin,
+                                    int rows, int KP, int C8, int transposed) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * KP) return;
+    const int r = (int)(t / KP), kk = (int)(t - (int64_t)r * KP);
+    const int tap = kk / C8, c = kk - tap * C8;
+    float w = 0.0f;
+    if (tap < 27) {
+        if (!transposed) {
+            if (r < Cout && c < Cin) w = theta[((size_t)r * Cin + c) * 27 + tap];
+        } else {
+            if (r < Cin && c < Cout) w = theta[((size_t)c * Cin + r) * 27 + (26 - tap)];
+        }
+    }
+    dst[t] = f32_to_bf16(w);
+}
+
+// out[b][o][v] (+)= act(bias[o] + sum_kk W[o][kk] X[kk][v]), one wavefront per
+// 16 output voxels, MT tiles of 16 output channels.  Gather of X for output
+// voxel (zo, yo, xo) and tap (kz, ky, kx):
+//   DILATE = false: input (s zo + kz - 1, ...) (convolution with stride s;
+//                   also the data gradient of a stride-1 convolution);
+//   DILATE = true:  p = zo + kz - 1 must be even, input p / 2 (the data
+//                   gradient of a stride-2 convolution: a stride-1
+//                   convolution of the zero-dilated output gradient).
+// Out-of-range positions are the zero padding.
+template <int MT, bool DILATE>
+__global__ void __launch_bounds__(256) conv_mfma_kernel(const float* __restrict__ x, const uint16_t* __restrict__ wpk,
+                                                       const float* __restrict__ bias, float* __restrict__ y, int C,
+                                                       int C8, int Co, int KP, int Zi, int Yi, int Xi, int Zo, int Yo,
+                                                       int Xo, int s, int act, int accumulate) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int b = blockIdx.y;
+    const int nvo = Zo * Yo * Xo;
+    const int v0 = (blockIdx.x * 4 + wave) * 16;
+    if (v0 >= nvo) return;   // no block-level synchronisation follows
+    const int col = lane & 15, kg = lane >> 4;
+    const int v = v0 + col;
+    const bool vok = v < nvo;
+    const int vv = vok ? v : v0;
+    const int xo = vv % Xo, yo = (vv / Xo) % Yo, zo = vv / (Xo * Yo);
+    const size_t plane = (size_t)Zi * Yi * Xi;
+    const float* xb = x + (size_t)b * C * plane;
+    f32x4 acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int nsteps = KP / 32;
+    // this lane's K values of step st start at kk = 32 st + 8 kg = tap C8 + c0;
+    // (tap, c0) and the tap's (kz, ky, kx) are advanced step by step
+    int tap = (8 * kg) / C8, c0 = 8 * kg - tap * C8;
+    int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
+    for (int st = 0; st < nsteps; ++st) {
+        if (st > 0) {
+            c0 += 32;
+            while (c0 >= C8) {
+                c0 -= C8;
+                ++tap;
+                if (++kx == 3) {
+                    kx = 0;
+                    if (++ky == 3) {
+                        ky = 0;
+                        ++kz;
+                    }
+                }
+            }
+        }
+        const int kk0 = st * 32 + 8 * kg;
+        int zi, yi, xi;
+        bool ok = vok && tap < 27;
+        if (!DILATE) {
+            zi = s * zo + kz - 1;
+            yi = s * yo + ky - 1;
+            xi = s * xo + kx - 1;
+        } else {
+            const int pz = zo + kz - 1, py = yo + ky - 1, px = xo + kx - 1;
+            ok = ok && pz >= 0 && py >= 0 && px >= 0 && !((pz | py | px) & 1);
+            zi = pz >> 1;
+            yi = py >> 1;
+            xi = px >> 1;
+        }
+        ok = ok && zi >= 0 && zi < Zi && yi >= 0 && yi < Yi && xi >= 0 && xi < Xi;
+        const float* xp = xb + (ok ? (size_t)c0 * plane + ((size_t)zi * Yi + yi) * Xi + xi : 0);
+        bf16x8 bh, bl;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int c = c0 + j;
+            const float val = (ok && c < C) ? xp[(size_t)j * plane] : 0.0f;
+            __bf16 h, l;
+            split_bf16(val, h, l);
+            bh[j] = h;
+            bl[j] = l;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(wpk + (size_t)(mt * 16 + col) * KP + kk0);
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc[mt], 0, 0, 0);
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[mt], 0, 0, 0);
+        }
+    }
+    if (!vok) return;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = mt * 16 + 4 * kg + r;
+            if (o >= Co) continue;
+            float val = acc[mt][r] + (bias ? bias[o] : 0.0f);
+            if (act && val <= 0.0f) val *= kSlope;
+            float* dst = y + ((size_t)b * Co + o) * nvo + v;
+            *dst = accumulate ? *dst + val : val;
+        }
+}
+
+// dst[b][v][c] = src[b][c][v] for c < C, 0 for C <= c < Cp (channels last,
+// padded): tiles of 64 voxels through LDS so that both sides are coalesced.
+__global__ void __launch_bounds__(256) to_channels_last_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                              int C, int Cp, int nv) {
+    __shared__ float tile[64][65];
+    const int b = blockIdx.y;
+    const int v0 = blockIdx.x * 64;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < Cp * 64; k += 256) {
+        const int c = k / 64, vl = k - c * 64;
+        tile[vl][c] = (c < C && v0 + vl < nv) ? src[((size_t)b * C + c) * nv + v0 + vl] : 0.0f;
+    }
+    __syncthreads();
+    for (int k = tid; k < Cp * 64; k += 256) {
+        const int vl = k / Cp, c = k - vl * Cp;
+        if (v0 + vl < nv) dst[((size_t)b * nv + v0 + vl) * Cp + c] = tile[vl][c];
+    }
+}
+
+// Weight and bias gradient as an implicit GEMM over the voxels of the batch:
+// part[kc][o][n] = sum over chunk kc of the voxels t = (b, v) of
+// gout[t][o] X[n][t] with n = tap * C16 + c (C16 = input channels rounded to
+// 16), X[n][t] = x[b][s v + k - 1][c] (zero padding), and the bias column
+// n = 27 C16 with X = 1.  Both operands are read channels last (x as
+// [b][voxel][C16], gout as [t][MP]), so the 16 channels of a tile are 64
+// contiguous bytes.  A wavefront owns 16 output channels (one tile), 16
+// input channels, the nine taps of one kz and a chunk of voxels: per K step
+// of 32 voxels it loads and splits its gout tile once and uses it for the
+// nine taps (voxel coordinates and bounds are worked out once per step; each
+// tap adds a constant offset).  Within a K step, element j of lane group kg
+// is voxel 4 j + kg (the same order for both operands).  Both operands are
+// split into BF16 pairs and the three leading products accumulated
+// (g x = gh xh + gh xl + gl xh up to 2^-16 relative).  wgrad_reduce_kernel
+// adds the chunks in fixed order.
+__global__ void __launch_bounds__(256) wgrad_mfma_kernel(const float* __restrict__ xcl, const float* __restrict__ gcl,
+                                                        float* __restrict__ part, int64_t K, int chunk, int nchunks,
+                                                        int C16, int NP, int MP, int Zi, int Yi, int Xi, int Zo, int Yo,
+                                                        int Xo, int s) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kc = blockIdx.x * 4 + wave;
+    if (kc >= nchunks) return;   // no block-level synchronisation follows
+    const int cg = blockIdx.y / 3, kz = blockIdx.y - cg * 3;
+    const int mt = blockIdx.z;
+    const int col = lane & 15, kg = lane >> 4;
+    const int o = mt * 16 + col;                 // row of the gout operand
+    const int c = cg * 16 + col;                 // input channel of this lane's X column
+    const bool bias = cg == 0 && kz == 0;        // this wavefront also forms the bias column
+    const int nvo = Zo * Yo * Xo;
+    const int64_t nvi = (int64_t)Zi * Yi * Xi;
+    const int64_t t_begin = (int64_t)kc * chunk;
+    const int64_t t_end = t_begin + chunk < K ? t_begin + chunk : K;
+    f32x4 acc[9], accb = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 ones;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ones[j] = (__bf16)(col == 0 ? 1.0f : 0.0f);
+    for (int64_t t0 = t_begin; t0 < t_end; t0 += 32) {
+        const int64_t t = t0 + kg;
+        int b = (int)(t / nvo);
+        int v = (int)(t - (int64_t)b * nvo);
+        int xo = v % Xo, yo = (v / Xo) % Yo, zo = v / (Xo * Yo);
+        bf16x8 gh, gl;
+        int64_t base[8];        // index of (zi, yi, xi) = (s zo + kz - 1, s yo - 1, s xo - 1), channel c
+        unsigned okm[8];        // bit ky: row s yo + ky - 1 in range; bit 3 + kx: column in range
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool tin = t + 4 * j < t_end;
+            const float g = tin ? gcl[(t + 4 * j) * MP + o] : 0.0f;
+            __bf16 h, l;
+            split_bf16(g, h, l);
+            gh[j] = h;
+            gl[j] = l;
+            const int zi = s * zo + kz - 1, yi0 = s * yo - 1, xi0 = s * xo - 1;
+            unsigned m = 0;
+            if (tin && zi >= 0 && zi < Zi) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    if (yi0 + k >= 0 && yi0 + k < Yi) m |= 1u << k;
+                    if (xi0 + k >= 0 && xi0 + k < Xi) m |= 8u << k;
+                }
+            }
+            okm[j] = m;
+            base[j] = ((int64_t)b * nvi + ((int64_t)zi * Yi + yi0) * Xi + xi0) * C16 + c;
+            // four voxels on (the order of the batch: b, then z, y, x)
+            xo += 4;
+            while (xo >= Xo) {
+                xo -= Xo;
+                if (++yo == Yo) {
+                    yo = 0;
+                    if (++zo == Zo) zo = 0;
+                }
+            }
+            v += 4;
+            while (v >= nvo) {
+                v -= nvo;
+                ++b;
+            }
+        }
+        if (bias) {
+            accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, ones, accb, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl, ones, accb, 0, 0, 0);
+        }
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                bf16x8 xh, xl;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bool in = ((okm[j] >> ky) & 1u) && ((okm[j] >> (3 + kx)) & 1u);
+                    const float xv = in ? xcl[base[j] + ((int64_t)ky * Xi + kx) * C16] : 0.0f;
+                    __bf16 h, l;
+                    split_bf16(xv, h, l);
+                    xh[j] = h;
+                    xl[j] = l;
+                }
+                f32x4& a = acc[ky * 3 + kx];
+                a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, xh, a, 0, 0, 0);
+                a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, xl, a, 0, 0, 0);
+                a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl, xh, a, 0, 0, 0);
+            }
+    }
+    // C tile: rows 4 kg + r (output channels), column col (input channel)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int tap = kz * 9 + k;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            part[((size_t)kc * MP + mt * 16 + 4 * kg + r) * NP + tap * C16 + cg * 16 + col] = acc[k][r];
+    }
+    if (bias)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[((size_t)kc * MP + mt * 16 + 4 * kg + r) * NP + 27 * C16 + col] = accb[r];
+}
+
+// Sums the chunks of the weight-gradient partials: a block takes 64
+// consecutive columns n of one row o; its four wavefronts add every fourth
+// chunk (ascending), then the four sums are added in wavefront order (a fixed
+// order: deterministic).  Column n = tap * C16 + c goes to dw[o][c][tap],
+// column 27 C16 to db[o].
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ part, float* __restrict__ dw,
+                                                          float* __restrict__ db, int nchunks, int C, int C16, int Co,
+                                                          int NP, int MP) {
+    __shared__ float red[4][64];
+    const int o = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + lane;
+    float sum = 0.0f;
+    if (n < NP)
+        for (int kc = w; kc < nchunks; kc += 4) sum += part[((size_t)kc * MP + o) * NP + n];
+    red[w][lane] = sum;
+    __syncthreads();
+    if (w != 0 || n > 27 * C16) return;
+    const float tot = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    if (n == 27 * C16) {
+        db[o] = tot;
+        return;
+    }
+    const int tap = n / C16, c = n - tap * C16;
+    if (c < C) dw[((size_t)o * C + c) * 27 + tap] = tot;
+}
+
 unsigned grid1(int64_t n, int bs = 256) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
 // splitmix64: a counter-based generator for the initial weights
@@ -398,53 +530,81 @@ std::vector<NetLayer> net_layers(const int widths[3]) {
 
 namespace {
 
-// Channel tile and block size: small grids take narrow channel tiles and
-// small blocks so that the launch still spreads over many CUs.
-struct ConvShape {
-    int tile, threads;
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Packed weight layouts of one layer (see pack_weights_kernel).
+struct PackInfo {
+    int c8in = 0, kpf = 0, rowsf = 0;   // forward: C8 = cin rounded to 8, K padded to 32, cout rounded to 16
+    int c8out = 0, kpb = 0, rowsb = 0;  // data gradient: C8 = cout rounded to 8, rows = cin rounded to 16
+    int64_t off_f = 0, off_b = 0;       // offsets into the packed buffer (multiples of 32 values)
 };
-ConvShape conv_shape(int64_t voxels, int K) {
-    ConvShape c;
-    c.tile = voxels >= 32768 ? 16 : (voxels >= 8192 ? 8 : 4);
-    while (c.tile > 4 && (int64_t)c.tile * K * 4 > 64 * 1024) c.tile /= 2;
-    c.threads = voxels >= 32768 ? 256 : 64;
-    return c;
+
+std::vector<PackInfo> pack_layout(const std::vector<NetLayer>& layers, int64_t* total) {
+    std::vector<PackInfo> pk(layers.size());
+    int64_t off = 0;
+    for (size_t k = 0; k < layers.size(); ++k) {
+        const NetLayer& L = layers[k];
+        PackInfo& q = pk[k];
+        q.c8in = round_up(L.cin, 8);
+        q.kpf = round_up(27 * q.c8in, 32);
+        q.rowsf = round_up(L.cout, 16);
+        q.c8out = round_up(L.cout, 8);
+        q.kpb = round_up(27 * q.c8out, 32);
+        q.rowsb = round_up(L.cin, 16);
+        q.off_f = off;
+        off += (int64_t)q.rowsf * q.kpf;
+        q.off_b = off;
+        off += (int64_t)q.rowsb * q.kpb;
+    }
+    *total = off;
+    return pk;
 }
 
-void conv_fwd(const float* x, const uint16_t* w, const float* bias, float* y, int B, int Ci, int Co, const int in[3],
-              const int out[3], int s, int act, hipStream_t st) {
+// y (+)= conv of x with packed weights (rows = output channels, padded to
+// 16 * mt): one wavefront per 16 output voxels
+void conv_mfma(const float* x, const uint16_t* wpk, const float* bias, float* y, int B, int C, int C8, int Co,
+               int KP, int rows, const int in[3], const int out[3], int s, bool dilate, int act, int accumulate,
+               hipStream_t st) {
     const int nvo = out[0] * out[1] * out[2];
-    const ConvShape c = conv_shape((int64_t)B * nvo, Ci * 27);
-    const size_t lds = (size_t)c.tile * Ci * 27 * sizeof(float);
-    dim3 grid(grid1(nvo, c.threads), (unsigned)((Co + c.tile - 1) / c.tile), (unsigned)B);
-    if (c.tile == 16)
-        hipLaunchKernelGGL(conv_fwd_kernel<16>, grid, dim3(c.threads), lds, st, x, w, bias, y, Ci, Co, in[0], in[1],
-                           in[2], out[0], out[1], out[2], s, act);
-    else if (c.tile == 8)
-        hipLaunchKernelGGL(conv_fwd_kernel<8>, grid, dim3(c.threads), lds, st, x, w, bias, y, Ci, Co, in[0], in[1],
-                           in[2], out[0], out[1], out[2], s, act);
-    else
-        hipLaunchKernelGGL(conv_fwd_kernel<4>, grid, dim3(c.threads), lds, st, x, w, bias, y, Ci, Co, in[0], in[1],
-                           in[2], out[0], out[1], out[2], s, act);
+    dim3 grid((unsigned)((nvo + 63) / 64), (unsigned)B);
+    const int mt = rows / 16;
+#define SNSW_CONV_MFMA(MT, DIL)                                                                                    \
+    hipLaunchKernelGGL((conv_mfma_kernel<MT, DIL>), grid, dim3(256), 0, st, x, wpk, bias, y, C, C8, Co, KP, in[0], \
+                       in[1], in[2], out[0], out[1], out[2], s, act, accumulate)
+    if (dilate) {
+        if (mt == 1) SNSW_CONV_MFMA(1, true);
+        else if (mt == 2) SNSW_CONV_MFMA(2, true);
+        else if (mt == 3) SNSW_CONV_MFMA(3, true);
+        else SNSW_CONV_MFMA(4, true);
+    } else {
+        if (mt == 1) SNSW_CONV_MFMA(1, false);
+        else if (mt == 2) SNSW_CONV_MFMA(2, false);
+        else if (mt == 3) SNSW_CONV_MFMA(3, false);
+        else SNSW_CONV_MFMA(4, false);
+    }
+#undef SNSW_CONV_MFMA
     HIP_OK(hipGetLastError());
 }
 
-void conv_bwd_data(const float* gout, const uint16_t* w, float* gin, int B, int Ci, int Co, const int in[3],
-                   const int out[3], int s, int accumulate, hipStream_t st) {
-    const int nv = in[0] * in[1] * in[2];
-    const ConvShape c = conv_shape((int64_t)B * nv, Co * 27);
-    const size_t lds = (size_t)c.tile * Co * 27 * sizeof(float);
-    dim3 grid(grid1(nv, c.threads), (unsigned)((Ci + c.tile - 1) / c.tile), (unsigned)B);
-    if (c.tile == 16)
-        hipLaunchKernelGGL(conv_bwd_data_kernel<16>, grid, dim3(c.threads), lds, st, gout, w, gin, Ci, Co, in[0],
-                           in[1], in[2], out[0], out[1], out[2], s, accumulate);
-    else if (c.tile == 8)
-        hipLaunchKernelGGL(conv_bwd_data_kernel<8>, grid, dim3(c.threads), lds, st, gout, w, gin, Ci, Co, in[0],
-                           in[1], in[2], out[0], out[1], out[2], s, accumulate);
-    else
-        hipLaunchKernelGGL(conv_bwd_data_kernel<4>, grid, dim3(c.threads), lds, st, gout, w, gin, Ci, Co, in[0],
-                           in[1], in[2], out[0], out[1], out[2], s, accumulate);
-    HIP_OK(hipGetLastError());
+// Weight-gradient GEMM of a layer: input channels per tap rounded to 16,
+// columns 27 C16 + 16 (the bias column and padding), wavefronts per chunk
+// (16-channel groups x 3 kz x output-channel tiles), voxels per chunk (about
+// 4096 wavefronts, at least 512 voxels each, a multiple of 32).
+struct WgradShape {
+    int C16, NP, MP, groups;
+    int64_t chunk;
+    int nchunks;
+};
+WgradShape wgrad_shape(const NetLayer& L, const PackInfo& q, int64_t K) {
+    WgradShape w;
+    w.C16 = round_up(L.cin, 16);
+    w.NP = 27 * w.C16 + 16;
+    w.MP = q.rowsf;
+    w.groups = (w.C16 / 16) * 3 * (w.MP / 16);
+    const int64_t want = std::max<int64_t>(1, 4096 / w.groups);
+    w.chunk = std::max<int64_t>(512, ((K + want - 1) / want + 31) / 32 * 32);
+    w.nchunks = (int)((K + w.chunk - 1) / w.chunk);
+    return w;
 }
 
 }  // namespace
@@ -465,13 +625,20 @@ struct snsw_net {
     float* m = nullptr;
     float* v = nullptr;
     float* grad = nullptr;
-    uint16_t* wbf = nullptr;     // BF16 copy used by the convolutions
+    uint16_t* wbf = nullptr;     // BF16 copy of the parameters (weights as the convolutions see them)
+    uint16_t* wpk = nullptr;     // BF16 weights packed for the implicit-GEMM convolutions
+    std::vector<PackInfo> pk;    // per layer: packed layouts (forward and data gradient)
     int64_t adam_t = 0;
     // workspace for the current shape
     int B = 0, dims[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     std::vector<float*> act;     // T_COUNT activations
     std::vector<float*> gact;    // their gradients
     float* gx_tmp = nullptr;     // gradient of the input when not requested
+    float* wg_part = nullptr;    // weight-gradient partial sums per voxel chunk
+    int64_t wg_cap = 0;          // its capacity (floats)
+    float* cl_x = nullptr;       // channels-last copies of a layer's input and output gradient
+    float* cl_g = nullptr;
+    int64_t cl_cap = 0;          // capacity of each (floats)
     const float* x_in = nullptr; // input of the last forward pass
     double* loss_dev = nullptr;
     // source-iteration workspace
@@ -491,6 +658,13 @@ void free_ws(snsw_net* net) {
         if (p) (void)hipFree(p), p = nullptr;
     if (net->gx_tmp) (void)hipFree(net->gx_tmp);
     net->gx_tmp = nullptr;
+    if (net->wg_part) (void)hipFree(net->wg_part);
+    net->wg_part = nullptr;
+    net->wg_cap = 0;
+    if (net->cl_x) (void)hipFree(net->cl_x);
+    if (net->cl_g) (void)hipFree(net->cl_g);
+    net->cl_x = net->cl_g = nullptr;
+    net->cl_cap = 0;
     net->B = 0;
 }
 
@@ -534,6 +708,21 @@ void ensure_ws(snsw_net* net, int B, int Z, int Y, int X) {
         HIP_OK(hipMalloc(&net->gact[t], tensor_len(net, t) * sizeof(float)));
     }
     HIP_OK(hipMalloc(&net->gx_tmp, (size_t)B * 3 * Z * Y * X * sizeof(float)));
+    int64_t cap = 0, clcap = 0;
+    for (size_t k = 0; k < net->layers.size(); ++k) {
+        const NetLayer& L = net->layers[k];
+        const int lout = L.stride == 2 ? L.level_in + 1 : L.level_in;
+        const int64_t K = (int64_t)B * net->dims[lout][0] * net->dims[lout][1] * net->dims[lout][2];
+        const WgradShape w = wgrad_shape(L, net->pk[k], K);
+        cap = std::max(cap, (int64_t)w.nchunks * w.MP * w.NP);
+        const int64_t Kin = (int64_t)B * net->dims[L.level_in][0] * net->dims[L.level_in][1] * net->dims[L.level_in][2];
+        clcap = std::max(clcap, std::max(Kin * w.C16, K * w.MP));
+    }
+    HIP_OK(hipMalloc(&net->wg_part, cap * sizeof(float)));
+    net->wg_cap = cap;
+    HIP_OK(hipMalloc(&net->cl_x, clcap * sizeof(float)));
+    HIP_OK(hipMalloc(&net->cl_g, clcap * sizeof(float)));
+    net->cl_cap = clcap;
 }
 
 // conv layer k: input tensor (or x), output tensor
@@ -545,10 +734,25 @@ const Wiring kWire[12] = {{-1, T_E0A}, {T_E0A, T_S0}, {T_S0, T_E1A}, {T_E1A, T_S
 
 void run_conv(snsw_net* net, int k, const float* x, hipStream_t s) {
     const NetLayer& L = net->layers[k];
+    const PackInfo& q = net->pk[k];
     const float* in = kWire[k].in < 0 ? x : net->act[kWire[k].in];
     const int lin = L.level_in, lout = L.stride == 2 ? lin + 1 : lin;
-    conv_fwd(in, net->wbf + L.w_off, net->theta + L.b_off, net->act[kWire[k].out], net->B, L.cin, L.cout,
-             net->dims[lin], net->dims[lout], L.stride, L.act, s);
+    conv_mfma(in, net->wpk + q.off_f, net->theta + L.b_off, net->act[kWire[k].out], net->B, L.cin, q.c8in, L.cout,
+              q.kpf, q.rowsf, net->dims[lin], net->dims[lout], L.stride, false, L.act, 0, s);
+}
+
+// refreshes the packed weights from the FP32 masters (after any change)
+void pack_weights(snsw_net* net, hipStream_t s) {
+    for (size_t k = 0; k < net->layers.size(); ++k) {
+        const NetLayer& L = net->layers[k];
+        const PackInfo& q = net->pk[k];
+        hipLaunchKernelGGL(pack_weights_kernel, dim3(grid1((int64_t)q.rowsf * q.kpf)), dim3(256), 0, s,
+                           net->theta + L.w_off, net->wpk + q.off_f, L.cout, L.cin, q.rowsf, q.kpf, q.c8in, 0);
+        HIP_OK(hipGetLastError());
+        hipLaunchKernelGGL(pack_weights_kernel, dim3(grid1((int64_t)q.rowsb * q.kpb)), dim3(256), 0, s,
+                           net->theta + L.w_off, net->wpk + q.off_b, L.cout, L.cin, q.rowsb, q.kpb, q.c8out, 1);
+        HIP_OK(hipGetLastError());
+    }
 }
 
 void run_upadd(snsw_net* net, int low, int skip, int out, hipStream_t s) {
@@ -588,14 +792,36 @@ void back_conv(snsw_net* net, int k, float* gin, int accumulate, hipStream_t s) 
         HIP_OK(hipGetLastError());
     }
     const float* in = kWire[k].in < 0 ? net->x_in : net->act[kWire[k].in];
-    hipLaunchKernelGGL(conv_bwd_weight_kernel, dim3((unsigned)(L.cout * L.cin)), dim3(256), 0, s, in, gout,
-                       net->grad + L.w_off, net->B, L.cin, L.cout, di[0], di[1], di[2], dout[0], dout[1], dout[2],
-                       L.stride);
-    HIP_OK(hipGetLastError());
-    hipLaunchKernelGGL(bias_grad_kernel, dim3((unsigned)L.cout), dim3(256), 0, s, gout, net->grad + L.b_off, net->B,
-                       L.cout, dout[0] * dout[1] * dout[2]);
-    HIP_OK(hipGetLastError());
-    if (gin) conv_bwd_data(gout, net->wbf + L.w_off, gin, net->B, L.cin, L.cout, di, dout, L.stride, accumulate, s);
+    const PackInfo& q = net->pk[k];
+    {
+        const int64_t K = (int64_t)net->B * dout[0] * dout[1] * dout[2];
+        const WgradShape w = wgrad_shape(L, q, K);
+        if ((int64_t)w.nchunks * w.MP * w.NP > net->wg_cap)
+            throw Error(SNSW_E_STATE, "weight-gradient workspace too small");
+        const int nvi = di[0] * di[1] * di[2], nvo = dout[0] * dout[1] * dout[2];
+        if ((int64_t)net->B * nvi * w.C16 > net->cl_cap || K * w.MP > net->cl_cap)
+            throw Error(SNSW_E_STATE, "channels-last workspace too small");
+        hipLaunchKernelGGL(to_channels_last_kernel, dim3((unsigned)((nvi + 63) / 64), (unsigned)net->B), dim3(256), 0,
+                           s, in, net->cl_x, L.cin, w.C16, nvi);
+        HIP_OK(hipGetLastError());
+        hipLaunchKernelGGL(to_channels_last_kernel, dim3((unsigned)((nvo + 63) / 64), (unsigned)net->B), dim3(256), 0,
+                           s, gout, net->cl_g, L.cout, w.MP, nvo);
+        HIP_OK(hipGetLastError());
+        dim3 grid((unsigned)((w.nchunks + 3) / 4), (unsigned)(w.C16 / 16 * 3), (unsigned)(w.MP / 16));
+        hipLaunchKernelGGL(wgrad_mfma_kernel, grid, dim3(256), 0, s, net->cl_x, net->cl_g, net->wg_part, K,
+                           (int)w.chunk, w.nchunks, w.C16, w.NP, w.MP, di[0], di[1], di[2], dout[0], dout[1], dout[2],
+                           L.stride);
+        HIP_OK(hipGetLastError());
+        hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((w.NP + 63) / 64), (unsigned)L.cout), dim3(256), 0,
+                           s, net->wg_part, net->grad + L.w_off, net->grad + L.b_off, w.nchunks, L.cin, w.C16, L.cout,
+                           w.NP, w.MP);
+        HIP_OK(hipGetLastError());
+    }
+    // data gradient: a convolution of gout with the mirrored, transposed
+    // weights (stride 2: over the zero-dilated gout)
+    if (gin)
+        conv_mfma(gout, net->wpk + q.off_b, nullptr, gin, net->B, L.cout, q.c8out, L.cin, q.kpb, q.rowsb, dout, di, 1,
+                  L.stride == 2, 0, accumulate, s);
 }
 
 void upadd_back(snsw_net* net, int h, int low, hipStream_t s) {
@@ -633,7 +859,7 @@ void net_release(snsw_net* net) noexcept {
     if (!net) return;
     (void)hipStreamSynchronize(static_cast<hipStream_t>(net->ctx->stream));
     free_ws(net);
-    void* ptrs[] = {net->theta, net->m, net->v, net->grad, net->wbf, net->loss_dev,
+    void* ptrs[] = {net->theta, net->m, net->v, net->grad, net->wbf, net->wpk, net->loss_dev,
                     net->si_avg, net->si_max, net->si_x, net->si_y};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -748,7 +974,10 @@ int snsw_net_create(snsw_ctx* ctx, const snsw_net_desc* desc, snsw_net** out) {
         HIP_OK(hipMalloc(&net->v, P * sizeof(float)));
         HIP_OK(hipMalloc(&net->grad, P * sizeof(float)));
         HIP_OK(hipMalloc(&net->wbf, P * sizeof(uint16_t)));
-        HIP_OK(hipMalloc(&net->loss_dev, sizeof(double)));
+        int64_t packed = 0;
+        net->pk = pack_layout(net->layers, &packed);
+        HIP_OK(hipMalloc(&net->wpk, packed * sizeof(uint16_t)));
+        HIP_OK(hipMalloc(&net->loss_dev, (1 + kMseBlocks) * sizeof(double)));
         // He-uniform weights (output layer scaled by 0.1), zero biases
         std::vector<float> h(P, 0.0f);
         uint64_t st = desc->seed;
@@ -766,6 +995,7 @@ int snsw_net_create(snsw_ctx* ctx, const snsw_net_desc* desc, snsw_net** out) {
         HIP_OK(hipMemsetAsync(net->grad, 0, P * sizeof(float), s));
         hipLaunchKernelGGL(to_bf16_kernel, dim3(grid1(P)), dim3(256), 0, s, net->theta, net->wbf, P);
         HIP_OK(hipGetLastError());
+        pack_weights(net, s);
         HIP_OK(hipStreamSynchronize(s));
         *out = net;
     });
@@ -812,6 +1042,7 @@ int snsw_net_set_params(snsw_net* net, const float* host) {
         HIP_OK(hipMemsetAsync(net->v, 0, P * sizeof(float), s));
         hipLaunchKernelGGL(to_bf16_kernel, dim3(grid1(P)), dim3(256), 0, s, net->theta, net->wbf, P);
         HIP_OK(hipGetLastError());
+        pack_weights(net, s);
         HIP_OK(hipStreamSynchronize(s));
         net->adam_t = 0;
     });
@@ -845,7 +1076,10 @@ int snsw_net_loss(snsw_net* net, const float* d_y, const float* d_t, int64_t cou
         if (count < 1) throw Error(SNSW_E_SHAPE, "count must be >= 1");
         DeviceGuard g(net->ctx->device);
         hipStream_t s = static_cast<hipStream_t>(net->ctx->stream);
-        hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(1024), 0, s, d_y, d_t, count, d_dy, net->loss_dev);
+        const int blocks = (int)std::min<int64_t>(kMseBlocks, (count + 255) / 256);
+        hipLaunchKernelGGL(mse_partial_kernel, dim3(blocks), dim3(256), 0, s, d_y, d_t, count, d_dy, net->loss_dev + 1);
+        HIP_OK(hipGetLastError());
+        hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(64), 0, s, net->loss_dev + 1, blocks, count, net->loss_dev);
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(loss, net->loss_dev, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
@@ -875,6 +1109,7 @@ int snsw_net_step(snsw_net* net, const snsw_adam* opt) {
         hipLaunchKernelGGL(adam_kernel, dim3(grid1(net->n_params)), dim3(256), 0, s, net->theta, net->grad, net->m,
                            net->v, net->wbf, net->n_params, opt->lr, opt->beta1, opt->beta2, opt->eps, c1, c2);
         HIP_OK(hipGetLastError());
+        pack_weights(net, s);
     });
 }
 

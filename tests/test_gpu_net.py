@@ -1,12 +1,15 @@
 """Learned correction on the GPU (HIP kernels through the C-ABI) against the
 CPU FP64 oracle.
 
-The kernels use BF16 weights and FP32 activations and accumulation; the
-oracle is evaluated in FP64 with the same BF16-rounded weights (round to
-nearest even, done here on the host) and FP32 biases, so the comparison
-measures only FP32 accumulation: each output sums c*27 <= 864 products, so
-its relative rounding error is below about 864 * 2^-24 = 5e-5 per layer,
-and 12 layers stay within the 1e-3 bar used here (normwise L-infinity).
+The kernels use BF16 weights and FP32 activations and accumulation (the
+convolutions are BF16 MFMA tiles: an FP32 activation enters as two BF16
+terms hi + lo, which carry it to 2^-16 relative; weight gradients add the
+three leading products of the two split operands); the oracle is evaluated
+in FP64 with the same BF16-rounded weights (round to nearest even, done here
+on the host) and FP32 biases.  The comparison thus measures the split
+(about 2^-16 = 1.5e-5 per product) and FP32 accumulation of c*27 <= 864
+products (about 864 * 2^-24 = 5e-5 per layer); 12 layers stay within the
+1e-3 bar used here (normwise L-infinity).
 """
 import numpy as np
 import pytest
