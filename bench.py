@@ -501,6 +501,41 @@ def ho_vs_lo(levels=(1, 2, 4)):
     return rows
 
 
+def learned_study(train_steps: int, eval_seeds=(100, 101, 102, 103), every: int = 40):
+    """The learned correction on the 48^3 S12 family: trained on seeds 0 and
+    1 (as the default line), then plain vs learned source iteration to 1e-8
+    on each held-out seed, and an ablation with the same network untrained
+    (its initial weights) on the first held-out seed."""
+    import torch
+    import workloads as W
+    from paper_1810_11080_amd import Context, Net, Problem
+    ctx = Context(device=0)
+    net, training = train_correction(ctx, lambda seed: W.c5(seed=seed), (0, 1), train_steps, 10, 1e-10)
+    untrained = Net(ctx, widths=(16, 32, 32), seed=0)
+    runs, ablation = [], None
+    for seed in eval_seeds:
+        P = Problem.from_workload(ctx, W.c5(seed=seed))
+        note(f"seed {seed}: problem built")
+        r = compare_solves(P, net, every)
+        runs.append(dict(seed=seed, **r))
+        if ablation is None:
+            P.reset()
+            phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+            rep = P.solve(phi, tol=1e-8, max_iters=50000, precond=untrained, precond_every=every,
+                          raise_on_not_converged=False)
+            ablation = {"seed": seed, "seconds": round(rep["seconds"], 4), "sweeps": rep["iterations"],
+                        "residual": rep["residual"], "corrections": rep["n_corrected"],
+                        "rejected": rep["n_rejected"]}
+            note(f"untrained network: {ablation}")
+        P.close()
+        del P
+        torch.cuda.synchronize()
+    block = learned_block(runs, training, every, DESCRIPTIONS["c5"].replace(" (seed 100)", "") +
+                          "; network trained on seeds 0 and 1", net.n_params)
+    block["untrained_network"] = ablation
+    return block
+
+
 def calibrate_copy(nbytes: int = 1 << 30, reps: int = 3):
     """A plain streaming kernel of known traffic (read nbytes, write nbytes):
     the reference for scaling HBM counter readings to bytes."""
@@ -537,6 +572,8 @@ def main():
                     help="only the unity / face / sigma-inverse-face weighting comparison")
     ap.add_argument("--ho-vs-lo", action="store_true",
                     help="only the high-order vs straightened low-order manufactured-solution comparison")
+    ap.add_argument("--learned-study", action="store_true",
+                    help="only the learned correction on 48^3 S12: held-out seeds 100-103 and an untrained ablation")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -557,6 +594,9 @@ def main():
         return
     if args.ho_vs_lo:
         print(json.dumps({"ho_vs_lo": ho_vs_lo()}))
+        return
+    if args.learned_study:
+        print(json.dumps({"learned_study": learned_study(args.train_steps)}))
         return
     if args.workload == "c4":
         bench_batch(args)
