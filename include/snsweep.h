@@ -147,6 +147,20 @@ typedef struct {
                                 of direction d at the DG nodes of element e;
                                 only nodes on boundary faces through which d
                                 flows in are read (others are ignored)      */
+    /* Unstructured conforming mesh (section 2: each element's map is given
+     * by its own control points, taken from a global list; shared faces
+     * share their control points).  elem_nodes == NULL: the structured
+     * lattice above.  Otherwise lattice is ignored, E = nx[0] (nx[1] and
+     * nx[2] must be 1), nodes [n_nodes][dim] are the control points and
+     * elem_nodes [E][(r+1)^dim] the indices of each element's control
+     * points in its local lexicographic order (x fastest).  Two element
+     * faces are the same face when their corner control points coincide (by
+     * index); they may meet in any orientation.  Every element map must be
+     * orientation preserving (det J > 0).  Such problems sweep on the LEVELS
+     * schedule (SNSW_SCHED_PERSISTENT gives SNSW_E_UNSUPPORTED).            */
+    int64_t n_nodes;
+    const double* nodes;
+    const int64_t* elem_nodes;
 } snsw_problem_desc;
 
 /* Builds the discretisation and the sweep schedule (section 3): quadrature,
@@ -415,7 +429,8 @@ int snsw_learn_pair_noalloc(snsw_problem* prob, const double* d_phi_prev, const 
  *              the class has tiles (tune_reps sweeps each, default 3), and
  *              keeps the fastest;
  *              SNSW_SCHED_PERSISTENT / SNSW_SCHED_LEVELS force one for every
- *              FP64 class.  Mixed-precision classes always use LEVELS.
+ *              FP64 class.  Mixed-precision classes and classes of
+ *              unstructured meshes always use LEVELS.
  *   use_graph  0: eager launches; otherwise hipGraph replay.
  * Autotuning sweeps the member problems, so create leaves their stored
  * angular flux zero (as snsw_reset).  A batch refers to its problems'

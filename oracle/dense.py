@@ -32,13 +32,12 @@ def assemble(disc):
             rhs[blk(d, e)] += bd[e]
         for s in range(2 * dim):
             _, Pin = disc.slot_blocks(d, s, elems)
-            tn = disc.slot_nodes[s]
-            tn_up = disc.slot_nodes[s ^ 1]
             for e in range(E):
+                tn = disc.slot_trace[e, s]
                 nb = disc.slot_nbr[e, s]
                 rows = blk(d, e).start + tn
                 if nb >= 0:
-                    cols = blk(d, nb).start + tn_up
+                    cols = blk(d, nb).start + disc.slot_up_trace[e, s]
                     A[np.ix_(rows, cols)] -= Pin[e]
                 elif disc.inflow_fn is not None:
                     rhs[rows] += disc.boundary_load(d, s, np.array([e]))[0]

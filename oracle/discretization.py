@@ -20,7 +20,7 @@ import numpy as np
 
 from . import quadrature
 from .faces import FaceSet
-from .geometry import ElementGeometry
+from .geometry import ElementGeometry, problem_control_points
 
 VACUUM, ISO_CONST, TABULATED = 0, 1, 2
 
@@ -35,17 +35,22 @@ class Discretization:
         constant incident flux.  Both are oracle-only test hooks."""
         self.prob = prob
         self.dim, self.nx, self.r, self.p = prob.dim, tuple(prob.nx), prob.r, prob.p
-        self.E = int(np.prod(self.nx))
+        self.unstructured = getattr(prob, "elem_nodes", None) is not None
+        self.E = len(prob.elem_nodes) if self.unstructured else int(np.prod(self.nx))
         self.n = (self.p + 1) ** self.dim
         if omega is None:
             omega, w = quadrature.level_symmetric(prob.sn_order, prob.dim)
         self.omega, self.w = np.asarray(omega), np.asarray(w)
         self.D = len(self.w)
-        self.geo = ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p)
+        xe = problem_control_points(prob)
+        self.geo = ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p, xe=xe)
         self.geo.check_positive()
         self.M = self.geo.mass()                     # (E, n, n)
         self.K = self.geo.grad_moments()             # (E, dim, n, n)
-        self.faces = FaceSet(prob.lattice, self.dim, self.nx, self.r, self.p)
+        if self.unstructured:
+            self.faces = FaceSet.from_elements(prob.nodes, prob.elem_nodes, self.dim, self.r, self.p)
+        else:
+            self.faces = FaceSet(prob.lattice, self.dim, self.nx, self.r, self.p)
         self.sigma_t = np.asarray(prob.sigma_t, dtype=np.float64)
         self.sigma_s = np.asarray(prob.sigma_s, dtype=np.float64)
         self.q = np.asarray(prob.q, dtype=np.float64)
@@ -60,31 +65,41 @@ class Discretization:
         self.q_dir = None if q_dir is None else np.asarray(q_dir, dtype=np.float64).reshape(-1, self.E, self.n)
         tab = getattr(prob, "psi_inc_tab", None) if prob.bc_kind == TABULATED else None
         self.psi_tab = None if tab is None else np.asarray(tab, dtype=np.float64).reshape(-1, self.E, self.n)
-        # element -> slot -> (face, side, neighbour), trace nodes per slot
-        e = np.arange(self.E)
-        eidx, rem = [], e.copy()
-        for a in range(self.dim):
-            eidx.append(rem % self.nx[a])
-            rem = rem // self.nx[a]
-        self.eidx = eidx
-        ns = 2 * self.dim
-        self.slot_face = np.zeros((self.E, ns), dtype=np.int64)
-        self.slot_side = np.zeros(ns, dtype=np.int64)
-        self.slot_nbr = np.zeros((self.E, ns), dtype=np.int64)
-        self.slot_nodes = np.zeros((ns, self.faces.nf), dtype=np.int64)
-        for s in range(ns):
-            fid, side = self.faces.face_of_slot(eidx, s)
-            self.slot_face[:, s] = fid
-            self.slot_side[s] = side
-            self.slot_nbr[:, s] = np.where(side == 0, self.faces.plus[fid], self.faces.minus[fid])
-            self.slot_nodes[s] = self.faces.trace_nodes(s)
+        # element -> slot -> (face, side, neighbour); the element's and the
+        # neighbour's DG nodes on the slot, both listed in the face's (s, t)
+        # order (on a lattice the same for every element: the slot's own
+        # trace nodes and those of the opposite slot)
+        if not self.unstructured:
+            e = np.arange(self.E)
+            eidx, rem = [], e.copy()
+            for a in range(self.dim):
+                eidx.append(rem % self.nx[a])
+                rem = rem // self.nx[a]
+            self.eidx = eidx
+        fs = self.faces
+        self.slot_face = fs.slot_face
+        self.slot_side = fs.slot_side                         # (E, 2 dim): 0 minus, 1 plus
+        self.slot_nbr = np.where(self.slot_side == 0, fs.plus[self.slot_face], fs.minus[self.slot_face])
+        self.slot_trace = fs.slot_trace                       # (E, 2 dim, nf)
+        self.slot_up_trace = np.zeros_like(self.slot_trace)
+        for f in np.nonzero(fs.interior)[0]:
+            em, ep = fs.minus[f], fs.plus[f]
+            sm = int(np.nonzero(self.slot_face[em] == f)[0][0])
+            sp = int(np.nonzero(self.slot_face[ep] == f)[0][0])
+            self.slot_up_trace[em, sm] = self.slot_trace[ep, sp]
+            self.slot_up_trace[ep, sp] = self.slot_trace[em, sm]
+        # face -> slot of its minus / plus element
+        self.face_slot = np.full((fs.n_faces, 2), -1, dtype=np.int64)
+        for e_ in range(self.E):
+            for s_ in range(2 * self.dim):
+                self.face_slot[self.slot_face[e_, s_], self.slot_side[e_, s_]] = s_
         self._cache_d = None
         self._cache = None
         self.inflow_fn = inflow_fn
         self.src_load = None
         if source_fn is not None:
             fine = ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p,
-                                   extra_points=4)
+                                   extra_points=4, xe=xe)
             self.src_load = np.stack([fine.load(source_fn(fine.x, self.omega[d]))
                                       for d in range(self.D)])
 
@@ -94,9 +109,6 @@ class Discretization:
         covers the full quadrature; a Discretization built on a subset of
         directions maps its d back through dir_rows)."""
         return int(self.dir_rows[d]) if getattr(self, "dir_rows", None) is not None else d
-
-    def opposite_slot(self, s: int) -> int:
-        return s ^ 1
 
     def face_blocks(self, d: int):
         """Face integrals for direction d (cached for the last direction)."""
@@ -110,22 +122,23 @@ class Discretization:
         return self._cache
 
     def slot_blocks(self, d: int, s: int, elems: np.ndarray):
-        """(P_out, P_in) of slot s for the given elements, direction d."""
+        """(P_out, P_in) of slot s for the given elements, direction d (in
+        the face's (s, t) node order)."""
         Pp, Pm, *_ = self.face_blocks(d)
         fid = self.slot_face[elems, s]
-        if self.slot_side[s] == 0:          # element is the face's minus side
-            return Pp[fid], Pm[fid]
-        return Pm[fid], Pp[fid]
+        minus = (self.slot_side[elems, s] == 0)[:, None, None]   # element is the face's minus side
+        return np.where(minus, Pp[fid], Pm[fid]), np.where(minus, Pm[fid], Pp[fid])
 
     def local_matrix(self, d: int, elems: np.ndarray) -> np.ndarray:
         """A_e for the given elements and direction d, (k, n, n)."""
         om = self.omega[d][: self.dim]
         A = self.sigma_t[elems, None, None] * self.M[elems]
         A = A - np.einsum("i,kimn->kmn", om, self.K[elems])
+        rows = np.arange(len(elems))[:, None, None]
         for s in range(2 * self.dim):
             Pout, _ = self.slot_blocks(d, s, elems)
-            tn = self.slot_nodes[s]
-            A[:, tn[:, None], tn[None, :]] += Pout
+            tn = self.slot_trace[elems, s]
+            A[rows, tn[:, :, None], tn[:, None, :]] += Pout
         return A
 
     def volume_source(self, phi: np.ndarray, elems: np.ndarray, d: int = 0) -> np.ndarray:
@@ -146,7 +159,7 @@ class Discretization:
         fid = self.slot_face[elems, s]
         # inflow of the minus side is where g < 0 (L_minus), of the plus side
         # where g > 0 (L_plus)
-        return Lm[fid] if self.slot_side[s] == 0 else Lp[fid]
+        return np.where((self.slot_side[elems, s] == 0)[:, None], Lm[fid], Lp[fid])
 
     def local_rhs(self, d, elems, phi, psi_kept, psi_lag, lagged_mask):
         """b_e for direction d.
@@ -155,29 +168,30 @@ class Discretization:
         lagged upwind couplings; lagged_mask (k, 2*dim) bool marks slots whose
         inflow edge was removed from the graph (read psi_lag)."""
         b = self.volume_source(phi, elems, d)
+        rows = np.arange(len(elems))[:, None]
         for s in range(2 * self.dim):
             _, Pin = self.slot_blocks(d, s, elems)
-            tn = self.slot_nodes[s]
-            tn_up = self.slot_nodes[self.opposite_slot(s)]
+            tn = self.slot_trace[elems, s]
+            tn_up = self.slot_up_trace[elems, s]
             nbr = self.slot_nbr[elems, s]
             interior = nbr >= 0
             up = np.zeros((len(elems), self.faces.nf))
             if np.any(interior):
-                src = np.where(lagged_mask[:, s][:, None], psi_lag[np.maximum(nbr, 0)][:, tn_up],
-                               psi_kept[np.maximum(nbr, 0)][:, tn_up])
+                nb = np.maximum(nbr, 0)[:, None]
+                src = np.where(lagged_mask[:, s][:, None], psi_lag[nb, tn_up], psi_kept[nb, tn_up])
                 up = np.where(interior[:, None], src, 0.0)
             if self.psi_tab is not None:
                 # tabulated incident flux at this element's own face nodes
-                tab = self.psi_tab[self.dir_index(d)][elems][:, tn]
+                tab = self.psi_tab[self.dir_index(d)][elems[:, None], tn]
                 up = np.where(interior[:, None], up, tab)
-                b[:, tn] += np.einsum("kab,kb->ka", Pin, up)
+                b[rows, tn] += np.einsum("kab,kb->ka", Pin, up)
                 continue
             if self.inflow_fn is not None:
                 up = np.where(interior[:, None], up, 0.0)
-                b[:, tn] += np.einsum("kab,kb->ka", Pin, up)
+                b[rows, tn] += np.einsum("kab,kb->ka", Pin, up)
                 bl = self.boundary_load(d, s, elems)
-                b[:, tn] += np.where(interior[:, None], 0.0, bl)
+                b[rows, tn] += np.where(interior[:, None], 0.0, bl)
                 continue
             up = np.where(interior[:, None], up, self.psi_inc)
-            b[:, tn] += np.einsum("kab,kb->ka", Pin, up)
+            b[rows, tn] += np.einsum("kab,kb->ka", Pin, up)
         return b

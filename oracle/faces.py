@@ -31,7 +31,9 @@ sign; it uses Romberg integration with an unstated tolerance).  Reading:
   each (exact on faces without a sign change).
 * Interior faces: a side whose inflow measure int max(-/+g, 0) ds_ref is at
   most tau = 1e-12 times int |g| ds_ref is dropped entirely (its P is set to
-  zero), so the operator and the dependency graph agree.
+  zero), so the operator and the dependency graph agree; a face along the
+  direction (int |g| ds_ref at most tau |int N ds_ref|, i.e. Omega . N is
+  zero up to rounding) has both sides dropped.
 """
 from __future__ import annotations
 
@@ -108,13 +110,150 @@ class FaceSet:
         self.minus = np.concatenate(minus)
         self.plus = np.concatenate(plus)
         self.ctrl = np.concatenate(ctrl)          # (F, (r+1)^(dim-1), dim)
+        self._finish()
+        # per element slot: face, side and the element's DG nodes in the
+        # face's (s, t) order (the same for every element of a lattice)
+        E = int(np.prod(nx))
+        e = np.arange(E)
+        eidx, rem = [], e.copy()
+        for a in range(dim):
+            eidx.append(rem % nx[a])
+            rem = rem // nx[a]
+        ns = 2 * dim
+        self.slot_face = np.zeros((E, ns), dtype=np.int64)
+        self.slot_side = np.zeros((E, ns), dtype=np.int64)
+        self.slot_trace = np.zeros((E, ns, self.nf), dtype=np.int64)
+        for sl in range(ns):
+            fid, side = self.face_of_slot(eidx, sl)
+            self.slot_face[:, sl] = fid
+            self.slot_side[:, sl] = side
+            self.slot_trace[:, sl, :] = self.trace_nodes(sl)[None, :]
+
+    def _finish(self):
         self.n_faces = len(self.axis)
         self.interior = (self.minus >= 0) & (self.plus >= 0)
-        self.nf = (p + 1) ** (dim - 1)
-        self._geo_nodes = basis.equispaced_points(r)
-        self._dg_nodes = basis.gll_points(p)
-        if dim == 3:
+        self.nf = (self.p + 1) ** (self.dim - 1)
+        self._geo_nodes = basis.equispaced_points(self.r)
+        self._dg_nodes = basis.gll_points(self.p)
+        if self.dim == 3:
             self._setup_3d_rule()
+        # |int N ds_ref| per face (the face's area scale)
+        if self.dim == 2:
+            xg, wg = basis.gauss_legendre(face_rule_2d(self.r, self.p))
+            Nq = self._normals(xg[:, None], per_face=False)               # (F, Q, 2)
+            self.n_area = np.linalg.norm(np.einsum("q,fqa->fa", wg, Nq), axis=1)
+        else:
+            self.n_area = np.linalg.norm(np.einsum("q,fqa->fa", self.rule3_w, self.rule3_N), axis=1)
+
+    # ------------------------------------------------------------------
+    @classmethod
+    def from_elements(cls, nodes, elem_nodes, dim: int, r: int, p: int):
+        """Faces of a conforming mesh given as element control-point lists.
+
+        Two element slots are the same face when their corner control points
+        coincide (by index).  Convention for each face: its minus element is
+        the one with the smaller index (the only one on the boundary); the
+        face is parametrised like the minus element's slot (remaining axes
+        ascending), mirrored when that slot is a xi_a = 0 face (2D: s ->
+        1 - s; 3D: s and t exchanged), so that N, computed from the axis
+        formula above, is the outward normal of the minus element.  The plus
+        element's face coordinates are related to the face's by one of the
+        symmetries of the reference face, read off the positions of the
+        shared control points.  Slot tables: per (element, slot) the face,
+        the side (0 minus, 1 plus) and the element's DG nodes listed in the
+        face's (s, t) order."""
+        fs = cls.__new__(cls)
+        nodes = np.asarray(nodes, dtype=np.float64)
+        en = np.asarray(elem_nodes, dtype=np.int64)
+        E, ns = len(en), 2 * dim
+        fs.dim, fs.r, fs.p, fs.nx = dim, r, p, (E,) + (1,) * (dim - 1)
+        nfc = (r + 1) ** (dim - 1)
+
+        def face_grid(order, slot):
+            """Element-local node numbers of a slot at per-axis order
+            `order`, as a (order+1)^(dim-1) grid in the slot's own (s, t)."""
+            a, hi = slot // 2, slot % 2
+            others = [b for b in range(dim) if b != a]
+            n1 = order + 1
+            out = np.zeros((n1,) * (dim - 1), dtype=np.int64)
+            for loc in np.ndindex(*((n1,) * (dim - 1))):
+                idx = [0] * dim
+                for k, b in enumerate(others):
+                    idx[b] = loc[::-1][k] if dim == 3 else loc[k]
+                idx[a] = order if hi else 0
+                out[loc] = sum(idx[b] * n1 ** b for b in range(dim))
+            return out   # 2D: out[i]; 3D: out[j, i] (t slow, s fast)
+
+        ctrl_grid = [face_grid(r, sl) for sl in range(ns)]
+        dg_grid = [face_grid(p, sl) for sl in range(ns)]
+
+        def corners(g):
+            return (g[0], g[-1]) if dim == 2 else (g[0, 0], g[0, -1], g[-1, 0], g[-1, -1])
+
+        table = {}
+        for e in range(E):
+            for sl in range(ns):
+                key = frozenset(int(en[e, c]) for c in corners(ctrl_grid[sl]))
+                table.setdefault(key, []).append((e, sl))
+        recs = sorted((sorted(v) for v in table.values()), key=lambda v: v[0])
+        F = len(recs)
+        fs.axis = np.zeros(F, dtype=np.int64)
+        fs.minus = np.full(F, -1, dtype=np.int64)
+        fs.plus = np.full(F, -1, dtype=np.int64)
+        fs.ctrl = np.zeros((F, nfc, dim))
+        fs.slot_face = np.full((E, ns), -1, dtype=np.int64)
+        fs.slot_side = np.zeros((E, ns), dtype=np.int64)
+        fs.slot_trace = np.zeros((E, ns, (p + 1) ** (dim - 1)), dtype=np.int64)
+
+        def mirror(g):
+            return g[::-1] if dim == 2 else g.T
+
+        for f, rec in enumerate(recs):
+            if len(rec) > 2 or (len(rec) == 2 and rec[0][0] == rec[1][0]):
+                raise ValueError(f"non-conforming face {rec}")
+            (em, sm) = rec[0]
+            cg, dgg = ctrl_grid[sm], dg_grid[sm]
+            if sm % 2 == 0:
+                cg, dgg = mirror(cg), mirror(dgg)
+            ids = en[em][cg]                          # face-ordered control point ids
+            fs.axis[f] = sm // 2
+            fs.minus[f] = em
+            fs.ctrl[f] = nodes[ids.reshape(-1)]
+            fs.slot_face[em, sm] = f
+            fs.slot_side[em, sm] = 0
+            fs.slot_trace[em, sm] = dgg.reshape(-1)
+            if len(rec) == 1:
+                continue
+            (ep, sp) = rec[1]
+            fs.plus[f] = ep
+            fs.slot_face[ep, sp] = f
+            fs.slot_side[ep, sp] = 1
+            # where each face control point sits in the plus slot's grid
+            pos = {int(en[ep][c]): loc for loc, c in np.ndenumerate(ctrl_grid[sp])}
+            try:
+                locs = {loc: pos[int(ids[loc])] for loc in np.ndindex(ids.shape)}
+            except KeyError as exc:
+                raise ValueError(f"non-conforming face between elements {em} and {ep}") from exc
+            # the symmetry as an affine map of normalised face coordinates
+            o = np.array(locs[(0,) * (dim - 1)]) / r
+            cols = []
+            for k in range(dim - 1):
+                unit = [0] * (dim - 1)
+                unit[k] = r
+                cols.append(np.array(locs[tuple(unit)]) / r - o)
+            for loc in np.ndindex(ids.shape):
+                want = o + sum(cols[k] * (loc[k] / r) for k in range(dim - 1))
+                if not np.array_equal(np.rint(want * r).astype(int), np.array(locs[loc])):
+                    raise ValueError(f"face {f}: control points do not match a face symmetry")
+            tr = np.zeros(dgg.shape, dtype=np.int64)
+            for loc in np.ndindex(dgg.shape):
+                u = o + sum(cols[k] * (loc[k] / p) for k in range(dim - 1))
+                tr[loc] = dg_grid[sp][tuple(np.rint(u * p).astype(int))]
+            fs.slot_trace[ep, sp] = tr.reshape(-1)
+        if np.any(fs.slot_face < 0):
+            raise ValueError("an element slot has no face")
+        fs._finish()
+        return fs
 
     # ------------------------------------------------------------------
     def face_of_slot(self, e_idx: np.ndarray, slot: int):
@@ -288,8 +427,12 @@ class FaceSet:
         mp = wp.sum(axis=1)
         mm = wm.sum(axis=1)
         mabs = mp + mm
-        drop_p = self.interior & (mp <= TAU * mabs)
-        drop_m = self.interior & (mm <= TAU * mabs)
+        # a face along the direction (int |g| at most tau |int N|: Omega . N
+        # vanishes up to rounding) couples nothing; otherwise a side whose
+        # measure is at most tau int |g| is dropped
+        tangential = self.interior & (mabs <= TAU * self.n_area)
+        drop_p = self.interior & ((mp <= TAU * mabs) | tangential)
+        drop_m = self.interior & ((mm <= TAU * mabs) | tangential)
         Pp[drop_p] = 0.0
         Pm[drop_m] = 0.0
         mp = np.where(drop_p, 0.0, mp)

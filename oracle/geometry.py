@@ -30,6 +30,14 @@ def volume_points_per_axis(dim: int, r: int, p: int) -> int:
     return p + r if dim == 2 else p + int(math.ceil(1.5 * r))
 
 
+def problem_control_points(prob) -> np.ndarray:
+    """(E, (r+1)^dim, dim) control points of a problem: from its element list
+    when the mesh is unstructured, else gathered from its lattice."""
+    if getattr(prob, "elem_nodes", None) is not None:
+        return np.asarray(prob.nodes, dtype=np.float64)[np.asarray(prob.elem_nodes)]
+    return element_control_points(prob.lattice, prob.dim, prob.nx, prob.r)
+
+
 def element_control_points(lattice: np.ndarray, dim: int, nx, r: int) -> np.ndarray:
     """(E, (r+1)^dim, dim) control points x_e gathered from the global lattice
     (the extraction operator x -> x_e of section 2)."""
@@ -59,7 +67,9 @@ def element_control_points(lattice: np.ndarray, dim: int, nx, r: int) -> np.ndar
 class ElementGeometry:
     """Jacobians and M, K_i for all elements."""
 
-    def __init__(self, lattice, dim, nx, r, p, extra_points: int = 0):
+    def __init__(self, lattice, dim, nx, r, p, extra_points: int = 0, xe=None):
+        """xe (E, (r+1)^dim, dim): the elements' control points when the mesh
+        is given as an element list (then lattice and nx are not used)."""
         self.dim, self.nx, self.r, self.p = dim, tuple(nx), r, p
         nq = volume_points_per_axis(dim, r, p) + extra_points
         xq, wq = basis.gauss_legendre(nq)
@@ -77,7 +87,9 @@ class ElementGeometry:
         # reference coordinates of the points, axis 0 fastest
         pts = np.array(np.meshgrid(*([xq] * dim), indexing="ij")).reshape(dim, -1)
         self.xi = pts[::-1].T.copy()                    # (Q, dim)
-        self.xe = element_control_points(lattice, dim, nx, r)   # (E, Nv, dim)
+        if xe is None:
+            xe = element_control_points(lattice, dim, nx, r)
+        self.xe = np.asarray(xe, dtype=np.float64)               # (E, Nv, dim)
         # J[e, q, a, b] = d x_a / d xi_b
         self.J = np.einsum("ema,qmb->eqab", self.xe, self.Gg)
         self.detJ = np.linalg.det(self.J)

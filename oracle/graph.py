@@ -75,18 +75,14 @@ def edges_for_direction(disc, d: int, weighting: int):
         elif weighting == 1:
             z = np.abs(blocks).max(axis=(1, 2))
         elif weighting == 2:
-            # slot of the downwind element on this face
-            axis = fs.axis[f]
-            slot = 2 * axis + (1 if down_side == 0 else 0)
-            z = np.zeros(len(f))
-            for s in np.unique(slot):
-                sel = slot == s
-                e = down[sel]
-                Mt = disc.sigma_t[e, None, None] * disc.M[e]
-                Minv = np.linalg.inv(Mt)
-                tn = disc.slot_nodes[s]
-                prod = np.einsum("kma,kab->kmb", Minv[:, :, tn], blocks[sel])
-                z[sel] = np.abs(prod).max(axis=(1, 2))
+            # slot of the downwind element on this face and its nodes there
+            slot = disc.face_slot[f, down_side]
+            tn = disc.slot_trace[down, slot]                       # (k, nf)
+            Mt = disc.sigma_t[down, None, None] * disc.M[down]
+            Minv = np.linalg.inv(Mt)
+            cols = np.take_along_axis(Minv, tn[:, None, :], axis=2)   # Minv[:, :, tn]
+            prod = np.einsum("kma,kab->kmb", cols, blocks)
+            z = np.abs(prod).max(axis=(1, 2))
         else:
             raise ValueError("weighting")
         ups.append(up)

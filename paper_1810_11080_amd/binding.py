@@ -30,7 +30,8 @@ class SnswProblemDesc(C.Structure):
                 ("q_per_dof", C.c_int32), ("bc_kind", C.c_int32), ("psi_inc", C.c_double),
                 ("weighting", C.c_int32), ("exact_scc_max", C.c_int32),
                 ("precision", C.c_int32), ("n_threads", C.c_int32), ("schedule", C.c_int32),
-                ("cache_inverse", C.c_int32), ("psi_inc_tab", c_double_p)]
+                ("cache_inverse", C.c_int32), ("psi_inc_tab", c_double_p),
+                ("n_nodes", C.c_int64), ("nodes", c_double_p), ("elem_nodes", C.POINTER(C.c_int64))]
 
 
 class SnswProblemInfo(C.Structure):
@@ -243,9 +244,12 @@ class Problem:
     def __init__(self, ctx: Context, *, dim, nx, geom_order, dg_order, lattice, sn_order,
                  sigma_t, sigma_s, q, bc_kind=0, psi_inc=0.0, weighting=1, exact_scc_max=10,
                  precision=0, n_threads=0, omega=None, w=None, schedule=0, cache_inverse=0,
-                 psi_inc_tab=None):
+                 psi_inc_tab=None, nodes=None, elem_nodes=None):
         """q: [E] or [E][n] isotropic, or [D][E][n] per direction (nodal
-        values); psi_inc_tab: [D][E][n] incident flux for bc_kind 2."""
+        values); psi_inc_tab: [D][E][n] incident flux for bc_kind 2.  With
+        elem_nodes ([E][(r+1)^dim] control-point indices into nodes
+        [n_nodes][dim]) the mesh is unstructured: nx = (E, 1[, 1]) and
+        lattice is ignored."""
         self.ctx = ctx
         if dim not in (2, 3):
             raise SnswError(-1, "dim must be 2 or 3")
@@ -266,8 +270,18 @@ class Problem:
             desc.nx[a] = int(nx[a]) if a < len(nx) else 1
         desc.geom_order = geom_order
         desc.dg_order = dg_order
-        L = int(np.prod([geom_order * int(nx[a]) + 1 for a in range(dim)]))
-        desc.lattice = arr(lattice, L * dim)
+        if elem_nodes is None:
+            L = int(np.prod([geom_order * int(nx[a]) + 1 for a in range(dim)]))
+            desc.lattice = arr(lattice, L * dim)
+        else:
+            en = np.ascontiguousarray(np.asarray(elem_nodes, dtype=np.int64))
+            if en.size != E * (geom_order + 1) ** dim:
+                raise ValueError("elem_nodes must have E*(r+1)^dim entries")
+            self._keep.append(en)
+            nd = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))
+            desc.n_nodes = nd.size // dim
+            desc.nodes = arr(nd)
+            desc.elem_nodes = en.ctypes.data_as(C.POINTER(C.c_int64))
         desc.sn_order = sn_order if omega is None else 0
         if omega is not None:
             desc.n_dirs = len(w)
@@ -309,7 +323,8 @@ class Problem:
                    weighting=prob.weighting if weighting is None else weighting,
                    exact_scc_max=prob.exact_scc_max if exact_scc_max is None else exact_scc_max,
                    precision=precision, n_threads=n_threads, schedule=schedule,
-                   cache_inverse=cache_inverse)
+                   cache_inverse=cache_inverse, nodes=getattr(prob, "nodes", None),
+                   elem_nodes=getattr(prob, "elem_nodes", None))
 
     def set_source(self, q, bc_kind=0, psi_inc=0.0, psi_inc_tab=None):
         """Replace the volume source and boundary condition (snsw_problem_set_source)."""

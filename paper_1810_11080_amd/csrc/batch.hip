@@ -25,6 +25,7 @@ struct BatchGraph {
 struct BatchClass {
     SweepClass cls;
     bool has_inv = false;              // every member keeps cached inverses
+    bool levels_only = false;          // mixed precision or unstructured meshes: level schedule
     int4* d_pairs = nullptr;           // level schedule
     std::vector<int64_t> level_off;
     bool tiled = false;                // every member has a tiled schedule
@@ -335,7 +336,7 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
     } else {
         for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
             const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
-            launch_sweep_level(c.dim, c.p, c.mixed, c.inv, L.table, c.pairs, b, n, class_problem(c), s);
+            launch_sweep_level(c.dim, c.p, c.mixed, c.inv, c.unstructured, L.table, c.pairs, b, n, class_problem(c), s);
         }
     }
     HIP_OK(hipGetLastError());
@@ -375,12 +376,12 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
         b->probs.assign(probs, probs + count);
         b->use_graph = o.use_graph != 0;
         // classes by (dim, p, precision, cached inverse), in order of first appearance
-        std::map<std::tuple<int, int, int, int>, int> key;
+        std::map<std::tuple<int, int, int, int, int>, int> key;
         b->entry_class.resize(count);
         for (int32_t k = 0; k < count; ++k) {
             const HostProblem& hp = probs[k]->hp;
             const int has_inv = probs[k]->dev->ainv != nullptr ? 1 : 0;
-            const auto kk = std::make_tuple(hp.dim, hp.p, hp.precision, has_inv);
+            const auto kk = std::make_tuple(hp.dim, hp.p, hp.precision, has_inv, hp.unstructured ? 1 : 0);
             auto it = key.find(kk);
             if (it == key.end()) {
                 it = key.emplace(kk, (int)b->classes.size()).first;
@@ -388,6 +389,9 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
                 bc.cls.dim = hp.dim;
                 bc.cls.p = hp.p;
                 bc.cls.mixed = hp.precision == SNSW_PREC_MIXED;
+                // mixed precision and unstructured meshes sweep level by level
+                bc.levels_only = bc.cls.mixed || hp.unstructured;
+                bc.cls.unstructured = hp.unstructured;
                 bc.has_inv = has_inv != 0;
                 bc.cls.ticket = (int)b->classes.size();
                 b->classes.push_back(bc);
@@ -402,7 +406,7 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
             build_class_schedule(b->probs, bc.cls.members, false, bc.level_off, pairs, intra);
             HIP_OK(hipMalloc(&bc.d_pairs, std::max<size_t>(1, pairs.size()) * sizeof(int32_t)));
             HIP_OK(hipMemcpyAsync(bc.d_pairs, pairs.data(), pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            bc.tiled = !bc.cls.mixed;
+            bc.tiled = !bc.levels_only;
             for (int k : bc.cls.members) bc.tiled = bc.tiled && b->probs[k]->hp.tile > 0;
             if (bc.tiled) {
                 build_class_schedule(b->probs, bc.cls.members, true, bc.tlevel_off, pairs, intra);
@@ -417,7 +421,7 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
             const bool pinv = bc.has_inv && persistent_uses_inverse(bc.cls.dim, bc.cls.p);
             const int64_t ptotal = bc.tiled ? bc.tlevel_off.back() : bc.level_off.back();
             bc.full_blocks = persistent_grid(bc.cls.dim, bc.cls.p, pinv, ptotal, ctx->device);
-            choose(bc, !bc.cls.mixed && o.schedule == SNSW_SCHED_PERSISTENT, bc.full_blocks);
+            choose(bc, !bc.levels_only && o.schedule == SNSW_SCHED_PERSISTENT, bc.full_blocks);
         }
         HIP_OK(hipMalloc(&b->table, count * sizeof(SweepArgs)));
         HIP_OK(hipMalloc(&b->tickets, b->classes.size() * kTicketWords * sizeof(unsigned int)));
@@ -439,7 +443,7 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
                 HIP_OK(hipMemsetAsync(phi_in, 0, b->max_En * sizeof(double), s));
                 for (size_t ci = 0; ci < b->classes.size(); ++ci) {
                     BatchClass& bc = b->classes[ci];
-                    if (bc.cls.mixed) continue;
+                    if (bc.levels_only) continue;
                     const int half = std::max(1, bc.full_blocks / 2);
                     bc.tuned_ms[0] = time_class(b, ci, false, 0, true, reps, phi_in, phi_out);
                     bc.tuned_ms[1] = time_class(b, ci, true, bc.full_blocks, true, reps, phi_in, phi_out);

@@ -40,6 +40,7 @@ struct SweepClass {
     bool mixed = false;
     bool persistent = false;
     bool inv = false;                  // cached inverses (every member has them)
+    bool unstructured = false;         // members are unstructured meshes (upwind nodes from a table)
     int blocks = 0;                    // persistent grid
     int ticket = 0;                    // index into the ticket array
     const int4* pairs = nullptr;       // device schedule
@@ -69,6 +70,7 @@ struct DeviceProblem {
     double* geo = nullptr;        // [E][dim+1][n][n] column-major matrices
     double* B = nullptr;          // [F][dim][nf][nf]
     double* Bsym = nullptr;       // 3D: [F][bsym_face_stride(nf)] packed upper triangles of B
+    int32_t* nbr_nodes = nullptr; // unstructured meshes: [E][nslot][nf] neighbour node of each slot node
     double* kink_tab = nullptr;   // [K][2][nf][nf]
     int32_t* kink_idx = nullptr;
     int4* pairs = nullptr;

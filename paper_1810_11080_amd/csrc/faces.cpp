@@ -24,6 +24,8 @@
 // agree.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <string>
 
 #include "host.hpp"
 
@@ -33,9 +35,159 @@ namespace {
 constexpr int kSub3 = 4;
 }  // namespace
 
+void face_geometry(HostProblem& hp);
+
+namespace {
+
+// Element-local node numbers on slot s at per-axis order `order`, listed in
+// the slot's own face order (remaining reference axes ascending, the first
+// fastest).
+std::vector<int32_t> slot_local_nodes(int dim, int order, int s) {
+    const int a = s / 2, hi = s % 2, n1 = order + 1;
+    const int cnt = dim == 2 ? n1 : n1 * n1;
+    std::vector<int32_t> out(cnt);
+    for (int l = 0; l < cnt; ++l) {
+        int idx[3] = {0, 0, 0}, rem = l;
+        for (int b = 0; b < dim; ++b) {
+            if (b == a) continue;
+            idx[b] = rem % n1;
+            rem /= n1;
+        }
+        idx[a] = hi ? order : 0;
+        int m = 0, st = 1;
+        for (int b = 0; b < dim; ++b) { m += idx[b] * st; st *= n1; }
+        out[l] = m;
+    }
+    return out;
+}
+
+// The symmetries of the reference face as maps of face-local grid indices
+// at per-axis order n1 - 1: 2D (identity, reversal); 3D the eight maps
+// (i, j) -> (x, y) or (y, x) with x in {i, n1-1-i}, y in {j, n1-1-j}.
+int face_sym_count(int dim) { return dim == 2 ? 2 : 8; }
+int face_sym(int dim, int t, int n1, int l) {
+    if (dim == 2) return t ? n1 - 1 - l : l;
+    const int i = l % n1, j = l / n1;
+    const int x = (t & 1) ? n1 - 1 - i : i, y = (t & 2) ? n1 - 1 - j : j;
+    return (t & 4) ? y + n1 * x : x + n1 * y;
+}
+
+// Faces of an unstructured conforming mesh.  Two element slots are one face
+// when their corner control points are the same (by index).  The face's
+// minus element is the one with the smaller index (the only one on the
+// boundary); the face is parametrised like the minus element's slot,
+// mirrored (2D: reversed; 3D: its two axes exchanged) when that slot is a
+// xi_a = 0 face, so that the normal of the axis formula is the minus
+// element's outward normal.  The plus element's slot is matched to the face
+// by the face symmetry that carries every control point onto its partner.
+void unstructured_topology(HostProblem& hp) {
+    const int dim = hp.dim, r = hp.r, p = hp.p, nf = hp.nf, ns = 2 * dim;
+    const int64_t E = hp.E;
+    int Nv = 1;
+    for (int a = 0; a < dim; ++a) Nv *= r + 1;
+    const int nloc = dim == 2 ? r + 1 : (r + 1) * (r + 1);
+    std::vector<std::vector<int32_t>> cl(ns), dl(ns);
+    for (int s = 0; s < ns; ++s) {
+        cl[s] = slot_local_nodes(dim, r, s);
+        dl[s] = slot_local_nodes(dim, p, s);
+    }
+    const int nc = dim == 2 ? 2 : 4;
+    auto corner = [&](int k) {   // face-local index of corner k
+        const int R = r;
+        if (dim == 2) return k ? R : 0;
+        return (k & 1 ? R : 0) + (r + 1) * (k & 2 ? R : 0);
+    };
+    struct Key {
+        int64_t c[4];
+        bool operator<(const Key& o) const { return std::lexicographical_compare(c, c + 4, o.c, o.c + 4); }
+    };
+    std::map<Key, std::vector<std::pair<int64_t, int>>> table;
+    for (int64_t e = 0; e < E; ++e)
+        for (int s = 0; s < ns; ++s) {
+            Key k{{-1, -1, -1, -1}};
+            for (int c = 0; c < nc; ++c) k.c[c] = hp.elem_nodes[(size_t)e * Nv + cl[s][corner(c)]];
+            std::sort(k.c, k.c + nc);
+            table[k].push_back({e, s});
+        }
+    std::vector<std::vector<std::pair<int64_t, int>>> recs;
+    recs.reserve(table.size());
+    for (auto& kv : table) {
+        std::sort(kv.second.begin(), kv.second.end());
+        if (kv.second.size() > 2 || (kv.second.size() == 2 && kv.second[0].first == kv.second[1].first))
+            throw Error(SNSW_E_SHAPE, "unstructured mesh: a face is shared by more than two element slots");
+        recs.push_back(kv.second);
+    }
+    std::sort(recs.begin(), recs.end());
+    hp.F = (int64_t)recs.size();
+    hp.nslot = ns;
+    hp.f_axis.assign(hp.F, 0);
+    hp.f_minus.assign(hp.F, -1);
+    hp.f_plus.assign(hp.F, -1);
+    hp.f_ctrl.assign((size_t)hp.F * nloc * dim, 0.0);
+    hp.f_slot_minus.assign(hp.F, -1);
+    hp.f_slot_plus.assign(hp.F, -1);
+    hp.slot_face.assign((size_t)E * ns, -1);
+    hp.slot_nbr.assign((size_t)E * ns, -1);
+    hp.hf_minus.assign((size_t)E * ns, 0);
+    hp.hf_trace.assign((size_t)E * ns * nf, 0);
+    hp.hf_up_trace.assign((size_t)E * ns * nf, 0);
+    const int mirror = dim == 2 ? 1 : 4;   // face symmetry used to mirror a xi_a = 0 slot
+    for (int64_t f = 0; f < hp.F; ++f) {
+        const auto& rec = recs[f];
+        const int64_t em = rec[0].first;
+        const int sm = rec[0].second;
+        const int tm = (sm & 1) ? 0 : mirror;   // face index l <- slot index face_sym(tm, l)
+        hp.f_axis[f] = sm / 2;
+        hp.f_minus[f] = (int32_t)em;
+        hp.f_slot_minus[f] = (int8_t)sm;
+        std::vector<int64_t> ids(nloc);
+        for (int l = 0; l < nloc; ++l) {
+            ids[l] = hp.elem_nodes[(size_t)em * Nv + cl[sm][face_sym(dim, tm, r + 1, l)]];
+            for (int c = 0; c < dim; ++c) hp.f_ctrl[((size_t)f * nloc + l) * dim + c] = hp.nodes[(size_t)ids[l] * dim + c];
+        }
+        hp.slot_face[em * ns + sm] = (int32_t)f;
+        hp.hf_minus[em * ns + sm] = 1;
+        for (int l = 0; l < nf; ++l) hp.hf_trace[((size_t)em * ns + sm) * nf + l] = dl[sm][face_sym(dim, tm, p + 1, l)];
+        if (rec.size() == 1) continue;
+        const int64_t ep = rec[1].first;
+        const int sp = rec[1].second;
+        int tp = -1;
+        for (int t = 0; t < face_sym_count(dim) && tp < 0; ++t) {
+            bool ok = true;
+            for (int l = 0; l < nloc && ok; ++l)
+                ok = hp.elem_nodes[(size_t)ep * Nv + cl[sp][face_sym(dim, t, r + 1, l)]] == ids[l];
+            if (ok) tp = t;
+        }
+        if (tp < 0) throw Error(SNSW_E_SHAPE, "unstructured mesh: non-conforming face between elements " +
+                                                  std::to_string(em) + " and " + std::to_string(ep));
+        hp.f_plus[f] = (int32_t)ep;
+        hp.f_slot_plus[f] = (int8_t)sp;
+        hp.slot_face[ep * ns + sp] = (int32_t)f;
+        hp.slot_nbr[em * ns + sm] = (int32_t)ep;
+        hp.slot_nbr[ep * ns + sp] = (int32_t)em;
+        for (int l = 0; l < nf; ++l) hp.hf_trace[((size_t)ep * ns + sp) * nf + l] = dl[sp][face_sym(dim, tp, p + 1, l)];
+        for (int l = 0; l < nf; ++l) {
+            hp.hf_up_trace[((size_t)em * ns + sm) * nf + l] = hp.hf_trace[((size_t)ep * ns + sp) * nf + l];
+            hp.hf_up_trace[((size_t)ep * ns + sp) * nf + l] = hp.hf_trace[((size_t)em * ns + sm) * nf + l];
+        }
+    }
+    for (int32_t v : hp.slot_face)
+        if (v < 0) throw Error(SNSW_E_SHAPE, "unstructured mesh: an element slot has no face");
+    hp.slot_nodes.assign((size_t)ns * nf, 0);
+    for (int s = 0; s < ns; ++s)
+        for (int l = 0; l < nf; ++l) hp.slot_nodes[(size_t)s * nf + l] = dl[s][l];
+}
+
+}  // namespace
+
 void build_faces(HostProblem& hp) {
     const int dim = hp.dim, r = hp.r, p = hp.p;
     const int nf = hp.nf;
+    if (hp.unstructured) {
+        unstructured_topology(hp);
+        face_geometry(hp);
+        return;
+    }
     int L[3] = {1, 1, 1};
     for (int a = 0; a < dim; ++a) L[a] = r * hp.nx[a] + 1;
     const int nloc = dim == 2 ? r + 1 : (r + 1) * (r + 1);
@@ -119,6 +271,15 @@ void build_faces(HostProblem& hp) {
         }
     }
 
+    face_geometry(hp);
+}
+
+// Normal moments B_k, int N_k and the 3D composite-rule tables of every face
+// (from f_axis and f_ctrl).
+void face_geometry(HostProblem& hp) {
+    const int dim = hp.dim, r = hp.r, p = hp.p;
+    const int nf = hp.nf;
+    const int nloc = dim == 2 ? r + 1 : (r + 1) * (r + 1);
     // normal moments B_k and int N_k with an exact Gauss rule
     std::vector<double> geo_nodes(r + 1);
     for (int a = 0; a <= r; ++a) geo_nodes[a] = (double)a / r;

@@ -45,10 +45,20 @@ void tensor_tables(int dim, const std::vector<double>& nodes, const std::vector<
     }
 }
 
-// Control points of element e of the structured lattice, [(r+1)^dim][dim],
-// local order a + (r+1) (b + (r+1) c).
+// Control points of element e, [(r+1)^dim][dim], local order
+// a + (r+1) (b + (r+1) c): from the structured lattice, or from the element's
+// control-point list on unstructured meshes.
 void element_ctrl(const HostProblem& hp, int64_t e, double* xe) {
     const int dim = hp.dim, r = hp.r;
+    if (hp.unstructured) {
+        int Nv = 1;
+        for (int a = 0; a < dim; ++a) Nv *= r + 1;
+        for (int m = 0; m < Nv; ++m) {
+            const int64_t id = hp.elem_nodes[(size_t)e * Nv + m];
+            for (int c = 0; c < dim; ++c) xe[m * dim + c] = hp.nodes[(size_t)id * dim + c];
+        }
+        return;
+    }
     int L[3] = {1, 1, 1};
     for (int a = 0; a < dim; ++a) L[a] = r * hp.nx[a] + 1;
     int ei[3] = {0, 0, 0};

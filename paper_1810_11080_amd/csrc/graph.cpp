@@ -210,9 +210,15 @@ void build_direction(const HostProblem& hp, int d, const std::vector<double>& Mi
         const bool interior = hp.f_minus[f] >= 0 && hp.f_plus[f] >= 0;
         uint8_t drop = 0;
         if (interior) {
+            // a face along the direction (int |g| at most tau |int N|) couples
+            // nothing; otherwise a side whose measure is at most tau int |g|
+            // is dropped
             const double mabs = mp + mm;
-            if (mm <= kTau * mabs) { drop |= 1; mm = 0.0; }
-            if (mp <= kTau * mabs) { drop |= 2; mp = 0.0; }
+            double na = 0.0;
+            for (int k = 0; k < dim; ++k) na += hp.Nint[(size_t)f * dim + k] * hp.Nint[(size_t)f * dim + k];
+            const bool tangential = mabs <= kTau * std::sqrt(na);
+            if (tangential || mm <= kTau * mabs) { drop |= 1; mm = 0.0; }
+            if (tangential || mp <= kTau * mabs) { drop |= 2; mp = 0.0; }
         }
         g.face_drop[f] = drop;
         if (cls == FC_KINK) {
@@ -248,9 +254,7 @@ void build_direction(const HostProblem& hp, int d, const std::vector<double>& Mi
                 if (hp.weighting == SNSW_WEIGHT_FACE) {
                     for (int i = 0; i < nf * nf; ++i) z = std::max(z, std::fabs(Pin[i]));
                 } else {
-                    const int a = hp.f_axis[f];
-                    const int slot = 2 * a + (side == 0 ? 1 : 0);
-                    const int* tn = &hp.slot_nodes[slot * nf];
+                    const int32_t* tn = slot_trace(hp, down, face_slot(hp, f, side));
                     const int n = hp.n;
                     const double* Mi = &Minv[(size_t)down * n * n];
                     const double st = hp.sigma_t[down];
@@ -463,7 +467,7 @@ void build_schedule(HostProblem& hp) {
             for (int s = 0; s < ns; ++s) {
                 const int32_t f = hp.slot_face[(size_t)e * ns + s];
                 const uint8_t fc = g.face_class[f];
-                const bool minus_side = (s & 1) != 0;
+                const bool minus_side = slot_is_minus(hp, e, s);
                 // drop bits: 1 = P_minus side, 2 = P_plus side
                 const bool in_dropped = (g.face_drop[f] & (minus_side ? 1 : 2)) != 0;
                 const bool out_dropped = (g.face_drop[f] & (minus_side ? 2 : 1)) != 0;

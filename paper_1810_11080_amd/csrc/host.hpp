@@ -75,7 +75,10 @@ struct HostProblem {
     int weighting = 1, exact_max = 10, precision = 0, bc = 0, nthreads = 1, schedule = 0, cache_inverse = 0;
     int inverse_cached = 0;   // set by the device upload
     double psi_inc = 0.0;
-    std::vector<double> lattice;              // [L][dim]
+    std::vector<double> lattice;              // [L][dim] (structured meshes)
+    bool unstructured = false;                // mesh given as element control-point lists
+    std::vector<double> nodes;                // [n_nodes][dim] (unstructured)
+    std::vector<int64_t> elem_nodes;          // [E][(r+1)^dim] (unstructured)
     std::vector<double> omega, w;             // [D][3], [D]
     std::vector<double> sigma_t, sigma_s, q;  // [E], [E], [E][n] (isotropic source)
     std::vector<double> q_dir;                // [D][E][n] direction-dependent source, or empty
@@ -91,6 +94,13 @@ struct HostProblem {
     FaceNormalData fnd;
     std::vector<int32_t> slot_face, slot_nbr; // [E][nslot]
     std::vector<int32_t> slot_nodes;          // [nslot][nf]
+    // unstructured meshes: per element slot whether the element is its
+    // face's minus side, and the element's / the neighbour's DG nodes listed
+    // in the face's (s, t) order ([E][nslot][nf]); per face the slot of its
+    // minus and plus element
+    std::vector<uint8_t> hf_minus;
+    std::vector<int32_t> hf_trace, hf_up_trace;
+    std::vector<int8_t> f_slot_minus, f_slot_plus;
     std::vector<DirGraph> graphs;             // [D]
     // combined schedule
     std::vector<int64_t> level_off;           // [L+1]
@@ -106,6 +116,20 @@ struct HostProblem {
     int64_t n_kinks = 0;
     double setup_seconds = 0.0;
 };
+
+// Whether element e is the minus side of the face on its slot s.
+inline bool slot_is_minus(const HostProblem& hp, int64_t e, int s) {
+    return hp.unstructured ? hp.hf_minus[(size_t)e * hp.nslot + s] != 0 : (s & 1) != 0;
+}
+// Element e's DG nodes on slot s, in the face's (s, t) order.
+inline const int32_t* slot_trace(const HostProblem& hp, int64_t e, int s) {
+    return hp.unstructured ? &hp.hf_trace[((size_t)e * hp.nslot + s) * hp.nf] : &hp.slot_nodes[(size_t)s * hp.nf];
+}
+// Slot of face f on its minus (side 0) or plus (side 1) element.
+inline int face_slot(const HostProblem& hp, int64_t f, int side) {
+    if (hp.unstructured) return side == 0 ? hp.f_slot_minus[f] : hp.f_slot_plus[f];
+    return 2 * hp.f_axis[f] + (side == 0 ? 1 : 0);
+}
 
 // geometry.cpp: element matrices; throws Error(SNSW_E_BAD_JACOBIAN)
 void build_geometry(HostProblem& hp);

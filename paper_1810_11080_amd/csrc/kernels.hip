@@ -154,7 +154,19 @@ __device__ __forceinline__ SweepArgs load_args(const SweepArgs* table, int k) {
     a.ainv = c->ainv;
     a.Bsym = c->Bsym;
     a.rhs_dir = c->rhs_dir;
+    a.nbr_nodes = c->nbr_nodes;
     return a;
+}
+
+// Node of the upwind neighbour that lies on the point of local node b of
+// slot s of element e: on a lattice the opposite slot's node of the same
+// local index; on an unstructured mesh read from the table (its faces meet
+// in any orientation).
+template <int DIM, int P, bool U>
+__device__ __forceinline__ int up_node(const SweepArgs& args, int e, int s, int b) {
+    using S = Shape<DIM, P>;
+    if constexpr (U) return args.nbr_nodes[((size_t)e * S::NS + s) * S::NF + b];
+    else return S::tn(s ^ 1, b);
 }
 
 // Volume source of row `row` of pair (e, d): the direction-independent
@@ -170,7 +182,7 @@ __device__ __forceinline__ double source_row(const SweepArgs& args, int e, int d
 // Assembles row `row` of A and b for pair (e, d).  With DEFER, inflow through
 // kept couplings (read from this sweep's flux) is left out of b and the slots
 // that need it are returned in *kept; lagged and boundary inflow are added.
-template <int DIM, int P, bool DEFER, bool KEEP_PIN = false>
+template <int DIM, int P, bool DEFER, bool KEEP_PIN = false, bool U = false>
 __device__ __forceinline__ void assemble_row(const SweepArgs& args, int4 pr, int row, double (&a)[Shape<DIM, P>::N],
                                              double& rhs, unsigned& kept, int (&krow)[2 * DIM],
                                              double (*pk)[Shape<DIM, P>::NF] = nullptr) {
@@ -250,7 +262,7 @@ __device__ __forceinline__ void assemble_row(const SweepArgs& args, int4 pr, int
             if (nb >= 0) {
                 const double* up = (lagged ? args.psi_prev : args.psi_cur) + ((size_t)d * args.E + nb) * N;
 #pragma unroll
-                for (int b = 0; b < NF; ++b) rhs += pin[b] * up[S::tn(s ^ 1, b)];
+                for (int b = 0; b < NF; ++b) rhs += pin[b] * up[up_node<DIM, P, U>(args, e, s, b)];
             } else {
 #pragma unroll
                 for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
@@ -272,7 +284,7 @@ __device__ __forceinline__ void wave_sync() {
 // row is rounded to FP32, factored A32 = L U in FP32, x0 = (LU)^{-1} b in
 // FP32; then one correction with the FP64 operator, r = b - A x0 (FP64),
 // x = x0 + (LU)^{-1} r.
-template <int DIM, int P, bool MIXED>
+template <int DIM, int P, bool MIXED, bool U = false>
 __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(const SweepArgs* table, const int4* pairs,
                                                                  int64_t begin, int64_t count, int problem) {
     using S = Shape<DIM, P>;
@@ -298,7 +310,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(const SweepArgs*
         d = (int)((unsigned)pr.y & kDirMask);
         unsigned kept;
         int krow[2 * DIM];
-        assemble_row<DIM, P, false>(args, pr, row, a, rhs, kept, krow);
+        assemble_row<DIM, P, false, false, U>(args, pr, row, a, rhs, kept, krow);
     } else {
 #pragma unroll
         for (int j = 0; j < N; ++j) a[j] = (j == row) ? 1.0 : 0.0;
@@ -1132,7 +1144,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
 // invert it in place by Gauss-Jordan without pivoting (A + A^T is positive
 // definite), pivot rows broadcast through LDS; A^{-1} is stored at
 // ainv[(d E + e) stride + InvLayout::at(i, j)].
-template <int DIM, int P>
+template <int DIM, int P, bool U = false>
 __global__ void __launch_bounds__(64 * kWaves) factor_kernel(const SweepArgs* table, const int4* pairs, int64_t count,
                                                             double* ainv) {
     using S = Shape<DIM, P>;
@@ -1153,7 +1165,7 @@ __global__ void __launch_bounds__(64 * kWaves) factor_kernel(const SweepArgs* ta
     double rhs;
     unsigned kept;
     int krow[2 * DIM];
-    assemble_row<DIM, P, true>(args, prs, row, m, rhs, kept, krow);
+    assemble_row<DIM, P, true, false, U>(args, prs, row, m, rhs, kept, krow);
     double* L = &lds[wave][in_group ? grp : 0][0];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -1188,7 +1200,7 @@ __global__ void __launch_bounds__(64 * kWaves) factor_kernel(const SweepArgs* ta
 // b of row `row` of pair pr: source plus every inflow term (kept couplings
 // read this sweep's flux, lagged ones the previous sweep's, boundary faces
 // psi_inc).
-template <int DIM, int P, bool DEFER = false>
+template <int DIM, int P, bool DEFER = false, bool U = false>
 __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int row, unsigned* kept_out = nullptr) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, NF = S::NF, NS = S::NS;
@@ -1232,7 +1244,7 @@ __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int
         if (nb >= 0) {
             const double* up = (lagged ? args.psi_prev : args.psi_cur) + ((size_t)d * args.E + nb) * N;
 #pragma unroll
-            for (int b = 0; b < NF; ++b) rhs += pin[b] * up[S::tn(s ^ 1, b)];
+            for (int b = 0; b < NF; ++b) rhs += pin[b] * up[up_node<DIM, P, U>(args, e, s, b)];
         } else {
 #pragma unroll
             for (int b = 0; b < NF; ++b) rhs += pin[b] * args.psi_inc;
@@ -1249,7 +1261,7 @@ __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int
 // dim partial sums of face-local row la meet in LDS (cf, [NS][dim * nf] per
 // pair) and are added to the rows on the face.  Same sums as inflow_rhs up to
 // their order.
-template <int DIM, int P>
+template <int DIM, int P, bool U = false>
 __device__ __forceinline__ double inflow_rhs_coop(const SweepArgs& args, int4 pr, int row, bool in_group,
                                                   double (*cf)[DIM * Shape<DIM, P>::NF]) {
     using S = Shape<DIM, P>;
@@ -1277,7 +1289,7 @@ __device__ __forceinline__ double inflow_rhs_coop(const SweepArgs& args, int4 pr
             if (a == 0) {
                 const double* Ti = args.kink_tab + (size_t)kr * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + la * NF;
 #pragma unroll
-                for (int b = 0; b < NF; ++b) t += Ti[b] * (nb >= 0 ? up[S::tn(s ^ 1, b)] : args.psi_inc);
+                for (int b = 0; b < NF; ++b) t += Ti[b] * (nb >= 0 ? up[up_node<DIM, P, U>(args, e, s, b)] : args.psi_inc);
             }
         } else {
             const int fc = args.slot_face[(size_t)e * NS + s];
@@ -1285,16 +1297,17 @@ __device__ __forceinline__ double inflow_rhs_coop(const SweepArgs& args, int4 pr
                 // row la of the symmetric moment matrix from its packed upper
                 // triangle (44 % fewer bytes than the full matrix)
                 constexpr int NT = NF * (NF + 1) / 2;
-                const double* Bs = args.Bsym + (size_t)fc * bsym_face_stride(NF) + a * NT;
+                const double* Bs = args.Bsym + (size_t)(fc * bsym_face_stride(NF) + a * NT);
 #pragma unroll
                 for (int b = 0; b < NF; ++b) {
                     const int i = la < b ? la : b, j = la < b ? b : la;
-                    t += Bs[i * NF - (i * (i - 1)) / 2 + (j - i)] * (nb >= 0 ? up[S::tn(s ^ 1, b)] : args.psi_inc);
+                    t += Bs[i * NF - (i * (i - 1)) / 2 + (j - i)] *
+                         (nb >= 0 ? up[up_node<DIM, P, U>(args, e, s, b)] : args.psi_inc);
                 }
             } else {
                 const double* Bf = args.B + ((size_t)fc * DIM + a) * NF * NF + la * NF;
 #pragma unroll
-                for (int b = 0; b < NF; ++b) t += Bf[b] * (nb >= 0 ? up[S::tn(s ^ 1, b)] : args.psi_inc);
+                for (int b = 0; b < NF; ++b) t += Bf[b] * (nb >= 0 ? up[up_node<DIM, P, U>(args, e, s, b)] : args.psi_inc);
             }
             t *= (s & 1) ? -oa : oa;   // P_in = -(outward normal) moments
         }
@@ -1321,7 +1334,7 @@ __device__ __forceinline__ double inflow_rhs_coop(const SweepArgs& args, int4 pr
 // of the 3D level sweep); then the contraction reads the trace from LDS.  The
 // same sums in the same order as inflow_rhs_coop.  Not used for nf = 16,
 // where holding the staged slots costs more registers than it saves.
-template <int DIM, int P>
+template <int DIM, int P, bool U = false>
 __device__ __forceinline__ double inflow_rhs_staged(const SweepArgs& args, int4 pr, int row, bool in_group,
                                                   double (*cf)[DIM * Shape<DIM, P>::NF],
                                                   double (*uf)[Shape<DIM, P>::NF]) {
@@ -1348,7 +1361,7 @@ __device__ __forceinline__ double inflow_rhs_staged(const SweepArgs& args, int4 
         if (a == 0) {
             const int nb = args.slot_nbr[(size_t)e * NS + s];
             const double* up = (lagged ? args.psi_prev : args.psi_cur) + ((size_t)d * args.E + (nb >= 0 ? nb : 0)) * N;
-            uf[s][la] = nb >= 0 ? up[S::tn(s ^ 1, la)] : args.psi_inc;
+            uf[s][la] = nb >= 0 ? up[up_node<DIM, P, U>(args, e, s, la)] : args.psi_inc;
         }
     }
     wave_sync();
@@ -1366,7 +1379,7 @@ __device__ __forceinline__ double inflow_rhs_staged(const SweepArgs& args, int4 
         } else {
             if (args.Bsym) {
                 constexpr int NT = NF * (NF + 1) / 2;
-                const double* Bs = args.Bsym + (size_t)fcs[s] * bsym_face_stride(NF) + a * NT;
+                const double* Bs = args.Bsym + (size_t)(fcs[s] * bsym_face_stride(NF) + a * NT);
 #pragma unroll
                 for (int b = 0; b < NF; ++b) {
                     const int i = la < b ? la : b, j = la < b ? b : la;
@@ -1397,7 +1410,7 @@ __device__ __forceinline__ double inflow_rhs_staged(const SweepArgs& args, int4 
 
 // One launch per level with cached inverses: b assembled per row, shared
 // through the wavefront's LDS, x = A^{-1} b.
-template <int DIM, int P>
+template <int DIM, int P, bool U = false>
 __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* table, const int4* pairs,
                                                               int64_t begin, int64_t count, int problem) {
     using S = Shape<DIM, P>;
@@ -1424,9 +1437,9 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     const double* Ab = args.ainv + ((size_t)d * args.E + e) * IL::kStride;
     auto rhs_of = [&]() {
         const int g = in_group ? grp : 0;
-        if constexpr (kStage) return inflow_rhs_staged<DIM, P>(args, prs, row, in_group, cfl[wave][g], ufl[wave][g]);
-        else if constexpr (kCoop) return inflow_rhs_coop<DIM, P>(args, prs, row, in_group, cfl[wave][g]);
-        else return inflow_rhs<DIM, P>(args, prs, row);
+        if constexpr (kStage) return inflow_rhs_staged<DIM, P, U>(args, prs, row, in_group, cfl[wave][g], ufl[wave][g]);
+        else if constexpr (kCoop) return inflow_rhs_coop<DIM, P, U>(args, prs, row, in_group, cfl[wave][g]);
+        else return inflow_rhs<DIM, P, false, U>(args, prs, row);
     };
     double* L = &lds[wave][in_group ? grp : 0][0];
     double x = 0.0;
@@ -1778,7 +1791,7 @@ sweep_persistent_staged(PersistArgs pa) {
                     }
                 } else {
                     constexpr int NT = NF * (NF + 1) / 2;
-                    const double* Bs = args.Bsym + (size_t)fcs[s] * bsym_face_stride(NF) + a * NT;
+                    const double* Bs = args.Bsym + (size_t)(fcs[s] * bsym_face_stride(NF) + a * NT);
 #pragma unroll
                     for (int b = 0; b < NF; ++b) {
                         const int i = la < b ? la : b, jj = la < b ? b : la;
@@ -1845,21 +1858,30 @@ __global__ void fill_sentinel_kernel(const SweepArgs* table) {
         p[t] = kSentinel;
 }
 
-template <int DIM, int P>
-void launch_tpl(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem, bool mixed,
-                bool inv, hipStream_t stream) {
+template <int DIM, int P, bool U>
+void launch_tpl_u(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem, bool mixed,
+                  bool inv, hipStream_t stream) {
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
     if (inv)
-        hipLaunchKernelGGL((sweep_level_inv<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, table,
+        hipLaunchKernelGGL((sweep_level_inv<DIM, P, U>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, table,
                            pairs, begin, count, problem);
     else if (mixed)
-        hipLaunchKernelGGL((sweep_level_fp64<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
+        hipLaunchKernelGGL((sweep_level_fp64<DIM, P, true, U>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
                            table, pairs, begin, count, problem);
     else
-        hipLaunchKernelGGL((sweep_level_fp64<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
-                           table, pairs, begin, count, problem);
+        hipLaunchKernelGGL((sweep_level_fp64<DIM, P, false, U>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                           stream, table, pairs, begin, count, problem);
+}
+
+// unstructured: the upwind neighbour's nodes come from the table (the
+// kernels of lattice meshes compute them)
+template <int DIM, int P>
+void launch_tpl(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem, bool mixed,
+                bool inv, bool unstructured, hipStream_t stream) {
+    if (unstructured) launch_tpl_u<DIM, P, true>(table, pairs, begin, count, problem, mixed, inv, stream);
+    else launch_tpl_u<DIM, P, false>(table, pairs, begin, count, problem, mixed, inv, stream);
 }
 
 // groups of 4 or 16 lanes exchange values by DPP, the others through LDS
@@ -1910,12 +1932,17 @@ void launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, hipStream_t 
 }
 
 template <int DIM, int P>
-void launch_factor_tpl(const SweepArgs* table, const int4* pairs, int64_t count, double* ainv, hipStream_t stream) {
+void launch_factor_tpl(const SweepArgs* table, const int4* pairs, int64_t count, double* ainv, bool unstructured,
+                       hipStream_t stream) {
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
-    hipLaunchKernelGGL((factor_kernel<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, table, pairs,
-                       count, ainv);
+    if (unstructured)
+        hipLaunchKernelGGL((factor_kernel<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
+                           table, pairs, count, ainv);
+    else
+        hipLaunchKernelGGL((factor_kernel<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
+                           table, pairs, count, ainv);
 }
 
 template <int DIM, int P>
@@ -2014,16 +2041,17 @@ __global__ void residual_kernel(int64_t len, const double* __restrict__ a, const
 
 }  // namespace
 
-void launch_sweep_level(int dim, int p, bool mixed, bool inv, const SweepArgs* table, const int4* pairs,
-                        int64_t begin, int64_t count, int problem, hipStream_t stream) {
+void launch_sweep_level(int dim, int p, bool mixed, bool inv, bool unstructured, const SweepArgs* table,
+                        const int4* pairs, int64_t begin, int64_t count, int problem, hipStream_t stream) {
+    const bool u = unstructured;
     if (dim == 2) {
-        if (p == 1) launch_tpl<2, 1>(table, pairs, begin, count, problem, mixed, inv, stream);
-        else if (p == 2) launch_tpl<2, 2>(table, pairs, begin, count, problem, mixed, inv, stream);
-        else launch_tpl<2, 3>(table, pairs, begin, count, problem, mixed, inv, stream);
+        if (p == 1) launch_tpl<2, 1>(table, pairs, begin, count, problem, mixed, inv, u, stream);
+        else if (p == 2) launch_tpl<2, 2>(table, pairs, begin, count, problem, mixed, inv, u, stream);
+        else launch_tpl<2, 3>(table, pairs, begin, count, problem, mixed, inv, u, stream);
     } else {
-        if (p == 1) launch_tpl<3, 1>(table, pairs, begin, count, problem, mixed, inv, stream);
-        else if (p == 2) launch_tpl<3, 2>(table, pairs, begin, count, problem, mixed, inv, stream);
-        else launch_tpl<3, 3>(table, pairs, begin, count, problem, mixed, inv, stream);
+        if (p == 1) launch_tpl<3, 1>(table, pairs, begin, count, problem, mixed, inv, u, stream);
+        else if (p == 2) launch_tpl<3, 2>(table, pairs, begin, count, problem, mixed, inv, u, stream);
+        else launch_tpl<3, 3>(table, pairs, begin, count, problem, mixed, inv, u, stream);
     }
 }
 
@@ -2032,16 +2060,17 @@ int64_t ainv_block_stride(int dim, int p) {
     return p == 1 ? InvLayout<3, 1>::kStride : p == 2 ? InvLayout<3, 2>::kStride : InvLayout<3, 3>::kStride;
 }
 
-void launch_factor(int dim, int p, const SweepArgs* table, const int4* pairs, int64_t count, double* ainv,
-                   hipStream_t stream) {
+void launch_factor(int dim, int p, bool unstructured, const SweepArgs* table, const int4* pairs, int64_t count,
+                   double* ainv, hipStream_t stream) {
+    const bool u = unstructured;
     if (dim == 2) {
-        if (p == 1) launch_factor_tpl<2, 1>(table, pairs, count, ainv, stream);
-        else if (p == 2) launch_factor_tpl<2, 2>(table, pairs, count, ainv, stream);
-        else launch_factor_tpl<2, 3>(table, pairs, count, ainv, stream);
+        if (p == 1) launch_factor_tpl<2, 1>(table, pairs, count, ainv, u, stream);
+        else if (p == 2) launch_factor_tpl<2, 2>(table, pairs, count, ainv, u, stream);
+        else launch_factor_tpl<2, 3>(table, pairs, count, ainv, u, stream);
     } else {
-        if (p == 1) launch_factor_tpl<3, 1>(table, pairs, count, ainv, stream);
-        else if (p == 2) launch_factor_tpl<3, 2>(table, pairs, count, ainv, stream);
-        else launch_factor_tpl<3, 3>(table, pairs, count, ainv, stream);
+        if (p == 1) launch_factor_tpl<3, 1>(table, pairs, count, ainv, u, stream);
+        else if (p == 2) launch_factor_tpl<3, 2>(table, pairs, count, ainv, u, stream);
+        else launch_factor_tpl<3, 3>(table, pairs, count, ainv, u, stream);
     }
 }
 

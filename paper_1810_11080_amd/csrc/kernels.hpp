@@ -36,6 +36,9 @@ struct SweepArgs {
                               // row, nf (nf + 1) / 2 entries (null in 2D)
     const double* rhs_dir;    // [D][E][n] fixed right-hand side per pair: M q_d (direction-dependent
                               // source) + tabulated boundary inflow; null when the problem has neither
+    const int32_t* nbr_nodes; // unstructured meshes: [E][2 dim][nf] the upwind neighbour's node on the
+                              // point of each slot node (slot order); null on a lattice, where it is
+                              // the opposite slot's node of the same local index
 };
 
 // Doubles per face in the packed face-moment array Bsym: dim packed upper
@@ -77,15 +80,16 @@ int persistent_blocks_per_cu(int dim, int p, bool inv);
 bool persistent_uses_inverse(int dim, int p);
 // Launches the level-sweep kernel over schedule entries [begin, begin+count)
 // (begin and count multiples of G); inv: x = A^{-1} b with cached inverses;
-// problem: table index of every entry, or -1 when entries name their problem.
-void launch_sweep_level(int dim, int p, bool mixed, bool inv, const SweepArgs* table, const int4* pairs,
-                        int64_t begin, int64_t count, int problem, hipStream_t stream);
+// unstructured: upwind nodes from SweepArgs::nbr_nodes; problem: table index
+// of every entry, or -1 when entries name their problem.
+void launch_sweep_level(int dim, int p, bool mixed, bool inv, bool unstructured, const SweepArgs* table,
+                        const int4* pairs, int64_t begin, int64_t count, int problem, hipStream_t stream);
 // Doubles per pair in the cached A^{-1} array (n^2, or n^2 + 1 where blocks
 // are padded to a 16-byte multiple).
 int64_t ainv_block_stride(int dim, int p);
 // Computes and stores A^{-1} of schedule entries [0, count) of one problem.
-void launch_factor(int dim, int p, const SweepArgs* table, const int4* pairs, int64_t count, double* ainv,
-                   hipStream_t stream);
+void launch_factor(int dim, int p, bool unstructured, const SweepArgs* table, const int4* pairs, int64_t count,
+                   double* ainv, hipStream_t stream);
 
 // Start of a sweep, for problems [0, count) of the table: swaps psi_cur and
 // psi_prev of each entry, zeroes the ticket counters of n_tickets schedules

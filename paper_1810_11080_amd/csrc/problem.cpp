@@ -167,12 +167,29 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
         if (desc->precision == SNSW_PREC_MIXED && hp.schedule == SNSW_SCHED_PERSISTENT)
             throw Error(SNSW_E_UNSUPPORTED, "mixed precision runs on the LEVELS schedule");
 
-        // lattice
-        if (!desc->lattice) throw Error(SNSW_E_INVALID_ARG, "lattice is NULL");
-        int64_t Lp = 1;
-        for (int a = 0; a < hp.dim; ++a) Lp *= (int64_t)hp.r * hp.nx[a] + 1;
-        hp.lattice.assign(desc->lattice, desc->lattice + Lp * hp.dim);
-        check_finite(hp.lattice.data(), hp.lattice.size(), "lattice");
+        // mesh: structured lattice or element control-point lists
+        if (desc->elem_nodes) {
+            hp.unstructured = true;
+            for (int a = 1; a < hp.dim; ++a)
+                if (hp.nx[a] != 1) throw Error(SNSW_E_SHAPE, "unstructured mesh: nx[1] (and nx[2]) must be 1");
+            if (!desc->nodes || desc->n_nodes < 1) throw Error(SNSW_E_INVALID_ARG, "unstructured mesh: no nodes");
+            if (desc->schedule == SNSW_SCHED_PERSISTENT)
+                throw Error(SNSW_E_UNSUPPORTED, "unstructured meshes sweep on the LEVELS schedule");
+            hp.schedule = SNSW_SCHED_LEVELS;
+            int64_t Nv = 1;
+            for (int a = 0; a < hp.dim; ++a) Nv *= hp.r + 1;
+            hp.nodes.assign(desc->nodes, desc->nodes + desc->n_nodes * hp.dim);
+            check_finite(hp.nodes.data(), hp.nodes.size(), "nodes");
+            hp.elem_nodes.assign(desc->elem_nodes, desc->elem_nodes + hp.E * Nv);
+            for (int64_t id : hp.elem_nodes)
+                if (id < 0 || id >= desc->n_nodes) throw Error(SNSW_E_INVALID_ARG, "elem_nodes index out of range");
+        } else {
+            if (!desc->lattice) throw Error(SNSW_E_INVALID_ARG, "lattice is NULL");
+            int64_t Lp = 1;
+            for (int a = 0; a < hp.dim; ++a) Lp *= (int64_t)hp.r * hp.nx[a] + 1;
+            hp.lattice.assign(desc->lattice, desc->lattice + Lp * hp.dim);
+            check_finite(hp.lattice.data(), hp.lattice.size(), "lattice");
+        }
         // quadrature
         if (desc->sn_order > 0) {
             if (desc->sn_order % 2) throw Error(SNSW_E_INVALID_ARG, "sn_order must be even");
@@ -204,7 +221,8 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
         build_schedule(hp);
         build_fixed_rhs(hp);
         // tiles of T x T elements per persistent batch for the DPP shapes
-        if (hp.dim == 2 && (hp.n == 16 || hp.n == 4)) build_tiled_schedule(hp, hp.n == 16 ? 2 : 4);
+        if (hp.dim == 2 && (hp.n == 16 || hp.n == 4) && !hp.unstructured)
+            build_tiled_schedule(hp, hp.n == 16 ? 2 : 4);
         hp.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (ctx->device >= 0) {
             try {

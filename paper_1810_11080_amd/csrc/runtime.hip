@@ -147,7 +147,96 @@ SweepArgs make_args(const snsw_problem* prob, int cur) {
     a.ainv = dp->ainv;
     a.Bsym = dp->Bsym;
     a.rhs_dir = hp.rhs_fixed.empty() ? nullptr : dp->rhs_dir;
+    a.nbr_nodes = dp->nbr_nodes;
     return a;
+}
+
+// Face data of an unstructured mesh in the layout the sweep kernels read on
+// a lattice, one entry per element slot, in the element's own slot order
+// (local index la of slot s = remaining reference axes ascending):
+//  * B [E*nslot][dim][nf][nf]: the face's normal moments, rows and columns
+//    permuted from the face's node order to the slot's, times the sign that
+//    makes (s odd ? 1 : -1) B the moments of the element's outward normal
+//    (the kernels' convention, where odd slots are the minus side);
+//  * slot_face[e][s] = e*nslot + s;
+//  * kink rows: every row of a (face, direction) with a sign change becomes
+//    two rows, 2R + [element is the minus side], each holding its element's
+//    inflow block in half (s & 1) and its outflow block in the other half
+//    (the halves the kernels read for a slot of that parity), and the
+//    schedule's kink indices are remapped to them;
+//  * nbr_nodes [E*nslot][nf]: the neighbour's DG node on the same point as
+//    local index la of the slot.
+void unstructured_face_view(const HostProblem& hp, std::vector<double>& B, std::vector<int32_t>& slot_face,
+                            std::vector<double>& kink, std::vector<int32_t>& kink_idx, std::vector<int32_t>& nbr) {
+    const int ns = hp.nslot, nf = hp.nf, dim = hp.dim;
+    const int64_t E = hp.E;
+    // face-order index of each local index of every element slot
+    std::vector<int32_t> pos((size_t)E * ns * nf);
+    for (int64_t e = 0; e < E; ++e)
+        for (int s = 0; s < ns; ++s) {
+            const int32_t* tr = slot_trace(hp, e, s);
+            for (int la = 0; la < nf; ++la) {
+                int l = -1;
+                for (int k = 0; k < nf; ++k)
+                    if (tr[k] == hp.slot_nodes[(size_t)s * nf + la]) l = k;
+                if (l < 0) throw Error(SNSW_E_STATE, "unstructured mesh: slot node map");
+                pos[((size_t)e * ns + s) * nf + la] = l;
+            }
+        }
+    B.assign((size_t)E * ns * dim * nf * nf, 0.0);
+    slot_face.assign((size_t)E * ns, 0);
+    nbr.assign((size_t)E * ns * nf, 0);
+    for (int64_t e = 0; e < E; ++e)
+        for (int s = 0; s < ns; ++s) {
+            const size_t hs = (size_t)e * ns + s;
+            slot_face[hs] = (int32_t)hs;
+            const int32_t f = hp.slot_face[hs];
+            const double sg = ((s & 1) ? 1.0 : -1.0) * (slot_is_minus(hp, e, s) ? 1.0 : -1.0);
+            const int32_t* P = &pos[hs * nf];
+            for (int a = 0; a < dim; ++a)
+                for (int i = 0; i < nf; ++i)
+                    for (int j = 0; j < nf; ++j)
+                        B[((hs * dim + a) * nf + i) * nf + j] =
+                            sg * hp.B[(((size_t)f * dim + a) * nf + P[i]) * nf + P[j]];
+            if (hp.slot_nbr[hs] >= 0)
+                for (int la = 0; la < nf; ++la) nbr[hs * nf + la] = hp.hf_up_trace[hs * nf + P[la]];
+        }
+    // kink rows per element slot
+    const size_t K = hp.kink_tab.size() / (2 * (size_t)nf * nf);
+    kink.assign(2 * K * 2 * nf * nf, 0.0);
+    kink_idx.assign(hp.kink_idx.size(), 0);
+    std::vector<uint8_t> done(2 * K, 0);
+    const size_t P4 = hp.pairs.size() / 4;
+    for (size_t t = 0; t < P4; ++t) {
+        const int32_t e = hp.pairs[4 * t], packed = hp.pairs[4 * t + 1], kb = hp.pairs[4 * t + 2];
+        if (e < 0) continue;
+        int kc = 0;
+        for (int s = 0; s < ns; ++s) {
+            const uint32_t cls = ((uint32_t)packed >> (kDirBits + 3 * s)) & 3u;
+            if (cls != SC_KINK) continue;
+            const size_t hs = (size_t)e * ns + s;
+            const bool minus = slot_is_minus(hp, e, s);
+            const int32_t R = hp.kink_idx[(size_t)kb + kc];
+            const size_t row = 2 * (size_t)R + (minus ? 1 : 0);
+            kink_idx[(size_t)kb + kc] = (int32_t)row;
+            ++kc;
+            if (done[row]) continue;
+            done[row] = 1;
+            const double* Pp = &hp.kink_tab[(size_t)R * 2 * nf * nf];
+            const double* Pm = Pp + (size_t)nf * nf;
+            const double* Pin = minus ? Pm : Pp;
+            const double* Pout = minus ? Pp : Pm;
+            double* dst = &kink[row * 2 * nf * nf];
+            double* din = dst + ((s & 1) ? nf * nf : 0);
+            double* dout = dst + ((s & 1) ? 0 : nf * nf);
+            const int32_t* P = &pos[hs * nf];
+            for (int i = 0; i < nf; ++i)
+                for (int j = 0; j < nf; ++j) {
+                    din[i * nf + j] = Pin[P[i] * nf + P[j]];
+                    dout[i * nf + j] = Pout[P[i] * nf + P[j]];
+                }
+        }
+    }
 }
 
 void sync_entry(SweepArgs* table, int k, const snsw_problem* prob, int* entry_cur, hipStream_t s) {
@@ -188,7 +277,7 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
                 const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
                 if (prof) prof->begin(s);
-                launch_sweep_level(c.dim, c.p, c.mixed, c.inv, L.table, c.pairs, b, n, class_problem(c), s);
+                launch_sweep_level(c.dim, c.p, c.mixed, c.inv, c.unstructured, L.table, c.pairs, b, n, class_problem(c), s);
                 if (prof) prof->end(s);
             }
         }
@@ -253,15 +342,26 @@ void device_upload(snsw_problem* prob) {
         dp->geo = dupload(dp, geo, s);
         HIP_OK(hipStreamSynchronize(s));
     }
-    dp->B = dupload(dp, hp.B, s);
+    // face data as the kernels read it: per face in the face's node order on
+    // a lattice; per element slot in the element's own slot order on an
+    // unstructured mesh (see unstructured_face_view)
+    std::vector<double> uB, ukink;
+    std::vector<int32_t> uslot_face, ukink_idx, unbr;
+    if (hp.unstructured) unstructured_face_view(hp, uB, uslot_face, ukink, ukink_idx, unbr);
+    const std::vector<double>& Bdev = hp.unstructured ? uB : hp.B;
+    const int64_t Fdev = hp.unstructured ? hp.E * hp.nslot : hp.F;
+    dp->B = dupload(dp, Bdev, s);
+    if (hp.unstructured) dp->nbr_nodes = dupload(dp, unbr, s);
     if (hp.dim == 3) {
         // B_a[i][j] = int N_a phi_i phi_j is symmetric in the two face nodes:
         // the level sweeps read its packed upper triangle
         const int nf = hp.nf, nt = nf * (nf + 1) / 2, fs = bsym_face_stride(nf);
-        std::vector<double> bs((size_t)hp.F * fs, 0.0);
-        for (int64_t f = 0; f < hp.F; ++f)
+        // the kernels index the packed moments with 32-bit offsets
+        if ((double)Fdev * fs >= 2147483647.0) throw Error(SNSW_E_UNSUPPORTED, "too many faces for the 3D sweep");
+        std::vector<double> bs((size_t)Fdev * fs, 0.0);
+        for (int64_t f = 0; f < Fdev; ++f)
             for (int a = 0; a < 3; ++a) {
-                const double* Bm = &hp.B[((size_t)f * 3 + a) * nf * nf];
+                const double* Bm = &Bdev[((size_t)f * 3 + a) * nf * nf];
                 double* dst = &bs[(size_t)f * fs + a * nt];
                 for (int i = 0; i < nf; ++i)
                     for (int j = i; j < nf; ++j)
@@ -270,8 +370,8 @@ void device_upload(snsw_problem* prob) {
         dp->Bsym = dupload(dp, bs, s);
         HIP_OK(hipStreamSynchronize(s));
     }
-    dp->kink_tab = dupload(dp, hp.kink_tab, s);
-    dp->kink_idx = dupload(dp, hp.kink_idx, s);
+    dp->kink_tab = dupload(dp, hp.unstructured ? ukink : hp.kink_tab, s);
+    dp->kink_idx = dupload(dp, hp.unstructured ? ukink_idx : hp.kink_idx, s);
     {
         int4* pp = dalloc<int4>(dp, hp.pairs.size() / 4);
         HIP_OK(hipMemcpyAsync(pp, hp.pairs.data(), hp.pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -304,7 +404,7 @@ void device_upload(snsw_problem* prob) {
             HIP_OK(hipStreamSynchronize(s));
         }
     }
-    dp->slot_face = dupload(dp, hp.slot_face, s);
+    dp->slot_face = dupload(dp, hp.unstructured ? uslot_face : hp.slot_face, s);
     dp->slot_nbr = dupload(dp, hp.slot_nbr, s);
     dp->sigma_t = dupload(dp, hp.sigma_t, s);
     dp->sigma_s = dupload(dp, hp.sigma_s, s);
@@ -339,6 +439,7 @@ void device_upload(snsw_problem* prob) {
     c.dim = hp.dim;
     c.p = hp.p;
     c.mixed = hp.precision == SNSW_PREC_MIXED;
+    c.unstructured = hp.unstructured;
     c.persistent = hp.schedule == SNSW_SCHED_PERSISTENT;
     c.inv = dp->ainv != nullptr && (!c.persistent || persistent_uses_inverse(hp.dim, hp.p));
     c.ticket = 0;
@@ -361,7 +462,7 @@ void device_upload(snsw_problem* prob) {
         HIP_OK(hipMemcpyAsync(dp->table, &a, sizeof(a), hipMemcpyHostToDevice, s));
     }
     if (dp->ainv) {
-        launch_factor(hp.dim, hp.p, dp->table, dp->pairs, hp.level_off.back(), dp->ainv, s);
+        launch_factor(hp.dim, hp.p, hp.unstructured, dp->table, dp->pairs, hp.level_off.back(), dp->ainv, s);
         HIP_OK(hipGetLastError());
     }
     HIP_OK(hipStreamSynchronize(s));
@@ -395,7 +496,8 @@ void device_release(snsw_problem* prob) noexcept {
     (void)hipSetDevice(dp->device);
     (void)hipStreamSynchronize(dp->stream);
     dp->prof.release();
-    void* ptrs[] = {dp->geo, dp->B, dp->Bsym, dp->kink_tab, dp->kink_idx, dp->pairs, dp->tpairs, dp->tintra, dp->tslots,
+    void* ptrs[] = {dp->geo, dp->B, dp->Bsym, dp->nbr_nodes, dp->kink_tab, dp->kink_idx, dp->pairs, dp->tpairs,
+                    dp->tintra, dp->tslots,
                     dp->slot_face, dp->slot_nbr,
                     dp->sigma_t, dp->sigma_s, dp->q, dp->rhs_dir, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
                     dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table, dp->ainv};

@@ -48,7 +48,7 @@ void build_fixed_rhs(HostProblem& hp) {
                 for (int s = 0; s < ns; ++s) {
                     if (hp.slot_nbr[(size_t)e * ns + s] >= 0) continue;   // interior face
                     const int32_t f = hp.slot_face[(size_t)e * ns + s];
-                    const bool minus_side = (s & 1) != 0;
+                    const bool minus_side = slot_is_minus(hp, e, s);
                     const uint8_t fc = g.face_class[f];
                     if (fc == FC_KINK) {
                         const auto it = std::lower_bound(g.kink_face.begin(), g.kink_face.end(), f);
@@ -66,7 +66,7 @@ void build_fixed_rhs(HostProblem& hp) {
                             pin[k] = sgn * v;
                         }
                     }
-                    const int* tn = &hp.slot_nodes[(size_t)s * nf];
+                    const int32_t* tn = slot_trace(hp, e, s);
                     for (int la = 0; la < nf; ++la) {
                         double v = 0.0;
                         for (int b = 0; b < nf; ++b) v += pin[(size_t)la * nf + b] * pe[tn[b]];

@@ -367,3 +367,57 @@ def test_full_size_sampled_directions_stored(torch, ctx, name):
     for k, d in enumerate(dirs):
         assert rel_err(got[k], ref[k]) < TOL, (name, int(d))
     P.close()
+
+
+UNSTRUCTURED = {
+    # a full annulus closing on itself (cycles around the hole), Q3, p = 2
+    "u_annulus": lambda: W.annulus_full(nr=4, nt=16, p=2, sn_order=4),
+    "u_annulus_p3": lambda: W.annulus_full(nr=3, nt=12, p=3, sn_order=8, seed=5),
+    # five-block O-grid disk (vertices shared by three elements), Q2, p = 1 / 2
+    "u_disk": lambda: W.disk_ogrid(n=3, m=2, p=2, sn_order=4),
+    "u_disk_p1": lambda: W.disk_ogrid(n=4, m=3, p=1, sn_order=6, seed=7),
+    # cylindrical shell, elements turned by any of the 24 rotations of the cube
+    "u_shell": lambda: W.annulus_shell_3d(nr=2, nt=8, nz=2, p=2, sn_order=4),
+    "u_shell_p1": lambda: W.annulus_shell_3d(nr=2, nt=10, nz=3, p=1, sn_order=2, seed=8),
+    # lattice meshes given as renumbered, rotated element lists
+    "u_c1": lambda: W.as_unstructured(W.c1(), 13),
+    "u_cyclic2d_p3": lambda: W.as_unstructured(W.make_problem("cyc_p3", 2, (9, 7), 3, 3, 8, 0.3 / 9, 2,
+                                                              np.linspace(0.5, 4, 63), 0.6, 1.0,
+                                                              bc_kind=W.ISO_CONST, psi_inc=0.4), 14),
+}
+
+
+@pytest.mark.parametrize("cache", [1, 2], ids=["inverse", "assembled"])
+@pytest.mark.parametrize("case", sorted(UNSTRUCTURED))
+def test_unstructured_sweeps_match_oracle(torch, ctx, case, cache):
+    """Unstructured conforming meshes (level schedule): three sweeps against
+    the oracle, with cached inverses and assembled per sweep."""
+    from paper_1810_11080_amd import Problem
+    wp = UNSTRUCTURED[case]()
+    P = Problem.from_workload(ctx, wp, cache_inverse=cache)
+    assert P.info()["schedule"] == 2
+    g_phi, g_psi = gpu_sweeps(torch, P, 3)
+    P.synchronize()
+    o_phi, o_psi, _, _ = oracle_sweeps(wp, 3)
+    for k in range(3):
+        assert rel_err(g_phi[k], o_phi[k]) < TOL, (case, k)
+    assert rel_err(g_psi[-1], o_psi[-1]) < TOL
+
+
+@pytest.mark.parametrize("case", ["u_annulus", "u_shell"])
+def test_unstructured_mixed_and_converged(torch, ctx, case):
+    """Mixed precision on unstructured meshes (1e-5), and the converged FP64
+    solve against the oracle's converged source iteration."""
+    from paper_1810_11080_amd import Problem
+    from oracle.sweep import source_iteration
+    wp = UNSTRUCTURED[case]()
+    Pm = Problem.from_workload(ctx, wp, precision=1)
+    g_phi, _ = gpu_sweeps(torch, Pm, 2)
+    Pm.synchronize()
+    o_phi, _, disc, gs = oracle_sweeps(wp, 2)
+    assert rel_err(g_phi[-1], o_phi[-1]) < MIXED_TOL
+    P = Problem.from_workload(ctx, wp)
+    phi = torch.zeros(P.E * P.n, dtype=torch.float64, device="cuda")
+    P.solve(phi, tol=1e-12, max_iters=2000)
+    ref, *_ = source_iteration(disc, gs, tol=1e-13, max_iters=2000)
+    assert rel_err(phi.cpu().numpy().reshape(P.E, P.n), ref) < 1e-9

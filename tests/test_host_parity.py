@@ -20,6 +20,15 @@ CASES = {
     "strongcyc": lambda: W.cyclic_2d(16, 2, 0.9, 1, 8),
     # curved domain boundary: quarter annulus, cycles of up to 9 elements
     "annulus": lambda: W.annulus_quarter(9, 15, 3, 4),
+    # unstructured element lists (renumbered, every element's frame rotated
+    # at random): a full annulus that closes on itself, a five-block O-grid
+    # disk, a cylindrical shell with all 24 rotations of the cube, and
+    # lattice meshes given as element lists (cyclic 2D Q3, warped 3D Q2)
+    "u_annulus": lambda: W.annulus_full(nr=4, nt=16, p=2, sn_order=4),
+    "u_disk": lambda: W.disk_ogrid(n=3, m=2, p=2, sn_order=4),
+    "u_shell": lambda: W.annulus_shell_3d(nr=2, nt=8, nz=2, p=2, sn_order=4),
+    "u_cyclic2d": lambda: W.as_unstructured(W.small(dim=2, n=12, r=3, p=2, N=8, amp=0.3 / 12, freq=3), 11),
+    "u_warp3d": lambda: W.as_unstructured(W.small(dim=3, n=4, r=2, p=2, N=4, amp=0.08, freq=1), 12),
 }
 
 
@@ -149,3 +158,25 @@ def test_set_source_validation(ctx):
     with pytest.raises(SnswError) as info:
         P.set_source(bad)
     assert info.value.code == -3
+
+
+def test_unstructured_input_errors(ctx):
+    """Bad element lists are reported, not swept: an index out of range, a
+    face shared by three element slots, a persistent schedule request."""
+    from paper_1810_11080_amd import Problem, SnswError
+    wp = W.annulus_full(nr=2, nt=8, p=1, sn_order=2)
+    en = wp.elem_nodes.copy()
+    en[3, 0] = len(wp.nodes)
+    with pytest.raises(SnswError) as ei:
+        Problem(ctx, dim=2, nx=(wp.n_elements, 1), geom_order=wp.r, dg_order=wp.p, lattice=None, sn_order=2,
+                sigma_t=wp.sigma_t, sigma_s=wp.sigma_s, q=wp.q, nodes=wp.nodes, elem_nodes=en)
+    assert ei.value.code == -1
+    dup = np.concatenate([wp.elem_nodes, wp.elem_nodes[:1]])
+    E = len(dup)
+    with pytest.raises(SnswError) as ei:
+        Problem(ctx, dim=2, nx=(E, 1), geom_order=wp.r, dg_order=wp.p, lattice=None, sn_order=2,
+                sigma_t=np.ones(E), sigma_s=np.zeros(E), q=np.ones(E), nodes=wp.nodes, elem_nodes=dup)
+    assert ei.value.code == -2
+    with pytest.raises(SnswError) as ei:
+        Problem.from_workload(ctx, wp, schedule=1)
+    assert ei.value.code == -9

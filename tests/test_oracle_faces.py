@@ -85,7 +85,7 @@ def test_face_identities(dim, r, p, n, amp, freq):
     net = np.zeros(disc.E)
     for s in range(2 * dim):
         fid = disc.slot_face[:, s]
-        sign = 1.0 if disc.slot_side[s] == 0 else -1.0
+        sign = np.where(disc.slot_side[:, s] == 0, 1.0, -1.0)
         net += sign * (mp[fid] - mm[fid])
     assert np.abs(net).max() < 1e-13
 

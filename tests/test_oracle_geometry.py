@@ -39,10 +39,19 @@ def test_unwarped_closed_forms(dim, r, p):
         assert np.allclose(K[:, i], Kref[i][None], atol=1e-14)
 
 
-@pytest.mark.parametrize("dim,r,p,n,amp,freq", [(2, 3, 3, 8, 0.3 / 8, 2), (2, 2, 1, 5, 0.05, 1),
-                                                 (3, 2, 2, 3, 0.05, 1)])
-def test_warped_invariants(dim, r, p, n, amp, freq):
+@pytest.mark.parametrize("dim,r,p,n,amp,freq,unstructured", [
+    (2, 3, 3, 8, 0.3 / 8, 2, None), (2, 2, 1, 5, 0.05, 1, None), (3, 2, 2, 3, 0.05, 1, None),
+    (2, 3, 3, 8, 0.3 / 8, 2, 5), (3, 2, 2, 3, 0.05, 1, 6), (3, 1, 2, 3, 0.05, 1, 7)])
+def test_warped_invariants(dim, r, p, n, amp, freq, unstructured):
+    """Volume, column sums of K_i, and integration by parts on every element
+    (K_i + K_i^T = the surface integral of u_m u_n n_i, assembled from the
+    element's faces through its slot tables).  With `unstructured` the same
+    mesh is given as an element list, renumbered and with every element's
+    local frame rotated at random, so each face is assembled through the
+    orientation found by face matching."""
     prob = W.small(dim=dim, n=n, r=r, p=p, N=2, amp=amp, freq=freq)
+    if unstructured is not None:
+        prob = W.as_unstructured(prob, seed=unstructured)
     disc = Discretization(prob)
     assert disc.geo.detJ.min() > 0
     # total volume of the unit box (the warp fixes the boundary)
@@ -55,11 +64,12 @@ def test_warped_invariants(dim, r, p, n, amp, freq):
         om[i] = 1.0
         Pp, Pm, *_ = disc.faces.integrals(om)
         S = np.zeros((disc.E, disc.n, disc.n))
+        rows = np.arange(disc.E)[:, None, None]
         for s in range(2 * dim):
             fid = disc.slot_face[:, s]
-            sign = 1.0 if disc.slot_side[s] == 0 else -1.0
-            tn = disc.slot_nodes[s]
-            S[:, tn[:, None], tn[None, :]] += sign * (Pp[fid] - Pm[fid])
+            sign = np.where(disc.slot_side[:, s] == 0, 1.0, -1.0)[:, None, None]
+            tn = disc.slot_trace[:, s]
+            S[rows, tn[:, :, None], tn[:, None, :]] += sign * (Pp[fid] - Pm[fid])
         Ki = disc.K[:, i]
         assert np.abs(Ki + Ki.transpose(0, 2, 1) - S).max() < 1e-12 * max(1, np.abs(S).max())
 

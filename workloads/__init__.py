@@ -58,6 +58,12 @@ class Problem:
     # optional direction-dependent data, nodal values at the DG nodes:
     q_dir: Optional[np.ndarray] = None        # (D, E, n) source per direction (replaces q)
     psi_inc_tab: Optional[np.ndarray] = None  # (D, E, n) incident flux (bc_kind TABULATED)
+    # optional unstructured conforming mesh (then `lattice` is unused and nx
+    # is (E, 1[, 1])): global control points and, per element, the indices of
+    # its (r+1)^dim control points in local lexicographic order (x fastest);
+    # elements sharing a face share its control points (in any orientation)
+    nodes: Optional[np.ndarray] = None        # (n_nodes, dim) float64
+    elem_nodes: Optional[np.ndarray] = None   # (E, (r+1)^dim) int64
 
     @property
     def n_elements(self) -> int:
@@ -405,3 +411,198 @@ def straightened(prob: Problem, p: int = 1) -> Problem:
                    sigma_t=prob.sigma_t[parent].copy(), sigma_s=prob.sigma_s[parent].copy(),
                    q=prob.q[parent].copy(), q_dir=None, psi_inc_tab=None,
                    meta=dict(prob.meta, straightened_from=prob.name, n_ref=r))
+
+
+# --------------------------------------------------------------------------
+# Unstructured conforming meshes (explicit element -> control point lists)
+# --------------------------------------------------------------------------
+
+def rotations(dim: int) -> List[np.ndarray]:
+    """The orientation-preserving symmetries of the reference square (4) or
+    cube (24) as signed permutation matrices with determinant +1."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(dim)):
+        for signs in itertools.product((1, -1), repeat=dim):
+            R = np.zeros((dim, dim), dtype=np.int64)
+            for i, j in enumerate(perm):
+                R[i, j] = signs[i]
+            if round(np.linalg.det(R)) == 1:
+                out.append(R)
+    return out
+
+
+def local_index_map(dim: int, n1: int, R: np.ndarray) -> np.ndarray:
+    """For a local grid of n1 points per axis (lexicographic, x fastest) and a
+    rotation R of the reference element about its centre: old[m] = index of
+    the point that moves to new index m, so new_values = old_values[old]."""
+    m = np.arange(n1 ** dim)
+    idx = np.stack([(m // n1 ** a) % n1 for a in range(dim)], axis=1)   # new positions
+    c = 2 * idx - (n1 - 1)                                             # centred, doubled
+    old_c = c @ R          # new = R old  ->  old = R^T new  (rows: c_new @ R = (R^T c_new)^T)
+    old_idx = (old_c + (n1 - 1)) // 2
+    return sum(old_idx[:, a] * n1 ** a for a in range(dim))
+
+
+def unstructured_from_elements(name: str, dim: int, r: int, p: int, sn_order: int, nodes: np.ndarray,
+                               elem_nodes: np.ndarray, sigma_t, sigma_s, q, seed: Optional[int] = None,
+                               **kw) -> Problem:
+    """An unstructured problem from element control-point lists; with a seed
+    the elements are renumbered at random and each element's local frame is
+    turned by a random rotation (so neighbours meet through arbitrary slot
+    pairs and face orientations).  The applied permutation and rotations are
+    kept in meta ('perm': new element k is old element perm[k]; 'rot': index
+    of the rotation in rotations(dim) for new element k)."""
+    E = len(elem_nodes)
+    st = np.broadcast_to(np.asarray(sigma_t, dtype=np.float64), (E,)).copy()
+    ss = np.broadcast_to(np.asarray(sigma_s, dtype=np.float64), (E,)).copy()
+    qq = np.broadcast_to(np.asarray(q, dtype=np.float64), (E,)).copy()
+    en = np.asarray(elem_nodes, dtype=np.int64).copy()
+    perm = np.arange(E)
+    rot = np.zeros(E, dtype=np.int64)
+    if seed is not None:
+        rng = np.random.default_rng(seed)
+        perm = rng.permutation(E)
+        rots = rotations(dim)
+        rot = rng.integers(0, len(rots), size=E)
+        maps = [local_index_map(dim, r + 1, R) for R in rots]
+        en = np.stack([en[perm[k]][maps[rot[k]]] for k in range(E)])
+        st, ss, qq = st[perm], ss[perm], qq[perm]
+    meta = dict(kw.pop("meta", {}), perm=perm, rot=rot, unstructured=True)
+    nx = (E,) + (1,) * (dim - 1)
+    return Problem(name=name, dim=dim, nx=nx, r=r, p=p, sn_order=sn_order, lattice=np.zeros((0, dim)),
+                   sigma_t=st, sigma_s=ss, q=qq, nodes=np.asarray(nodes, dtype=np.float64),
+                   elem_nodes=en, meta=meta, **kw)
+
+
+def structured_element_nodes(dim: int, nx, r: int) -> np.ndarray:
+    """(E, (r+1)^dim) lattice indices of the control points of each element
+    of a structured lattice (the lattice layout of the module docstring)."""
+    L = lattice_shape(dim, nx, r)
+    ijk = element_ijk(dim, nx)
+    n1 = r + 1
+    m = np.arange(n1 ** dim)
+    loc = np.stack([(m // n1 ** a) % n1 for a in range(dim)], axis=1)
+    flat = np.zeros((len(ijk), len(m)), dtype=np.int64)
+    stride = 1
+    for a in range(dim):
+        flat += (r * ijk[:, a][:, None] + loc[:, a][None, :]) * stride
+        stride *= L[a]
+    return flat
+
+
+def as_unstructured(prob: Problem, seed: int = 0) -> Problem:
+    """The same mesh and materials given as an unstructured element list,
+    renumbered and locally rotated at random (seeded)."""
+    en = structured_element_nodes(prob.dim, prob.nx, prob.r)
+    return unstructured_from_elements(f"{prob.name}_unstructured{seed}", prob.dim, prob.r, prob.p,
+                                      prob.sn_order, prob.lattice, en, prob.sigma_t, prob.sigma_s, prob.q,
+                                      seed=seed, bc_kind=prob.bc_kind, psi_inc=prob.psi_inc, tol=prob.tol,
+                                      weighting=prob.weighting, exact_scc_max=prob.exact_scc_max,
+                                      meta=dict(prob.meta, structured_from=prob.name))
+
+
+def _merge_nodes(points: np.ndarray, ndigits: int = 9):
+    """Unique control points (by coordinates rounded to ndigits) and the index
+    of each input point among them."""
+    keys = np.round(points, ndigits)
+    _, first, inv = np.unique(keys, axis=0, return_index=True, return_inverse=True)
+    return points[first], inv.reshape(-1)
+
+
+def annulus_full(nr: int = 4, nt: int = 16, p: int = 2, sn_order: int = 4, r: int = 3, r_in: float = 1.0,
+                 r_out: float = 2.0, seed: Optional[int] = 1) -> Problem:
+    """Full annulus r in [r_in, r_out] (theta periodic: the mesh closes on
+    itself, which no structured lattice can express), nr x nt elements of
+    order r with control points on circles, three nested material rings
+    (sigma_t = 2.0, 2.2, 2.4, sigma_s = 1), q = 1, vacuum; renumbered and
+    locally rotated at random (seed)."""
+    n1 = r + 1
+    m = np.arange(n1 * n1)
+    a, b = m % n1, m // n1
+    i, j = np.meshgrid(np.arange(nr), np.arange(nt), indexing="ij")
+    i, j = i.reshape(-1), j.reshape(-1)
+    ri = r * i[:, None] + a[None, :]                    # radial node index
+    tj = (r * j[:, None] + b[None, :]) % (r * nt)       # angular node index (periodic)
+    elem = ri * (r * nt) + tj
+    rr = r_in + (r_out - r_in) * np.arange(r * nr + 1) / (r * nr)
+    th = 2.0 * math.pi * np.arange(r * nt) / (r * nt)
+    R, T = np.meshgrid(rr, th, indexing="ij")
+    nodes = np.stack([(R * np.cos(T)).reshape(-1), (R * np.sin(T)).reshape(-1)], axis=1)
+    ring = np.minimum(i * 3 // nr, 2)
+    st = np.array([2.0, 2.2, 2.4])[ring]
+    return unstructured_from_elements(f"annulus_{nr}x{nt}_q{r}_p{p}_s{sn_order}", 2, r, p, sn_order, nodes, elem,
+                                      st, 1.0, 1.0, seed=seed, tol=1e-8,
+                                      meta=dict(r_in=r_in, r_out=r_out))
+
+
+def disk_ogrid(n: int = 3, m: int = 2, p: int = 2, sn_order: int = 4, r: int = 2, seed: Optional[int] = 2) -> Problem:
+    """Unit disk as a five-block O-grid: a central square [-h, h]^2 of n x n
+    elements and four blocks of m x n elements joining its sides to the
+    circle (the square's corners are vertices of three elements, so the mesh
+    is not a lattice).  Order-r elements; the outer blocks blend the square
+    side into the circular arc.  sigma_t = 1 inside the square, 2 outside,
+    c = 0.5, q = 1, vacuum; renumbered and locally rotated at random."""
+    h = 0.45
+    n1 = r + 1
+    loc = np.arange(n1 * n1)
+    la, lb = (loc % n1) / r, (loc // n1) / r
+    pts, mats = [], []
+    # central square, element (i, j): x = -h + 2h (i + a)/n
+    for jj in range(n):
+        for ii in range(n):
+            x = -h + 2 * h * (ii + la) / n
+            y = -h + 2 * h * (jj + lb) / n
+            pts.append(np.stack([x, y], axis=1))
+            mats.append(1.0)
+    # outer blocks: side k of the square (counter-clockwise), xi along the
+    # side, eta outward; the inner edge is the square side, the outer the arc
+    for k in range(4):
+        ang0 = -0.25 * math.pi + 0.5 * math.pi * k
+        c0, s0 = math.cos(0.5 * math.pi * k), math.sin(0.5 * math.pi * k)
+        # local axes (outward, counter-clockwise along the side): right-handed
+        for ii in range(n):
+            for jj in range(m):
+                eta = (jj + la) / m
+                xi = (ii + lb) / n
+                # square side point (rotated copy of the right side x = h)
+                sx, sy = h, -h + 2 * h * xi
+                ix, iy = c0 * sx - s0 * sy, s0 * sx + c0 * sy
+                phi = ang0 + 0.5 * math.pi * xi
+                ox, oy = np.cos(phi), np.sin(phi)
+                pts.append(np.stack([(1 - eta) * ix + eta * ox, (1 - eta) * iy + eta * oy], axis=1))
+                mats.append(2.0)
+    allp = np.concatenate(pts)
+    nodes, inv = _merge_nodes(allp)
+    elem = inv.reshape(len(pts), n1 * n1)
+    st = np.array(mats)
+    return unstructured_from_elements(f"disk_ogrid_{n}x{m}_q{r}_p{p}_s{sn_order}", 2, r, p, sn_order, nodes, elem,
+                                      st, 0.5 * st, 1.0, seed=seed, tol=1e-8)
+
+
+def annulus_shell_3d(nr: int = 2, nt: int = 8, nz: int = 2, p: int = 2, sn_order: int = 4, r: int = 2,
+                     r_in: float = 1.0, r_out: float = 2.0, height: float = 1.0,
+                     seed: Optional[int] = 3) -> Problem:
+    """Cylindrical shell r in [r_in, r_out], theta periodic, z in [0, height],
+    nr x nt x nz elements of order r (control points on circles), sigma_t = 1
+    in the inner half of the radius and 3 in the outer, c = 0.5, q = 1,
+    vacuum; renumbered and locally rotated at random (any of the 24 rotations
+    of the reference cube, so faces meet in all eight orientations)."""
+    n1 = r + 1
+    m = np.arange(n1 ** 3)
+    a, b, c = m % n1, (m // n1) % n1, m // (n1 * n1)
+    i, j, k = np.meshgrid(np.arange(nr), np.arange(nt), np.arange(nz), indexing="ij")
+    i, j, k = i.reshape(-1), j.reshape(-1), k.reshape(-1)
+    NR, NT, NZ = r * nr + 1, r * nt, r * nz + 1
+    ri = r * i[:, None] + a[None, :]
+    tj = (r * j[:, None] + b[None, :]) % NT
+    zk = r * k[:, None] + c[None, :]
+    elem = (ri * NT + tj) * NZ + zk
+    rr = r_in + (r_out - r_in) * np.arange(NR) / (NR - 1)
+    th = 2.0 * math.pi * np.arange(NT) / NT
+    zz = height * np.arange(NZ) / (NZ - 1)
+    R, T, Z = np.meshgrid(rr, th, zz, indexing="ij")
+    nodes = np.stack([(R * np.cos(T)).reshape(-1), (R * np.sin(T)).reshape(-1), Z.reshape(-1)], axis=1)
+    st = np.where(i * 2 < nr, 1.0, 3.0)
+    return unstructured_from_elements(f"shell3d_{nr}x{nt}x{nz}_q{r}_p{p}_s{sn_order}", 3, r, p, sn_order, nodes,
+                                      elem, st, 0.5 * st, 1.0, seed=seed, tol=1e-8)
