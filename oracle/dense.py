@@ -30,7 +30,7 @@ def assemble(disc):
         for e in range(E):
             A[blk(d, e), blk(d, e)] += Ad[e]
             rhs[blk(d, e)] += bd[e]
-        for s in range(2 * dim):
+        for s in range(disc.ns):
             _, Pin = disc.slot_blocks(d, s, elems)
             for e in range(E):
                 tn = disc.slot_trace[e, s]
@@ -39,6 +39,8 @@ def assemble(disc):
                 if nb >= 0:
                     cols = blk(d, nb).start + disc.slot_up_trace[e, s]
                     A[np.ix_(rows, cols)] -= Pin[e]
+                elif disc.psi_tab is not None:
+                    rhs[rows] += Pin[e] @ disc.psi_tab[disc.dir_index(d)][e, tn]
                 elif disc.inflow_fn is not None:
                     rhs[rows] += disc.boundary_load(d, s, np.array([e]))[0]
                 else:

@@ -21,6 +21,7 @@ import numpy as np
 from . import quadrature
 from .faces import FaceSet
 from .geometry import ElementGeometry, problem_control_points
+from .simplex import SimplexGeometry
 
 VACUUM, ISO_CONST, TABULATED = 0, 1, 2
 
@@ -36,19 +37,24 @@ class Discretization:
         self.prob = prob
         self.dim, self.nx, self.r, self.p = prob.dim, tuple(prob.nx), prob.r, prob.p
         self.unstructured = getattr(prob, "elem_nodes", None) is not None
+        self.simplex = getattr(prob, "element", "tensor") == "simplex"
         self.E = len(prob.elem_nodes) if self.unstructured else int(np.prod(self.nx))
-        self.n = (self.p + 1) ** self.dim
+        self.n = (self.p + 1) * (self.p + 2) // 2 if self.simplex else (self.p + 1) ** self.dim
         if omega is None:
             omega, w = quadrature.level_symmetric(prob.sn_order, prob.dim)
         self.omega, self.w = np.asarray(omega), np.asarray(w)
         self.D = len(self.w)
         xe = problem_control_points(prob)
-        self.geo = ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p, xe=xe)
+        if self.simplex:
+            self.geo = SimplexGeometry(xe, self.r, self.p)
+        else:
+            self.geo = ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p, xe=xe)
         self.geo.check_positive()
         self.M = self.geo.mass()                     # (E, n, n)
         self.K = self.geo.grad_moments()             # (E, dim, n, n)
         if self.unstructured:
-            self.faces = FaceSet.from_elements(prob.nodes, prob.elem_nodes, self.dim, self.r, self.p)
+            self.faces = FaceSet.from_elements(prob.nodes, prob.elem_nodes, self.dim, self.r, self.p,
+                                               simplex=self.simplex)
         else:
             self.faces = FaceSet(prob.lattice, self.dim, self.nx, self.r, self.p)
         self.sigma_t = np.asarray(prob.sigma_t, dtype=np.float64)
@@ -78,7 +84,8 @@ class Discretization:
             self.eidx = eidx
         fs = self.faces
         self.slot_face = fs.slot_face
-        self.slot_side = fs.slot_side                         # (E, 2 dim): 0 minus, 1 plus
+        self.ns = self.slot_face.shape[1]                     # slots per element (2 dim, or 3)
+        self.slot_side = fs.slot_side                         # (E, ns): 0 minus, 1 plus
         self.slot_nbr = np.where(self.slot_side == 0, fs.plus[self.slot_face], fs.minus[self.slot_face])
         self.slot_trace = fs.slot_trace                       # (E, 2 dim, nf)
         self.slot_up_trace = np.zeros_like(self.slot_trace)
@@ -91,15 +98,15 @@ class Discretization:
         # face -> slot of its minus / plus element
         self.face_slot = np.full((fs.n_faces, 2), -1, dtype=np.int64)
         for e_ in range(self.E):
-            for s_ in range(2 * self.dim):
+            for s_ in range(self.ns):
                 self.face_slot[self.slot_face[e_, s_], self.slot_side[e_, s_]] = s_
         self._cache_d = None
         self._cache = None
         self.inflow_fn = inflow_fn
         self.src_load = None
         if source_fn is not None:
-            fine = ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p,
-                                   extra_points=4, xe=xe)
+            fine = (SimplexGeometry(xe, self.r, self.p, extra_points=4) if self.simplex else
+                    ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p, extra_points=4, xe=xe))
             self.src_load = np.stack([fine.load(source_fn(fine.x, self.omega[d]))
                                       for d in range(self.D)])
 
@@ -135,7 +142,7 @@ class Discretization:
         A = self.sigma_t[elems, None, None] * self.M[elems]
         A = A - np.einsum("i,kimn->kmn", om, self.K[elems])
         rows = np.arange(len(elems))[:, None, None]
-        for s in range(2 * self.dim):
+        for s in range(self.ns):
             Pout, _ = self.slot_blocks(d, s, elems)
             tn = self.slot_trace[elems, s]
             A[rows, tn[:, :, None], tn[:, None, :]] += Pout
@@ -165,11 +172,11 @@ class Discretization:
         """b_e for direction d.
 
         psi_kept / psi_lag: (E, n) angular flux of direction d used for kept /
-        lagged upwind couplings; lagged_mask (k, 2*dim) bool marks slots whose
+        lagged upwind couplings; lagged_mask (k, ns) bool marks slots whose
         inflow edge was removed from the graph (read psi_lag)."""
         b = self.volume_source(phi, elems, d)
         rows = np.arange(len(elems))[:, None]
-        for s in range(2 * self.dim):
+        for s in range(self.ns):
             _, Pin = self.slot_blocks(d, s, elems)
             tn = self.slot_trace[elems, s]
             tn_up = self.slot_up_trace[elems, s]

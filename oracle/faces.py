@@ -42,6 +42,7 @@ import math
 import numpy as np
 
 from . import basis
+from . import simplex as simplex_ref
 
 TAU = 1e-12
 KINK_SUBDIV_3D = 4
@@ -147,8 +148,12 @@ class FaceSet:
 
     # ------------------------------------------------------------------
     @classmethod
-    def from_elements(cls, nodes, elem_nodes, dim: int, r: int, p: int):
+    def from_elements(cls, nodes, elem_nodes, dim: int, r: int, p: int, simplex: bool = False):
         """Faces of a conforming mesh given as element control-point lists.
+
+        simplex: the elements are P_r triangles (``simplex`` module: three
+        counter-clockwise edge slots, whose N of the 2D axis-0 formula is the
+        outward normal, so no slot is mirrored and every face has axis 0).
 
         Two element slots are the same face when their corner control points
         coincide (by index).  Convention for each face: its minus element is
@@ -165,7 +170,9 @@ class FaceSet:
         fs = cls.__new__(cls)
         nodes = np.asarray(nodes, dtype=np.float64)
         en = np.asarray(elem_nodes, dtype=np.int64)
-        E, ns = len(en), 2 * dim
+        if simplex and dim != 2:
+            raise ValueError("simplicial elements: triangles (dim 2) only")
+        E, ns = len(en), (3 if simplex else 2 * dim)
         fs.dim, fs.r, fs.p, fs.nx = dim, r, p, (E,) + (1,) * (dim - 1)
         nfc = (r + 1) ** (dim - 1)
 
@@ -184,8 +191,12 @@ class FaceSet:
                 out[loc] = sum(idx[b] * n1 ** b for b in range(dim))
             return out   # 2D: out[i]; 3D: out[j, i] (t slow, s fast)
 
-        ctrl_grid = [face_grid(r, sl) for sl in range(ns)]
-        dg_grid = [face_grid(p, sl) for sl in range(ns)]
+        if simplex:
+            ctrl_grid = [simplex_ref.slot_nodes(r, sl) for sl in range(ns)]
+            dg_grid = [simplex_ref.slot_nodes(p, sl) for sl in range(ns)]
+        else:
+            ctrl_grid = [face_grid(r, sl) for sl in range(ns)]
+            dg_grid = [face_grid(p, sl) for sl in range(ns)]
 
         def corners(g):
             return (g[0], g[-1]) if dim == 2 else (g[0, 0], g[0, -1], g[-1, 0], g[-1, -1])
@@ -213,10 +224,10 @@ class FaceSet:
                 raise ValueError(f"non-conforming face {rec}")
             (em, sm) = rec[0]
             cg, dgg = ctrl_grid[sm], dg_grid[sm]
-            if sm % 2 == 0:
+            if sm % 2 == 0 and not simplex:
                 cg, dgg = mirror(cg), mirror(dgg)
             ids = en[em][cg]                          # face-ordered control point ids
-            fs.axis[f] = sm // 2
+            fs.axis[f] = 0 if simplex else sm // 2
             fs.minus[f] = em
             fs.ctrl[f] = nodes[ids.reshape(-1)]
             fs.slot_face[em, sm] = f

@@ -26,8 +26,8 @@ from .graph import direction_graph
 
 
 def lag_masks(disc, g) -> np.ndarray:
-    """(E, 2*dim) bool: slot of element receives its inflow on a lagged edge."""
-    mask = np.zeros((disc.E, 2 * disc.dim), dtype=bool)
+    """(E, ns) bool: slot of element receives its inflow on a lagged edge."""
+    mask = np.zeros((disc.E, disc.ns), dtype=bool)
     for dn, up in zip(g.removed_down.tolist(), g.removed_up.tolist()):
         slots = np.nonzero(disc.slot_nbr[dn] == up)[0]
         mask[dn, slots] = True

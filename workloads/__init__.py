@@ -64,6 +64,10 @@ class Problem:
     # elements sharing a face share its control points (in any orientation)
     nodes: Optional[np.ndarray] = None        # (n_nodes, dim) float64
     elem_nodes: Optional[np.ndarray] = None   # (E, (r+1)^dim) int64
+    # "tensor" (quadrilaterals / hexahedra) or "simplex" (P_r triangles: then
+    # elem_nodes lists (r+1)(r+2)/2 control points per element in the
+    # triangle lattice order of tri_lattice, and n = (p+1)(p+2)/2)
+    element: str = "tensor"
 
     @property
     def n_elements(self) -> int:
@@ -71,6 +75,8 @@ class Problem:
 
     @property
     def n_dof(self) -> int:
+        if self.element == "simplex":
+            return (self.p + 1) * (self.p + 2) // 2
         return (self.p + 1) ** self.dim
 
     @property
@@ -606,3 +612,111 @@ def annulus_shell_3d(nr: int = 2, nt: int = 8, nz: int = 2, p: int = 2, sn_order
     st = np.where(i * 2 < nr, 1.0, 3.0)
     return unstructured_from_elements(f"shell3d_{nr}x{nt}x{nz}_q{r}_p{p}_s{sn_order}", 3, r, p, sn_order, nodes,
                                       elem, st, 0.5 * st, 1.0, seed=seed, tol=1e-8)
+
+
+# ---------------------------------------------------------------- triangles
+def tri_lattice(k: int) -> np.ndarray:
+    """(n, 2) lattice pairs (i, j), i + j <= k, of the nodes of order k on a
+    triangle, row by row (j slowest): the local order of a simplex element's
+    control points (reference position (i / k, j / k) for vertices v0 = (0, 0),
+    v1 = (1, 0), v2 = (0, 1))."""
+    return np.array([(i, j) for j in range(k + 1) for i in range(k + 1 - j)], dtype=np.int64)
+
+
+def tri_rotation_map(r: int, turns: int) -> np.ndarray:
+    """Local index map of a triangle whose vertex order is turned `turns`
+    times (v0, v1, v2) -> (v1, v2, v0): new local node k is old node map[k]."""
+    L = tri_lattice(r)
+    idx = {(int(i), int(j)): k for k, (i, j) in enumerate(L)}
+    out = np.arange(len(L))
+    for _ in range(turns % 3):
+        # new (i', j') is the old node with barycentrics lambda_v1 = 1 - (i'+j')/r, lambda_v2 = i'/r
+        out = np.array([out[idx[(r - int(i) - int(j), int(i))]] for i, j in L])
+    return out
+
+
+def triangulated(name: str, r: int, p: int, sn_order: int, nx: int, ny: int, x_of, sigma_t, sigma_s, q,
+                 periodic_v: bool = False, seed: Optional[int] = None, **kw) -> Problem:
+    """Triangles from an nx x ny grid of cells on the parameter square
+    [0, 1]^2, each cell cut along one diagonal (alternating), counter-clockwise
+    in parameter space, mapped by x_of(u, v) -> (x, y) (orientation
+    preserving): each triangle's control points are the map at its order-r
+    lattice points, so triangles are curved wherever the map is not affine.
+    periodic_v: v = 1 is glued to v = 0 (a closed ring).  sigma_t, sigma_s, q:
+    per element or callables of the cell centre (u, v).  With a seed the
+    elements are renumbered and each element's vertex order turned at
+    random (meta 'perm', 'turns')."""
+    fu, fv = r * nx + 1, r * ny + (0 if periodic_v else 1)
+    U, V = np.meshgrid(np.arange(fu) / (r * nx), np.arange(fv) / (r * ny), indexing="xy")   # u fastest
+    X = x_of(U.reshape(-1), V.reshape(-1))
+    nodes = np.stack([np.asarray(X[0], dtype=np.float64), np.asarray(X[1], dtype=np.float64)], axis=1)
+    L = tri_lattice(r)
+    elems, centres = [], []
+    for cj in range(ny):
+        for ci in range(nx):
+            P00, P10, P01, P11 = (r * ci, r * cj), (r * (ci + 1), r * cj), (r * ci, r * (cj + 1)), \
+                (r * (ci + 1), r * (cj + 1))
+            tris = [(P00, P10, P11), (P00, P11, P01)] if (ci + cj) % 2 == 0 else \
+                [(P00, P10, P01), (P10, P11, P01)]
+            for A, B, C in tris:
+                ids = []
+                for i, j in L:
+                    fi = A[0] + i * (B[0] - A[0]) // r + j * (C[0] - A[0]) // r
+                    fj = A[1] + i * (B[1] - A[1]) // r + j * (C[1] - A[1]) // r
+                    ids.append(fi + fu * (fj % fv if periodic_v else fj))
+                elems.append(ids)
+                centres.append(((A[0] + B[0] + C[0]) / (3.0 * r * nx), (A[1] + B[1] + C[1]) / (3.0 * r * ny)))
+    en = np.array(elems, dtype=np.int64)
+    cu, cv = np.array(centres).T
+    E = len(en)
+
+    def per_elem(v):
+        return np.asarray(v(cu, cv) if callable(v) else np.broadcast_to(v, (E,)), dtype=np.float64).copy()
+
+    st, ss, qq = per_elem(sigma_t), per_elem(sigma_s), per_elem(q)
+    perm = np.arange(E)
+    turns = np.zeros(E, dtype=np.int64)
+    if seed is not None:
+        rng = np.random.default_rng(seed)
+        perm = rng.permutation(E)
+        turns = rng.integers(0, 3, size=E)
+        maps = [tri_rotation_map(r, t) for t in range(3)]
+        en = np.stack([en[perm[k]][maps[turns[k]]] for k in range(E)])
+        st, ss, qq = st[perm], ss[perm], qq[perm]
+    meta = dict(kw.pop("meta", {}), perm=perm, turns=turns, unstructured=True)
+    return Problem(name=name, dim=2, nx=(E, 1), r=r, p=p, sn_order=sn_order, lattice=np.zeros((0, 2)),
+                   sigma_t=st, sigma_s=ss, q=qq, nodes=nodes, elem_nodes=en, element="simplex", meta=meta, **kw)
+
+
+def tri_square(n: int = 4, r: int = 2, p: int = 2, sn_order: int = 4, amp: float = 0.05,
+               seed: Optional[int] = 3) -> Problem:
+    """Warped unit square, x = u + amp sin(2 pi u) sin(2 pi v),
+    y = v + amp sin(2 pi u) sin(pi v), n x n cells cut into 2 n^2 curved
+    order-r triangles; checkerboard sigma_t in {1, 4} by cell, sigma_s = 0.5,
+    q = 1, vacuum."""
+    def x_of(u, v):
+        return (u + amp * np.sin(2 * math.pi * u) * np.sin(2 * math.pi * v),
+                v + amp * np.sin(2 * math.pi * u) * np.sin(math.pi * v))
+
+    def sig(cu, cv):
+        return np.where((np.floor(cu * n) + np.floor(cv * n)) % 2 == 0, 1.0, 4.0)
+
+    return triangulated(f"tri_square_{n}_q{r}_p{p}_s{sn_order}", r, p, sn_order, n, n, x_of, sig, 0.5, 1.0,
+                        seed=seed, tol=1e-10, meta=dict(amp=amp))
+
+
+def tri_annulus(nr: int = 3, nt: int = 12, r: int = 3, p: int = 2, sn_order: int = 4, r_in: float = 1.0,
+                r_out: float = 2.0, seed: Optional[int] = 1) -> Problem:
+    """Full annulus (closed in theta) of 2 nr nt curved order-r triangles with
+    control points on circles; curved faces on which Omega . n changes sign
+    and cyclic dependencies; sigma_t rings 2.0 / 2.2 / 2.4, sigma_s = 1,
+    q = 1, vacuum."""
+    def x_of(u, v):
+        rho = r_in + (r_out - r_in) * u
+        return rho * np.cos(2 * math.pi * v), rho * np.sin(2 * math.pi * v)
+
+    def sig(cu, cv):
+        return np.array([2.0, 2.2, 2.4])[np.minimum((cu * 3).astype(int), 2)]
+
+    return triangulated(f"tri_annulus_{nr}x{nt}_q{r}_p{p}_s{sn_order}", r, p, sn_order, nr, nt, x_of, sig, 1.0,
+                        1.0, periodic_v=True, seed=seed, tol=1e-8, meta=dict(r_in=r_in, r_out=r_out))
