@@ -1,6 +1,7 @@
 /*
  * snsweep -- graph-based upwind DG transport sweeps for the steady,
- * mono-energetic S_N equations on curved high-order quad/hex meshes, on
+ * mono-energetic S_N equations on curved high-order quad/hex (and
+ * triangle) meshes, on
  * AMD Instinct MI355X (gfx950).
  *
  * Method: Haut, Maginot, Tomov, Southworth, Brunner, Bailey, "An Efficient
@@ -96,6 +97,21 @@ extern "C" {
 #define SNSW_CACHE_ON      1
 #define SNSW_CACHE_OFF     2
 
+/* Element type of an unstructured mesh (snsw_problem_desc.element).
+ * SIMPLEX: the simplicial elements that section 2 allows next to the
+ * tensor-product ones (after eq. elementTransformation: P_r map and P_s
+ * DG basis); 2D only (triangles).  Reference triangle {x, y >= 0,
+ * x + y <= 1}, vertices v0 = (0,0), v1 = (1,0), v2 = (0,1).  Nodes of
+ * order k sit on the lattice pairs (i, j), i + j <= k, numbered row by row
+ * (j slowest): node (i, j) is local index j (k+1) - j (j-1)/2 + i.
+ *   control points (k = r): at (i/r, j/r), elem_nodes [E][(r+1)(r+2)/2];
+ *   DOFs (k = p): n = (p+1)(p+2)/2, on the edges at the Gauss-Lobatto
+ *     points (g_i, g_j) of [0, 1], inside (p = 3: the centroid) at (i/p, j/p).
+ * Every element map must keep the orientation (v0, v1, v2 counter-
+ * clockwise).  Element slots are the edges v0->v1, v1->v2, v2->v0.         */
+#define SNSW_ELEM_TENSOR   0
+#define SNSW_ELEM_SIMPLEX  1
+
 typedef struct snsw_ctx snsw_ctx;
 typedef struct snsw_problem snsw_problem;
 
@@ -161,6 +177,8 @@ typedef struct {
     int64_t n_nodes;
     const double* nodes;
     const int64_t* elem_nodes;
+    int32_t element;         /* SNSW_ELEM_*: element type of an unstructured
+                                mesh (SIMPLEX needs elem_nodes and dim 2)   */
 } snsw_problem_desc;
 
 /* Builds the discretisation and the sweep schedule (section 3): quadrature,
@@ -220,7 +238,8 @@ int snsw_problem_set_source(snsw_problem* prob, int32_t q_per_dof, const double*
 int snsw_get_node_coordinates(const snsw_problem* prob, int64_t e0, int64_t count, double* xyz);
 
 /* Tensor Gauss-Legendre rule on elements [e0, e0+count) with `extra` points
- * per axis beyond the rule of the element matrices (extra in [0, 8]):
+ * per axis beyond the rule of the element matrices (extra in [0, 8]; on
+ * triangles the collapsed Gauss rule, (p + r + extra)^2 points):
  * *n_points receives Q, the points per element; if x is not NULL, x
  * [count][Q][dim] receives the physical points, wdet [count][Q] the weights
  * times |det J|, and basis (nullable) [Q][n] the DG basis at the reference

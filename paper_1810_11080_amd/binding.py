@@ -31,7 +31,8 @@ class SnswProblemDesc(C.Structure):
                 ("weighting", C.c_int32), ("exact_scc_max", C.c_int32),
                 ("precision", C.c_int32), ("n_threads", C.c_int32), ("schedule", C.c_int32),
                 ("cache_inverse", C.c_int32), ("psi_inc_tab", c_double_p),
-                ("n_nodes", C.c_int64), ("nodes", c_double_p), ("elem_nodes", C.POINTER(C.c_int64))]
+                ("n_nodes", C.c_int64), ("nodes", c_double_p), ("elem_nodes", C.POINTER(C.c_int64)),
+                ("element", C.c_int32)]
 
 
 class SnswProblemInfo(C.Structure):
@@ -244,17 +245,20 @@ class Problem:
     def __init__(self, ctx: Context, *, dim, nx, geom_order, dg_order, lattice, sn_order,
                  sigma_t, sigma_s, q, bc_kind=0, psi_inc=0.0, weighting=1, exact_scc_max=10,
                  precision=0, n_threads=0, omega=None, w=None, schedule=0, cache_inverse=0,
-                 psi_inc_tab=None, nodes=None, elem_nodes=None):
+                 psi_inc_tab=None, nodes=None, elem_nodes=None, element=0):
         """q: [E] or [E][n] isotropic, or [D][E][n] per direction (nodal
         values); psi_inc_tab: [D][E][n] incident flux for bc_kind 2.  With
-        elem_nodes ([E][(r+1)^dim] control-point indices into nodes
-        [n_nodes][dim]) the mesh is unstructured: nx = (E, 1[, 1]) and
-        lattice is ignored."""
+        elem_nodes ([E][nv] control-point indices into nodes [n_nodes][dim])
+        the mesh is unstructured: nx = (E, 1[, 1]) and lattice is ignored;
+        element 0: Q_r quads / hexes, nv = (r+1)^dim; 1: P_r triangles (2D),
+        nv = (r+1)(r+2)/2, n = (p+1)(p+2)/2."""
         self.ctx = ctx
         if dim not in (2, 3):
             raise SnswError(-1, "dim must be 2 or 3")
         E = int(np.prod(nx[:dim]))
-        n = (dg_order + 1) ** dim
+        simplex = element == 1
+        n = (dg_order + 1) * (dg_order + 2) // 2 if simplex else (dg_order + 1) ** dim
+        nv = (geom_order + 1) * (geom_order + 2) // 2 if simplex else (geom_order + 1) ** dim
         self._keep = []
 
         def arr(x, size=None):
@@ -275,8 +279,8 @@ class Problem:
             desc.lattice = arr(lattice, L * dim)
         else:
             en = np.ascontiguousarray(np.asarray(elem_nodes, dtype=np.int64))
-            if en.size != E * (geom_order + 1) ** dim:
-                raise ValueError("elem_nodes must have E*(r+1)^dim entries")
+            if en.size != E * nv:
+                raise ValueError(f"elem_nodes must have E*{nv} entries")
             self._keep.append(en)
             nd = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))
             desc.n_nodes = nd.size // dim
@@ -302,6 +306,7 @@ class Problem:
         desc.n_threads = n_threads
         desc.schedule = schedule
         desc.cache_inverse = cache_inverse
+        desc.element = element
         h = C.c_void_p()
         _check(lib().snsw_problem_create(ctx.handle, C.byref(desc), C.byref(h)))
         self.handle = h
@@ -324,7 +329,8 @@ class Problem:
                    exact_scc_max=prob.exact_scc_max if exact_scc_max is None else exact_scc_max,
                    precision=precision, n_threads=n_threads, schedule=schedule,
                    cache_inverse=cache_inverse, nodes=getattr(prob, "nodes", None),
-                   elem_nodes=getattr(prob, "elem_nodes", None))
+                   elem_nodes=getattr(prob, "elem_nodes", None),
+                   element=1 if getattr(prob, "element", "tensor") == "simplex" else 0)
 
     def set_source(self, q, bc_kind=0, psi_inc=0.0, psi_inc_tab=None):
         """Replace the volume source and boundary condition (snsw_problem_set_source)."""

@@ -1,4 +1,5 @@
-// 1D rules and Lagrange bases on [0, 1] for the host setup.
+// 1D rules and Lagrange bases on [0, 1] for the host setup, and the
+// reference triangle of the simplicial elements.
 #include <algorithm>
 #include <cmath>
 
@@ -105,6 +106,115 @@ std::vector<std::vector<double>> lagrange_derivative_monomials(const std::vector
         out[m] = d;
     }
     return out;
+}
+
+// ------------------------------------------------------------- triangles
+// Reference triangle {x, y >= 0, x + y <= 1}, vertices v0 = (0, 0),
+// v1 = (1, 0), v2 = (0, 1).  Nodes of order k sit on the lattice pairs
+// (i, j), i + j <= k, numbered row by row (j slowest).
+
+int tri_index(int k, int i, int j) { return j * (k + 1) - j * (j - 1) / 2 + i; }
+
+std::vector<int32_t> tri_slot_nodes(int k, int s) {
+    std::vector<int32_t> out(k + 1);
+    for (int b = 0; b <= k; ++b) {
+        const int i = s == 0 ? b : (s == 1 ? k - b : 0);
+        const int j = s == 0 ? 0 : (s == 1 ? b : k - b);
+        out[b] = tri_index(k, i, j);
+    }
+    return out;
+}
+
+std::vector<double> tri_geometry_nodes(int r) {
+    std::vector<double> x;
+    for (int j = 0; j <= r; ++j)
+        for (int i = 0; i + j <= r; ++i) {
+            x.push_back((double)i / r);
+            x.push_back((double)j / r);
+        }
+    return x;
+}
+
+std::vector<double> tri_dg_nodes(int p) {
+    const std::vector<double> g = gll01(p);
+    std::vector<double> x;
+    for (int j = 0; j <= p; ++j)
+        for (int i = 0; i + j <= p; ++i) {
+            const bool edge = i == 0 || j == 0 || i + j == p;
+            x.push_back(edge ? g[i] : (double)i / p);
+            x.push_back(edge ? g[j] : (double)j / p);
+        }
+    return x;
+}
+
+TriBasis::TriBasis(const std::vector<double>& nodes, int k_) : k(k_), n((k_ + 1) * (k_ + 2) / 2) {
+    for (int c = 0; c <= k; ++c)
+        for (int a = 0; a + c <= k; ++a) mono.push_back({a, c});
+    // C = V^{-1}, V[node][monomial]: Gauss-Jordan with partial pivoting
+    std::vector<double> V((size_t)n * n), I((size_t)n * n, 0.0);
+    for (int m = 0; m < n; ++m) {
+        I[(size_t)m * n + m] = 1.0;
+        for (int t = 0; t < n; ++t)
+            V[(size_t)m * n + t] = std::pow(nodes[2 * m], mono[t].first) * std::pow(nodes[2 * m + 1], mono[t].second);
+    }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r2 = c + 1; r2 < n; ++r2)
+            if (std::fabs(V[(size_t)r2 * n + c]) > std::fabs(V[(size_t)piv * n + c])) piv = r2;
+        if (std::fabs(V[(size_t)piv * n + c]) < 1e-14) throw Error(SNSW_E_STATE, "triangle nodes are not unisolvent");
+        for (int t = 0; t < n; ++t) {
+            std::swap(V[(size_t)c * n + t], V[(size_t)piv * n + t]);
+            std::swap(I[(size_t)c * n + t], I[(size_t)piv * n + t]);
+        }
+        const double d = 1.0 / V[(size_t)c * n + c];
+        for (int t = 0; t < n; ++t) {
+            V[(size_t)c * n + t] *= d;
+            I[(size_t)c * n + t] *= d;
+        }
+        for (int r2 = 0; r2 < n; ++r2) {
+            if (r2 == c) continue;
+            const double f = V[(size_t)r2 * n + c];
+            if (f == 0.0) continue;
+            for (int t = 0; t < n; ++t) {
+                V[(size_t)r2 * n + t] -= f * V[(size_t)c * n + t];
+                I[(size_t)r2 * n + t] -= f * I[(size_t)c * n + t];
+            }
+        }
+    }
+    C = I;   // C[monomial][basis function]
+}
+
+void TriBasis::eval(double x, double y, double* val, double* dx, double* dy) const {
+    auto pw = [](double t, int e) { return e < 0 ? 0.0 : std::pow(t, e); };
+    for (int m = 0; m < n; ++m) {
+        if (val) val[m] = 0.0;
+        if (dx) dx[m] = 0.0;
+        if (dy) dy[m] = 0.0;
+    }
+    for (int t = 0; t < n; ++t) {
+        const int a = mono[t].first, c = mono[t].second;
+        const double v = pw(x, a) * pw(y, c), vx = a * pw(x, a - 1) * pw(y, c), vy = c * pw(x, a) * pw(y, c - 1);
+        const double* Ct = &C[(size_t)t * n];
+        for (int m = 0; m < n; ++m) {
+            if (val) val[m] += v * Ct[m];
+            if (dx) dx[m] += vx * Ct[m];
+            if (dy) dy[m] += vy * Ct[m];
+        }
+    }
+}
+
+void tri_collapsed_rule(int nq, std::vector<double>& x, std::vector<double>& y, std::vector<double>& w) {
+    std::vector<double> g, gw;
+    gauss_legendre01(nq, g, gw);
+    x.clear();
+    y.clear();
+    w.clear();
+    for (int a = 0; a < nq; ++a)
+        for (int b = 0; b < nq; ++b) {
+            x.push_back(g[a]);
+            y.push_back(g[b] * (1.0 - g[a]));
+            w.push_back(gw[a] * gw[b] * (1.0 - g[a]));
+        }
 }
 
 }  // namespace snsw

@@ -197,7 +197,7 @@ void build_class_schedule(const std::vector<snsw_problem*>& probs, const std::ve
     }
     for (size_t m = 0; m < members.size(); ++m) {
         const HostProblem& hp = probs[members[m]]->hp;
-        const int ns = 2 * hp.dim;
+        const int ns = hp.nslot;
         for (size_t i = 0; i < where[m].size(); ++i)
             if (where[m][i] < 0) throw Error(SNSW_E_STATE, "batch schedule: a pair is missing");
         for (int64_t d = 0; d < hp.D; ++d)
@@ -336,7 +336,8 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
     } else {
         for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
             const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
-            launch_sweep_level(c.dim, c.p, c.mixed, c.inv, c.unstructured, L.table, c.pairs, b, n, class_problem(c), s);
+            launch_sweep_level(c.dim, c.p, c.simplex, c.mixed, c.inv, c.unstructured, L.table, c.pairs, b, n,
+                                   class_problem(c), s);
         }
     }
     HIP_OK(hipGetLastError());
@@ -381,7 +382,7 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
         for (int32_t k = 0; k < count; ++k) {
             const HostProblem& hp = probs[k]->hp;
             const int has_inv = probs[k]->dev->ainv != nullptr ? 1 : 0;
-            const auto kk = std::make_tuple(hp.dim, hp.p, hp.precision, has_inv, hp.unstructured ? 1 : 0);
+            const auto kk = std::make_tuple(hp.dim, hp.p, hp.precision, has_inv, (hp.unstructured ? 1 : 0) + (hp.simplex ? 2 : 0));
             auto it = key.find(kk);
             if (it == key.end()) {
                 it = key.emplace(kk, (int)b->classes.size()).first;
@@ -392,6 +393,7 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
                 // mixed precision and unstructured meshes sweep level by level
                 bc.levels_only = bc.cls.mixed || hp.unstructured;
                 bc.cls.unstructured = hp.unstructured;
+                bc.cls.simplex = hp.simplex;
                 bc.has_inv = has_inv != 0;
                 bc.cls.ticket = (int)b->classes.size();
                 b->classes.push_back(bc);

@@ -41,6 +41,7 @@ struct SweepClass {
     bool persistent = false;
     bool inv = false;                  // cached inverses (every member has them)
     bool unstructured = false;         // members are unstructured meshes (upwind nodes from a table)
+    bool simplex = false;              // members are triangle meshes
     int blocks = 0;                    // persistent grid
     int ticket = 0;                    // index into the ticket array
     const int4* pairs = nullptr;       // device schedule

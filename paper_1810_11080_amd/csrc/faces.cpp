@@ -80,16 +80,19 @@ int face_sym(int dim, int t, int n1, int l) {
 // xi_a = 0 face, so that the normal of the axis formula is the minus
 // element's outward normal.  The plus element's slot is matched to the face
 // by the face symmetry that carries every control point onto its partner.
+//
+// Triangles: the three edge slots run counter-clockwise (v0 -> v1 -> v2), so
+// the axis-0 normal of the slot's own order is already the outward normal:
+// no slot is mirrored and every face has axis 0.
 void unstructured_topology(HostProblem& hp) {
-    const int dim = hp.dim, r = hp.r, p = hp.p, nf = hp.nf, ns = 2 * dim;
+    const int dim = hp.dim, r = hp.r, p = hp.p, nf = hp.nf, ns = hp.simplex ? 3 : 2 * dim;
     const int64_t E = hp.E;
-    int Nv = 1;
-    for (int a = 0; a < dim; ++a) Nv *= r + 1;
+    const int Nv = hp.nv;
     const int nloc = dim == 2 ? r + 1 : (r + 1) * (r + 1);
     std::vector<std::vector<int32_t>> cl(ns), dl(ns);
     for (int s = 0; s < ns; ++s) {
-        cl[s] = slot_local_nodes(dim, r, s);
-        dl[s] = slot_local_nodes(dim, p, s);
+        cl[s] = hp.simplex ? tri_slot_nodes(r, s) : slot_local_nodes(dim, r, s);
+        dl[s] = hp.simplex ? tri_slot_nodes(p, s) : slot_local_nodes(dim, p, s);
     }
     const int nc = dim == 2 ? 2 : 4;
     auto corner = [&](int k) {   // face-local index of corner k
@@ -136,8 +139,8 @@ void unstructured_topology(HostProblem& hp) {
         const auto& rec = recs[f];
         const int64_t em = rec[0].first;
         const int sm = rec[0].second;
-        const int tm = (sm & 1) ? 0 : mirror;   // face index l <- slot index face_sym(tm, l)
-        hp.f_axis[f] = sm / 2;
+        const int tm = ((sm & 1) || hp.simplex) ? 0 : mirror;   // face index l <- slot index face_sym(tm, l)
+        hp.f_axis[f] = hp.simplex ? 0 : sm / 2;
         hp.f_minus[f] = (int32_t)em;
         hp.f_slot_minus[f] = (int8_t)sm;
         std::vector<int64_t> ids(nloc);

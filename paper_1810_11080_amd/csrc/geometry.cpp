@@ -8,6 +8,11 @@
 //                                                         G = -sum_i Omega_i K_i)
 // on a tensor Gauss-Legendre rule with p+r (2D) or p+ceil(3r/2) (3D) points
 // per axis, exact for these polynomial integrands.
+//
+// Triangles (simplicial elements): P_r map at equispaced control points and
+// P_p DG basis (Gauss-Lobatto points on the edges, equispaced inside), on
+// the collapsed Gauss rule with p+r points per direction (exact for total
+// degree 2(p+r)-2, the largest degree of these integrands).
 #include <atomic>
 #include <cmath>
 
@@ -45,14 +50,74 @@ void tensor_tables(int dim, const std::vector<double>& nodes, const std::vector<
     }
 }
 
-// Control points of element e, [(r+1)^dim][dim], local order
-// a + (r+1) (b + (r+1) c): from the structured lattice, or from the element's
-// control-point list on unstructured meshes.
+// Reference tables of an element type: rule points' weights, the map's
+// basis (values [Q][Nv], gradients [Q][Nv][dim]) and the DG basis (values
+// [Q][n], gradients [Q][n][dim]) at the points.
+struct RefTables {
+    int Q = 0, Nv = 0;
+    std::vector<double> w, Vg, Gg, U, GU;
+};
+
+int tensor_points_per_axis(const HostProblem& hp) {
+    return hp.dim == 2 ? hp.p + hp.r : hp.p + (3 * hp.r + 1) / 2;
+}
+
+RefTables reference_tables(const HostProblem& hp, int extra) {
+    const int dim = hp.dim, r = hp.r, p = hp.p;
+    RefTables t;
+    if (hp.simplex) {
+        std::vector<double> x, y;
+        tri_collapsed_rule(p + r + extra, x, y, t.w);
+        t.Q = (int)t.w.size();
+        const TriBasis geo(tri_geometry_nodes(r), r), dg(tri_dg_nodes(p), p);
+        t.Nv = geo.n;
+        t.Vg.resize((size_t)t.Q * geo.n);
+        t.Gg.resize((size_t)t.Q * geo.n * 2);
+        t.U.resize((size_t)t.Q * dg.n);
+        t.GU.resize((size_t)t.Q * dg.n * 2);
+        std::vector<double> dx(10), dy(10);
+        for (int q = 0; q < t.Q; ++q) {
+            geo.eval(x[q], y[q], &t.Vg[(size_t)q * geo.n], dx.data(), dy.data());
+            for (int m = 0; m < geo.n; ++m) {
+                t.Gg[((size_t)q * geo.n + m) * 2 + 0] = dx[m];
+                t.Gg[((size_t)q * geo.n + m) * 2 + 1] = dy[m];
+            }
+            dg.eval(x[q], y[q], &t.U[(size_t)q * dg.n], dx.data(), dy.data());
+            for (int m = 0; m < dg.n; ++m) {
+                t.GU[((size_t)q * dg.n + m) * 2 + 0] = dx[m];
+                t.GU[((size_t)q * dg.n + m) * 2 + 1] = dy[m];
+            }
+        }
+        return t;
+    }
+    const int nq1 = tensor_points_per_axis(hp) + extra;
+    std::vector<double> x1, w1;
+    gauss_legendre01(nq1, x1, w1);
+    std::vector<double> geo_nodes(r + 1);
+    for (int a = 0; a <= r; ++a) geo_nodes[a] = (double)a / r;
+    tensor_tables(dim, geo_nodes, x1, t.Vg, t.Gg);
+    tensor_tables(dim, gll01(p), x1, t.U, t.GU);
+    t.Q = 1;
+    t.Nv = 1;
+    for (int a = 0; a < dim; ++a) { t.Q *= nq1; t.Nv *= r + 1; }
+    t.w.resize(t.Q);
+    for (int q = 0; q < t.Q; ++q) {
+        double ww = 1.0;
+        int rq = q;
+        for (int a = 0; a < dim; ++a) { ww *= w1[rq % nq1]; rq /= nq1; }
+        t.w[q] = ww;
+    }
+    return t;
+}
+
+// Control points of element e, [nv][dim]: tensor elements in the local
+// order a + (r+1) (b + (r+1) c), triangles in lattice order; from the
+// structured lattice, or from the element's control-point list on
+// unstructured meshes.
 void element_ctrl(const HostProblem& hp, int64_t e, double* xe) {
     const int dim = hp.dim, r = hp.r;
     if (hp.unstructured) {
-        int Nv = 1;
-        for (int a = 0; a < dim; ++a) Nv *= r + 1;
+        const int Nv = hp.nv;
         for (int m = 0; m < Nv; ++m) {
             const int64_t id = hp.elem_nodes[(size_t)e * Nv + m];
             for (int c = 0; c < dim; ++c) xe[m * dim + c] = hp.nodes[(size_t)id * dim + c];
@@ -86,7 +151,14 @@ std::vector<double> equispaced(int r) {
 void node_coordinates(const HostProblem& hp, int64_t e0, int64_t count, double* xyz) {
     const int dim = hp.dim, n = hp.n;
     std::vector<double> Vg, Gg;
-    tensor_tables(dim, equispaced(hp.r), gll01(hp.p), Vg, Gg);
+    if (hp.simplex) {
+        const TriBasis geo(tri_geometry_nodes(hp.r), hp.r);
+        const std::vector<double> xn = tri_dg_nodes(hp.p);
+        Vg.resize((size_t)n * geo.n);
+        for (int q = 0; q < n; ++q) geo.eval(xn[2 * q], xn[2 * q + 1], &Vg[(size_t)q * geo.n], nullptr, nullptr);
+    } else {
+        tensor_tables(dim, equispaced(hp.r), gll01(hp.p), Vg, Gg);
+    }
     const int Nv = (int)(Vg.size() / n);
     std::vector<double> xe((size_t)Nv * dim);
     for (int64_t e = e0; e < e0 + count; ++e) {
@@ -102,18 +174,16 @@ void node_coordinates(const HostProblem& hp, int64_t e0, int64_t count, double* 
 
 int volume_rule(const HostProblem& hp, int extra, int64_t e0, int64_t count, double* x, double* wdet,
                 double* basis) {
-    const int dim = hp.dim, r = hp.r, p = hp.p, n = hp.n;
-    const int nq1 = (dim == 2 ? p + r : p + (3 * r + 1) / 2) + extra;
-    int Q = 1;
-    for (int a = 0; a < dim; ++a) Q *= nq1;
-    if (!x) return Q;
-    std::vector<double> x1, w1;
-    gauss_legendre01(nq1, x1, w1);
-    std::vector<double> Vg, Gg, U, GU;
-    tensor_tables(dim, equispaced(r), x1, Vg, Gg);
-    tensor_tables(dim, gll01(p), x1, U, GU);
-    const int Nv = (int)(Vg.size() / Q);
-    if (basis) std::copy(U.begin(), U.end(), basis);
+    const int dim = hp.dim;
+    if (!x) {
+        if (hp.simplex) return (hp.p + hp.r + extra) * (hp.p + hp.r + extra);
+        int Q = 1;
+        for (int a = 0; a < dim; ++a) Q *= tensor_points_per_axis(hp) + extra;
+        return Q;
+    }
+    const RefTables t = reference_tables(hp, extra);
+    const int Q = t.Q, Nv = t.Nv;
+    if (basis) std::copy(t.U.begin(), t.U.end(), basis);
     std::vector<double> xe((size_t)Nv * dim);
     for (int64_t e = e0; e < e0 + count; ++e) {
         element_ctrl(hp, e, xe.data());
@@ -121,8 +191,8 @@ int volume_rule(const HostProblem& hp, int extra, int64_t e0, int64_t count, dou
             double J[3][3] = {{0}}, X[3] = {0, 0, 0};
             for (int m = 0; m < Nv; ++m)
                 for (int c = 0; c < dim; ++c) {
-                    X[c] += xe[m * dim + c] * Vg[(size_t)q * Nv + m];
-                    for (int b = 0; b < dim; ++b) J[c][b] += xe[m * dim + c] * Gg[((size_t)q * Nv + m) * dim + b];
+                    X[c] += xe[m * dim + c] * t.Vg[(size_t)q * Nv + m];
+                    for (int b = 0; b < dim; ++b) J[c][b] += xe[m * dim + c] * t.Gg[((size_t)q * Nv + m) * dim + b];
                 }
             double det;
             if (dim == 2) det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
@@ -130,36 +200,18 @@ int volume_rule(const HostProblem& hp, int extra, int64_t e0, int64_t count, dou
                 det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-            double wq = 1.0;
-            int rq = q;
-            for (int a = 0; a < dim; ++a) { wq *= w1[rq % nq1]; rq /= nq1; }
             for (int c = 0; c < dim; ++c) x[((e - e0) * Q + q) * dim + c] = X[c];
-            wdet[(e - e0) * Q + q] = wq * std::fabs(det);
+            wdet[(e - e0) * Q + q] = t.w[q] * std::fabs(det);
         }
     }
     return Q;
 }
 
 void build_geometry(HostProblem& hp) {
-    const int dim = hp.dim, r = hp.r, p = hp.p, n = hp.n;
-    const int nq1 = dim == 2 ? p + r : p + (3 * r + 1) / 2;
-    std::vector<double> x1, w1;
-    gauss_legendre01(nq1, x1, w1);
-    std::vector<double> geo_nodes(r + 1);
-    for (int a = 0; a <= r; ++a) geo_nodes[a] = (double)a / r;
-    std::vector<double> dg_nodes = gll01(p);
-    std::vector<double> Vg, Gg, U, GU;
-    tensor_tables(dim, geo_nodes, x1, Vg, Gg);
-    tensor_tables(dim, dg_nodes, x1, U, GU);
-    int Q = 1, Nv = 1;
-    for (int a = 0; a < dim; ++a) { Q *= nq1; Nv *= r + 1; }
-    std::vector<double> wq(Q);
-    for (int q = 0; q < Q; ++q) {
-        double ww = 1.0;
-        int rq = q;
-        for (int a = 0; a < dim; ++a) { ww *= w1[rq % nq1]; rq /= nq1; }
-        wq[q] = ww;
-    }
+    const int dim = hp.dim, n = hp.n;
+    const RefTables t = reference_tables(hp, 0);
+    const int Q = t.Q, Nv = t.Nv;
+    const std::vector<double>&wq = t.w, &Gg = t.Gg, &U = t.U, &GU = t.GU;
     hp.M.assign((size_t)hp.E * n * n, 0.0);
     hp.K.assign((size_t)hp.E * dim * n * n, 0.0);
     std::atomic<bool> bad(false);

@@ -5,6 +5,7 @@
 #include <functional>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "snsweep.h"
@@ -32,6 +33,30 @@ void lagrange_eval(const std::vector<double>& nodes, double x, double* val, doub
 // Monomial coefficients (ascending powers) of the derivative of each Lagrange
 // polynomial of `nodes`: out[m][k], k = 0..nn-2.
 std::vector<std::vector<double>> lagrange_derivative_monomials(const std::vector<double>& nodes);
+
+// Triangles (simplicial elements): reference triangle {x, y >= 0, x + y <= 1}
+// with vertices v0 = (0,0), v1 = (1,0), v2 = (0,1); nodes of order k on the
+// lattice pairs (i, j), i + j <= k, numbered row by row (j slowest).
+int tri_index(int k, int i, int j);
+// Element-local nodes of edge slot s in slot order (slot 0: v0 -> v1,
+// slot 1: v1 -> v2, slot 2: v2 -> v0, counter-clockwise).
+std::vector<int32_t> tri_slot_nodes(int k, int s);
+// Node positions [n][2]: control points at (i/r, j/r); DG nodes at the
+// Gauss-Lobatto points (g_i, g_j) on the edges and at (i/p, j/p) inside.
+std::vector<double> tri_geometry_nodes(int r);
+std::vector<double> tri_dg_nodes(int p);
+// Nodal P_k basis of the given nodes (monomial Vandermonde inverse).
+struct TriBasis {
+    int k = 0, n = 0;
+    std::vector<std::pair<int, int>> mono;   // exponents (a, c) of x^a y^c
+    std::vector<double> C;                   // [monomial][basis function]
+    TriBasis(const std::vector<double>& nodes, int k);
+    // values and x / y derivatives of the n basis functions (nullable outputs)
+    void eval(double x, double y, double* val, double* dx, double* dy) const;
+};
+// Collapsed Gauss rule on the triangle: nq x nq points (x = u, y = v (1 - u),
+// weight w_u w_v (1 - u)), exact for total degree 2 nq - 2.
+void tri_collapsed_rule(int nq, std::vector<double>& x, std::vector<double>& y, std::vector<double>& w);
 
 // ------------------------------------------------------------ quadrature.cpp
 // Level-symmetric S_N set: omega [D][3], w [D] (2D: z > 0 half, doubled).
@@ -77,8 +102,10 @@ struct HostProblem {
     double psi_inc = 0.0;
     std::vector<double> lattice;              // [L][dim] (structured meshes)
     bool unstructured = false;                // mesh given as element control-point lists
+    bool simplex = false;                     // P_r triangles with a P_p DG basis (unstructured, 2D)
+    int nv = 0;                               // control points per element
     std::vector<double> nodes;                // [n_nodes][dim] (unstructured)
-    std::vector<int64_t> elem_nodes;          // [E][(r+1)^dim] (unstructured)
+    std::vector<int64_t> elem_nodes;          // [E][nv] (unstructured)
     std::vector<double> omega, w;             // [D][3], [D]
     std::vector<double> sigma_t, sigma_s, q;  // [E], [E], [E][n] (isotropic source)
     std::vector<double> q_dir;                // [D][E][n] direction-dependent source, or empty

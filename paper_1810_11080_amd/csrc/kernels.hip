@@ -45,7 +45,7 @@ constexpr int kIntraGroupShiftDev = 8;   // intra word: group of slot s at bits 
 #endif
 
 template <int DIM, int P>
-struct Shape {
+struct TensorShape {
     static constexpr int Q = P + 1;
     static constexpr int N = DIM == 2 ? Q * Q : Q * Q * Q;
     static constexpr int NF = DIM == 2 ? Q : Q * Q;
@@ -76,7 +76,59 @@ struct Shape {
         }
         return l;
     }
+    // whether node i lies on slot s (the xi_a = 0 face for s = 2a, xi_a = 1 for s = 2a + 1)
+    __host__ __device__ static constexpr bool on(int i, int s) { return coord(i, s / 2) == ((s & 1) ? P : 0); }
 };
+
+// Triangle of order P (simplicial element): nodes on the lattice pairs
+// (i, j), i + j <= P, numbered row by row (j slowest); slots are the edges
+// v0 -> v1 (j = 0), v1 -> v2 (i + j = P), v2 -> v0 (i = 0), each listed from
+// its first vertex.
+template <int P>
+struct TriShape {
+    static constexpr int N = (P + 1) * (P + 2) / 2;
+    static constexpr int NF = P + 1;
+    static constexpr int NS = 3;
+    static constexpr int G = 64 / N;
+    __host__ __device__ static constexpr int index(int i, int j) { return j * (P + 1) - j * (j - 1) / 2 + i; }
+    __host__ __device__ static constexpr int row_of(int m) {
+        int j = 0;
+        while (j < P && m >= index(0, j + 1)) ++j;
+        return j;
+    }
+    __host__ __device__ static constexpr int tn(int s, int b) {
+        return s == 0 ? index(b, 0) : (s == 1 ? index(P - b, b) : index(0, P - b));
+    }
+    __host__ __device__ static constexpr bool on(int m, int s) {
+        const int j = row_of(m), i = m - index(0, j);
+        return s == 0 ? j == 0 : (s == 1 ? i + j == P : i == 0);
+    }
+    __host__ __device__ static constexpr int local(int m, int s) {
+        const int j = row_of(m), i = m - index(0, j);
+        return s == 0 ? i : (s == 1 ? j : P - j);
+    }
+};
+
+// Element shapes: Shape<DIM, P> is the Q_P tensor element, and for
+// P >= kTri the triangle of order P - kTri (2D).
+constexpr int kTri = 16;
+template <int DIM, int P>
+using Shape = std::conditional_t<(P >= kTri), TriShape<P - kTri>, TensorShape<DIM, P>>;
+
+template <int P>
+constexpr bool tri_tables_ok() {
+    using S = TriShape<P>;
+    for (int s = 0; s < S::NS; ++s)
+        for (int b = 0; b < S::NF; ++b) {
+            const int m = S::tn(s, b);
+            if (m < 0 || m >= S::N || !S::on(m, s) || S::local(m, s) != b) return false;
+        }
+    for (int m = 0; m < S::N; ++m)
+        for (int s = 0; s < S::NS; ++s)
+            if (S::on(m, s) && S::tn(s, S::local(m, s)) != m) return false;
+    return true;
+}
+static_assert(tri_tables_ok<1>() && tri_tables_ok<2>() && tri_tables_ok<3>(), "triangle slot tables");
 
 // Layout of one pair's cached A^{-1} block.  Column-major (entry (i, j) at
 // j n + i), except for 3D p = 2 (n = 27): there columns 2c and 2c + 1 are
@@ -113,7 +165,8 @@ constexpr bool inv_layout_ok() {
     return IL::kStride % 2 == 0 || !IL::kPaired;
 }
 static_assert(inv_layout_ok<2, 1>() && inv_layout_ok<2, 2>() && inv_layout_ok<2, 3>() && inv_layout_ok<3, 1>() &&
-                  inv_layout_ok<3, 2>() && inv_layout_ok<3, 3>(),
+                  inv_layout_ok<3, 2>() && inv_layout_ok<3, 3>() && inv_layout_ok<2, kTri + 1>() &&
+                  inv_layout_ok<2, kTri + 2>() && inv_layout_ok<2, kTri + 3>(),
               "A^{-1} block layouts");
 
 // Table entry and problem index read through the constant address space, so
@@ -165,6 +218,7 @@ __device__ __forceinline__ SweepArgs load_args(const SweepArgs* table, int k) {
 template <int DIM, int P, bool U>
 __device__ __forceinline__ int up_node(const SweepArgs& args, int e, int s, int b) {
     using S = Shape<DIM, P>;
+    static_assert(U || P < kTri, "triangles read the upwind node table");
     if constexpr (U) return args.nbr_nodes[((size_t)e * S::NS + s) * S::NF + b];
     else return S::tn(s ^ 1, b);
 }
@@ -223,7 +277,7 @@ __device__ __forceinline__ void assemble_row(const SweepArgs& args, int4 pr, int
         const int nb = args.slot_nbr[(size_t)e * NS + s];
         const bool defer = DEFER && cls != kOut && nb >= 0 && !lagged;
         if (defer) kept |= 1u << s;
-        const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+        const bool on = S::on(row, s);
         if (!on) continue;
         const int la = S::local(row, s);
         double pout[NF], pin[NF];
@@ -553,7 +607,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
         // any that still holds the sentinel is re-read (bounded likewise)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+            const bool on = S::on(row, s);
             if (!(active && on && ((kept >> s) & 1u))) continue;
             const int la = S::local(row, s);
             const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
@@ -765,7 +819,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
             const int nb = nbs[s];
             const bool defer = cls != kOut && nb >= 0 && !lagged;
             if (defer) kept |= 1u << s;
-            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+            const bool on = S::on(row, s);
             if (!on) continue;
             const int la = S::local(row, s);
             double pout[NF], pin[NF];
@@ -1027,7 +1081,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
             const int nb = nbs[s];
             const bool defer = nb >= 0 && !lagged;
             if (defer) kept |= 1u << s;
-            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+            const bool on = S::on(row, s);
             if (!on) continue;
             const int la = S::local(row, s);
             double pin[NF];
@@ -1059,7 +1113,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
         bool need[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+            const bool on = S::on(row, s);
             need[s] = active && on && ((kept >> s) & 1u);
             up[s] = (const gdouble*)(args.psi_cur + ((size_t)d * args.E + (need[s] ? nbs[s] : 0)) * N);
         }
@@ -1101,7 +1155,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
                 double b = rhs;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+                    const bool on = S::on(row, s);
                     if (!(on && ((kept >> s) & 1u))) continue;
                     const int la = S::local(row, s);
 #pragma unroll
@@ -1222,7 +1276,7 @@ __device__ __forceinline__ double inflow_rhs(const SweepArgs& args, int4 pr, int
             kept |= 1u << s;   // read from this sweep's flux after the wait
             continue;
         }
-        const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+        const bool on = S::on(row, s);
         if (!on) continue;
         const int la = S::local(row, s);
         double pin[NF];
@@ -1319,7 +1373,7 @@ __device__ __forceinline__ double inflow_rhs_coop(const SweepArgs& args, int4 pr
     for (int s = 0; s < NS; ++s) {
         const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
         if (cls == kOut || cls == kNone) continue;
-        if (S::coord(row, s / 2) != ((s & 1) ? P : 0)) continue;
+        if (!S::on(row, s)) continue;
         const int l = S::local(row, s);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) rhs += cf[s][c * NF + l];
@@ -1400,7 +1454,7 @@ __device__ __forceinline__ double inflow_rhs_staged(const SweepArgs& args, int4 
     for (int s = 0; s < NS; ++s) {
         const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
         if (cls == kOut || cls == kNone) continue;
-        if (S::coord(row, s / 2) != ((s & 1) ? P : 0)) continue;
+        if (!S::on(row, s)) continue;
         const int l = S::local(row, s);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) rhs += cf[s][c * NF + l];
@@ -1591,7 +1645,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs 
                 const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
                 int kr = 0;
                 if (cls == kKink) kr = args.kink_idx[prs.z + kc++];
-                const bool on = S::coord(row, s / 2) == ((s & 1) ? P : 0);
+                const bool on = S::on(row, s);
                 if (!(on && ((kept >> s) & 1u))) continue;
                 const int la = S::local(row, s);
                 const int nb = args.slot_nbr[(size_t)e * NS + s];
@@ -1807,7 +1861,7 @@ sweep_persistent_staged(PersistArgs pa) {
             for (int s = 0; s < NS; ++s) {
                 const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
                 if (cls == kOut || cls == kNone || !active) continue;
-                if (S::coord(row, s / 2) != ((s & 1) ? P : 0)) continue;
+                if (!S::on(row, s)) continue;
                 const int l = S::local(row, s);
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) rhs += cfl[wave][g][s][c * NF + l];
@@ -1937,12 +1991,18 @@ void launch_factor_tpl(const SweepArgs* table, const int4* pairs, int64_t count,
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
-    if (unstructured)
+    if constexpr (P >= kTri) {
+        // triangles always come with the upwind node table
         hipLaunchKernelGGL((factor_kernel<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
                            table, pairs, count, ainv);
-    else
-        hipLaunchKernelGGL((factor_kernel<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
-                           table, pairs, count, ainv);
+    } else {
+        if (unstructured)
+            hipLaunchKernelGGL((factor_kernel<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
+                               table, pairs, count, ainv);
+        else
+            hipLaunchKernelGGL((factor_kernel<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                               stream, table, pairs, count, ainv);
+    }
 }
 
 template <int DIM, int P>
@@ -2041,10 +2101,16 @@ __global__ void residual_kernel(int64_t len, const double* __restrict__ a, const
 
 }  // namespace
 
-void launch_sweep_level(int dim, int p, bool mixed, bool inv, bool unstructured, const SweepArgs* table,
-                        const int4* pairs, int64_t begin, int64_t count, int problem, hipStream_t stream) {
+void launch_sweep_level(int dim, int p, bool simplex, bool mixed, bool inv, bool unstructured,
+                        const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem,
+                        hipStream_t stream) {
     const bool u = unstructured;
-    if (dim == 2) {
+    if (simplex) {
+        // triangles come as element lists: always the table of upwind nodes
+        if (p == 1) launch_tpl_u<2, kTri + 1, true>(table, pairs, begin, count, problem, mixed, inv, stream);
+        else if (p == 2) launch_tpl_u<2, kTri + 2, true>(table, pairs, begin, count, problem, mixed, inv, stream);
+        else launch_tpl_u<2, kTri + 3, true>(table, pairs, begin, count, problem, mixed, inv, stream);
+    } else if (dim == 2) {
         if (p == 1) launch_tpl<2, 1>(table, pairs, begin, count, problem, mixed, inv, u, stream);
         else if (p == 2) launch_tpl<2, 2>(table, pairs, begin, count, problem, mixed, inv, u, stream);
         else launch_tpl<2, 3>(table, pairs, begin, count, problem, mixed, inv, u, stream);
@@ -2055,15 +2121,22 @@ void launch_sweep_level(int dim, int p, bool mixed, bool inv, bool unstructured,
     }
 }
 
-int64_t ainv_block_stride(int dim, int p) {
+int64_t ainv_block_stride(int dim, int p, bool simplex) {
+    if (simplex)
+        return p == 1 ? InvLayout<2, kTri + 1>::kStride
+                      : p == 2 ? InvLayout<2, kTri + 2>::kStride : InvLayout<2, kTri + 3>::kStride;
     if (dim == 2) return p == 1 ? InvLayout<2, 1>::kStride : p == 2 ? InvLayout<2, 2>::kStride : InvLayout<2, 3>::kStride;
     return p == 1 ? InvLayout<3, 1>::kStride : p == 2 ? InvLayout<3, 2>::kStride : InvLayout<3, 3>::kStride;
 }
 
-void launch_factor(int dim, int p, bool unstructured, const SweepArgs* table, const int4* pairs, int64_t count,
-                   double* ainv, hipStream_t stream) {
+void launch_factor(int dim, int p, bool simplex, bool unstructured, const SweepArgs* table, const int4* pairs,
+                   int64_t count, double* ainv, hipStream_t stream) {
     const bool u = unstructured;
-    if (dim == 2) {
+    if (simplex) {
+        if (p == 1) launch_factor_tpl<2, kTri + 1>(table, pairs, count, ainv, true, stream);
+        else if (p == 2) launch_factor_tpl<2, kTri + 2>(table, pairs, count, ainv, true, stream);
+        else launch_factor_tpl<2, kTri + 3>(table, pairs, count, ainv, true, stream);
+    } else if (dim == 2) {
         if (p == 1) launch_factor_tpl<2, 1>(table, pairs, count, ainv, u, stream);
         else if (p == 2) launch_factor_tpl<2, 2>(table, pairs, count, ainv, u, stream);
         else launch_factor_tpl<2, 3>(table, pairs, count, ainv, u, stream);

@@ -79,17 +79,19 @@ int persistent_blocks_per_cu(int dim, int p, bool inv);
 // Whether the persistent kernel of this shape has a cached-inverse variant.
 bool persistent_uses_inverse(int dim, int p);
 // Launches the level-sweep kernel over schedule entries [begin, begin+count)
-// (begin and count multiples of G); inv: x = A^{-1} b with cached inverses;
+// (begin and count multiples of G); simplex: order-p triangles (2D, always
+// with the upwind node table); inv: x = A^{-1} b with cached inverses;
 // unstructured: upwind nodes from SweepArgs::nbr_nodes; problem: table index
 // of every entry, or -1 when entries name their problem.
-void launch_sweep_level(int dim, int p, bool mixed, bool inv, bool unstructured, const SweepArgs* table,
-                        const int4* pairs, int64_t begin, int64_t count, int problem, hipStream_t stream);
+void launch_sweep_level(int dim, int p, bool simplex, bool mixed, bool inv, bool unstructured,
+                        const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem,
+                        hipStream_t stream);
 // Doubles per pair in the cached A^{-1} array (n^2, or n^2 + 1 where blocks
 // are padded to a 16-byte multiple).
-int64_t ainv_block_stride(int dim, int p);
+int64_t ainv_block_stride(int dim, int p, bool simplex);
 // Computes and stores A^{-1} of schedule entries [0, count) of one problem.
-void launch_factor(int dim, int p, bool unstructured, const SweepArgs* table, const int4* pairs, int64_t count,
-                   double* ainv, hipStream_t stream);
+void launch_factor(int dim, int p, bool simplex, bool unstructured, const SweepArgs* table, const int4* pairs,
+                   int64_t count, double* ainv, hipStream_t stream);
 
 // Start of a sweep, for problems [0, count) of the table: swaps psi_cur and
 // psi_prev of each entry, zeroes the ticket counters of n_tickets schedules

@@ -133,10 +133,22 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
             hp.E *= hp.nx[a];
         }
         if (hp.E > (int64_t)1 << 30) throw Error(SNSW_E_SHAPE, "too many elements");
+        if (desc->element != SNSW_ELEM_TENSOR && desc->element != SNSW_ELEM_SIMPLEX)
+            throw Error(SNSW_E_INVALID_ARG, "element must be TENSOR or SIMPLEX");
+        hp.simplex = desc->element == SNSW_ELEM_SIMPLEX;
+        if (hp.simplex && !desc->elem_nodes)
+            throw Error(SNSW_E_INVALID_ARG, "simplicial elements need an element list (elem_nodes)");
+        if (hp.simplex && hp.dim != 2) throw Error(SNSW_E_UNSUPPORTED, "simplicial elements: triangles (dim 2) only");
         hp.n = 1;
         hp.nf = 1;
+        hp.nv = 1;
         for (int a = 0; a < hp.dim; ++a) hp.n *= hp.p + 1;
         for (int a = 0; a + 1 < hp.dim; ++a) hp.nf *= hp.p + 1;
+        for (int a = 0; a < hp.dim; ++a) hp.nv *= hp.r + 1;
+        if (hp.simplex) {
+            hp.n = (hp.p + 1) * (hp.p + 2) / 2;
+            hp.nv = (hp.r + 1) * (hp.r + 2) / 2;
+        }
         hp.nthreads = desc->n_threads > 0 ? desc->n_threads
                                           : (int)std::max(1u, std::thread::hardware_concurrency());
         hp.weighting = desc->weighting;
@@ -176,8 +188,7 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
             if (desc->schedule == SNSW_SCHED_PERSISTENT)
                 throw Error(SNSW_E_UNSUPPORTED, "unstructured meshes sweep on the LEVELS schedule");
             hp.schedule = SNSW_SCHED_LEVELS;
-            int64_t Nv = 1;
-            for (int a = 0; a < hp.dim; ++a) Nv *= hp.r + 1;
+            const int64_t Nv = hp.nv;
             hp.nodes.assign(desc->nodes, desc->nodes + desc->n_nodes * hp.dim);
             check_finite(hp.nodes.data(), hp.nodes.size(), "nodes");
             hp.elem_nodes.assign(desc->elem_nodes, desc->elem_nodes + hp.E * Nv);

@@ -277,7 +277,8 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
                 const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
                 if (prof) prof->begin(s);
-                launch_sweep_level(c.dim, c.p, c.mixed, c.inv, c.unstructured, L.table, c.pairs, b, n, class_problem(c), s);
+                launch_sweep_level(c.dim, c.p, c.simplex, c.mixed, c.inv, c.unstructured, L.table, c.pairs, b, n,
+                                   class_problem(c), s);
                 if (prof) prof->end(s);
             }
         }
@@ -425,14 +426,14 @@ void device_upload(snsw_problem* prob) {
     HIP_OK(hipMemsetAsync(dp->error, 0, sizeof(int32_t), s));
     // cached inverses: D*E blocks of about n^2 doubles
     {
-        const size_t need = sizeof(double) * (size_t)hp.D * hp.E * ainv_block_stride(hp.dim, hp.p);
+        const size_t need = sizeof(double) * (size_t)hp.D * hp.E * ainv_block_stride(hp.dim, hp.p, hp.simplex);
         bool cache = false;
         if (hp.precision == SNSW_PREC_FP64 && hp.cache_inverse != SNSW_CACHE_OFF) {
             size_t free_b = 0, total_b = 0;
             HIP_OK(hipMemGetInfo(&free_b, &total_b));
             cache = hp.cache_inverse == SNSW_CACHE_ON || need <= free_b / 2;
         }
-        if (cache) dp->ainv = dalloc<double>(dp, (size_t)hp.D * hp.E * ainv_block_stride(hp.dim, hp.p));
+        if (cache) dp->ainv = dalloc<double>(dp, (size_t)hp.D * hp.E * ainv_block_stride(hp.dim, hp.p, hp.simplex));
         hp.inverse_cached = cache ? 1 : 0;
     }
     SweepClass& c = dp->cls;
@@ -440,6 +441,7 @@ void device_upload(snsw_problem* prob) {
     c.p = hp.p;
     c.mixed = hp.precision == SNSW_PREC_MIXED;
     c.unstructured = hp.unstructured;
+    c.simplex = hp.simplex;
     c.persistent = hp.schedule == SNSW_SCHED_PERSISTENT;
     c.inv = dp->ainv != nullptr && (!c.persistent || persistent_uses_inverse(hp.dim, hp.p));
     c.ticket = 0;
@@ -462,7 +464,7 @@ void device_upload(snsw_problem* prob) {
         HIP_OK(hipMemcpyAsync(dp->table, &a, sizeof(a), hipMemcpyHostToDevice, s));
     }
     if (dp->ainv) {
-        launch_factor(hp.dim, hp.p, hp.unstructured, dp->table, dp->pairs, hp.level_off.back(), dp->ainv, s);
+        launch_factor(hp.dim, hp.p, hp.simplex, hp.unstructured, dp->table, dp->pairs, hp.level_off.back(), dp->ainv, s);
         HIP_OK(hipGetLastError());
     }
     HIP_OK(hipStreamSynchronize(s));

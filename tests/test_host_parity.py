@@ -29,6 +29,13 @@ CASES = {
     "u_shell": lambda: W.annulus_shell_3d(nr=2, nt=8, nz=2, p=2, sn_order=4),
     "u_cyclic2d": lambda: W.as_unstructured(W.small(dim=2, n=12, r=3, p=2, N=8, amp=0.3 / 12, freq=3), 11),
     "u_warp3d": lambda: W.as_unstructured(W.small(dim=3, n=4, r=2, p=2, N=4, amp=0.08, freq=1), 12),
+    # curved triangles (renumbered, every element's vertex order turned at
+    # random): a warped square, a closed annulus with sign changes of
+    # Omega . n and cycles, both at several orders
+    "t_square": lambda: W.tri_square(n=6, r=2, p=2, sn_order=4),
+    "t_square_q1p1": lambda: W.tri_square(n=8, r=1, p=1, sn_order=8),
+    "t_annulus": lambda: W.tri_annulus(nr=3, nt=16, r=3, p=2, sn_order=4),
+    "t_annulus_p3": lambda: W.tri_annulus(nr=2, nt=12, r=2, p=3, sn_order=8),
 }
 
 
@@ -142,6 +149,21 @@ def test_node_coordinates_and_volume_rule(ctx, dim, r, p):
     assert rel_err(basis, g.U) < 1e-14
 
 
+@pytest.mark.parametrize("r,p", [(2, 2), (3, 1), (1, 3)])
+def test_triangle_node_coordinates_and_volume_rule(ctx, r, p):
+    """The same on curved triangles (collapsed Gauss rule)."""
+    from oracle.simplex import SimplexGeometry
+    from paper_1810_11080_amd import Problem
+    wp = W.tri_annulus(nr=2, nt=8, r=r, p=p, sn_order=4)
+    P = Problem.from_workload(ctx, wp)
+    g = SimplexGeometry(wp.nodes[wp.elem_nodes], r, p, extra_points=2)
+    assert rel_err(P.node_coordinates(), g.dg_node_positions()) < 1e-14
+    x, wd, basis = P.volume_rule(extra=2)
+    assert rel_err(x, g.x) < 1e-14
+    assert rel_err(wd, g.wq[None, :] * g.detJ) < 1e-13
+    assert rel_err(basis, g.U) < 1e-13
+
+
 def test_set_source_validation(ctx):
     from paper_1810_11080_amd import Problem
     from paper_1810_11080_amd.binding import SnswError
@@ -180,3 +202,20 @@ def test_unstructured_input_errors(ctx):
     with pytest.raises(SnswError) as ei:
         Problem.from_workload(ctx, wp, schedule=1)
     assert ei.value.code == -9
+    # triangles: only as element lists, only in 2D, with (r+1)(r+2)/2 control
+    # points per element
+    tw = W.tri_square(n=2, r=2, p=1, sn_order=2)
+    E = tw.n_elements
+    with pytest.raises(SnswError) as ei:
+        Problem(ctx, dim=2, nx=(E, 1), geom_order=2, dg_order=1, lattice=np.zeros(((2 * E + 1) * 3, 2)), sn_order=2,
+                sigma_t=tw.sigma_t, sigma_s=tw.sigma_s, q=tw.q, element=1)
+    assert ei.value.code == -1
+    with pytest.raises(SnswError) as ei:
+        Problem(ctx, dim=3, nx=(E, 1, 1), geom_order=2, dg_order=1, lattice=None, sn_order=2,
+                sigma_t=tw.sigma_t, sigma_s=tw.sigma_s, q=tw.q, nodes=np.zeros((len(tw.nodes), 3)),
+                elem_nodes=tw.elem_nodes, element=1)
+    assert ei.value.code == -9
+    with pytest.raises(ValueError):
+        Problem(ctx, dim=2, nx=(E, 1), geom_order=2, dg_order=1, lattice=None, sn_order=2,
+                sigma_t=tw.sigma_t, sigma_s=tw.sigma_s, q=tw.q, nodes=tw.nodes,
+                elem_nodes=tw.elem_nodes[:, :5], element=1)
