@@ -112,6 +112,23 @@ extern "C" {
 #define SNSW_ELEM_TENSOR   0
 #define SNSW_ELEM_SIMPLEX  1
 
+/* Integration of the face matrices (eqs. localFDiagonalMatrix,
+ * localFOffDiagonalMatrix) on faces where Omega . n changes sign, whose
+ * integrands are only piecewise smooth (section 2, end):
+ *   EXACT   2D: split at the real roots of the polynomial Omega . N(s),
+ *           Gauss on each piece (exact); 3D: fixed composite Gauss rule on
+ *           4 x 4 sub-squares of the face (exact without a sign change);
+ *   ROMBERG adaptive Romberg, the paper's choice: Romberg's table (up to 6
+ *           rows) on an interval, halved with half the tolerance until two
+ *           successive diagonal entries agree to the tolerance (or to 1e-14
+ *           of the largest entry); faces of hexahedra iterated (t outer,
+ *           inner tolerance a tenth).  Absolute tolerance face_tol times
+ *           int |Omega . N| over the face (face_tol <= 0: 1e-10).
+ * Which faces change sign is decided as for EXACT, and faces without a sign
+ * change keep their exact Gauss rule under both.                           */
+#define SNSW_FACE_EXACT    0
+#define SNSW_FACE_ROMBERG  1
+
 typedef struct snsw_ctx snsw_ctx;
 typedef struct snsw_problem snsw_problem;
 
@@ -179,6 +196,8 @@ typedef struct {
     const int64_t* elem_nodes;
     int32_t element;         /* SNSW_ELEM_*: element type of an unstructured
                                 mesh (SIMPLEX needs elem_nodes and dim 2)   */
+    int32_t face_rule;       /* SNSW_FACE_*                                   */
+    double  face_tol;        /* relative tolerance of SNSW_FACE_ROMBERG       */
 } snsw_problem_desc;
 
 /* Builds the discretisation and the sweep schedule (section 3): quadrature,
@@ -279,6 +298,21 @@ int snsw_get_removed_edges(const snsw_problem* prob, int d, int32_t* down,
                            int32_t* up, int64_t cap, int64_t* count);
 /* ASAP level of every element in the cut graph of direction d, [E].         */
 int snsw_get_levels(const snsw_problem* prob, int d, int32_t* level);
+
+/* Upwind integrals of face f (0 <= f < n_faces) for direction d as the setup
+ * computes them with the problem's face rule, before near-empty sides are
+ * dropped (eqs. localFDiagonalMatrix, localFOffDiagonalMatrix): *cls = 0 when
+ * Omega . N >= 0 on the whole face, 1 when <= 0, 2 when it changes sign;
+ * *mp = int max(Omega . N, 0), *mm = int max(-Omega . N, 0) over the
+ * reference face; for class 2, Pp / Pm [nf][nf] = the same integrals
+ * weighted by the products of the face's trace basis functions (zero for
+ * the other classes).  N is the area-scaled normal from the face's minus
+ * to its plus element.  Faces: on a lattice numbered per axis a (faces on
+ * the planes xi_a = const, x fastest), offset by the counts of the earlier
+ * axes; on element lists ordered by the (element, slot) of their minus
+ * side.  Every output is nullable; host arrays.  Introspection for tests.  */
+int snsw_get_face_integrals(const snsw_problem* prob, int d, int64_t f, int32_t* cls, double* mp,
+                            double* mm, double* Pp, double* Pm);
 
 /* ------------------------------------------------------------------- sweep
  * One lagged transport sweep over all directions (eq. laggedSourceIteration):

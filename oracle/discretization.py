@@ -57,6 +57,8 @@ class Discretization:
                                                simplex=self.simplex)
         else:
             self.faces = FaceSet(prob.lattice, self.dim, self.nx, self.r, self.p)
+        if getattr(prob, "face_rule", "exact") == "romberg":
+            self.faces.romberg_tol = float(getattr(prob, "face_tol", 1e-10))
         self.sigma_t = np.asarray(prob.sigma_t, dtype=np.float64)
         self.sigma_s = np.asarray(prob.sigma_s, dtype=np.float64)
         self.q = np.asarray(prob.q, dtype=np.float64)

@@ -29,6 +29,13 @@ sign; it uses Romberg integration with an unstated tolerance).  Reading:
   ceil((r+2p)/2) Gauss points per piece.
 * 3D: fixed composite rule, K x K sub-squares (K = 4) with (p+r)^2 Gauss points
   each (exact on faces without a sign change).
+* With ``romberg_tol`` set (the paper's choice for these integrands; see
+  the ``romberg`` module), every face where Omega . N changes sign -- 2D: a
+  root of g in (0,1); 3D: both signs of g at the points of the fixed
+  composite rule -- is integrated instead by adaptive Romberg to the
+  absolute tolerance romberg_tol * int |g| ds_ref (int |g| from the rule
+  above); the other faces keep their exact Gauss rule, and so do the faces
+  along the direction (dropped below).
 * Interior faces: a side whose inflow measure int max(-/+g, 0) ds_ref is at
   most tau = 1e-12 times int |g| ds_ref is dropped entirely (its P is set to
   zero), so the operator and the dependency graph agree; a face along the
@@ -43,8 +50,26 @@ import numpy as np
 
 from . import basis
 from . import simplex as simplex_ref
+from .romberg import romberg, romberg_square
 
 TAU = 1e-12
+
+
+class _Poly1D:
+    """Lagrange polynomials of a node set as monomial coefficients (inverse
+    Vandermonde), for many evaluations: val(x) (k, n), der(x) (k, n)."""
+
+    def __init__(self, nodes):
+        nodes = np.asarray(nodes, dtype=np.float64)
+        self.n = len(nodes)
+        self.C = np.linalg.inv(np.vander(nodes, self.n, increasing=True))
+        self.dC = self.C[1:] * np.arange(1, self.n)[:, None]
+
+    def val(self, x):
+        return np.vander(x, self.n, increasing=True) @ self.C
+
+    def der(self, x):
+        return np.vander(x, self.n - 1, increasing=True) @ self.dC
 KINK_SUBDIV_3D = 4
 
 
@@ -129,6 +154,8 @@ class FaceSet:
             self.slot_face[:, sl] = fid
             self.slot_side[:, sl] = side
             self.slot_trace[:, sl, :] = self.trace_nodes(sl)[None, :]
+
+    romberg_tol = None   # relative tolerance of adaptive Romberg on sign-changing faces, or None
 
     def _finish(self):
         self.n_faces = len(self.axis)
@@ -381,6 +408,52 @@ class FaceSet:
         roots.sort(axis=1)
         return np.concatenate([np.zeros((F, 1)), roots, np.ones((F, 1))], axis=1)
 
+    def _normal_one(self, f: int, s: np.ndarray, t: float = 0.0) -> np.ndarray:
+        """N of face f at the points (s_k) (2D) or (s_k, t) (3D), (k, dim)."""
+        return self._normal_fast(f, np.asarray(s, dtype=np.float64), t, _Poly1D(self._geo_nodes))
+
+    def _normal_fast(self, f, s, t, geo):
+        X = self.ctrl[f]
+        if self.dim == 2:
+            tg = geo.der(s) @ X
+            sgn = 1.0 if self.axis[f] == 0 else -1.0
+            return np.stack([sgn * tg[:, 1], -sgn * tg[:, 0]], axis=1)
+        n1 = self.r + 1
+        Xg = X.reshape(n1, n1, 3)                     # [bt][bs][c]
+        Vt, Dt = geo.val(np.array([t]))[0], geo.der(np.array([t]))[0]
+        a = np.einsum("qi,ji->jqc" if False else "qi,jic->qjc", geo.der(s), Xg)   # d/ds at each bt row
+        b = np.einsum("qi,jic->qjc", geo.val(s), Xg)
+        t1 = np.einsum("j,qjc->qc", Vt, a)             # x_s
+        t2 = np.einsum("j,qjc->qc", Dt, b)             # x_t
+        n12 = np.stack([t1[:, 1] * t2[:, 2] - t1[:, 2] * t2[:, 1],
+                        t1[:, 2] * t2[:, 0] - t1[:, 0] * t2[:, 2],
+                        t1[:, 0] * t2[:, 1] - t1[:, 1] * t2[:, 0]], axis=1)
+        return -n12 if self.axis[f] == 1 else n12
+
+    def _romberg_face(self, f: int, om: np.ndarray, tol: float):
+        """(P_plus, P_minus, m_plus, m_minus) of face f by adaptive Romberg."""
+        nf = self.nf
+        geo, dg = _Poly1D(self._geo_nodes), _Poly1D(self._dg_nodes)
+
+        def values(g, phi):
+            gp, gm = np.maximum(g, 0.0), np.maximum(-g, 0.0)
+            pp = (gp[:, None, None] * phi[:, :, None] * phi[:, None, :]).reshape(len(g), -1)
+            pm = (gm[:, None, None] * phi[:, :, None] * phi[:, None, :]).reshape(len(g), -1)
+            return np.concatenate([pp, pm, gp[:, None], gm[:, None]], axis=1)
+
+        if self.dim == 2:
+            def F(s):
+                return values(self._normal_fast(f, s, 0.0, geo) @ om, dg.val(s))
+            out = romberg(F, 0.0, 1.0, tol)
+        else:
+            def F(s, t):
+                Vt = dg.val(np.array([t]))[0]
+                phi = (Vt[None, :, None] * dg.val(s)[:, None, :]).reshape(len(s), -1)   # t slow, s fast
+                return values(self._normal_fast(f, s, t, geo) @ om, phi)
+            out = romberg_square(F, tol)
+        k = nf * nf
+        return out[:k].reshape(nf, nf), out[k:2 * k].reshape(nf, nf), out[2 * k], out[2 * k + 1]
+
     def face_points_physical(self, s: np.ndarray, per_face: bool) -> np.ndarray:
         """Physical coordinates of face parameter points, (F, Q, dim)."""
         if self.dim == 2:
@@ -437,6 +510,15 @@ class FaceSet:
                 Lm = np.einsum("fq,fq,qa->fa", wm, fvals, self.rule3_phi)
         mp = wp.sum(axis=1)
         mm = wm.sum(axis=1)
+        if self.romberg_tol is not None:
+            if dim == 2:
+                kink = bp[:, 1] < 1.0
+            else:
+                kink = (g > 0.0).any(axis=1) & (g < 0.0).any(axis=1)
+            # faces along the direction are dropped below: no Romberg there
+            kink &= ~(self.interior & (mp + mm <= TAU * self.n_area))
+            for f in np.nonzero(kink)[0]:
+                Pp[f], Pm[f], mp[f], mm[f] = self._romberg_face(f, om, self.romberg_tol * (mp[f] + mm[f]))
         mabs = mp + mm
         # a face along the direction (int |g| at most tau |int N|: Omega . N
         # vanishes up to rounding) couples nothing; otherwise a side whose

@@ -32,7 +32,7 @@ class SnswProblemDesc(C.Structure):
                 ("precision", C.c_int32), ("n_threads", C.c_int32), ("schedule", C.c_int32),
                 ("cache_inverse", C.c_int32), ("psi_inc_tab", c_double_p),
                 ("n_nodes", C.c_int64), ("nodes", c_double_p), ("elem_nodes", C.POINTER(C.c_int64)),
-                ("element", C.c_int32)]
+                ("element", C.c_int32), ("face_rule", C.c_int32), ("face_tol", C.c_double)]
 
 
 class SnswProblemInfo(C.Structure):
@@ -100,6 +100,8 @@ SIGNATURES = {
     "snsw_get_removed_edges": (C.c_int, [C.c_void_p, C.c_int, c_int32_p, c_int32_p, C.c_int64,
                                          c_int64_p]),
     "snsw_get_levels": (C.c_int, [C.c_void_p, C.c_int, c_int32_p]),
+    "snsw_get_face_integrals": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, c_int32_p, c_double_p, c_double_p,
+                                          c_double_p, c_double_p]),
     "snsw_sweep": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "snsw_reset": (C.c_int, [C.c_void_p]),
     "snsw_synchronize": (C.c_int, [C.c_void_p]),
@@ -245,13 +247,15 @@ class Problem:
     def __init__(self, ctx: Context, *, dim, nx, geom_order, dg_order, lattice, sn_order,
                  sigma_t, sigma_s, q, bc_kind=0, psi_inc=0.0, weighting=1, exact_scc_max=10,
                  precision=0, n_threads=0, omega=None, w=None, schedule=0, cache_inverse=0,
-                 psi_inc_tab=None, nodes=None, elem_nodes=None, element=0):
+                 psi_inc_tab=None, nodes=None, elem_nodes=None, element=0, face_rule=0, face_tol=0.0):
         """q: [E] or [E][n] isotropic, or [D][E][n] per direction (nodal
         values); psi_inc_tab: [D][E][n] incident flux for bc_kind 2.  With
         elem_nodes ([E][nv] control-point indices into nodes [n_nodes][dim])
         the mesh is unstructured: nx = (E, 1[, 1]) and lattice is ignored;
         element 0: Q_r quads / hexes, nv = (r+1)^dim; 1: P_r triangles (2D),
-        nv = (r+1)(r+2)/2, n = (p+1)(p+2)/2."""
+        nv = (r+1)(r+2)/2, n = (p+1)(p+2)/2.  face_rule 1: adaptive Romberg
+        on faces where Omega . n changes sign, relative tolerance face_tol
+        (<= 0: 1e-10)."""
         self.ctx = ctx
         if dim not in (2, 3):
             raise SnswError(-1, "dim must be 2 or 3")
@@ -307,6 +311,8 @@ class Problem:
         desc.schedule = schedule
         desc.cache_inverse = cache_inverse
         desc.element = element
+        desc.face_rule = face_rule
+        desc.face_tol = face_tol
         h = C.c_void_p()
         _check(lib().snsw_problem_create(ctx.handle, C.byref(desc), C.byref(h)))
         self.handle = h
@@ -330,7 +336,9 @@ class Problem:
                    precision=precision, n_threads=n_threads, schedule=schedule,
                    cache_inverse=cache_inverse, nodes=getattr(prob, "nodes", None),
                    elem_nodes=getattr(prob, "elem_nodes", None),
-                   element=1 if getattr(prob, "element", "tensor") == "simplex" else 0)
+                   element=1 if getattr(prob, "element", "tensor") == "simplex" else 0,
+                   face_rule=1 if getattr(prob, "face_rule", "exact") == "romberg" else 0,
+                   face_tol=getattr(prob, "face_tol", 1e-10))
 
     def set_source(self, q, bc_kind=0, psi_inc=0.0, psi_inc_tab=None):
         """Replace the volume source and boundary condition (snsw_problem_set_source)."""
@@ -423,6 +431,16 @@ class Problem:
         lev = np.zeros(self.E, dtype=np.int32)
         _check(lib().snsw_get_levels(self.handle, d, _dptr(lev, C.c_int32)))
         return lev
+
+    def face_integrals(self, d: int, f: int, nf: int):
+        """(class, m_plus, m_minus, P_plus, P_minus) of face f, direction d."""
+        cls = np.zeros(1, dtype=np.int32)
+        m = np.zeros(2)
+        Pp, Pm = np.zeros((nf, nf)), np.zeros((nf, nf))
+        _check(lib().snsw_get_face_integrals(self.handle, d, f, _dptr(cls, C.c_int32), _dptr(m[0:], C.c_double),
+                                             _dptr(m[1:], C.c_double), _dptr(Pp, C.c_double),
+                                             _dptr(Pm, C.c_double)))
+        return int(cls[0]), float(m[0]), float(m[1]), Pp, Pm
 
     # ------------------------------------------------------------------ device
     def sweep(self, phi_in, phi_out, psi_out=None):

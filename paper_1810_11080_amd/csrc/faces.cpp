@@ -19,11 +19,14 @@
 //       (degree r-1 <= 2) and using ceil((r+2p)/2) Gauss points per piece;
 //   3D: with a fixed composite rule of 4x4 sub-squares, (p+r)^2 Gauss points
 //       each (the rule also decides whether a sign change is present).
+// With SNSW_FACE_ROMBERG the sign-changing faces are integrated instead by
+// adaptive Romberg (below) to the absolute tolerance face_tol * int |g|.
 // Interior faces: a side whose measure int max(+-g,0) is at most 1e-12 of
 // int |g| is dropped (matrix set to zero), so the operator and the graph
 // agree.
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <map>
 #include <string>
 
@@ -413,6 +416,168 @@ void face_geometry(HostProblem& hp) {
 }
 
 // ---------------------------------------------------------------------------
+// Adaptive Romberg integration of a sign-changing face (SNSW_FACE_ROMBERG;
+// section 2 names Romberg for these piecewise smooth integrands without a
+// tolerance or a refinement rule).  Reading: Romberg's table on [a, b]
+// (trapezoid sums with 1, 2, 4, ... panels and Richardson's extrapolation)
+// for up to 6 rows; the interval is accepted, from the third row on, when
+// two successive diagonal entries differ by at most its tolerance in the
+// max-norm over the components (or by 1e-14 times the largest component, the
+// rounding level of the sums); otherwise it is halved, each half with half
+// the tolerance, down to 30 halvings.  Hexahedron faces: iterated, the outer
+// rule over t of the inner integral over s (inner tolerance a tenth of the
+// outer).  The components are P_plus, P_minus (nf x nf each), m_plus,
+// m_minus.
+
+namespace {
+
+constexpr int kRombergRows = 6;
+constexpr int kRombergDepth = 30;
+
+// f(s, k, out): the m components at the k points s, out[k][m]
+using PointFn = std::function<void(const double*, int, double*)>;
+
+void romberg(const PointFn& f, int m, double a, double b, double tol, int depth, double* result) {
+    const double h = b - a;
+    std::vector<double> prev((size_t)(kRombergRows + 1) * m), cur((size_t)(kRombergRows + 1) * m);
+    std::vector<double> vals(2 * (size_t)m), pts;
+    const double ends[2] = {a, b};
+    f(ends, 2, vals.data());
+    for (int c = 0; c < m; ++c) prev[c] = 0.5 * h * (vals[c] + vals[(size_t)m + c]);
+    for (int k = 1; k <= kRombergRows; ++k) {
+        const int n_new = 1 << (k - 1);
+        const double hk = h / (double)(1 << k);
+        pts.resize(n_new);
+        for (int i = 0; i < n_new; ++i) pts[i] = a + hk * (2.0 * i + 1.0);
+        vals.resize((size_t)n_new * m);
+        f(pts.data(), n_new, vals.data());
+        for (int c = 0; c < m; ++c) {
+            double sum = 0.0;
+            for (int i = 0; i < n_new; ++i) sum += vals[(size_t)i * m + c];
+            cur[c] = 0.5 * prev[c] + hk * sum;
+        }
+        double p4 = 1.0;
+        for (int j = 1; j <= k; ++j) {
+            p4 *= 4.0;
+            for (int c = 0; c < m; ++c) {
+                const double t = cur[(size_t)(j - 1) * m + c];
+                cur[(size_t)j * m + c] = t + (t - prev[(size_t)(j - 1) * m + c]) / (p4 - 1.0);
+            }
+        }
+        if (k >= 2) {
+            double diff = 0.0, big = 0.0;
+            for (int c = 0; c < m; ++c) {
+                diff = std::max(diff, std::fabs(cur[(size_t)k * m + c] - prev[(size_t)(k - 1) * m + c]));
+                big = std::max(big, std::fabs(cur[(size_t)k * m + c]));
+            }
+            if (diff <= std::max(tol, 1e-14 * big)) {
+                std::copy(&cur[(size_t)k * m], &cur[(size_t)k * m] + m, result);
+                return;
+            }
+        }
+        prev.swap(cur);
+    }
+    if (depth >= kRombergDepth) {
+        std::copy(&prev[(size_t)kRombergRows * m], &prev[(size_t)kRombergRows * m] + m, result);
+        return;
+    }
+    const double mid = 0.5 * (a + b);
+    std::vector<double> left(m), right(m);
+    romberg(f, m, a, mid, 0.5 * tol, depth + 1, left.data());
+    romberg(f, m, mid, b, 0.5 * tol, depth + 1, right.data());
+    for (int c = 0; c < m; ++c) result[c] = left[c] + right[c];
+}
+
+// Components at one face point from g = Omega . N and the trace values phi.
+void face_components(double g, const double* phi, int nf, double* out) {
+    const double gp = std::max(g, 0.0), gm = std::max(-g, 0.0);
+    for (int i = 0; i < nf; ++i)
+        for (int j = 0; j < nf; ++j) {
+            out[i * nf + j] = gp * phi[i] * phi[j];
+            out[nf * nf + i * nf + j] = gm * phi[i] * phi[j];
+        }
+    out[2 * nf * nf] = gp;
+    out[2 * nf * nf + 1] = gm;
+}
+
+void romberg_face(const HostProblem& hp, int64_t f, const double* om, double tol, double& mp, double& mm,
+                  double* Pp, double* Pm) {
+    const int dim = hp.dim, r = hp.r, p = hp.p, nf = hp.nf, m = 2 * nf * nf + 2;
+    std::vector<double> geo(r + 1);
+    for (int a = 0; a <= r; ++a) geo[a] = (double)a / r;
+    const std::vector<double> dg = gll01(p);
+    std::vector<double> out(m);
+    if (dim == 2) {
+        const double* mo = &hp.fnd.mono[(size_t)f * 2 * r];
+        PointFn fn = [&](const double* s, int k, double* v) {
+            double phi[8];
+            for (int q = 0; q < k; ++q) {
+                double g = 0.0, sp = 1.0;
+                for (int c = 0; c < r; ++c) {
+                    g += (om[0] * mo[c] + om[1] * mo[r + c]) * sp;
+                    sp *= s[q];
+                }
+                lagrange_eval(dg, s[q], phi, nullptr);
+                face_components(g, phi, nf, v + (size_t)q * m);
+            }
+        };
+        romberg(fn, m, 0.0, 1.0, tol, 0, out.data());
+    } else {
+        const double* X = &hp.f_ctrl[(size_t)f * (r + 1) * (r + 1) * 3];
+        const double sgn = hp.f_axis[f] == 1 ? -1.0 : 1.0;
+        auto point = [&](double s, double t, double* v) {
+            double Vs[4], Ds[4], Vt[4], Dt[4], us[4], ut[4], phi[16];
+            lagrange_eval(geo, s, Vs, Ds);
+            lagrange_eval(geo, t, Vt, Dt);
+            double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0};
+            for (int bt = 0; bt <= r; ++bt)
+                for (int bs = 0; bs <= r; ++bs) {
+                    const double* x = &X[(bt * (r + 1) + bs) * 3];
+                    for (int c = 0; c < 3; ++c) {
+                        t1[c] += x[c] * Ds[bs] * Vt[bt];
+                        t2[c] += x[c] * Vs[bs] * Dt[bt];
+                    }
+                }
+            const double N0 = sgn * (t1[1] * t2[2] - t1[2] * t2[1]);
+            const double N1 = sgn * (t1[2] * t2[0] - t1[0] * t2[2]);
+            const double N2 = sgn * (t1[0] * t2[1] - t1[1] * t2[0]);
+            lagrange_eval(dg, s, us, nullptr);
+            lagrange_eval(dg, t, ut, nullptr);
+            for (int bt = 0; bt <= p; ++bt)
+                for (int bs = 0; bs <= p; ++bs) phi[bt * (p + 1) + bs] = us[bs] * ut[bt];
+            face_components(om[0] * N0 + om[1] * N1 + om[2] * N2, phi, nf, v);
+        };
+        PointFn outer = [&](const double* t, int k, double* v) {
+            for (int q = 0; q < k; ++q) {
+                const double tq = t[q];
+                PointFn inner = [&](const double* s, int ks, double* w) {
+                    for (int i = 0; i < ks; ++i) point(s[i], tq, w + (size_t)i * m);
+                };
+                romberg(inner, m, 0.0, 1.0, 0.1 * tol, 0, v + (size_t)q * m);
+            }
+        };
+        romberg(outer, m, 0.0, 1.0, tol, 0, out.data());
+    }
+    std::copy(out.begin(), out.begin() + nf * nf, Pp);
+    std::copy(out.begin() + nf * nf, out.begin() + 2 * nf * nf, Pm);
+    mp = out[2 * nf * nf];
+    mm = out[2 * nf * nf + 1];
+}
+
+// Romberg replaces the fixed rule on a sign-changing face, except on a face
+// along the direction (int |g| at most 1e-12 |int N|), which the graph drops.
+void maybe_romberg(const HostProblem& hp, int64_t f, const double* om, double& mp, double& mm, double* Pp,
+                   double* Pm) {
+    if (hp.face_rule != SNSW_FACE_ROMBERG) return;
+    double na = 0.0;
+    for (int k = 0; k < hp.dim; ++k) na += hp.Nint[(size_t)f * hp.dim + k] * hp.Nint[(size_t)f * hp.dim + k];
+    const bool interior = hp.f_minus[f] >= 0 && hp.f_plus[f] >= 0;
+    if (interior && mp + mm <= 1e-12 * std::sqrt(na)) return;
+    romberg_face(hp, f, om, hp.face_tol * (mp + mm), mp, mm, Pp, Pm);
+}
+
+}  // namespace
+
 // Integrals of one face for direction om.  Returns the class; measures
 // mp = int max(g,0), mm = int max(-g,0); for FC_KINK also Pp, Pm (nf x nf).
 uint8_t face_integrals(const HostProblem& hp, int64_t f, const double* om, double& mp,
@@ -487,6 +652,7 @@ uint8_t face_integrals(const HostProblem& hp, int64_t f, const double* om, doubl
                     }
             }
         }
+        maybe_romberg(hp, f, om, mp, mm, Pp, Pm);
         return FC_KINK;
     }
     // 3D: cheap bound first
@@ -540,6 +706,7 @@ uint8_t face_integrals(const HostProblem& hp, int64_t f, const double* om, doubl
             }
     }
     (void)p;
+    maybe_romberg(hp, f, om, mp, mm, Pp, Pm);
     return FC_KINK;
 }
 

@@ -104,6 +104,8 @@ struct HostProblem {
     bool unstructured = false;                // mesh given as element control-point lists
     bool simplex = false;                     // P_r triangles with a P_p DG basis (unstructured, 2D)
     int nv = 0;                               // control points per element
+    int face_rule = 0;                        // SNSW_FACE_*: sign-changing faces exact/fixed or Romberg
+    double face_tol = 1e-10;                  // relative tolerance of the Romberg face rule
     std::vector<double> nodes;                // [n_nodes][dim] (unstructured)
     std::vector<int64_t> elem_nodes;          // [E][nv] (unstructured)
     std::vector<double> omega, w;             // [D][3], [D]

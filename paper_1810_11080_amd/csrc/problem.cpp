@@ -136,6 +136,11 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
         if (desc->element != SNSW_ELEM_TENSOR && desc->element != SNSW_ELEM_SIMPLEX)
             throw Error(SNSW_E_INVALID_ARG, "element must be TENSOR or SIMPLEX");
         hp.simplex = desc->element == SNSW_ELEM_SIMPLEX;
+        if (desc->face_rule != SNSW_FACE_EXACT && desc->face_rule != SNSW_FACE_ROMBERG)
+            throw Error(SNSW_E_INVALID_ARG, "face_rule must be EXACT or ROMBERG");
+        hp.face_rule = desc->face_rule;
+        if (!std::isfinite(desc->face_tol)) throw Error(SNSW_E_NONFINITE, "face_tol");
+        hp.face_tol = desc->face_tol > 0.0 ? desc->face_tol : 1e-10;
         if (hp.simplex && !desc->elem_nodes)
             throw Error(SNSW_E_INVALID_ARG, "simplicial elements need an element list (elem_nodes)");
         if (hp.simplex && hp.dim != 2) throw Error(SNSW_E_UNSUPPORTED, "simplicial elements: triangles (dim 2) only");
@@ -365,6 +370,29 @@ int snsw_get_removed_edges(const snsw_problem* prob, int d, int32_t* down, int32
             if (down) down[i] = g.rem_down[i];
             if (up) up[i] = g.rem_up[i];
         }
+    });
+}
+
+int snsw_get_face_integrals(const snsw_problem* prob, int d, int64_t f, int32_t* cls, double* mp, double* mm,
+                            double* Pp, double* Pm) {
+    return snsw_guard([&] {
+        if (!prob) throw Error(SNSW_E_INVALID_ARG, "NULL problem");
+        const HostProblem& hp = prob->hp;
+        if (d < 0 || d >= hp.D) throw Error(SNSW_E_INVALID_ARG, "direction out of range");
+        if (f < 0 || f >= hp.F) throw Error(SNSW_E_INVALID_ARG, "face out of range");
+        const int nf = hp.nf;
+        std::vector<double> pp((size_t)nf * nf, 0.0), pm((size_t)nf * nf, 0.0);
+        double a = 0.0, b = 0.0;
+        const uint8_t c = face_integrals(hp, f, &hp.omega[(size_t)d * 3], a, b, pp.data(), pm.data());
+        if (c != FC_KINK) {
+            std::fill(pp.begin(), pp.end(), 0.0);
+            std::fill(pm.begin(), pm.end(), 0.0);
+        }
+        if (cls) *cls = c;
+        if (mp) *mp = a;
+        if (mm) *mm = b;
+        if (Pp) std::copy(pp.begin(), pp.end(), Pp);
+        if (Pm) std::copy(pm.begin(), pm.end(), Pm);
     });
 }
 

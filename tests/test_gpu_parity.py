@@ -497,3 +497,27 @@ def test_triangle_linear_solution_exact(torch, ctx, r, p):
     P.solve(phi, tol=1e-13, max_iters=500)
     phi_exact = np.einsum("d,den->en", P.quadrature()[1], psi_exact)
     assert rel_err(phi.cpu().numpy().reshape(P.E, P.n), phi_exact) < 1e-11
+
+
+ROMBERG = {
+    "quads_q3p2": lambda: W.small(dim=2, n=8, r=3, p=2, N=4, amp=0.3 / 8, freq=2, c=0.7),
+    "t_annulus_p3": SIMPLEX["t_annulus_p3"],
+}
+
+
+@pytest.mark.parametrize("case", sorted(ROMBERG))
+def test_romberg_face_rule_sweeps(torch, ctx, case):
+    """Sign-changing faces integrated by adaptive Romberg (tolerance 1e-12):
+    three GPU sweeps against the oracle with its own Romberg face rule
+    (the two Romberg implementations agree to the tolerance, far below the
+    parity bar)."""
+    from dataclasses import replace
+    from paper_1810_11080_amd import Problem
+    wp = replace(ROMBERG[case](), face_rule="romberg", face_tol=1e-12)
+    P = Problem.from_workload(ctx, wp, schedule=2)
+    g_phi, g_psi = gpu_sweeps(torch, P, 3)
+    P.synchronize()
+    o_phi, o_psi, _, _ = oracle_sweeps(wp, 3)
+    for k in range(3):
+        assert rel_err(g_phi[k], o_phi[k]) < TOL, (case, k)
+    assert rel_err(g_psi[-1], o_psi[-1]) < TOL

@@ -68,6 +68,11 @@ class Problem:
     # elem_nodes lists (r+1)(r+2)/2 control points per element in the
     # triangle lattice order of tri_lattice, and n = (p+1)(p+2)/2)
     element: str = "tensor"
+    # integration of the face matrices on faces where Omega . n changes sign:
+    # "exact" (2D: split at the roots; 3D: fixed composite rule) or
+    # "romberg" (adaptive Romberg to the relative tolerance face_tol)
+    face_rule: str = "exact"
+    face_tol: float = 1e-10
 
     @property
     def n_elements(self) -> int:
