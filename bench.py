@@ -501,6 +501,34 @@ def ho_vs_lo(levels=(1, 2, 4)):
     return rows
 
 
+def element_study(steps: int = 20, warmup: int = 3):
+    """Sweep rates of curved triangles (the simplicial elements) against
+    quadrilaterals on the same closed annulus (r in [1, 2], cubic maps, p = 2,
+    S8): 96 x 384 cells as 73,728 triangles (n = 6) or 36,864 quads (n = 9),
+    level schedule, with cached inverses and assembled per sweep."""
+    import workloads as W
+    from paper_1810_11080_amd import Context, Problem
+    ctx = Context(0)
+    rows = []
+    meshes = (("triangles P2 (Q3 map)", W.tri_annulus(nr=96, nt=384, r=3, p=2, sn_order=8, seed=1)),
+              ("quads Q2 (Q3 map)", W.annulus_full(nr=96, nt=384, p=2, sn_order=8, r=3, seed=1)))
+    for label, wp in meshes:
+        for cache, cname in ((1, "cached inverse"), (2, "assembled")):
+            t0 = time.perf_counter()
+            P = Problem.from_workload(ctx, wp, schedule=2, cache_inverse=cache)
+            setup = time.perf_counter() - t0
+            ms, launches, kernel_ms = time_sweeps(P, steps, warmup)
+            rate = P.E * P.n * P.D / (ms * 1e-3)
+            row = {"mesh": label, "elements": int(P.E), "n": int(P.n), "directions": int(P.D), "path": cname,
+                   "ms_per_sweep": round(ms, 4), "launches": launches, "dof_dir_per_s": rate,
+                   "pairs_per_s": P.E * P.D / (ms * 1e-3), "setup_s": round(setup, 2)}
+            rows.append(row)
+            note("| {mesh} | {path} | {elements} | {n} | {ms_per_sweep} | {dof_dir_per_s:.3e} | "
+                 "{pairs_per_s:.3e} |".format(**row))
+            del P
+    return rows
+
+
 def learned_study(train_steps: int, eval_seeds=(100, 101, 102, 103), every: int = 40):
     """The learned correction on the 48^3 S12 family: trained on seeds 0 and
     1 (as the default line), then plain vs learned source iteration to 1e-8
@@ -572,6 +600,8 @@ def main():
                     help="only the unity / face / sigma-inverse-face weighting comparison")
     ap.add_argument("--ho-vs-lo", action="store_true",
                     help="only the high-order vs straightened low-order manufactured-solution comparison")
+    ap.add_argument("--element-study", action="store_true",
+                    help="only the sweep rates of curved triangles vs quads on one closed annulus")
     ap.add_argument("--learned-study", action="store_true",
                     help="only the learned correction on 48^3 S12: held-out seeds 100-103 and an untrained ablation")
     args = ap.parse_args()
@@ -597,6 +627,9 @@ def main():
         return
     if args.learned_study:
         print(json.dumps({"learned_study": learned_study(args.train_steps)}))
+        return
+    if args.element_study:
+        print(json.dumps({"element_study": element_study()}))
         return
     if args.workload == "c4":
         bench_batch(args)
