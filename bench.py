@@ -46,7 +46,8 @@ METRIC = "DOF-direction updates/s per sweep; time to 1e-8 residual, learned vs p
 # named after each kernel and workload hold the counts.  Only valid for the
 # kernel build it was measured on: drop an entry when the kernel changes.
 MEASURED_TRAFFIC = {("sweep_persistent_dpp<2,3,inv,nt>", "c2", "fp64"): 1.902e9,
-                    ("sweep_level_inv<3,2>", "c5", "fp64"): 4.884e8}
+                    ("sweep_level_inv<3,2>", "c5", "fp64"): 4.884e8,
+                    ("sweep_level_inv<3,2,f32>", "c5", "mixed"): 3.291e8}
 DESCRIPTIONS = {
     "c1": "2D 8x8 Q2 curved (warp 0.05), p=1, S4 (12 dirs), sigma_t=1, c=0.5, q=1, vacuum",
     "c2": "2D 128x128 Q3 curved (warp 0.3 h, 4-element wavelength, cyclic sweep graphs), p=3, "
@@ -95,13 +96,14 @@ def interior_faces(nx) -> int:
     return tot
 
 
-def inverse_stream_bytes_per_pair(dim: int, p: int) -> float:
+def inverse_stream_bytes_per_pair(dim: int, p: int, f32: bool = False) -> float:
     """Bytes the cached-inverse kernels read or write per pair: its A^{-1}
-    (n^2 doubles), its new angular flux (n) and the upwind traces of its d
-    inflow faces (nf each)."""
+    (n^2 doubles, or in mixed precision n * 4 ceil(n/4) floats), its new
+    angular flux (n) and the upwind traces of its d inflow faces (nf each)."""
     n = (p + 1) ** dim
     nf = (p + 1) ** (dim - 1)
-    return 8.0 * (n * n + n + dim * nf)
+    inv = 4.0 * n * 4 * ((n + 3) // 4) if f32 else 8.0 * n * n
+    return inv + 8.0 * (n + dim * nf)
 
 
 def host_cpu():
@@ -168,7 +170,7 @@ def cpu_baseline(wp, block: int = None, n_dirs_sample: int = None):
     return out
 
 
-def kernel_name(wp, sched: int, inv: bool, tile: int) -> str:
+def kernel_name(wp, sched: int, inv: int, tile: int) -> str:
     if sched == 1:
         if wp.dim == 2 and wp.p != 2:
             nt = ",nt" if inv and tile > 0 else ""
@@ -176,6 +178,8 @@ def kernel_name(wp, sched: int, inv: bool, tile: int) -> str:
         if inv:
             return f"sweep_persistent_lds2d<{wp.p}>" if wp.dim == 2 else f"sweep_persistent_inv<{wp.dim},{wp.p}>"
         return f"sweep_persistent_fp64<{wp.dim},{wp.p}>"
+    if inv == 2:
+        return f"sweep_level_inv<{wp.dim},{wp.p},f32>"
     return f"sweep_level_inv<{wp.dim},{wp.p}>" if inv else f"sweep_level_fp64<{wp.dim},{wp.p}>"
 
 
@@ -217,7 +221,7 @@ def sweep_line(P, wp, name: str, sched: int, prec: int, steps: int, warmup: int)
     E, n, D = P.E, P.n, P.D
     ms, launches, kernel_ms = time_sweeps(P, steps, warmup)
     inv = bool(info["cached_inverse"])
-    kname = kernel_name(wp, sched, inv, info["tile"])
+    kname = kernel_name(wp, sched, info["cached_inverse"], info["tile"])
     flops_pair, _, _ = work_model(wp.dim, wp.p)
     flops = flops_pair * E * D
     nbytes = algorithmic_bytes(wp.dim, wp.p, E, D, interior_faces(wp.nx))
@@ -239,7 +243,7 @@ def sweep_line(P, wp, name: str, sched: int, prec: int, steps: int, warmup: int)
                  "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches_per_sweep": launches,
                  "kernel_share_of_step": round(kernel_ms / ms, 4)})
     if inv:
-        sb = inverse_stream_bytes_per_pair(wp.dim, wp.p) * E * D + 8.0 * E * n
+        sb = inverse_stream_bytes_per_pair(wp.dim, wp.p, f32=info["cached_inverse"] == 2) * E * D + 8.0 * E * n
         gbs = sb / launches / avg_launch_s / 1e9
         roof["inverse_stream"] = {"bytes_per_sweep": sb, "achieved_gbs": round(gbs, 1),
                                   "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 5),
@@ -674,6 +678,21 @@ def main():
     del P
     torch.cuda.synchronize()
 
+    mixed = None
+    if name == "c5" and prec == 0 and not args.no_secondary:
+        # the same sweep in mixed precision: A^{-1} kept in FP32 (half the
+        # bytes of the stream that bounds the FP64 sweep), FP64 sums
+        t0 = time.perf_counter()
+        Pm = Problem.from_workload(ctx, wp, precision=1, schedule=2, cache_inverse=cache)
+        ml = sweep_line(Pm, wp, name, 2, 1, args.steps, args.warmup)
+        mixed = {"precision": "mixed (A^-1 in FP32, FP64 products and sums; parity bar 1e-5)",
+                 "value": ml["value"], "unit": "DOF-dir/s", "ms_per_step": ml["ms_per_step"],
+                 "setup_s": round(time.perf_counter() - t0, 2), "roofline": ml["roofline"]}
+        note(f"{name} mixed: {ml['ms_per_step']} ms per sweep")
+        Pm.close()
+        del Pm
+        torch.cuda.synchronize()
+
     secondary = None
     if name == "c5" and not args.no_secondary:
         wp2 = W.c2()
@@ -710,6 +729,7 @@ def main():
         "solve_to_1e-8": solve,
         "learned_vs_plain": learned,
         "cpu_baseline": cpu,
+        "mixed": mixed,
         "secondary": secondary,
     }
     print(json.dumps(line))

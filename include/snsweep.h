@@ -74,7 +74,9 @@ extern "C" {
 #define SNSW_WEIGHT_SIGINVFACE  2 /* z = max |M_{t,e}^{-1} F_{e,e'}|          */
 
 #define SNSW_PREC_FP64   0        /* assembly, LU and solve in FP64          */
-#define SNSW_PREC_MIXED  1        /* FP32 LU + one FP64 residual correction  */
+#define SNSW_PREC_MIXED  1        /* assembled: FP32 LU + one FP64 residual
+                                     correction; cached: A^{-1} rounded to
+                                     FP32 (SNSW_CACHE_*)                     */
 
 /* Device schedule of one sweep.  PERSISTENT: one launch; wavefronts claim
  * (element, direction) pairs in level order and wait only for the upwind
@@ -91,8 +93,11 @@ extern "C" {
  * inverse it is factored once (Gauss-Jordan on the device, at create) and a
  * sweep only assembles b and forms A^{-1} b: D*E*n^2 doubles of device
  * memory, one more double per pair for 3D p = 2 (e.g. 15 GB for 32^3
- * elements, p = 2, S8).  AUTO caches in FP64 mode when that takes at most
- * half of the free device memory.                                          */
+ * elements, p = 2, S8).  With SNSW_PREC_MIXED the inverse (computed in
+ * FP64) is kept rounded to FP32, D*E*n*4*ceil(n/4) floats, and the sweep
+ * forms A^{-1} b with FP64 products and sums (elements of at most 32 nodes;
+ * larger ones take the assembled path).  AUTO caches when that takes at
+ * most half of the free device memory.                                     */
 #define SNSW_CACHE_AUTO    0
 #define SNSW_CACHE_ON      1
 #define SNSW_CACHE_OFF     2
@@ -217,7 +222,8 @@ typedef struct {
     int64_t n_removed_total;     /* lagged edges over all directions         */
     int64_t n_kink_faces_total;  /* (face, direction) with a sign change     */
     double  setup_seconds;       /* host setup wall time                     */
-    int32_t cached_inverse;      /* 1 if A^{-1} per pair is kept on device   */
+    int32_t cached_inverse;      /* A^{-1} per pair kept on device: 0 no,
+                                    1 FP64, 2 FP32 (mixed precision)        */
     int32_t schedule;            /* resolved SNSW_SCHED_PERSISTENT / LEVELS  */
     int32_t tile;                /* T > 0: the persistent sweep takes T x T
                                     tiles of elements of one direction per

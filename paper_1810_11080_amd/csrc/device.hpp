@@ -94,6 +94,7 @@ struct DeviceProblem {
     int32_t* error = nullptr;     // device-side wait failure flag
     int32_t spin_limit = 1 << 20; // polls per dependency wait of persistent sweeps
     double* ainv = nullptr;       // [D][E] cached A^{-1} blocks (InvLayout) or null
+    float* ainv32 = nullptr;      // mixed precision: [D][E] FP32 A^{-1} blocks (InvLayout32) or null
     SweepArgs* table = nullptr;   // this problem as a table of one
     int table_cur = 0;            // buffer index in table->psi_cur
     int cur = 0;                  // psi[cur] holds the latest sweep

@@ -146,6 +146,21 @@ struct InvLayout {
     }
 };
 typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Layout of one pair's A^{-1} rounded to FP32 (mixed precision): groups of 4
+// columns, entry (i, j) at ((j / 4) n + i) 4 + j mod 4, the last group padded,
+// so that a lane reads four entries of its row with one 16-byte load.
+template <int DIM, int P>
+struct InvLayout32 {
+    static constexpr int N = Shape<DIM, P>::N;
+    static constexpr int kGroups = (N + 3) / 4;
+    static constexpr int kStride = kGroups * N * 4;
+    __host__ __device__ static constexpr int at(int i, int j) { return ((j >> 2) * N + i) * 4 + (j & 3); }
+};
+// FP32 inverses are kept for elements with at most this many nodes (their
+// row of A^{-1} stays in registers); larger ones use the assembled path.
+constexpr int kMaxInv32 = 32;
 
 // Every block layout is a permutation of [0, n^2) inside its stride, and the
 // paired columns sit at even offsets next to each other (16-byte loads).
@@ -208,6 +223,7 @@ __device__ __forceinline__ SweepArgs load_args(const SweepArgs* table, int k) {
     a.Bsym = c->Bsym;
     a.rhs_dir = c->rhs_dir;
     a.nbr_nodes = c->nbr_nodes;
+    a.ainv32 = c->ainv32;
     return a;
 }
 
@@ -1198,9 +1214,9 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
 // invert it in place by Gauss-Jordan without pivoting (A + A^T is positive
 // definite), pivot rows broadcast through LDS; A^{-1} is stored at
 // ainv[(d E + e) stride + InvLayout::at(i, j)].
-template <int DIM, int P, bool U = false>
+template <int DIM, int P, bool U = false, bool F32 = false>
 __global__ void __launch_bounds__(64 * kWaves) factor_kernel(const SweepArgs* table, const int4* pairs, int64_t count,
-                                                            double* ainv) {
+                                                            void* ainv) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, G = S::G;
     __shared__ double lds[kWaves][G][N + 1];
@@ -1244,10 +1260,17 @@ __global__ void __launch_bounds__(64 * kWaves) factor_kernel(const SweepArgs* ta
     }
     if (active) {
         const int d = (int)((unsigned)pr.y & kDirMask);
-        using IL = InvLayout<DIM, P>;
-        double* dst = ainv + ((size_t)d * args.E + pr.x) * IL::kStride;
+        if constexpr (F32) {
+            using IL = InvLayout32<DIM, P>;
+            float* dst = static_cast<float*>(ainv) + ((size_t)d * args.E + pr.x) * IL::kStride;
 #pragma unroll
-        for (int j = 0; j < N; ++j) dst[IL::at(row, j)] = m[j];
+            for (int j = 0; j < N; ++j) dst[IL::at(row, j)] = (float)m[j];
+        } else {
+            using IL = InvLayout<DIM, P>;
+            double* dst = static_cast<double*>(ainv) + ((size_t)d * args.E + pr.x) * IL::kStride;
+#pragma unroll
+            for (int j = 0; j < N; ++j) dst[IL::at(row, j)] = m[j];
+        }
     }
 }
 
@@ -1464,7 +1487,7 @@ __device__ __forceinline__ double inflow_rhs_staged(const SweepArgs& args, int4 
 
 // One launch per level with cached inverses: b assembled per row, shared
 // through the wavefront's LDS, x = A^{-1} b.
-template <int DIM, int P, bool U = false>
+template <int DIM, int P, bool U = false, bool F32 = false>
 __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* table, const int4* pairs,
                                                               int64_t begin, int64_t count, int problem) {
     using S = Shape<DIM, P>;
@@ -1488,7 +1511,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     const int e = prs.x;
     const int d = (int)((unsigned)prs.y & kDirMask);
     using IL = InvLayout<DIM, P>;
-    const double* Ab = args.ainv + ((size_t)d * args.E + e) * IL::kStride;
+    const double* Ab = F32 ? nullptr : args.ainv + ((size_t)d * args.E + e) * IL::kStride;
     auto rhs_of = [&]() {
         const int g = in_group ? grp : 0;
         if constexpr (kStage) return inflow_rhs_staged<DIM, P, U>(args, prs, row, in_group, cfl[wave][g], ufl[wave][g]);
@@ -1497,7 +1520,36 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     };
     double* L = &lds[wave][in_group ? grp : 0][0];
     double x = 0.0;
-    if constexpr (N > SNSW_LEVEL_CHUNK_MIN) {
+    if constexpr (F32) {
+        // mixed precision: the row of A^{-1} rounded to FP32, four entries
+        // per 16-byte load, products and sum in FP64
+        static_assert(N <= kMaxInv32, "FP32 inverse rows are held in registers");
+        using IL32 = InvLayout32<DIM, P>;
+        const float* Af = args.ainv32 + ((size_t)d * args.E + e) * IL32::kStride;
+        const double b = rhs_of();
+        if (in_group) L[row] = b;
+        wave_sync();
+        __builtin_amdgcn_sched_barrier(0);
+        float m[IL32::kGroups * 4];
+#pragma unroll
+        for (int g = 0; g < IL32::kGroups; ++g) {
+            const flt4 v = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(Af + IL32::at(row, 4 * g)));
+            m[4 * g] = v.x;
+            m[4 * g + 1] = v.y;
+            m[4 * g + 2] = v.z;
+            m[4 * g + 3] = v.w;
+        }
+        // b read back from LDS a few entries at a time (fewer live registers)
+        constexpr int LG = SNSW_LEVEL_LDS_GROUP;
+#pragma unroll
+        for (int g0 = 0; g0 < N; g0 += LG) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = g0; j < g0 + LG && j < N; ++j) x += (double)m[j] * L[j];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        __asm__ volatile("" : "+v"(x));
+    } else if constexpr (N > SNSW_LEVEL_CHUNK_MIN) {
         // large elements: b first; then the row of A^{-1} is loaded a chunk
         // of columns at a time (all of it for n <= 32) while b is read back
         // from LDS a few entries at a time.  The scheduling barriers keep
@@ -1918,7 +1970,12 @@ void launch_tpl_u(const SweepArgs* table, const int4* pairs, int64_t begin, int6
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
-    if (inv)
+    if (inv && mixed) {
+        // mixed precision with cached inverses: the FP32 copy
+        if constexpr (Shape<DIM, P>::N <= kMaxInv32)
+            hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                               stream, table, pairs, begin, count, problem);
+    } else if (inv)
         hipLaunchKernelGGL((sweep_level_inv<DIM, P, U>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, table,
                            pairs, begin, count, problem);
     else if (mixed)
@@ -1985,24 +2042,32 @@ void launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, hipStream_t 
     }
 }
 
-template <int DIM, int P>
-void launch_factor_tpl(const SweepArgs* table, const int4* pairs, int64_t count, double* ainv, bool unstructured,
-                       hipStream_t stream) {
+template <int DIM, int P, bool F32>
+void launch_factor_f(const SweepArgs* table, const int4* pairs, int64_t count, void* ainv, bool unstructured,
+                     hipStream_t stream) {
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
     if constexpr (P >= kTri) {
         // triangles always come with the upwind node table
-        hipLaunchKernelGGL((factor_kernel<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
+        hipLaunchKernelGGL((factor_kernel<DIM, P, true, F32>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
                            table, pairs, count, ainv);
     } else {
         if (unstructured)
-            hipLaunchKernelGGL((factor_kernel<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
-                               table, pairs, count, ainv);
+            hipLaunchKernelGGL((factor_kernel<DIM, P, true, F32>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                               stream, table, pairs, count, ainv);
         else
-            hipLaunchKernelGGL((factor_kernel<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+            hipLaunchKernelGGL((factor_kernel<DIM, P, false, F32>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
                                stream, table, pairs, count, ainv);
     }
+}
+
+template <int DIM, int P>
+void launch_factor_tpl(const SweepArgs* table, const int4* pairs, int64_t count, void* ainv, bool f32,
+                       bool unstructured, hipStream_t stream) {
+    if (!f32) launch_factor_f<DIM, P, false>(table, pairs, count, ainv, unstructured, stream);
+    else if constexpr (Shape<DIM, P>::N <= kMaxInv32)
+        launch_factor_f<DIM, P, true>(table, pairs, count, ainv, unstructured, stream);
 }
 
 template <int DIM, int P>
@@ -2121,29 +2186,36 @@ void launch_sweep_level(int dim, int p, bool simplex, bool mixed, bool inv, bool
     }
 }
 
-int64_t ainv_block_stride(int dim, int p, bool simplex) {
-    if (simplex)
-        return p == 1 ? InvLayout<2, kTri + 1>::kStride
-                      : p == 2 ? InvLayout<2, kTri + 2>::kStride : InvLayout<2, kTri + 3>::kStride;
-    if (dim == 2) return p == 1 ? InvLayout<2, 1>::kStride : p == 2 ? InvLayout<2, 2>::kStride : InvLayout<2, 3>::kStride;
-    return p == 1 ? InvLayout<3, 1>::kStride : p == 2 ? InvLayout<3, 2>::kStride : InvLayout<3, 3>::kStride;
+template <int DIM, int P>
+int64_t inv_bytes_tpl(bool f32) {
+    if (f32) return Shape<DIM, P>::N <= kMaxInv32 ? (int64_t)sizeof(float) * InvLayout32<DIM, P>::kStride : 0;
+    return (int64_t)sizeof(double) * InvLayout<DIM, P>::kStride;
 }
 
-void launch_factor(int dim, int p, bool simplex, bool unstructured, const SweepArgs* table, const int4* pairs,
-                   int64_t count, double* ainv, hipStream_t stream) {
+int64_t ainv_block_bytes(int dim, int p, bool simplex, bool f32) {
+    if (simplex)
+        return p == 1 ? inv_bytes_tpl<2, kTri + 1>(f32) : p == 2 ? inv_bytes_tpl<2, kTri + 2>(f32)
+                                                                 : inv_bytes_tpl<2, kTri + 3>(f32);
+    if (dim == 2)
+        return p == 1 ? inv_bytes_tpl<2, 1>(f32) : p == 2 ? inv_bytes_tpl<2, 2>(f32) : inv_bytes_tpl<2, 3>(f32);
+    return p == 1 ? inv_bytes_tpl<3, 1>(f32) : p == 2 ? inv_bytes_tpl<3, 2>(f32) : inv_bytes_tpl<3, 3>(f32);
+}
+
+void launch_factor(int dim, int p, bool simplex, bool f32, bool unstructured, const SweepArgs* table,
+                   const int4* pairs, int64_t count, void* ainv, hipStream_t stream) {
     const bool u = unstructured;
     if (simplex) {
-        if (p == 1) launch_factor_tpl<2, kTri + 1>(table, pairs, count, ainv, true, stream);
-        else if (p == 2) launch_factor_tpl<2, kTri + 2>(table, pairs, count, ainv, true, stream);
-        else launch_factor_tpl<2, kTri + 3>(table, pairs, count, ainv, true, stream);
+        if (p == 1) launch_factor_tpl<2, kTri + 1>(table, pairs, count, ainv, f32, true, stream);
+        else if (p == 2) launch_factor_tpl<2, kTri + 2>(table, pairs, count, ainv, f32, true, stream);
+        else launch_factor_tpl<2, kTri + 3>(table, pairs, count, ainv, f32, true, stream);
     } else if (dim == 2) {
-        if (p == 1) launch_factor_tpl<2, 1>(table, pairs, count, ainv, u, stream);
-        else if (p == 2) launch_factor_tpl<2, 2>(table, pairs, count, ainv, u, stream);
-        else launch_factor_tpl<2, 3>(table, pairs, count, ainv, u, stream);
+        if (p == 1) launch_factor_tpl<2, 1>(table, pairs, count, ainv, f32, u, stream);
+        else if (p == 2) launch_factor_tpl<2, 2>(table, pairs, count, ainv, f32, u, stream);
+        else launch_factor_tpl<2, 3>(table, pairs, count, ainv, f32, u, stream);
     } else {
-        if (p == 1) launch_factor_tpl<3, 1>(table, pairs, count, ainv, u, stream);
-        else if (p == 2) launch_factor_tpl<3, 2>(table, pairs, count, ainv, u, stream);
-        else launch_factor_tpl<3, 3>(table, pairs, count, ainv, u, stream);
+        if (p == 1) launch_factor_tpl<3, 1>(table, pairs, count, ainv, f32, u, stream);
+        else if (p == 2) launch_factor_tpl<3, 2>(table, pairs, count, ainv, f32, u, stream);
+        else launch_factor_tpl<3, 3>(table, pairs, count, ainv, f32, u, stream);
     }
 }
 

@@ -39,6 +39,8 @@ struct SweepArgs {
     const int32_t* nbr_nodes; // unstructured meshes: [E][2 dim][nf] the upwind neighbour's node on the
                               // point of each slot node (slot order); null on a lattice, where it is
                               // the opposite slot's node of the same local index
+    const float* ainv32;      // mixed precision: [D][E] blocks of A^{-1} rounded to FP32 (kernels.hip
+                              // InvLayout32), or null
 };
 
 // Doubles per face in the packed face-moment array Bsym: dim packed upper
@@ -80,18 +82,21 @@ int persistent_blocks_per_cu(int dim, int p, bool inv);
 bool persistent_uses_inverse(int dim, int p);
 // Launches the level-sweep kernel over schedule entries [begin, begin+count)
 // (begin and count multiples of G); simplex: order-p triangles (2D, always
-// with the upwind node table); inv: x = A^{-1} b with cached inverses;
+// with the upwind node table); inv: x = A^{-1} b with cached inverses (FP32
+// copies when mixed, else FP64);
 // unstructured: upwind nodes from SweepArgs::nbr_nodes; problem: table index
 // of every entry, or -1 when entries name their problem.
 void launch_sweep_level(int dim, int p, bool simplex, bool mixed, bool inv, bool unstructured,
                         const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem,
                         hipStream_t stream);
-// Doubles per pair in the cached A^{-1} array (n^2, or n^2 + 1 where blocks
-// are padded to a 16-byte multiple).
-int64_t ainv_block_stride(int dim, int p, bool simplex);
-// Computes and stores A^{-1} of schedule entries [0, count) of one problem.
-void launch_factor(int dim, int p, bool simplex, bool unstructured, const SweepArgs* table, const int4* pairs,
-                   int64_t count, double* ainv, hipStream_t stream);
+// Bytes per pair of the cached A^{-1}: FP64 (n^2 doubles, n^2 + 1 where blocks
+// are padded to a 16-byte multiple) or, f32, rounded to FP32 in groups of four
+// columns (0: no FP32 copy for this shape, n > 32).
+int64_t ainv_block_bytes(int dim, int p, bool simplex, bool f32);
+// Computes A^{-1} of schedule entries [0, count) of one problem in FP64 and
+// stores it (f32: rounded to FP32).
+void launch_factor(int dim, int p, bool simplex, bool f32, bool unstructured, const SweepArgs* table,
+                   const int4* pairs, int64_t count, void* ainv, hipStream_t stream);
 
 // Start of a sweep, for problems [0, count) of the table: swaps psi_cur and
 // psi_prev of each entry, zeroes the ticket counters of n_tickets schedules

@@ -179,8 +179,9 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
         if (hp.cache_inverse != SNSW_CACHE_AUTO && hp.cache_inverse != SNSW_CACHE_ON &&
             hp.cache_inverse != SNSW_CACHE_OFF)
             throw Error(SNSW_E_INVALID_ARG, "cache_inverse must be AUTO, ON or OFF");
-        if (hp.cache_inverse == SNSW_CACHE_ON && desc->precision == SNSW_PREC_MIXED)
-            throw Error(SNSW_E_UNSUPPORTED, "cached inverses are FP64 only");
+        if (hp.cache_inverse == SNSW_CACHE_ON && desc->precision == SNSW_PREC_MIXED && hp.n > 32)
+            throw Error(SNSW_E_UNSUPPORTED, "cached FP32 inverses need elements of at most 32 nodes");
+
         if (desc->precision == SNSW_PREC_MIXED && hp.schedule == SNSW_SCHED_PERSISTENT)
             throw Error(SNSW_E_UNSUPPORTED, "mixed precision runs on the LEVELS schedule");
 

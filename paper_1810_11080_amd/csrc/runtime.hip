@@ -148,6 +148,7 @@ SweepArgs make_args(const snsw_problem* prob, int cur) {
     a.Bsym = dp->Bsym;
     a.rhs_dir = hp.rhs_fixed.empty() ? nullptr : dp->rhs_dir;
     a.nbr_nodes = dp->nbr_nodes;
+    a.ainv32 = dp->ainv32;
     return a;
 }
 
@@ -424,17 +425,21 @@ void device_upload(snsw_problem* prob) {
     HIP_OK(hipMemsetAsync(dp->ticket, 0, sizeof(unsigned int) * kTicketWords, s));
     dp->error = dalloc<int32_t>(dp, 1);
     HIP_OK(hipMemsetAsync(dp->error, 0, sizeof(int32_t), s));
-    // cached inverses: D*E blocks of about n^2 doubles
+    // cached inverses: D*E blocks of about n^2 doubles (FP64), or of n^2
+    // floats in mixed precision (elements of at most 32 nodes)
+    const bool mixed = hp.precision == SNSW_PREC_MIXED;
     {
-        const size_t need = sizeof(double) * (size_t)hp.D * hp.E * ainv_block_stride(hp.dim, hp.p, hp.simplex);
+        const int64_t blk = ainv_block_bytes(hp.dim, hp.p, hp.simplex, mixed);
+        const size_t need = (size_t)hp.D * hp.E * (size_t)blk;
         bool cache = false;
-        if (hp.precision == SNSW_PREC_FP64 && hp.cache_inverse != SNSW_CACHE_OFF) {
+        if (hp.cache_inverse != SNSW_CACHE_OFF && blk > 0) {
             size_t free_b = 0, total_b = 0;
             HIP_OK(hipMemGetInfo(&free_b, &total_b));
             cache = hp.cache_inverse == SNSW_CACHE_ON || need <= free_b / 2;
         }
-        if (cache) dp->ainv = dalloc<double>(dp, (size_t)hp.D * hp.E * ainv_block_stride(hp.dim, hp.p, hp.simplex));
-        hp.inverse_cached = cache ? 1 : 0;
+        if (cache && mixed) dp->ainv32 = dalloc<float>(dp, need / sizeof(float));
+        else if (cache) dp->ainv = dalloc<double>(dp, need / sizeof(double));
+        hp.inverse_cached = cache ? (mixed ? 2 : 1) : 0;
     }
     SweepClass& c = dp->cls;
     c.dim = hp.dim;
@@ -443,7 +448,7 @@ void device_upload(snsw_problem* prob) {
     c.unstructured = hp.unstructured;
     c.simplex = hp.simplex;
     c.persistent = hp.schedule == SNSW_SCHED_PERSISTENT;
-    c.inv = dp->ainv != nullptr && (!c.persistent || persistent_uses_inverse(hp.dim, hp.p));
+    c.inv = (dp->ainv != nullptr || dp->ainv32 != nullptr) && (!c.persistent || persistent_uses_inverse(hp.dim, hp.p));
     c.ticket = 0;
     c.pairs = dp->pairs;
     c.level_off = hp.level_off;
@@ -463,8 +468,9 @@ void device_upload(snsw_problem* prob) {
         dp->table = dalloc<SweepArgs>(dp, 1);
         HIP_OK(hipMemcpyAsync(dp->table, &a, sizeof(a), hipMemcpyHostToDevice, s));
     }
-    if (dp->ainv) {
-        launch_factor(hp.dim, hp.p, hp.simplex, hp.unstructured, dp->table, dp->pairs, hp.level_off.back(), dp->ainv, s);
+    if (dp->ainv || dp->ainv32) {
+        launch_factor(hp.dim, hp.p, hp.simplex, dp->ainv32 != nullptr, hp.unstructured, dp->table, dp->pairs,
+                      hp.level_off.back(), dp->ainv32 ? (void*)dp->ainv32 : (void*)dp->ainv, s);
         HIP_OK(hipGetLastError());
     }
     HIP_OK(hipStreamSynchronize(s));
@@ -502,7 +508,7 @@ void device_release(snsw_problem* prob) noexcept {
                     dp->tintra, dp->tslots,
                     dp->slot_face, dp->slot_nbr,
                     dp->sigma_t, dp->sigma_s, dp->q, dp->rhs_dir, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
-                    dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table, dp->ainv};
+                    dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table, dp->ainv, dp->ainv32};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
