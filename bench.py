@@ -509,7 +509,8 @@ def element_study(steps: int = 20, warmup: int = 3):
     """Sweep rates of curved triangles (the simplicial elements) against
     quadrilaterals on the same closed annulus (r in [1, 2], cubic maps, p = 2,
     S8): 96 x 384 cells as 73,728 triangles (n = 6) or 36,864 quads (n = 9),
-    level schedule, with cached inverses and assembled per sweep."""
+    level schedule and persistent kernels, with cached inverses and
+    assembled per sweep."""
     import workloads as W
     from paper_1810_11080_amd import Context, Problem
     ctx = Context(0)
@@ -517,9 +518,10 @@ def element_study(steps: int = 20, warmup: int = 3):
     meshes = (("triangles P2 (Q3 map)", W.tri_annulus(nr=96, nt=384, r=3, p=2, sn_order=8, seed=1)),
               ("quads Q2 (Q3 map)", W.annulus_full(nr=96, nt=384, p=2, sn_order=8, r=3, seed=1)))
     for label, wp in meshes:
-        for cache, cname in ((1, "cached inverse"), (2, "assembled")):
+        for sched, cache, cname in ((2, 1, "levels, cached inverse"), (2, 2, "levels, assembled"),
+                                    (1, 1, "persistent, cached inverse"), (1, 2, "persistent, assembled")):
             t0 = time.perf_counter()
-            P = Problem.from_workload(ctx, wp, schedule=2, cache_inverse=cache)
+            P = Problem.from_workload(ctx, wp, schedule=sched, cache_inverse=cache)
             setup = time.perf_counter() - t0
             ms, launches, kernel_ms = time_sweeps(P, steps, warmup)
             rate = P.E * P.n * P.D / (ms * 1e-3)

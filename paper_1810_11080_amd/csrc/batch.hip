@@ -332,7 +332,7 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
         pa.problem = class_problem(c);
         pa.slots = c.slots;
         pa.nt = 0;
-        launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
+        launch_sweep_persistent(c.dim, c.p, c.simplex, c.unstructured, c.inv, pa, c.blocks, s);
     } else {
         for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
             const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
@@ -422,7 +422,8 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
             HIP_OK(hipStreamSynchronize(s));
             const bool pinv = bc.has_inv && persistent_uses_inverse(bc.cls.dim, bc.cls.p);
             const int64_t ptotal = bc.tiled ? bc.tlevel_off.back() : bc.level_off.back();
-            bc.full_blocks = persistent_grid(bc.cls.dim, bc.cls.p, pinv, ptotal, ctx->device);
+            bc.full_blocks = persistent_grid(bc.cls.dim, bc.cls.p, bc.cls.simplex, bc.cls.unstructured, pinv, ptotal,
+                                             ctx->device);
             choose(bc, !bc.levels_only && o.schedule == SNSW_SCHED_PERSISTENT, bc.full_blocks);
         }
         HIP_OK(hipMalloc(&b->table, count * sizeof(SweepArgs)));

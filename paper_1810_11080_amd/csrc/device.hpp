@@ -134,6 +134,7 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
 void check_error_flag(int32_t* flag, hipStream_t s);
 
 DeviceProblem* need_device(snsw_problem* prob);
-int persistent_grid(int dim, int p, bool inv, int64_t total, int device, double fraction = 1.0);
+int persistent_grid(int dim, int p, bool simplex, bool unstructured, bool inv, int64_t total, int device,
+                    double fraction = 1.0);
 
 }  // namespace snsw

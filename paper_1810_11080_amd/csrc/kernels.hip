@@ -522,7 +522,7 @@ constexpr unsigned long long kSentinel = 0x7FF4000000005EEDull;
 // finishing a smaller one): the waits end.  A wait that exceeds spin_limit
 // polls sets *error and gives up (the result is then wrong but the kernel
 // still terminates).
-template <int DIM, int P>
+template <int DIM, int P, bool U = false>
 __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs pa) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
@@ -558,7 +558,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
         unsigned kept = 0;
         int krow[2 * DIM];
         const int4 prs = active ? pr : make_int4(0, 0, 0, 0);
-        assemble_row<DIM, P, true>(args, prs, row, a, rhs, kept, krow);
+        assemble_row<DIM, P, true, false, U>(args, prs, row, a, rhs, kept, krow);
         const int e = prs.x;
         const unsigned packed = (unsigned)pr.y;
         const int d = (int)(packed & kDirMask);
@@ -597,7 +597,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
                 for (int s = 0; s < NS; ++s) {
                     if (!need[s]) continue;
                     const int nb = args.slot_nbr[(size_t)e * NS + s];
-                    double* ad = args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, 0);
+                    double* ad = args.psi_cur + ((size_t)d * args.E + nb) * N + up_node<DIM, P, U>(args, e, s, 0);
                     const double val = __hip_atomic_load(ad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if ((unsigned long long)__double_as_longlong(val) == sent) all = false;
                     else need[s] = false;
@@ -641,13 +641,13 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_fp64(PersistArgs
             double vals[NF];
 #pragma unroll
             for (int b = 0; b < NF; ++b)
-                vals[b] = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                vals[b] = __hip_atomic_load(up + up_node<DIM, P, U>(args, e, s, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
             for (int b = 0; b < NF; ++b) {
                 for (int spin = 0;
                      (unsigned long long)__double_as_longlong(vals[b]) == sent && spin < pa.spin_limit; ++spin) {
                     __builtin_amdgcn_s_sleep(1);
-                    vals[b] = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    vals[b] = __hip_atomic_load(up + up_node<DIM, P, U>(args, e, s, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 // a value still unwritten after the bound is a failed wait
                 if ((unsigned long long)__double_as_longlong(vals[b]) == sent) atomicExch(pa.error, 1);
@@ -1614,7 +1614,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
 // row of A^{-1} is loaded and b assembled without the kept inflow before the
 // wait; after it the face lanes add the kept inflow and x = A^{-1} b is one
 // LDS exchange of b.
-template <int DIM, int P>
+template <int DIM, int P, bool U = false>
 __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs pa) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
@@ -1648,7 +1648,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs 
 #pragma unroll
         for (int j = 0; j < N; ++j) m[j] = Ai[IL::at(row, j)];
         unsigned kept = 0;
-        double rhs = inflow_rhs<DIM, P, true>(args, prs, row, &kept);
+        double rhs = inflow_rhs<DIM, P, true, U>(args, prs, row, &kept);
         if (!active) kept = 0;
 
         // wait: the lane on the first node of each kept face polls the
@@ -1668,7 +1668,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs 
                 for (int s = 0; s < NS; ++s) {
                     if (!need[s]) continue;
                     const int nb = args.slot_nbr[(size_t)e * NS + s];
-                    double* ad = args.psi_cur + ((size_t)d * args.E + nb) * N + S::tn(s ^ 1, 0);
+                    double* ad = args.psi_cur + ((size_t)d * args.E + nb) * N + up_node<DIM, P, U>(args, e, s, 0);
                     const double val = __hip_atomic_load(ad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if ((unsigned long long)__double_as_longlong(val) == sent) all = false;
                     else need[s] = false;
@@ -1707,13 +1707,13 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_inv(PersistArgs 
                 double val[NF];
 #pragma unroll
                 for (int b = 0; b < NF; ++b)
-                    val[b] = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    val[b] = __hip_atomic_load(up + up_node<DIM, P, U>(args, e, s, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
                 for (int b = 0; b < NF; ++b) {
                     for (int spin = 0;
                          (unsigned long long)__double_as_longlong(val[b]) == sent && spin < pa.spin_limit; ++spin) {
                         __builtin_amdgcn_s_sleep(1);
-                        val[b] = __hip_atomic_load(up + S::tn(s ^ 1, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        val[b] = __hip_atomic_load(up + up_node<DIM, P, U>(args, e, s, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                     // a value still unwritten after the bound is a failed wait
                     if ((unsigned long long)__double_as_longlong(val[b]) == sent) atomicExch(pa.error, 1);
@@ -2042,6 +2042,27 @@ void launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, hipStream_t 
     }
 }
 
+// Element lists (lattices given as element lists, triangles): the generic
+// persistent kernels with the per-slot upwind node table.
+template <int DIM, int P>
+void launch_persist_u(const PersistArgs& a, int blocks, bool inv, hipStream_t stream) {
+    if (inv)
+        hipLaunchKernelGGL((sweep_persistent_inv<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
+                           a);
+    else
+        hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                           stream, a);
+}
+
+template <int DIM, int P>
+int occupancy_u(bool inv) {
+    int nb = 0;
+    const hipError_t rc =
+        inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_inv<DIM, P, true>, 64 * kWaves, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P, true>, 64 * kWaves, 0);
+    return rc == hipSuccess && nb > 0 ? nb : 1;
+}
+
 template <int DIM, int P, bool F32>
 void launch_factor_f(const SweepArgs* table, const int4* pairs, int64_t count, void* ainv, bool unstructured,
                      hipStream_t stream) {
@@ -2232,8 +2253,23 @@ void launch_fill_sentinel(const SweepArgs* table, int count, int64_t max_DEn, hi
     hipLaunchKernelGGL(fill_sentinel_kernel, dim3((unsigned)blocks, (unsigned)count), dim3(256), 0, stream, table);
 }
 
-void launch_sweep_persistent(int dim, int p, bool inv, const PersistArgs& a, int blocks, hipStream_t stream) {
-    if (dim == 2) {
+void launch_sweep_persistent(int dim, int p, bool simplex, bool unstructured, bool inv, const PersistArgs& a,
+                             int blocks, hipStream_t stream) {
+    if (simplex) {
+        if (p == 1) launch_persist_u<2, kTri + 1>(a, blocks, inv, stream);
+        else if (p == 2) launch_persist_u<2, kTri + 2>(a, blocks, inv, stream);
+        else launch_persist_u<2, kTri + 3>(a, blocks, inv, stream);
+    } else if (unstructured) {
+        if (dim == 2) {
+            if (p == 1) launch_persist_u<2, 1>(a, blocks, inv, stream);
+            else if (p == 2) launch_persist_u<2, 2>(a, blocks, inv, stream);
+            else launch_persist_u<2, 3>(a, blocks, inv, stream);
+        } else {
+            if (p == 1) launch_persist_u<3, 1>(a, blocks, inv, stream);
+            else if (p == 2) launch_persist_u<3, 2>(a, blocks, inv, stream);
+            else launch_persist_u<3, 3>(a, blocks, inv, stream);
+        }
+    } else if (dim == 2) {
         if (p == 1) launch_persist_tpl<2, 1>(a, blocks, inv, stream);
         else if (p == 2) launch_persist_tpl<2, 2>(a, blocks, inv, stream);
         else launch_persist_tpl<2, 3>(a, blocks, inv, stream);
@@ -2244,7 +2280,14 @@ void launch_sweep_persistent(int dim, int p, bool inv, const PersistArgs& a, int
     }
 }
 
-int persistent_blocks_per_cu(int dim, int p, bool inv) {
+int persistent_blocks_per_cu(int dim, int p, bool simplex, bool unstructured, bool inv) {
+    if (simplex)
+        return p == 1 ? occupancy_u<2, kTri + 1>(inv) : p == 2 ? occupancy_u<2, kTri + 2>(inv)
+                                                             : occupancy_u<2, kTri + 3>(inv);
+    if (unstructured) {
+        if (dim == 2) return p == 1 ? occupancy_u<2, 1>(inv) : p == 2 ? occupancy_u<2, 2>(inv) : occupancy_u<2, 3>(inv);
+        return p == 1 ? occupancy_u<3, 1>(inv) : p == 2 ? occupancy_u<3, 2>(inv) : occupancy_u<3, 3>(inv);
+    }
     if (dim == 2)
         return p == 1 ? occupancy_tpl<2, 1>(inv) : p == 2 ? occupancy_tpl<2, 2>(inv) : occupancy_tpl<2, 3>(inv);
     return p == 1 ? occupancy_tpl<3, 1>(inv) : p == 2 ? occupancy_tpl<3, 2>(inv) : occupancy_tpl<3, 3>(inv);

@@ -74,10 +74,13 @@ struct PersistArgs {
 };
 
 // Launches the persistent sweep kernel (all levels in one launch); inv: read
-// the cached inverses.
-void launch_sweep_persistent(int dim, int p, bool inv, const PersistArgs& a, int blocks, hipStream_t stream);
+// the cached inverses; simplex / unstructured: element lists (triangles, or
+// quads / hexes), swept by the generic persistent kernels with the upwind
+// node table.
+void launch_sweep_persistent(int dim, int p, bool simplex, bool unstructured, bool inv, const PersistArgs& a,
+                             int blocks, hipStream_t stream);
 // Blocks per CU that the persistent kernel can keep resident.
-int persistent_blocks_per_cu(int dim, int p, bool inv);
+int persistent_blocks_per_cu(int dim, int p, bool simplex, bool unstructured, bool inv);
 // Whether the persistent kernel of this shape has a cached-inverse variant.
 bool persistent_uses_inverse(int dim, int p);
 // Launches the level-sweep kernel over schedule entries [begin, begin+count)

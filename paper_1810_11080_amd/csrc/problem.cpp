@@ -191,9 +191,8 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
             for (int a = 1; a < hp.dim; ++a)
                 if (hp.nx[a] != 1) throw Error(SNSW_E_SHAPE, "unstructured mesh: nx[1] (and nx[2]) must be 1");
             if (!desc->nodes || desc->n_nodes < 1) throw Error(SNSW_E_INVALID_ARG, "unstructured mesh: no nodes");
-            if (desc->schedule == SNSW_SCHED_PERSISTENT)
-                throw Error(SNSW_E_UNSUPPORTED, "unstructured meshes sweep on the LEVELS schedule");
-            hp.schedule = SNSW_SCHED_LEVELS;
+            // element lists: the generic persistent kernels on request, else levels
+            hp.schedule = desc->schedule == SNSW_SCHED_PERSISTENT ? SNSW_SCHED_PERSISTENT : SNSW_SCHED_LEVELS;
             const int64_t Nv = hp.nv;
             hp.nodes.assign(desc->nodes, desc->nodes + desc->n_nodes * hp.dim);
             check_finite(hp.nodes.data(), hp.nodes.size(), "nodes");

@@ -272,7 +272,7 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             // sweeps (2D 128^2 p = 3 S8: 4 %) and lost on batches
             pa.nt = c.intra != nullptr ? 1 : 0;
             if (prof) prof->begin(s);
-            launch_sweep_persistent(c.dim, c.p, c.inv, pa, c.blocks, s);
+            launch_sweep_persistent(c.dim, c.p, c.simplex, c.unstructured, c.inv, pa, c.blocks, s);
             if (prof) prof->end(s);
         } else {
             for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
@@ -300,11 +300,12 @@ void check_error_flag(int32_t* flag, hipStream_t s) {
     }
 }
 
-int persistent_grid(int dim, int p, bool inv, int64_t total, int device, double fraction) {
+int persistent_grid(int dim, int p, bool simplex, bool unstructured, bool inv, int64_t total, int device,
+                    double fraction) {
     int cus = 0;
     HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-    const int per_cu = persistent_blocks_per_cu(dim, p, inv);
-    const int n = dim == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
+    const int per_cu = persistent_blocks_per_cu(dim, p, simplex, unstructured, inv);
+    const int n = simplex ? (p + 1) * (p + 2) / 2 : dim == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
     const int64_t per_block = 4 * (64 / n);
     const int64_t need = (total + per_block - 1) / per_block;
     const int64_t cap = std::max<int64_t>(1, (int64_t)(fraction * per_cu * cus));
@@ -459,7 +460,9 @@ void device_upload(snsw_problem* prob) {
         c.slots = dp->tslots;
     }
     c.members = {0};
-    c.blocks = persistent_grid(hp.dim, hp.p, c.inv, hp.level_off.back(), dp->device);
+    c.blocks = c.persistent ? persistent_grid(hp.dim, hp.p, hp.simplex, hp.unstructured, c.inv,
+                                              hp.level_off.back(), dp->device)
+                            : 0;
     {
         dp->cur = 0;
         dp->table_cur = 0;

@@ -211,9 +211,12 @@ def test_wait_failure_reported_and_recovered(torch, ctx, case, cache):
     bit.  Cases: the DPP kernel (2D p = 3), the LDS kernel with cached
     inverses (2D p = 2 stand-in), the assembled kernel (2D p = 2, no cache)
     and the 3D kernel with cached inverses (p = 2)."""
+    wait_failure_roundtrip(torch, ctx, SMALL[case](), case, cache)
+
+
+def wait_failure_roundtrip(torch, ctx, wp, case, cache):
     from paper_1810_11080_amd import Problem
     from paper_1810_11080_amd.binding import SnswError
-    wp = SMALL[case]()
     print(f"wait failure: {case}, cache {cache}", flush=True)
     P = Problem.from_workload(ctx, wp, schedule=1, cache_inverse=cache)
     with pytest.raises(SnswError):
@@ -395,15 +398,18 @@ UNSTRUCTURED = {
 }
 
 
+@pytest.mark.parametrize("schedule", [2, 1], ids=["levels", "persistent"])
 @pytest.mark.parametrize("cache", [1, 2], ids=["inverse", "assembled"])
 @pytest.mark.parametrize("case", sorted(UNSTRUCTURED))
-def test_unstructured_sweeps_match_oracle(torch, ctx, case, cache):
-    """Unstructured conforming meshes (level schedule): three sweeps against
-    the oracle, with cached inverses and assembled per sweep."""
+def test_unstructured_sweeps_match_oracle(torch, ctx, case, cache, schedule):
+    """Unstructured conforming meshes: three sweeps against the oracle, with
+    cached inverses and assembled per sweep, on the level schedule and on the
+    generic persistent kernels (per-value waits, upwind nodes from the
+    table)."""
     from paper_1810_11080_amd import Problem
     wp = UNSTRUCTURED[case]()
-    P = Problem.from_workload(ctx, wp, cache_inverse=cache)
-    assert P.info()["schedule"] == 2
+    P = Problem.from_workload(ctx, wp, cache_inverse=cache, schedule=schedule)
+    assert P.info()["schedule"] == schedule
     g_phi, g_psi = gpu_sweeps(torch, P, 3)
     P.synchronize()
     o_phi, o_psi, _, _ = oracle_sweeps(wp, 3)
@@ -446,15 +452,16 @@ SIMPLEX = {
 }
 
 
+@pytest.mark.parametrize("schedule", [2, 1], ids=["levels", "persistent"])
 @pytest.mark.parametrize("cache", [1, 2], ids=["inverse", "assembled"])
 @pytest.mark.parametrize("case", sorted(SIMPLEX))
-def test_triangle_sweeps_match_oracle(torch, ctx, case, cache):
-    """Triangle meshes (level schedule): three sweeps against the oracle,
-    with cached inverses and assembled per sweep."""
+def test_triangle_sweeps_match_oracle(torch, ctx, case, cache, schedule):
+    """Triangle meshes: three sweeps against the oracle, with cached inverses
+    and assembled per sweep, level schedule and persistent kernels."""
     from paper_1810_11080_amd import Problem
     wp = SIMPLEX[case]()
-    P = Problem.from_workload(ctx, wp, cache_inverse=cache)
-    assert P.info()["schedule"] == 2 and P.n == (wp.p + 1) * (wp.p + 2) // 2
+    P = Problem.from_workload(ctx, wp, cache_inverse=cache, schedule=schedule)
+    assert P.info()["schedule"] == schedule and P.n == (wp.p + 1) * (wp.p + 2) // 2
     g_phi, g_psi = gpu_sweeps(torch, P, 3)
     P.synchronize()
     o_phi, o_psi, _, _ = oracle_sweeps(wp, 3)
@@ -529,3 +536,10 @@ def test_romberg_face_rule_sweeps(torch, ctx, case):
     for k in range(3):
         assert rel_err(g_phi[k], o_phi[k]) < TOL, (case, k)
     assert rel_err(g_psi[-1], o_psi[-1]) < TOL
+
+
+@pytest.mark.parametrize("case,cache", [("t_annulus_p2", 1), ("t_square_p3", 2), ("u_annulus", 1), ("u_shell", 2)])
+def test_wait_failure_element_lists(torch, ctx, case, cache):
+    """The forced failure path (zero-poll wait bound) of the generic
+    persistent kernels on element lists, and recovery bit for bit."""
+    wait_failure_roundtrip(torch, ctx, (SIMPLEX if case in SIMPLEX else UNSTRUCTURED)[case](), case, cache)

@@ -184,7 +184,7 @@ def test_set_source_validation(ctx):
 
 def test_unstructured_input_errors(ctx):
     """Bad element lists are reported, not swept: an index out of range, a
-    face shared by three element slots, a persistent schedule request."""
+    face shared by three element slots; triangles only as 2D element lists."""
     from paper_1810_11080_amd import Problem, SnswError
     wp = W.annulus_full(nr=2, nt=8, p=1, sn_order=2)
     en = wp.elem_nodes.copy()
@@ -199,9 +199,9 @@ def test_unstructured_input_errors(ctx):
         Problem(ctx, dim=2, nx=(E, 1), geom_order=wp.r, dg_order=wp.p, lattice=None, sn_order=2,
                 sigma_t=np.ones(E), sigma_s=np.zeros(E), q=np.ones(E), nodes=wp.nodes, elem_nodes=dup)
     assert ei.value.code == -2
-    with pytest.raises(SnswError) as ei:
-        Problem.from_workload(ctx, wp, schedule=1)
-    assert ei.value.code == -9
+    # element lists sweep on the level schedule unless the persistent one is asked for
+    assert Problem.from_workload(ctx, wp).info()["schedule"] == 2
+    assert Problem.from_workload(ctx, wp, schedule=1).info()["schedule"] == 1
     # triangles: only as element lists, only in 2D, with (r+1)(r+2)/2 control
     # points per element
     tw = W.tri_square(n=2, r=2, p=1, sn_order=2)
