@@ -21,7 +21,7 @@ import numpy as np
 from . import quadrature
 from .faces import FaceSet
 from .geometry import ElementGeometry, problem_control_points
-from .simplex import SimplexGeometry
+from .simplex import SimplexGeometry, TetGeometry
 
 VACUUM, ISO_CONST, TABULATED = 0, 1, 2
 
@@ -39,14 +39,18 @@ class Discretization:
         self.unstructured = getattr(prob, "elem_nodes", None) is not None
         self.simplex = getattr(prob, "element", "tensor") == "simplex"
         self.E = len(prob.elem_nodes) if self.unstructured else int(np.prod(self.nx))
-        self.n = (self.p + 1) * (self.p + 2) // 2 if self.simplex else (self.p + 1) ** self.dim
+        if self.simplex:
+            k = self.p
+            self.n = (k + 1) * (k + 2) // 2 if self.dim == 2 else (k + 1) * (k + 2) * (k + 3) // 6
+        else:
+            self.n = (self.p + 1) ** self.dim
         if omega is None:
             omega, w = quadrature.level_symmetric(prob.sn_order, prob.dim)
         self.omega, self.w = np.asarray(omega), np.asarray(w)
         self.D = len(self.w)
         xe = problem_control_points(prob)
         if self.simplex:
-            self.geo = SimplexGeometry(xe, self.r, self.p)
+            self.geo = (SimplexGeometry if self.dim == 2 else TetGeometry)(xe, self.r, self.p)
         else:
             self.geo = ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p, xe=xe)
         self.geo.check_positive()
@@ -107,7 +111,8 @@ class Discretization:
         self.inflow_fn = inflow_fn
         self.src_load = None
         if source_fn is not None:
-            fine = (SimplexGeometry(xe, self.r, self.p, extra_points=4) if self.simplex else
+            fine = ((SimplexGeometry if self.dim == 2 else TetGeometry)(xe, self.r, self.p, extra_points=4)
+                    if self.simplex else
                     ElementGeometry(prob.lattice, self.dim, self.nx, self.r, self.p, extra_points=4, xe=xe))
             self.src_load = np.stack([fine.load(source_fn(fine.x, self.omega[d]))
                                       for d in range(self.D)])

@@ -157,13 +157,20 @@ class FaceSet:
 
     romberg_tol = None   # relative tolerance of adaptive Romberg on sign-changing faces, or None
 
+    tri_faces = False   # faces are triangles (tetrahedra)
+
     def _finish(self):
         self.n_faces = len(self.axis)
         self.interior = (self.minus >= 0) & (self.plus >= 0)
-        self.nf = (self.p + 1) ** (self.dim - 1)
+        if self.tri_faces:
+            self.nf = (self.p + 1) * (self.p + 2) // 2
+        else:
+            self.nf = (self.p + 1) ** (self.dim - 1)
         self._geo_nodes = basis.equispaced_points(self.r)
         self._dg_nodes = basis.gll_points(self.p)
-        if self.dim == 3:
+        if self.tri_faces:
+            self._setup_tri_rule()
+        elif self.dim == 3:
             self._setup_3d_rule()
         # |int N ds_ref| per face (the face's area scale)
         if self.dim == 2:
@@ -180,7 +187,8 @@ class FaceSet:
 
         simplex: the elements are P_r triangles (``simplex`` module: three
         counter-clockwise edge slots, whose N of the 2D axis-0 formula is the
-        outward normal, so no slot is mirrored and every face has axis 0).
+        outward normal, so no slot is mirrored and every face has axis 0) or,
+        in 3D, tetrahedra (``from_tets``).
 
         Two element slots are the same face when their corner control points
         coincide (by index).  Convention for each face: its minus element is
@@ -194,11 +202,11 @@ class FaceSet:
         shared control points.  Slot tables: per (element, slot) the face,
         the side (0 minus, 1 plus) and the element's DG nodes listed in the
         face's (s, t) order."""
+        if simplex and dim == 3:
+            return cls.from_tets(nodes, elem_nodes, r, p)
         fs = cls.__new__(cls)
         nodes = np.asarray(nodes, dtype=np.float64)
         en = np.asarray(elem_nodes, dtype=np.int64)
-        if simplex and dim != 2:
-            raise ValueError("simplicial elements: triangles (dim 2) only")
         E, ns = len(en), (3 if simplex else 2 * dim)
         fs.dim, fs.r, fs.p, fs.nx = dim, r, p, (E,) + (1,) * (dim - 1)
         nfc = (r + 1) ** (dim - 1)
@@ -293,6 +301,82 @@ class FaceSet:
         fs._finish()
         return fs
 
+    @classmethod
+    def from_tets(cls, nodes, elem_nodes, r: int, p: int):
+        """Faces of a conforming mesh of P_r tetrahedra.  A face is the set of
+        its three corner control points; its minus element is the one with
+        the smaller index (the only one on the boundary) and the face takes
+        that slot's vertex order and triangle coordinates, so N = x_s x x_t
+        is the minus element's outward normal.  The plus element's slot
+        lists the same three corners in another order: a face node with
+        barycentric coordinates c over the minus order has them permuted
+        over the plus order, which gives the plus element's node on the same
+        point."""
+        fs = cls.__new__(cls)
+        nodes = np.asarray(nodes, dtype=np.float64)
+        en = np.asarray(elem_nodes, dtype=np.int64)
+        E, ns = len(en), 4
+        fs.dim, fs.r, fs.p, fs.nx = 3, r, p, (E, 1, 1)
+        fs.tri_faces = True
+        ctrl = [simplex_ref.tet_slot_nodes(r, sl) for sl in range(ns)]
+        dgl = [simplex_ref.tet_slot_nodes(p, sl) for sl in range(ns)]
+        ccorner = [0, r, len(simplex_ref.lattice(r)) - 1]        # face lattice (0,0), (r,0), (0,r)
+
+        def face_index(k):
+            return {(int(a), int(b)): q for q, (a, b) in enumerate(simplex_ref.lattice(k))}
+
+        table = {}
+        for e in range(E):
+            for sl in range(ns):
+                key = frozenset(int(en[e, ctrl[sl][c]]) for c in ccorner)
+                table.setdefault(key, []).append((e, sl))
+        recs = sorted((sorted(v) for v in table.values()), key=lambda v: v[0])
+        F = len(recs)
+        nfc = len(simplex_ref.lattice(r))
+        fs.axis = np.zeros(F, dtype=np.int64)
+        fs.minus = np.full(F, -1, dtype=np.int64)
+        fs.plus = np.full(F, -1, dtype=np.int64)
+        fs.ctrl = np.zeros((F, nfc, 3))
+        fs.slot_face = np.full((E, ns), -1, dtype=np.int64)
+        fs.slot_side = np.zeros((E, ns), dtype=np.int64)
+        fs.slot_trace = np.zeros((E, ns, len(simplex_ref.lattice(p))), dtype=np.int64)
+        fi = {k: face_index(k) for k in (r, p)}
+        for f, rec in enumerate(recs):
+            if len(rec) > 2 or (len(rec) == 2 and rec[0][0] == rec[1][0]):
+                raise ValueError(f"non-conforming face {rec}")
+            em, sm = rec[0]
+            ids = en[em][ctrl[sm]]
+            fs.minus[f] = em
+            fs.ctrl[f] = nodes[ids]
+            fs.slot_face[em, sm] = f
+            fs.slot_side[em, sm] = 0
+            fs.slot_trace[em, sm] = dgl[sm]
+            if len(rec) == 1:
+                continue
+            ep, sp = rec[1]
+            fs.plus[f] = ep
+            fs.slot_face[ep, sp] = f
+            fs.slot_side[ep, sp] = 1
+            mc = [int(ids[c]) for c in ccorner]
+            pc = [int(en[ep][ctrl[sp][c]]) for c in ccorner]
+            perm = [pc.index(v) for v in mc]        # minus vertex i is plus vertex perm[i]
+
+            def plus_local(k, q):
+                a, b = simplex_ref.lattice(k)[q]
+                c = [k - a - b, a, b]
+                cp = [0, 0, 0]
+                for i in range(3):
+                    cp[perm[i]] = c[i]
+                return fi[k][(cp[1], cp[2])]
+            for q in range(nfc):
+                if int(en[ep][ctrl[sp][plus_local(r, q)]]) != int(ids[q]):
+                    raise ValueError(f"face {f}: control points of elements {em} and {ep} do not match")
+            fs.slot_trace[ep, sp] = [dgl[sp][plus_local(p, q)] for q in range(len(dgl[sp]))]
+        if np.any(fs.slot_face < 0):
+            raise ValueError("an element slot has no face")
+        fs._finish()
+        return fs
+
     # ------------------------------------------------------------------
     def face_of_slot(self, e_idx: np.ndarray, slot: int):
         """Face id and side (0 = element is minus, 1 = plus) of element slot.
@@ -353,6 +437,21 @@ class FaceSet:
         t2 = np.einsum("qm,fma->fqa", Dt, self.ctrl)
         n12 = np.cross(t1, t2)
         return np.where((self.axis == 1)[:, None, None], -n12, n12)
+
+    def _tri_normals(self, pts: np.ndarray) -> np.ndarray:
+        """N = x_s x x_t of every triangular face at reference points (Q, 2): (F, Q, 3)."""
+        _, G = simplex_ref.lagrange(simplex_ref.geometry_nodes(self.r), self.r, pts)   # (Q, nfc, 2)
+        t1 = np.einsum("qm,fma->fqa", G[:, :, 0], self.ctrl)
+        t2 = np.einsum("qm,fma->fqa", G[:, :, 1], self.ctrl)
+        return np.cross(t1, t2)
+
+    def _setup_tri_rule(self):
+        """Fixed composite rule of triangular faces: K x K congruent
+        sub-triangles (K = 4), the collapsed Gauss rule of p + r points per
+        direction on each (exact where Omega . N keeps its sign)."""
+        self.rule3_pts, self.rule3_w = simplex_ref.triangle_composite_rule(KINK_SUBDIV_3D, self.p + self.r)
+        self.rule3_phi, _ = simplex_ref.lagrange(simplex_ref.dg_nodes(self.p), self.p, self.rule3_pts)
+        self.rule3_N = self._tri_normals(self.rule3_pts)
 
     def _setup_3d_rule(self):
         K = KINK_SUBDIV_3D
@@ -441,7 +540,19 @@ class FaceSet:
             pm = (gm[:, None, None] * phi[:, :, None] * phi[:, None, :]).reshape(len(g), -1)
             return np.concatenate([pp, pm, gp[:, None], gm[:, None]], axis=1)
 
-        if self.dim == 2:
+        if self.tri_faces:
+            # collapsed coordinates: (s, t) = (u, v (1 - u)), area element 1 - u
+            dgn, geon = simplex_ref.dg_nodes(self.p), simplex_ref.geometry_nodes(self.r)
+            X = self.ctrl[f]
+
+            def F(v, u):
+                pts = np.stack([np.full(len(v), u), v * (1.0 - u)], axis=1)
+                phi, _ = simplex_ref.lagrange(dgn, self.p, pts)
+                _, G = simplex_ref.lagrange(geon, self.r, pts)
+                N = np.cross(G[:, :, 0] @ X, G[:, :, 1] @ X)
+                return values(N @ om, phi) * (1.0 - u)
+            out = romberg_square(F, tol)
+        elif self.dim == 2:
             def F(s):
                 return values(self._normal_fast(f, s, 0.0, geo) @ om, dg.val(s))
             out = romberg(F, 0.0, 1.0, tol)

@@ -225,3 +225,132 @@ def test_numbering_and_frames_do_not_matter(maker):
     maps = [W.tri_rotation_map(p0.p, t) for t in range(3)]
     back = np.stack([phi0[perm[k]][maps[turns[k]]] for k in range(len(perm))])
     assert np.abs(phi1 - back).max() < 1e-12 * np.abs(back).max()
+
+
+# ----------------------------------------------------------------- tetrahedra
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_tet_nodal_basis(k):
+    nodes = simplex.tet_dg_nodes(k)
+    assert len(nodes) == simplex.tet_n_nodes(k)
+    V, G = simplex.tet_lagrange(nodes, k, nodes)
+    assert np.allclose(V, np.eye(len(nodes)), atol=1e-12)
+    pts = np.random.default_rng(k).dirichlet(np.ones(4), size=40)[:, :3]
+    V, G = simplex.tet_lagrange(nodes, k, pts)
+    assert np.allclose(V.sum(axis=1), 1.0, atol=1e-12)
+    assert np.allclose(G.sum(axis=1), 0.0, atol=1e-11)
+    x, y, z = pts.T
+    for a in range(k + 1):
+        for b in range(k + 1 - a):
+            for c in range(k + 1 - a - b):
+                f = nodes[:, 0] ** a * nodes[:, 1] ** b * nodes[:, 2] ** c
+                assert np.allclose(V @ f, x ** a * y ** b * z ** c, atol=1e-11)
+    # every face carries the triangle's DG node set, placed on that face
+    tri = simplex.dg_nodes(k)
+    Vt = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    for s in range(4):
+        A, B, C = simplex.TET_FACES[s]
+        want = Vt[A][None] + tri[:, :1] * (Vt[B] - Vt[A])[None] + tri[:, 1:] * (Vt[C] - Vt[A])[None]
+        assert np.allclose(nodes[simplex.tet_slot_nodes(k, s)], want, atol=1e-15)
+        # outward: the face normal (B - A) x (C - A) points away from the opposite vertex
+        nrm = np.cross(Vt[B] - Vt[A], Vt[C] - Vt[A])
+        assert nrm @ (Vt[s] - Vt[A]) < 0
+
+
+@pytest.mark.parametrize("nq", [1, 2, 3])
+def test_tet_collapsed_rule_monomials(nq):
+    x, w = simplex.tet_collapsed_rule(nq)
+    for a in range(2 * nq - 2):
+        for b in range(2 * nq - 2 - a):
+            for c in range(2 * nq - 2 - a - b):
+                exact = math.factorial(a) * math.factorial(b) * math.factorial(c) / math.factorial(a + b + c + 3)
+                assert abs(np.sum(w * x[:, 0] ** a * x[:, 1] ** b * x[:, 2] ** c) - exact) < 1e-15
+
+
+def test_tet_affine_mass_closed_form():
+    rng = np.random.default_rng(5)
+    A = rng.normal(size=(4, 3))
+    if np.linalg.det(A[1:] - A[0]) < 0:
+        A = A[[0, 2, 1, 3]]
+    vol = np.linalg.det(A[1:] - A[0]) / 6.0
+    xe = A[0] + simplex.tet_geometry_nodes(1) @ (A[1:] - A[0])
+    M = simplex.TetGeometry(xe[None], 1, 1).mass()[0]
+    assert np.abs(M - vol / 20.0 * (np.ones((4, 4)) + np.eye(4))).max() < 1e-14 * max(1.0, vol)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.tet_cube(n=2, r=2, p=2, seed=3),
+    lambda: W.tet_cube(n=1, r=3, p=3, amp=0.05, seed=4),
+    lambda: W.tet_cube(n=2, r=1, p=1, seed=None),
+    lambda: W.tet_shell(nr=1, nt=6, nz=1, r=2, p=1, seed=1),
+    lambda: W.tet_shell(nr=1, nt=6, nz=1, r=1, p=2, seed=2),
+], ids=["cube-q2p2", "cube-q3p3", "cube-q1p1", "shell-q2p1", "shell-q1p2"])
+def test_tet_curved_invariants(make):
+    prob = make()
+    disc = Discretization(prob)
+    assert disc.geo.detJ.min() > 0
+    if prob.name.startswith("tet_cube"):
+        assert abs(disc.M.sum() - 1.0) < 1e-13            # the warp fixes the cube's boundary
+    assert np.abs(disc.K.sum(axis=2)).max() < 1e-13
+    xn = disc.geo.dg_node_positions()
+    if prob.r <= prob.p:
+        for i in range(3):
+            for j in range(3):
+                lhs = np.einsum("em,emn->en", xn[:, :, i], disc.K[:, j])
+                rhs = disc.M.sum(axis=1) if i == j else 0.0 * lhs
+                assert np.abs(lhs - rhs).max() < 1e-12
+    for i in range(3):
+        om = np.zeros(3)
+        om[i] = 1.0
+        Pp, Pm, *_ = disc.faces.integrals(om)
+        S = np.zeros((disc.E, disc.n, disc.n))
+        rows = np.arange(disc.E)[:, None, None]
+        for s in range(disc.ns):
+            fid = disc.slot_face[:, s]
+            sign = np.where(disc.slot_side[:, s] == 0, 1.0, -1.0)[:, None, None]
+            tn = disc.slot_trace[:, s]
+            S[rows, tn[:, :, None], tn[:, None, :]] += sign * (Pp[fid] - Pm[fid])
+        Ki = disc.K[:, i]
+        assert np.abs(Ki + Ki.transpose(0, 2, 1) - S).max() < 1e-12 * max(1, np.abs(S).max())
+    fs = disc.faces
+    for f in np.nonzero(fs.interior)[0]:
+        em, ep = fs.minus[f], fs.plus[f]
+        sm = int(np.nonzero(disc.slot_face[em] == f)[0][0])
+        sp = int(np.nonzero(disc.slot_face[ep] == f)[0][0])
+        assert np.allclose(xn[em, disc.slot_trace[em, sm]], xn[ep, disc.slot_trace[ep, sp]], atol=1e-13)
+    assert fs.n_faces == (4 * disc.E + (~fs.interior).sum()) // 2
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.tet_cube(n=1, r=1, p=1, seed=3),
+    lambda: W.tet_cube(n=1, r=2, p=2, amp=0.05, seed=4),
+    lambda: W.tet_shell(nr=1, nt=6, nz=1, r=2, p=2, seed=5),
+], ids=["cube-q1p1", "cube-q2p2", "shell-q2p2"])
+def test_tet_linear_solution_reproduced(make):
+    """As for triangles: a linear angular flux (r <= p) with its manufactured
+    source and tabulated inflow is the exact discrete solution on curved
+    tetrahedra, faces with sign changes of Omega . N included."""
+    prob = make()
+    prob.sigma_s[:] = 0.0
+    disc0 = Discretization(prob)
+    xn = disc0.geo.dg_node_positions()
+    rng = np.random.default_rng(13)
+    D = disc0.D
+    a = rng.uniform(0.5, 1.5, D)
+    b = rng.uniform(-0.3, 0.3, (D, 3))
+    psi_exact = a[:, None, None] + np.einsum("dc,enc->den", b, xn)
+    prob.q_dir = np.einsum("dc,dc->d", disc0.omega, b)[:, None, None] + prob.sigma_t[None, :, None] * psi_exact
+    prob.bc_kind = W.TABULATED
+    prob.psi_inc_tab = psi_exact
+    disc = Discretization(prob)
+    _, psi = dense.solve(disc)
+    assert np.abs(psi - psi_exact).max() < 1e-11 * np.abs(psi_exact).max()
+
+
+def test_tet_numbering_and_frames_do_not_matter():
+    p0, p1 = W.tet_cube(n=1, r=2, p=2, seed=None), W.tet_cube(n=1, r=2, p=2, seed=9)
+    phi0, _ = dense.solve(Discretization(p0))
+    phi1, _ = dense.solve(Discretization(p1))
+    perm, rot = p1.meta["perm"], p1.meta["rot"]
+    evens = W.tet_even_permutations()
+    back = np.stack([phi0[perm[k]][W.tet_rotation_map(p0.p, evens[rot[k]])] for k in range(len(perm))])
+    assert np.abs(phi1 - back).max() < 1e-12 * np.abs(back).max()

@@ -64,9 +64,10 @@ class Problem:
     # elements sharing a face share its control points (in any orientation)
     nodes: Optional[np.ndarray] = None        # (n_nodes, dim) float64
     elem_nodes: Optional[np.ndarray] = None   # (E, (r+1)^dim) int64
-    # "tensor" (quadrilaterals / hexahedra) or "simplex" (P_r triangles: then
-    # elem_nodes lists (r+1)(r+2)/2 control points per element in the
-    # triangle lattice order of tri_lattice, and n = (p+1)(p+2)/2)
+    # "tensor" (quadrilaterals / hexahedra) or "simplex" (P_r triangles /
+    # tetrahedra: then elem_nodes lists the element's control points in the
+    # lattice order of tri_lattice / tet_lattice, and n = (p+1)(p+2)/2 /
+    # (p+1)(p+2)(p+3)/6)
     element: str = "tensor"
     # integration of the face matrices on faces where Omega . n changes sign:
     # "exact" (2D: split at the roots; 3D: fixed composite rule) or
@@ -81,7 +82,8 @@ class Problem:
     @property
     def n_dof(self) -> int:
         if self.element == "simplex":
-            return (self.p + 1) * (self.p + 2) // 2
+            k = self.p
+            return (k + 1) * (k + 2) // 2 if self.dim == 2 else (k + 1) * (k + 2) * (k + 3) // 6
         return (self.p + 1) ** self.dim
 
     @property
@@ -725,3 +727,136 @@ def tri_annulus(nr: int = 3, nt: int = 12, r: int = 3, p: int = 2, sn_order: int
 
     return triangulated(f"tri_annulus_{nr}x{nt}_q{r}_p{p}_s{sn_order}", r, p, sn_order, nr, nt, x_of, sig, 1.0,
                         1.0, periodic_v=True, seed=seed, tol=1e-8, meta=dict(r_in=r_in, r_out=r_out))
+
+
+# --------------------------------------------------------------- tetrahedra
+def tet_lattice(k: int) -> np.ndarray:
+    """(n, 3) lattice triples (i, j, l), i + j + l <= k, of the nodes of order
+    k on a tetrahedron, l slowest then j: the local order of a tetrahedron's
+    control points (reference position (i, j, l) / k for vertices (0,0,0),
+    (1,0,0), (0,1,0), (0,0,1))."""
+    return np.array([(i, j, l) for l in range(k + 1) for j in range(k + 1 - l) for i in range(k + 1 - j - l)],
+                    dtype=np.int64)
+
+
+def tet_even_permutations() -> List[tuple]:
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(4)):
+        inv = sum(1 for a in range(4) for b in range(a + 1, 4) if perm[a] > perm[b])
+        if inv % 2 == 0:
+            out.append(perm)
+    return out
+
+
+def tet_rotation_map(r: int, perm) -> np.ndarray:
+    """Local index map of a tetrahedron whose vertex t becomes old vertex
+    perm[t] (an even permutation keeps the orientation): new local node k is
+    old node map[k]."""
+    L = tet_lattice(r)
+    idx = {tuple(int(v) for v in t): k for k, t in enumerate(L)}
+    out = []
+    for i, j, l in L:
+        cn = [r - i - j - l, i, j, l]
+        co = [0, 0, 0, 0]
+        for t in range(4):
+            co[perm[t]] = cn[t]
+        out.append(idx[(co[1], co[2], co[3])])
+    return np.array(out, dtype=np.int64)
+
+
+def tetrahedralized(name: str, r: int, p: int, sn_order: int, n: tuple, x_of, sigma_t, sigma_s, q,
+                    periodic_v: bool = False, seed: Optional[int] = None, **kw) -> Problem:
+    """Tetrahedra from an n[0] x n[1] x n[2] grid of cells on the parameter
+    cube [0, 1]^3, each cell cut into the six tetrahedra along its main
+    diagonal (the same cut in every cell, so the mesh is conforming), with
+    the vertex order chosen to keep the orientation, mapped by
+    x_of(u, v, w) -> (x, y, z) (orientation preserving): control points are
+    the map at each tetrahedron's order-r lattice points.  periodic_v: v = 1
+    is glued to v = 0.  sigma_t, sigma_s, q: per element or callables of the
+    cell centre.  With a seed the elements are renumbered and each one's
+    vertex order permuted by a random even permutation (meta 'perm',
+    'rot')."""
+    import itertools
+    fu, fv, fw = r * n[0] + 1, r * n[1] + (0 if periodic_v else 1), r * n[2] + 1
+    W_, V, U = np.meshgrid(np.arange(fw) / (r * n[2]), np.arange(fv) / (r * n[1]), np.arange(fu) / (r * n[0]),
+                           indexing="ij")
+    X = x_of(U.reshape(-1), V.reshape(-1), W_.reshape(-1))                 # u fastest, then v, then w
+    nodes = np.stack([np.asarray(c, dtype=np.float64) for c in X], axis=1)
+    L = tet_lattice(r)
+    elems, centres = [], []
+    for ck in range(n[2]):
+        for cj in range(n[1]):
+            for ci in range(n[0]):
+                base = np.array([ci, cj, ck]) * r
+                for perm in itertools.permutations(range(3)):
+                    e = [np.zeros(3, dtype=np.int64)]
+                    for a in perm:
+                        v = e[-1].copy()
+                        v[a] += 1
+                        e.append(v)
+                    verts = [e[0], e[1], e[2], e[3]]
+                    if np.linalg.det(np.stack([verts[1], verts[2], verts[3]]).astype(float)) < 0:
+                        verts = [verts[0], verts[2], verts[1], verts[3]]
+                    ids = []
+                    for i, j, l in L:
+                        pt = base + i * verts[1] + j * verts[2] + l * verts[3]
+                        ids.append(int(pt[0] + fu * ((pt[1] % fv) if periodic_v else pt[1]) + fu * fv * pt[2]))
+                    elems.append(ids)
+                    centres.append(((ci + 0.5) / n[0], (cj + 0.5) / n[1], (ck + 0.5) / n[2]))
+    en = np.array(elems, dtype=np.int64)
+    cu, cv, cw = np.array(centres).T
+    E = len(en)
+
+    def per_elem(v):
+        return np.asarray(v(cu, cv, cw) if callable(v) else np.broadcast_to(v, (E,)), dtype=np.float64).copy()
+
+    st, ss, qq = per_elem(sigma_t), per_elem(sigma_s), per_elem(q)
+    perm_e = np.arange(E)
+    rot = np.zeros(E, dtype=np.int64)
+    if seed is not None:
+        rng = np.random.default_rng(seed)
+        perm_e = rng.permutation(E)
+        evens = tet_even_permutations()
+        rot = rng.integers(0, len(evens), size=E)
+        maps = [tet_rotation_map(r, P_) for P_ in evens]
+        en = np.stack([en[perm_e[k]][maps[rot[k]]] for k in range(E)])
+        st, ss, qq = st[perm_e], ss[perm_e], qq[perm_e]
+    meta = dict(kw.pop("meta", {}), perm=perm_e, rot=rot, unstructured=True)
+    return Problem(name=name, dim=3, nx=(E, 1, 1), r=r, p=p, sn_order=sn_order, lattice=np.zeros((0, 3)),
+                   sigma_t=st, sigma_s=ss, q=qq, nodes=nodes, elem_nodes=en, element="simplex", meta=meta, **kw)
+
+
+def tet_cube(n: int = 2, r: int = 2, p: int = 2, sn_order: int = 4, amp: float = 0.04,
+             seed: Optional[int] = 3) -> Problem:
+    """Warped unit cube, x = u + amp sin(2 pi u) sin(2 pi v) sin(2 pi w) and
+    likewise for y, z with the factors shifted (the warp fixes the boundary),
+    n^3 cells cut into 6 n^3 curved order-r tetrahedra; checkerboard
+    sigma_t in {1, 4} by cell, sigma_s = 0.5, q = 1, vacuum."""
+    def x_of(u, v, w):
+        s = np.sin(2 * math.pi * u) * np.sin(2 * math.pi * v) * np.sin(2 * math.pi * w)
+        return u + amp * s, v + 0.7 * amp * s, w - 0.5 * amp * s
+
+    def sig(cu, cv, cw):
+        return np.where((np.floor(cu * n) + np.floor(cv * n) + np.floor(cw * n)) % 2 == 0, 1.0, 4.0)
+
+    return tetrahedralized(f"tet_cube_{n}_q{r}_p{p}_s{sn_order}", r, p, sn_order, (n, n, n), x_of, sig, 0.5, 1.0,
+                           seed=seed, tol=1e-10, meta=dict(amp=amp))
+
+
+def tet_shell(nr: int = 2, nt: int = 8, nz: int = 1, r: int = 2, p: int = 2, sn_order: int = 4,
+              r_in: float = 1.0, r_out: float = 2.0, height: float = 1.0, seed: Optional[int] = 1) -> Problem:
+    """Cylindrical shell r in [r_in, r_out], theta closed, z in [0, height],
+    of 6 nr nt nz curved order-r tetrahedra with control points on circles:
+    faces on which Omega . n changes sign and cyclic dependencies around the
+    hole; sigma_t 2.0 / 2.4 by radial half, sigma_s = 1, q = 1, vacuum."""
+    def x_of(u, v, w):
+        rho = r_in + (r_out - r_in) * u
+        return rho * np.cos(2 * math.pi * v), rho * np.sin(2 * math.pi * v), height * w
+
+    def sig(cu, cv, cw):
+        return np.where(cu < 0.5, 2.0, 2.4)
+
+    return tetrahedralized(f"tet_shell_{nr}x{nt}x{nz}_q{r}_p{p}_s{sn_order}", r, p, sn_order, (nr, nt, nz), x_of,
+                           sig, 1.0, 1.0, periodic_v=True, seed=seed, tol=1e-8,
+                           meta=dict(r_in=r_in, r_out=r_out, height=height))
