@@ -105,15 +105,25 @@ extern "C" {
 /* Element type of an unstructured mesh (snsw_problem_desc.element).
  * SIMPLEX: the simplicial elements that section 2 allows next to the
  * tensor-product ones (after eq. elementTransformation: P_r map and P_s
- * DG basis); 2D only (triangles).  Reference triangle {x, y >= 0,
- * x + y <= 1}, vertices v0 = (0,0), v1 = (1,0), v2 = (0,1).  Nodes of
- * order k sit on the lattice pairs (i, j), i + j <= k, numbered row by row
- * (j slowest): node (i, j) is local index j (k+1) - j (j-1)/2 + i.
+ * DG basis): triangles (dim 2) and tetrahedra (dim 3).
+ * Triangles: reference {x, y >= 0, x + y <= 1}, vertices v0 = (0,0),
+ * v1 = (1,0), v2 = (0,1).  Nodes of order k sit on the lattice pairs
+ * (i, j), i + j <= k, numbered row by row (j slowest): node (i, j) is local
+ * index j (k+1) - j (j-1)/2 + i.
  *   control points (k = r): at (i/r, j/r), elem_nodes [E][(r+1)(r+2)/2];
  *   DOFs (k = p): n = (p+1)(p+2)/2, on the edges at the Gauss-Lobatto
  *     points (g_i, g_j) of [0, 1], inside (p = 3: the centroid) at (i/p, j/p).
- * Every element map must keep the orientation (v0, v1, v2 counter-
- * clockwise).  Element slots are the edges v0->v1, v1->v2, v2->v0.         */
+ * Element slots are the edges v0->v1, v1->v2, v2->v0 (counter-clockwise).
+ * Tetrahedra: vertices V0 = (0,0,0), V1 = (1,0,0), V2 = (0,1,0),
+ * V3 = (0,0,1); nodes of order k on the lattice triples (i, j, l),
+ * i + j + l <= k, numbered with l slowest, then j, then i; barycentric
+ * lattice coordinates c = (k-i-j-l, i, j, l).
+ *   control points (k = r): at (i, j, l)/r, elem_nodes [E][(r+1)(r+2)(r+3)/6];
+ *   DOFs (k = p): n = (p+1)(p+2)(p+3)/6, at sum_v lambda_v V_v with
+ *     lambda_v = g_{c_v} on the edges (Gauss-Lobatto) and c_v/p elsewhere
+ *     (p = 3: the centroid of each face).
+ * Element slot s is the face opposite V_s.  Every element map must keep
+ * the orientation of its reference element (det J > 0).                   */
 #define SNSW_ELEM_TENSOR   0
 #define SNSW_ELEM_SIMPLEX  1
 
@@ -200,7 +210,7 @@ typedef struct {
     const double* nodes;
     const int64_t* elem_nodes;
     int32_t element;         /* SNSW_ELEM_*: element type of an unstructured
-                                mesh (SIMPLEX needs elem_nodes and dim 2)   */
+                                mesh (SIMPLEX needs elem_nodes)             */
     int32_t face_rule;       /* SNSW_FACE_*                                   */
     double  face_tol;        /* relative tolerance of SNSW_FACE_ROMBERG       */
 } snsw_problem_desc;

@@ -252,8 +252,9 @@ class Problem:
         values); psi_inc_tab: [D][E][n] incident flux for bc_kind 2.  With
         elem_nodes ([E][nv] control-point indices into nodes [n_nodes][dim])
         the mesh is unstructured: nx = (E, 1[, 1]) and lattice is ignored;
-        element 0: Q_r quads / hexes, nv = (r+1)^dim; 1: P_r triangles (2D),
-        nv = (r+1)(r+2)/2, n = (p+1)(p+2)/2.  face_rule 1: adaptive Romberg
+        element 0: Q_r quads / hexes, nv = (r+1)^dim; 1: P_r triangles
+        (nv = (r+1)(r+2)/2, n = (p+1)(p+2)/2) or tetrahedra (nv =
+        (r+1)(r+2)(r+3)/6, n = (p+1)(p+2)(p+3)/6).  face_rule 1: adaptive Romberg
         on faces where Omega . n changes sign, relative tolerance face_tol
         (<= 0: 1e-10)."""
         self.ctx = ctx
@@ -261,8 +262,12 @@ class Problem:
             raise SnswError(-1, "dim must be 2 or 3")
         E = int(np.prod(nx[:dim]))
         simplex = element == 1
-        n = (dg_order + 1) * (dg_order + 2) // 2 if simplex else (dg_order + 1) ** dim
-        nv = (geom_order + 1) * (geom_order + 2) // 2 if simplex else (geom_order + 1) ** dim
+
+        def count(k):   # nodes of order k on the element
+            if not simplex:
+                return (k + 1) ** dim
+            return (k + 1) * (k + 2) // 2 if dim == 2 else (k + 1) * (k + 2) * (k + 3) // 6
+        n, nv = count(dg_order), count(geom_order)
         self._keep = []
 
         def arr(x, size=None):

@@ -217,4 +217,162 @@ void tri_collapsed_rule(int nq, std::vector<double>& x, std::vector<double>& y, 
         }
 }
 
+// ----------------------------------------------------------- tetrahedra
+// Reference tetrahedron with vertices V0 = (0,0,0), V1 = (1,0,0),
+// V2 = (0,1,0), V3 = (0,0,1); nodes of order k on the lattice triples
+// (i, j, l), i + j + l <= k, numbered with l slowest, then j, then i.
+
+int tet_index(int k, int i, int j, int l) {
+    int m = 0;
+    for (int ll = 0; ll < l; ++ll) m += (k + 1 - ll) * (k + 2 - ll) / 2;
+    const int kk = k - l;   // the layer l is a triangle of order k - l
+    return m + j * (kk + 1) - j * (j - 1) / 2 + i;
+}
+
+// Vertices of face slot s (the face opposite V_s), in the order that makes
+// x_s x x_t point out of the element.
+static const int kTetFace[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+
+std::vector<int32_t> tet_slot_nodes(int k, int s) {
+    std::vector<int32_t> out;
+    for (int b = 0; b <= k; ++b)
+        for (int a = 0; a + b <= k; ++a) {
+            int c[4] = {0, 0, 0, 0};
+            c[kTetFace[s][0]] = k - a - b;
+            c[kTetFace[s][1]] = a;
+            c[kTetFace[s][2]] = b;
+            out.push_back(tet_index(k, c[1], c[2], c[3]));
+        }
+    return out;
+}
+
+std::vector<double> tet_geometry_nodes(int r) {
+    std::vector<double> x;
+    for (int l = 0; l <= r; ++l)
+        for (int j = 0; j + l <= r; ++j)
+            for (int i = 0; i + j + l <= r; ++i) {
+                x.push_back((double)i / r);
+                x.push_back((double)j / r);
+                x.push_back((double)l / r);
+            }
+    return x;
+}
+
+std::vector<double> tet_dg_nodes(int p) {
+    const std::vector<double> g = gll01(p);
+    std::vector<double> x;
+    for (int l = 0; l <= p; ++l)
+        for (int j = 0; j + l <= p; ++j)
+            for (int i = 0; i + j + l <= p; ++i) {
+                const int c[4] = {p - i - j - l, i, j, l};
+                int nz = 0;
+                for (int v = 0; v < 4; ++v) nz += c[v] > 0;
+                // on an edge (two nonzero coordinates): Gauss-Lobatto; else equispaced
+                for (int v = 1; v < 4; ++v) x.push_back(nz <= 2 ? g[c[v]] : (double)c[v] / p);
+            }
+    return x;
+}
+
+TetBasis::TetBasis(const std::vector<double>& nodes, int k_) : k(k_), n((k_ + 1) * (k_ + 2) * (k_ + 3) / 6) {
+    for (int c = 0; c <= k; ++c)
+        for (int b = 0; b + c <= k; ++b)
+            for (int a = 0; a + b + c <= k; ++a) mono.push_back({a, b, c});
+    std::vector<double> V((size_t)n * n), I((size_t)n * n, 0.0);
+    for (int m = 0; m < n; ++m) {
+        I[(size_t)m * n + m] = 1.0;
+        for (int t = 0; t < n; ++t)
+            V[(size_t)m * n + t] = std::pow(nodes[3 * m], mono[t][0]) * std::pow(nodes[3 * m + 1], mono[t][1]) *
+                                   std::pow(nodes[3 * m + 2], mono[t][2]);
+    }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r2 = c + 1; r2 < n; ++r2)
+            if (std::fabs(V[(size_t)r2 * n + c]) > std::fabs(V[(size_t)piv * n + c])) piv = r2;
+        if (std::fabs(V[(size_t)piv * n + c]) < 1e-14) throw Error(SNSW_E_STATE, "tetrahedron nodes are not unisolvent");
+        for (int t = 0; t < n; ++t) {
+            std::swap(V[(size_t)c * n + t], V[(size_t)piv * n + t]);
+            std::swap(I[(size_t)c * n + t], I[(size_t)piv * n + t]);
+        }
+        const double d = 1.0 / V[(size_t)c * n + c];
+        for (int t = 0; t < n; ++t) {
+            V[(size_t)c * n + t] *= d;
+            I[(size_t)c * n + t] *= d;
+        }
+        for (int r2 = 0; r2 < n; ++r2) {
+            if (r2 == c) continue;
+            const double f = V[(size_t)r2 * n + c];
+            if (f == 0.0) continue;
+            for (int t = 0; t < n; ++t) {
+                V[(size_t)r2 * n + t] -= f * V[(size_t)c * n + t];
+                I[(size_t)r2 * n + t] -= f * I[(size_t)c * n + t];
+            }
+        }
+    }
+    C = I;
+}
+
+void TetBasis::eval(double x, double y, double z, double* val, double* dx, double* dy, double* dz) const {
+    auto pw = [](double t, int e) { return e < 0 ? 0.0 : std::pow(t, e); };
+    for (int m = 0; m < n; ++m) {
+        if (val) val[m] = 0.0;
+        if (dx) dx[m] = 0.0;
+        if (dy) dy[m] = 0.0;
+        if (dz) dz[m] = 0.0;
+    }
+    for (int t = 0; t < n; ++t) {
+        const int a = mono[t][0], b = mono[t][1], c = mono[t][2];
+        const double v = pw(x, a) * pw(y, b) * pw(z, c);
+        const double vx = a * pw(x, a - 1) * pw(y, b) * pw(z, c);
+        const double vy = b * pw(x, a) * pw(y, b - 1) * pw(z, c);
+        const double vz = c * pw(x, a) * pw(y, b) * pw(z, c - 1);
+        const double* Ct = &C[(size_t)t * n];
+        for (int m = 0; m < n; ++m) {
+            if (val) val[m] += v * Ct[m];
+            if (dx) dx[m] += vx * Ct[m];
+            if (dy) dy[m] += vy * Ct[m];
+            if (dz) dz[m] += vz * Ct[m];
+        }
+    }
+}
+
+void tet_collapsed_rule(int nq, std::vector<double>& x, std::vector<double>& y, std::vector<double>& z,
+                        std::vector<double>& w) {
+    std::vector<double> g, gw;
+    gauss_legendre01(nq, g, gw);
+    x.clear();
+    y.clear();
+    z.clear();
+    w.clear();
+    for (int a = 0; a < nq; ++a)
+        for (int b = 0; b < nq; ++b)
+            for (int c = 0; c < nq; ++c) {
+                x.push_back(g[a]);
+                y.push_back(g[b] * (1.0 - g[a]));
+                z.push_back(g[c] * (1.0 - g[a]) * (1.0 - g[b]));
+                w.push_back(gw[a] * gw[b] * gw[c] * (1.0 - g[a]) * (1.0 - g[a]) * (1.0 - g[b]));
+            }
+}
+
+void tri_composite_rule(int K, int nq, std::vector<double>& s, std::vector<double>& t, std::vector<double>& w) {
+    std::vector<double> x, y, wq;
+    tri_collapsed_rule(nq, x, y, wq);
+    s.clear();
+    t.clear();
+    w.clear();
+    for (int j = 0; j < K; ++j)
+        for (int i = 0; i + j < K; ++i) {
+            for (size_t q = 0; q < wq.size(); ++q) {   // upward sub-triangle at corner (i, j) / K
+                s.push_back((i + x[q]) / K);
+                t.push_back((j + y[q]) / K);
+                w.push_back(wq[q] / (K * K));
+            }
+            if (i + j < K - 1)
+                for (size_t q = 0; q < wq.size(); ++q) {   // downward one, corner (i+1, j+1) / K
+                    s.push_back((i + 1 - x[q]) / K);
+                    t.push_back((j + 1 - y[q]) / K);
+                    w.push_back(wq[q] / (K * K));
+                }
+        }
+}
+
 }  // namespace snsw

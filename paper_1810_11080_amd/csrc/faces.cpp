@@ -36,6 +36,20 @@ namespace snsw {
 
 namespace {
 constexpr int kSub3 = 4;
+
+// N = x_s x x_t of a triangular face from its control points X [nfc][3] and
+// the basis derivatives at one point.
+void tri_face_normal(const double* X, int nfc, const double* gs, const double* gt, double* N) {
+    double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0};
+    for (int m = 0; m < nfc; ++m)
+        for (int c = 0; c < 3; ++c) {
+            t1[c] += X[m * 3 + c] * gs[m];
+            t2[c] += X[m * 3 + c] * gt[m];
+        }
+    N[0] = t1[1] * t2[2] - t1[2] * t2[1];
+    N[1] = t1[2] * t2[0] - t1[0] * t2[2];
+    N[2] = t1[0] * t2[1] - t1[1] * t2[0];
+}
 }  // namespace
 
 void face_geometry(HostProblem& hp);
@@ -64,15 +78,32 @@ std::vector<int32_t> slot_local_nodes(int dim, int order, int s) {
     return out;
 }
 
-// The symmetries of the reference face as maps of face-local grid indices
-// at per-axis order n1 - 1: 2D (identity, reversal); 3D the eight maps
-// (i, j) -> (x, y) or (y, x) with x in {i, n1-1-i}, y in {j, n1-1-j}.
-int face_sym_count(int dim) { return dim == 2 ? 2 : 8; }
-int face_sym(int dim, int t, int n1, int l) {
-    if (dim == 2) return t ? n1 - 1 - l : l;
-    const int i = l % n1, j = l / n1;
-    const int x = (t & 1) ? n1 - 1 - i : i, y = (t & 2) ? n1 - 1 - j : j;
-    return (t & 4) ? y + n1 * x : x + n1 * y;
+// Kinds of reference faces: a segment (2D elements), a square (hexahedra),
+// a triangle (tetrahedra).
+enum FaceKind { FK_SEG = 2, FK_QUAD = 3, FK_TRI = 4 };
+FaceKind face_kind(const HostProblem& hp) { return hp.dim == 2 ? FK_SEG : (hp.simplex ? FK_TRI : FK_QUAD); }
+
+// The symmetries of the reference face as maps of face-local node indices at
+// order k: segment (identity, reversal); square the eight maps
+// (i, j) -> (x, y) or (y, x) with x in {i, k-i}, y in {j, k-j}; triangle the
+// six permutations of its vertices acting on the barycentric lattice
+// coordinates (k - a - b, a, b) of node (a, b).
+int face_sym_count(FaceKind kind) { return kind == FK_SEG ? 2 : (kind == FK_QUAD ? 8 : 6); }
+int face_sym(FaceKind kind, int t, int k, int l) {
+    if (kind == FK_SEG) return t ? k - l : l;
+    if (kind == FK_QUAD) {
+        const int n1 = k + 1, i = l % n1, j = l / n1;
+        const int x = (t & 1) ? k - i : i, y = (t & 2) ? k - j : j;
+        return (t & 4) ? y + n1 * x : x + n1 * y;
+    }
+    static const int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int b = 0, rem = l;
+    while (rem > k - b) rem -= k - b + 1, ++b;   // row b of the triangle lattice holds k - b + 1 nodes
+    const int a = rem;
+    const int c[3] = {k - a - b, a, b};
+    int cp[3] = {0, 0, 0};
+    for (int i = 0; i < 3; ++i) cp[kPerm[t][i]] = c[i];
+    return tri_index(k, cp[1], cp[2]);
 }
 
 // Faces of an unstructured conforming mesh.  Two element slots are one face
@@ -86,21 +117,34 @@ int face_sym(int dim, int t, int n1, int l) {
 //
 // Triangles: the three edge slots run counter-clockwise (v0 -> v1 -> v2), so
 // the axis-0 normal of the slot's own order is already the outward normal:
-// no slot is mirrored and every face has axis 0.
+// no slot is mirrored and every face has axis 0.  Tetrahedra: the four
+// triangular face slots list their vertices in the outward order, so again
+// no slot is mirrored; faces are matched by their three corners.
 void unstructured_topology(HostProblem& hp) {
-    const int dim = hp.dim, r = hp.r, p = hp.p, nf = hp.nf, ns = hp.simplex ? 3 : 2 * dim;
+    const int dim = hp.dim, r = hp.r, p = hp.p, nf = hp.nf;
+    const int ns = hp.simplex ? dim + 1 : 2 * dim;
+    const FaceKind kind = face_kind(hp);
     const int64_t E = hp.E;
     const int Nv = hp.nv;
-    const int nloc = dim == 2 ? r + 1 : (r + 1) * (r + 1);
+    const int nloc = kind == FK_SEG ? r + 1 : (kind == FK_QUAD ? (r + 1) * (r + 1) : (r + 1) * (r + 2) / 2);
     std::vector<std::vector<int32_t>> cl(ns), dl(ns);
     for (int s = 0; s < ns; ++s) {
-        cl[s] = hp.simplex ? tri_slot_nodes(r, s) : slot_local_nodes(dim, r, s);
-        dl[s] = hp.simplex ? tri_slot_nodes(p, s) : slot_local_nodes(dim, p, s);
+        if (kind == FK_TRI) {
+            cl[s] = tet_slot_nodes(r, s);
+            dl[s] = tet_slot_nodes(p, s);
+        } else if (hp.simplex) {
+            cl[s] = tri_slot_nodes(r, s);
+            dl[s] = tri_slot_nodes(p, s);
+        } else {
+            cl[s] = slot_local_nodes(dim, r, s);
+            dl[s] = slot_local_nodes(dim, p, s);
+        }
     }
-    const int nc = dim == 2 ? 2 : 4;
+    const int nc = kind == FK_SEG ? 2 : (kind == FK_QUAD ? 4 : 3);
     auto corner = [&](int k) {   // face-local index of corner k
         const int R = r;
-        if (dim == 2) return k ? R : 0;
+        if (kind == FK_SEG) return k ? R : 0;
+        if (kind == FK_TRI) return k == 0 ? 0 : (k == 1 ? R : nloc - 1);
         return (k & 1 ? R : 0) + (r + 1) * (k & 2 ? R : 0);
     };
     struct Key {
@@ -148,20 +192,20 @@ void unstructured_topology(HostProblem& hp) {
         hp.f_slot_minus[f] = (int8_t)sm;
         std::vector<int64_t> ids(nloc);
         for (int l = 0; l < nloc; ++l) {
-            ids[l] = hp.elem_nodes[(size_t)em * Nv + cl[sm][face_sym(dim, tm, r + 1, l)]];
+            ids[l] = hp.elem_nodes[(size_t)em * Nv + cl[sm][face_sym(kind, tm, r, l)]];
             for (int c = 0; c < dim; ++c) hp.f_ctrl[((size_t)f * nloc + l) * dim + c] = hp.nodes[(size_t)ids[l] * dim + c];
         }
         hp.slot_face[em * ns + sm] = (int32_t)f;
         hp.hf_minus[em * ns + sm] = 1;
-        for (int l = 0; l < nf; ++l) hp.hf_trace[((size_t)em * ns + sm) * nf + l] = dl[sm][face_sym(dim, tm, p + 1, l)];
+        for (int l = 0; l < nf; ++l) hp.hf_trace[((size_t)em * ns + sm) * nf + l] = dl[sm][face_sym(kind, tm, p, l)];
         if (rec.size() == 1) continue;
         const int64_t ep = rec[1].first;
         const int sp = rec[1].second;
         int tp = -1;
-        for (int t = 0; t < face_sym_count(dim) && tp < 0; ++t) {
+        for (int t = 0; t < face_sym_count(kind) && tp < 0; ++t) {
             bool ok = true;
             for (int l = 0; l < nloc && ok; ++l)
-                ok = hp.elem_nodes[(size_t)ep * Nv + cl[sp][face_sym(dim, t, r + 1, l)]] == ids[l];
+                ok = hp.elem_nodes[(size_t)ep * Nv + cl[sp][face_sym(kind, t, r, l)]] == ids[l];
             if (ok) tp = t;
         }
         if (tp < 0) throw Error(SNSW_E_SHAPE, "unstructured mesh: non-conforming face between elements " +
@@ -171,7 +215,7 @@ void unstructured_topology(HostProblem& hp) {
         hp.slot_face[ep * ns + sp] = (int32_t)f;
         hp.slot_nbr[em * ns + sm] = (int32_t)ep;
         hp.slot_nbr[ep * ns + sp] = (int32_t)em;
-        for (int l = 0; l < nf; ++l) hp.hf_trace[((size_t)ep * ns + sp) * nf + l] = dl[sp][face_sym(dim, tp, p + 1, l)];
+        for (int l = 0; l < nf; ++l) hp.hf_trace[((size_t)ep * ns + sp) * nf + l] = dl[sp][face_sym(kind, tp, p, l)];
         for (int l = 0; l < nf; ++l) {
             hp.hf_up_trace[((size_t)em * ns + sm) * nf + l] = hp.hf_trace[((size_t)ep * ns + sp) * nf + l];
             hp.hf_up_trace[((size_t)ep * ns + sp) * nf + l] = hp.hf_trace[((size_t)em * ns + sm) * nf + l];
@@ -280,9 +324,75 @@ void build_faces(HostProblem& hp) {
     face_geometry(hp);
 }
 
+// Triangular faces (tetrahedra): face map x(s, t) = sum_m X_m psi_m(s, t)
+// over the P_r triangle basis of the face's control points, N = x_s x x_t
+// (outward for the minus element by the slot's vertex order); B_k and int N
+// with the collapsed Gauss rule of p + r points per direction (exact: N has
+// degree 2(r-1), the traces' products 2p); the composite rule of 4 x 4
+// sub-triangles for the classification of sign changes.
+void face_geometry_tri(HostProblem& hp) {
+    const int r = hp.r, p = hp.p, nf = hp.nf;
+    const int nfc = (r + 1) * (r + 2) / 2;
+    const TriBasis geo(tri_geometry_nodes(r), r), dg(tri_dg_nodes(p), p);
+    std::vector<double> xs, ys, ws;
+    tri_collapsed_rule(p + r, xs, ys, ws);
+    const size_t Q = ws.size();
+    std::vector<double> Gs(Q * nfc), Gt(Q * nfc), Ph(Q * nf);
+    for (size_t q = 0; q < Q; ++q) {
+        geo.eval(xs[q], ys[q], nullptr, &Gs[q * nfc], &Gt[q * nfc]);
+        dg.eval(xs[q], ys[q], &Ph[q * nf], nullptr, nullptr);
+    }
+    FaceNormalData& nd = hp.fnd;
+    nd = FaceNormalData();
+    nd.nfc = nfc;
+    std::vector<double> cs, ct;
+    tri_composite_rule(kSub3, p + r, cs, ct, nd.cw);
+    const size_t Qc = nd.cw.size();
+    nd.tgs.resize(Qc * nfc);
+    nd.tgt.resize(Qc * nfc);
+    nd.cphi.resize(Qc * nf);
+    for (size_t q = 0; q < Qc; ++q) {
+        geo.eval(cs[q], ct[q], nullptr, &nd.tgs[q * nfc], &nd.tgt[q * nfc]);
+        dg.eval(cs[q], ct[q], &nd.cphi[q * nf], nullptr, nullptr);
+    }
+    nd.Rf.assign(hp.F, 0.0);
+    hp.B.assign((size_t)hp.F * 3 * nf * nf, 0.0);
+    hp.Nint.assign((size_t)hp.F * 3, 0.0);
+    parallel_for(hp.F, hp.nthreads, [&](int64_t f0, int64_t f1) {
+        for (int64_t f = f0; f < f1; ++f) {
+            const double* X = &hp.f_ctrl[(size_t)f * nfc * 3];
+            double* Bf = &hp.B[(size_t)f * 3 * nf * nf];
+            double* Nf = &hp.Nint[(size_t)f * 3];
+            for (size_t q = 0; q < Q; ++q) {
+                double N[3];
+                tri_face_normal(X, nfc, &Gs[q * nfc], &Gt[q * nfc], N);
+                const double* ph = &Ph[q * nf];
+                for (int k = 0; k < 3; ++k) {
+                    Nf[k] += ws[q] * N[k];
+                    for (int i = 0; i < nf; ++i)
+                        for (int j = 0; j < nf; ++j) Bf[(k * nf + i) * nf + j] += ws[q] * N[k] * ph[i] * ph[j];
+                }
+            }
+            double R = 0.0;
+            for (size_t q = 0; q < Qc; ++q) {
+                double N[3];
+                tri_face_normal(X, nfc, &nd.tgs[q * nfc], &nd.tgt[q * nfc], N);
+                // the mean normal is 2 int N (the reference triangle has area 1/2)
+                const double dx = N[0] - 2.0 * Nf[0], dy = N[1] - 2.0 * Nf[1], dz = N[2] - 2.0 * Nf[2];
+                R = std::max(R, std::sqrt(dx * dx + dy * dy + dz * dz));
+            }
+            hp.fnd.Rf[f] = R;
+        }
+    });
+}
+
 // Normal moments B_k, int N_k and the 3D composite-rule tables of every face
 // (from f_axis and f_ctrl).
 void face_geometry(HostProblem& hp) {
+    if (hp.simplex && hp.dim == 3) {
+        face_geometry_tri(hp);
+        return;
+    }
     const int dim = hp.dim, r = hp.r, p = hp.p;
     const int nf = hp.nf;
     const int nloc = dim == 2 ? r + 1 : (r + 1) * (r + 1);
@@ -507,7 +617,32 @@ void romberg_face(const HostProblem& hp, int64_t f, const double* om, double tol
     for (int a = 0; a <= r; ++a) geo[a] = (double)a / r;
     const std::vector<double> dg = gll01(p);
     std::vector<double> out(m);
-    if (dim == 2) {
+    if (dim == 3 && hp.simplex) {
+        // triangular face in collapsed coordinates: (s, t) = (u, v (1 - u)),
+        // area element 1 - u; u outer, v inner
+        const int nfc = (r + 1) * (r + 2) / 2;
+        const double* X = &hp.f_ctrl[(size_t)f * nfc * 3];
+        const TriBasis tg(tri_geometry_nodes(r), r), td(tri_dg_nodes(p), p);
+        auto point = [&](double u, double v, double* w) {
+            double gs[10], gt[10], phi[10], N[3];
+            const double s = u, t = v * (1.0 - u);
+            tg.eval(s, t, nullptr, gs, gt);
+            td.eval(s, t, phi, nullptr, nullptr);
+            tri_face_normal(X, nfc, gs, gt, N);
+            face_components(om[0] * N[0] + om[1] * N[1] + om[2] * N[2], phi, nf, w);
+            for (int c = 0; c < m; ++c) w[c] *= 1.0 - u;
+        };
+        PointFn outer = [&](const double* u, int k, double* v) {
+            for (int q = 0; q < k; ++q) {
+                const double uq = u[q];
+                PointFn inner = [&](const double* vv, int kv, double* w) {
+                    for (int i = 0; i < kv; ++i) point(uq, vv[i], w + (size_t)i * m);
+                };
+                romberg(inner, m, 0.0, 1.0, 0.1 * tol, 0, v + (size_t)q * m);
+            }
+        };
+        romberg(outer, m, 0.0, 1.0, tol, 0, out.data());
+    } else if (dim == 2) {
         const double* mo = &hp.fnd.mono[(size_t)f * 2 * r];
         PointFn fn = [&](const double* s, int k, double* v) {
             double phi[8];
@@ -655,11 +790,46 @@ uint8_t face_integrals(const HostProblem& hp, int64_t f, const double* om, doubl
         maybe_romberg(hp, f, om, mp, mm, Pp, Pm);
         return FC_KINK;
     }
-    // 3D: cheap bound first
+    // 3D: cheap bound first (|Omega . N_mean| above the largest deviation of
+    // N from its mean at the rule's points: no sign change there)
     const double R = nd.Rf[f];
-    if (std::fabs(gbar) > R * (1.0 + 1e-9) + 1e-300) {
+    const double gmean = hp.simplex ? 2.0 * gbar : gbar;
+    if (std::fabs(gmean) > R * (1.0 + 1e-9) + 1e-300) {
         if (gbar > 0.0) { mp = gbar; mm = 0.0; return FC_POS; }
         mp = 0.0; mm = -gbar; return FC_NEG;
+    }
+    if (hp.simplex) {
+        // triangular faces: Omega . N at the points of the composite rule
+        const int nfc = nd.nfc;
+        const double* X = &hp.f_ctrl[(size_t)f * nfc * 3];
+        const size_t Qc = nd.cw.size();
+        std::vector<double> g(Qc);
+        double gmin = 1e300, gmax = -1e300;
+        for (size_t q = 0; q < Qc; ++q) {
+            double N[3];
+            tri_face_normal(X, nfc, &nd.tgs[q * nfc], &nd.tgt[q * nfc], N);
+            g[q] = om[0] * N[0] + om[1] * N[1] + om[2] * N[2];
+            gmin = std::min(gmin, g[q]);
+            gmax = std::max(gmax, g[q]);
+        }
+        if (gmin >= 0.0) { mp = gbar; mm = 0.0; return FC_POS; }
+        if (gmax <= 0.0) { mp = 0.0; mm = -gbar; return FC_NEG; }
+        std::fill(Pp, Pp + nf * nf, 0.0);
+        std::fill(Pm, Pm + nf * nf, 0.0);
+        mp = mm = 0.0;
+        for (size_t q = 0; q < Qc; ++q) {
+            const double wp = nd.cw[q] * std::max(g[q], 0.0), wm = nd.cw[q] * std::max(-g[q], 0.0);
+            mp += wp;
+            mm += wm;
+            const double* ph = &nd.cphi[q * nf];
+            for (int i = 0; i < nf; ++i)
+                for (int j = 0; j < nf; ++j) {
+                    Pp[i * nf + j] += wp * ph[i] * ph[j];
+                    Pm[i * nf + j] += wm * ph[i] * ph[j];
+                }
+        }
+        maybe_romberg(hp, f, om, mp, mm, Pp, Pm);
+        return FC_KINK;
     }
     const double* X = &hp.f_ctrl[(size_t)f * (r + 1) * (r + 1) * 3];
     const int a = hp.f_axis[f];

@@ -12,7 +12,8 @@
 // Triangles (simplicial elements): P_r map at equispaced control points and
 // P_p DG basis (Gauss-Lobatto points on the edges, equispaced inside), on
 // the collapsed Gauss rule with p+r points per direction (exact for total
-// degree 2(p+r)-2, the largest degree of these integrands).
+// degree 2(p+r)-2, the largest degree of these integrands).  Tetrahedra: the
+// same with p + ceil(3r/2) points per direction (exact for 2p + 3r - 3).
 #include <atomic>
 #include <cmath>
 
@@ -65,6 +66,33 @@ int tensor_points_per_axis(const HostProblem& hp) {
 RefTables reference_tables(const HostProblem& hp, int extra) {
     const int dim = hp.dim, r = hp.r, p = hp.p;
     RefTables t;
+    if (hp.simplex && dim == 3) {
+        std::vector<double> x, y, z;
+        tet_collapsed_rule(p + (3 * r + 1) / 2 + extra, x, y, z, t.w);
+        t.Q = (int)t.w.size();
+        const TetBasis geo(tet_geometry_nodes(r), r), dg(tet_dg_nodes(p), p);
+        t.Nv = geo.n;
+        t.Vg.resize((size_t)t.Q * geo.n);
+        t.Gg.resize((size_t)t.Q * geo.n * 3);
+        t.U.resize((size_t)t.Q * dg.n);
+        t.GU.resize((size_t)t.Q * dg.n * 3);
+        std::vector<double> dx(20), dy(20), dz(20);
+        for (int q = 0; q < t.Q; ++q) {
+            geo.eval(x[q], y[q], z[q], &t.Vg[(size_t)q * geo.n], dx.data(), dy.data(), dz.data());
+            for (int m = 0; m < geo.n; ++m) {
+                t.Gg[((size_t)q * geo.n + m) * 3 + 0] = dx[m];
+                t.Gg[((size_t)q * geo.n + m) * 3 + 1] = dy[m];
+                t.Gg[((size_t)q * geo.n + m) * 3 + 2] = dz[m];
+            }
+            dg.eval(x[q], y[q], z[q], &t.U[(size_t)q * dg.n], dx.data(), dy.data(), dz.data());
+            for (int m = 0; m < dg.n; ++m) {
+                t.GU[((size_t)q * dg.n + m) * 3 + 0] = dx[m];
+                t.GU[((size_t)q * dg.n + m) * 3 + 1] = dy[m];
+                t.GU[((size_t)q * dg.n + m) * 3 + 2] = dz[m];
+            }
+        }
+        return t;
+    }
     if (hp.simplex) {
         std::vector<double> x, y;
         tri_collapsed_rule(p + r + extra, x, y, t.w);
@@ -151,7 +179,13 @@ std::vector<double> equispaced(int r) {
 void node_coordinates(const HostProblem& hp, int64_t e0, int64_t count, double* xyz) {
     const int dim = hp.dim, n = hp.n;
     std::vector<double> Vg, Gg;
-    if (hp.simplex) {
+    if (hp.simplex && dim == 3) {
+        const TetBasis geo(tet_geometry_nodes(hp.r), hp.r);
+        const std::vector<double> xn = tet_dg_nodes(hp.p);
+        Vg.resize((size_t)n * geo.n);
+        for (int q = 0; q < n; ++q)
+            geo.eval(xn[3 * q], xn[3 * q + 1], xn[3 * q + 2], &Vg[(size_t)q * geo.n], nullptr, nullptr, nullptr);
+    } else if (hp.simplex) {
         const TriBasis geo(tri_geometry_nodes(hp.r), hp.r);
         const std::vector<double> xn = tri_dg_nodes(hp.p);
         Vg.resize((size_t)n * geo.n);
@@ -176,6 +210,10 @@ int volume_rule(const HostProblem& hp, int extra, int64_t e0, int64_t count, dou
                 double* basis) {
     const int dim = hp.dim;
     if (!x) {
+        if (hp.simplex && dim == 3) {
+            const int nq = hp.p + (3 * hp.r + 1) / 2 + extra;
+            return nq * nq * nq;
+        }
         if (hp.simplex) return (hp.p + hp.r + extra) * (hp.p + hp.r + extra);
         int Q = 1;
         for (int a = 0; a < dim; ++a) Q *= tensor_points_per_axis(hp) + extra;

@@ -1,6 +1,7 @@
 // Internal host-side structures of the snsweep library (not part of the ABI).
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <functional>
 #include <stdexcept>
@@ -58,6 +59,35 @@ struct TriBasis {
 // weight w_u w_v (1 - u)), exact for total degree 2 nq - 2.
 void tri_collapsed_rule(int nq, std::vector<double>& x, std::vector<double>& y, std::vector<double>& w);
 
+// Tetrahedra: reference tetrahedron with vertices V0 = (0,0,0), V1 = (1,0,0),
+// V2 = (0,1,0), V3 = (0,0,1); nodes of order k on the lattice triples
+// (i, j, l), i + j + l <= k, numbered with l slowest, then j, then i.
+int tet_index(int k, int i, int j, int l);
+// Element nodes of face slot s (the face opposite V_s, its vertices in the
+// outward order (V1,V2,V3), (V0,V3,V2), (V0,V1,V3), (V0,V2,V1)), in the
+// face's triangle lattice order: face node (a, b) has barycentric
+// coordinates k - a - b, a, b on the face's vertices.
+std::vector<int32_t> tet_slot_nodes(int k, int s);
+// Node positions [n][3]: control points at (i, j, l) / r; DG nodes at the
+// Gauss-Lobatto points of the edges on the edges, equispaced elsewhere.
+std::vector<double> tet_geometry_nodes(int r);
+std::vector<double> tet_dg_nodes(int p);
+// Nodal P_k basis of the given nodes on the tetrahedron.
+struct TetBasis {
+    int k = 0, n = 0;
+    std::vector<std::array<int, 3>> mono;    // exponents of x^a y^b z^c
+    std::vector<double> C;                   // [monomial][basis function]
+    TetBasis(const std::vector<double>& nodes, int k);
+    void eval(double x, double y, double z, double* val, double* dx, double* dy, double* dz) const;
+};
+// Collapsed Gauss rule on the tetrahedron, nq^3 points, exact for total
+// degree 2 nq - 3.
+void tet_collapsed_rule(int nq, std::vector<double>& x, std::vector<double>& y, std::vector<double>& z,
+                        std::vector<double>& w);
+// The reference triangle cut into K^2 congruent sub-triangles with the
+// collapsed Gauss rule (nq per direction) on each.
+void tri_composite_rule(int K, int nq, std::vector<double>& s, std::vector<double>& t, std::vector<double>& w);
+
 // ------------------------------------------------------------ quadrature.cpp
 // Level-symmetric S_N set: omega [D][3], w [D] (2D: z > 0 half, doubled).
 void level_symmetric(int N, int dim, std::vector<double>& omega, std::vector<double>& w);
@@ -89,7 +119,9 @@ struct FaceNormalData {
     std::vector<double> gV1, gD1;    // geometry 1D tables at the abscissae
     std::vector<int> ci, cj;         // abscissa index of each point
     int nc1 = 0;
-    std::vector<double> Rf;          // 3D: max |N_q - int N| over the points
+    std::vector<double> Rf;          // 3D: max |N_q - mean N| over the points
+    std::vector<double> tgs, tgt;    // triangular faces: map basis derivatives at the points [Qc][nfc]
+    int nfc = 0;                     // triangular faces: control points per face
 };
 
 struct HostProblem {

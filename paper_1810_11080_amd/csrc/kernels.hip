@@ -109,11 +109,59 @@ struct TriShape {
     }
 };
 
-// Element shapes: Shape<DIM, P> is the Q_P tensor element, and for
-// P >= kTri the triangle of order P - kTri (2D).
+// Tetrahedron of order P: nodes on the lattice triples (i, j, l),
+// i + j + l <= P, numbered with l slowest, then j; barycentric lattice
+// coordinates c = (P - i - j - l, i, j, l).  Slot s is the face opposite
+// vertex s, its nodes listed in the face's triangle lattice order over the
+// face's vertices in the outward order (1,2,3), (0,3,2), (0,1,3), (0,2,1).
+template <int P>
+struct TetShape {
+    static constexpr int N = (P + 1) * (P + 2) * (P + 3) / 6;
+    static constexpr int NF = (P + 1) * (P + 2) / 2;
+    static constexpr int NS = 4;
+    static constexpr int G = 64 / N;
+    __host__ __device__ static constexpr int face_vertex(int s, int v) {
+        return s == 0 ? v + 1 : (s == 1 ? (v == 0 ? 0 : 4 - v) : (s == 2 ? (v == 0 ? 0 : (v == 1 ? 1 : 3)) : (v == 0 ? 0 : 3 - v)));
+    }
+    __host__ __device__ static constexpr int index(int i, int j, int l) {
+        int m = 0;
+        for (int ll = 0; ll < l; ++ll) m += (P + 1 - ll) * (P + 2 - ll) / 2;
+        return m + j * (P - l + 1) - j * (j - 1) / 2 + i;
+    }
+    // barycentric lattice coordinate v of node m
+    __host__ __device__ static constexpr int bary(int m, int v) {
+        int l = 0;
+        while (l < P && m >= index(0, 0, l + 1)) ++l;
+        int r = m - index(0, 0, l), j = 0;
+        while (r > P - l - j) r -= P - l - j + 1, ++j;
+        const int i = r;
+        return v == 0 ? P - i - j - l : (v == 1 ? i : (v == 2 ? j : l));
+    }
+    __host__ __device__ static constexpr int tn(int s, int b) {
+        int bb = 0, r = b;
+        while (r > P - bb) r -= P - bb + 1, ++bb;   // face node (a, bb)
+        const int a = r;
+        int c[4] = {0, 0, 0, 0};
+        c[face_vertex(s, 0)] = P - a - bb;
+        c[face_vertex(s, 1)] = a;
+        c[face_vertex(s, 2)] = bb;
+        return index(c[1], c[2], c[3]);
+    }
+    __host__ __device__ static constexpr bool on(int m, int s) { return bary(m, s) == 0; }
+    __host__ __device__ static constexpr int local(int m, int s) {
+        const int a = bary(m, face_vertex(s, 1)), bb = bary(m, face_vertex(s, 2));
+        return bb * (P + 1) - bb * (bb - 1) / 2 + a;
+    }
+};
+
+// Element shapes: Shape<DIM, P> is the Q_P tensor element; for P >= kTri
+// the triangle of order P - kTri (2D) and for P >= kTet the tetrahedron of
+// order P - kTet (3D).
 constexpr int kTri = 16;
+constexpr int kTet = 32;
 template <int DIM, int P>
-using Shape = std::conditional_t<(P >= kTri), TriShape<P - kTri>, TensorShape<DIM, P>>;
+using Shape = std::conditional_t<(P >= kTet), TetShape<P - kTet>,
+                                 std::conditional_t<(P >= kTri), TriShape<P - kTri>, TensorShape<DIM, P>>>;
 
 template <int P>
 constexpr bool tri_tables_ok() {
@@ -129,6 +177,22 @@ constexpr bool tri_tables_ok() {
     return true;
 }
 static_assert(tri_tables_ok<1>() && tri_tables_ok<2>() && tri_tables_ok<3>(), "triangle slot tables");
+
+template <int P>
+constexpr bool tet_tables_ok() {
+    using S = TetShape<P>;
+    for (int s = 0; s < S::NS; ++s) {
+        int on_count = 0;
+        for (int m = 0; m < S::N; ++m) on_count += S::on(m, s) ? 1 : 0;
+        if (on_count != S::NF) return false;
+        for (int b = 0; b < S::NF; ++b) {
+            const int m = S::tn(s, b);
+            if (m < 0 || m >= S::N || !S::on(m, s) || S::local(m, s) != b) return false;
+        }
+    }
+    return true;
+}
+static_assert(tet_tables_ok<1>() && tet_tables_ok<2>() && tet_tables_ok<3>(), "tetrahedron slot tables");
 
 // Layout of one pair's cached A^{-1} block.  Column-major (entry (i, j) at
 // j n + i), except for 3D p = 2 (n = 27): there columns 2c and 2c + 1 are
@@ -181,7 +245,8 @@ constexpr bool inv_layout_ok() {
 }
 static_assert(inv_layout_ok<2, 1>() && inv_layout_ok<2, 2>() && inv_layout_ok<2, 3>() && inv_layout_ok<3, 1>() &&
                   inv_layout_ok<3, 2>() && inv_layout_ok<3, 3>() && inv_layout_ok<2, kTri + 1>() &&
-                  inv_layout_ok<2, kTri + 2>() && inv_layout_ok<2, kTri + 3>(),
+                  inv_layout_ok<2, kTri + 2>() && inv_layout_ok<2, kTri + 3>() && inv_layout_ok<3, kTet + 1>() &&
+                  inv_layout_ok<3, kTet + 2>() && inv_layout_ok<3, kTet + 3>(),
               "A^{-1} block layouts");
 
 // Table entry and problem index read through the constant address space, so
@@ -2191,7 +2256,11 @@ void launch_sweep_level(int dim, int p, bool simplex, bool mixed, bool inv, bool
                         const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem,
                         hipStream_t stream) {
     const bool u = unstructured;
-    if (simplex) {
+    if (simplex && dim == 3) {
+        if (p == 1) launch_tpl_u<3, kTet + 1, true>(table, pairs, begin, count, problem, mixed, inv, stream);
+        else if (p == 2) launch_tpl_u<3, kTet + 2, true>(table, pairs, begin, count, problem, mixed, inv, stream);
+        else launch_tpl_u<3, kTet + 3, true>(table, pairs, begin, count, problem, mixed, inv, stream);
+    } else if (simplex) {
         // triangles come as element lists: always the table of upwind nodes
         if (p == 1) launch_tpl_u<2, kTri + 1, true>(table, pairs, begin, count, problem, mixed, inv, stream);
         else if (p == 2) launch_tpl_u<2, kTri + 2, true>(table, pairs, begin, count, problem, mixed, inv, stream);
@@ -2214,6 +2283,9 @@ int64_t inv_bytes_tpl(bool f32) {
 }
 
 int64_t ainv_block_bytes(int dim, int p, bool simplex, bool f32) {
+    if (simplex && dim == 3)
+        return p == 1 ? inv_bytes_tpl<3, kTet + 1>(f32) : p == 2 ? inv_bytes_tpl<3, kTet + 2>(f32)
+                                                                 : inv_bytes_tpl<3, kTet + 3>(f32);
     if (simplex)
         return p == 1 ? inv_bytes_tpl<2, kTri + 1>(f32) : p == 2 ? inv_bytes_tpl<2, kTri + 2>(f32)
                                                                  : inv_bytes_tpl<2, kTri + 3>(f32);
@@ -2225,7 +2297,11 @@ int64_t ainv_block_bytes(int dim, int p, bool simplex, bool f32) {
 void launch_factor(int dim, int p, bool simplex, bool f32, bool unstructured, const SweepArgs* table,
                    const int4* pairs, int64_t count, void* ainv, hipStream_t stream) {
     const bool u = unstructured;
-    if (simplex) {
+    if (simplex && dim == 3) {
+        if (p == 1) launch_factor_tpl<3, kTet + 1>(table, pairs, count, ainv, f32, true, stream);
+        else if (p == 2) launch_factor_tpl<3, kTet + 2>(table, pairs, count, ainv, f32, true, stream);
+        else launch_factor_tpl<3, kTet + 3>(table, pairs, count, ainv, f32, true, stream);
+    } else if (simplex) {
         if (p == 1) launch_factor_tpl<2, kTri + 1>(table, pairs, count, ainv, f32, true, stream);
         else if (p == 2) launch_factor_tpl<2, kTri + 2>(table, pairs, count, ainv, f32, true, stream);
         else launch_factor_tpl<2, kTri + 3>(table, pairs, count, ainv, f32, true, stream);
@@ -2255,7 +2331,11 @@ void launch_fill_sentinel(const SweepArgs* table, int count, int64_t max_DEn, hi
 
 void launch_sweep_persistent(int dim, int p, bool simplex, bool unstructured, bool inv, const PersistArgs& a,
                              int blocks, hipStream_t stream) {
-    if (simplex) {
+    if (simplex && dim == 3) {
+        if (p == 1) launch_persist_u<3, kTet + 1>(a, blocks, inv, stream);
+        else if (p == 2) launch_persist_u<3, kTet + 2>(a, blocks, inv, stream);
+        else launch_persist_u<3, kTet + 3>(a, blocks, inv, stream);
+    } else if (simplex) {
         if (p == 1) launch_persist_u<2, kTri + 1>(a, blocks, inv, stream);
         else if (p == 2) launch_persist_u<2, kTri + 2>(a, blocks, inv, stream);
         else launch_persist_u<2, kTri + 3>(a, blocks, inv, stream);
@@ -2281,6 +2361,9 @@ void launch_sweep_persistent(int dim, int p, bool simplex, bool unstructured, bo
 }
 
 int persistent_blocks_per_cu(int dim, int p, bool simplex, bool unstructured, bool inv) {
+    if (simplex && dim == 3)
+        return p == 1 ? occupancy_u<3, kTet + 1>(inv) : p == 2 ? occupancy_u<3, kTet + 2>(inv)
+                                                             : occupancy_u<3, kTet + 3>(inv);
     if (simplex)
         return p == 1 ? occupancy_u<2, kTri + 1>(inv) : p == 2 ? occupancy_u<2, kTri + 2>(inv)
                                                              : occupancy_u<2, kTri + 3>(inv);

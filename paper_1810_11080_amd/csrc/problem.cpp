@@ -143,16 +143,19 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
         hp.face_tol = desc->face_tol > 0.0 ? desc->face_tol : 1e-10;
         if (hp.simplex && !desc->elem_nodes)
             throw Error(SNSW_E_INVALID_ARG, "simplicial elements need an element list (elem_nodes)");
-        if (hp.simplex && hp.dim != 2) throw Error(SNSW_E_UNSUPPORTED, "simplicial elements: triangles (dim 2) only");
         hp.n = 1;
         hp.nf = 1;
         hp.nv = 1;
         for (int a = 0; a < hp.dim; ++a) hp.n *= hp.p + 1;
         for (int a = 0; a + 1 < hp.dim; ++a) hp.nf *= hp.p + 1;
         for (int a = 0; a < hp.dim; ++a) hp.nv *= hp.r + 1;
-        if (hp.simplex) {
+        if (hp.simplex && hp.dim == 2) {
             hp.n = (hp.p + 1) * (hp.p + 2) / 2;
             hp.nv = (hp.r + 1) * (hp.r + 2) / 2;
+        } else if (hp.simplex) {
+            hp.n = (hp.p + 1) * (hp.p + 2) * (hp.p + 3) / 6;
+            hp.nf = (hp.p + 1) * (hp.p + 2) / 2;
+            hp.nv = (hp.r + 1) * (hp.r + 2) * (hp.r + 3) / 6;
         }
         hp.nthreads = desc->n_threads > 0 ? desc->n_threads
                                           : (int)std::max(1u, std::thread::hardware_concurrency());

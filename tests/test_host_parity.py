@@ -36,6 +36,11 @@ CASES = {
     "t_square_q1p1": lambda: W.tri_square(n=8, r=1, p=1, sn_order=8),
     "t_annulus": lambda: W.tri_annulus(nr=3, nt=16, r=3, p=2, sn_order=4),
     "t_annulus_p3": lambda: W.tri_annulus(nr=2, nt=12, r=2, p=3, sn_order=8),
+    # curved tetrahedra (renumbered, vertex orders permuted at random): a
+    # warped cube cut into Kuhn tetrahedra, a closed cylindrical shell
+    "k_cube": lambda: W.tet_cube(n=3, r=2, p=2, sn_order=4),
+    "k_cube_p3": lambda: W.tet_cube(n=2, r=1, p=3, sn_order=2),
+    "k_shell": lambda: W.tet_shell(nr=2, nt=8, nz=2, r=2, p=1, sn_order=4),
 }
 
 
@@ -164,6 +169,21 @@ def test_triangle_node_coordinates_and_volume_rule(ctx, r, p):
     assert rel_err(basis, g.U) < 1e-13
 
 
+@pytest.mark.parametrize("r,p", [(2, 2), (1, 3), (3, 1)])
+def test_tet_node_coordinates_and_volume_rule(ctx, r, p):
+    """The same on curved tetrahedra (collapsed Gauss rule)."""
+    from oracle.simplex import TetGeometry
+    from paper_1810_11080_amd import Problem
+    wp = W.tet_shell(nr=1, nt=6, nz=1, r=r, p=p, sn_order=2)
+    P = Problem.from_workload(ctx, wp)
+    g = TetGeometry(wp.nodes[wp.elem_nodes], r, p, extra_points=2)
+    assert rel_err(P.node_coordinates(), g.dg_node_positions()) < 1e-14
+    x, wd, basis = P.volume_rule(extra=2)
+    assert rel_err(x, g.x) < 1e-14
+    assert rel_err(wd, g.wq[None, :] * g.detJ) < 1e-13
+    assert rel_err(basis, g.U) < 1e-12
+
+
 def test_set_source_validation(ctx):
     from paper_1810_11080_amd import Problem
     from paper_1810_11080_amd.binding import SnswError
@@ -202,19 +222,18 @@ def test_unstructured_input_errors(ctx):
     # element lists sweep on the level schedule unless the persistent one is asked for
     assert Problem.from_workload(ctx, wp).info()["schedule"] == 2
     assert Problem.from_workload(ctx, wp, schedule=1).info()["schedule"] == 1
-    # triangles: only as element lists, only in 2D, with (r+1)(r+2)/2 control
-    # points per element
+    # simplices: only as element lists, with (r+1)(r+2)/2 control points per
+    # triangle
     tw = W.tri_square(n=2, r=2, p=1, sn_order=2)
     E = tw.n_elements
     with pytest.raises(SnswError) as ei:
         Problem(ctx, dim=2, nx=(E, 1), geom_order=2, dg_order=1, lattice=np.zeros(((2 * E + 1) * 3, 2)), sn_order=2,
                 sigma_t=tw.sigma_t, sigma_s=tw.sigma_s, q=tw.q, element=1)
     assert ei.value.code == -1
-    with pytest.raises(SnswError) as ei:
+    with pytest.raises(ValueError):   # 3D simplices need (r+1)(r+2)(r+3)/6 control points
         Problem(ctx, dim=3, nx=(E, 1, 1), geom_order=2, dg_order=1, lattice=None, sn_order=2,
                 sigma_t=tw.sigma_t, sigma_s=tw.sigma_s, q=tw.q, nodes=np.zeros((len(tw.nodes), 3)),
                 elem_nodes=tw.elem_nodes, element=1)
-    assert ei.value.code == -9
     with pytest.raises(ValueError):
         Problem(ctx, dim=2, nx=(E, 1), geom_order=2, dg_order=1, lattice=None, sn_order=2,
                 sigma_t=tw.sigma_t, sigma_s=tw.sigma_s, q=tw.q, nodes=tw.nodes,
