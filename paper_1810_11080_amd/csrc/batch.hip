@@ -337,7 +337,7 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
         for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
             const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
             launch_sweep_level(c.dim, c.p, c.simplex, c.mixed, c.inv, c.unstructured, L.table, c.pairs, b, n,
-                                   class_problem(c), s);
+                                   class_problem(c), s, c.face_points);
         }
     }
     HIP_OK(hipGetLastError());
@@ -394,12 +394,14 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
                 bc.levels_only = bc.cls.mixed || hp.unstructured;
                 bc.cls.unstructured = hp.unstructured;
                 bc.cls.simplex = hp.simplex;
+                bc.cls.face_points = true;
                 bc.has_inv = has_inv != 0;
                 bc.cls.ticket = (int)b->classes.size();
                 b->classes.push_back(bc);
             }
             b->entry_class[k] = it->second;
             b->classes[it->second].cls.members.push_back(k);
+            b->classes[it->second].cls.face_points &= probs[k]->dev->Nq != nullptr;
             b->max_En = std::max<int64_t>(b->max_En, hp.E * hp.n);
             b->max_DEn = std::max<int64_t>(b->max_DEn, hp.D * hp.E * hp.n);
         }

@@ -41,7 +41,8 @@ struct SweepClass {
     bool persistent = false;
     bool inv = false;                  // cached inverses (every member has them)
     bool unstructured = false;         // members are unstructured meshes (upwind nodes from a table)
-    bool simplex = false;              // members are triangle meshes
+    bool simplex = false;              // members are simplex meshes
+    bool face_points = false;          // every member carries face Gauss-point normals (DeviceProblem::Nq)
     int blocks = 0;                    // persistent grid
     int ticket = 0;                    // index into the ticket array
     const int4* pairs = nullptr;       // device schedule
@@ -71,6 +72,7 @@ struct DeviceProblem {
     double* geo = nullptr;        // [E][dim+1][n][n] column-major matrices
     double* B = nullptr;          // [F][dim][nf][nf]
     double* Bsym = nullptr;       // 3D: [F][bsym_face_stride(nf)] packed upper triangles of B
+    double* Nq = nullptr;         // 3D p = 2 lattices (r = 2): [F][16][3] w_q N(q) at the face Gauss points
     int32_t* nbr_nodes = nullptr; // unstructured meshes: [E][nslot][nf] neighbour node of each slot node
     double* kink_tab = nullptr;   // [K][2][nf][nf]
     int32_t* kink_idx = nullptr;

@@ -413,6 +413,9 @@ void face_geometry(HostProblem& hp) {
     FaceNormalData& nd = hp.fnd;
     nd = FaceNormalData();
     if (dim == 2) nd.mono.assign((size_t)hp.F * 2 * r, 0.0);
+    // 3D: w_q N(q) at the moments' Gauss points (the level sweeps of p = 2
+    // lattices contract the inflow through them)
+    hp.Nq.assign(dim == 3 ? (size_t)hp.F * nq1 * nq1 * 3 : 0, 0.0);
     // 3D composite rule tables
     if (dim == 3) {
         std::vector<double> xs, ws;
@@ -499,6 +502,8 @@ void face_geometry(HostProblem& hp) {
                         double N[3];
                         normal_at(&gV[qs * (r + 1)], &gD[qs * (r + 1)], &gV[qt * (r + 1)], &gD[qt * (r + 1)], N);
                         const double wq = w1[qs] * w1[qt];
+                        double* wn = &hp.Nq[(((size_t)f * nq1 + qt) * nq1 + qs) * 3];
+                        for (int k = 0; k < 3; ++k) wn[k] = wq * N[k];
                         for (int bt = 0; bt <= p; ++bt)
                             for (int bs = 0; bs <= p; ++bs)
                                 phi[bt * (p + 1) + bs] = uV[qs * (p + 1) + bs] * uV[qt * (p + 1) + bt];

@@ -152,6 +152,7 @@ struct HostProblem {
     std::vector<double> f_ctrl;               // [F][(r+1)^(dim-1)][dim]
     std::vector<double> B;                    // [F][dim][nf][nf] int N_k phi_a phi_b
     std::vector<double> Nint;                 // [F][dim] int N_k
+    std::vector<double> Nq;                   // 3D tensor faces: [F][nq][nq][3] w_q N(q) at the Gauss points of B
     FaceNormalData fnd;
     std::vector<int32_t> slot_face, slot_nbr; // [E][nslot]
     std::vector<int32_t> slot_nodes;          // [nslot][nf]

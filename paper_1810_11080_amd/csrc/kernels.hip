@@ -287,6 +287,7 @@ __device__ __forceinline__ SweepArgs load_args(const SweepArgs* table, int k) {
     a.ainv = c->ainv;
     a.Bsym = c->Bsym;
     a.rhs_dir = c->rhs_dir;
+    a.Nq = c->Nq;
     a.nbr_nodes = c->nbr_nodes;
     a.ainv32 = c->ainv32;
     return a;
@@ -1550,9 +1551,125 @@ __device__ __forceinline__ double inflow_rhs_staged(const SweepArgs& args, int4 
     return rhs;
 }
 
+// Inflow of one pair through the face normals at Gauss points (3D lattices,
+// p = 2, faces with 4 x 4 Gauss points: SweepArgs::Nq).  The inflow block of
+// an inflow slot applied to the upwind trace u is
+//   (P_in u)_i = -sgn sum_q phi_i(q) (Omega . w_q N(q)) u(q),  u(q) = sum_b phi_b(q) u_b,
+// the same sums as the moments B_a = sum_q w_q N_a(q) phi_i(q) phi_j(q) (the
+// rule is exact for them) in another order, reading 48 doubles per face
+// instead of 135 packed moments.  Traces staged in LDS as in
+// inflow_rhs_staged; lanes 0..15 of a pair form the point values
+// t_q = (Omega . w_q N(q)) u(q) of each inflow face in cf[s][q], then every
+// row sums phi_l(q) t_q over the faces it lies on.  phi at the points is the
+// product of the 1D Lagrange polynomials of the Gauss-Lobatto nodes
+// {0, 1/2, 1} at the 4 Gauss points.
+__device__ __forceinline__ void lagrange3(double x, double* l) {
+    l[0] = 2.0 * (x - 0.5) * (x - 1.0);
+    l[1] = -4.0 * x * (x - 1.0);
+    l[2] = 2.0 * x * (x - 0.5);
+}
+// the i-th of them at x (i in 0..2, not known at compile time)
+__device__ __forceinline__ double lagrange3_at(int i, double x) {
+    return i == 0 ? 2.0 * (x - 0.5) * (x - 1.0) : (i == 1 ? -4.0 * x * (x - 1.0) : 2.0 * x * (x - 0.5));
+}
+// The k-th point of the 4-point Gauss-Legendre rule on [0, 1], ascending
+// (1/2 -+ x/2 with x^2 = 3/7 +- (2/7) sqrt(6/5)); a select, not a table, so
+// that a runtime k costs no memory access.
+__device__ __forceinline__ double gauss4(int k) {
+    constexpr double a = 0.86113631159405257522, b = 0.33998104358485626480;
+    return k == 0 ? 0.5 - 0.5 * a : (k == 1 ? 0.5 - 0.5 * b : (k == 2 ? 0.5 + 0.5 * b : 0.5 + 0.5 * a));
+}
+
+template <int DIM, int P>
+__device__ __forceinline__ double inflow_rhs_quad(const SweepArgs& args, int4 pr, int row, bool in_group,
+                                                 double (*cf)[DIM * Shape<DIM, P>::NF],
+                                                 double (*uf)[Shape<DIM, P>::NF]) {
+    using S = Shape<DIM, P>;
+    constexpr int NF = S::NF, NS = S::NS;
+    static_assert(DIM == 3 && P == 2 && NF == 9, "3D p = 2 lattices");
+    const int e = pr.x;
+    const unsigned packed = (unsigned)pr.y;
+    const int d = (int)(packed & kDirMask);
+    const int a = row / NF, la = row - a * NF;
+    const bool worker = in_group && a < DIM;
+    const double o0 = args.omega[3 * d], o1 = args.omega[3 * d + 1], o2 = args.omega[3 * d + 2];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+        const bool lagged = (packed >> (kSlotShift + 3 * s + 2)) & 1u;
+        if (cls == kOut || cls == kNone || !worker) continue;
+        if (a == 0) {
+            const int nb = args.slot_nbr[(size_t)e * NS + s];
+            const double* up = (lagged ? args.psi_prev : args.psi_cur) + ((size_t)d * args.E + (nb >= 0 ? nb : 0)) * S::N;
+            uf[s][la] = nb >= 0 ? up[S::tn(s ^ 1, la)] : args.psi_inc;
+        }
+    }
+    wave_sync();
+    // point values t_q (lanes row < 16) and kink contractions (lanes a == 0)
+    const int q0 = row & 3, q1 = (row >> 2) & 3;
+    int kc = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+        int kr = 0;
+        if (cls == kKink) kr = args.kink_idx[pr.z + kc++];
+        if (cls == kOut || cls == kNone || !worker) continue;
+        if (cls == kKink) {
+            if (a == 0) {
+                const double* Ti = args.kink_tab + (size_t)kr * 2 * NF * NF + ((s & 1) ? NF * NF : 0) + la * NF;
+                double t = 0.0;
+#pragma unroll
+                for (int b = 0; b < NF; ++b) t += Ti[b] * uf[s][b];
+                cf[s][la] = t;
+            }
+        } else if (row < 16) {
+            // phi_b at this lane's point (recomputed per face: fewer live registers)
+            double lq0[3], lq1[3];
+            lagrange3(gauss4(q0), lq0);
+            lagrange3(gauss4(q1), lq1);
+            double u = 0.0;
+#pragma unroll
+            for (int b1 = 0; b1 < 3; ++b1) {
+                double v = 0.0;
+#pragma unroll
+                for (int b0 = 0; b0 < 3; ++b0) v += lq0[b0] * uf[s][b1 * 3 + b0];
+                u += lq1[b1] * v;
+            }
+            const double* wn = args.Nq + ((size_t)args.slot_face[(size_t)e * NS + s] * 16 + row) * 3;
+            cf[s][row] = (o0 * wn[0] + o1 * wn[1] + o2 * wn[2]) * u;
+        }
+    }
+    wave_sync();
+    double rhs = in_group ? source_row(args, e, d, row, S::N) : 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const unsigned cls = (packed >> (kSlotShift + 3 * s)) & 3u;
+        if (cls == kOut || cls == kNone) continue;
+        if (!S::on(row, s)) continue;
+        const int l = S::local(row, s);
+        if (cls == kKink) {
+            rhs += cf[s][l];
+            continue;
+        }
+        const int i0 = l % 3, i1 = l / 3;
+        double e0[4], c = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e0[j] = lagrange3_at(i0, gauss4(j));
+#pragma unroll
+        for (int j1 = 0; j1 < 4; ++j1) {
+            double v = 0.0;
+#pragma unroll
+            for (int j0 = 0; j0 < 4; ++j0) v += e0[j0] * cf[s][j1 * 4 + j0];
+            c += lagrange3_at(i1, gauss4(j1)) * v;
+        }
+        rhs += (s & 1) ? -c : c;   // P_in = -(outward normal) moments
+    }
+    return rhs;
+}
+
 // One launch per level with cached inverses: b assembled per row, shared
 // through the wavefront's LDS, x = A^{-1} b.
-template <int DIM, int P, bool U = false, bool F32 = false>
+template <int DIM, int P, bool U = false, bool F32 = false, bool QUAD = false>
 __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* table, const int4* pairs,
                                                               int64_t begin, int64_t count, int problem) {
     using S = Shape<DIM, P>;
@@ -1579,7 +1696,10 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* 
     const double* Ab = F32 ? nullptr : args.ainv + ((size_t)d * args.E + e) * IL::kStride;
     auto rhs_of = [&]() {
         const int g = in_group ? grp : 0;
-        if constexpr (kStage) return inflow_rhs_staged<DIM, P, U>(args, prs, row, in_group, cfl[wave][g], ufl[wave][g]);
+        if constexpr (QUAD) {
+            static_assert(kStage && !U && DIM == 3 && P == 2, "face points: 3D p = 2 lattices");
+            return inflow_rhs_quad<DIM, P>(args, prs, row, in_group, cfl[wave][g], ufl[wave][g]);
+        } else if constexpr (kStage) return inflow_rhs_staged<DIM, P, U>(args, prs, row, in_group, cfl[wave][g], ufl[wave][g]);
         else if constexpr (kCoop) return inflow_rhs_coop<DIM, P, U>(args, prs, row, in_group, cfl[wave][g]);
         else return inflow_rhs<DIM, P, false, U>(args, prs, row);
     };
@@ -2031,15 +2151,28 @@ __global__ void fill_sentinel_kernel(const SweepArgs* table) {
 
 template <int DIM, int P, bool U>
 void launch_tpl_u(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem, bool mixed,
-                  bool inv, hipStream_t stream) {
+                  bool inv, hipStream_t stream, bool quad = false) {
     constexpr int per_block = kWaves * Shape<DIM, P>::G;
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
+    const dim3 grid((unsigned)blocks), block(64 * kWaves);
+    if constexpr (DIM == 3 && P == 2 && !U) {
+        // lattices with face Gauss-point normals: inflow contracted through them
+        if (inv && quad) {
+            if (mixed)
+                hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, true, true>), grid, block, 0, stream, table, pairs,
+                                   begin, count, problem);
+            else
+                hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, false, true>), grid, block, 0, stream, table, pairs,
+                                   begin, count, problem);
+            return;
+        }
+    }
     if (inv && mixed) {
         // mixed precision with cached inverses: the FP32 copy
         if constexpr (Shape<DIM, P>::N <= kMaxInv32)
-            hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
-                               stream, table, pairs, begin, count, problem);
+            hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, true>), grid, block, 0, stream, table, pairs, begin, count,
+                               problem);
     } else if (inv)
         hipLaunchKernelGGL((sweep_level_inv<DIM, P, U>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, table,
                            pairs, begin, count, problem);
@@ -2055,9 +2188,9 @@ void launch_tpl_u(const SweepArgs* table, const int4* pairs, int64_t begin, int6
 // kernels of lattice meshes compute them)
 template <int DIM, int P>
 void launch_tpl(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem, bool mixed,
-                bool inv, bool unstructured, hipStream_t stream) {
+                bool inv, bool unstructured, hipStream_t stream, bool quad = false) {
     if (unstructured) launch_tpl_u<DIM, P, true>(table, pairs, begin, count, problem, mixed, inv, stream);
-    else launch_tpl_u<DIM, P, false>(table, pairs, begin, count, problem, mixed, inv, stream);
+    else launch_tpl_u<DIM, P, false>(table, pairs, begin, count, problem, mixed, inv, stream, quad);
 }
 
 // groups of 4 or 16 lanes exchange values by DPP, the others through LDS
@@ -2254,7 +2387,7 @@ __global__ void residual_kernel(int64_t len, const double* __restrict__ a, const
 
 void launch_sweep_level(int dim, int p, bool simplex, bool mixed, bool inv, bool unstructured,
                         const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem,
-                        hipStream_t stream) {
+                        hipStream_t stream, bool face_points) {
     const bool u = unstructured;
     if (simplex && dim == 3) {
         if (p == 1) launch_tpl_u<3, kTet + 1, true>(table, pairs, begin, count, problem, mixed, inv, stream);
@@ -2271,7 +2404,7 @@ void launch_sweep_level(int dim, int p, bool simplex, bool mixed, bool inv, bool
         else launch_tpl<2, 3>(table, pairs, begin, count, problem, mixed, inv, u, stream);
     } else {
         if (p == 1) launch_tpl<3, 1>(table, pairs, begin, count, problem, mixed, inv, u, stream);
-        else if (p == 2) launch_tpl<3, 2>(table, pairs, begin, count, problem, mixed, inv, u, stream);
+        else if (p == 2) launch_tpl<3, 2>(table, pairs, begin, count, problem, mixed, inv, u, stream, face_points);
         else launch_tpl<3, 3>(table, pairs, begin, count, problem, mixed, inv, u, stream);
     }
 }

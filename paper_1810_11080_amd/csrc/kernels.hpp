@@ -41,6 +41,8 @@ struct SweepArgs {
                               // the opposite slot's node of the same local index
     const float* ainv32;      // mixed precision: [D][E] blocks of A^{-1} rounded to FP32 (kernels.hip
                               // InvLayout32), or null
+    const double* Nq;         // 3D lattices, p = 2, 4 x 4 face Gauss points: [F][16][3] w_q N(q) at the
+                              // points q = 4 q_t + q_s (face order), or null (moments instead)
 };
 
 // Doubles per face in the packed face-moment array Bsym: dim packed upper
@@ -89,9 +91,11 @@ bool persistent_uses_inverse(int dim, int p);
 // copies when mixed, else FP64);
 // unstructured: upwind nodes from SweepArgs::nbr_nodes; problem: table index
 // of every entry, or -1 when entries name their problem.
+// face_points: every problem of the launch carries SweepArgs::Nq (3D p = 2
+// lattices), and the cached-inverse kernel contracts the inflow through it.
 void launch_sweep_level(int dim, int p, bool simplex, bool mixed, bool inv, bool unstructured,
                         const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem,
-                        hipStream_t stream);
+                        hipStream_t stream, bool face_points = false);
 // Bytes per pair of the cached A^{-1}: FP64 (n^2 doubles, n^2 + 1 where blocks
 // are padded to a 16-byte multiple) or, f32, rounded to FP32 in groups of four
 // columns (0: no FP32 copy for this shape, n > 32).

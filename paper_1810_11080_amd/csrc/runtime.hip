@@ -7,6 +7,7 @@
 #include <chrono>
 #include <climits>
 #include <cstdint>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -149,6 +150,7 @@ SweepArgs make_args(const snsw_problem* prob, int cur) {
     a.rhs_dir = hp.rhs_fixed.empty() ? nullptr : dp->rhs_dir;
     a.nbr_nodes = dp->nbr_nodes;
     a.ainv32 = dp->ainv32;
+    a.Nq = dp->Nq;
     return a;
 }
 
@@ -279,7 +281,7 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
                 const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
                 if (prof) prof->begin(s);
                 launch_sweep_level(c.dim, c.p, c.simplex, c.mixed, c.inv, c.unstructured, L.table, c.pairs, b, n,
-                                   class_problem(c), s);
+                                   class_problem(c), s, c.face_points);
                 if (prof) prof->end(s);
             }
         }
@@ -372,6 +374,10 @@ void device_upload(snsw_problem* prob) {
             }
         dp->Bsym = dupload(dp, bs, s);
         HIP_OK(hipStreamSynchronize(s));
+        // p = 2 lattices with 4 x 4 face Gauss points (r = 2): the level
+        // sweep contracts the inflow through w_q N(q) instead of the moments
+        const char* env = std::getenv("SNSWEEP_FACE_POINTS");
+        if (!hp.unstructured && hp.p == 2 && hp.r == 2 && !(env && env[0] == '0')) dp->Nq = dupload(dp, hp.Nq, s);
     }
     dp->kink_tab = dupload(dp, hp.unstructured ? ukink : hp.kink_tab, s);
     dp->kink_idx = dupload(dp, hp.unstructured ? ukink_idx : hp.kink_idx, s);
@@ -448,6 +454,7 @@ void device_upload(snsw_problem* prob) {
     c.mixed = hp.precision == SNSW_PREC_MIXED;
     c.unstructured = hp.unstructured;
     c.simplex = hp.simplex;
+    c.face_points = dp->Nq != nullptr;
     c.persistent = hp.schedule == SNSW_SCHED_PERSISTENT;
     c.inv = (dp->ainv != nullptr || dp->ainv32 != nullptr) && (!c.persistent || persistent_uses_inverse(hp.dim, hp.p));
     c.ticket = 0;
@@ -511,7 +518,7 @@ void device_release(snsw_problem* prob) noexcept {
                     dp->tintra, dp->tslots,
                     dp->slot_face, dp->slot_nbr,
                     dp->sigma_t, dp->sigma_s, dp->q, dp->rhs_dir, dp->omega, dp->w, dp->src, dp->psi[0], dp->psi[1],
-                    dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table, dp->ainv, dp->ainv32};
+                    dp->phi_tmp, dp->red, dp->ticket, dp->error, dp->table, dp->ainv, dp->ainv32, dp->Nq};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
