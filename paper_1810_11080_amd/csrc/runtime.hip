@@ -376,8 +376,7 @@ void device_upload(snsw_problem* prob) {
         HIP_OK(hipStreamSynchronize(s));
         // p = 2 lattices with 4 x 4 face Gauss points (r = 2): the level
         // sweep contracts the inflow through w_q N(q) instead of the moments
-        const char* env = std::getenv("SNSWEEP_FACE_POINTS");
-        if (!hp.unstructured && hp.p == 2 && hp.r == 2 && !(env && env[0] == '0')) dp->Nq = dupload(dp, hp.Nq, s);
+        if (!hp.unstructured && hp.p == 2 && hp.r == 2) dp->Nq = dupload(dp, hp.Nq, s);
     }
     dp->kink_tab = dupload(dp, hp.unstructured ? ukink : hp.kink_tab, s);
     dp->kink_idx = dupload(dp, hp.unstructured ? ukink_idx : hp.kink_idx, s);
