@@ -174,7 +174,8 @@ def kernel_name(wp, sched: int, inv: int, tile: int) -> str:
     if sched == 1:
         if wp.dim == 2 and wp.p != 2:
             nt = ",nt" if inv and tile > 0 else ""
-            return f"sweep_persistent_dpp<{wp.dim},{wp.p}{',inv' if inv else ''}{nt}>"
+            f32 = ",f32" if inv == 2 else ""
+            return f"sweep_persistent_dpp<{wp.dim},{wp.p}{',inv' if inv else ''}{nt}{f32}>"
         if inv:
             return f"sweep_persistent_lds2d<{wp.p}>" if wp.dim == 2 else f"sweep_persistent_inv<{wp.dim},{wp.p}>"
         return f"sweep_persistent_fp64<{wp.dim},{wp.p}>"
@@ -652,10 +653,9 @@ def main():
     wp = W.CONFIGS[name]()
     t0 = time.perf_counter()
     sched = {"auto": 0, "persistent": 1, "levels": 2}[args.schedule]
-    if sched == 0:   # same rule as the library's automatic choice
-        sched = 1 if (wp.dim == 2 and wp.p != 2 and prec == 0) else 2
     cache = {"auto": 0, "on": 1, "off": 2}[args.cache_inverse]
     P = Problem.from_workload(ctx, wp, precision=prec, schedule=sched, cache_inverse=cache)
+    sched = P.info()["schedule"]      # the library's choice under "auto"
     setup_s = time.perf_counter() - t0
     note(f"{name}: setup {setup_s:.1f} s")
     main_line = sweep_line(P, wp, name, sched, prec, args.steps, args.warmup)
@@ -702,6 +702,15 @@ def main():
         sec = sweep_line(P2, wp2, "c2", 1, 0, args.steps, args.warmup)
         secondary = {"workload": sec["config"]["workload"], "value": sec["value"], "unit": "DOF-dir/s",
                      "ms_per_step": sec["ms_per_step"], "roofline": sec["roofline"]}
+        P2.close()
+        # and in mixed precision (the persistent kernel with FP32 inverses)
+        P2 = Problem.from_workload(ctx, wp2, precision=1)
+        s2 = P2.info()["schedule"]
+        sm = sweep_line(P2, wp2, "c2", s2, 1, args.steps, args.warmup)
+        secondary["mixed"] = {"precision": "mixed (A^-1 in FP32, FP64 products and sums; parity bar 1e-5)",
+                              "schedule": "persistent" if s2 == 1 else "levels", "value": sm["value"],
+                              "unit": "DOF-dir/s", "ms_per_step": sm["ms_per_step"], "roofline": sm["roofline"]}
+        note(f"c2 mixed: {sm['ms_per_step']} ms per sweep")
         P2.close()
 
     cpu = None

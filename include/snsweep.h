@@ -82,8 +82,11 @@ extern "C" {
  * (element, direction) pairs in level order and wait only for the upwind
  * values they read (latency-bound sweeps: 2D).  LEVELS: one launch per level
  * (throughput-bound sweeps: 3D).  AUTO picks PERSISTENT for 2D FP64
- * problems (for p = 2 unless cache_inverse is SNSW_CACHE_OFF) and LEVELS
- * otherwise; SNSW_PREC_MIXED requires LEVELS.                              */
+ * problems (for p = 2 unless cache_inverse is SNSW_CACHE_OFF) and for 2D
+ * SNSW_PREC_MIXED lattices with p = 1 or 3 whose inverses are not switched
+ * off, and LEVELS otherwise.  SNSW_PREC_MIXED takes PERSISTENT only there
+ * (SNSW_E_UNSUPPORTED elsewhere); if AUTO then finds too little memory for
+ * the FP32 inverses the problem sweeps on LEVELS (info reports it).      */
 #define SNSW_SCHED_AUTO        0
 #define SNSW_SCHED_PERSISTENT  1
 #define SNSW_SCHED_LEVELS      2
@@ -205,7 +208,8 @@ typedef struct {
      * faces are the same face when their corner control points coincide (by
      * index); they may meet in any orientation.  Every element map must be
      * orientation preserving (det J > 0).  Such problems sweep on the LEVELS
-     * schedule (SNSW_SCHED_PERSISTENT gives SNSW_E_UNSUPPORTED).            */
+     * schedule unless SNSW_SCHED_PERSISTENT is asked for (FP64 only: the
+     * generic persistent kernels with a per-slot upwind node table).       */
     int64_t n_nodes;
     const double* nodes;
     const int64_t* elem_nodes;

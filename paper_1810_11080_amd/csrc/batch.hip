@@ -332,7 +332,8 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
         pa.problem = class_problem(c);
         pa.slots = c.slots;
         pa.nt = 0;
-        launch_sweep_persistent(c.dim, c.p, c.simplex, c.unstructured, c.inv, pa, c.blocks, s);
+        if (!launch_sweep_persistent(c.dim, c.p, c.simplex, c.unstructured, c.inv, pa, c.blocks, s))
+            throw Error(SNSW_E_STATE, "batch class without a persistent kernel");
     } else {
         for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
             const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;

@@ -137,6 +137,6 @@ void check_error_flag(int32_t* flag, hipStream_t s);
 
 DeviceProblem* need_device(snsw_problem* prob);
 int persistent_grid(int dim, int p, bool simplex, bool unstructured, bool inv, int64_t total, int device,
-                    double fraction = 1.0);
+                    double fraction = 1.0, bool f32 = false);
 
 }  // namespace snsw

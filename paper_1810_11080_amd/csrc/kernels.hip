@@ -805,12 +805,14 @@ __device__ __forceinline__ void static_for(F&& f) {
 // parked in LDS (each face lane writes its own row), the wait state is kept
 // per axis, and after the wait the face lanes form c = P_in psi_up, which is
 // broadcast into x += A^{-1}[:, tn_s] c.  NT: the rows of A^{-1} are read
-// with non-temporal loads.
-template <int DIM, int P, bool INV, bool NT = false>
+// with non-temporal loads.  F32 (mixed precision): the cached A^{-1} is the
+// FP32 copy, held in registers as FP32, with products and sums in FP64.
+template <int DIM, int P, bool INV, bool NT = false, bool F32 = false>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3, 8))) sweep_persistent_dpp(PersistArgs pa) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, NF = S::NF, NS = S::NS, G = S::G;
     static_assert(G * N == 64, "groups must tile the wavefront");
+    static_assert(INV || !F32, "FP32 rows come from the cached inverses");
     __shared__ double pin_lds[kWaves][G][NS][NF][NF + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / N, row = lane - grp * N;
@@ -847,8 +849,22 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         // ---- assembly of row `row`, branch-free: padding lanes assemble
         // element 0 and are masked (divergent branches here would keep two
         // copies of the row alive).
-        double m[N];
-        if constexpr (INV) {
+        std::conditional_t<F32, float, double> m[N];
+        if constexpr (F32) {
+            // row `row` of the FP32 copy, four entries per 16-byte load
+            using IL32 = InvLayout32<DIM, P>;
+            static_assert(IL32::kGroups * 4 == N, "whole groups of four columns");
+            const float* Af = args.ainv32 + ((size_t)d * args.E + e) * IL32::kStride;
+#pragma unroll
+            for (int g = 0; g < IL32::kGroups; ++g) {
+                const flt4* src = reinterpret_cast<const flt4*>(Af + IL32::at(row, 4 * g));
+                const flt4 v = NT ? __builtin_nontemporal_load(src) : *src;
+                m[4 * g] = v.x;
+                m[4 * g + 1] = v.y;
+                m[4 * g + 2] = v.z;
+                m[4 * g + 3] = v.w;
+            }
+        } else if constexpr (INV) {
             // row `row` of the cached A^{-1} (stored column-major; a column
             // of n = 4 or 16 doubles lies in one 128 B line).  NT: read as
             // streaming (non-temporal) data, once per sweep, so that it does
@@ -963,7 +979,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
         double x = 0.0;
         static_for<0, N>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            x += m[j] * group_bcast<N, j>(rhs);
+            x += (double)m[j] * group_bcast<N, j>(rhs);
         });
 
         // ---- wait and finish: the lane on face-local node la of a kept slot
@@ -1064,7 +1080,7 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
                             });
                             static_for<0, NF>([&](auto ac) {
                                 constexpr int aa = decltype(ac)::value;
-                                x += m[S::tn(s, aa)] * group_bcast<N, S::tn(s, aa)>(c);
+                                x += (double)m[S::tn(s, aa)] * group_bcast<N, S::tn(s, aa)>(c);
                             });
                         }
                     });
@@ -2206,37 +2222,33 @@ constexpr bool use_staged() {
 }
 
 template <int DIM, int P>
-void launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, hipStream_t stream) {
+bool launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, bool f32, hipStream_t stream) {
+    const dim3 grid((unsigned)blocks), block(64 * kWaves);
     if constexpr (use_dpp<DIM, P>()) {
-        if (inv && a.nt)
-            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, true, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
-                               stream, a);
+        if (inv && f32 && a.nt)
+            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, true, true, true>), grid, block, 0, stream, a);
+        else if (inv && f32)
+            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, true, false, true>), grid, block, 0, stream, a);
+        else if (inv && a.nt)
+            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, true, true>), grid, block, 0, stream, a);
         else if (inv)
-            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
-                               stream, a);
+            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, true>), grid, block, 0, stream, a);
         else
-            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
-                               stream, a);
-    } else if constexpr (DIM == 2) {
-        if (inv)
-            hipLaunchKernelGGL((sweep_persistent_lds2d<P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, a);
-        else
-            hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
-                               stream, a);
-    } else if constexpr (use_staged<DIM, P>()) {
-        if (inv)
-            hipLaunchKernelGGL((sweep_persistent_staged<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
-                               stream, a);
-        else
-            hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
-                               stream, a);
+            hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, false>), grid, block, 0, stream, a);
+        return true;
     } else {
-        if (inv)
-            hipLaunchKernelGGL((sweep_persistent_inv<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
-                               a);
-        else
-            hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
-                               stream, a);
+        if (f32) return false;   // FP32 inverses: the DPP kernels only
+        if constexpr (DIM == 2) {
+            if (inv) hipLaunchKernelGGL((sweep_persistent_lds2d<P>), grid, block, 0, stream, a);
+            else hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), grid, block, 0, stream, a);
+        } else if constexpr (use_staged<DIM, P>()) {
+            if (inv) hipLaunchKernelGGL((sweep_persistent_staged<DIM, P>), grid, block, 0, stream, a);
+            else hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), grid, block, 0, stream, a);
+        } else {
+            if (inv) hipLaunchKernelGGL((sweep_persistent_inv<DIM, P>), grid, block, 0, stream, a);
+            else hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), grid, block, 0, stream, a);
+        }
+        return true;
     }
 }
 
@@ -2290,12 +2302,14 @@ void launch_factor_tpl(const SweepArgs* table, const int4* pairs, int64_t count,
 }
 
 template <int DIM, int P>
-int occupancy_tpl(bool inv) {
+int occupancy_tpl(bool inv, bool f32) {
     int nb = 0;
     hipError_t rc;
     if constexpr (use_dpp<DIM, P>())
-        rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, true>, 64 * kWaves, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, false>, 64 * kWaves, 0);
+        rc = inv && f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &nb, sweep_persistent_dpp<DIM, P, true, false, true>, 64 * kWaves, 0)
+             : inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, true>, 64 * kWaves, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, false>, 64 * kWaves, 0);
     else if constexpr (DIM == 2)
         rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_lds2d<P>, 64 * kWaves, 0)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P>, 64 * kWaves, 0);
@@ -2462,18 +2476,19 @@ void launch_fill_sentinel(const SweepArgs* table, int count, int64_t max_DEn, hi
     hipLaunchKernelGGL(fill_sentinel_kernel, dim3((unsigned)blocks, (unsigned)count), dim3(256), 0, stream, table);
 }
 
-void launch_sweep_persistent(int dim, int p, bool simplex, bool unstructured, bool inv, const PersistArgs& a,
-                             int blocks, hipStream_t stream) {
-    if (simplex && dim == 3) {
-        if (p == 1) launch_persist_u<3, kTet + 1>(a, blocks, inv, stream);
-        else if (p == 2) launch_persist_u<3, kTet + 2>(a, blocks, inv, stream);
-        else launch_persist_u<3, kTet + 3>(a, blocks, inv, stream);
-    } else if (simplex) {
-        if (p == 1) launch_persist_u<2, kTri + 1>(a, blocks, inv, stream);
-        else if (p == 2) launch_persist_u<2, kTri + 2>(a, blocks, inv, stream);
-        else launch_persist_u<2, kTri + 3>(a, blocks, inv, stream);
-    } else if (unstructured) {
-        if (dim == 2) {
+bool launch_sweep_persistent(int dim, int p, bool simplex, bool unstructured, bool inv, const PersistArgs& a,
+                             int blocks, hipStream_t stream, bool f32) {
+    if (simplex || unstructured) {
+        if (f32) return false;
+        if (simplex && dim == 3) {
+            if (p == 1) launch_persist_u<3, kTet + 1>(a, blocks, inv, stream);
+            else if (p == 2) launch_persist_u<3, kTet + 2>(a, blocks, inv, stream);
+            else launch_persist_u<3, kTet + 3>(a, blocks, inv, stream);
+        } else if (simplex) {
+            if (p == 1) launch_persist_u<2, kTri + 1>(a, blocks, inv, stream);
+            else if (p == 2) launch_persist_u<2, kTri + 2>(a, blocks, inv, stream);
+            else launch_persist_u<2, kTri + 3>(a, blocks, inv, stream);
+        } else if (dim == 2) {
             if (p == 1) launch_persist_u<2, 1>(a, blocks, inv, stream);
             else if (p == 2) launch_persist_u<2, 2>(a, blocks, inv, stream);
             else launch_persist_u<2, 3>(a, blocks, inv, stream);
@@ -2482,18 +2497,19 @@ void launch_sweep_persistent(int dim, int p, bool simplex, bool unstructured, bo
             else if (p == 2) launch_persist_u<3, 2>(a, blocks, inv, stream);
             else launch_persist_u<3, 3>(a, blocks, inv, stream);
         }
-    } else if (dim == 2) {
-        if (p == 1) launch_persist_tpl<2, 1>(a, blocks, inv, stream);
-        else if (p == 2) launch_persist_tpl<2, 2>(a, blocks, inv, stream);
-        else launch_persist_tpl<2, 3>(a, blocks, inv, stream);
-    } else {
-        if (p == 1) launch_persist_tpl<3, 1>(a, blocks, inv, stream);
-        else if (p == 2) launch_persist_tpl<3, 2>(a, blocks, inv, stream);
-        else launch_persist_tpl<3, 3>(a, blocks, inv, stream);
+        return true;
     }
+    if (dim == 2) {
+        if (p == 1) return launch_persist_tpl<2, 1>(a, blocks, inv, f32, stream);
+        if (p == 2) return launch_persist_tpl<2, 2>(a, blocks, inv, f32, stream);
+        return launch_persist_tpl<2, 3>(a, blocks, inv, f32, stream);
+    }
+    if (p == 1) return launch_persist_tpl<3, 1>(a, blocks, inv, f32, stream);
+    if (p == 2) return launch_persist_tpl<3, 2>(a, blocks, inv, f32, stream);
+    return launch_persist_tpl<3, 3>(a, blocks, inv, f32, stream);
 }
 
-int persistent_blocks_per_cu(int dim, int p, bool simplex, bool unstructured, bool inv) {
+int persistent_blocks_per_cu(int dim, int p, bool simplex, bool unstructured, bool inv, bool f32) {
     if (simplex && dim == 3)
         return p == 1 ? occupancy_u<3, kTet + 1>(inv) : p == 2 ? occupancy_u<3, kTet + 2>(inv)
                                                              : occupancy_u<3, kTet + 3>(inv);
@@ -2505,8 +2521,14 @@ int persistent_blocks_per_cu(int dim, int p, bool simplex, bool unstructured, bo
         return p == 1 ? occupancy_u<3, 1>(inv) : p == 2 ? occupancy_u<3, 2>(inv) : occupancy_u<3, 3>(inv);
     }
     if (dim == 2)
-        return p == 1 ? occupancy_tpl<2, 1>(inv) : p == 2 ? occupancy_tpl<2, 2>(inv) : occupancy_tpl<2, 3>(inv);
-    return p == 1 ? occupancy_tpl<3, 1>(inv) : p == 2 ? occupancy_tpl<3, 2>(inv) : occupancy_tpl<3, 3>(inv);
+        return p == 1 ? occupancy_tpl<2, 1>(inv, f32) : p == 2 ? occupancy_tpl<2, 2>(inv, f32)
+                                                             : occupancy_tpl<2, 3>(inv, f32);
+    return p == 1 ? occupancy_tpl<3, 1>(inv, f32) : p == 2 ? occupancy_tpl<3, 2>(inv, f32)
+                                                         : occupancy_tpl<3, 3>(inv, f32);
+}
+
+bool persistent_f32(int dim, int p, bool simplex, bool unstructured) {
+    return dim == 2 && !simplex && !unstructured && (p == 1 || p == 3);
 }
 
 bool persistent_uses_inverse(int dim, int p) {

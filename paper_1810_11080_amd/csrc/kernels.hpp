@@ -76,13 +76,17 @@ struct PersistArgs {
 };
 
 // Launches the persistent sweep kernel (all levels in one launch); inv: read
-// the cached inverses; simplex / unstructured: element lists (triangles, or
-// quads / hexes), swept by the generic persistent kernels with the upwind
-// node table.
-void launch_sweep_persistent(int dim, int p, bool simplex, bool unstructured, bool inv, const PersistArgs& a,
-                             int blocks, hipStream_t stream);
+// the cached inverses (f32: their FP32 copy); simplex / unstructured: element
+// lists (triangles, or quads / hexes), swept by the generic persistent
+// kernels with the upwind node table.  Returns false, launching nothing, for
+// a combination without a kernel (f32 outside persistent_f32).
+bool launch_sweep_persistent(int dim, int p, bool simplex, bool unstructured, bool inv, const PersistArgs& a,
+                             int blocks, hipStream_t stream, bool f32 = false);
 // Blocks per CU that the persistent kernel can keep resident.
-int persistent_blocks_per_cu(int dim, int p, bool simplex, bool unstructured, bool inv);
+int persistent_blocks_per_cu(int dim, int p, bool simplex, bool unstructured, bool inv, bool f32 = false);
+// Whether the persistent kernel of this shape reads FP32 cached inverses
+// (2D lattices with 4- or 16-node elements: the DPP kernel).
+bool persistent_f32(int dim, int p, bool simplex, bool unstructured);
 // Whether the persistent kernel of this shape has a cached-inverse variant.
 bool persistent_uses_inverse(int dim, int p);
 // Launches the level-sweep kernel over schedule entries [begin, begin+count)

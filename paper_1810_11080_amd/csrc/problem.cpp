@@ -171,12 +171,18 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
             hp.schedule != SNSW_SCHED_LEVELS)
             throw Error(SNSW_E_INVALID_ARG, "schedule must be AUTO, PERSISTENT or LEVELS");
         hp.cache_inverse = desc->cache_inverse;
+        // mixed precision sweeps persistently where a persistent kernel reads
+        // the FP32 inverses: 2D lattices with p = 1 or 3 (4- or 16-node
+        // elements), inverses not switched off
+        const bool mixed_persistent = hp.dim == 2 && !desc->elem_nodes && (hp.p == 1 || hp.p == 3) &&
+                                      hp.cache_inverse != SNSW_CACHE_OFF;
         if (hp.schedule == SNSW_SCHED_AUTO) {
-            // 2D FP64 sweeps are latency-bound: persistent (p = 2 only with
+            // 2D sweeps are latency-bound: persistent (FP64: p = 2 only with
             // cached inverses; its assembled persistent kernel is slower than
             // the level schedule)
-            const bool ok = hp.dim == 2 && desc->precision == SNSW_PREC_FP64 &&
-                            (hp.p != 2 || hp.cache_inverse != SNSW_CACHE_OFF);
+            const bool ok = desc->precision == SNSW_PREC_MIXED
+                                ? mixed_persistent
+                                : hp.dim == 2 && (hp.p != 2 || hp.cache_inverse != SNSW_CACHE_OFF);
             hp.schedule = ok ? SNSW_SCHED_PERSISTENT : SNSW_SCHED_LEVELS;
         }
         if (hp.cache_inverse != SNSW_CACHE_AUTO && hp.cache_inverse != SNSW_CACHE_ON &&
@@ -185,8 +191,10 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
         if (hp.cache_inverse == SNSW_CACHE_ON && desc->precision == SNSW_PREC_MIXED && hp.n > 32)
             throw Error(SNSW_E_UNSUPPORTED, "cached FP32 inverses need elements of at most 32 nodes");
 
-        if (desc->precision == SNSW_PREC_MIXED && hp.schedule == SNSW_SCHED_PERSISTENT)
-            throw Error(SNSW_E_UNSUPPORTED, "mixed precision runs on the LEVELS schedule");
+        if (desc->precision == SNSW_PREC_MIXED && hp.schedule == SNSW_SCHED_PERSISTENT && !mixed_persistent)
+            throw Error(SNSW_E_UNSUPPORTED,
+                        "mixed precision runs on the LEVELS schedule (persistent: 2D lattices, p = 1 or 3, "
+                        "inverses not switched off)");
 
         // mesh: structured lattice or element control-point lists
         if (desc->elem_nodes) {

@@ -274,7 +274,9 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             // sweeps (2D 128^2 p = 3 S8: 4 %) and lost on batches
             pa.nt = c.intra != nullptr ? 1 : 0;
             if (prof) prof->begin(s);
-            launch_sweep_persistent(c.dim, c.p, c.simplex, c.unstructured, c.inv, pa, c.blocks, s);
+            if (!launch_sweep_persistent(c.dim, c.p, c.simplex, c.unstructured, c.inv, pa, c.blocks, s,
+                                         c.mixed && c.inv))
+                throw Error(SNSW_E_UNSUPPORTED, "no persistent kernel reads FP32 inverses for this element");
             if (prof) prof->end(s);
         } else {
             for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
@@ -303,10 +305,10 @@ void check_error_flag(int32_t* flag, hipStream_t s) {
 }
 
 int persistent_grid(int dim, int p, bool simplex, bool unstructured, bool inv, int64_t total, int device,
-                    double fraction) {
+                    double fraction, bool f32) {
     int cus = 0;
     HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-    const int per_cu = persistent_blocks_per_cu(dim, p, simplex, unstructured, inv);
+    const int per_cu = persistent_blocks_per_cu(dim, p, simplex, unstructured, inv, f32);
     const int n = simplex ? (p + 1) * (p + 2) / 2 : dim == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
     const int64_t per_block = 4 * (64 / n);
     const int64_t need = (total + per_block - 1) / per_block;
@@ -454,6 +456,9 @@ void device_upload(snsw_problem* prob) {
     c.unstructured = hp.unstructured;
     c.simplex = hp.simplex;
     c.face_points = dp->Nq != nullptr;
+    // mixed precision without cached inverses (AUTO found too little
+    // memory) sweeps level by level: no persistent kernel assembles in FP32
+    if (c.mixed && hp.schedule == SNSW_SCHED_PERSISTENT && !dp->ainv32) hp.schedule = SNSW_SCHED_LEVELS;
     c.persistent = hp.schedule == SNSW_SCHED_PERSISTENT;
     c.inv = (dp->ainv != nullptr || dp->ainv32 != nullptr) && (!c.persistent || persistent_uses_inverse(hp.dim, hp.p));
     c.ticket = 0;
@@ -467,7 +472,7 @@ void device_upload(snsw_problem* prob) {
     }
     c.members = {0};
     c.blocks = c.persistent ? persistent_grid(hp.dim, hp.p, hp.simplex, hp.unstructured, c.inv,
-                                              hp.level_off.back(), dp->device)
+                                              hp.level_off.back(), dp->device, 1.0, c.mixed && c.inv)
                             : 0;
     {
         dp->cur = 0;

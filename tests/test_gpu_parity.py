@@ -322,12 +322,34 @@ def test_mixed_precision_sweeps(torch, ctx, case, cache):
     assert rel_err(g_psi[-1], o_psi[-1]) < MIXED_TOL
 
 
-@pytest.mark.parametrize("cache", [1, 2], ids=["fp32-inverse", "assembled"])
-def test_mixed_precision_c2_full(torch, ctx, c2_oracle, cache):
+@pytest.mark.parametrize("schedule", [1, 2], ids=["persistent", "levels"])
+@pytest.mark.parametrize("case", ["c1", "cyclic2d_p3"])
+def test_mixed_precision_2d_schedules(torch, ctx, case, schedule):
+    """FP32 inverses on both 2D schedules: the persistent DPP kernel (tiled
+    schedule; FP32 rows in registers, FP64 products) and the level kernel."""
+    from paper_1810_11080_amd import Problem
+    wp = SMALL[case]()
+    P = Problem.from_workload(ctx, wp, precision=1, schedule=schedule)
+    info = P.info()
+    assert info["cached_inverse"] == 2 and info["schedule"] == schedule
+    g_phi, g_psi = gpu_sweeps(torch, P, 3)
+    P.synchronize()
+    o_phi, o_psi, _, _ = oracle_sweeps(wp, 3)
+    for k in range(3):
+        assert rel_err(g_phi[k], o_phi[k]) < MIXED_TOL
+    assert rel_err(g_psi[-1], o_psi[-1]) < MIXED_TOL
+
+
+@pytest.mark.parametrize("cache,schedule", [(1, 0), (1, 2), (2, 0)],
+                         ids=["fp32-inverse-persistent", "fp32-inverse-levels", "assembled"])
+def test_mixed_precision_c2_full(torch, ctx, c2_oracle, cache, schedule):
     from paper_1810_11080_amd import Problem
     wp, phi0, psi0, o_phi, o_psi = c2_oracle
-    P = Problem.from_workload(ctx, wp, precision=1, cache_inverse=cache)
-    assert P.info()["cached_inverse"] == (2 if cache == 1 else 0)
+    P = Problem.from_workload(ctx, wp, precision=1, cache_inverse=cache, schedule=schedule)
+    info = P.info()
+    assert info["cached_inverse"] == (2 if cache == 1 else 0)
+    # AUTO: persistent with the FP32 inverses, else level by level
+    assert info["schedule"] == (schedule if schedule else (1 if cache == 1 else 2))
     P.state_load(state_bytes(wp, psi0))
     g_phi, g_psi = gpu_sweeps(torch, P, 1, phi0)
     P.synchronize()

@@ -238,3 +238,25 @@ def test_unstructured_input_errors(ctx):
         Problem(ctx, dim=2, nx=(E, 1), geom_order=2, dg_order=1, lattice=None, sn_order=2,
                 sigma_t=tw.sigma_t, sigma_s=tw.sigma_s, q=tw.q, nodes=tw.nodes,
                 elem_nodes=tw.elem_nodes[:, :5], element=1)
+
+
+def test_mixed_precision_schedule_choice(ctx):
+    """Mixed precision sweeps persistently where the persistent kernel reads
+    FP32 inverses (2D lattices, p = 1 or 3, inverses not switched off) and
+    level by level elsewhere; asking for the persistent schedule elsewhere is
+    refused (SNSW_E_UNSUPPORTED)."""
+    from paper_1810_11080_amd import Problem, SnswError
+    for p in (1, 3):
+        wp = W.small(dim=2, n=4, r=2, p=p, N=2)
+        assert Problem.from_workload(ctx, wp, precision=1).info()["schedule"] == 1
+        assert Problem.from_workload(ctx, wp, precision=1, schedule=2).info()["schedule"] == 2
+        assert Problem.from_workload(ctx, wp, precision=1, cache_inverse=2).info()["schedule"] == 2
+        with pytest.raises(SnswError) as ei:
+            Problem.from_workload(ctx, wp, precision=1, cache_inverse=2, schedule=1)
+        assert ei.value.code == -9
+    for wp in (W.small(dim=2, n=4, r=2, p=2, N=2), W.small(dim=3, n=2, r=1, p=1, N=2),
+               W.annulus_full(nr=2, nt=8, p=1, sn_order=2)):
+        assert Problem.from_workload(ctx, wp, precision=1).info()["schedule"] == 2
+        with pytest.raises(SnswError) as ei:
+            Problem.from_workload(ctx, wp, precision=1, schedule=1)
+        assert ei.value.code == -9
