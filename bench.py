@@ -46,6 +46,7 @@ METRIC = "DOF-direction updates/s per sweep; time to 1e-8 residual, learned vs p
 # named after each kernel and workload hold the counts.  Only valid for the
 # kernel build it was measured on: drop an entry when the kernel changes.
 MEASURED_TRAFFIC = {("sweep_persistent_dpp<2,3,inv,nt>", "c2", "fp64"): 1.902e9,
+                    ("sweep_persistent_dpp<2,3,inv,nt,f32>", "c2", "mixed"): 1.247e9,
                     ("sweep_level_inv<3,2>", "c5", "fp64"): 4.338e8,
                     ("sweep_level_inv<3,2,f32>", "c5", "mixed"): 2.744e8}
 DESCRIPTIONS = {
@@ -177,7 +178,9 @@ def kernel_name(wp, sched: int, inv: int, tile: int) -> str:
             f32 = ",f32" if inv == 2 else ""
             return f"sweep_persistent_dpp<{wp.dim},{wp.p}{',inv' if inv else ''}{nt}{f32}>"
         if inv:
-            return f"sweep_persistent_lds2d<{wp.p}>" if wp.dim == 2 else f"sweep_persistent_inv<{wp.dim},{wp.p}>"
+            if wp.dim == 2:
+                return f"sweep_persistent_lds2d<{wp.p}{',f32' if inv == 2 else ''}>"
+            return f"sweep_persistent_inv<{wp.dim},{wp.p}>"
         return f"sweep_persistent_fp64<{wp.dim},{wp.p}>"
     if inv == 2:
         return f"sweep_level_inv<{wp.dim},{wp.p},f32>"

@@ -83,8 +83,8 @@ extern "C" {
  * values they read (latency-bound sweeps: 2D).  LEVELS: one launch per level
  * (throughput-bound sweeps: 3D).  AUTO picks PERSISTENT for 2D FP64
  * problems (for p = 2 unless cache_inverse is SNSW_CACHE_OFF) and for 2D
- * SNSW_PREC_MIXED lattices with p = 1 or 3 whose inverses are not switched
- * off, and LEVELS otherwise.  SNSW_PREC_MIXED takes PERSISTENT only there
+ * SNSW_PREC_MIXED lattices whose inverses are not switched off, and LEVELS
+ * otherwise.  SNSW_PREC_MIXED takes PERSISTENT only there
  * (SNSW_E_UNSUPPORTED elsewhere); if AUTO then finds too little memory for
  * the FP32 inverses the problem sweeps on LEVELS (info reports it).      */
 #define SNSW_SCHED_AUTO        0

@@ -1116,8 +1116,9 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
 // all nf upwind values of the face (all loads of a poll issued together),
 // and each group finishes as soon as its lanes hold them: b += P_in psi_up
 // on the face lanes, b through LDS, x = A^{-1} b, device-scope store.  The
-// groups of a wavefront do not wait for each other.
-template <int P>
+// groups of a wavefront do not wait for each other.  F32 (mixed precision):
+// the FP32 copy of A^{-1}, FP64 products and sums.
+template <int P, bool F32 = false>
 __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArgs pa) {
     constexpr int DIM = 2;
     using S = Shape<DIM, P>;
@@ -1150,10 +1151,24 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
         const unsigned packed = (unsigned)prs.y;
         const int d = (int)(packed & kDirMask);
         static_assert(!InvLayout<DIM, P>::kPaired, "column-major blocks only");
-        const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
-        double m[N];
+        using IL32 = InvLayout32<DIM, P>;
+        std::conditional_t<F32, float, double> m[F32 ? IL32::kGroups * 4 : N];
+        if constexpr (F32) {
+            // four entries of the FP32 row per 16-byte load
+            const float* Af = args.ainv32 + ((size_t)d * args.E + e) * IL32::kStride;
 #pragma unroll
-        for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+            for (int g = 0; g < IL32::kGroups; ++g) {
+                const flt4 v = *reinterpret_cast<const flt4*>(Af + IL32::at(row, 4 * g));
+                m[4 * g] = v.x;
+                m[4 * g + 1] = v.y;
+                m[4 * g + 2] = v.z;
+                m[4 * g + 3] = v.w;
+            }
+        } else {
+            const double* Ai = args.ainv + ((size_t)d * args.E + e) * N * N + row;
+#pragma unroll
+            for (int j = 0; j < N; ++j) m[j] = Ai[j * N];
+        }
 
         // ---- faces: index loads first, then face data
         int nbs[NS], fcs[NS], krows[NS];
@@ -1263,7 +1278,7 @@ __global__ void __launch_bounds__(64 * kWaves) sweep_persistent_lds2d(PersistArg
                 wave_sync();
                 double x = 0.0;
 #pragma unroll
-                for (int j = 0; j < N; ++j) x += m[j] * L[j];
+                for (int j = 0; j < N; ++j) x += (double)m[j] * L[j];
                 __hip_atomic_store(args.psi_cur + ((size_t)d * args.E + e) * N + row, x, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
                 done = true;
@@ -2237,9 +2252,10 @@ bool launch_persist_tpl(const PersistArgs& a, int blocks, bool inv, bool f32, hi
             hipLaunchKernelGGL((sweep_persistent_dpp<DIM, P, false>), grid, block, 0, stream, a);
         return true;
     } else {
-        if (f32) return false;   // FP32 inverses: the DPP kernels only
+        if (f32 && !(inv && DIM == 2)) return false;   // FP32 inverses: the 2D lattice kernels only
         if constexpr (DIM == 2) {
-            if (inv) hipLaunchKernelGGL((sweep_persistent_lds2d<P>), grid, block, 0, stream, a);
+            if (inv && f32) hipLaunchKernelGGL((sweep_persistent_lds2d<P, true>), grid, block, 0, stream, a);
+            else if (inv) hipLaunchKernelGGL((sweep_persistent_lds2d<P>), grid, block, 0, stream, a);
             else hipLaunchKernelGGL((sweep_persistent_fp64<DIM, P>), grid, block, 0, stream, a);
         } else if constexpr (use_staged<DIM, P>()) {
             if (inv) hipLaunchKernelGGL((sweep_persistent_staged<DIM, P>), grid, block, 0, stream, a);
@@ -2311,7 +2327,8 @@ int occupancy_tpl(bool inv, bool f32) {
              : inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, true>, 64 * kWaves, 0)
                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_dpp<DIM, P, false>, 64 * kWaves, 0);
     else if constexpr (DIM == 2)
-        rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_lds2d<P>, 64 * kWaves, 0)
+        rc = inv && f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_lds2d<P, true>, 64 * kWaves, 0)
+             : inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_lds2d<P>, 64 * kWaves, 0)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_fp64<DIM, P>, 64 * kWaves, 0);
     else if constexpr (use_staged<DIM, P>())
         rc = inv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_persistent_staged<DIM, P>, 64 * kWaves, 0)
@@ -2528,7 +2545,8 @@ int persistent_blocks_per_cu(int dim, int p, bool simplex, bool unstructured, bo
 }
 
 bool persistent_f32(int dim, int p, bool simplex, bool unstructured) {
-    return dim == 2 && !simplex && !unstructured && (p == 1 || p == 3);
+    (void)p;
+    return dim == 2 && !simplex && !unstructured;
 }
 
 bool persistent_uses_inverse(int dim, int p) {

@@ -85,7 +85,7 @@ bool launch_sweep_persistent(int dim, int p, bool simplex, bool unstructured, bo
 // Blocks per CU that the persistent kernel can keep resident.
 int persistent_blocks_per_cu(int dim, int p, bool simplex, bool unstructured, bool inv, bool f32 = false);
 // Whether the persistent kernel of this shape reads FP32 cached inverses
-// (2D lattices with 4- or 16-node elements: the DPP kernel).
+// (2D lattices: the DPP and LDS kernels).
 bool persistent_f32(int dim, int p, bool simplex, bool unstructured);
 // Whether the persistent kernel of this shape has a cached-inverse variant.
 bool persistent_uses_inverse(int dim, int p);

@@ -172,10 +172,8 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
             throw Error(SNSW_E_INVALID_ARG, "schedule must be AUTO, PERSISTENT or LEVELS");
         hp.cache_inverse = desc->cache_inverse;
         // mixed precision sweeps persistently where a persistent kernel reads
-        // the FP32 inverses: 2D lattices with p = 1 or 3 (4- or 16-node
-        // elements), inverses not switched off
-        const bool mixed_persistent = hp.dim == 2 && !desc->elem_nodes && (hp.p == 1 || hp.p == 3) &&
-                                      hp.cache_inverse != SNSW_CACHE_OFF;
+        // the FP32 inverses: 2D lattices, inverses not switched off
+        const bool mixed_persistent = hp.dim == 2 && !desc->elem_nodes && hp.cache_inverse != SNSW_CACHE_OFF;
         if (hp.schedule == SNSW_SCHED_AUTO) {
             // 2D sweeps are latency-bound: persistent (FP64: p = 2 only with
             // cached inverses; its assembled persistent kernel is slower than
@@ -193,8 +191,8 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
 
         if (desc->precision == SNSW_PREC_MIXED && hp.schedule == SNSW_SCHED_PERSISTENT && !mixed_persistent)
             throw Error(SNSW_E_UNSUPPORTED,
-                        "mixed precision runs on the LEVELS schedule (persistent: 2D lattices, p = 1 or 3, "
-                        "inverses not switched off)");
+                        "mixed precision runs on the LEVELS schedule (persistent: 2D lattices with cached "
+                        "inverses)");
 
         // mesh: structured lattice or element control-point lists
         if (desc->elem_nodes) {

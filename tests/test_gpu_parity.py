@@ -323,10 +323,11 @@ def test_mixed_precision_sweeps(torch, ctx, case, cache):
 
 
 @pytest.mark.parametrize("schedule", [1, 2], ids=["persistent", "levels"])
-@pytest.mark.parametrize("case", ["c1", "cyclic2d_p3"])
+@pytest.mark.parametrize("case", ["c1", "cyclic2d_p2", "cyclic2d_p3"])
 def test_mixed_precision_2d_schedules(torch, ctx, case, schedule):
-    """FP32 inverses on both 2D schedules: the persistent DPP kernel (tiled
-    schedule; FP32 rows in registers, FP64 products) and the level kernel."""
+    """FP32 inverses on both 2D schedules: the persistent kernels (DPP on the
+    tiled schedule for p = 1, 3; LDS exchanges for p = 2; FP32 rows in
+    registers, FP64 products) and the level kernel."""
     from paper_1810_11080_amd import Problem
     wp = SMALL[case]()
     P = Problem.from_workload(ctx, wp, precision=1, schedule=schedule)

@@ -241,12 +241,12 @@ def test_unstructured_input_errors(ctx):
 
 
 def test_mixed_precision_schedule_choice(ctx):
-    """Mixed precision sweeps persistently where the persistent kernel reads
-    FP32 inverses (2D lattices, p = 1 or 3, inverses not switched off) and
-    level by level elsewhere; asking for the persistent schedule elsewhere is
-    refused (SNSW_E_UNSUPPORTED)."""
+    """Mixed precision sweeps persistently where the persistent kernels read
+    FP32 inverses (2D lattices, inverses not switched off) and level by level
+    elsewhere; asking for the persistent schedule elsewhere is refused
+    (SNSW_E_UNSUPPORTED)."""
     from paper_1810_11080_amd import Problem, SnswError
-    for p in (1, 3):
+    for p in (1, 2, 3):
         wp = W.small(dim=2, n=4, r=2, p=p, N=2)
         assert Problem.from_workload(ctx, wp, precision=1).info()["schedule"] == 1
         assert Problem.from_workload(ctx, wp, precision=1, schedule=2).info()["schedule"] == 2
@@ -254,7 +254,7 @@ def test_mixed_precision_schedule_choice(ctx):
         with pytest.raises(SnswError) as ei:
             Problem.from_workload(ctx, wp, precision=1, cache_inverse=2, schedule=1)
         assert ei.value.code == -9
-    for wp in (W.small(dim=2, n=4, r=2, p=2, N=2), W.small(dim=3, n=2, r=1, p=1, N=2),
+    for wp in (W.small(dim=3, n=2, r=1, p=1, N=2), W.small(dim=3, n=2, r=1, p=2, N=2),
                W.annulus_full(nr=2, nt=8, p=1, sn_order=2)):
         assert Problem.from_workload(ctx, wp, precision=1).info()["schedule"] == 2
         with pytest.raises(SnswError) as ei:
