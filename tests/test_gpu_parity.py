@@ -200,9 +200,10 @@ def test_constant_solution_c5_size(torch, ctx):
     P.close()
 
 
-@pytest.mark.parametrize("case,cache", [("cyclic2d_p3", 0), ("standin2d", 0), ("cyclic2d_p2", 2), ("warp3d_p2", 1)],
-                         ids=["dpp", "lds2d", "assembled2d_p2", "inverse3d_p2"])
-def test_wait_failure_reported_and_recovered(torch, ctx, case, cache):
+@pytest.mark.parametrize("case,cache,precision", [("cyclic2d_p3", 0, 0), ("standin2d", 0, 0), ("cyclic2d_p2", 2, 0),
+                                                  ("warp3d_p2", 1, 0), ("cyclic2d_p3", 0, 1), ("cyclic2d_p2", 0, 1)],
+                         ids=["dpp", "lds2d", "assembled2d_p2", "inverse3d_p2", "dpp_mixed", "lds2d_mixed"])
+def test_wait_failure_reported_and_recovered(torch, ctx, case, cache, precision):
     """The failure path of a persistent sweep, forced from the host: with a
     bound of zero polls every dependency wait whose value is not there at
     the first poll (or at its re-read) gives up at once, the grid drains and
@@ -210,15 +211,16 @@ def test_wait_failure_reported_and_recovered(torch, ctx, case, cache):
     the stored flux reset, sweeps equal those of a fresh problem bit for
     bit.  Cases: the DPP kernel (2D p = 3), the LDS kernel with cached
     inverses (2D p = 2 stand-in), the assembled kernel (2D p = 2, no cache)
-    and the 3D kernel with cached inverses (p = 2)."""
-    wait_failure_roundtrip(torch, ctx, SMALL[case](), case, cache)
+    and the 3D kernel with cached inverses (p = 2); the DPP and LDS kernels
+    with FP32 inverses (mixed precision)."""
+    wait_failure_roundtrip(torch, ctx, SMALL[case](), case, cache, precision)
 
 
-def wait_failure_roundtrip(torch, ctx, wp, case, cache):
+def wait_failure_roundtrip(torch, ctx, wp, case, cache, precision=0):
     from paper_1810_11080_amd import Problem
     from paper_1810_11080_amd.binding import SnswError
-    print(f"wait failure: {case}, cache {cache}", flush=True)
-    P = Problem.from_workload(ctx, wp, schedule=1, cache_inverse=cache)
+    print(f"wait failure: {case}, cache {cache}, precision {precision}", flush=True)
+    P = Problem.from_workload(ctx, wp, schedule=1, cache_inverse=cache, precision=precision)
     with pytest.raises(SnswError):
         P.set_wait_limit(-1)
     P.set_wait_limit(0)
@@ -232,7 +234,7 @@ def wait_failure_roundtrip(torch, ctx, wp, case, cache):
     P.reset()
     g_phi, g_psi = gpu_sweeps(torch, P, 3)
     P.synchronize()
-    Q = Problem.from_workload(ctx, wp, schedule=1, cache_inverse=cache)
+    Q = Problem.from_workload(ctx, wp, schedule=1, cache_inverse=cache, precision=precision)
     r_phi, r_psi = gpu_sweeps(torch, Q, 3)
     Q.synchronize()
     for k in range(3):
