@@ -496,14 +496,15 @@ int snsw_learn_pair_noalloc(snsw_problem* prob, const double* d_phi_prev, const 
  * kept) or, with use_graph = 0, an eager launch sequence.
  *
  * opts (nullable: all fields 0):
- *   schedule   SNSW_SCHED_AUTO: the autotuner times, per FP64 class, the
+ *   schedule   SNSW_SCHED_AUTO: the autotuner times, per class, the
  *              level schedule and the persistent one at full and half grid,
  *              and with single pairs instead of tiles per wavefront where
  *              the class has tiles (tune_reps sweeps each, default 3), and
  *              keeps the fastest;
  *              SNSW_SCHED_PERSISTENT / SNSW_SCHED_LEVELS force one for every
- *              FP64 class.  Mixed-precision classes and classes of
- *              unstructured meshes always use LEVELS.
+ *              class.  Classes of unstructured meshes, and mixed-precision
+ *              classes other than 2D lattices with FP32 inverses, always
+ *              use LEVELS.
  *   use_graph  0: eager launches; otherwise hipGraph replay.
  * Autotuning sweeps the member problems, so create leaves their stored
  * angular flux zero (as snsw_reset).  A batch refers to its problems'

@@ -25,7 +25,7 @@ struct BatchGraph {
 struct BatchClass {
     SweepClass cls;
     bool has_inv = false;              // every member keeps cached inverses
-    bool levels_only = false;          // mixed precision or unstructured meshes: level schedule
+    bool levels_only = false;          // unstructured meshes, mixed precision without a persistent FP32 kernel
     int4* d_pairs = nullptr;           // level schedule
     std::vector<int64_t> level_off;
     bool tiled = false;                // every member has a tiled schedule
@@ -332,7 +332,7 @@ void enqueue_sweep_class(const SweepLaunch& L, const SweepClass& c, hipStream_t 
         pa.problem = class_problem(c);
         pa.slots = c.slots;
         pa.nt = 0;
-        if (!launch_sweep_persistent(c.dim, c.p, c.simplex, c.unstructured, c.inv, pa, c.blocks, s))
+        if (!launch_sweep_persistent(c.dim, c.p, c.simplex, c.unstructured, c.inv, pa, c.blocks, s, c.mixed && c.inv))
             throw Error(SNSW_E_STATE, "batch class without a persistent kernel");
     } else {
         for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
@@ -391,8 +391,10 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
                 bc.cls.dim = hp.dim;
                 bc.cls.p = hp.p;
                 bc.cls.mixed = hp.precision == SNSW_PREC_MIXED;
-                // mixed precision and unstructured meshes sweep level by level
-                bc.levels_only = bc.cls.mixed || hp.unstructured;
+                // unstructured meshes sweep level by level, and so does mixed
+                // precision except on 2D lattices with FP32 inverses
+                bc.levels_only = hp.unstructured ||
+                                 (bc.cls.mixed && !(has_inv && persistent_f32(hp.dim, hp.p, hp.simplex, hp.unstructured)));
                 bc.cls.unstructured = hp.unstructured;
                 bc.cls.simplex = hp.simplex;
                 bc.cls.face_points = true;
@@ -426,7 +428,7 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
             const bool pinv = bc.has_inv && persistent_uses_inverse(bc.cls.dim, bc.cls.p);
             const int64_t ptotal = bc.tiled ? bc.tlevel_off.back() : bc.level_off.back();
             bc.full_blocks = persistent_grid(bc.cls.dim, bc.cls.p, bc.cls.simplex, bc.cls.unstructured, pinv, ptotal,
-                                             ctx->device);
+                                             ctx->device, 1.0, bc.cls.mixed && pinv);
             choose(bc, !bc.levels_only && o.schedule == SNSW_SCHED_PERSISTENT, bc.full_blocks);
         }
         HIP_OK(hipMalloc(&b->table, count * sizeof(SweepArgs)));
@@ -439,7 +441,7 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
         for (int32_t k = 0; k < count; ++k) b->entry_cur[k] = probs[k]->dev->cur;
 
         if (o.schedule == SNSW_SCHED_AUTO) {
-            // autotuner: levels vs persistent (full and half grid) per FP64 class
+            // autotuner: levels vs persistent (full and half grid) per class
             upload_table(b, true);
             double* phi_in = nullptr;
             double* phi_out = nullptr;

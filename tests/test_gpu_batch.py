@@ -77,8 +77,10 @@ def single_run(torch, P, phi0, K):
     return res
 
 
-# ragged mix: 2D p = 1, 2, 3 (two of them in one class), 3D p = 1, 2, a
-# mixed-precision member, cyclic graphs, an isotropic inflow boundary
+# ragged mix: 2D p = 1, 2, 3 (two of them in one class), 3D p = 1, 2,
+# mixed-precision members (2D p = 3 and p = 2: persistent kernels with FP32
+# inverses when the batch sweeps persistently), cyclic graphs, an isotropic
+# inflow boundary
 MIX = [
     ("cyc2d_p1", lambda: W.small(dim=2, n=12, r=3, p=1, N=8, amp=0.3 / 12, freq=3, c=0.7), 0),
     ("cyc2d_p3", lambda: W.make_problem("cyc_p3", 2, (17, 11), 3, 3, 8, 0.3 / 17, 4,
@@ -91,6 +93,7 @@ MIX = [
     ("warp3d_p2", lambda: W.make_problem("w3p2", 3, (4, 4, 3), 2, 2, 4, 0.07, 1,
                                          np.linspace(0.5, 5, 48), 0.8, 1.0), 0),
     ("mixed2d_p3", lambda: W.small(dim=2, n=6, r=2, p=3, N=6, amp=0.05, c=0.8), 1),
+    ("mixed2d_p2", lambda: W.small(dim=2, n=(7, 9), r=3, p=2, N=8, amp=0.3 / 9, freq=2, c=0.9), 1),
 ]
 
 
@@ -114,7 +117,10 @@ def test_batch_matches_oracle(torch, ctx, mix_reference, schedule, use_graph):
     B = Batch(ctx, problems, schedule=schedule, use_graph=use_graph, tune_reps=1)
     classes = B.classes()
     assert sum(c["n_problems"] for c in classes) == len(problems)
-    assert len(classes) == 6
+    assert len(classes) == 7
+    if schedule == PERSISTENT:   # lattices only: every class, mixed ones included, sweeps persistently
+        assert all(c["persistent"] == 1 for c in classes)
+        assert sum(c["precision"] == 1 for c in classes) == 2
     got = batch_run(torch, B, problems, phi0s, 3)
     for k, (name, _, prec) in enumerate(MIX):
         tol = MIXED_TOL if prec else TOL
