@@ -225,7 +225,10 @@ def sweep_line(P, wp, name: str, sched: int, prec: int, steps: int, warmup: int)
     E, n, D = P.E, P.n, P.D
     ms, launches, kernel_ms = time_sweeps(P, steps, warmup)
     inv = bool(info["cached_inverse"])
+    partial = inv and info["cached_dirs"] < D
     kname = kernel_name(wp, sched, info["cached_inverse"], info["tile"])
+    if partial:
+        kname += " + " + kernel_name(wp, sched, 0, info["tile"])
     flops_pair, _, _ = work_model(wp.dim, wp.p)
     flops = flops_pair * E * D
     nbytes = algorithmic_bytes(wp.dim, wp.p, E, D, interior_faces(wp.nx))
@@ -240,13 +243,13 @@ def sweep_line(P, wp, name: str, sched: int, prec: int, steps: int, warmup: int)
         achieved = nbytes / launches / avg_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5)}
-    traffic = MEASURED_TRAFFIC.get((kname, name, "fp64" if prec == 0 else "mixed"))
+    traffic = None if partial else MEASURED_TRAFFIC.get((kname, name, "fp64" if prec == 0 else "mixed"))
     roof.update({"traffic": traffic, "kernel": kname,
                  "algorithmic_flops_per_sweep": flops, "algorithmic_bytes_per_sweep": nbytes,
                  "roofline_ms_per_sweep": round(max(t_alu, t_hbm) * 1e3, 4),
                  "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches_per_sweep": launches,
                  "kernel_share_of_step": round(kernel_ms / ms, 4)})
-    if inv:
+    if inv and not partial:
         sb = inverse_stream_bytes_per_pair(wp.dim, wp.p, f32=info["cached_inverse"] == 2) * E * D + 8.0 * E * n
         gbs = sb / launches / avg_launch_s / 1e9
         roof["inverse_stream"] = {"bytes_per_sweep": sb, "achieved_gbs": round(gbs, 1),
@@ -256,6 +259,7 @@ def sweep_line(P, wp, name: str, sched: int, prec: int, steps: int, warmup: int)
             "config": {"workload": DESCRIPTIONS[name], "elements": E, "dofs_per_element": n, "directions": D,
                        "levels": info["n_levels_total"], "lagged_edges": info["n_removed_total"],
                        "kink_face_dirs": info["n_kink_faces_total"], "cached_inverse": inv,
+                       "cached_dirs": info["cached_dirs"],
                        "schedule": "persistent" if sched == 1 else "levels",
                        "precision": "fp64" if prec == 0 else "mixed"}}
 
@@ -598,6 +602,9 @@ def main():
     ap.add_argument("--schedule", default="auto", choices=["auto", "persistent", "levels"])
     ap.add_argument("--cache-inverse", default="auto", choices=["auto", "on", "off"],
                     help="keep each pair's A^{-1} on the device (factored once at setup)")
+    ap.add_argument("--cache-budget", type=float, default=0.0,
+                    help="GB the cached inverses may take under auto (0: half the free memory; less than all of "
+                         "them caches the first directions that fit)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and the learned-vs-plain comparison (plain solve only)")
@@ -657,7 +664,8 @@ def main():
     t0 = time.perf_counter()
     sched = {"auto": 0, "persistent": 1, "levels": 2}[args.schedule]
     cache = {"auto": 0, "on": 1, "off": 2}[args.cache_inverse]
-    P = Problem.from_workload(ctx, wp, precision=prec, schedule=sched, cache_inverse=cache)
+    P = Problem.from_workload(ctx, wp, precision=prec, schedule=sched, cache_inverse=cache,
+                              cache_budget=args.cache_budget * 1e9)
     sched = P.info()["schedule"]      # the library's choice under "auto"
     setup_s = time.perf_counter() - t0
     note(f"{name}: setup {setup_s:.1f} s")

@@ -100,7 +100,12 @@ extern "C" {
  * FP64) is kept rounded to FP32, D*E*n*4*ceil(n/4) floats, and the sweep
  * forms A^{-1} b with FP64 products and sums (elements of at most 32 nodes;
  * larger ones take the assembled path).  AUTO caches when that takes at
- * most half of the free device memory.                                     */
+ * most cache_budget bytes (default: half of the free device memory); on
+ * the LEVELS schedule, when all of them would take more, it caches the
+ * inverses of as many whole directions as fit (the first ones) and
+ * assembles the pairs of the others in every sweep: each level then runs
+ * as two launches, cached pairs and assembled pairs.  Persistent schedules
+ * cache all or nothing.                                                    */
 #define SNSW_CACHE_AUTO    0
 #define SNSW_CACHE_ON      1
 #define SNSW_CACHE_OFF     2
@@ -217,6 +222,9 @@ typedef struct {
                                 mesh (SIMPLEX needs elem_nodes)             */
     int32_t face_rule;       /* SNSW_FACE_*                                   */
     double  face_tol;        /* relative tolerance of SNSW_FACE_ROMBERG       */
+    double  cache_budget;    /* bytes of device memory the cached inverses
+                                may take under SNSW_CACHE_AUTO (<= 0: half
+                                the free memory); see SNSW_CACHE_*            */
 } snsw_problem_desc;
 
 /* Builds the discretisation and the sweep schedule (section 3): quadrature,
@@ -243,6 +251,12 @@ typedef struct {
                                     tiles of elements of one direction per
                                     wavefront (2D, p = 1 or 3); 0: single
                                     pairs                                    */
+    int32_t cached_dirs;         /* directions whose inverses are cached: D
+                                    (all), 0 (none) or, partially, the first
+                                    cached_dirs of them                      */
+    int64_t inverse_block_bytes; /* device bytes of one pair's cached A^{-1}
+                                    in the problem's precision (0: none
+                                    possible)                                 */
 } snsw_problem_info;
 int snsw_problem_get_info(const snsw_problem* prob, snsw_problem_info* info);
 

@@ -32,7 +32,8 @@ class SnswProblemDesc(C.Structure):
                 ("precision", C.c_int32), ("n_threads", C.c_int32), ("schedule", C.c_int32),
                 ("cache_inverse", C.c_int32), ("psi_inc_tab", c_double_p),
                 ("n_nodes", C.c_int64), ("nodes", c_double_p), ("elem_nodes", C.POINTER(C.c_int64)),
-                ("element", C.c_int32), ("face_rule", C.c_int32), ("face_tol", C.c_double)]
+                ("element", C.c_int32), ("face_rule", C.c_int32), ("face_tol", C.c_double),
+                ("cache_budget", C.c_double)]
 
 
 class SnswProblemInfo(C.Structure):
@@ -40,7 +41,8 @@ class SnswProblemInfo(C.Structure):
                 ("n_dirs", C.c_int64), ("n_levels_total", C.c_int64), ("n_pairs", C.c_int64),
                 ("n_edges_total", C.c_int64), ("n_removed_total", C.c_int64),
                 ("n_kink_faces_total", C.c_int64), ("setup_seconds", C.c_double),
-                ("cached_inverse", C.c_int32), ("schedule", C.c_int32), ("tile", C.c_int32)]
+                ("cached_inverse", C.c_int32), ("schedule", C.c_int32), ("tile", C.c_int32),
+                ("cached_dirs", C.c_int32), ("inverse_block_bytes", C.c_int64)]
 
 
 class SnswGraphStats(C.Structure):
@@ -247,7 +249,8 @@ class Problem:
     def __init__(self, ctx: Context, *, dim, nx, geom_order, dg_order, lattice, sn_order,
                  sigma_t, sigma_s, q, bc_kind=0, psi_inc=0.0, weighting=1, exact_scc_max=10,
                  precision=0, n_threads=0, omega=None, w=None, schedule=0, cache_inverse=0,
-                 psi_inc_tab=None, nodes=None, elem_nodes=None, element=0, face_rule=0, face_tol=0.0):
+                 psi_inc_tab=None, nodes=None, elem_nodes=None, element=0, face_rule=0, face_tol=0.0,
+                 cache_budget=0.0):
         """q: [E] or [E][n] isotropic, or [D][E][n] per direction (nodal
         values); psi_inc_tab: [D][E][n] incident flux for bc_kind 2.  With
         elem_nodes ([E][nv] control-point indices into nodes [n_nodes][dim])
@@ -256,7 +259,10 @@ class Problem:
         (nv = (r+1)(r+2)/2, n = (p+1)(p+2)/2) or tetrahedra (nv =
         (r+1)(r+2)(r+3)/6, n = (p+1)(p+2)(p+3)/6).  face_rule 1: adaptive Romberg
         on faces where Omega . n changes sign, relative tolerance face_tol
-        (<= 0: 1e-10)."""
+        (<= 0: 1e-10).  cache_budget: bytes the cached inverses may take
+        under cache_inverse AUTO (<= 0: half the free device memory); on the
+        level schedule a smaller budget caches the first directions that
+        fit."""
         self.ctx = ctx
         if dim not in (2, 3):
             raise SnswError(-1, "dim must be 2 or 3")
@@ -318,6 +324,7 @@ class Problem:
         desc.element = element
         desc.face_rule = face_rule
         desc.face_tol = face_tol
+        desc.cache_budget = cache_budget
         h = C.c_void_p()
         _check(lib().snsw_problem_create(ctx.handle, C.byref(desc), C.byref(h)))
         self.handle = h
@@ -329,7 +336,7 @@ class Problem:
 
     @classmethod
     def from_workload(cls, ctx: Context, prob, precision=0, n_threads=0, weighting=None,
-                      exact_scc_max=None, schedule=0, cache_inverse=0):
+                      exact_scc_max=None, schedule=0, cache_inverse=0, cache_budget=0.0):
         """Build from a ``workloads.Problem`` (seeded synthetic inputs)."""
         q_dir = getattr(prob, "q_dir", None)
         return cls(ctx, dim=prob.dim, nx=tuple(prob.nx), geom_order=prob.r, dg_order=prob.p,
@@ -343,7 +350,7 @@ class Problem:
                    elem_nodes=getattr(prob, "elem_nodes", None),
                    element=1 if getattr(prob, "element", "tensor") == "simplex" else 0,
                    face_rule=1 if getattr(prob, "face_rule", "exact") == "romberg" else 0,
-                   face_tol=getattr(prob, "face_tol", 1e-10))
+                   face_tol=getattr(prob, "face_tol", 1e-10), cache_budget=cache_budget)
 
     def set_source(self, q, bc_kind=0, psi_inc=0.0, psi_inc_tab=None):
         """Replace the volume source and boundary condition (snsw_problem_set_source)."""

@@ -382,7 +382,9 @@ int snsw_batch_create(snsw_ctx* ctx, snsw_problem* const* probs, int32_t count, 
         b->entry_class.resize(count);
         for (int32_t k = 0; k < count; ++k) {
             const HostProblem& hp = probs[k]->hp;
-            const int has_inv = (probs[k]->dev->ainv != nullptr || probs[k]->dev->ainv32 != nullptr) ? 1 : 0;
+            // members with a partial inverse cache sweep assembled here
+            const int has_inv =
+                (probs[k]->dev->ainv != nullptr || probs[k]->dev->ainv32 != nullptr) && hp.cached_dirs == hp.D ? 1 : 0;
             const auto kk = std::make_tuple(hp.dim, hp.p, hp.precision, has_inv, (hp.unstructured ? 1 : 0) + (hp.simplex ? 2 : 0));
             auto it = key.find(kk);
             if (it == key.end()) {

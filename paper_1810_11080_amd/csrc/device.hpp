@@ -49,6 +49,7 @@ struct SweepClass {
     const int32_t* intra = nullptr;    // tiled schedule: intra-tile dependency words
     const int4* slots = nullptr;       // per entry slot records (2D; else null: element tables)
     std::vector<int64_t> level_off;    // [L+1] offsets into pairs
+    std::vector<int64_t> level_split;  // [L] partial inverse cache: end of each level's cached pairs (else empty)
     std::vector<int> members;          // table indices of its problems
 };
 

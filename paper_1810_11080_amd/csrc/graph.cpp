@@ -520,6 +520,40 @@ void build_schedule(HostProblem& hp) {
 }
 
 
+void split_levels_by_cache(HostProblem& hp, int Dc) {
+    const int64_t L = (int64_t)hp.level_off.size() - 1;
+    const int64_t G = std::max(1, 64 / hp.n);
+    std::vector<int32_t> pairs;
+    std::vector<int64_t> off(L + 1, 0), split(L, 0);
+    pairs.reserve(hp.pairs.size());
+    auto pad = [&]() {
+        while ((pairs.size() / 4) % G) {
+            pairs.push_back(-1);
+            pairs.push_back(0);
+            pairs.push_back(0);
+            pairs.push_back(0);
+        }
+    };
+    for (int64_t k = 0; k < L; ++k) {
+        for (int part = 0; part < 2; ++part) {
+            for (int64_t t = hp.level_off[k]; t < hp.level_off[k + 1]; ++t) {
+                const int32_t* pr = &hp.pairs[(size_t)t * 4];
+                if (pr[0] < 0) continue;
+                const int d = (int)((uint32_t)pr[1] & ((1u << kDirBits) - 1));
+                if ((d < Dc) != (part == 0)) continue;
+                pairs.insert(pairs.end(), pr, pr + 4);
+            }
+            pad();
+            if (part == 0) split[k] = (int64_t)pairs.size() / 4;
+        }
+        off[k + 1] = (int64_t)pairs.size() / 4;
+    }
+    hp.pairs.swap(pairs);
+    hp.level_off.swap(off);
+    hp.level_split.swap(split);
+}
+
+
 bool build_tiled_schedule(HostProblem& hp, int T) {
     hp.tile = 0;
     hp.tlevel_off.clear();

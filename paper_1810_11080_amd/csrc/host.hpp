@@ -131,6 +131,8 @@ struct HostProblem {
     int D = 0;
     int weighting = 1, exact_max = 10, precision = 0, bc = 0, nthreads = 1, schedule = 0, cache_inverse = 0;
     int inverse_cached = 0;   // set by the device upload
+    int cached_dirs = 0;      // directions whose inverses are cached (set by the device upload)
+    double cache_budget = 0.0;  // bytes the inverses may take under CACHE_AUTO (<= 0: half the free memory)
     double psi_inc = 0.0;
     std::vector<double> lattice;              // [L][dim] (structured meshes)
     bool unstructured = false;                // mesh given as element control-point lists
@@ -166,6 +168,10 @@ struct HostProblem {
     std::vector<DirGraph> graphs;             // [D]
     // combined schedule
     std::vector<int64_t> level_off;           // [L+1]
+    // partial inverse cache: level k holds the cached pairs in
+    // [level_off[k], level_split[k]) and the others up to level_off[k+1],
+    // both padded to whole batches; empty when every pair is alike
+    std::vector<int64_t> level_split;         // [L]
     std::vector<int32_t> pairs;               // [P][4]: e, packed, kink_base, 0
     std::vector<int32_t> kink_idx;            // per pair kink slots -> kink rows
     // tiled schedule (2D, persistent kernels with G = T*T groups): a batch is
@@ -215,6 +221,13 @@ int volume_rule(const HostProblem& hp, int extra, int64_t e0, int64_t count, dou
 // graph.cpp: per-direction graph, FAS and levels; combined schedule
 void build_graphs(HostProblem& hp);
 void build_schedule(HostProblem& hp);
+// Reorders every level of the combined schedule into the pairs of the first
+// Dc directions (whose inverses are cached) and the rest, each padded to
+// whole batches, and fills level_split.
+void split_levels_by_cache(HostProblem& hp, int Dc);
+// Device bytes of one pair's cached A^{-1} (FP64, or the FP32 copy when f32;
+// 0 when that element has no cached form), as the kernels lay it out.
+int64_t ainv_block_bytes(int dim, int p, bool simplex, bool f32);
 // Tiled schedule with T x T tiles (T*T = 64/n); returns false (and leaves it
 // empty) when the contracted tile graph of some direction has a cycle.
 bool build_tiled_schedule(HostProblem& hp, int T);

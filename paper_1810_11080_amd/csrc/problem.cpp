@@ -171,6 +171,8 @@ int snsw_problem_create(snsw_ctx* ctx, const snsw_problem_desc* desc, snsw_probl
             hp.schedule != SNSW_SCHED_LEVELS)
             throw Error(SNSW_E_INVALID_ARG, "schedule must be AUTO, PERSISTENT or LEVELS");
         hp.cache_inverse = desc->cache_inverse;
+        if (!std::isfinite(desc->cache_budget)) throw Error(SNSW_E_NONFINITE, "cache_budget");
+        hp.cache_budget = desc->cache_budget;
         // mixed precision sweeps persistently where a persistent kernel reads
         // the FP32 inverses: 2D lattices, inverses not switched off
         const bool mixed_persistent = hp.dim == 2 && !desc->elem_nodes && hp.cache_inverse != SNSW_CACHE_OFF;
@@ -285,6 +287,8 @@ int snsw_problem_get_info(const snsw_problem* prob, snsw_problem_info* info) {
         info->n_kink_faces_total = hp.n_kinks;
         info->setup_seconds = hp.setup_seconds;
         info->cached_inverse = hp.inverse_cached;
+        info->cached_dirs = hp.cached_dirs;
+        info->inverse_block_bytes = ainv_block_bytes(hp.dim, hp.p, hp.simplex, hp.precision == SNSW_PREC_MIXED);
         info->tile = hp.tile;
         info->schedule = hp.schedule;
     });

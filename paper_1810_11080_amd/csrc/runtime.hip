@@ -280,11 +280,20 @@ void enqueue_sweep(const SweepLaunch& L, const std::vector<SweepClass>& classes,
             if (prof) prof->end(s);
         } else {
             for (size_t k = 0; k + 1 < c.level_off.size(); ++k) {
-                const int64_t b = c.level_off[k], n = c.level_off[k + 1] - b;
+                // with a partial inverse cache: the cached pairs of the
+                // level, then its assembled ones
+                const int64_t b = c.level_off[k], end = c.level_off[k + 1];
+                const int64_t m = c.level_split.empty() ? end : c.level_split[k];
                 if (prof) prof->begin(s);
-                launch_sweep_level(c.dim, c.p, c.simplex, c.mixed, c.inv, c.unstructured, L.table, c.pairs, b, n,
+                launch_sweep_level(c.dim, c.p, c.simplex, c.mixed, c.inv, c.unstructured, L.table, c.pairs, b, m - b,
                                    class_problem(c), s, c.face_points);
                 if (prof) prof->end(s);
+                if (end > m) {
+                    if (prof) prof->begin(s);
+                    launch_sweep_level(c.dim, c.p, c.simplex, c.mixed, false, c.unstructured, L.table, c.pairs, m,
+                                       end - m, class_problem(c), s, c.face_points);
+                    if (prof) prof->end(s);
+                }
             }
         }
         HIP_OK(hipGetLastError());
@@ -331,6 +340,27 @@ void device_upload(snsw_problem* prob) {
     dp->stream = static_cast<hipStream_t>(prob->ctx->stream);
     const hipStream_t s = dp->stream;
     const int n = hp.n, dim = hp.dim;
+    // cached inverses, decided before anything is allocated: D*E blocks of
+    // about n^2 doubles (FP64), or of n^2 floats in mixed precision
+    // (elements of at most 32 nodes).  AUTO: all of them within the budget,
+    // else (level schedule) the first directions that fit, whose pairs each
+    // level then sweeps apart from the assembled ones
+    const bool mixed = hp.precision == SNSW_PREC_MIXED;
+    const int64_t blk = ainv_block_bytes(hp.dim, hp.p, hp.simplex, mixed);
+    int cache_dirs = 0;
+    if (hp.cache_inverse != SNSW_CACHE_OFF && blk > 0) {
+        if (hp.cache_inverse == SNSW_CACHE_ON) {
+            cache_dirs = hp.D;
+        } else {
+            size_t free_b = 0, total_b = 0;
+            HIP_OK(hipMemGetInfo(&free_b, &total_b));
+            const double budget = hp.cache_budget > 0.0 ? hp.cache_budget : 0.5 * (double)free_b;
+            const double fit = std::floor(budget / ((double)hp.E * (double)blk));
+            if (fit >= (double)hp.D) cache_dirs = hp.D;
+            else if (hp.schedule == SNSW_SCHED_LEVELS && fit >= 1.0) cache_dirs = (int)fit;
+        }
+    }
+    if (cache_dirs > 0 && cache_dirs < hp.D) split_levels_by_cache(hp, cache_dirs);
     // geometry: matrix k of element e stored column-major at [e][k][j][i]
     {
         std::vector<double> geo((size_t)hp.E * (dim + 1) * n * n);
@@ -433,21 +463,12 @@ void device_upload(snsw_problem* prob) {
     HIP_OK(hipMemsetAsync(dp->ticket, 0, sizeof(unsigned int) * kTicketWords, s));
     dp->error = dalloc<int32_t>(dp, 1);
     HIP_OK(hipMemsetAsync(dp->error, 0, sizeof(int32_t), s));
-    // cached inverses: D*E blocks of about n^2 doubles (FP64), or of n^2
-    // floats in mixed precision (elements of at most 32 nodes)
-    const bool mixed = hp.precision == SNSW_PREC_MIXED;
     {
-        const int64_t blk = ainv_block_bytes(hp.dim, hp.p, hp.simplex, mixed);
-        const size_t need = (size_t)hp.D * hp.E * (size_t)blk;
-        bool cache = false;
-        if (hp.cache_inverse != SNSW_CACHE_OFF && blk > 0) {
-            size_t free_b = 0, total_b = 0;
-            HIP_OK(hipMemGetInfo(&free_b, &total_b));
-            cache = hp.cache_inverse == SNSW_CACHE_ON || need <= free_b / 2;
-        }
-        if (cache && mixed) dp->ainv32 = dalloc<float>(dp, need / sizeof(float));
-        else if (cache) dp->ainv = dalloc<double>(dp, need / sizeof(double));
-        hp.inverse_cached = cache ? (mixed ? 2 : 1) : 0;
+        const size_t need = (size_t)cache_dirs * hp.E * (size_t)blk;
+        if (cache_dirs > 0 && mixed) dp->ainv32 = dalloc<float>(dp, need / sizeof(float));
+        else if (cache_dirs > 0) dp->ainv = dalloc<double>(dp, need / sizeof(double));
+        hp.inverse_cached = cache_dirs > 0 ? (mixed ? 2 : 1) : 0;
+        hp.cached_dirs = cache_dirs;
     }
     SweepClass& c = dp->cls;
     c.dim = hp.dim;
@@ -464,6 +485,7 @@ void device_upload(snsw_problem* prob) {
     c.ticket = 0;
     c.pairs = dp->pairs;
     c.level_off = hp.level_off;
+    if (!c.persistent) c.level_split = hp.level_split;
     if (c.persistent && hp.tile > 0) {
         c.pairs = dp->tpairs;
         c.level_off = hp.tlevel_off;
@@ -483,9 +505,29 @@ void device_upload(snsw_problem* prob) {
         HIP_OK(hipMemcpyAsync(dp->table, &a, sizeof(a), hipMemcpyHostToDevice, s));
     }
     if (dp->ainv || dp->ainv32) {
-        launch_factor(hp.dim, hp.p, hp.simplex, dp->ainv32 != nullptr, hp.unstructured, dp->table, dp->pairs,
-                      hp.level_off.back(), dp->ainv32 ? (void*)dp->ainv32 : (void*)dp->ainv, s);
-        HIP_OK(hipGetLastError());
+        // a partial cache factors the cached part of every level only
+        const int4* fpairs = dp->pairs;
+        int64_t fcount = hp.level_off.back();
+        std::vector<int32_t> cp;
+        int4* tmp = nullptr;
+        if (!hp.level_split.empty()) {
+            for (size_t k = 0; k < hp.level_split.size(); ++k)
+                cp.insert(cp.end(), hp.pairs.begin() + hp.level_off[k] * 4, hp.pairs.begin() + hp.level_split[k] * 4);
+            fcount = (int64_t)cp.size() / 4;
+            if (fcount > 0) {
+                HIP_OK(hipMalloc(&tmp, cp.size() * sizeof(int32_t)));
+                HIP_OK(hipMemcpyAsync(tmp, cp.data(), cp.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            }
+            fpairs = tmp;
+        }
+        if (fcount > 0)
+            launch_factor(hp.dim, hp.p, hp.simplex, dp->ainv32 != nullptr, hp.unstructured, dp->table, fpairs, fcount,
+                          dp->ainv32 ? (void*)dp->ainv32 : (void*)dp->ainv, s);
+        const hipError_t launch_rc = hipGetLastError();
+        const hipError_t sync_rc = hipStreamSynchronize(s);
+        if (tmp) HIP_OK(hipFree(tmp));
+        HIP_OK(launch_rc);
+        HIP_OK(sync_rc);
     }
     HIP_OK(hipStreamSynchronize(s));
 }

@@ -360,9 +360,43 @@ def test_mixed_precision_c2_full(torch, ctx, c2_oracle, cache, schedule):
     assert rel_err(g_psi[0], o_psi) < MIXED_TOL
 
 
-@pytest.mark.parametrize("name,precision", [("c3", 0), ("c5", 0), ("c5", 1)],
-                         ids=["c3", "c5", "c5-mixed"])
-def test_full_size_sampled_directions_stored(torch, ctx, name, precision):
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_partial_inverse_cache(torch, ctx, precision):
+    """A cache budget below the whole set of inverses (level schedule): the
+    first directions that fit keep their inverses, the others are assembled
+    in every sweep (two launches per level), against the oracle.  A budget
+    below one direction caches nothing; persistent schedules cache all or
+    nothing."""
+    from paper_1810_11080_amd import Problem
+    wp = SMALL["warp3d_p2"]()
+    full = Problem.from_workload(ctx, wp, precision=precision)
+    info = full.info()
+    D, E, blk = full.D, full.E, info["inverse_block_bytes"]
+    assert info["cached_dirs"] == D and blk == (8 * 730 if precision == 0 else 4 * 4 * 7 * 27)
+    full.close()
+    P = Problem.from_workload(ctx, wp, precision=precision, cache_budget=(D // 3 + 0.5) * E * blk)
+    info = P.info()
+    assert info["cached_dirs"] == D // 3 and info["cached_inverse"] == 1 + precision and info["schedule"] == 2
+    g_phi, g_psi = gpu_sweeps(torch, P, 3)
+    P.synchronize()
+    o_phi, o_psi, _, _ = oracle_sweeps(wp, 3)
+    tol = MIXED_TOL if precision else TOL
+    for k in range(3):
+        assert rel_err(g_phi[k], o_phi[k]) < tol
+    assert rel_err(g_psi[-1], o_psi[-1]) < tol
+    P.close()
+    Q = Problem.from_workload(ctx, wp, precision=precision, cache_budget=0.5 * E * blk)
+    assert Q.info()["cached_dirs"] == 0 and Q.info()["cached_inverse"] == 0
+    Q.close()
+    if precision == 0:
+        R = Problem.from_workload(ctx, wp, schedule=1, cache_budget=(D // 3 + 0.5) * E * blk)
+        assert R.info()["cached_dirs"] == 0
+        R.close()
+
+
+@pytest.mark.parametrize("name,precision,part", [("c3", 0, 0), ("c3", 0, 1), ("c5", 0, 0), ("c5", 1, 0)],
+                         ids=["c3", "c3-partial-cache", "c5", "c5-mixed"])
+def test_full_size_sampled_directions_stored(torch, ctx, name, precision, part):
     """Full-size 3D workloads in the configuration bench.py times (level
     schedule, cached inverses): 32^3 Q2 p=2 S8 (checkerboard sigma_t in
     {1, 10}, c = 0.9) and 48^3 Q2 p=2 S12 (sigma_t in {1, 100} at random,
@@ -370,15 +404,26 @@ def test_full_size_sampled_directions_stored(torch, ctx, name, precision):
     (scattering source on); the angular flux of one direction per octant on
     sampled elements against the oracle's values, stored by
     tests/golden/make_large_sweep_samples.py (the oracle takes minutes
-    here).  Mixed precision (the inverses kept in FP32) at the 1e-5 bar."""
+    here).  Mixed precision (the inverses kept in FP32) at the 1e-5 bar.
+    part: a cache budget of half the directions (the sampled ones on both
+    sides of the split)."""
     import os
     from paper_1810_11080_amd import Problem
     data = np.load(os.path.join(os.path.dirname(__file__), "golden", f"{name}_sweep_samples.npz"))
     wp = {"c3": W.c3, "c5": W.c5}[name]()
     dirs, elems = data["dirs"], data["elems"]
     print(f"{name}: building problem", flush=True)
-    P = Problem.from_workload(ctx, wp, precision=precision)
-    assert P.info()["cached_inverse"] == 1 + precision and P.info()["schedule"] == 2
+    budget = 0.0
+    if part:
+        from oracle.quadrature import level_symmetric
+        E, D = int(np.prod(wp.nx)), len(level_symmetric(wp.sn_order, wp.dim)[1])
+        budget = (D // 2 + 0.5) * E * 8 * 730          # FP64 blocks of 3D p = 2: 730 doubles
+    P = Problem.from_workload(ctx, wp, precision=precision, cache_budget=budget)
+    info = P.info()
+    assert info["cached_inverse"] == 1 + precision and info["schedule"] == 2
+    assert info["cached_dirs"] == (P.D // 2 if part else P.D)
+    if part:
+        assert info["inverse_block_bytes"] == 8 * 730 and min(dirs) < P.D // 2 <= max(dirs)
     phi0, psi0 = W.sweep_inputs(wp, int(data["seed"]), dirs)
     # lagged state: the sampled directions seeded, the others zero (directions
     # are independent within a sweep)
