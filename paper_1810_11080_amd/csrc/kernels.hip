@@ -27,6 +27,13 @@ namespace snsw {
 namespace {
 
 constexpr int kWaves = 4;              // wavefronts per block
+#ifndef SNSW_LEVEL_WAVES
+#define SNSW_LEVEL_WAVES 1
+#endif
+// wavefronts per block of the cached-inverse level sweeps (smaller blocks
+// refill the CUs sooner as a level drains: 48^3 S12 32.3 / 31.6 / 31.5 ms
+// FP64 and 24.4 / 23.7 / 23.6 ms mixed with 4 / 2 / 1; 8 is slower)
+constexpr int kLevelWaves = SNSW_LEVEL_WAVES;
 constexpr int kDirMask = 1023;         // packed word: direction bits
 constexpr int kSlotShift = 10;         // then 3 bits per slot
 constexpr unsigned kOut = 0, kIn = 1, kKink = 2, kNone = 3;
@@ -1701,20 +1708,20 @@ __device__ __forceinline__ double inflow_rhs_quad(const SweepArgs& args, int4 pr
 // One launch per level with cached inverses: b assembled per row, shared
 // through the wavefront's LDS, x = A^{-1} b.
 template <int DIM, int P, bool U = false, bool F32 = false, bool QUAD = false>
-__global__ void __launch_bounds__(64 * kWaves) sweep_level_inv(const SweepArgs* table, const int4* pairs,
+__global__ void __launch_bounds__(64 * kLevelWaves) sweep_level_inv(const SweepArgs* table, const int4* pairs,
                                                               int64_t begin, int64_t count, int problem) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, G = S::G;
     constexpr bool kCoop = DIM == 3 && DIM * S::NF <= N;
-    __shared__ double lds[kWaves][G][N + 1];
-    __shared__ double cfl[kWaves][kCoop ? G : 1][kCoop ? S::NS : 1][DIM * S::NF];
+    __shared__ double lds[kLevelWaves][G][N + 1];
+    __shared__ double cfl[kLevelWaves][kCoop ? G : 1][kCoop ? S::NS : 1][DIM * S::NF];
     constexpr bool kStage = kCoop && S::NF <= 9;
-    __shared__ double ufl[kWaves][kStage ? G : 1][kStage ? S::NS : 1][kStage ? S::NF : 1];
+    __shared__ double ufl[kLevelWaves][kStage ? G : 1][kStage ? S::NS : 1][kStage ? S::NF : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = lane / N, row = lane - grp * N;
     const bool in_group = grp < G;
-    const int64_t wbase = begin + ((int64_t)blockIdx.x * kWaves + wave) * G;
+    const int64_t wbase = begin + ((int64_t)blockIdx.x * kLevelWaves + wave) * G;
     if (wbase >= begin + count) return;   // LDS is per wavefront: no block barrier follows
     const SweepArgs args = load_args(table, batch_problem(pairs, wbase, problem));
     int4 pr = make_int4(-1, 0, 0, 0);
@@ -2187,14 +2194,17 @@ void launch_tpl_u(const SweepArgs* table, const int4* pairs, int64_t begin, int6
     const int64_t blocks = (count + per_block - 1) / per_block;
     if (blocks == 0) return;
     const dim3 grid((unsigned)blocks), block(64 * kWaves);
+    // the cached-inverse kernels take blocks of kLevelWaves wavefronts
+    constexpr int per_iblock = kLevelWaves * Shape<DIM, P>::G;
+    const dim3 igrid((unsigned)((count + per_iblock - 1) / per_iblock)), iblock(64 * kLevelWaves);
     if constexpr (DIM == 3 && P == 2 && !U) {
         // lattices with face Gauss-point normals: inflow contracted through them
         if (inv && quad) {
             if (mixed)
-                hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, true, true>), grid, block, 0, stream, table, pairs,
+                hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, true, true>), igrid, iblock, 0, stream, table, pairs,
                                    begin, count, problem);
             else
-                hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, false, true>), grid, block, 0, stream, table, pairs,
+                hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, false, true>), igrid, iblock, 0, stream, table, pairs,
                                    begin, count, problem);
             return;
         }
@@ -2202,10 +2212,10 @@ void launch_tpl_u(const SweepArgs* table, const int4* pairs, int64_t begin, int6
     if (inv && mixed) {
         // mixed precision with cached inverses: the FP32 copy
         if constexpr (Shape<DIM, P>::N <= kMaxInv32)
-            hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, true>), grid, block, 0, stream, table, pairs, begin, count,
+            hipLaunchKernelGGL((sweep_level_inv<DIM, P, U, true>), igrid, iblock, 0, stream, table, pairs, begin, count,
                                problem);
     } else if (inv)
-        hipLaunchKernelGGL((sweep_level_inv<DIM, P, U>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, table,
+        hipLaunchKernelGGL((sweep_level_inv<DIM, P, U>), igrid, iblock, 0, stream, table,
                            pairs, begin, count, problem);
     else if (mixed)
         hipLaunchKernelGGL((sweep_level_fp64<DIM, P, true, U>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
