@@ -30,9 +30,10 @@ constexpr int kWaves = 4;              // wavefronts per block
 #ifndef SNSW_LEVEL_WAVES
 #define SNSW_LEVEL_WAVES 1
 #endif
-// wavefronts per block of the cached-inverse level sweeps (smaller blocks
-// refill the CUs sooner as a level drains: 48^3 S12 32.3 / 31.6 / 31.5 ms
-// FP64 and 24.4 / 23.7 / 23.6 ms mixed with 4 / 2 / 1; 8 is slower)
+// wavefronts per block of the level sweeps (smaller blocks refill the CUs
+// sooner as a level drains: 48^3 S12 with cached inverses 32.3 / 31.6 /
+// 31.5 ms FP64 and 24.4 / 23.7 / 23.6 ms mixed with 4 / 2 / 1, 8 slower;
+// assembled 145.3 -> 127.2 ms with 1)
 constexpr int kLevelWaves = SNSW_LEVEL_WAVES;
 constexpr int kDirMask = 1023;         // packed word: direction bits
 constexpr int kSlotShift = 10;         // then 3 bits per slot
@@ -428,17 +429,17 @@ __device__ __forceinline__ void wave_sync() {
 // FP32; then one correction with the FP64 operator, r = b - A x0 (FP64),
 // x = x0 + (LU)^{-1} r.
 template <int DIM, int P, bool MIXED, bool U = false>
-__global__ void __launch_bounds__(64 * kWaves) sweep_level_fp64(const SweepArgs* table, const int4* pairs,
+__global__ void __launch_bounds__(64 * kLevelWaves) sweep_level_fp64(const SweepArgs* table, const int4* pairs,
                                                                  int64_t begin, int64_t count, int problem) {
     using S = Shape<DIM, P>;
     constexpr int N = S::N, G = S::G;
-    __shared__ double lds[kWaves][G][N + 1];
+    __shared__ double lds[kLevelWaves][G][N + 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = lane / N, row = lane - grp * N;
     const bool in_group = grp < G;
     // this wavefront's batch of G entries (one problem; count is a multiple of G)
-    const int64_t wbase = begin + ((int64_t)blockIdx.x * kWaves + wave) * G;
+    const int64_t wbase = begin + ((int64_t)blockIdx.x * kLevelWaves + wave) * G;
     if (wbase >= begin + count) return;   // LDS is per wavefront: no block barrier follows
     const SweepArgs args = load_args(table, batch_problem(pairs, wbase, problem));
     int4 pr = make_int4(-1, 0, 0, 0);
@@ -2190,13 +2191,11 @@ __global__ void fill_sentinel_kernel(const SweepArgs* table) {
 template <int DIM, int P, bool U>
 void launch_tpl_u(const SweepArgs* table, const int4* pairs, int64_t begin, int64_t count, int problem, bool mixed,
                   bool inv, hipStream_t stream, bool quad = false) {
-    constexpr int per_block = kWaves * Shape<DIM, P>::G;
-    const int64_t blocks = (count + per_block - 1) / per_block;
-    if (blocks == 0) return;
-    const dim3 grid((unsigned)blocks), block(64 * kWaves);
-    // the cached-inverse kernels take blocks of kLevelWaves wavefronts
+    // level kernels take blocks of kLevelWaves wavefronts
     constexpr int per_iblock = kLevelWaves * Shape<DIM, P>::G;
-    const dim3 igrid((unsigned)((count + per_iblock - 1) / per_iblock)), iblock(64 * kLevelWaves);
+    const int64_t blocks = (count + per_iblock - 1) / per_iblock;
+    if (blocks == 0) return;
+    const dim3 igrid((unsigned)blocks), iblock(64 * kLevelWaves);
     if constexpr (DIM == 3 && P == 2 && !U) {
         // lattices with face Gauss-point normals: inflow contracted through them
         if (inv && quad) {
@@ -2218,10 +2217,10 @@ void launch_tpl_u(const SweepArgs* table, const int4* pairs, int64_t begin, int6
         hipLaunchKernelGGL((sweep_level_inv<DIM, P, U>), igrid, iblock, 0, stream, table,
                            pairs, begin, count, problem);
     else if (mixed)
-        hipLaunchKernelGGL((sweep_level_fp64<DIM, P, true, U>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream,
+        hipLaunchKernelGGL((sweep_level_fp64<DIM, P, true, U>), igrid, iblock, 0, stream,
                            table, pairs, begin, count, problem);
     else
-        hipLaunchKernelGGL((sweep_level_fp64<DIM, P, false, U>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+        hipLaunchKernelGGL((sweep_level_fp64<DIM, P, false, U>), igrid, iblock, 0,
                            stream, table, pairs, begin, count, problem);
 }
 
