@@ -47,9 +47,9 @@ METRIC = "DOF-direction updates/s per sweep; time to 1e-8 residual, learned vs p
 # kernel build it was measured on: drop an entry when the kernel changes.
 MEASURED_TRAFFIC = {("sweep_persistent_dpp<2,3,inv,nt>", "c2", "fp64"): 1.902e9,
                     ("sweep_persistent_dpp<2,3,inv,nt,f32>", "c2", "mixed"): 1.247e9,
-                    ("sweep_level_inv<3,2>", "c5", "fp64"): 4.594e8,
-                    ("sweep_level_inv<3,2,f32>", "c5", "mixed"): 2.999e8,
-                    ("sweep_level_inv<3,2>", "c3", "fp64"): 1.349e8}
+                    ("sweep_level_inv<3,2>", "c5", "fp64"): 4.701e8,
+                    ("sweep_level_inv<3,2,f32>", "c5", "mixed"): 3.102e8,
+                    ("sweep_level_inv<3,2>", "c3", "fp64"): 1.376e8}
 DESCRIPTIONS = {
     "c1": "2D 8x8 Q2 curved (warp 0.05), p=1, S4 (12 dirs), sigma_t=1, c=0.5, q=1, vacuum",
     "c2": "2D 128x128 Q3 curved (warp 0.3 h, 4-element wavelength, cyclic sweep graphs), p=3, "

@@ -17,6 +17,7 @@
 // repeatedly, else the vertex of largest w_out - w_in, smallest id on ties).
 // Levels: ASAP levels of the graph without the lagged edges.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -520,37 +521,57 @@ void build_schedule(HostProblem& hp) {
 }
 
 
-void split_levels_by_cache(HostProblem& hp, int Dc) {
+void arrange_levels_for_cache(HostProblem& hp, int Dc) {
+    const int D = hp.D;
+    if (Dc <= 0) return;                          // all assembled: element-major, as built
+    const bool split = Dc < D;
+    const bool dir_major = hp.dim == 3;
+    if (!split && !dir_major) return;
     const int64_t L = (int64_t)hp.level_off.size() - 1;
     const int64_t G = std::max(1, 64 / hp.n);
+    const uint32_t dmask = (1u << kDirBits) - 1;
     std::vector<int32_t> pairs;
-    std::vector<int64_t> off(L + 1, 0), split(L, 0);
+    std::vector<int64_t> off(L + 1, 0), cut(L, 0);
     pairs.reserve(hp.pairs.size());
-    auto pad = [&]() {
+    std::vector<std::array<int32_t, 4>> part;
+    auto emit = [&](bool by_dir) {
+        if (by_dir)
+            std::stable_sort(part.begin(), part.end(), [&](const auto& a, const auto& b) {
+                return ((uint32_t)a[1] & dmask) < ((uint32_t)b[1] & dmask);
+            });
+        for (const auto& r : part) pairs.insert(pairs.end(), r.begin(), r.end());
         while ((pairs.size() / 4) % G) {
             pairs.push_back(-1);
             pairs.push_back(0);
             pairs.push_back(0);
             pairs.push_back(0);
         }
+        part.clear();
     };
     for (int64_t k = 0; k < L; ++k) {
-        for (int part = 0; part < 2; ++part) {
+        // entries of a level come element-major; the cached ones go
+        // direction-major in 3D, the assembled ones stay element-major (they
+        // share the element matrices across directions)
+        for (int cached = 1; cached >= 0; --cached) {
             for (int64_t t = hp.level_off[k]; t < hp.level_off[k + 1]; ++t) {
                 const int32_t* pr = &hp.pairs[(size_t)t * 4];
                 if (pr[0] < 0) continue;
-                const int d = (int)((uint32_t)pr[1] & ((1u << kDirBits) - 1));
-                if ((d < Dc) != (part == 0)) continue;
-                pairs.insert(pairs.end(), pr, pr + 4);
+                if (((int)((uint32_t)pr[1] & dmask) < Dc) != (cached == 1)) continue;
+                part.push_back({pr[0], pr[1], pr[2], pr[3]});
             }
-            pad();
-            if (part == 0) split[k] = (int64_t)pairs.size() / 4;
+            if (cached == 1) {
+                emit(dir_major);
+                cut[k] = (int64_t)pairs.size() / 4;
+            } else {
+                emit(false);
+            }
         }
         off[k + 1] = (int64_t)pairs.size() / 4;
     }
     hp.pairs.swap(pairs);
     hp.level_off.swap(off);
-    hp.level_split.swap(split);
+    if (split) hp.level_split.swap(cut);
+    else hp.level_split.clear();
 }
 
 

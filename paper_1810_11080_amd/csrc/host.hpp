@@ -221,10 +221,11 @@ int volume_rule(const HostProblem& hp, int extra, int64_t e0, int64_t count, dou
 // graph.cpp: per-direction graph, FAS and levels; combined schedule
 void build_graphs(HostProblem& hp);
 void build_schedule(HostProblem& hp);
-// Reorders every level of the combined schedule into the pairs of the first
-// Dc directions (whose inverses are cached) and the rest, each padded to
-// whole batches, and fills level_split.
-void split_levels_by_cache(HostProblem& hp, int Dc);
+// Arranges every level of the combined schedule for an inverse cache of the
+// first Dc directions: their pairs first (direction-major in 3D), then the
+// others (element-major), each part padded to whole batches; fills
+// level_split when 0 < Dc < D.  Dc = 0 keeps the schedule as built.
+void arrange_levels_for_cache(HostProblem& hp, int Dc);
 // Device bytes of one pair's cached A^{-1} (FP64, or the FP32 copy when f32;
 // 0 when that element has no cached form), as the kernels lay it out.
 int64_t ainv_block_bytes(int dim, int p, bool simplex, bool f32);

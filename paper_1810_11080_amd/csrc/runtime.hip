@@ -360,7 +360,7 @@ void device_upload(snsw_problem* prob) {
             else if (hp.schedule == SNSW_SCHED_LEVELS && fit >= 1.0) cache_dirs = (int)fit;
         }
     }
-    if (cache_dirs > 0 && cache_dirs < hp.D) split_levels_by_cache(hp, cache_dirs);
+    if (hp.schedule == SNSW_SCHED_LEVELS) arrange_levels_for_cache(hp, cache_dirs);
     // geometry: matrix k of element e stored column-major at [e][k][j][i]
     {
         std::vector<double> geo((size_t)hp.E * (dim + 1) * n * n);
